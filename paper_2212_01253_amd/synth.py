@@ -1,0 +1,193 @@
+"""Seeded synthetic inputs for the multislice forward model.
+
+This module only draws inputs: slice stacks of slice-averaged refractive
+index decrements (delta) and absorption indices (beta), measured amplitudes
+and geometry records.  It holds none of the multislice arithmetic, so the
+FP64 oracle and the HIP path can both consume what it produces without
+sharing any computation.
+
+The paper's samples (Table 1 of arXiv 2212.01253) are elongated bars on a
+substrate: much longer along the beam than wide, and only tens of nanometres
+high.  Its experimental images are not public (Data availability), so these
+generators stand in for them with the same structure: a substrate slab in the
+low rows (row 0 is the deepest substrate row), and rectangular bars and lines
+on top, each a box in (x = slice index, y = row, z = column).
+
+All random draws use ``numpy.random.Generator(PCG64(seed))``; values are drawn
+in float64 and handed out as float32, which is what both sides compute from.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, asdict, field
+
+import numpy as np
+
+# Optical constants used by the synthetic workloads (not printed by the paper;
+# typical hard-X-ray values for a Si-like substrate and an Au-like pattern).
+SUBSTRATE_DELTA = 7.6e-6
+SUBSTRATE_BETA = 1.7e-7
+BAR_DELTA = 1.5e-5
+BAR_BETA = 1.0e-6
+
+
+@dataclass
+class Geometry:
+    """Grid and beam parameters of one multislice run (lengths in nm, angles in rad)."""
+
+    ny: int
+    nz: int
+    n_slices: int
+    dy_nm: float = 1.0
+    dz_nm: float = 1.0
+    dx_nm: float = 10.0
+    wavelength_nm: float = 0.1
+    alpha_i_rad: float = 0.0
+    propagator: int = 0  # 0 = paraxial (Fresnel), 1 = exact angular spectrum
+
+    def as_dict(self):
+        return asdict(self)
+
+
+@dataclass
+class Workload:
+    geom: Geometry
+    delta: np.ndarray  # float32 [Ns][Ny][Nz]
+    beta: np.ndarray   # float32 [Ns][Ny][Nz]
+    seed: int
+    name: str
+    meta: dict = field(default_factory=dict)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _fill_box(arr, x0, x1, y0, y1, z0, z1, value):
+    arr[x0:x1, y0:y1, z0:z1] = value
+
+
+def bars_on_substrate(geom: Geometry, seed: int, *, substrate_rows: int,
+                      n_bars=(3, 8), bar_height=(5, 20), bar_width=(2, 16),
+                      bar_len_frac=(0.25, 1.0), n_lines=(0, 0),
+                      line_height=(2, 40), line_width=(1, 4),
+                      delta_range=None, beta_over_delta=None,
+                      bar_delta=BAR_DELTA, bar_beta=BAR_BETA,
+                      substrate=(SUBSTRATE_DELTA, SUBSTRATE_BETA)) -> Workload:
+    """Substrate slab plus seeded rectangular bars (and optional full-length lines).
+
+    Integer ranges are inclusive.  When ``delta_range`` is given every feature
+    draws its own delta uniformly in that range and beta = delta * beta_over_delta;
+    otherwise all features use (bar_delta, bar_beta).  Later features overwrite
+    earlier ones where they overlap.  Bars start at the substrate surface row.
+    """
+    ny, nz, ns = geom.ny, geom.nz, geom.n_slices
+    rng = _rng(seed)
+    delta = np.zeros((ns, ny, nz), np.float32)
+    beta = np.zeros((ns, ny, nz), np.float32)
+    sd, sb = substrate
+    delta[:, :substrate_rows, :] = np.float32(sd)
+    beta[:, :substrate_rows, :] = np.float32(sb)
+    y_base = substrate_rows
+    feats = []
+
+    def feature_values():
+        if delta_range is None:
+            return float(bar_delta), float(bar_beta)
+        d = float(rng.uniform(delta_range[0], delta_range[1]))
+        return d, d * float(beta_over_delta)
+
+    nb = int(rng.integers(n_bars[0], n_bars[1] + 1))
+    for _ in range(nb):
+        h = int(rng.integers(bar_height[0], bar_height[1] + 1))
+        w = int(rng.integers(bar_width[0], min(bar_width[1], nz) + 1))
+        lo = max(1, int(math.ceil(bar_len_frac[0] * ns)))
+        hi = max(lo, int(math.floor(bar_len_frac[1] * ns)))
+        ln = int(rng.integers(lo, hi + 1))
+        z0 = int(rng.integers(0, nz - w + 1))
+        x0 = int(rng.integers(0, ns - ln + 1))
+        y1 = min(ny, y_base + h)
+        d, b = feature_values()
+        _fill_box(delta, x0, x0 + ln, y_base, y1, z0, z0 + w, np.float32(d))
+        _fill_box(beta, x0, x0 + ln, y_base, y1, z0, z0 + w, np.float32(b))
+        feats.append(("bar", x0, ln, y_base, y1, z0, w, d, b))
+    nl = int(rng.integers(n_lines[0], n_lines[1] + 1)) if n_lines[1] > 0 else 0
+    for _ in range(nl):
+        h = int(rng.integers(line_height[0], line_height[1] + 1))
+        w = int(rng.integers(line_width[0], min(line_width[1], nz) + 1))
+        z0 = int(rng.integers(0, nz - w + 1))
+        y1 = min(ny, y_base + h)
+        d, b = feature_values()
+        _fill_box(delta, 0, ns, y_base, y1, z0, z0 + w, np.float32(d))
+        _fill_box(beta, 0, ns, y_base, y1, z0, z0 + w, np.float32(b))
+        feats.append(("line", 0, ns, y_base, y1, z0, w, d, b))
+    return Workload(geom, delta, beta, seed, "bars", {"features": feats})
+
+
+def parity_small(seed: int = 0) -> Workload:
+    """64x64 grid, 128 slices of 10 nm, 0.1 nm wavelength, 0.2 deg incidence.
+
+    Substrate in rows 0..23 (delta 7.6e-6, beta 1.7e-7); 3..8 bars of height
+    5..20 px, width 2..16 px and length Ns/4..Ns slices (delta 1.5e-5, beta 1e-6).
+    """
+    g = Geometry(64, 64, 128, 1.0, 1.0, 10.0, 0.1, math.radians(0.2), 0)
+    w = bars_on_substrate(g, seed, substrate_rows=24)
+    w.name = "parity_64x64x128"
+    return w
+
+
+def throughput_512(seed: int = 2212, n_slices: int = 2048, n: int = 512) -> Workload:
+    """512x512 grid, 2048 slices of 5 nm, 0.1 nm wavelength, incidence U[0.1, 0.4] deg.
+
+    Substrate in the lower quarter of the rows; 8..32 bars (height 2..40,
+    width 4..64, length Ns/8..Ns) and 2..8 full-length lines (height 2..40,
+    width 1..4), each feature with delta U[5e-6, 3e-5] and beta = delta/20.
+    ``n_slices`` and ``n`` exist so tests can draw the same kind of stack at
+    reduced size; the throughput workload uses the defaults.
+    """
+    rng = _rng(seed)
+    alpha = math.radians(float(rng.uniform(0.1, 0.4)))
+    g = Geometry(n, n, n_slices, 1.0, 1.0, 5.0, 0.1, alpha, 0)
+    w = bars_on_substrate(g, seed + 1, substrate_rows=n // 4, n_bars=(8, 32),
+                          bar_height=(2, 40), bar_width=(4, 64),
+                          bar_len_frac=(1.0 / 8.0, 1.0), n_lines=(2, 8),
+                          line_height=(2, 40), line_width=(1, 4),
+                          delta_range=(5e-6, 3e-5), beta_over_delta=1.0 / 20.0)
+    w.name = f"bars_{n}x{n}x{n_slices}"
+    return w
+
+
+def recon_256(seed: int = 4242, n_slices: int = 1024, n: int = 256) -> Workload:
+    """256x256 grid, 1024 slices of 5 nm, 0.1 nm, 0.2 deg: the gradient workload.
+
+    The pattern occupies the 64 rows above a substrate of Ny/4 rows; beta = delta/20.
+    """
+    g = Geometry(n, n, n_slices, 1.0, 1.0, 5.0, 0.1, math.radians(0.2), 0)
+    w = bars_on_substrate(g, seed, substrate_rows=n // 4, n_bars=(8, 32),
+                          bar_height=(2, 40), bar_width=(4, 64),
+                          bar_len_frac=(1.0 / 8.0, 1.0), n_lines=(2, 8),
+                          line_height=(2, 40), line_width=(1, 4),
+                          delta_range=(5e-6, 3e-5), beta_over_delta=1.0 / 20.0)
+    w.name = f"recon_{n}x{n}x{n_slices}"
+    return w
+
+
+def random_stack(ny, nz, ns, seed, delta_scale=1e-5, beta_scale=5e-7):
+    """Dense random slice stack (uniform [0, scale)), float32."""
+    rng = _rng(seed)
+    d = (rng.random((ns, ny, nz)) * delta_scale).astype(np.float32)
+    b = (rng.random((ns, ny, nz)) * beta_scale).astype(np.float32)
+    return d, b
+
+
+def random_field(ny, nz, seed, scale=1.0):
+    """Random complex64 field with standard-normal real and imaginary parts."""
+    rng = _rng(seed)
+    return ((rng.standard_normal((ny, nz)) + 1j * rng.standard_normal((ny, nz)))
+            * scale).astype(np.complex64)
+
+
+def random_measured_amplitude(ny, nz, seed, scale=1.0):
+    """Non-negative float32 amplitudes (a stand-in for sqrt of detector counts)."""
+    rng = _rng(seed)
+    return (np.abs(rng.standard_normal((ny, nz))) * scale).astype(np.float32)

@@ -1,0 +1,399 @@
+"""Pins for the FP64 oracle: checks against mathematics and textbook physics.
+
+Every test here runs on the CPU.  None of them compares the oracle with
+itself: each one checks it against a brute-force definition, a closed form,
+an invariant or an independent formula, chosen so that a wrong sign, a
+dropped factor or a transposed axis in the oracle fails at least one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import msl_oracle as O
+from paper_2212_01253_amd import synth
+
+
+def geom(ny, nz, ns, dy=1.0, dz=1.0, dx=10.0, lam=0.1, alpha=0.0, prop=0):
+    return synth.Geometry(ny, nz, ns, dy, dz, dx, lam, alpha, prop)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def rand_c(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+class Repeat:
+    """A slice stack whose every slice is the same 2-D map."""
+
+    def __init__(self, arr):
+        self.arr = arr
+
+    def __getitem__(self, s):
+        return self.arr
+
+
+# --- P1: brute-force DFT ----------------------------------------------------
+
+@pytest.mark.parametrize("ny,nz", [(2, 4), (4, 8), (8, 8), (3, 5), (6, 4), (5, 3)])
+@pytest.mark.parametrize("prop", [0, 1])
+def test_p1_brute_force_dft(ny, nz, prop):
+    rng = np.random.default_rng(ny * 31 + nz + 7 * prop)
+    g = geom(ny, nz, 3, dy=0.7, dz=1.3, dx=4.0, lam=0.15, alpha=0.01, prop=prop)
+    d = rng.random((3, ny, nz)) * 3e-3
+    b = rng.random((3, ny, nz)) * 1e-3
+    p0 = rand_c(rng, (ny, nz))
+    ref = O.forward(g, d, b, p0)
+    assert rel(O.brute_forward(g, d, b, p0), ref) < 1e-12
+    assert rel(O.brute_forward(g, d, b, p0, kron=True), ref) < 1e-12
+    assert rel(O.brute_far_field(ref), O.far_field(g, ref)) < 1e-12
+
+
+# --- P2: vacuum composition -------------------------------------------------
+
+@pytest.mark.parametrize("prop", [0, 1])
+def test_p2_vacuum_composition(prop):
+    rng = np.random.default_rng(2)
+    ny, nz, ns = 32, 16, 7
+    g = geom(ny, nz, ns, dy=0.5, dz=2.0, dx=6.0, prop=prop)
+    g1 = geom(ny, nz, 1, dy=0.5, dz=2.0, dx=6.0 * ns, prop=prop)
+    p0 = rand_c(rng, (ny, nz))
+    zero = np.zeros((ns, ny, nz))
+    assert rel(O.forward(g, zero, zero, p0), O.forward(g1, zero[:1], zero[:1], p0)) < 1e-12
+
+
+# --- P3: plane-wave eigenmodes (closed-form phase and far-field position) ----
+
+@pytest.mark.parametrize("prop", [0, 1])
+def test_p3_plane_wave(prop):
+    ny, nz, ns = 64, 32, 9
+    dy, dz, dx, lam = 0.8, 1.7, 12.0, 0.12
+    m, p = 3, -2                       # on-bin tilts along y and z
+    g = geom(ny, nz, ns, dy, dz, dx, lam, 0.0, prop)
+    k = 2 * math.pi / lam
+    qy = 2 * math.pi * m / (ny * dy)
+    qz = 2 * math.pi * p / (nz * dz)
+    jj, ll = np.meshgrid(np.arange(ny), np.arange(nz), indexing="ij")
+    p0 = np.exp(1j * (qy * jj * dy + qz * ll * dz))
+    zero = np.zeros((ns, ny, nz))
+    out = O.forward(g, zero, zero, p0)
+    kp2 = qy * qy + qz * qz
+    if prop == 0:
+        phase = ns * dx * kp2 / (2 * k)
+    else:
+        phase = ns * dx * kp2 / (k + math.sqrt(k * k - kp2))
+    assert rel(out, p0 * np.exp(1j * phase)) < 1e-12
+    I = O.far_field(g, out)
+    r, c = np.unravel_index(np.argmax(I), I.shape)
+    assert (r, c) == (ny // 2 - m, nz // 2 - p)
+    assert abs(I[r, c] - ny * nz) < 1e-9 * ny * nz
+    assert I.sum() - I[r, c] < 1e-9
+
+
+def test_p3_tilted_probe_is_on_bin_plane_wave():
+    ny, nz = 64, 8
+    m = 5
+    dy = 1.0
+    lam = 0.1
+    alpha = math.asin(m * lam / (ny * dy))      # k sin(a) = 2 pi m / (Ny dy)
+    g = geom(ny, nz, 1, dy=dy, lam=lam, alpha=alpha)
+    I = O.far_field(g, O.tilted_probe(g))
+    r, c = np.unravel_index(np.argmax(I), I.shape)
+    assert (r, c) == (ny // 2 - m, nz // 2)  # direct beam below the horizon
+
+
+# --- P4: uniform slab (transmission sign, absorption, Beer-Lambert) ----------
+
+def test_p4_uniform_slab():
+    rng = np.random.default_rng(4)
+    ny, nz, ns = 16, 32, 11
+    g = geom(ny, nz, ns, dy=1.5, dz=0.9, dx=8.0, lam=0.1, alpha=0.003)
+    d0, b0 = 2.3e-5, 4.0e-6
+    p0 = rand_c(rng, (ny, nz))
+    vac = O.forward(g, np.zeros((ns, ny, nz)), np.zeros((ns, ny, nz)), p0)
+    slab = O.forward(g, np.full((ns, ny, nz), d0), np.full((ns, ny, nz), b0), p0)
+    k = 2 * math.pi / 0.1
+    L = ns * 8.0
+    assert rel(slab, np.exp(1j * k * L * (d0 + 1j * b0)) * vac) < 1e-12
+    ratio = np.sum(np.abs(slab) ** 2) / np.sum(np.abs(p0) ** 2)
+    assert abs(ratio - math.exp(-2 * k * b0 * L)) < 1e-12
+
+
+# --- P5: Parseval / unitarity ----------------------------------------------
+
+def test_p5_parseval():
+    rng = np.random.default_rng(5)
+    ny, nz, ns = 32, 32, 20
+    g = geom(ny, nz, ns, dx=10.0, alpha=0.004)
+    d = rng.random((ns, ny, nz)) * 3e-5
+    zero = np.zeros_like(d)
+    psi, kept = O.forward(g, d, zero, None, keep=True)
+    n0 = np.sum(np.abs(kept[0]) ** 2)
+    for f in kept[1:] + [psi]:
+        assert abs(np.sum(np.abs(f) ** 2) / n0 - 1) < 1e-12
+    I = O.far_field(g, psi)
+    assert abs(I.sum() / np.sum(np.abs(psi) ** 2) - 1) < 1e-12
+    # with absorption the norm never increases
+    b = rng.random((ns, ny, nz)) * 1e-6
+    psi, kept = O.forward(g, d, b, None, keep=True)
+    norms = [np.sum(np.abs(f) ** 2) for f in kept + [psi]]
+    assert all(norms[i + 1] <= norms[i] * (1 + 1e-14) for i in range(len(norms) - 1))
+
+
+# --- P6: convention consistency ------------------------------------------------
+
+def _mixed_forward(g, d, b):
+    """Wrong model on purpose: this convention's T with the paper's H."""
+    H = O.propagator(g, conj_convention=True)
+    psi = O.tilted_probe(g)
+    for s in range(g.n_slices):
+        psi = psi * O.transmission(d[s], b[s], g)
+        psi = np.fft.ifft2(H * np.fft.fft2(psi))
+    return psi
+
+
+def test_p6_conjugation_symmetry():
+    w = synth.parity_small(0)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 32})
+    d, b = w.delta[:32], w.beta[:32]
+    psi = O.forward(g, d, b)
+    I = O.far_field(g, psi)
+    psi_p, I_p = O.forward_paper_convention(g, d, b)
+    assert rel(psi_p, np.conj(psi)) < 1e-13
+    assert rel(I_p, I) < 1e-13
+    Im = O.far_field(g, _mixed_forward(g, d, b))
+    up = slice(g.ny // 2 + 1, None)          # reflected side, q_y > 0
+    assert rel(Im[up], I[up]) > 0.01
+
+
+# --- P7: Fresnel reflectivity of a flat substrate ---------------------------
+
+SUB_D, SUB_B = 7.6e-6, 1.7e-7
+
+
+def _reflectivity_multislice(alpha_deg, dx=50.0, ny=2048, dy=2.0, w0=200.0, h0=600.0,
+                             mixed=False):
+    """R from a 1-D (z-uniform) multislice run: reflected power over incident power."""
+    a = math.radians(alpha_deg)
+    lam = 0.1
+    k = 2 * math.pi / lam
+    half = ny // 2
+    ns = int(math.ceil((2 * h0 + 3 * w0) / math.tan(a) / dx))
+    g = geom(ny, 1, ns, dy=dy, dz=1.0, dx=dx, lam=lam, alpha=a)
+    y = np.arange(ny) * dy
+    surf = half * dy
+    d = np.zeros((ny, 1))
+    b = np.zeros((ny, 1))
+    d[:half] = SUB_D
+    b[:half] = SUB_B
+    sponge = 256
+    ramp = np.cos(0.5 * math.pi * np.arange(sponge) / sponge) ** 2   # 1 at row 0
+    b[:sponge, 0] += 1e-4 * ramp
+    yc = surf + h0
+    p0 = (np.exp(-((y - yc) / w0) ** 2) * np.exp(1j * k * math.sin(a) * (y - yc)))[:, None]
+    if mixed:
+        H = O.propagator(g, conj_convention=True)
+        T = O.transmission(d, b, g)
+        psi = p0.astype(np.complex128)
+        for _ in range(ns):
+            psi = np.fft.ifft(H[:, 0] * np.fft.fft((psi * T)[:, 0]))[:, None]
+    else:
+        psi = O.forward(g, Repeat(d), Repeat(b), p0)
+    I = O.far_field(g, psi)[:, 0]
+    # q_y > 0 (rows above Ny/2) is the reflected side
+    return float(I[half + 1:].sum() / np.sum(np.abs(p0) ** 2)), w0, k
+
+
+def _fresnel_averaged(alpha_deg, w0, k):
+    """Fresnel R averaged over the Gaussian probe's angular spectrum."""
+    a = math.radians(alpha_deg)
+    sig = 2.0 / (k * w0)                    # 1/e^2 angular half-width of |amp|^2... of amplitude
+    t = np.linspace(-4 * sig, 4 * sig, 801)
+    wgt = np.exp(-2 * (t / sig) ** 2)
+    R = O.fresnel_reflectivity(a + t, SUB_D, SUB_B)
+    return float(np.sum(R * wgt) / np.sum(wgt))
+
+
+@pytest.mark.parametrize("alpha_deg", [0.12, 0.18, 0.21, 0.24, 0.30])
+def test_p7_fresnel_reflectivity(alpha_deg):
+    R_ms, w0, k = _reflectivity_multislice(alpha_deg)
+    R_F = _fresnel_averaged(alpha_deg, w0, k)
+    assert abs(R_ms - R_F) < 0.02, (alpha_deg, R_ms, R_F)
+
+
+def test_p7_total_external_reflection_needs_consistent_signs():
+    # Below the critical angle the consistent model reflects almost everything,
+    # as the Fresnel formula says; mixing this convention's transmission with
+    # the paper's propagator sign gives a different medium and misses it.
+    R_ok, w0, k = _reflectivity_multislice(0.12)
+    R_bad, _, _ = _reflectivity_multislice(0.12, mixed=True)
+    R_F = _fresnel_averaged(0.12, w0, k)
+    assert R_ok > 0.9 and abs(R_ok - R_F) < 0.02
+    assert abs(R_bad - R_F) > 0.1
+
+
+def test_fresnel_closed_form_against_full_snell_law():
+    a = np.radians(np.array([0.05, 0.1, 0.15, 0.2, 0.2234, 0.25, 0.3, 0.4, 0.5]))
+    small = O.fresnel_reflectivity(a, SUB_D, SUB_B)
+    full = O.fresnel_reflectivity_exact(a, SUB_D, SUB_B)
+    assert np.max(np.abs(small - full)) < 2e-3
+    assert small[0] > 0.98 and small[-1] < 0.01
+    # critical angle sqrt(2 delta)
+    ac = math.sqrt(2 * SUB_D)
+    assert O.fresnel_reflectivity(ac * 0.9, SUB_D, 0.0) == pytest.approx(1.0, abs=1e-12)
+
+
+# --- P8: Born (kinematic) limit ----------------------------------------------
+
+def test_p8_born_limit():
+    rng = np.random.default_rng(8)
+    ny, nz = 32, 16
+    g = geom(ny, nz, 1, dy=1.0, dz=1.0, dx=10.0, lam=0.1)
+    k = 2 * math.pi / 0.1
+    d = rng.random((1, ny, nz)) * 1e-6
+    b = rng.random((1, ny, nz)) * 1e-7
+    psi = O.forward(g, d, b, np.ones((ny, nz), np.complex128))
+    I = O.far_field(g, psi)
+    eps = k * 10.0 * (d[0] + 1j * b[0])
+    pred = np.fft.fftshift(np.abs(np.fft.ifft2(eps) * ny * nz) ** 2 / (ny * nz))
+    mask = np.ones_like(I, bool)
+    mask[ny // 2, nz // 2] = False
+    assert rel(I[mask], pred[mask]) < 2e-3
+
+
+# --- P9: slice-thickness convergence (first-order splitting) -------------------
+
+def test_p9_dx_convergence_order():
+    rng = np.random.default_rng(9)
+    ny, nz = 64, 16
+    L = 640.0
+    base = np.zeros((ny, nz))
+    base[:20] = 2e-4
+    base[20:28, 4:10] = 5e-4
+    bb = base / 20
+    p0 = np.exp(-((np.arange(ny) - 40.0) / 8.0) ** 2)[:, None] * np.ones((1, nz))
+    p0 = p0 * np.exp(1j * rng.uniform(0, 0.1, (ny, nz)))
+
+    def run(ns):
+        g = geom(ny, nz, ns, dx=L / ns, lam=0.1, dy=1.0, dz=1.0)
+        return O.forward(g, Repeat(base), Repeat(bb), p0)
+
+    ref = run(2048)
+    errs = [np.linalg.norm(run(n) - ref) for n in (16, 32, 64)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.6 < r1 < 2.6 and 1.6 < r2 < 2.6, (errs, r1, r2)
+
+
+# --- P10: gradient against central finite differences -----------------------
+
+def test_p10_gradient_finite_differences():
+    rng = np.random.default_rng(10)
+    ny, nz, ns = 16, 16, 6
+    g = geom(ny, nz, ns, dx=10.0, lam=0.1, alpha=math.radians(0.2))
+    d = rng.random((ns, ny, nz)) * 2e-5
+    b = d / 20
+    meas = np.sqrt(O.far_field(g, O.forward(g, d * 1.3, b * 1.3))) * (1 + 0.05 * rng.random((ny, nz)))
+    L, gd, gb, _, _, _ = O.loss_and_gradient(g, d, b, meas)
+    pick = np.random.default_rng(4245)
+    idx = [tuple(pick.integers(0, n) for n in d.shape) for _ in range(16)]
+    for h in (1e-9, 1e-8):
+        for ix in idx:
+            for arr, grad in ((d, gd), (b, gb)):
+                save = arr[ix]
+                arr[ix] = save + h
+                Lp = O.loss_and_gradient(g, d, b, meas)[0]
+                arr[ix] = save - h
+                Lm = O.loss_and_gradient(g, d, b, meas)[0]
+                arr[ix] = save
+                fd = (Lp - Lm) / (2 * h)
+                scale = max(abs(grad[ix]), 1e-3 * np.max(np.abs(grad)))
+                assert abs(fd - grad[ix]) <= 2e-5 * scale + 1e-9, (ix, fd, grad[ix])
+
+
+# --- P11: dot-product (adjoint) test ------------------------------------------
+
+@pytest.mark.parametrize("prop", [0, 1])
+def test_p11_dot_product(prop):
+    rng = np.random.default_rng(11)
+    ny, nz, ns = 16, 8, 5
+    g = geom(ny, nz, ns, dy=0.9, dz=1.1, dx=7.0, prop=prop)
+    d = rng.random((ns, ny, nz)) * 1e-3
+    b = rng.random((ns, ny, nz)) * 1e-4
+    v = rand_c(rng, (ny, nz))
+    w = rand_c(rng, (ny, nz))
+    Jv = O.forward(g, d, b, v)
+    _, _, JHw = O.adjoint(g, d, b, w, probe=v)
+    lhs = np.vdot(w, Jv)
+    rhs = np.vdot(JHw, v)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_p11_linearised_delta_map():
+    rng = np.random.default_rng(111)
+    ny, nz, ns = 16, 8, 4
+    g = geom(ny, nz, ns, dx=10.0, lam=0.1)
+    d = rng.random((ns, ny, nz)) * 1e-4
+    b = rng.random((ns, ny, nz)) * 1e-5
+    p0 = rand_c(rng, (ny, nz))
+    dd = rng.standard_normal(d.shape)
+    w = rand_c(rng, (ny, nz))
+    eps = 1e-7
+    jvp = (O.forward(g, d + eps * dd, b, p0) - O.forward(g, d - eps * dd, b, p0)) / (2 * eps)
+    gd, _, _ = O.adjoint(g, d, b, w, probe=p0)
+    lhs = np.real(np.vdot(w, jvp))
+    rhs = float(np.sum(gd * dd))
+    assert abs(lhs - rhs) < 1e-7 * abs(lhs)
+
+
+# --- P12: reversibility ---------------------------------------------------------
+
+def test_p12_reversibility():
+    rng = np.random.default_rng(12)
+    ny, nz, ns = 32, 16, 12
+    g = geom(ny, nz, ns, dx=10.0, alpha=0.003)
+    d = rng.random((ns, ny, nz)) * 3e-5
+    zero = np.zeros_like(d)
+    p0 = rand_c(rng, (ny, nz))
+    psi = O.forward(g, d, zero, p0)
+    _, _, back = O.adjoint(g, d, zero, psi, probe=p0)
+    assert rel(back, p0) < 1e-12
+
+
+# --- far field, loss and their adjoints -----------------------------------------
+
+def test_far_field_point_source_is_flat():
+    ny, nz = 16, 8
+    psi = np.zeros((ny, nz), np.complex128)
+    psi[3, 5] = 2.0
+    I = O.far_field(geom(ny, nz, 1), psi)
+    assert np.allclose(I, 4.0 / (ny * nz), rtol=0, atol=1e-14)
+
+
+def test_amp_loss_closed_form():
+    I = np.array([[4.0, 0.0], [1.0, 9.0]])
+    m = np.array([[1.0, 2.0], [1.0, 0.0]])
+    L, Lm, gI = O.amp_loss(I, m)
+    assert L == pytest.approx((2 - 1) ** 2 + (0 - 2) ** 2 + 0 + 9)
+    assert Lm == pytest.approx(L / 4)
+    assert np.allclose(gI, [[1 - 1 / 2, 0.0], [0.0, 1.0]])
+
+
+def test_far_field_adjoint_finite_differences():
+    rng = np.random.default_rng(13)
+    ny, nz = 8, 8
+    g = geom(ny, nz, 1)
+    psi = rand_c(rng, (ny, nz))
+    m = np.abs(rand_c(rng, (ny, nz)))
+
+    def loss(p):
+        return O.amp_loss(O.far_field(g, p), m)[0]
+
+    _, _, gI = O.amp_loss(O.far_field(g, psi), m)
+    gpsi = O.far_field_adjoint(g, psi, gI)
+    dz = rand_c(rng, (ny, nz))
+    eps = 1e-6
+    fd = (loss(psi + eps * dz) - loss(psi - eps * dz)) / (2 * eps)
+    assert abs(fd - np.real(np.vdot(gpsi, dz))) < 1e-7 * abs(fd)
