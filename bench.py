@@ -1,0 +1,176 @@
+"""Benchmark: multislice forward + adjoint (one gradient evaluation) on one MI355X.
+
+One step = the whole hot path over the 512 x 512 x 2048 bars-on-substrate
+workload (5 nm slices, 0.1 nm wavelength): forward sweep with checkpoints
+every 32 slices, far-field intensity, amplitude loss and its derivative,
+far-field adjoint, and the checkpointed adjoint sweep producing dL/d delta,
+dL/d beta and dL/d probe.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is voxel-slice-steps per second of the
+forward + adjoint step (Ny * Nz * Ns / step time).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FWD_BYTES = 24.0          # per voxel-slice: delta + beta (8 B) + field read and write (16 B)
+
+
+def grad_bytes_per_voxel_slice(k):
+    # forward 24 + 8/k (checkpoint stores) ; segment recompute 24 + 8 (store psi_s) ;
+    # reverse 8 (delta, beta) + 8 (psi_s) + 16 (cotangent read + write) + 8 (two gradients)
+    return 24.0 + 8.0 / k + 32.0 + 40.0
+
+
+def cpu_baseline(w, meas, n_sample):
+    import numpy as np
+    from oracle import msl_oracle as O
+    from paper_2212_01253_amd import synth
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": n_sample})
+    d = np.ascontiguousarray(w.delta[:n_sample])
+    b = np.ascontiguousarray(w.beta[:n_sample])
+    t0 = time.perf_counter()
+    O.loss_and_gradient(g, d, b, meas)
+    dt = time.perf_counter() - t0
+    vs = g.ny * g.nz * n_sample
+    return {"value": vs / dt, "unit": "voxel-slice-steps/s", "cores": O.WORKERS, "kind": "oracle",
+            "sample": f"FP64 oracle forward+far field+loss+adjoint (all fields kept) on the first "
+                      f"{n_sample} of the {w.geom.n_slices} slices of the same {g.ny}x{g.nz} workload: "
+                      f"{dt:.2f} s",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ckpt-every", type=int, default=32)
+    ap.add_argument("--schedule", type=int, default=0, help="0 auto, 1 per-pass launches, 2 persistent")
+    ap.add_argument("--slices", type=int, default=2048)
+    ap.add_argument("--cpu-sample-slices", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the multislice recurrence is sequential over slices and "
+              f"this build has no multi-GPU path); got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2212_01253_amd import msl, synth
+
+    w = synth.throughput_512(n_slices=args.slices)
+    g = w.geom
+    ny, nz, ns = g.ny, g.nz, g.n_slices
+    k = args.ckpt_every
+    meas = synth.random_measured_amplitude(ny, nz, 77, 1.0)
+    print(f"# workload {w.name}: alpha {math.degrees(g.alpha_i_rad):.4f} deg", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    msl.set_schedule(args.schedule)
+    D = torch.from_numpy(w.delta).to(dev)
+    B = torch.from_numpy(w.beta).to(dev)
+    Mm = torch.from_numpy(meas).to(dev)
+    ws = msl.workspace(g, k, dev)
+    field = torch.empty((ny, nz), dtype=torch.complex64, device=dev)
+    ck = torch.empty((msl.checkpoint_count(g, k), ny, nz), dtype=torch.complex64, device=dev)
+    gd = torch.empty_like(D)
+    gb = torch.empty_like(B)
+    I = torch.empty((ny, nz), dtype=torch.float32, device=dev)
+    gpsi = torch.empty((ny, nz), dtype=torch.complex64, device=dev)
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        msl.forward(g, D, B, None, k, ws=ws, out=field, ckpt=ck)
+        if ev:
+            ev[1].record()
+        msl.far_field(g, field, ws=ws, out=I)
+        _, gI = msl.amp_loss(g, I, Mm, ws=ws)
+        msl.far_field_adjoint(g, field, gI, ws=ws, out=gpsi)
+        if ev:
+            ev[2].record()
+        msl.adjoint(g, D, B, ck, k, gpsi, ws=ws, gd=gd, gb=gb, want_probe=True)
+        if ev:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"# warmup done", file=sys.stderr, flush=True)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for i in range(args.steps):
+        step(evs[i])
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms = total_ms / args.steps
+    fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    mid_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    adj_ms = [e[2].elapsed_time(e[3]) for e in evs]
+    vs = ny * nz * ns
+    value = vs / (ms / 1e3)
+    bpv = grad_bytes_per_voxel_slice(k)
+    achieved = vs * bpv / (ms / 1e3) / 1e9
+    fwd_med = float(np.median(fwd_ms))
+    fwd_gbs = vs * (FWD_BYTES + 8.0 / k) / (fwd_med / 1e3) / 1e9
+    print(f"# step {ms:.3f} ms: forward {fwd_med:.3f} ms, far field+loss+seed {np.median(mid_ms):.3f} ms, "
+          f"adjoint {np.median(adj_ms):.3f} ms", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "multislice voxel-slice-steps/s fwd+adj (c64)",
+        "value": value,
+        "unit": "voxel-slice-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [ny, nz], "n_slices": ns, "dx_nm": g.dx_nm,
+                   "wavelength_nm": g.wavelength_nm, "alpha_deg": math.degrees(g.alpha_i_rad),
+                   "propagator": "paraxial", "ckpt_every": k, "seed": w.seed,
+                   "schedule": ["auto", "per_pass", "persistent"][args.schedule]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "line-pass kernels of the whole step (forward, recompute, reverse)",
+                     "bytes_per_voxel_slice": bpv},
+        "forward": {"ms": fwd_med, "voxel_slice_steps_per_s": vs / (fwd_med / 1e3), "achieved_GBs": fwd_gbs,
+                    "frac": fwd_gbs / HBM_PEAK_GBS, "bytes_per_voxel_slice": FWD_BYTES + 8.0 / k},
+        "adjoint_ms": float(np.median(adj_ms)),
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, meas, args.cpu_sample_slices)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

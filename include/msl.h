@@ -1,0 +1,175 @@
+/*
+ * msl.h -- C ABI of libmsl, the MI355X (gfx950) multislice library for
+ * coherent surface scattering imaging in reflection geometry
+ * (Myint et al., "Multislice forward modeling of Coherent Surface Scattering
+ * Imaging on surface and interfacial structures", arXiv 2212.01253).
+ *
+ * What is computed (paper passages in brackets):
+ *   - the multislice recurrence of Eq. (1) [Sec. 1]: for every slice s the
+ *     complex field is multiplied by the slice transmission
+ *     T_s = exp(i k dx (delta_s + i beta_s)), Fourier transformed, multiplied
+ *     by the Fresnel propagator and inverse transformed; the exit wave of one
+ *     slice enters the next [Sec. 1; Fig. 1 caption];
+ *   - the far-field detector intensity: Fourier transform of the final exit
+ *     wave, squared [Sec. 1; Fig. 1 caption];
+ *   - the amplitude loss of Eq. (4) [Sec. 4.1] and its gradient with respect
+ *     to every slice's delta and beta, which the paper obtains by automatic
+ *     differentiation [Sec. 1, Sec. 3, Sec. 4] and this library by an explicit
+ *     adjoint sweep with checkpoints.
+ *
+ * Conventions (the complex conjugate of the paper's exp(+ikZ) form; every
+ * detector intensity is identical to the paper-convention one):
+ *   transmission   T = exp(i k dx (delta + i beta)), k = 2 pi / lambda
+ *   propagator     paraxial H = exp(+i dx (ky^2 + kz^2) / 2k)      [Eq. 1]
+ *                  exact    H = exp(+i dx kp^2 / (k + sqrt(k^2 - kp^2)))
+ *                  (kp >= k: exp(-dx sqrt(kp^2 - k^2)) exp(i k dx))
+ *   the global carrier exp(i k dx) of Eq. (1) is dropped (one phase per slice);
+ *   default probe  psi0[j][l] = exp(+i k sin(alpha_i) * j * dy), a plane wave
+ *                  tilted toward row 0 (incidence enters as a beam tilt in the
+ *                  sample frame instead of the object rotation of Eq. 2-3);
+ *   far field      A = sum_j psi_j exp(+2 pi i (u jy / Ny + v jz / Nz)),
+ *                  I = |A|^2 / (Ny Nz), fftshifted: row Ny/2 is the horizon.
+ *
+ * Coordinates (paper lab frame -> this library): the beam axis Z of the paper
+ * is x here (slice index s, thickness dx); the surface normal Y is y (rows,
+ * index j, row 0 is the deepest substrate row); the horizontal transverse
+ * axis X is z (columns, index l).
+ *
+ * Layouts: every field is complex64 [ny][nz] row-major (interleaved re, im);
+ * slice stacks (delta, beta and their gradients) are float32 [n_slices][ny][nz];
+ * intensities and measured amplitudes are float32 [ny][nz] in fftshifted order.
+ *
+ * Memory and ownership: every array argument is DEVICE memory owned by the
+ * caller.  The library allocates nothing; it builds its tables (FFT
+ * twiddles, propagator, probe) in the caller's workspace on every call, so it
+ * keeps no state between calls and calls on different streams with different
+ * workspaces may overlap.  Calls that share a workspace or an output must be
+ * ordered by the caller.
+ *
+ * Asynchrony: every call only enqueues work on `hip_stream` (a hipStream_t
+ * passed as void*, NULL = the null stream) and returns.  Faults during
+ * execution surface at the caller's next synchronisation.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued;
+ * on a non-OK status nothing was enqueued and outputs are untouched, and
+ * msl_last_error() returns a description.  A failing HIP launch returns
+ * MSL_ERR_HIP with HIP's error string.
+ */
+#ifndef MSL_H
+#define MSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSL_ABI_VERSION 1
+
+typedef struct { float re, im; } msl_c64;
+
+typedef enum {
+  MSL_OK = 0,
+  MSL_ERR_ARG = -1,          /* null/misaligned pointer, bad size or parameter */
+  MSL_ERR_UNSUPPORTED = -2,  /* valid request outside what the library implements */
+  MSL_ERR_WORKSPACE = -3,    /* workspace missing, misaligned or too small */
+  MSL_ERR_HIP = -4           /* a HIP runtime call or launch failed */
+} msl_status;
+
+typedef enum { MSL_PROP_PARAXIAL = 0, MSL_PROP_EXACT = 1 } msl_propagator;
+
+/* Execution schedule of the slice loop (msl_set_schedule). */
+typedef enum {
+  MSL_SCHED_AUTO = 0,        /* library choice */
+  MSL_SCHED_PER_PASS = 1,    /* one kernel launch per line pass */
+  MSL_SCHED_PERSISTENT = 2   /* one cooperative launch per phase, grid barriers between passes */
+} msl_schedule;
+
+typedef struct {
+  int32_t ny, nz;            /* rows (y) and columns (z): powers of two in [16, 1024] */
+  int32_t n_slices;          /* Ns >= 1 */
+  double  dy_nm, dz_nm;      /* transverse pixel pitch (nm), > 0 */
+  double  dx_nm;             /* slice thickness along the beam (nm), > 0 */
+  double  wavelength_nm;     /* lambda > 0 */
+  double  alpha_i_rad;       /* incidence angle (rad), |alpha| < pi/2 */
+  int32_t propagator;        /* msl_propagator */
+} msl_geometry;
+
+/* ABI version of the loaded library (MSL_ABI_VERSION). */
+int32_t msl_abi_version(void);
+
+/* Bytes of workspace every entry point below needs for geometry g when
+ * checkpoints are taken every `ckpt_every` slices (0 = no checkpoints; the
+ * adjoint needs ckpt_every >= 1).  Returns 0 if g is invalid. */
+size_t msl_workspace_bytes(const msl_geometry* g, int32_t ckpt_every);
+
+/* Number of checkpoint fields msl_forward writes: ceil(Ns / ckpt_every). */
+int32_t msl_checkpoint_count(const msl_geometry* g, int32_t ckpt_every);
+
+/* Forward multislice [Eq. 1; Sec. 1; Fig. 1 caption].
+ *   delta, beta  float32 [Ns][ny][nz]: slice-averaged refractive index
+ *                decrement and absorption index of every slice (the slice
+ *                integral of Eq. 1 is dx times these averages).
+ *   probe        complex64 [ny][nz] entrance field, or NULL for the tilted
+ *                plane wave above.
+ *   field_out    complex64 [ny][nz]: exit wave psi_Ns after the last slice
+ *                (including its propagation).  Used as scratch while running.
+ *   ckpt         NULL (then ckpt_every must be 0) or complex64
+ *                [msl_checkpoint_count][ny][nz]: ckpt[c] receives the
+ *                entrance field of slice c * ckpt_every (ckpt[0] = probe).
+ *   workspace    device memory, 256-byte aligned, >= msl_workspace_bytes. */
+msl_status msl_forward(const msl_geometry* g, const float* delta, const float* beta,
+                       const msl_c64* probe, msl_c64* field_out,
+                       msl_c64* ckpt, int32_t ckpt_every,
+                       void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Far-field detector intensity of a field [Sec. 1; Fig. 1 caption]:
+ * intensity[r][c] = |A|^2 / (ny nz) at fftshifted position (r, c), float32. */
+msl_status msl_far_field(const msl_geometry* g, const msl_c64* field, float* intensity,
+                         void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Amplitude loss of Eq. (4) [Sec. 4.1], summed (not averaged) over pixels:
+ *   loss_out[0]     (double, device) = sum (sqrt(I) - m)^2, accumulated in FP64;
+ *   grad_intensity  float32 [ny][nz] (may be NULL) = dL/dI = 1 - m / sqrt(I),
+ *                   0 where I = 0.
+ * intensity and meas_amp are float32 [ny][nz] in the same (fftshifted) order. */
+msl_status msl_amp_loss(const msl_geometry* g, const float* intensity, const float* meas_amp,
+                        double* loss_out, float* grad_intensity,
+                        void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Cotangent of a field from the cotangent of its far-field intensity:
+ * grad_field = FFT2(2 * gI * A / (ny nz)) with A the unshifted backward DFT
+ * of `field` and gI = grad_intensity moved back to unshifted order.
+ * Complex cotangents use dL = Re sum conj(g) dz (PyTorch's convention). */
+msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field,
+                                 const float* grad_intensity, msl_c64* grad_field,
+                                 void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Gradient of a real loss through the multislice recurrence (reverse sweep
+ * of Eq. 1 with checkpoint recomputation).
+ *   delta, beta, probe, ckpt, ckpt_every: exactly as given to / produced by
+ *                msl_forward (ckpt is required, ckpt_every >= 1).
+ *   grad_field   complex64 [ny][nz]: cotangent of psi_Ns.
+ *   grad_delta, grad_beta  float32 [Ns][ny][nz] (either may be NULL):
+ *                overwritten with dL/d delta and dL/d beta.
+ *   grad_probe   NULL or complex64 [ny][nz]: cotangent of the probe. */
+msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* beta,
+                       const msl_c64* probe, const msl_c64* ckpt, int32_t ckpt_every,
+                       const msl_c64* grad_field, float* grad_delta, float* grad_beta,
+                       msl_c64* grad_probe,
+                       void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Select the slice-loop schedule for later calls from this process
+ * (process-wide; not synchronised with calls running on other threads).
+ * Returns the previous setting, or MSL_ERR_ARG for an unknown value. */
+int32_t msl_set_schedule(int32_t schedule);
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char* msl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSL_H */

@@ -50,12 +50,16 @@ the beam axis, each dx thick.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import scipy.fft as sfft
 
 PARAXIAL = 0
 EXACT = 1
+
+# FFT threads: the cores this process may run on
+WORKERS = len(os.sched_getaffinity(0))
 
 
 def _g(geom, name):
@@ -121,11 +125,11 @@ def transmission(delta_s, beta_s, geom) -> np.ndarray:
 
 
 def _fft2(x):
-    return sfft.fft2(x, workers=-1)
+    return sfft.fft2(x, workers=WORKERS)
 
 
 def _ifft2(x):
-    return sfft.ifft2(x, workers=-1)
+    return sfft.ifft2(x, workers=WORKERS)
 
 
 def forward(geom, delta, beta, probe=None, keep=False):

@@ -1,0 +1,523 @@
+// libmsl: host entry points of the C ABI declared in include/msl.h, table
+// builders and kernel launches.  Multislice forward model, far field,
+// amplitude loss and adjoint of arXiv 2212.01253 (Eq. 1, Eq. 4; Sec. 1, 3, 4).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "msl.h"
+#include "msl_device.hpp"
+#include "msl_passes.hpp"
+#include "msl_persistent.hpp"
+
+using msl::Ctx;
+using msl::PassDesc;
+using msl::PhaseSpec;
+
+namespace {
+
+thread_local std::string g_last_error;
+int g_schedule = MSL_SCHED_AUTO;
+
+msl_status fail(msl_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+bool is_pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+constexpr size_t kAlign = 256;
+size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace layout (byte offsets, each region 256-byte aligned).
+struct Layout {
+  size_t twz_hi, twz_lo, twy_hi, twy_lo;
+  size_t hz_hi, hz_lo, hy_hi, hy_lo;
+  size_t H_hi, H_lo;
+  size_t bar, partials, tmp, W, G, seg;
+  size_t total;
+};
+
+constexpr int kPartials = 1024;
+
+Layout layout(const msl_geometry& g, int k) {
+  Layout L{};
+  const size_t m = (size_t)g.ny * g.nz;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
+  L.twz_hi = take(g.nz * 8);
+  L.twz_lo = take(g.nz * 8);
+  L.twy_hi = take(g.ny * 8);
+  L.twy_lo = take(g.ny * 8);
+  L.hz_hi = take(g.nz * 8);
+  L.hz_lo = take(g.nz * 8);
+  L.hy_hi = take(g.ny * 8);
+  L.hy_lo = take(g.ny * 8);
+  const bool exact = g.propagator == MSL_PROP_EXACT;
+  L.H_hi = take(exact ? m * 8 : 0);
+  L.H_lo = take(exact ? m * 8 : 0);
+  L.bar = take(kAlign);
+  L.partials = take(kPartials * sizeof(double));
+  L.tmp = take(m * 8);
+  if (k >= 1) {
+    L.W = take(m * 8);
+    L.G = take(m * 8);
+    L.seg = take((size_t)(k > 1 ? k - 1 : 0) * m * 8);
+  }
+  L.total = o;
+  return L;
+}
+
+msl_status check_geometry(const msl_geometry* g) {
+  if (!g) return fail(MSL_ERR_ARG, "geometry pointer is NULL");
+  if (!is_pow2_in(g->ny, 16, 1024) || !is_pow2_in(g->nz, 16, 1024))
+    return fail(MSL_ERR_ARG, "ny and nz must be powers of two in [16, 1024], got " +
+                                 std::to_string(g->ny) + " x " + std::to_string(g->nz));
+  if (g->n_slices < 1) return fail(MSL_ERR_ARG, "n_slices must be >= 1");
+  if (!finite_pos(g->dy_nm) || !finite_pos(g->dz_nm)) return fail(MSL_ERR_ARG, "dy_nm and dz_nm must be finite and > 0");
+  if (!finite_pos(g->dx_nm)) return fail(MSL_ERR_ARG, "dx_nm must be finite and > 0");
+  if (!finite_pos(g->wavelength_nm)) return fail(MSL_ERR_ARG, "wavelength_nm must be finite and > 0");
+  if (!std::isfinite(g->alpha_i_rad) || std::fabs(g->alpha_i_rad) >= M_PI / 2)
+    return fail(MSL_ERR_ARG, "alpha_i_rad must be finite with |alpha| < pi/2");
+  if (g->propagator != MSL_PROP_PARAXIAL && g->propagator != MSL_PROP_EXACT)
+    return fail(MSL_ERR_ARG, "propagator must be MSL_PROP_PARAXIAL (0) or MSL_PROP_EXACT (1)");
+  return MSL_OK;
+}
+
+msl_status check_ptr(const void* p, size_t align, const char* name, bool allow_null = false) {
+  if (!p) return allow_null ? MSL_OK : fail(MSL_ERR_ARG, std::string(name) + " is NULL");
+  if (!aligned(p, align)) return fail(MSL_ERR_ARG, std::string(name) + " is not " + std::to_string(align) + "-byte aligned");
+  return MSL_OK;
+}
+
+msl_status check_ws(const msl_geometry& g, int k, const void* ws, size_t ws_bytes) {
+  const size_t need = layout(g, k).total;
+  if (!ws) return fail(MSL_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(ws, kAlign)) return fail(MSL_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(MSL_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes, got " +
+                                       std::to_string(ws_bytes));
+  return MSL_OK;
+}
+
+#define MSL_TRY(expr)                     \
+  do {                                    \
+    msl_status _s = (expr);               \
+    if (_s != MSL_OK) return _s;          \
+  } while (0)
+
+msl_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(MSL_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return MSL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// table builders (FP64 arithmetic, results split into float32 hi + lo)
+
+__device__ inline void split_store(double re, double im, float2* hi, float2* lo, int64_t i) {
+  const float hr = (float)re, hm = (float)im;
+  hi[i] = make_float2(hr, hm);
+  lo[i] = make_float2((float)(re - (double)hr), (float)(im - (double)hm));
+}
+
+// Angular spatial frequency of DFT bin m of an n-point grid with pitch d:
+// 2 pi f / (n d) with f = m for m < n/2 and m - n otherwise.
+__device__ inline double kfreq(int m, int n, double d) {
+  const int f = m < n / 2 ? m : m - n;
+  return 2.0 * M_PI * (double)f / ((double)n * d);
+}
+
+// Twiddles W_n^e = exp(-2 pi i e / n), e < n.
+__global__ void k_twiddles(int n, float2* hi, float2* lo) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s, c;
+  sincospi(-2.0 * (double)e / (double)n, &s, &c);
+  split_store(c, s, hi, lo, e);
+}
+
+// Paraxial one-axis propagator factor exp(+i dx kq^2 / 2k) / n.
+__global__ void k_hpar(int n, double d, double dx, double k, float2* hi, float2* lo) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const double q = kfreq(m, n, d);
+  const double ph = dx * q * q / (2.0 * k);
+  double s, c;
+  sincos(ph, &s, &c);
+  split_store(c / n, s / n, hi, lo, m);
+}
+
+// Exact angular-spectrum propagator H[my][mz] / ny.
+__global__ void k_hexact(int ny, int nz, double dy, double dz, double dx, double k, float2* hi, float2* lo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ny * nz) return;
+  const int my = (int)(i / nz), mz = (int)(i % nz);
+  const double ky = kfreq(my, ny, dy), kz = kfreq(mz, nz, dz);
+  const double kp2 = ky * ky + kz * kz;
+  double re, im;
+  if (kp2 < k * k) {
+    const double ph = dx * kp2 / (k + sqrt(k * k - kp2));
+    sincos(ph, &im, &re);
+  } else {
+    const double amp = exp(-dx * sqrt(kp2 - k * k));
+    double s, c;
+    sincos(fmod(k * dx, 2.0 * M_PI), &s, &c);
+    re = amp * c;
+    im = amp * s;
+  }
+  split_store(re / ny, im / ny, hi, lo, i);
+}
+
+// Tilted plane wave exp(+i k sin(alpha) j dy).
+__global__ void k_probe(int ny, int nz, double q, float2* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ny * nz) return;
+  const int j = (int)(i / nz);
+  double s, c;
+  sincos(fmod(q * (double)j, 2.0 * M_PI), &s, &c);
+  out[i] = make_float2((float)c, (float)s);
+}
+
+// Amplitude loss partial sums (FP64) and dL/dI.
+__global__ void __launch_bounds__(256) k_amp_loss(const float* I, const float* mamp, float* gI,
+                                                  double* partials, int64_t n) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = sqrt((double)I[i]);
+    const double r = a - (double)mamp[i];
+    acc += r * r;
+    if (gI) gI[i] = a > 0.0 ? (float)(1.0 - (double)mamp[i] / a) : 0.0f;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(const double* partials, int n, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// per-pass launches
+
+template <int N, int AXIS>
+__global__ void __launch_bounds__(128) k_pass(Ctx c, PassDesc pd) {
+  __shared__ float2 lds[1152];
+  constexpr int L = N / 8;
+  const int g = threadIdx.x / L, j = threadIdx.x % L;
+  const int G = blockDim.x / L;
+  const int group = msl::xcd_group(blockIdx.x, gridDim.x);
+  msl::run_line<N, AXIS>(c, pd, group * G + g, j, lds + g * (N + N / 8));
+}
+
+template <int N, int AXIS>
+hipError_t launch_pass_t(const Ctx& c, const PassDesc& pd, hipStream_t st) {
+  const int nlines = AXIS == msl::ROW ? c.ny : c.nz;
+  constexpr int L = N / 8;
+  int G = L >= 64 ? 1 : 64 / L;
+  if (G > nlines) G = nlines;
+  hipLaunchKernelGGL((k_pass<N, AXIS>), dim3(nlines / G), dim3(L * G), 0, st, c, pd);
+  return hipGetLastError();
+}
+
+template <int AXIS>
+hipError_t launch_pass_axis(int n, const Ctx& c, const PassDesc& pd, hipStream_t st) {
+  switch (n) {
+    case 16: return launch_pass_t<16, AXIS>(c, pd, st);
+    case 32: return launch_pass_t<32, AXIS>(c, pd, st);
+    case 64: return launch_pass_t<64, AXIS>(c, pd, st);
+    case 128: return launch_pass_t<128, AXIS>(c, pd, st);
+    case 256: return launch_pass_t<256, AXIS>(c, pd, st);
+    case 512: return launch_pass_t<512, AXIS>(c, pd, st);
+    case 1024: return launch_pass_t<1024, AXIS>(c, pd, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pass(const Ctx& c, const PassDesc& pd, hipStream_t st) {
+  return pd.axis == msl::ROW ? launch_pass_axis<msl::ROW>(c.nz, c, pd, st)
+                             : launch_pass_axis<msl::COL>(c.ny, c, pd, st);
+}
+
+// ---------------------------------------------------------------------------
+// call setup
+
+struct Call {
+  msl_geometry g;
+  Layout L;
+  Ctx c;
+  char* ws;
+  hipStream_t st;
+};
+
+Call make_call(const msl_geometry& g, int k, void* ws, hipStream_t st) {
+  Call k_{};
+  k_.g = g;
+  k_.L = layout(g, k);
+  k_.ws = static_cast<char*>(ws);
+  k_.st = st;
+  Ctx& c = k_.c;
+  auto P = [&](size_t off) { return reinterpret_cast<float2*>(k_.ws + off); };
+  c.ny = g.ny;
+  c.nz = g.nz;
+  c.m = (int64_t)g.ny * g.nz;
+  c.twz_hi = P(k_.L.twz_hi);
+  c.twz_lo = P(k_.L.twz_lo);
+  c.twy_hi = P(k_.L.twy_hi);
+  c.twy_lo = P(k_.L.twy_lo);
+  c.hz_hi = P(k_.L.hz_hi);
+  c.hz_lo = P(k_.L.hz_lo);
+  c.hy_hi = P(k_.L.hy_hi);
+  c.hy_lo = P(k_.L.hy_lo);
+  c.H_hi = P(k_.L.H_hi);
+  c.H_lo = P(k_.L.H_lo);
+  const double kk = 2.0 * M_PI / g.wavelength_nm;
+  const double kdx = kk * g.dx_nm;
+  c.kdx_hi = (float)kdx;
+  c.kdx_lo = (float)(kdx - (double)c.kdx_hi);
+  c.inv_m = 1.0f / (float)c.m;
+  return k_;
+}
+
+msl_status build_tables(const Call& k, bool need_prop) {
+  const msl_geometry& g = k.g;
+  auto P = [&](size_t off) { return reinterpret_cast<float2*>(k.ws + off); };
+  const int tb = 256;
+  hipLaunchKernelGGL(k_twiddles, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, k.st, g.nz, P(k.L.twz_hi), P(k.L.twz_lo));
+  hipLaunchKernelGGL(k_twiddles, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, k.st, g.ny, P(k.L.twy_hi), P(k.L.twy_lo));
+  if (need_prop) {
+    const double kk = 2.0 * M_PI / g.wavelength_nm;
+    if (g.propagator == MSL_PROP_PARAXIAL) {
+      hipLaunchKernelGGL(k_hpar, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, k.st, g.nz, g.dz_nm, g.dx_nm, kk,
+                         P(k.L.hz_hi), P(k.L.hz_lo));
+      hipLaunchKernelGGL(k_hpar, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, k.st, g.ny, g.dy_nm, g.dx_nm, kk,
+                         P(k.L.hy_hi), P(k.L.hy_lo));
+    } else {
+      const int64_t m = (int64_t)g.ny * g.nz;
+      hipLaunchKernelGGL(k_hexact, dim3((unsigned)((m + tb - 1) / tb)), dim3(tb), 0, k.st, g.ny, g.nz, g.dy_nm,
+                         g.dz_nm, g.dx_nm, kk, P(k.L.H_hi), P(k.L.H_lo));
+    }
+  }
+  return hip_check(hipGetLastError(), "table kernels");
+}
+
+msl_status run_phase(const Call& k, const PhaseSpec& ph) {
+  const int np = msl::phase_npasses(ph);
+  if (np == 0) return MSL_OK;
+  const bool persistent = (g_schedule == MSL_SCHED_PERSISTENT) ||
+                          (g_schedule == MSL_SCHED_AUTO && msl::persistent_preferred(k.c, np));
+  if (persistent) {
+    hipError_t e = msl::launch_persistent(k.c, ph, np, reinterpret_cast<unsigned*>(k.ws + k.L.bar), k.st);
+    if (e == hipSuccess) return MSL_OK;
+    if (g_schedule == MSL_SCHED_PERSISTENT) return hip_check(e, "persistent pass kernel");
+    (void)hipGetLastError();  // AUTO: the per-pass schedule below does the same work
+  }
+  for (int p = 0; p < np; ++p) {
+    const PassDesc pd = msl::phase_pass(ph, p);
+    hipError_t e = launch_pass(k.c, pd, k.st);
+    if (e != hipSuccess) return hip_check(e, "pass kernel");
+  }
+  return MSL_OK;
+}
+
+msl_status copy_field(const Call& k, void* dst, const void* src) {
+  return hip_check(hipMemcpyAsync(dst, src, (size_t)k.c.m * 8, hipMemcpyDeviceToDevice, k.st), "hipMemcpyAsync");
+}
+
+PhaseSpec blank_phase(const Call& k, int kind) {
+  PhaseSpec ph{};
+  ph.kind = kind;
+  ph.exact = k.g.propagator == MSL_PROP_EXACT;
+  ph.ns = k.g.n_slices;
+  ph.m = k.c.m;
+  return ph;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int32_t msl_abi_version(void) { return MSL_ABI_VERSION; }
+
+const char* msl_last_error(void) { return g_last_error.c_str(); }
+
+int32_t msl_set_schedule(int32_t schedule) {
+  if (schedule != MSL_SCHED_AUTO && schedule != MSL_SCHED_PER_PASS && schedule != MSL_SCHED_PERSISTENT) {
+    g_last_error = "unknown schedule " + std::to_string(schedule);
+    return MSL_ERR_ARG;
+  }
+  const int prev = g_schedule;
+  g_schedule = schedule;
+  return prev;
+}
+
+size_t msl_workspace_bytes(const msl_geometry* g, int32_t ckpt_every) {
+  if (check_geometry(g) != MSL_OK || ckpt_every < 0) return 0;
+  return layout(*g, ckpt_every).total;
+}
+
+int32_t msl_checkpoint_count(const msl_geometry* g, int32_t ckpt_every) {
+  if (check_geometry(g) != MSL_OK || ckpt_every < 1) return 0;
+  return (g->n_slices + ckpt_every - 1) / ckpt_every;
+}
+
+msl_status msl_forward(const msl_geometry* g, const float* delta, const float* beta, const msl_c64* probe,
+                       msl_c64* field_out, msl_c64* ckpt, int32_t ckpt_every, void* workspace, size_t ws_bytes,
+                       void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  MSL_TRY(check_ptr(delta, 4, "delta"));
+  MSL_TRY(check_ptr(beta, 4, "beta"));
+  MSL_TRY(check_ptr(probe, 8, "probe", true));
+  MSL_TRY(check_ptr(field_out, 8, "field_out"));
+  MSL_TRY(check_ptr(ckpt, 8, "ckpt", true));
+  if (ckpt && ckpt_every < 1) return fail(MSL_ERR_ARG, "ckpt given but ckpt_every < 1");
+  if (!ckpt && ckpt_every != 0) return fail(MSL_ERR_ARG, "ckpt_every != 0 but ckpt is NULL");
+  MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
+  Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
+  k.c.delta = delta;
+  k.c.beta = beta;
+  MSL_TRY(build_tables(k, true));
+  float2* f = reinterpret_cast<float2*>(field_out);
+  if (probe) {
+    MSL_TRY(copy_field(k, f, probe));
+  } else {
+    const double q = 2.0 * M_PI / g->wavelength_nm * std::sin(g->alpha_i_rad) * g->dy_nm;
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)((k.c.m + 255) / 256)), dim3(256), 0, k.st, g->ny, g->nz, q, f);
+    MSL_TRY(hip_check(hipGetLastError(), "probe kernel"));
+  }
+  PhaseSpec ph = blank_phase(k, msl::PH_FWD_FULL);
+  ph.s0 = 0;
+  ph.s1 = g->n_slices;
+  ph.field = f;
+  ph.ckpt = reinterpret_cast<float2*>(ckpt);
+  ph.ckpt_every = ckpt ? ckpt_every : 0;
+  return run_phase(k, ph);
+}
+
+msl_status msl_far_field(const msl_geometry* g, const msl_c64* field, float* intensity, void* workspace,
+                         size_t ws_bytes, void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  MSL_TRY(check_ptr(field, 8, "field"));
+  MSL_TRY(check_ptr(intensity, 4, "intensity"));
+  MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
+  Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
+  k.c.intensity = intensity;
+  MSL_TRY(build_tables(k, false));
+  PhaseSpec ph = blank_phase(k, msl::PH_FF);
+  ph.ff_src = reinterpret_cast<const float2*>(field);
+  ph.ff_tmp = reinterpret_cast<float2*>(k.ws + k.L.tmp);
+  return run_phase(k, ph);
+}
+
+msl_status msl_amp_loss(const msl_geometry* g, const float* intensity, const float* meas_amp, double* loss_out,
+                        float* grad_intensity, void* workspace, size_t ws_bytes, void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  MSL_TRY(check_ptr(intensity, 4, "intensity"));
+  MSL_TRY(check_ptr(meas_amp, 4, "meas_amp"));
+  MSL_TRY(check_ptr(loss_out, 8, "loss_out"));
+  MSL_TRY(check_ptr(grad_intensity, 4, "grad_intensity", true));
+  MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
+  Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
+  double* partials = reinterpret_cast<double*>(k.ws + k.L.partials);
+  const int64_t m = k.c.m;
+  int blocks = (int)((m + 255) / 256);
+  if (blocks > kPartials) blocks = kPartials;
+  hipLaunchKernelGGL(k_amp_loss, dim3(blocks), dim3(256), 0, k.st, intensity, meas_amp, grad_intensity, partials, m);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, k.st, partials, blocks, loss_out);
+  return hip_check(hipGetLastError(), "loss kernels");
+}
+
+msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field, const float* grad_intensity,
+                                 msl_c64* grad_field, void* workspace, size_t ws_bytes, void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  MSL_TRY(check_ptr(field, 8, "field"));
+  MSL_TRY(check_ptr(grad_intensity, 4, "grad_intensity"));
+  MSL_TRY(check_ptr(grad_field, 8, "grad_field"));
+  MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
+  Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
+  k.c.grad_intensity = grad_intensity;
+  MSL_TRY(build_tables(k, false));
+  PhaseSpec ph = blank_phase(k, msl::PH_FFADJ);
+  ph.ff_src = reinterpret_cast<const float2*>(field);
+  ph.ff_tmp = reinterpret_cast<float2*>(grad_field);
+  return run_phase(k, ph);
+}
+
+msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* beta, const msl_c64* probe,
+                       const msl_c64* ckpt, int32_t ckpt_every, const msl_c64* grad_field, float* grad_delta,
+                       float* grad_beta, msl_c64* grad_probe, void* workspace, size_t ws_bytes,
+                       void* hip_stream) {
+  (void)probe;  // the probe is ckpt[0]
+  MSL_TRY(check_geometry(g));
+  MSL_TRY(check_ptr(delta, 4, "delta"));
+  MSL_TRY(check_ptr(beta, 4, "beta"));
+  MSL_TRY(check_ptr(probe, 8, "probe", true));
+  MSL_TRY(check_ptr(ckpt, 8, "ckpt"));
+  if (ckpt_every < 1) return fail(MSL_ERR_ARG, "ckpt_every must be >= 1 for the adjoint");
+  MSL_TRY(check_ptr(grad_field, 8, "grad_field"));
+  MSL_TRY(check_ptr(grad_delta, 4, "grad_delta", true));
+  MSL_TRY(check_ptr(grad_beta, 4, "grad_beta", true));
+  MSL_TRY(check_ptr(grad_probe, 8, "grad_probe", true));
+  MSL_TRY(check_ws(*g, ckpt_every, workspace, ws_bytes));
+  Call k = make_call(*g, ckpt_every, workspace, static_cast<hipStream_t>(hip_stream));
+  k.c.delta = delta;
+  k.c.beta = beta;
+  k.c.gdelta = grad_delta;
+  k.c.gbeta = grad_beta;
+  MSL_TRY(build_tables(k, true));
+  float2* W = reinterpret_cast<float2*>(k.ws + k.L.W);
+  float2* G = reinterpret_cast<float2*>(k.ws + k.L.G);
+  float2* seg = reinterpret_cast<float2*>(k.ws + k.L.seg);
+  const float2* ck = reinterpret_cast<const float2*>(ckpt);
+  MSL_TRY(copy_field(k, G, grad_field));
+  const int ns = g->n_slices;
+  const int nck = (ns + ckpt_every - 1) / ckpt_every;
+  for (int c = nck - 1; c >= 0; --c) {
+    const int s0 = c * ckpt_every;
+    const int s1 = s0 + ckpt_every < ns ? s0 + ckpt_every : ns;
+    const float2* ckc = ck + (int64_t)c * k.c.m;
+    if (s1 - s0 >= 2) {
+      MSL_TRY(copy_field(k, W, ckc));
+      PhaseSpec ph = blank_phase(k, msl::PH_FWD_RECOMP);
+      ph.s0 = s0;
+      ph.s1 = s1;
+      ph.field = W;
+      ph.seg = seg;
+      MSL_TRY(run_phase(k, ph));
+    }
+    PhaseSpec rv = blank_phase(k, msl::PH_REV);
+    rv.s0 = s0;
+    rv.s1 = s1;
+    rv.leading = c == nck - 1;
+    rv.field = G;
+    rv.seg = seg;
+    rv.ckpt_c = ckc;
+    MSL_TRY(run_phase(k, rv));
+  }
+  if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));
+  return MSL_OK;
+}
+
+}  // extern "C"

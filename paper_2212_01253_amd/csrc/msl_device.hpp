@@ -1,0 +1,369 @@
+// Device building blocks of libmsl: compensated complex arithmetic, the
+// register/LDS line FFT, the slice transmission and the line-pass program.
+//
+// Numerical design.  The multislice recurrence (Eq. 1 of arXiv 2212.01253)
+// applies the same propagator, FFT twiddles and (for a bar that spans many
+// slices) the same transmission value thousands of times.  A constant rounded
+// once to float32 therefore contributes the same relative error at every
+// slice and the errors add up linearly with the slice count, while the
+// rounding of data-dependent sums and products behaves like a random walk.
+// Every multiplication by a constant (FFT twiddles, the radix-8 internal
+// factor sqrt(1/2), the propagator) is thus done with a two-term (hi + lo)
+// float32 constant applied through FMAs, and the transmission is applied as
+// psi + psi * (T - 1) with T - 1 evaluated directly, so that its rounding is
+// relative to the small quantity T - 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msl {
+
+enum Axis : int { ROW = 0, COL = 1 };  // ROW: line along z (contiguous), COL: along y
+
+enum PreOp : int { PRE_NONE = 0, PRE_PROP = 1, PRE_FFT = 2, PRE_IFFT_N = 3, PRE_IFFT_U = 4 };
+enum MidOp : int { MID_NONE = 0, MID_T_FWD = 1, MID_T_ADJ = 2, MID_FF_OUT = 3, MID_FF_SEED = 4 };
+enum PostOp : int { POST_NONE = 0, POST_PROP = 1, POST_FFT = 2, POST_PROP2D = 3 };
+
+// One sweep over all lines of one axis.
+struct PassDesc {
+  int axis;
+  int pre, mid, post;
+  int conj;             // adjoint: use conj(h) / conj(H)
+  int slice;            // slice index of the transmission step
+  const float2* src;    // field read
+  float2* dst;          // field written (may equal src; nullptr = not written)
+  float2* psi_store;    // store the line before the mid step (nullptr = no)
+  const float2* psi_load;  // entrance field psi_s for the adjoint step
+};
+
+// Everything a pass reads besides the descriptor.
+struct Ctx {
+  int ny, nz;
+  int64_t m;                        // ny * nz
+  const float* delta;               // [Ns][ny][nz]
+  const float* beta;
+  float* gdelta;                    // [Ns][ny][nz] or nullptr
+  float* gbeta;
+  const float2* twz_hi; const float2* twz_lo;   // W_nz^e, e < nz
+  const float2* twy_hi; const float2* twy_lo;   // W_ny^e, e < ny
+  const float2* hz_hi; const float2* hz_lo;     // paraxial h_z / nz (DFT order)
+  const float2* hy_hi; const float2* hy_lo;     // paraxial h_y / ny
+  const float2* H_hi; const float2* H_lo;       // exact H[ky][kz] / ny
+  float kdx_hi, kdx_lo;             // k * dx as a two-term float
+  float inv_m;                      // 1 / (ny nz)
+  float* intensity;                 // far-field output (fftshifted) or nullptr
+  const float* grad_intensity;      // far-field seed input (fftshifted) or nullptr
+};
+
+// ---------------------------------------------------------------------------
+// complex helpers
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// x * (wh + wl), or x * conj(wh + wl) when CONJ; the small product x*wl is
+// formed first and folded into the rounding of the main product.
+template <bool CONJ>
+__device__ __forceinline__ float2 cmul_comp(float2 x, float2 wh, float2 wl) {
+  const float whi = CONJ ? -wh.y : wh.y;
+  const float wli = CONJ ? -wl.y : wl.y;
+  const float cr = __builtin_fmaf(x.x, wl.x, -(x.y * wli));
+  const float ci = __builtin_fmaf(x.x, wli, x.y * wl.x);
+  const float re = __builtin_fmaf(x.x, wh.x, __builtin_fmaf(-x.y, whi, cr));
+  const float im = __builtin_fmaf(x.x, whi, __builtin_fmaf(x.y, wh.x, ci));
+  return make_float2(re, im);
+}
+
+__device__ __forceinline__ float2 cmul_comp_dyn(float2 x, float2 wh, float2 wl, bool conj) {
+  return conj ? cmul_comp<true>(x, wh, wl) : cmul_comp<false>(x, wh, wl);
+}
+
+// sqrt(1/2) as hi + lo float32 (hi = nearest float, lo = nearest float of the rest)
+constexpr float RS2_HI = 0.70710677f;
+constexpr float RS2_LO = 1.21016175e-08f;
+
+__device__ __forceinline__ float scale_rs2(float s) { return __builtin_fmaf(s, RS2_HI, s * RS2_LO); }
+
+// 4-point DFT, forward (W4 = -i) or inverse (W4 = +i), unnormalised.
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 y0, float2 y1, float2 y2, float2 y3,
+                                     float2& Y0, float2& Y1, float2& Y2, float2& Y3) {
+  const float2 c0 = cadd(y0, y2), c1 = csub(y0, y2), c2 = cadd(y1, y3), d = csub(y1, y3);
+  const float2 c3 = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+  Y0 = cadd(c0, c2);
+  Y2 = csub(c0, c2);
+  Y1 = cadd(c1, c3);
+  Y3 = csub(c1, c3);
+}
+
+// 8-point DFT in place: v[k] <- sum_n v[n] W8^{+-nk}.
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+  const float2 a0 = cadd(v[0], v[4]), a1 = cadd(v[1], v[5]), a2 = cadd(v[2], v[6]), a3 = cadd(v[3], v[7]);
+  float2 b0 = csub(v[0], v[4]), b1 = csub(v[1], v[5]), b2 = csub(v[2], v[6]), b3 = csub(v[3], v[7]);
+  if (!INV) {
+    b1 = make_float2(scale_rs2(b1.x + b1.y), scale_rs2(b1.y - b1.x));    // * (1 - i)/sqrt2
+    b2 = make_float2(b2.y, -b2.x);                                      // * -i
+    b3 = make_float2(scale_rs2(b3.y - b3.x), -scale_rs2(b3.x + b3.y));  // * (-1 - i)/sqrt2
+  } else {
+    b1 = make_float2(scale_rs2(b1.x - b1.y), scale_rs2(b1.x + b1.y));   // * (1 + i)/sqrt2
+    b2 = make_float2(-b2.y, b2.x);                                      // * +i
+    b3 = make_float2(-scale_rs2(b3.x + b3.y), scale_rs2(b3.x - b3.y));  // * (-1 + i)/sqrt2
+  }
+  dft4<INV>(a0, a1, a2, a3, v[0], v[2], v[4], v[6]);
+  dft4<INV>(b0, b1, b2, b3, v[1], v[3], v[5], v[7]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  const float2 s = cadd(a, b), d = csub(a, b);
+  a = s;
+  b = d;
+}
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+// Line FFT of N points held by N/8 lanes, 8 points per lane.  On entry and on
+// exit lane j holds element j + t*N/8 in v[t] ("t-layout", natural order).
+// Stockham autosort: a first stage of radix 2, 4 or 8 without twiddles, then
+// radix-8 stages; every stage but the last exchanges through LDS (padded one
+// slot in eight to spread the stride-8 writes over the banks).  All threads
+// of the block call it together (it contains block barriers).
+template <int N, bool INV>
+__device__ __forceinline__ void fft_line(float2 (&v)[8], float2* sh, int j,
+                                         const float2* __restrict__ twh,
+                                         const float2* __restrict__ twl) {
+  constexpr int L = N / 8;
+  constexpr int LG = ilog2c(N);
+  constexpr int R0 = (LG % 3 == 0) ? 8 : ((LG % 3 == 1) ? 2 : 4);
+  // ---- stage 0: radix R0, sub-length 1, trivial twiddles
+  __syncthreads();
+  if constexpr (R0 == 8) {
+    dft8<INV>(v);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) sh[lds_pad(8 * j + r)] = v[r];
+  } else if constexpr (R0 == 4) {
+    float2 y[4];
+    dft4<INV>(v[0], v[2], v[4], v[6], y[0], y[1], y[2], y[3]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sh[lds_pad(4 * j + r)] = y[r];
+    dft4<INV>(v[1], v[3], v[5], v[7], y[0], y[1], y[2], y[3]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sh[lds_pad(4 * (j + L) + r)] = y[r];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float2 a = v[q], b = v[q + 4];
+      dft2<INV>(a, b);
+      sh[lds_pad(2 * (j + q * L))] = a;
+      sh[lds_pad(2 * (j + q * L) + 1)] = b;
+    }
+  }
+  __syncthreads();
+  // ---- radix-8 stages with sub-length NS = R0, 8 R0, ...
+#pragma unroll
+  for (int NS = R0; NS < N; NS *= 8) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = sh[lds_pad(j + t * L)];
+    const int jm = j % NS;
+    const int step = N / (8 * NS);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      const int e = jm * r * step;
+      v[r] = cmul_comp<INV>(v[r], twh[e], twl[e]);
+    }
+    dft8<INV>(v);
+    if (NS * 8 < N) {
+      const int base = (j / NS) * NS * 8 + jm;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) sh[lds_pad(base + r * NS)] = v[r];
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// slice transmission
+
+// Returns T - 1 for T = exp(i a - b): Taylor forms for |a|, |b| <= 1/8 (all
+// workloads of interest: k dx delta is ~1e-2), library functions otherwise.
+__device__ __forceinline__ float2 transmission_m1(float a, float b) {
+  float sa, sh, em1;
+  if (fabsf(a) <= 0.125f) {
+    const float a2 = a * a;
+    // sin x = x (1 - x^2/6 (1 - x^2/20 (1 - x^2/42)))
+    sa = a * __builtin_fmaf(-a2 * (1.0f / 6.0f),
+                            __builtin_fmaf(-a2 * (1.0f / 20.0f),
+                                           __builtin_fmaf(-a2, 1.0f / 42.0f, 1.0f), 1.0f), 1.0f);
+    const float h = 0.5f * a, h2 = h * h;
+    sh = h * __builtin_fmaf(-h2 * (1.0f / 6.0f),
+                            __builtin_fmaf(-h2 * (1.0f / 20.0f),
+                                           __builtin_fmaf(-h2, 1.0f / 42.0f, 1.0f), 1.0f), 1.0f);
+  } else {
+    sa = sinf(a);
+    sh = sinf(0.5f * a);
+  }
+  if (fabsf(b) <= 0.125f) {
+    // expm1(-b) = -b (1 - b/2 (1 - b/3 (1 - b/4 (1 - b/5 (1 - b/6 (1 - b/7))))))
+    float p = __builtin_fmaf(-b, 1.0f / 7.0f, 1.0f);
+    p = __builtin_fmaf(-b * (1.0f / 6.0f), p, 1.0f);
+    p = __builtin_fmaf(-b * (1.0f / 5.0f), p, 1.0f);
+    p = __builtin_fmaf(-b * (1.0f / 4.0f), p, 1.0f);
+    p = __builtin_fmaf(-b * (1.0f / 3.0f), p, 1.0f);
+    p = __builtin_fmaf(-b * 0.5f, p, 1.0f);
+    em1 = -b * p;
+  } else {
+    em1 = expm1f(-b);
+  }
+  const float cm1 = -2.0f * sh * sh;  // cos a - 1
+  // T - 1 = (1 + em1)(1 + cm1 + i sa) - 1
+  return make_float2(__builtin_fmaf(em1, cm1, cm1 + em1), __builtin_fmaf(em1, sa, sa));
+}
+
+// psi * T  = psi + psi (T - 1)
+__device__ __forceinline__ float2 apply_t(float2 p, float2 tm1) {
+  return make_float2(__builtin_fmaf(p.x, tm1.x, __builtin_fmaf(-p.y, tm1.y, p.x)),
+                     __builtin_fmaf(p.x, tm1.y, __builtin_fmaf(p.y, tm1.x, p.y)));
+}
+
+// g * conj(T) = g + g conj(T - 1)
+__device__ __forceinline__ float2 apply_tconj(float2 g, float2 tm1) {
+  return make_float2(__builtin_fmaf(g.x, tm1.x, __builtin_fmaf(g.y, tm1.y, g.x)),
+                     __builtin_fmaf(-g.x, tm1.y, __builtin_fmaf(g.y, tm1.x, g.y)));
+}
+
+__device__ __forceinline__ float phase_arg(float d, const Ctx& c) {
+  return __builtin_fmaf(d, c.kdx_hi, d * c.kdx_lo);
+}
+
+// ---------------------------------------------------------------------------
+// one line of one pass
+
+template <int N, int AXIS>
+__device__ __forceinline__ int64_t line_addr(const Ctx& c, int line, int i) {
+  return AXIS == ROW ? (int64_t)line * c.nz + i : (int64_t)i * c.nz + line;
+}
+
+template <int N, int AXIS>
+__device__ __forceinline__ void prop_line(float2 (&v)[8], float2* sh, int j, const Ctx& c, bool conj) {
+  constexpr int L = N / 8;
+  const float2* twh = AXIS == ROW ? c.twz_hi : c.twy_hi;
+  const float2* twl = AXIS == ROW ? c.twz_lo : c.twy_lo;
+  const float2* hh = AXIS == ROW ? c.hz_hi : c.hy_hi;
+  const float2* hl = AXIS == ROW ? c.hz_lo : c.hy_lo;
+  fft_line<N, false>(v, sh, j, twh, twl);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = cmul_comp_dyn(v[t], hh[j + t * L], hl[j + t * L], conj);
+  fft_line<N, true>(v, sh, j, twh, twl);
+}
+
+// y-FFT, multiply by the 2-D propagator (already divided by ny), y-IFFT;
+// only for columns (the field is in (y, kz) order, kz = line).
+template <int N, int AXIS>
+__device__ __forceinline__ void prop2d_line(float2 (&v)[8], float2* sh, int j, int line, const Ctx& c,
+                                            bool conj) {
+  constexpr int L = N / 8;
+  fft_line<N, false>(v, sh, j, c.twy_hi, c.twy_lo);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t e = (int64_t)(j + t * L) * c.nz + line;
+    v[t] = cmul_comp_dyn(v[t], c.H_hi[e], c.H_lo[e], conj);
+  }
+  fft_line<N, true>(v, sh, j, c.twy_hi, c.twy_lo);
+}
+
+template <int N, int AXIS>
+__device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
+  constexpr int L = N / 8;
+  const float2* twh = AXIS == ROW ? c.twz_hi : c.twy_hi;
+  const float2* twl = AXIS == ROW ? c.twz_lo : c.twy_lo;
+  const float inv_n = 1.0f / (float)N;
+  float2 v[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = pd.src[line_addr<N, AXIS>(c, line, j + t * L)];
+
+  switch (pd.pre) {
+    case PRE_PROP: prop_line<N, AXIS>(v, sh, j, c, pd.conj != 0); break;
+    case PRE_FFT: fft_line<N, false>(v, sh, j, twh, twl); break;
+    case PRE_IFFT_N:
+      fft_line<N, true>(v, sh, j, twh, twl);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = make_float2(v[t].x * inv_n, v[t].y * inv_n);
+      break;
+    case PRE_IFFT_U: fft_line<N, true>(v, sh, j, twh, twl); break;
+    default: break;
+  }
+
+  if (pd.psi_store) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) pd.psi_store[line_addr<N, AXIS>(c, line, j + t * L)] = v[t];
+  }
+
+  if (pd.mid == MID_T_FWD) {
+    const int64_t so = (int64_t)pd.slice * c.m;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t e = so + line_addr<N, AXIS>(c, line, j + t * L);
+      v[t] = apply_t(v[t], transmission_m1(phase_arg(c.delta[e], c), phase_arg(c.beta[e], c)));
+    }
+  } else if (pd.mid == MID_T_ADJ) {
+    const int64_t so = (int64_t)pd.slice * c.m;
+    const float kdx = c.kdx_hi;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t a = line_addr<N, AXIS>(c, line, j + t * L);
+      const int64_t e = so + a;
+      const float2 tm1 = transmission_m1(phase_arg(c.delta[e], c), phase_arg(c.beta[e], c));
+      const float2 pt = apply_t(pd.psi_load[a], tm1);  // psi'_s = T_s psi_s
+      const float2 g = v[t];                           // cotangent of psi'_s
+      // conj(g) * psi' = (gx px + gy py) + i (gx py - gy px)
+      const float cre = __builtin_fmaf(g.x, pt.x, g.y * pt.y);
+      const float cim = __builtin_fmaf(g.x, pt.y, -(g.y * pt.x));
+      if (c.gdelta) c.gdelta[e] = -kdx * cim;
+      if (c.gbeta) c.gbeta[e] = -kdx * cre;
+      v[t] = apply_tconj(g, tm1);
+    }
+  } else if (pd.mid == MID_FF_OUT) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = j + t * L;
+      const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
+      const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
+      const float p = __builtin_fmaf(v[t].x, v[t].x, v[t].y * v[t].y);
+      c.intensity[(int64_t)rs * c.nz + cs] = p * c.inv_m;
+    }
+  } else if (pd.mid == MID_FF_SEED) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = j + t * L;
+      const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
+      const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
+      const float s = 2.0f * c.inv_m * c.grad_intensity[(int64_t)rs * c.nz + cs];
+      v[t] = make_float2(v[t].x * s, v[t].y * s);
+    }
+  }
+
+  switch (pd.post) {
+    case POST_PROP: prop_line<N, AXIS>(v, sh, j, c, pd.conj != 0); break;
+    case POST_FFT: fft_line<N, false>(v, sh, j, twh, twl); break;
+    case POST_PROP2D: prop2d_line<N, AXIS>(v, sh, j, line, c, pd.conj != 0); break;
+    default: break;
+  }
+
+  if (pd.dst) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) pd.dst[line_addr<N, AXIS>(c, line, j + t * L)] = v[t];
+  }
+}
+
+// Workgroups are dealt to the XCDs round robin; give each XCD a contiguous
+// range of lines so that column passes of one XCD share cache lines in its L2.
+__device__ __forceinline__ int xcd_group(int b, int n) {
+  return (n % 8 == 0) ? (b % 8) * (n / 8) + b / 8 : b;
+}
+
+}  // namespace msl

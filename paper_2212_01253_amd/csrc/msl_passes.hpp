@@ -1,0 +1,210 @@
+// Pass programs: which line passes make up each phase of the multislice
+// forward sweep, the adjoint sweep and the far field.
+//
+// Paraxial propagator.  The Fresnel propagator of Eq. (1) (arXiv 2212.01253)
+// factorises, exp(i dx (ky^2 + kz^2)/2k) = h_y(ky) h_z(kz), so one slice's
+// 2-D propagation is the product of a propagation along rows (P_z) and one
+// along columns (P_y), and the two commute.  Alternating the order from one
+// slice to the next puts the two halves that touch the same axis side by
+// side:  T_0, P_z | P_y, T_1, P_y | P_z, T_2, P_z | ...  so every slice is
+// ONE pass over lines of one axis: propagate, transmit, propagate.  That is
+// one field round trip and one global exchange per slice instead of two.
+//
+// Exact angular-spectrum propagator.  It does not factorise; each slice takes
+// a row pass (z-IFFT, transmission, z-FFT) and a column pass (y-FFT, H, y-IFFT)
+// with the field kept in (y, kz) order between them.
+#pragma once
+
+#include "msl_device.hpp"
+
+namespace msl {
+
+enum PhaseKind : int {
+  PH_FWD_FULL = 0,    // slices [s0, s1) from the field in `field`, ending with psi_{s1}
+  PH_FWD_RECOMP = 1,  // slices [s0, s1): store psi_s, s0 < s < s1, into seg[s - s0 - 1]
+  PH_REV = 2,         // reverse sweep over slices s1-1 .. s0 on the cotangent in `field`
+  PH_FF = 3,          // far-field intensity of ff_src
+  PH_FFADJ = 4        // far-field adjoint: cotangent of ff_src into ff_tmp
+};
+
+struct PhaseSpec {
+  int kind;
+  int exact;          // exact (non-separable) propagator
+  int s0, s1, ns;
+  int ckpt_every;
+  int leading;        // PH_REV: first reverse phase (adds the leading half-propagation)
+  int64_t m;
+  float2* field;      // working buffer, transformed in place
+  float2* ckpt;       // PH_FWD_FULL: checkpoint array or nullptr
+  float2* seg;        // PH_FWD_RECOMP output / PH_REV input
+  const float2* ckpt_c;  // PH_REV: psi_{s0}
+  const float2* ff_src;
+  float2* ff_tmp;
+};
+
+__host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
+  const int n = ph.s1 - ph.s0;
+  switch (ph.kind) {
+    case PH_FWD_FULL: return ph.exact ? 2 * n + 1 : n + 1;
+    case PH_FWD_RECOMP: return n < 2 ? 0 : (ph.exact ? 2 * n - 1 : n);
+    case PH_REV: return (ph.exact ? 2 * n : n) + (ph.leading ? 1 : 0);
+    case PH_FF: return 2;
+    case PH_FFADJ: return 3;
+    default: return 0;
+  }
+}
+
+__host__ __device__ inline PassDesc blank_pass(int axis, const float2* src, float2* dst) {
+  PassDesc p;
+  p.axis = axis;
+  p.pre = PRE_NONE;
+  p.mid = MID_NONE;
+  p.post = POST_NONE;
+  p.conj = 0;
+  p.slice = 0;
+  p.src = src;
+  p.dst = dst;
+  p.psi_store = nullptr;
+  p.psi_load = nullptr;
+  return p;
+}
+
+__host__ __device__ inline float2* ckpt_slot(const PhaseSpec& ph, int s) {
+  if (!ph.ckpt || ph.ckpt_every <= 0 || (s % ph.ckpt_every) != 0) return nullptr;
+  return ph.ckpt + (int64_t)(s / ph.ckpt_every) * ph.m;
+}
+
+__host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
+  const int n = ph.s1 - ph.s0;
+  float2* f = ph.field;
+  switch (ph.kind) {
+    case PH_FWD_FULL:
+      if (!ph.exact) {
+        PassDesc d = blank_pass((p & 1) ? COL : ROW, f, f);
+        if (p < n) {
+          d.pre = p == 0 ? PRE_NONE : PRE_PROP;
+          d.mid = MID_T_FWD;
+          d.slice = ph.s0 + p;
+          d.psi_store = ckpt_slot(ph, ph.s0 + p);
+          d.post = POST_PROP;
+        } else {
+          d.pre = PRE_PROP;
+        }
+        return d;
+      } else {
+        if (p & 1) {
+          PassDesc d = blank_pass(COL, f, f);
+          d.post = POST_PROP2D;
+          return d;
+        }
+        PassDesc d = blank_pass(ROW, f, f);
+        const int q = p / 2;
+        d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
+        if (q < n) {
+          d.mid = MID_T_FWD;
+          d.slice = ph.s0 + q;
+          d.psi_store = ckpt_slot(ph, ph.s0 + q);
+          d.post = POST_FFT;
+        }
+        return d;
+      }
+    case PH_FWD_RECOMP:
+      if (!ph.exact) {
+        PassDesc d = blank_pass((p & 1) ? COL : ROW, f, f);
+        d.pre = p == 0 ? PRE_NONE : PRE_PROP;
+        if (p > 0) d.psi_store = ph.seg + (int64_t)(p - 1) * ph.m;
+        if (p < n - 1) {
+          d.mid = MID_T_FWD;
+          d.slice = ph.s0 + p;
+          d.post = POST_PROP;
+        } else {
+          d.dst = nullptr;
+        }
+        return d;
+      } else {
+        if (p & 1) {
+          PassDesc d = blank_pass(COL, f, f);
+          d.post = POST_PROP2D;
+          return d;
+        }
+        PassDesc d = blank_pass(ROW, f, f);
+        const int q = p / 2;
+        d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
+        if (q > 0) d.psi_store = ph.seg + (int64_t)(q - 1) * ph.m;
+        if (q < n - 1) {
+          d.mid = MID_T_FWD;
+          d.slice = ph.s0 + q;
+          d.post = POST_FFT;
+        } else {
+          d.dst = nullptr;
+        }
+        return d;
+      }
+    case PH_REV: {
+      if (ph.leading && p == 0) {
+        PassDesc d = blank_pass(ROW, f, f);
+        if (ph.exact) d.post = POST_FFT;
+        else { d.pre = PRE_PROP; d.conj = 1; }
+        return d;
+      }
+      const int q = p - (ph.leading ? 1 : 0);
+      if (!ph.exact) {
+        const int s = ph.s1 - 1 - q;
+        const int r = ph.ns - s;  // global reverse pass index sets the axis
+        PassDesc d = blank_pass((r & 1) ? COL : ROW, f, f);
+        d.pre = PRE_PROP;
+        d.conj = 1;
+        d.mid = MID_T_ADJ;
+        d.slice = s;
+        d.psi_load = s == ph.s0 ? ph.ckpt_c : ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
+        d.post = s == 0 ? POST_NONE : POST_PROP;
+        return d;
+      } else {
+        const int s = ph.s1 - 1 - q / 2;
+        if ((q & 1) == 0) {
+          PassDesc d = blank_pass(COL, f, f);
+          d.post = POST_PROP2D;
+          d.conj = 1;
+          return d;
+        }
+        PassDesc d = blank_pass(ROW, f, f);
+        d.pre = PRE_IFFT_N;
+        d.mid = MID_T_ADJ;
+        d.slice = s;
+        d.psi_load = s == ph.s0 ? ph.ckpt_c : ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
+        d.post = s == 0 ? POST_NONE : POST_FFT;
+        return d;
+      }
+    }
+    case PH_FF:
+      if (p == 0) {
+        PassDesc d = blank_pass(ROW, ph.ff_src, ph.ff_tmp);
+        d.pre = PRE_IFFT_U;
+        return d;
+      } else {
+        PassDesc d = blank_pass(COL, ph.ff_tmp, nullptr);
+        d.pre = PRE_IFFT_U;
+        d.mid = MID_FF_OUT;
+        return d;
+      }
+    case PH_FFADJ:
+    default:
+      if (p == 0) {
+        PassDesc d = blank_pass(ROW, ph.ff_src, ph.ff_tmp);
+        d.pre = PRE_IFFT_U;
+        return d;
+      } else if (p == 1) {
+        PassDesc d = blank_pass(COL, ph.ff_tmp, ph.ff_tmp);
+        d.pre = PRE_IFFT_U;
+        d.mid = MID_FF_SEED;
+        d.post = POST_FFT;
+        return d;
+      } else {
+        PassDesc d = blank_pass(ROW, ph.ff_tmp, ph.ff_tmp);
+        d.pre = PRE_FFT;
+        return d;
+      }
+  }
+}
+
+}  // namespace msl

@@ -1,0 +1,350 @@
+// Host-only check of the pass programs (msl_passes.hpp).
+//
+// Executes the PassDesc sequences that the library launches, with a plain
+// FP64 line engine (naive DFTs, exact propagator factors and transmission),
+// and compares the results with direct 2-D evaluations of the same
+// quantities.  This tests the scheduling logic (pass order, axis alternation,
+// checkpoint and segment slots, reverse indexing) without a GPU; the GPU
+// kernels are checked separately against the oracle.
+//
+// Build: hipcc --offload-host-only -std=c++17 -I include -o schedule_check schedule_check.cpp
+// Run:   ./schedule_check   (prints "OK" and exits 0 on success)
+#include <complex>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "msl_passes.hpp"
+
+using cd = std::complex<double>;
+using Field = std::vector<cd>;
+
+namespace {
+
+struct Geo {
+  int ny, nz, ns;
+  double dy, dz, dx, lam;
+  bool exact;
+};
+
+double kf(int m, int n, double d) {
+  const int f = m < n / 2 ? m : m - n;
+  return 2 * M_PI * f / (n * d);
+}
+
+cd hpar(int m, int n, double d, const Geo& g) {
+  const double k = 2 * M_PI / g.lam, q = kf(m, n, d);
+  return std::polar(1.0, g.dx * q * q / (2 * k));
+}
+
+cd hexact(int my, int mz, const Geo& g) {
+  const double k = 2 * M_PI / g.lam, ky = kf(my, g.ny, g.dy), kz = kf(mz, g.nz, g.dz);
+  const double kp2 = ky * ky + kz * kz;
+  return std::polar(1.0, g.dx * kp2 / (k + std::sqrt(k * k - kp2)));
+}
+
+// 1-D DFT of a line, sign -1 forward, +1 inverse (unnormalised)
+std::vector<cd> dft(const std::vector<cd>& x, int sign) {
+  const int n = (int)x.size();
+  std::vector<cd> y(n);
+  for (int u = 0; u < n; ++u) {
+    cd s = 0;
+    for (int j = 0; j < n; ++j) s += x[j] * std::polar(1.0, sign * 2 * M_PI * double(u) * j / n);
+    y[u] = s;
+  }
+  return y;
+}
+
+struct Engine {
+  Geo g;
+  std::vector<float> delta, beta;      // [ns][ny][nz]
+  std::vector<double> gdelta, gbeta;
+  std::vector<float> gI;               // shifted
+  std::vector<double> inten;           // shifted
+  // device pointers are stand-ins: map float2* tags to host fields
+  std::vector<Field*> bufs;
+  std::vector<const float2*> tags;
+
+  Field* buf(const float2* p) {
+    for (size_t i = 0; i < tags.size(); ++i)
+      if (tags[i] == p) return bufs[i];
+    // pointer inside a registered array of fields (ckpt / seg)
+    return nullptr;
+  }
+};
+
+struct Arr {
+  std::vector<Field> f;
+  const float2* base;
+  int64_t m;
+  Field* at(const float2* p) {
+    const int64_t off = p - base;
+    if (off < 0 || off % m) return nullptr;
+    const int64_t i = off / m;
+    if (i >= (int64_t)f.size()) return nullptr;
+    return &f[i];
+  }
+};
+
+std::vector<Arr*> g_arrays;
+
+Field* resolve(const float2* p) {
+  for (Arr* a : g_arrays)
+    if (Field* f = a->at(p)) return f;
+  std::fprintf(stderr, "unresolved pointer\n");
+  std::exit(3);
+}
+
+cd tfun(const Engine& E, int s, int64_t e) {
+  const double k = 2 * M_PI / E.g.lam;
+  const int64_t m = (int64_t)E.g.ny * E.g.nz;
+  return std::exp(cd(0, 1) * k * E.g.dx * cd(E.delta[s * m + e], E.beta[s * m + e]));
+}
+
+void run_pass(Engine& E, const msl::PassDesc& pd) {
+  const Geo& g = E.g;
+  const int64_t m = (int64_t)g.ny * g.nz;
+  const bool row = pd.axis == msl::ROW;
+  const int nl = row ? g.ny : g.nz, n = row ? g.nz : g.ny;
+  Field* src = resolve(pd.src);
+  Field out = *src;
+  const double k = 2 * M_PI / g.lam;
+  for (int line = 0; line < nl; ++line) {
+    auto addr = [&](int i) -> int64_t { return row ? (int64_t)line * g.nz + i : (int64_t)i * g.nz + line; };
+    std::vector<cd> v(n);
+    for (int i = 0; i < n; ++i) v[i] = (*src)[addr(i)];
+    auto prop = [&](bool conj) {
+      v = dft(v, -1);
+      for (int i = 0; i < n; ++i) {
+        cd h = row ? hpar(i, g.nz, g.dz, g) : hpar(i, g.ny, g.dy, g);
+        v[i] *= (conj ? std::conj(h) : h) / double(n);
+      }
+      v = dft(v, +1);
+    };
+    switch (pd.pre) {
+      case msl::PRE_PROP: prop(pd.conj); break;
+      case msl::PRE_FFT: v = dft(v, -1); break;
+      case msl::PRE_IFFT_N: v = dft(v, +1); for (auto& x : v) x /= double(n); break;
+      case msl::PRE_IFFT_U: v = dft(v, +1); break;
+      default: break;
+    }
+    if (pd.psi_store) {
+      Field* st = resolve(pd.psi_store);
+      for (int i = 0; i < n; ++i) (*st)[addr(i)] = v[i];
+    }
+    if (pd.mid == msl::MID_T_FWD) {
+      for (int i = 0; i < n; ++i) v[i] *= tfun(E, pd.slice, addr(i));
+    } else if (pd.mid == msl::MID_T_ADJ) {
+      Field* ps = resolve(pd.psi_load);
+      for (int i = 0; i < n; ++i) {
+        const cd T = tfun(E, pd.slice, addr(i));
+        const cd pt = T * (*ps)[addr(i)];
+        const cd c = std::conj(v[i]) * pt;
+        E.gdelta[pd.slice * m + addr(i)] = -k * g.dx * c.imag();
+        E.gbeta[pd.slice * m + addr(i)] = -k * g.dx * c.real();
+        v[i] *= std::conj(T);
+      }
+    } else if (pd.mid == msl::MID_FF_OUT || pd.mid == msl::MID_FF_SEED) {
+      for (int i = 0; i < n; ++i) {
+        const int r = row ? line : i, c = row ? i : line;
+        const int64_t sidx = (int64_t)((r + g.ny / 2) % g.ny) * g.nz + (c + g.nz / 2) % g.nz;
+        if (pd.mid == msl::MID_FF_OUT) E.inten[sidx] = std::norm(v[i]) / double(m);
+        else v[i] *= 2.0 * E.gI[sidx] / double(m);
+      }
+    }
+    switch (pd.post) {
+      case msl::POST_PROP: prop(pd.conj); break;
+      case msl::POST_FFT: v = dft(v, -1); break;
+      case msl::POST_PROP2D:
+        v = dft(v, -1);
+        for (int i = 0; i < n; ++i) {
+          const cd h = hexact(i, line, g) / double(g.ny);
+          v[i] *= pd.conj ? std::conj(h) : h;
+        }
+        v = dft(v, +1);
+        break;
+      default: break;
+    }
+    for (int i = 0; i < n; ++i) out[addr(i)] = v[i];
+  }
+  if (pd.dst) *resolve(pd.dst) = out;
+}
+
+void run_phase(Engine& E, const msl::PhaseSpec& ph) {
+  const int np = msl::phase_npasses(ph);
+  for (int p = 0; p < np; ++p) run_pass(E, msl::phase_pass(ph, p));
+}
+
+// --- direct 2-D references
+Field dft2(const Field& x, const Geo& g, int sign) {
+  Field y = x;
+  for (int r = 0; r < g.ny; ++r) {
+    std::vector<cd> v(y.begin() + (int64_t)r * g.nz, y.begin() + (int64_t)(r + 1) * g.nz);
+    v = dft(v, sign);
+    std::copy(v.begin(), v.end(), y.begin() + (int64_t)r * g.nz);
+  }
+  for (int c = 0; c < g.nz; ++c) {
+    std::vector<cd> v(g.ny);
+    for (int r = 0; r < g.ny; ++r) v[r] = y[(int64_t)r * g.nz + c];
+    v = dft(v, sign);
+    for (int r = 0; r < g.ny; ++r) y[(int64_t)r * g.nz + c] = v[r];
+  }
+  return y;
+}
+
+cd H2(int my, int mz, const Geo& g) {
+  return g.exact ? hexact(my, mz, g) : hpar(my, g.ny, g.dy, g) * hpar(mz, g.nz, g.dz, g);
+}
+
+Field prop2(const Field& x, const Geo& g, bool conj) {
+  Field y = dft2(x, g, -1);
+  const double m = double(g.ny) * g.nz;
+  for (int r = 0; r < g.ny; ++r)
+    for (int c = 0; c < g.nz; ++c) {
+      cd h = H2(r, c, g);
+      y[(int64_t)r * g.nz + c] *= (conj ? std::conj(h) : h) / m;
+    }
+  return dft2(y, g, +1);
+}
+
+double rel(const Field& a, const Field& b) {
+  double n = 0, d = 0;
+  for (size_t i = 0; i < a.size(); ++i) { n += std::norm(a[i] - b[i]); d += std::norm(b[i]); }
+  return std::sqrt(n / d);
+}
+
+double relv(const std::vector<double>& a, const std::vector<double>& b) {
+  double n = 0, d = 0;
+  for (size_t i = 0; i < a.size(); ++i) { n += (a[i] - b[i]) * (a[i] - b[i]); d += b[i] * b[i]; }
+  return std::sqrt(n / d);
+}
+
+int check(const Geo& g, int kck) {
+  const int64_t m = (int64_t)g.ny * g.nz;
+  std::mt19937_64 rng(12345 + g.ny * 7 + g.nz + g.ns + kck + (g.exact ? 1000 : 0));
+  std::uniform_real_distribution<double> U(0, 1);
+  Engine E;
+  E.g = g;
+  E.delta.resize(g.ns * m);
+  E.beta.resize(g.ns * m);
+  for (auto& x : E.delta) x = float(U(rng) * 2e-3);
+  for (auto& x : E.beta) x = float(U(rng) * 2e-4);
+  E.gdelta.assign(g.ns * m, 0);
+  E.gbeta.assign(g.ns * m, 0);
+  E.gI.resize(m);
+  for (auto& x : E.gI) x = float(U(rng) - 0.5);
+  E.inten.assign(m, 0);
+  Field probe(m);
+  for (auto& x : probe) x = cd(U(rng) - 0.5, U(rng) - 0.5);
+
+  // fake device addresses: distinct, well separated, multiples of m
+  const int64_t SPAN = 1 << 20;
+  auto fake = [&](int slot) { return reinterpret_cast<float2*>((uintptr_t)(SPAN * 64 * (slot + 1))); };
+  const int nck = (g.ns + kck - 1) / kck;
+  Arr field{{probe}, fake(0), m}, ckpt{std::vector<Field>(nck, Field(m)), fake(1), m},
+      seg{std::vector<Field>(kck > 1 ? kck - 1 : 1, Field(m)), fake(2), m}, W{{Field(m)}, fake(3), m},
+      G{{Field(m)}, fake(4), m}, tmp{{Field(m)}, fake(5), m};
+  g_arrays = {&field, &ckpt, &seg, &W, &G, &tmp};
+
+  // forward with checkpoints
+  msl::PhaseSpec ph{};
+  ph.kind = msl::PH_FWD_FULL; ph.exact = g.exact; ph.s0 = 0; ph.s1 = g.ns; ph.ns = g.ns; ph.m = m;
+  ph.field = field.base == fake(0) ? fake(0) : nullptr;
+  ph.ckpt = fake(1); ph.ckpt_every = kck;
+  run_phase(E, ph);
+
+  // direct reference
+  std::vector<Field> kept;
+  Field psi = probe;
+  for (int s = 0; s < g.ns; ++s) {
+    kept.push_back(psi);
+    for (int64_t e = 0; e < m; ++e) psi[e] *= tfun(E, s, e);
+    psi = prop2(psi, g, false);
+  }
+  int bad = 0;
+  const double ef = rel(field.f[0], psi);
+  if (ef > 1e-10) { std::printf("forward mismatch %g\n", ef); ++bad; }
+  for (int c = 0; c < nck; ++c) {
+    const double e = rel(ckpt.f[c], kept[c * kck]);
+    if (e > 1e-10) { std::printf("checkpoint %d mismatch %g\n", c, e); ++bad; }
+  }
+
+  // far field
+  msl::PhaseSpec ff{};
+  ff.kind = msl::PH_FF; ff.m = m; ff.ff_src = fake(0); ff.ff_tmp = fake(5);
+  run_phase(E, ff);
+  Field A = dft2(psi, g, +1);
+  std::vector<double> Iref(m);
+  for (int r = 0; r < g.ny; ++r)
+    for (int c = 0; c < g.nz; ++c)
+      Iref[(int64_t)((r + g.ny / 2) % g.ny) * g.nz + (c + g.nz / 2) % g.nz] = std::norm(A[(int64_t)r * g.nz + c]) / m;
+  if (relv(E.inten, Iref) > 1e-10) { std::printf("far field mismatch\n"); ++bad; }
+
+  // far-field adjoint into G
+  msl::PhaseSpec fa{};
+  fa.kind = msl::PH_FFADJ; fa.m = m; fa.ff_src = fake(0); fa.ff_tmp = fake(4);
+  run_phase(E, fa);
+  Field seed(m);
+  for (int r = 0; r < g.ny; ++r)
+    for (int c = 0; c < g.nz; ++c) {
+      const double gi = E.gI[(int64_t)((r + g.ny / 2) % g.ny) * g.nz + (c + g.nz / 2) % g.nz];
+      seed[(int64_t)r * g.nz + c] = 2.0 * gi * A[(int64_t)r * g.nz + c] / double(m);
+    }
+  Field gref = dft2(seed, g, -1);
+  if (rel(G.f[0], gref) > 1e-10) { std::printf("far-field adjoint mismatch %g\n", rel(G.f[0], gref)); ++bad; }
+
+  // adjoint with recompute
+  for (int c = nck - 1; c >= 0; --c) {
+    const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
+    if (s1 - s0 >= 2) {
+      W.f[0] = ckpt.f[c];
+      msl::PhaseSpec rc{};
+      rc.kind = msl::PH_FWD_RECOMP; rc.exact = g.exact; rc.s0 = s0; rc.s1 = s1; rc.ns = g.ns; rc.m = m;
+      rc.field = fake(3); rc.seg = fake(2);
+      run_phase(E, rc);
+    }
+    msl::PhaseSpec rv{};
+    rv.kind = msl::PH_REV; rv.exact = g.exact; rv.s0 = s0; rv.s1 = s1; rv.ns = g.ns; rv.m = m;
+    rv.leading = c == nck - 1; rv.field = fake(4); rv.seg = fake(2);
+    rv.ckpt_c = fake(1) + (int64_t)c * m;
+    run_phase(E, rv);
+  }
+  // direct reverse sweep
+  Field gg = gref;
+  std::vector<double> gd(g.ns * m), gb(g.ns * m);
+  const double k = 2 * M_PI / g.lam;
+  for (int s = g.ns - 1; s >= 0; --s) {
+    Field gp = prop2(gg, g, true);
+    for (int64_t e = 0; e < m; ++e) {
+      const cd T = tfun(E, s, e);
+      const cd cc = std::conj(gp[e]) * (T * kept[s][e]);
+      gd[s * m + e] = -k * g.dx * cc.imag();
+      gb[s * m + e] = -k * g.dx * cc.real();
+      gp[e] *= std::conj(T);
+    }
+    gg = gp;
+  }
+  if (relv(E.gdelta, gd) > 1e-9) { std::printf("grad delta mismatch %g\n", relv(E.gdelta, gd)); ++bad; }
+  if (relv(E.gbeta, gb) > 1e-9) { std::printf("grad beta mismatch %g\n", relv(E.gbeta, gb)); ++bad; }
+  if (rel(G.f[0], gg) > 1e-10) { std::printf("grad probe mismatch %g\n", rel(G.f[0], gg)); ++bad; }
+  std::printf("%s ny=%d nz=%d ns=%d k=%d: field %.1e -> %s\n", g.exact ? "exact" : "paraxial", g.ny, g.nz, g.ns,
+              kck, ef, bad ? "FAIL" : "ok");
+  return bad;
+}
+
+}  // namespace
+
+int main() {
+  int bad = 0;
+  for (int exact = 0; exact < 2; ++exact) {
+    const int cfg[][4] = {{8, 16, 1, 1}, {8, 16, 5, 2}, {16, 8, 7, 3}, {8, 8, 6, 6}, {16, 16, 9, 4}, {8, 32, 4, 10}};
+    for (auto& c : cfg) {
+      Geo g{c[0], c[1], c[2], 0.9, 1.3, 7.0, 0.15, exact == 1};
+      bad += check(g, c[3]);
+    }
+  }
+  std::printf(bad ? "FAILED\n" : "OK\n");
+  return bad ? 1 : 0;
+}

@@ -1,0 +1,288 @@
+"""ctypes binding of libmsl (C ABI in include/msl.h) plus autograd wrappers.
+
+Argument marshalling only: every step of the multislice path runs in the HIP
+library.  PyTorch provides device memory (tensors, the workspace) and the
+stream (``torch.cuda.current_stream()``).  If ``libmsl.so`` is missing the
+first call raises; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import c_double, c_int32, c_size_t, c_void_p
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsl.so")
+
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = 0, -1, -2, -3, -4
+PROP_PARAXIAL, PROP_EXACT = 0, 1
+SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
+
+EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_forward",
+           "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
+           "msl_set_schedule", "msl_last_error")
+
+
+class CGeometry(ctypes.Structure):
+    """Mirror of msl_geometry."""
+
+    _fields_ = [("ny", c_int32), ("nz", c_int32), ("n_slices", c_int32),
+                ("dy_nm", c_double), ("dz_nm", c_double), ("dx_nm", c_double),
+                ("wavelength_nm", c_double), ("alpha_i_rad", c_double),
+                ("propagator", c_int32)]
+
+
+class MslError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libmsl status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libmsl.so (once); raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    G = ctypes.POINTER(CGeometry)
+    L.msl_abi_version.restype = c_int32
+    L.msl_abi_version.argtypes = []
+    L.msl_workspace_bytes.restype = c_size_t
+    L.msl_workspace_bytes.argtypes = [G, c_int32]
+    L.msl_checkpoint_count.restype = c_int32
+    L.msl_checkpoint_count.argtypes = [G, c_int32]
+    L.msl_forward.restype = c_int32
+    L.msl_forward.argtypes = [G, P, P, P, P, P, c_int32, P, c_size_t, P]
+    L.msl_far_field.restype = c_int32
+    L.msl_far_field.argtypes = [G, P, P, P, c_size_t, P]
+    L.msl_amp_loss.restype = c_int32
+    L.msl_amp_loss.argtypes = [G, P, P, P, P, P, c_size_t, P]
+    L.msl_far_field_adjoint.restype = c_int32
+    L.msl_far_field_adjoint.argtypes = [G, P, P, P, P, c_size_t, P]
+    L.msl_adjoint.restype = c_int32
+    L.msl_adjoint.argtypes = [G, P, P, P, P, c_int32, P, P, P, P, P, c_size_t, P]
+    L.msl_set_schedule.restype = c_int32
+    L.msl_set_schedule.argtypes = [c_int32]
+    L.msl_last_error.restype = ctypes.c_char_p
+    L.msl_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def geometry(g) -> CGeometry:
+    """msl_geometry from a synth.Geometry, a dict or a CGeometry."""
+    if isinstance(g, CGeometry):
+        return g
+    get = (lambda k: g[k]) if isinstance(g, dict) else (lambda k: getattr(g, k))
+    return CGeometry(int(get("ny")), int(get("nz")), int(get("n_slices")),
+                     float(get("dy_nm")), float(get("dz_nm")), float(get("dx_nm")),
+                     float(get("wavelength_nm")), float(get("alpha_i_rad")),
+                     int(get("propagator")))
+
+
+def _check(status):
+    if status != OK:
+        raise MslError(status, lib().msl_last_error().decode())
+
+
+def _ptr(t, dtype, shape, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def abi_version():
+    return lib().msl_abi_version()
+
+
+def set_schedule(mode: int) -> int:
+    r = lib().msl_set_schedule(int(mode))
+    if r < 0:
+        _check(r)
+    return r
+
+
+def workspace_bytes(g, ckpt_every=0) -> int:
+    return int(lib().msl_workspace_bytes(ctypes.byref(geometry(g)), int(ckpt_every)))
+
+
+def checkpoint_count(g, ckpt_every) -> int:
+    return int(lib().msl_checkpoint_count(ctypes.byref(geometry(g)), int(ckpt_every)))
+
+
+def workspace(g, ckpt_every=0, device="cuda"):
+    """A workspace tensor large enough for every entry point at this geometry."""
+    n = workspace_bytes(g, ckpt_every)
+    if n == 0:
+        raise ValueError("invalid geometry")
+    ws = torch.empty(n, dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        ws = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        ws = ws[off:off + n]
+    return ws
+
+
+def forward(g, delta, beta, probe=None, ckpt_every=0, ws=None, out=None, ckpt=None):
+    """msl_forward: returns (psi_Ns complex64 [ny, nz], checkpoints or None)."""
+    cg = geometry(g)
+    ny, nz, ns = cg.ny, cg.nz, cg.n_slices
+    dev = delta.device
+    if ws is None:
+        ws = workspace(cg, ckpt_every, dev)
+    if out is None:
+        out = torch.empty((ny, nz), dtype=torch.complex64, device=dev)
+    if ckpt_every and ckpt is None:
+        ckpt = torch.empty((checkpoint_count(cg, ckpt_every), ny, nz), dtype=torch.complex64, device=dev)
+    st = lib().msl_forward(
+        ctypes.byref(cg), _ptr(delta, torch.float32, (ns, ny, nz), "delta"),
+        _ptr(beta, torch.float32, (ns, ny, nz), "beta"),
+        _ptr(probe, torch.complex64, (ny, nz), "probe", True),
+        _ptr(out, torch.complex64, (ny, nz), "out"),
+        _ptr(ckpt, torch.complex64, (checkpoint_count(cg, ckpt_every), ny, nz), "ckpt", True)
+        if ckpt_every else None,
+        int(ckpt_every), ws.data_ptr(), ws.numel(), _stream())
+    _check(st)
+    return out, (ckpt if ckpt_every else None)
+
+
+def far_field(g, field, ws=None, out=None):
+    cg = geometry(g)
+    if ws is None:
+        ws = workspace(cg, 0, field.device)
+    if out is None:
+        out = torch.empty((cg.ny, cg.nz), dtype=torch.float32, device=field.device)
+    _check(lib().msl_far_field(ctypes.byref(cg), _ptr(field, torch.complex64, (cg.ny, cg.nz), "field"),
+                               _ptr(out, torch.float32, (cg.ny, cg.nz), "intensity"),
+                               ws.data_ptr(), ws.numel(), _stream()))
+    return out
+
+
+def amp_loss(g, intensity, meas_amp, ws=None, want_grad=True):
+    """msl_amp_loss: returns (loss float64 scalar tensor on the device, dL/dI or None)."""
+    cg = geometry(g)
+    dev = intensity.device
+    if ws is None:
+        ws = workspace(cg, 0, dev)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    gI = torch.empty((cg.ny, cg.nz), dtype=torch.float32, device=dev) if want_grad else None
+    _check(lib().msl_amp_loss(ctypes.byref(cg), _ptr(intensity, torch.float32, (cg.ny, cg.nz), "intensity"),
+                              _ptr(meas_amp, torch.float32, (cg.ny, cg.nz), "meas_amp"),
+                              loss.data_ptr(), gI.data_ptr() if gI is not None else None,
+                              ws.data_ptr(), ws.numel(), _stream()))
+    return loss, gI
+
+
+def far_field_adjoint(g, field, grad_intensity, ws=None, out=None):
+    cg = geometry(g)
+    if ws is None:
+        ws = workspace(cg, 0, field.device)
+    if out is None:
+        out = torch.empty((cg.ny, cg.nz), dtype=torch.complex64, device=field.device)
+    _check(lib().msl_far_field_adjoint(
+        ctypes.byref(cg), _ptr(field, torch.complex64, (cg.ny, cg.nz), "field"),
+        _ptr(grad_intensity, torch.float32, (cg.ny, cg.nz), "grad_intensity"),
+        _ptr(out, torch.complex64, (cg.ny, cg.nz), "grad_field"), ws.data_ptr(), ws.numel(), _stream()))
+    return out
+
+
+def adjoint(g, delta, beta, ckpt, ckpt_every, grad_field, probe=None, ws=None,
+            want_delta=True, want_beta=True, want_probe=True, gd=None, gb=None):
+    """msl_adjoint: returns (dL/d delta, dL/d beta, dL/d probe), None where not wanted."""
+    cg = geometry(g)
+    ny, nz, ns = cg.ny, cg.nz, cg.n_slices
+    dev = delta.device
+    if ws is None:
+        ws = workspace(cg, ckpt_every, dev)
+    if want_delta and gd is None:
+        gd = torch.empty((ns, ny, nz), dtype=torch.float32, device=dev)
+    if want_beta and gb is None:
+        gb = torch.empty((ns, ny, nz), dtype=torch.float32, device=dev)
+    gp = torch.empty((ny, nz), dtype=torch.complex64, device=dev) if want_probe else None
+    _check(lib().msl_adjoint(
+        ctypes.byref(cg), _ptr(delta, torch.float32, (ns, ny, nz), "delta"),
+        _ptr(beta, torch.float32, (ns, ny, nz), "beta"),
+        _ptr(probe, torch.complex64, (ny, nz), "probe", True),
+        _ptr(ckpt, torch.complex64, (checkpoint_count(cg, ckpt_every), ny, nz), "ckpt"),
+        int(ckpt_every), _ptr(grad_field, torch.complex64, (ny, nz), "grad_field"),
+        gd.data_ptr() if want_delta else None, gb.data_ptr() if want_beta else None,
+        gp.data_ptr() if gp is not None else None, ws.data_ptr(), ws.numel(), _stream()))
+    return (gd if want_delta else None), (gb if want_beta else None), gp
+
+
+# ---------------------------------------------------------------------------
+# autograd wrappers
+
+class Multislice(torch.autograd.Function):
+    """psi_Ns = Multislice.apply(delta, beta, geom, probe=None, ckpt_every=32)."""
+
+    @staticmethod
+    def forward(ctx, delta, beta, geom, probe=None, ckpt_every=32):
+        cg = geometry(geom)
+        k = max(1, min(int(ckpt_every), cg.n_slices))
+        out, ck = forward(cg, delta.contiguous(), beta.contiguous(), probe, ckpt_every=k)
+        ctx.save_for_backward(delta, beta, ck)
+        ctx.cg, ctx.k, ctx.has_probe = cg, k, probe is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        delta, beta, ck = ctx.saved_tensors
+        gd, gb, gp = adjoint(ctx.cg, delta.contiguous(), beta.contiguous(), ck, ctx.k,
+                             grad_out.contiguous(),
+                             want_delta=ctx.needs_input_grad[0], want_beta=ctx.needs_input_grad[1],
+                             want_probe=ctx.has_probe and ctx.needs_input_grad[3])
+        return gd, gb, None, gp, None
+
+
+class FarField(torch.autograd.Function):
+    """I = FarField.apply(field, geom): fftshifted detector intensity."""
+
+    @staticmethod
+    def forward(ctx, field, geom):
+        cg = geometry(geom)
+        ctx.cg = cg
+        ctx.save_for_backward(field)
+        return far_field(cg, field.contiguous())
+
+    @staticmethod
+    def backward(ctx, gI):
+        (field,) = ctx.saved_tensors
+        return far_field_adjoint(ctx.cg, field.contiguous(), gI.contiguous()), None
+
+
+class AmpLoss(torch.autograd.Function):
+    """L = AmpLoss.apply(I, meas_amp, geom) = sum (sqrt(I) - m)^2 (float64 scalar)."""
+
+    @staticmethod
+    def forward(ctx, intensity, meas_amp, geom):
+        cg = geometry(geom)
+        loss, gI = amp_loss(cg, intensity.contiguous(), meas_amp.contiguous())
+        ctx.save_for_backward(gI)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gL):
+        (gI,) = ctx.saved_tensors
+        return gI * gL.to(torch.float32), None, None

@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI (CPU only: no call here reaches the GPU).
+
+The library must load, export every function declared in include/msl.h, and
+reject invalid arguments on the host with the documented status codes before
+it touches HIP.  Only arguments that fail validation are passed, so no kernel
+is ever enqueued.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2212_01253_amd import msl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "msl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(msl_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return msl.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(msl.EXPORTS)
+
+
+def test_abi_version(L):
+    assert msl.abi_version() == 1
+
+
+def G(**kw):
+    base = dict(ny=64, nz=64, n_slices=8, dy_nm=1.0, dz_nm=1.0, dx_nm=10.0,
+                wavelength_nm=0.1, alpha_i_rad=0.003, propagator=0)
+    base.update(kw)
+    return msl.CGeometry(**base)
+
+
+FAKE = 0x7F0000000000  # never dereferenced: validation fails first
+
+
+def fwd(L, g, delta=FAKE, beta=FAKE, probe=None, out=FAKE, ckpt=None, k=0, ws=FAKE, wsb=1 << 40):
+    return L.msl_forward(ctypes.byref(g), delta, beta, probe, out, ckpt, k, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw", [dict(ny=15), dict(nz=2048), dict(ny=8), dict(nz=48), dict(n_slices=0),
+                                dict(dy_nm=0.0), dict(dz_nm=-1.0), dict(dx_nm=float("nan")),
+                                dict(wavelength_nm=0.0), dict(alpha_i_rad=1.6), dict(propagator=2)])
+def test_invalid_geometry(L, kw):
+    assert fwd(L, G(**kw)) == msl.ERR_ARG
+    assert L.msl_last_error().decode()
+    assert L.msl_workspace_bytes(ctypes.byref(G(**kw)), 0) == 0
+
+
+def test_null_and_misaligned_pointers(L):
+    g = G()
+    assert fwd(L, g, delta=None) == msl.ERR_ARG
+    assert "delta" in L.msl_last_error().decode()
+    assert fwd(L, g, beta=FAKE + 2) == msl.ERR_ARG
+    assert fwd(L, g, out=FAKE + 4) == msl.ERR_ARG
+    assert fwd(L, g, probe=FAKE + 4) == msl.ERR_ARG
+
+
+def test_checkpoint_argument_rules(L):
+    g = G()
+    assert fwd(L, g, ckpt=FAKE, k=0) == msl.ERR_ARG
+    assert fwd(L, g, ckpt=None, k=4) == msl.ERR_ARG
+    # the adjoint requires checkpoints
+    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, None, 4, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, None)
+    assert st == msl.ERR_ARG
+    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, FAKE, 0, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, None)
+    assert st == msl.ERR_ARG
+
+
+def test_workspace_rules(L):
+    g = G()
+    need = L.msl_workspace_bytes(ctypes.byref(g), 0)
+    assert need > 0
+    assert fwd(L, g, ws=None) == msl.ERR_WORKSPACE
+    assert fwd(L, g, ws=FAKE + 128) == msl.ERR_WORKSPACE
+    assert fwd(L, g, wsb=need - 1) == msl.ERR_WORKSPACE
+    assert "need" in L.msl_last_error().decode()
+    # adjoint workspace grows with the checkpoint interval (segment buffer)
+    assert L.msl_workspace_bytes(ctypes.byref(g), 8) > L.msl_workspace_bytes(ctypes.byref(g), 2) > need
+    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, FAKE, 8, FAKE, FAKE, FAKE, None, FAKE,
+                       L.msl_workspace_bytes(ctypes.byref(g), 2), None)
+    assert st == msl.ERR_WORKSPACE
+
+
+def test_checkpoint_count(L):
+    assert L.msl_checkpoint_count(ctypes.byref(G(n_slices=100)), 32) == 4
+    assert L.msl_checkpoint_count(ctypes.byref(G(n_slices=96)), 32) == 3
+    assert L.msl_checkpoint_count(ctypes.byref(G(n_slices=5)), 1) == 5
+    assert L.msl_checkpoint_count(ctypes.byref(G()), 0) == 0
+
+
+def test_other_entry_points_validate(L):
+    g = G()
+    assert L.msl_far_field(ctypes.byref(g), None, FAKE, FAKE, 1 << 40, None) == msl.ERR_ARG
+    assert L.msl_far_field(ctypes.byref(G(ny=3)), FAKE, FAKE, FAKE, 1 << 40, None) == msl.ERR_ARG
+    assert L.msl_amp_loss(ctypes.byref(g), FAKE, FAKE, FAKE + 4, None, FAKE, 1 << 40, None) == msl.ERR_ARG
+    assert L.msl_far_field_adjoint(ctypes.byref(g), FAKE, None, FAKE, FAKE, 1 << 40, None) == msl.ERR_ARG
+
+
+def test_schedule_setter(L):
+    prev = msl.set_schedule(msl.SCHED_PER_PASS)
+    assert msl.set_schedule(prev) == msl.SCHED_PER_PASS
+    with pytest.raises(msl.MslError):
+        msl.set_schedule(7)

@@ -1,0 +1,214 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Tolerances: exit field relative L2 <= 2e-5 and far-field intensity relative
+L2 <= 1e-4 (complex64 on the GPU against complex128 on the CPU from the same
+float32 inputs).  Gradients: relative L2 <= 1e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import msl_oracle as O
+from paper_2212_01253_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 2e-5
+INT_TOL = 1e-4
+GRAD_TOL = 1e-3
+SCHEDULES = [1]  # per-pass launches (the persistent schedule is added to this list once built)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_01253_amd import msl
+    msl.lib()
+    yield msl
+    msl.set_schedule(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_forward(M, g, d, b, probe=None, k=0, sched=1):
+    M.set_schedule(sched)
+    f, ck = M.forward(g, dev(d), dev(b), None if probe is None else dev(probe.astype(np.complex64)),
+                      ckpt_every=k)
+    I = M.far_field(g, f)
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), I.cpu().numpy(), (None if ck is None else ck.cpu().numpy())
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("seed", [0, 1])
+def test_parity_64x64x128(M, sched, seed):
+    w = synth.parity_small(seed)
+    f, I, _ = run_forward(M, w.geom, w.delta, w.beta, sched=sched)
+    rf = O.forward(w.geom, w.delta, w.beta)
+    rI = O.far_field(w.geom, rf)
+    print(f"seed {seed} sched {sched}: field {rel(f, rf):.3e} intensity {rel(I, rI):.3e}")
+    assert rel(f, rf) <= FIELD_TOL
+    assert rel(I, rI) <= INT_TOL
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("ny,nz,ns", [(16, 16, 5), (32, 64, 9), (128, 32, 7), (16, 1024, 4), (1024, 16, 4),
+                                      (256, 256, 12), (512, 128, 6), (1024, 1024, 3)])
+def test_size_sweep(M, sched, ny, nz, ns):
+    g = synth.Geometry(ny, nz, ns, 0.9, 1.2, 8.0, 0.12, math.radians(0.15), 0)
+    d, b = synth.random_stack(ny, nz, ns, ny * 7 + nz + ns, 3e-5, 2e-6)
+    p = synth.random_field(ny, nz, ny + nz)
+    f, I, _ = run_forward(M, g, d, b, probe=p, sched=sched)
+    rf = O.forward(g, d, b, p.astype(np.complex128))
+    rI = O.far_field(g, rf)
+    assert rel(f, rf) <= FIELD_TOL, rel(f, rf)
+    assert rel(I, rI) <= INT_TOL, rel(I, rI)
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_exact_propagator(M, sched):
+    w = synth.parity_small(3)
+    g = synth.Geometry(**{**w.geom.as_dict(), "propagator": 1})
+    f, I, _ = run_forward(M, g, w.delta, w.beta, sched=sched)
+    rf = O.forward(g, w.delta, w.beta)
+    assert rel(f, rf) <= FIELD_TOL
+    assert rel(I, O.far_field(g, rf)) <= INT_TOL
+    # and it is a different model from the paraxial one
+    assert rel(rf, O.forward(w.geom, w.delta, w.beta)) > 1e-3
+
+
+def test_checkpoints_hold_entrance_fields(M):
+    w = synth.parity_small(4)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 40})
+    d, b = w.delta[:40], w.beta[:40]
+    f, _, ck = run_forward(M, g, d, b, k=7)
+    rf, kept = O.forward(g, d, b, keep=True)
+    assert ck.shape == (6, 64, 64)
+    for c in range(6):
+        assert rel(ck[c], kept[7 * c]) <= FIELD_TOL
+    assert rel(f, rf) <= FIELD_TOL
+
+
+def test_vacuum_composition_on_gpu(M):
+    ny, nz = 64, 32
+    p = synth.random_field(ny, nz, 5)
+    g = synth.Geometry(ny, nz, 16, 1.0, 1.0, 6.0, 0.1, 0.0, 0)
+    g1 = synth.Geometry(ny, nz, 1, 1.0, 1.0, 96.0, 0.1, 0.0, 0)
+    z = np.zeros((16, ny, nz), np.float32)
+    f16, _, _ = run_forward(M, g, z, z, probe=p)
+    f1, _, _ = run_forward(M, g1, z[:1], z[:1], probe=p)
+    assert rel(f16, f1) <= FIELD_TOL
+
+
+def test_parseval_on_gpu(M):
+    w = synth.parity_small(2)
+    f, I, _ = run_forward(M, w.geom, w.delta, np.zeros_like(w.beta))
+    n0 = w.geom.ny * w.geom.nz  # |probe|^2 = 1 per pixel
+    assert abs(np.sum(np.abs(f.astype(np.complex128)) ** 2) / n0 - 1) <= 1e-5
+    assert abs(I.astype(np.float64).sum() / np.sum(np.abs(f.astype(np.complex128)) ** 2) - 1) <= 1e-5
+
+
+def test_deterministic_repeat(M):
+    w = synth.parity_small(1)
+    f1, I1, _ = run_forward(M, w.geom, w.delta, w.beta)
+    f2, I2, _ = run_forward(M, w.geom, w.delta, w.beta)
+    assert np.array_equal(f1, f2) and np.array_equal(I1, I2)
+
+
+def test_far_field_and_loss(M):
+    ny, nz = 64, 128
+    g = synth.Geometry(ny, nz, 1, 1.0, 1.0, 10.0, 0.1, 0.0, 0)
+    psi = synth.random_field(ny, nz, 11)
+    meas = synth.random_measured_amplitude(ny, nz, 12, 3.0)
+    fpsi = dev(psi)
+    I = M.far_field(g, fpsi)
+    loss, gI = M.amp_loss(g, I, dev(meas))
+    gpsi = M.far_field_adjoint(g, fpsi, gI)
+    torch.cuda.synchronize()
+    rI = O.far_field(g, psi.astype(np.complex128))
+    L, _, rgI = O.amp_loss(I.cpu().numpy().astype(np.float64), meas)
+    assert rel(I.cpu().numpy(), rI) <= INT_TOL
+    assert abs(float(loss.cpu()) - L) <= 1e-9 * abs(L)
+    assert rel(gI.cpu().numpy(), rgI) <= 1e-6
+    rg = O.far_field_adjoint(g, psi.astype(np.complex128), gI.cpu().numpy().astype(np.float64))
+    assert rel(gpsi.cpu().numpy(), rg) <= 1e-5
+
+
+def test_loss_zero_intensity_pixels(M):
+    ny, nz = 16, 16
+    g = synth.Geometry(ny, nz, 1, 1.0, 1.0, 10.0, 0.1, 0.0, 0)
+    I = np.zeros((ny, nz), np.float32)
+    I[3, 4] = 4.0
+    m = np.full((ny, nz), 0.5, np.float32)
+    loss, gI = M.amp_loss(g, dev(I), dev(m))
+    torch.cuda.synchronize()
+    L, _, rgI = O.amp_loss(I, m)
+    assert float(loss.cpu()) == pytest.approx(L, rel=1e-12)
+    assert np.allclose(gI.cpu().numpy(), rgI, atol=1e-7)
+
+
+def _grad_case(M, g, d, b, meas, k, sched=1):
+    M.set_schedule(sched)
+    D, B = dev(d), dev(b)
+    f, ck = M.forward(g, D, B, ckpt_every=k)
+    I = M.far_field(g, f)
+    loss, gI = M.amp_loss(g, I, dev(meas))
+    gpsi = M.far_field_adjoint(g, f, gI)
+    gd, gb, gp = M.adjoint(g, D, B, ck, k, gpsi)
+    torch.cuda.synchronize()
+    return float(loss.cpu()), gd.cpu().numpy(), gb.cpu().numpy(), gp.cpu().numpy()
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("k", [1, 3, 32, 40])
+def test_gradient_parity(M, sched, k):
+    w = synth.parity_small(5)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 40})
+    d, b = w.delta[:40], w.beta[:40]
+    meas = (np.sqrt(O.far_field(g, O.forward(g, d * 1.1, b * 1.1)))
+            * (1 + 0.05 * np.random.default_rng(6).random((64, 64)))).astype(np.float32)
+    L, gd, gb, gp = _grad_case(M, g, d, b, meas, k, sched)
+    rL, rd, rb, rp, _, _ = O.loss_and_gradient(g, d, b, meas)
+    print(f"k={k}: loss {abs(L - rL) / rL:.2e} gd {rel(gd, rd):.2e} gb {rel(gb, rb):.2e} gp {rel(gp, rp):.2e}")
+    assert abs(L - rL) <= 1e-4 * abs(rL)
+    assert rel(gd, rd) <= GRAD_TOL
+    assert rel(gb, rb) <= GRAD_TOL
+    assert rel(gp, rp) <= GRAD_TOL
+
+
+def test_gradient_exact_propagator(M):
+    w = synth.parity_small(6)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 24, "propagator": 1})
+    d, b = w.delta[:24], w.beta[:24]
+    meas = synth.random_measured_amplitude(64, 64, 9, 0.05)
+    L, gd, gb, gp = _grad_case(M, g, d, b, meas, 5)
+    rL, rd, rb, rp, _, _ = O.loss_and_gradient(g, d, b, meas)
+    assert rel(gd, rd) <= GRAD_TOL and rel(gb, rb) <= GRAD_TOL and rel(gp, rp) <= GRAD_TOL
+
+
+def test_autograd_wrappers(M):
+    w = synth.parity_small(7)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 16})
+    d = dev(w.delta[:16]).requires_grad_(True)
+    b = dev(w.beta[:16]).requires_grad_(True)
+    meas = synth.random_measured_amplitude(64, 64, 10, 0.05)
+    f = M.Multislice.apply(d, b, g, None, 4)
+    I = M.FarField.apply(f, g)
+    L = M.AmpLoss.apply(I, dev(meas), g)
+    L.backward()
+    rL, rd, rb, _, _, _ = O.loss_and_gradient(g, w.delta[:16], w.beta[:16], meas)
+    assert abs(float(L.detach().cpu()) - rL) <= 1e-4 * rL
+    assert rel(d.grad.cpu().numpy(), rd) <= GRAD_TOL
+    assert rel(b.grad.cpu().numpy(), rb) <= GRAD_TOL
