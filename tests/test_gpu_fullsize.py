@@ -1,0 +1,90 @@
+"""Full-size parity on the throughput workload (512 x 512 grid, 2048 slices).
+
+The benchmark's forward sweep, in the launch configuration the benchmark
+uses, against the FP64 oracle on the same float32 inputs: exit field relative
+L2 <= 2e-5 and far-field intensity relative L2 <= 1e-4.  The oracle needs
+about a minute of host CPU here.  A gradient check at the gradient workload's
+full size (256 x 256 x 1024, checkpoints every 32 slices) compares the GPU
+gradient with the oracle's on 16 sampled voxels and on its relative L2 norm.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import msl_oracle as O
+from paper_2212_01253_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_01253_amd import msl
+    msl.lib()
+    msl.set_schedule(0)
+    yield msl
+    msl.set_schedule(0)
+
+
+@pytest.mark.timeout(900)
+def test_forward_512x512x2048(M):
+    w = synth.throughput_512()
+    g = w.geom
+    print(f"workload {w.name} alpha {math.degrees(g.alpha_i_rad):.4f} deg", flush=True)
+    D = torch.from_numpy(w.delta).cuda()
+    B = torch.from_numpy(w.beta).cuda()
+    f, _ = M.forward(g, D, B, ckpt_every=32)
+    I = M.far_field(g, f)
+    torch.cuda.synchronize()
+    f = f.cpu().numpy()
+    I = I.cpu().numpy()
+    del D, B
+    t0 = time.time()
+    rf = O.forward(g, w.delta, w.beta)
+    rI = O.far_field(g, rf)
+    ef, ei = rel(f, rf), rel(I, rI)
+    print(f"oracle {time.time() - t0:.1f} s; field rel-L2 {ef:.3e}, intensity rel-L2 {ei:.3e}", flush=True)
+    assert ef <= 2e-5
+    assert ei <= 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_gradient_256x256x1024(M):
+    w = synth.recon_256()
+    g = w.geom
+    rng = np.random.default_rng(4243)
+    # measured amplitudes from a perturbed structure with 5 % multiplicative noise
+    t0 = time.time()
+    meas = (np.sqrt(O.far_field(g, O.forward(g, w.delta * 1.05, w.beta * 1.05)))
+            * (1 + 0.05 * rng.random((g.ny, g.nz)))).astype(np.float32)
+    D = torch.from_numpy(w.delta).cuda()
+    B = torch.from_numpy(w.beta).cuda()
+    f, ck = M.forward(g, D, B, ckpt_every=32)
+    I = M.far_field(g, f)
+    loss, gI = M.amp_loss(g, I, torch.from_numpy(meas).cuda())
+    gpsi = M.far_field_adjoint(g, f, gI)
+    gd, gb, gp = M.adjoint(g, D, B, ck, 32, gpsi)
+    torch.cuda.synchronize()
+    gd, gb, gp = gd.cpu().numpy(), gb.cpu().numpy(), gp.cpu().numpy()
+    L = float(loss.cpu())
+    del D, B
+    rL, rd, rb, rp, _, _ = O.loss_and_gradient(g, w.delta, w.beta, meas)
+    pick = np.random.default_rng(4245)
+    idx = [tuple(int(pick.integers(0, n)) for n in w.delta.shape) for _ in range(16)]
+    scale = np.sqrt(np.mean(rd ** 2))
+    worst = max(abs(gd[i] - rd[i]) / scale for i in idx)
+    print(f"oracle {time.time() - t0:.1f} s; loss {abs(L - rL) / rL:.2e}; grad delta {rel(gd, rd):.2e} "
+          f"beta {rel(gb, rb):.2e} probe {rel(gp, rp):.2e}; sampled voxels {worst:.2e}", flush=True)
+    assert abs(L - rL) <= 1e-4 * rL
+    assert rel(gd, rd) <= 1e-3 and rel(gb, rb) <= 1e-3 and rel(gp, rp) <= 1e-3
+    assert worst <= 1e-3
