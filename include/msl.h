@@ -83,7 +83,8 @@ typedef enum { MSL_PROP_PARAXIAL = 0, MSL_PROP_EXACT = 1 } msl_propagator;
 typedef enum {
   MSL_SCHED_AUTO = 0,        /* library choice */
   MSL_SCHED_PER_PASS = 1,    /* one kernel launch per line pass */
-  MSL_SCHED_PERSISTENT = 2   /* one cooperative launch per phase, grid barriers between passes */
+  MSL_SCHED_PERSISTENT = 2   /* one cooperative launch per phase, grid barriers between passes
+                                (square grids, ny == nz; other shapes run per pass) */
 } msl_schedule;
 
 typedef struct {

@@ -323,8 +323,9 @@ msl_status build_tables(const Call& k, bool need_prop) {
 msl_status run_phase(const Call& k, const PhaseSpec& ph) {
   const int np = msl::phase_npasses(ph);
   if (np == 0) return MSL_OK;
-  const bool persistent = (g_schedule == MSL_SCHED_PERSISTENT) ||
-                          (g_schedule == MSL_SCHED_AUTO && msl::persistent_preferred(k.c, np));
+  // the persistent kernel serves square grids; other shapes always run per pass
+  const bool persistent = k.c.ny == k.c.nz && ((g_schedule == MSL_SCHED_PERSISTENT) ||
+                          (g_schedule == MSL_SCHED_AUTO && msl::persistent_preferred(k.c, np)));
   if (persistent) {
     hipError_t e = msl::launch_persistent(k.c, ph, np, reinterpret_cast<unsigned*>(k.ws + k.L.bar), k.st);
     if (e == hipSuccess) return MSL_OK;

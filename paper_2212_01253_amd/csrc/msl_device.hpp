@@ -126,6 +126,34 @@ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 
+// Per-lane twiddles of one line FFT: lane j of an N-point line needs
+// W_N^{(j mod NS) r N / (8 NS)}, r = 1..7, for every twiddled radix-8 stage
+// (sub-length NS = R0, 8 R0, ...).  They are loaded once per pass into
+// registers, hi and lo parts, and serve the forward and inverse transforms.
+template <int N>
+struct LineTw {
+  static constexpr int LG = ilog2c(N);
+  static constexpr int R0 = (LG % 3 == 0) ? 8 : ((LG % 3 == 1) ? 2 : 4);
+  static constexpr int NST = (LG - ilog2c(R0)) / 3;
+  float2 hi[NST][7];
+  float2 lo[NST][7];
+};
+
+template <int N>
+__device__ __forceinline__ void load_tw(LineTw<N>& tw, const float2* __restrict__ twh,
+                                        const float2* __restrict__ twl, int j) {
+#pragma unroll
+  for (int s = 0, NS = LineTw<N>::R0; s < LineTw<N>::NST; ++s, NS *= 8) {
+    const int jm = j % NS;
+    const int step = N / (8 * NS);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      tw.hi[s][r - 1] = twh[jm * r * step];
+      tw.lo[s][r - 1] = twl[jm * r * step];
+    }
+  }
+}
+
 // Line FFT of N points held by N/8 lanes, 8 points per lane.  On entry and on
 // exit lane j holds element j + t*N/8 in v[t] ("t-layout", natural order).
 // Stockham autosort: a first stage of radix 2, 4 or 8 without twiddles, then
@@ -133,12 +161,9 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 // slot in eight to spread the stride-8 writes over the banks).  All threads
 // of the block call it together (it contains block barriers).
 template <int N, bool INV>
-__device__ __forceinline__ void fft_line(float2 (&v)[8], float2* sh, int j,
-                                         const float2* __restrict__ twh,
-                                         const float2* __restrict__ twl) {
+__device__ __forceinline__ void fft_line(float2 (&v)[8], float2* sh, int j, const LineTw<N>& tw) {
   constexpr int L = N / 8;
-  constexpr int LG = ilog2c(N);
-  constexpr int R0 = (LG % 3 == 0) ? 8 : ((LG % 3 == 1) ? 2 : 4);
+  constexpr int R0 = LineTw<N>::R0;
   // ---- stage 0: radix R0, sub-length 1, trivial twiddles
   __syncthreads();
   if constexpr (R0 == 8) {
@@ -165,19 +190,14 @@ __device__ __forceinline__ void fft_line(float2 (&v)[8], float2* sh, int j,
   __syncthreads();
   // ---- radix-8 stages with sub-length NS = R0, 8 R0, ...
 #pragma unroll
-  for (int NS = R0; NS < N; NS *= 8) {
+  for (int s = 0, NS = R0; s < LineTw<N>::NST; ++s, NS *= 8) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = sh[lds_pad(j + t * L)];
-    const int jm = j % NS;
-    const int step = N / (8 * NS);
 #pragma unroll
-    for (int r = 1; r < 8; ++r) {
-      const int e = jm * r * step;
-      v[r] = cmul_comp<INV>(v[r], twh[e], twl[e]);
-    }
+    for (int r = 1; r < 8; ++r) v[r] = cmul_comp<INV>(v[r], tw.hi[s][r - 1], tw.lo[s][r - 1]);
     dft8<INV>(v);
     if (NS * 8 < N) {
-      const int base = (j / NS) * NS * 8 + jm;
+      const int base = (j / NS) * NS * 8 + (j % NS);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 8; ++r) sh[lds_pad(base + r * NS)] = v[r];
@@ -248,53 +268,100 @@ __device__ __forceinline__ int64_t line_addr(const Ctx& c, int line, int i) {
   return AXIS == ROW ? (int64_t)line * c.nz + i : (int64_t)i * c.nz + line;
 }
 
-template <int N, int AXIS>
-__device__ __forceinline__ void prop_line(float2 (&v)[8], float2* sh, int j, const Ctx& c, bool conj) {
-  constexpr int L = N / 8;
-  const float2* twh = AXIS == ROW ? c.twz_hi : c.twy_hi;
-  const float2* twl = AXIS == ROW ? c.twz_lo : c.twy_lo;
-  const float2* hh = AXIS == ROW ? c.hz_hi : c.hy_hi;
-  const float2* hl = AXIS == ROW ? c.hz_lo : c.hy_lo;
-  fft_line<N, false>(v, sh, j, twh, twl);
-#pragma unroll
-  for (int t = 0; t < 8; ++t) v[t] = cmul_comp_dyn(v[t], hh[j + t * L], hl[j + t * L], conj);
-  fft_line<N, true>(v, sh, j, twh, twl);
+// Everything a line pass reads, gathered in registers.  Loads are issued
+// together at the top of the pass (one memory latency instead of one per
+// FFT stage); inputs that do not depend on the previous pass can be fetched
+// before the grid barrier that separates two passes.
+template <int N>
+struct LineIn {
+  float2 v[8];            // field
+  float dl[8], bt[8];     // delta, beta of the slice
+  float2 ps[8];           // psi_s (adjoint)
+  float gi[8];            // far-field seed (shifted read)
+  float2 hh[8], hl[8];    // propagator factor (1-D paraxial or 2-D exact)
+  LineTw<N> tw;
+};
+
+__device__ __forceinline__ bool uses_h1d(const PassDesc& pd) {
+  return pd.pre == PRE_PROP || pd.post == POST_PROP;
 }
 
-// y-FFT, multiply by the 2-D propagator (already divided by ny), y-IFFT;
-// only for columns (the field is in (y, kz) order, kz = line).
 template <int N, int AXIS>
-__device__ __forceinline__ void prop2d_line(float2 (&v)[8], float2* sh, int j, int line, const Ctx& c,
-                                            bool conj) {
+__device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N>& in) {
   constexpr int L = N / 8;
-  fft_line<N, false>(v, sh, j, c.twy_hi, c.twy_lo);
+  load_tw<N>(in.tw, AXIS == ROW ? c.twz_hi : c.twy_hi, AXIS == ROW ? c.twz_lo : c.twy_lo, j);
+  if (uses_h1d(pd)) {
+    const float2* hh = AXIS == ROW ? c.hz_hi : c.hy_hi;
+    const float2* hl = AXIS == ROW ? c.hz_lo : c.hy_lo;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int64_t e = (int64_t)(j + t * L) * c.nz + line;
-    v[t] = cmul_comp_dyn(v[t], c.H_hi[e], c.H_lo[e], conj);
+    for (int t = 0; t < 8; ++t) {
+      in.hh[t] = hh[j + t * L];
+      in.hl[t] = hl[j + t * L];
+    }
+  } else if (pd.post == POST_PROP2D) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t e = (int64_t)(j + t * L) * c.nz + line;
+      in.hh[t] = c.H_hi[e];
+      in.hl[t] = c.H_lo[e];
+    }
   }
-  fft_line<N, true>(v, sh, j, c.twy_hi, c.twy_lo);
+  if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
+    const float* dp = c.delta + (int64_t)pd.slice * c.m;
+    const float* bp = c.beta + (int64_t)pd.slice * c.m;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t a = line_addr<N, AXIS>(c, line, j + t * L);
+      in.dl[t] = dp[a];
+      in.bt[t] = bp[a];
+    }
+  }
+  if (pd.mid == MID_T_ADJ) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) in.ps[t] = pd.psi_load[line_addr<N, AXIS>(c, line, j + t * L)];
+  }
+  if (pd.mid == MID_FF_SEED) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = j + t * L;
+      const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
+      const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
+      in.gi[t] = c.grad_intensity[(int64_t)rs * c.nz + cs];
+    }
+  }
 }
 
 template <int N, int AXIS>
-__device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
+__device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N>& in) {
   constexpr int L = N / 8;
-  const float2* twh = AXIS == ROW ? c.twz_hi : c.twy_hi;
-  const float2* twl = AXIS == ROW ? c.twz_lo : c.twy_lo;
-  const float inv_n = 1.0f / (float)N;
-  float2 v[8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) v[t] = pd.src[line_addr<N, AXIS>(c, line, j + t * L)];
+  for (int t = 0; t < 8; ++t) in.v[t] = pd.src[line_addr<N, AXIS>(c, line, j + t * L)];
+}
+
+template <int N>
+__device__ __forceinline__ void prop_line(float2 (&v)[8], float2* sh, int j, const LineIn<N>& in, bool conj) {
+  fft_line<N, false>(v, sh, j, in.tw);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj);
+  fft_line<N, true>(v, sh, j, in.tw);
+}
+
+template <int N, int AXIS>
+__device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh,
+                                             LineIn<N>& in) {
+  constexpr int L = N / 8;
+  const float inv_n = 1.0f / (float)N;
+  float2 (&v)[8] = in.v;
 
   switch (pd.pre) {
-    case PRE_PROP: prop_line<N, AXIS>(v, sh, j, c, pd.conj != 0); break;
-    case PRE_FFT: fft_line<N, false>(v, sh, j, twh, twl); break;
+    case PRE_PROP: prop_line<N>(v, sh, j, in, pd.conj != 0); break;
+    case PRE_FFT: fft_line<N, false>(v, sh, j, in.tw); break;
     case PRE_IFFT_N:
-      fft_line<N, true>(v, sh, j, twh, twl);
+      fft_line<N, true>(v, sh, j, in.tw);
 #pragma unroll
       for (int t = 0; t < 8; ++t) v[t] = make_float2(v[t].x * inv_n, v[t].y * inv_n);
       break;
-    case PRE_IFFT_U: fft_line<N, true>(v, sh, j, twh, twl); break;
+    case PRE_IFFT_U: fft_line<N, true>(v, sh, j, in.tw); break;
     default: break;
   }
 
@@ -304,22 +371,18 @@ __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int l
   }
 
   if (pd.mid == MID_T_FWD) {
-    const int64_t so = (int64_t)pd.slice * c.m;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t e = so + line_addr<N, AXIS>(c, line, j + t * L);
-      v[t] = apply_t(v[t], transmission_m1(phase_arg(c.delta[e], c), phase_arg(c.beta[e], c)));
-    }
+    for (int t = 0; t < 8; ++t)
+      v[t] = apply_t(v[t], transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c)));
   } else if (pd.mid == MID_T_ADJ) {
     const int64_t so = (int64_t)pd.slice * c.m;
     const float kdx = c.kdx_hi;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int64_t a = line_addr<N, AXIS>(c, line, j + t * L);
-      const int64_t e = so + a;
-      const float2 tm1 = transmission_m1(phase_arg(c.delta[e], c), phase_arg(c.beta[e], c));
-      const float2 pt = apply_t(pd.psi_load[a], tm1);  // psi'_s = T_s psi_s
-      const float2 g = v[t];                           // cotangent of psi'_s
+      const int64_t e = so + line_addr<N, AXIS>(c, line, j + t * L);
+      const float2 tm1 = transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c));
+      const float2 pt = apply_t(in.ps[t], tm1);  // psi'_s = T_s psi_s
+      const float2 g = v[t];                     // cotangent of psi'_s
       // conj(g) * psi' = (gx px + gy py) + i (gx py - gy px)
       const float cre = __builtin_fmaf(g.x, pt.x, g.y * pt.y);
       const float cim = __builtin_fmaf(g.x, pt.y, -(g.y * pt.x));
@@ -339,18 +402,15 @@ __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int l
   } else if (pd.mid == MID_FF_SEED) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int i = j + t * L;
-      const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
-      const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
-      const float s = 2.0f * c.inv_m * c.grad_intensity[(int64_t)rs * c.nz + cs];
+      const float s = 2.0f * c.inv_m * in.gi[t];
       v[t] = make_float2(v[t].x * s, v[t].y * s);
     }
   }
 
   switch (pd.post) {
-    case POST_PROP: prop_line<N, AXIS>(v, sh, j, c, pd.conj != 0); break;
-    case POST_FFT: fft_line<N, false>(v, sh, j, twh, twl); break;
-    case POST_PROP2D: prop2d_line<N, AXIS>(v, sh, j, line, c, pd.conj != 0); break;
+    case POST_PROP: prop_line<N>(v, sh, j, in, pd.conj != 0); break;
+    case POST_FFT: fft_line<N, false>(v, sh, j, in.tw); break;
+    case POST_PROP2D: prop_line<N>(v, sh, j, in, pd.conj != 0); break;  // H[ky][kz] / ny loaded in hh, hl
     default: break;
   }
 
@@ -358,6 +418,14 @@ __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int l
 #pragma unroll
     for (int t = 0; t < 8; ++t) pd.dst[line_addr<N, AXIS>(c, line, j + t * L)] = v[t];
   }
+}
+
+template <int N, int AXIS>
+__device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
+  LineIn<N> in;
+  load_field<N, AXIS>(c, pd, line, j, in);
+  load_static<N, AXIS>(c, pd, line, j, in);
+  compute_line<N, AXIS>(c, pd, line, j, sh, in);
 }
 
 // Workgroups are dealt to the XCDs round robin; give each XCD a contiguous

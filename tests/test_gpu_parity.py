@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 FIELD_TOL = 2e-5
 INT_TOL = 1e-4
 GRAD_TOL = 1e-3
-SCHEDULES = [1]  # per-pass launches (the persistent schedule is added to this list once built)
+SCHEDULES = [1, 2]  # per-pass launches, persistent cooperative kernel
 
 
 def rel(a, b):
