@@ -66,7 +66,7 @@ def main():
     ap.add_argument("--ckpt-every", type=int, default=32)
     ap.add_argument("--schedule", type=int, default=0, help="0 auto, 1 per-pass launches, 2 persistent")
     ap.add_argument("--slices", type=int, default=2048)
-    ap.add_argument("--cpu-sample-slices", type=int, default=128)
+    ap.add_argument("--cpu-sample-slices", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -39,7 +39,7 @@ struct Layout {
   size_t twz_hi, twz_lo, twy_hi, twy_lo;
   size_t hz_hi, hz_lo, hy_hi, hy_lo;
   size_t H_hi, H_lo;
-  size_t bar, partials, tmp, W, G, seg;
+  size_t bar, partials, tmp, dbT, W, G, seg, gT;
   size_t total;
 };
 
@@ -61,13 +61,17 @@ Layout layout(const msl_geometry& g, int k) {
   const bool exact = g.propagator == MSL_PROP_EXACT;
   L.H_hi = take(exact ? m * 8 : 0);
   L.H_lo = take(exact ? m * 8 : 0);
-  L.bar = take(kAlign);
+  L.bar = take(8192);
   L.partials = take(kPartials * sizeof(double));
   L.tmp = take(m * 8);
+  // paraxial: odd slices' (delta, beta) packed and transposed for the column passes
+  const size_t odd = exact ? 0 : (size_t)(g.n_slices / 2);
+  L.dbT = take(odd * m * 8);
   if (k >= 1) {
     L.W = take(m * 8);
     L.G = take(m * 8);
-    L.seg = take((size_t)(k > 1 ? k - 1 : 0) * m * 8);
+    L.seg = take((size_t)(k > 1 ? k - 1 : 0) * m * 8 * 2);  // two segment buffers
+    L.gT = take(odd * m * 8);  // odd slices' gradients, same layout as dbT
   }
   L.total = o;
   return L;
@@ -183,6 +187,40 @@ __global__ void k_probe(int ny, int nz, double q, float2* out) {
   out[i] = make_float2((float)c, (float)s);
 }
 
+// Odd slices' (delta, beta) -> dbT[s/2][z][y] (float2), through 16x16 LDS tiles.
+__global__ void __launch_bounds__(256) k_pack_odd(const float* d, const float* b, float2* out, int ny, int nz,
+                                                  int nodd) {
+  __shared__ float2 tile[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int z0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+  const int64_t m = (int64_t)ny * nz;
+  for (int s2 = blockIdx.z; s2 < nodd; s2 += gridDim.z) {
+    const int64_t si = (int64_t)(2 * s2 + 1) * m;
+    tile[ty][tx] = make_float2(d[si + (int64_t)(y0 + ty) * nz + z0 + tx], b[si + (int64_t)(y0 + ty) * nz + z0 + tx]);
+    __syncthreads();
+    out[(int64_t)s2 * m + (int64_t)(z0 + ty) * ny + y0 + tx] = tile[tx][ty];
+    __syncthreads();
+  }
+}
+
+// gT[s/2][z][y] (float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z] for odd s.
+__global__ void __launch_bounds__(256) k_unpack_odd(const float2* gT, float* gd, float* gb, int ny, int nz,
+                                                    int nodd) {
+  __shared__ float2 tile[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int z0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+  const int64_t m = (int64_t)ny * nz;
+  for (int s2 = blockIdx.z; s2 < nodd; s2 += gridDim.z) {
+    tile[ty][tx] = gT[(int64_t)s2 * m + (int64_t)(z0 + ty) * ny + y0 + tx];
+    __syncthreads();
+    const float2 v = tile[tx][ty];
+    const int64_t o = (int64_t)(2 * s2 + 1) * m + (int64_t)(y0 + ty) * nz + z0 + tx;
+    if (gd) gd[o] = v.x;
+    if (gb) gb[o] = v.y;
+    __syncthreads();
+  }
+}
+
 // Amplitude loss partial sums (FP64) and dL/dI.
 __global__ void __launch_bounds__(256) k_amp_loss(const float* I, const float* mamp, float* gI,
                                                   double* partials, int64_t n) {
@@ -227,6 +265,44 @@ __global__ void __launch_bounds__(128) k_pass(Ctx c, PassDesc pd) {
   const int G = blockDim.x / L;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
   msl::run_line<N, AXIS>(c, pd, group * G + g, j, lds + g * (N + N / 8));
+}
+
+// Two independent passes in one launch (square grids): blocks [0, nba) run
+// `a`, the rest run `b`; each block picks its axis at run time.
+template <int N>
+__global__ void __launch_bounds__(128) k_pass2(Ctx c, PassDesc a, PassDesc b, int nba) {
+  __shared__ float2 lds[1152];
+  constexpr int L = N / 8;
+  const int g = threadIdx.x / L, j = threadIdx.x % L;
+  const int G = blockDim.x / L;
+  const bool second = (int)blockIdx.x >= nba;
+  const PassDesc pd = second ? b : a;
+  const int nb = second ? (int)gridDim.x - nba : nba;
+  const int group = msl::xcd_group(second ? (int)blockIdx.x - nba : (int)blockIdx.x, nb);
+  msl::run_line_any<N>(c, pd, group * G + g, j, lds + g * (N + N / 8));
+}
+
+template <int N>
+hipError_t launch_pass2_t(const Ctx& c, const PassDesc& a, const PassDesc& b, hipStream_t st) {
+  constexpr int L = N / 8;
+  int G = L >= 64 ? 1 : 64 / L;
+  if (G > N) G = N;
+  const int nb = N / G;
+  hipLaunchKernelGGL((k_pass2<N>), dim3(2 * nb), dim3(L * G), 0, st, c, a, b, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass2(const Ctx& c, const PassDesc& a, const PassDesc& b, hipStream_t st) {
+  switch (c.ny) {
+    case 16: return launch_pass2_t<16>(c, a, b, st);
+    case 32: return launch_pass2_t<32>(c, a, b, st);
+    case 64: return launch_pass2_t<64>(c, a, b, st);
+    case 128: return launch_pass2_t<128>(c, a, b, st);
+    case 256: return launch_pass2_t<256>(c, a, b, st);
+    case 512: return launch_pass2_t<512>(c, a, b, st);
+    case 1024: return launch_pass2_t<1024>(c, a, b, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int N, int AXIS>
@@ -320,28 +396,53 @@ msl_status build_tables(const Call& k, bool need_prop) {
   return hip_check(hipGetLastError(), "table kernels");
 }
 
-msl_status run_phase(const Call& k, const PhaseSpec& ph) {
-  const int np = msl::phase_npasses(ph);
-  if (np == 0) return MSL_OK;
+bool use_persistent(const Call& k, int np) {
   // the persistent kernel serves square grids; other shapes always run per pass
-  const bool persistent = k.c.ny == k.c.nz && ((g_schedule == MSL_SCHED_PERSISTENT) ||
-                          (g_schedule == MSL_SCHED_AUTO && msl::persistent_preferred(k.c, np)));
-  if (persistent) {
-    hipError_t e = msl::launch_persistent(k.c, ph, np, reinterpret_cast<unsigned*>(k.ws + k.L.bar), k.st);
+  if (k.c.ny != k.c.nz) return false;
+  return g_schedule == MSL_SCHED_PERSISTENT ||
+         (g_schedule == MSL_SCHED_AUTO && msl::persistent_preferred(k.c, np));
+}
+
+// Runs phase a, and phase b beside it when given (independent fields of a
+// square grid), either as one cooperative launch or as launches per pass.
+msl_status run_phases(const Call& k, const PhaseSpec& a, const PhaseSpec* b) {
+  const int npa = msl::phase_npasses(a);
+  const int npb = b ? msl::phase_npasses(*b) : 0;
+  const int np = npa > npb ? npa : npb;
+  if (np == 0) return MSL_OK;
+  unsigned* bar = reinterpret_cast<unsigned*>(k.ws + k.L.bar);
+  if (use_persistent(k, np)) {
+    hipError_t e = msl::launch_persistent(k.c, a, npa, npb > 0 ? b : nullptr, npb, bar, k.st);
     if (e == hipSuccess) return MSL_OK;
     if (g_schedule == MSL_SCHED_PERSISTENT) return hip_check(e, "persistent pass kernel");
     (void)hipGetLastError();  // AUTO: the per-pass schedule below does the same work
   }
   for (int p = 0; p < np; ++p) {
-    const PassDesc pd = msl::phase_pass(ph, p);
-    hipError_t e = launch_pass(k.c, pd, k.st);
+    hipError_t e;
+    if (p < npa && p < npb) e = launch_pass2(k.c, msl::phase_pass(a, p), msl::phase_pass(*b, p), k.st);
+    else if (p < npa) e = launch_pass(k.c, msl::phase_pass(a, p), k.st);
+    else e = launch_pass(k.c, msl::phase_pass(*b, p), k.st);
     if (e != hipSuccess) return hip_check(e, "pass kernel");
   }
   return MSL_OK;
 }
 
+msl_status run_phase(const Call& k, const PhaseSpec& ph) { return run_phases(k, ph, nullptr); }
+
 msl_status copy_field(const Call& k, void* dst, const void* src) {
   return hip_check(hipMemcpyAsync(dst, src, (size_t)k.c.m * 8, hipMemcpyDeviceToDevice, k.st), "hipMemcpyAsync");
+}
+
+int odd_slices(const msl_geometry& g) { return g.propagator == MSL_PROP_PARAXIAL ? g.n_slices / 2 : 0; }
+
+msl_status pack_odd(Call& k, const float* delta, const float* beta) {
+  const int nodd = odd_slices(k.g);
+  if (nodd == 0) return MSL_OK;
+  float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
+  dim3 grid(k.g.nz / 16, k.g.ny / 16, nodd < 8192 ? nodd : 8192);
+  hipLaunchKernelGGL(k_pack_odd, grid, dim3(256), 0, k.st, delta, beta, dbT, k.g.ny, k.g.nz, nodd);
+  k.c.dbT = dbT;
+  return hip_check(hipGetLastError(), "pack kernel");
 }
 
 PhaseSpec blank_phase(const Call& k, int kind) {
@@ -400,6 +501,7 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   k.c.delta = delta;
   k.c.beta = beta;
   MSL_TRY(build_tables(k, true));
+  MSL_TRY(pack_odd(k, delta, beta));
   float2* f = reinterpret_cast<float2*>(field_out);
   if (probe) {
     MSL_TRY(copy_field(k, f, probe));
@@ -488,6 +590,9 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   k.c.gdelta = grad_delta;
   k.c.gbeta = grad_beta;
   MSL_TRY(build_tables(k, true));
+  MSL_TRY(pack_odd(k, delta, beta));
+  const int nodd = odd_slices(*g);
+  if (nodd > 0 && (grad_delta || grad_beta)) k.c.gT = reinterpret_cast<float2*>(k.ws + k.L.gT);
   float2* W = reinterpret_cast<float2*>(k.ws + k.L.W);
   float2* G = reinterpret_cast<float2*>(k.ws + k.L.G);
   float2* seg = reinterpret_cast<float2*>(k.ws + k.L.seg);
@@ -495,27 +600,52 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   MSL_TRY(copy_field(k, G, grad_field));
   const int ns = g->n_slices;
   const int nck = (ns + ckpt_every - 1) / ckpt_every;
-  for (int c = nck - 1; c >= 0; --c) {
-    const int s0 = c * ckpt_every;
-    const int s1 = s0 + ckpt_every < ns ? s0 + ckpt_every : ns;
-    const float2* ckc = ck + (int64_t)c * k.c.m;
-    if (s1 - s0 >= 2) {
-      MSL_TRY(copy_field(k, W, ckc));
-      PhaseSpec ph = blank_phase(k, msl::PH_FWD_RECOMP);
-      ph.s0 = s0;
-      ph.s1 = s1;
-      ph.field = W;
-      ph.seg = seg;
-      MSL_TRY(run_phase(k, ph));
-    }
+  const int64_t seg_stride = (int64_t)(ckpt_every > 1 ? ckpt_every - 1 : 0) * k.c.m;
+  auto seg_of = [&](int c) { return seg + (c & 1) * seg_stride; };
+  auto recomp = [&](int c) {
+    PhaseSpec ph = blank_phase(k, msl::PH_FWD_RECOMP);
+    ph.s0 = c * ckpt_every;
+    ph.s1 = ph.s0 + ckpt_every < ns ? ph.s0 + ckpt_every : ns;
+    ph.field = W;
+    ph.seg = seg_of(c);
+    return ph;
+  };
+  auto reverse = [&](int c) {
     PhaseSpec rv = blank_phase(k, msl::PH_REV);
-    rv.s0 = s0;
-    rv.s1 = s1;
+    rv.s0 = c * ckpt_every;
+    rv.s1 = rv.s0 + ckpt_every < ns ? rv.s0 + ckpt_every : ns;
     rv.leading = c == nck - 1;
     rv.field = G;
-    rv.seg = seg;
-    rv.ckpt_c = ckc;
-    MSL_TRY(run_phase(k, rv));
+    rv.seg = seg_of(c);
+    rv.ckpt_c = ck + (int64_t)c * k.c.m;
+    return rv;
+  };
+  // Segment c-1 is recomputed from its checkpoint while the reverse sweep runs
+  // over segment c: the two fields are independent, so on square grids they
+  // share passes (and each pass has twice the lines to spread over the chip).
+  const bool pair = g->ny == g->nz;
+  PhaseSpec rc = recomp(nck - 1);
+  MSL_TRY(copy_field(k, W, ck + (int64_t)(nck - 1) * k.c.m));
+  MSL_TRY(run_phase(k, rc));
+  for (int c = nck - 1; c >= 0; --c) {
+    PhaseSpec rv = reverse(c);
+    if (c >= 1) {
+      PhaseSpec nx = recomp(c - 1);
+      MSL_TRY(copy_field(k, W, ck + (int64_t)(c - 1) * k.c.m));
+      if (pair) {
+        MSL_TRY(run_phases(k, rv, &nx));
+      } else {
+        MSL_TRY(run_phase(k, rv));
+        MSL_TRY(run_phase(k, nx));
+      }
+    } else {
+      MSL_TRY(run_phase(k, rv));
+    }
+  }
+  if (k.c.gT) {
+    dim3 grid(g->nz / 16, g->ny / 16, nodd < 8192 ? nodd : 8192);
+    hipLaunchKernelGGL(k_unpack_odd, grid, dim3(256), 0, k.st, k.c.gT, grad_delta, grad_beta, g->ny, g->nz, nodd);
+    MSL_TRY(hip_check(hipGetLastError(), "unpack kernel"));
   }
   if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));
   return MSL_OK;

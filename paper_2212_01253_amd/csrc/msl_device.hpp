@@ -54,6 +54,12 @@ struct Ctx {
   float inv_m;                      // 1 / (ny nz)
   float* intensity;                 // far-field output (fftshifted) or nullptr
   const float* grad_intensity;      // far-field seed input (fftshifted) or nullptr
+  // Odd slices are always transmitted in column passes (paraxial schedule).
+  // For them the workspace may hold (delta, beta) packed and transposed,
+  // [Ns/2][nz][ny] float2, and a staging area for their (dL/d delta,
+  // dL/d beta) in the same layout, so column passes access both coalesced.
+  const float2* dbT;                // or nullptr
+  float2* gT;                       // or nullptr
 };
 
 // ---------------------------------------------------------------------------
@@ -209,35 +215,37 @@ __device__ __forceinline__ void fft_line(float2 (&v)[8], float2* sh, int j, cons
 // ---------------------------------------------------------------------------
 // slice transmission
 
-// Returns T - 1 for T = exp(i a - b): Taylor forms for |a|, |b| <= 1/8 (all
-// workloads of interest: k dx delta is ~1e-2), library functions otherwise.
+// Returns T - 1 for T = exp(i a - b).  Taylor forms serve |a|, |b| <= 1/8
+// (every workload of interest: k dx delta is ~1e-2); the library functions
+// run only in waves where some lane is outside that range.
+__device__ __forceinline__ float sin_small(float x) {
+  // sin x = x (1 - x^2/6 (1 - x^2/20 (1 - x^2/42))), |x| <= 1/8
+  const float x2 = x * x;
+  return x * __builtin_fmaf(-x2 * (1.0f / 6.0f),
+                            __builtin_fmaf(-x2 * (1.0f / 20.0f), __builtin_fmaf(-x2, 1.0f / 42.0f, 1.0f), 1.0f),
+                            1.0f);
+}
+
+__device__ __forceinline__ float expm1_neg_small(float b) {
+  // expm1(-b) = -b (1 - b/2 (1 - b/3 (1 - b/4 (1 - b/5 (1 - b/6 (1 - b/7)))))), |b| <= 1/8
+  float p = __builtin_fmaf(-b, 1.0f / 7.0f, 1.0f);
+  p = __builtin_fmaf(-b * (1.0f / 6.0f), p, 1.0f);
+  p = __builtin_fmaf(-b * (1.0f / 5.0f), p, 1.0f);
+  p = __builtin_fmaf(-b * (1.0f / 4.0f), p, 1.0f);
+  p = __builtin_fmaf(-b * (1.0f / 3.0f), p, 1.0f);
+  p = __builtin_fmaf(-b * 0.5f, p, 1.0f);
+  return -b * p;
+}
+
 __device__ __forceinline__ float2 transmission_m1(float a, float b) {
-  float sa, sh, em1;
-  if (fabsf(a) <= 0.125f) {
-    const float a2 = a * a;
-    // sin x = x (1 - x^2/6 (1 - x^2/20 (1 - x^2/42)))
-    sa = a * __builtin_fmaf(-a2 * (1.0f / 6.0f),
-                            __builtin_fmaf(-a2 * (1.0f / 20.0f),
-                                           __builtin_fmaf(-a2, 1.0f / 42.0f, 1.0f), 1.0f), 1.0f);
-    const float h = 0.5f * a, h2 = h * h;
-    sh = h * __builtin_fmaf(-h2 * (1.0f / 6.0f),
-                            __builtin_fmaf(-h2 * (1.0f / 20.0f),
-                                           __builtin_fmaf(-h2, 1.0f / 42.0f, 1.0f), 1.0f), 1.0f);
-  } else {
-    sa = sinf(a);
-    sh = sinf(0.5f * a);
-  }
-  if (fabsf(b) <= 0.125f) {
-    // expm1(-b) = -b (1 - b/2 (1 - b/3 (1 - b/4 (1 - b/5 (1 - b/6 (1 - b/7))))))
-    float p = __builtin_fmaf(-b, 1.0f / 7.0f, 1.0f);
-    p = __builtin_fmaf(-b * (1.0f / 6.0f), p, 1.0f);
-    p = __builtin_fmaf(-b * (1.0f / 5.0f), p, 1.0f);
-    p = __builtin_fmaf(-b * (1.0f / 4.0f), p, 1.0f);
-    p = __builtin_fmaf(-b * (1.0f / 3.0f), p, 1.0f);
-    p = __builtin_fmaf(-b * 0.5f, p, 1.0f);
-    em1 = -b * p;
-  } else {
-    em1 = expm1f(-b);
+  float sa = sin_small(a), sh = sin_small(0.5f * a), em1 = expm1_neg_small(b);
+  const bool big = !(fabsf(a) <= 0.125f && fabsf(b) <= 0.125f);
+  if (__builtin_expect(__ballot(big) != 0, 0)) {
+    if (big) {
+      sa = sinf(a);
+      sh = sinf(0.5f * a);
+      em1 = expm1f(-b);
+    }
   }
   const float cm1 = -2.0f * sh * sh;  // cos a - 1
   // T - 1 = (1 + em1)(1 + cm1 + i sa) - 1
@@ -307,13 +315,23 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd, in
     }
   }
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
-    const float* dp = c.delta + (int64_t)pd.slice * c.m;
-    const float* bp = c.beta + (int64_t)pd.slice * c.m;
+    if (AXIS == COL && c.dbT && (pd.slice & 1)) {
+      const float2* q = c.dbT + (int64_t)(pd.slice >> 1) * c.m + (int64_t)line * c.ny;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t a = line_addr<N, AXIS>(c, line, j + t * L);
-      in.dl[t] = dp[a];
-      in.bt[t] = bp[a];
+      for (int t = 0; t < 8; ++t) {
+        const float2 db = q[j + t * L];
+        in.dl[t] = db.x;
+        in.bt[t] = db.y;
+      }
+    } else {
+      const float* dp = c.delta + (int64_t)pd.slice * c.m;
+      const float* bp = c.beta + (int64_t)pd.slice * c.m;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t a = line_addr<N, AXIS>(c, line, j + t * L);
+        in.dl[t] = dp[a];
+        in.bt[t] = bp[a];
+      }
     }
   }
   if (pd.mid == MID_T_ADJ) {
@@ -331,11 +349,36 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd, in
   }
 }
 
-template <int N, int AXIS>
+// Field element access.  COH selects device-coherent accesses (agent-scope
+// atomics: written through to and read from the coherence point, past the
+// per-XCD L2 caches), used when another XCD reads the data within the same
+// kernel; plain accesses otherwise.
+template <bool COH>
+__device__ __forceinline__ float2 field_ld(const float2* p) {
+  if constexpr (COH) {
+    const unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, u);
+  } else {
+    return *p;
+  }
+}
+
+template <bool COH>
+__device__ __forceinline__ void field_st(float2* p, float2 v) {
+  if constexpr (COH) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = v;
+  }
+}
+
+template <int N, int AXIS, bool COH = false>
 __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N>& in) {
   constexpr int L = N / 8;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) in.v[t] = pd.src[line_addr<N, AXIS>(c, line, j + t * L)];
+  for (int t = 0; t < 8; ++t) in.v[t] = field_ld<COH>(pd.src + line_addr<N, AXIS>(c, line, j + t * L));
 }
 
 template <int N>
@@ -346,7 +389,7 @@ __device__ __forceinline__ void prop_line(float2 (&v)[8], float2* sh, int j, con
   fft_line<N, true>(v, sh, j, in.tw);
 }
 
-template <int N, int AXIS>
+template <int N, int AXIS, bool COH = false>
 __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh,
                                              LineIn<N>& in) {
   constexpr int L = N / 8;
@@ -386,8 +429,12 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, i
       // conj(g) * psi' = (gx px + gy py) + i (gx py - gy px)
       const float cre = __builtin_fmaf(g.x, pt.x, g.y * pt.y);
       const float cim = __builtin_fmaf(g.x, pt.y, -(g.y * pt.x));
-      if (c.gdelta) c.gdelta[e] = -kdx * cim;
-      if (c.gbeta) c.gbeta[e] = -kdx * cre;
+      if (AXIS == COL && c.gT && (pd.slice & 1)) {
+        c.gT[(int64_t)(pd.slice >> 1) * c.m + (int64_t)line * c.ny + j + t * L] = make_float2(-kdx * cim, -kdx * cre);
+      } else {
+        if (c.gdelta) c.gdelta[e] = -kdx * cim;
+        if (c.gbeta) c.gbeta[e] = -kdx * cre;
+      }
       v[t] = apply_tconj(g, tm1);
     }
   } else if (pd.mid == MID_FF_OUT) {
@@ -416,16 +463,23 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, i
 
   if (pd.dst) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) pd.dst[line_addr<N, AXIS>(c, line, j + t * L)] = v[t];
+    for (int t = 0; t < 8; ++t) field_st<COH>(pd.dst + line_addr<N, AXIS>(c, line, j + t * L), v[t]);
   }
 }
 
-template <int N, int AXIS>
+template <int N, int AXIS, bool COH = false>
 __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
   LineIn<N> in;
-  load_field<N, AXIS>(c, pd, line, j, in);
+  load_field<N, AXIS, COH>(c, pd, line, j, in);
   load_static<N, AXIS>(c, pd, line, j, in);
-  compute_line<N, AXIS>(c, pd, line, j, sh, in);
+  compute_line<N, AXIS, COH>(c, pd, line, j, sh, in);
+}
+
+// Either axis, chosen per pass at run time (square grids: both line lengths are N).
+template <int N, bool COH = false>
+__device__ __forceinline__ void run_line_any(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
+  if (pd.axis == ROW) run_line<N, ROW, COH>(c, pd, line, j, sh);
+  else run_line<N, COL, COH>(c, pd, line, j, sh);
 }
 
 // Workgroups are dealt to the XCDs round robin; give each XCD a contiguous

@@ -9,6 +9,9 @@
 // side:  T_0, P_z | P_y, T_1, P_y | P_z, T_2, P_z | ...  so every slice is
 // ONE pass over lines of one axis: propagate, transmit, propagate.  That is
 // one field round trip and one global exchange per slice instead of two.
+// Slice s is always transmitted in a pass of axis s mod 2 (rows for even
+// slices, columns for odd ones), in every phase, so the odd slices' inputs
+// and gradients can be kept in a column-friendly layout.
 //
 // Exact angular-spectrum propagator.  It does not factorise; each slice takes
 // a row pass (z-IFFT, transmission, z-FFT) and a column pass (y-FFT, H, y-IFFT)
@@ -80,7 +83,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
   switch (ph.kind) {
     case PH_FWD_FULL:
       if (!ph.exact) {
-        PassDesc d = blank_pass((p & 1) ? COL : ROW, f, f);
+        PassDesc d = blank_pass(((ph.s0 + p) & 1) ? COL : ROW, f, f);
         if (p < n) {
           d.pre = p == 0 ? PRE_NONE : PRE_PROP;
           d.mid = MID_T_FWD;
@@ -110,7 +113,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       }
     case PH_FWD_RECOMP:
       if (!ph.exact) {
-        PassDesc d = blank_pass((p & 1) ? COL : ROW, f, f);
+        PassDesc d = blank_pass(((ph.s0 + p) & 1) ? COL : ROW, f, f);
         d.pre = p == 0 ? PRE_NONE : PRE_PROP;
         if (p > 0) d.psi_store = ph.seg + (int64_t)(p - 1) * ph.m;
         if (p < n - 1) {
@@ -142,7 +145,8 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       }
     case PH_REV: {
       if (ph.leading && p == 0) {
-        PassDesc d = blank_pass(ROW, f, f);
+        // precedes the pass of slice ns - 1, so it takes the other axis
+        PassDesc d = blank_pass((!ph.exact && (ph.ns & 1)) ? COL : ROW, f, f);
         if (ph.exact) d.post = POST_FFT;
         else { d.pre = PRE_PROP; d.conj = 1; }
         return d;
@@ -150,8 +154,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       const int q = p - (ph.leading ? 1 : 0);
       if (!ph.exact) {
         const int s = ph.s1 - 1 - q;
-        const int r = ph.ns - s;  // global reverse pass index sets the axis
-        PassDesc d = blank_pass((r & 1) ? COL : ROW, f, f);
+        PassDesc d = blank_pass((s & 1) ? COL : ROW, f, f);
         d.pre = PRE_PROP;
         d.conj = 1;
         d.mid = MID_T_ADJ;

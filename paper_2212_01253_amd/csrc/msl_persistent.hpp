@@ -1,20 +1,24 @@
-// Persistent schedule: one cooperative launch runs every pass of a phase,
-// with a device-wide barrier between passes.
+// Persistent schedule: one cooperative launch runs every pass of a phase (or
+// of two independent phases side by side), with a device-wide barrier
+// between passes.
 //
 // Each pass is an all-to-all dependency (a column needs every row of the
-// previous pass), so a barrier per pass is the minimum synchronisation.  A
-// kernel launch per pass costs a launch, a drain and a ramp-up; a barrier
-// inside one resident grid costs one round of agent-scope atomics.  Grid
-// size is capped by what is co-resident (hipLaunchCooperativeKernel refuses
-// anything larger), so every block that waits at a barrier is running.
+// previous pass), so one barrier per pass is the minimum synchronisation.
+// Grid size is capped by what is co-resident (hipLaunchCooperativeKernel
+// refuses anything larger), so every block that waits at a barrier runs.
 //
-// Barrier: a monotonic arrival counter in the workspace, zeroed by a small
-// kernel before the launch.  Every wave releases its stores at agent scope
-// (the XCDs' L2 caches are not coherent with each other), one thread per
-// block adds its arrival and spins with s_sleep until all blocks of this
-// pass have arrived, then every wave acquires.  The spin is bounded: after
-// kSpinLimit polls it sets an error word and stops waiting, in this and
-// every later barrier, so the grid always drains.
+// Exchange and barrier.  The per-XCD L2 caches are not coherent with each
+// other, and an agent-scope release fence writes back a whole L2, which
+// costs more than the pass itself.  Instead, the field that passes hand to
+// each other is written and read with device-coherent (agent-scope atomic)
+// accesses, and the barrier only has to order them: every wave waits for
+// its own stores to complete, then each block publishes the barrier epoch
+// in its own flag word, and every block polls all flags.  No counter is
+// shared, so arrivals do not serialise on one address.  Other outputs
+// (checkpoints, segment fields, gradients) are read only by later kernels.
+// The wait is bounded: after kSpinLimit polls a block raises an error word
+// and stops waiting, in this and every later barrier, so the grid always
+// drains.
 #pragma once
 
 #include "msl_passes.hpp"
@@ -22,27 +26,32 @@
 namespace msl {
 
 constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int kMaxFlags = 2040;  // flag words after the error word (bar[0]) in the barrier area
 
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target) {
-  __threadfence();
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned epoch, int nb) {
+  unsigned* err = bar;
+  unsigned* flags = bar + 8;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
-        __hip_atomic_fetch_or(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
+  if (threadIdx.x == 0) __hip_atomic_store(flags + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned spins = 0;
+  for (;;) {
+    int ok = 1;
+    for (int t = threadIdx.x; t < nb; t += blockDim.x)
+      ok &= __hip_atomic_load(flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+    const int errd = threadIdx.x == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (__syncthreads_and(ok) || __syncthreads_or(errd)) break;
+    if (++spins > kSpinLimit) {
+      if (threadIdx.x == 0) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
     }
+    __builtin_amdgcn_s_sleep(2);
   }
-  __syncthreads();
-  __threadfence();
 }
 
-// Lines of one pass handled by one block per round, and block size.
+// Block size and lines per block of one field.
 template <int N>
 struct PersistShape {
   static constexpr int L = N / 8;
@@ -52,54 +61,47 @@ struct PersistShape {
   static constexpr int LDS = G * (N + N / 8);
 };
 
+// Blocks [0, nbA) run phase A, blocks [nbA, gridDim.x) run phase B (if npB > 0).
 template <int N>
-__global__ void __launch_bounds__(256) k_persist(Ctx c, PhaseSpec ph, int np, unsigned* bar, int rounds) {
+__global__ void __launch_bounds__(256) k_persist(Ctx c, PhaseSpec A, PhaseSpec B, int npA, int npB, int nbA,
+                                                 unsigned* bar, int rounds) {
   using S = PersistShape<N>;
   __shared__ float2 lds[S::LDS];
   const int g = threadIdx.x / S::L, j = threadIdx.x % S::L;
-  const int nb = gridDim.x;
-  const int bid = xcd_group(blockIdx.x, nb);
+  const bool second = (int)blockIdx.x >= nbA;
+  const PhaseSpec ph = second ? B : A;
+  const int np_mine = second ? npB : npA;
+  const int np_all = npA > npB ? npA : npB;
+  const int nb = second ? (int)gridDim.x - nbA : nbA;
+  const int bid = xcd_group(second ? (int)blockIdx.x - nbA : (int)blockIdx.x, nb);
   float2* sh = lds + g * (N + N / 8);
-  unsigned target = 0;
-  for (int p = 0; p < np; ++p) {
-    const PassDesc pd = phase_pass(ph, p);
-    for (int r = 0; r < rounds; ++r) {
-      const int line = (r * nb + bid) * S::G + g;
-      LineIn<N> in;
-      if (pd.axis == ROW) {
-        load_field<N, ROW>(c, pd, line, j, in);
-        load_static<N, ROW>(c, pd, line, j, in);
-        compute_line<N, ROW>(c, pd, line, j, sh, in);
-      } else {
-        load_field<N, COL>(c, pd, line, j, in);
-        load_static<N, COL>(c, pd, line, j, in);
-        compute_line<N, COL>(c, pd, line, j, sh, in);
-      }
+  for (int p = 0; p < np_all; ++p) {
+    if (p < np_mine) {
+      const PassDesc pd = phase_pass(ph, p);
+      for (int r = 0; r < rounds; ++r) run_line_any<N, true>(c, pd, (r * nb + bid) * S::G + g, j, sh);
     }
-    if (p + 1 < np) {
-      target += (unsigned)nb;
-      grid_barrier(bar, target);
-    }
+    if (p + 1 < np_all) grid_barrier(bar, (unsigned)(p + 1), (int)gridDim.x);
   }
 }
 
 __global__ void k_zero_words(unsigned* p, int n) {
-  const int i = threadIdx.x;
-  if (i < n) p[i] = 0u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 // The persistent schedule serves square grids (both pass axes have the same
-// line length and line count); long phases profit most.
+// line length and line count).
 inline bool persistent_preferred(const Ctx& c, int np) { return false && c.ny == c.nz && np >= 8; }
 
 struct PersistLaunch {
   int grid = 0, block = 0, rounds = 0;
 };
 
+// Blocks per field: the largest power of two <= line groups that fits
+// `fields` times in the co-resident limit.
 template <int N>
-hipError_t persist_shape(PersistLaunch& pl) {
+hipError_t persist_shape(PersistLaunch& pl, int fields) {
   using S = PersistShape<N>;
-  static int max_blocks = -1;  // co-resident blocks on this device (cached per process)
+  static int max_blocks = -1;  // co-resident blocks on the current device (cached per process)
   if (max_blocks < 0) {
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
@@ -111,10 +113,11 @@ hipError_t persist_shape(PersistLaunch& pl) {
     if (e != hipSuccess) return e;
     max_blocks = per_cu * prop.multiProcessorCount;
   }
-  const int groups = N / S::G;  // line groups per pass (square grid: N lines)
+  const int groups = N / S::G;
+  const int cap = max_blocks / fields;
+  if (cap < 1) return hipErrorCooperativeLaunchTooLarge;
   int grid = 1;
-  while (grid * 2 <= groups && grid * 2 <= max_blocks) grid *= 2;
-  if (grid < 1 || max_blocks < 1) return hipErrorCooperativeLaunchTooLarge;
+  while (grid * 2 <= groups && grid * 2 <= cap && grid * 2 * fields <= kMaxFlags) grid *= 2;
   pl.grid = grid;
   pl.block = S::T;
   pl.rounds = groups / grid;
@@ -122,31 +125,36 @@ hipError_t persist_shape(PersistLaunch& pl) {
 }
 
 template <int N>
-hipError_t launch_persistent_n(const Ctx& c, const PhaseSpec& ph, int np, unsigned* bar, hipStream_t st) {
+hipError_t launch_persistent_n(const Ctx& c, const PhaseSpec& a, int npa, const PhaseSpec* b, int npb,
+                               unsigned* bar, hipStream_t st) {
+  const int fields = (b && npb > 0) ? 2 : 1;
   PersistLaunch pl;
-  hipError_t e = persist_shape<N>(pl);
+  hipError_t e = persist_shape<N>(pl, fields);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, bar, 64);
+  const int total = pl.grid * fields;
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, bar, 8 + total);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   Ctx cc = c;
-  PhaseSpec pp = ph;
-  int npp = np, rr = pl.rounds;
-  void* args[] = {&cc, &pp, &npp, &bar, &rr};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<N>), dim3(pl.grid), dim3(pl.block),
+  PhaseSpec pa = a, pb = fields == 2 ? *b : a;
+  int npa_ = npa, npb_ = fields == 2 ? npb : 0, nba = pl.grid, rr = pl.rounds;
+  void* args[] = {&cc, &pa, &pb, &npa_, &npb_, &nba, &bar, &rr};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<N>), dim3(total), dim3(pl.block),
                                     args, 0, st);
 }
 
-inline hipError_t launch_persistent(const Ctx& c, const PhaseSpec& ph, int np, unsigned* bar, hipStream_t st) {
+// Runs phase a (and phase b beside it, if given) as one cooperative launch.
+inline hipError_t launch_persistent(const Ctx& c, const PhaseSpec& a, int npa, const PhaseSpec* b, int npb,
+                                    unsigned* bar, hipStream_t st) {
   if (c.ny != c.nz) return hipErrorNotSupported;
   switch (c.ny) {
-    case 16: return launch_persistent_n<16>(c, ph, np, bar, st);
-    case 32: return launch_persistent_n<32>(c, ph, np, bar, st);
-    case 64: return launch_persistent_n<64>(c, ph, np, bar, st);
-    case 128: return launch_persistent_n<128>(c, ph, np, bar, st);
-    case 256: return launch_persistent_n<256>(c, ph, np, bar, st);
-    case 512: return launch_persistent_n<512>(c, ph, np, bar, st);
-    case 1024: return launch_persistent_n<1024>(c, ph, np, bar, st);
+    case 16: return launch_persistent_n<16>(c, a, npa, b, npb, bar, st);
+    case 32: return launch_persistent_n<32>(c, a, npa, b, npb, bar, st);
+    case 64: return launch_persistent_n<64>(c, a, npa, b, npb, bar, st);
+    case 128: return launch_persistent_n<128>(c, a, npa, b, npb, bar, st);
+    case 256: return launch_persistent_n<256>(c, a, npa, b, npb, bar, st);
+    case 512: return launch_persistent_n<512>(c, a, npa, b, npb, bar, st);
+    case 1024: return launch_persistent_n<1024>(c, a, npa, b, npb, bar, st);
     default: return hipErrorNotSupported;
   }
 }

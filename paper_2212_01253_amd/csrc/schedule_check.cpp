@@ -244,7 +244,7 @@ int check(const Geo& g, int kck) {
   auto fake = [&](int slot) { return reinterpret_cast<float2*>((uintptr_t)(SPAN * 64 * (slot + 1))); };
   const int nck = (g.ns + kck - 1) / kck;
   Arr field{{probe}, fake(0), m}, ckpt{std::vector<Field>(nck, Field(m)), fake(1), m},
-      seg{std::vector<Field>(kck > 1 ? kck - 1 : 1, Field(m)), fake(2), m}, W{{Field(m)}, fake(3), m},
+      seg{std::vector<Field>(kck > 1 ? 2 * (kck - 1) : 1, Field(m)), fake(2), m}, W{{Field(m)}, fake(3), m},
       G{{Field(m)}, fake(4), m}, tmp{{Field(m)}, fake(5), m};
   g_arrays = {&field, &ckpt, &seg, &W, &G, &tmp};
 
@@ -295,21 +295,28 @@ int check(const Geo& g, int kck) {
   Field gref = dft2(seed, g, -1);
   if (rel(G.f[0], gref) > 1e-10) { std::printf("far-field adjoint mismatch %g\n", rel(G.f[0], gref)); ++bad; }
 
-  // adjoint with recompute
+  // adjoint with recompute: the same order as the library (segment c-1 is
+  // recomputed beside the reverse sweep over segment c, into the other of two
+  // segment buffers)
+  auto recomp = [&](int c) {
+    const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
+    if (s1 - s0 < 2) return;
+    W.f[0] = ckpt.f[c];
+    msl::PhaseSpec rc{};
+    rc.kind = msl::PH_FWD_RECOMP; rc.exact = g.exact; rc.s0 = s0; rc.s1 = s1; rc.ns = g.ns; rc.m = m;
+    rc.field = fake(3); rc.seg = fake(2) + (c & 1) * (int64_t)(kck > 1 ? kck - 1 : 0) * m;
+    run_phase(E, rc);
+  };
+  recomp(nck - 1);
   for (int c = nck - 1; c >= 0; --c) {
     const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
-    if (s1 - s0 >= 2) {
-      W.f[0] = ckpt.f[c];
-      msl::PhaseSpec rc{};
-      rc.kind = msl::PH_FWD_RECOMP; rc.exact = g.exact; rc.s0 = s0; rc.s1 = s1; rc.ns = g.ns; rc.m = m;
-      rc.field = fake(3); rc.seg = fake(2);
-      run_phase(E, rc);
-    }
     msl::PhaseSpec rv{};
     rv.kind = msl::PH_REV; rv.exact = g.exact; rv.s0 = s0; rv.s1 = s1; rv.ns = g.ns; rv.m = m;
-    rv.leading = c == nck - 1; rv.field = fake(4); rv.seg = fake(2);
+    rv.leading = c == nck - 1; rv.field = fake(4);
+    rv.seg = fake(2) + (c & 1) * (int64_t)(kck > 1 ? kck - 1 : 0) * m;
     rv.ckpt_c = fake(1) + (int64_t)c * m;
     run_phase(E, rv);
+    if (c >= 1) recomp(c - 1);
   }
   // direct reverse sweep
   Field gg = gref;
