@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "msl.h"
@@ -396,6 +397,32 @@ msl_status build_tables(const Call& k, bool need_prop) {
   return hip_check(hipGetLastError(), "table kernels");
 }
 
+// Helper stream and fork/join events of one device: the adjoint runs the
+// segment recompute on it beside the reverse sweep on the caller's stream.
+// Created on first use and kept for the life of the process (default
+// priority, non-blocking).
+struct Helper {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+msl_status helper_for_current_device(Helper*& out) {
+  static std::mutex mu;
+  static Helper helpers[64];
+  int dev = 0;
+  MSL_TRY(hip_check(hipGetDevice(&dev), "hipGetDevice"));
+  if (dev < 0 || dev >= 64) return fail(MSL_ERR_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  Helper& h = helpers[dev];
+  if (!h.s) {
+    MSL_TRY(hip_check(hipStreamCreateWithFlags(&h.s, hipStreamNonBlocking), "hipStreamCreateWithFlags"));
+    MSL_TRY(hip_check(hipEventCreateWithFlags(&h.fork, hipEventDisableTiming), "hipEventCreateWithFlags"));
+    MSL_TRY(hip_check(hipEventCreateWithFlags(&h.join, hipEventDisableTiming), "hipEventCreateWithFlags"));
+  }
+  out = &h;
+  return MSL_OK;
+}
+
 bool use_persistent(const Call& k, int np) {
   // the persistent kernel serves square grids; other shapes always run per pass
   if (k.c.ny != k.c.nz) return false;
@@ -623,23 +650,41 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   // Segment c-1 is recomputed from its checkpoint while the reverse sweep runs
   // over segment c: the two fields are independent, so on square grids they
   // share passes (and each pass has twice the lines to spread over the chip).
-  const bool pair = g->ny == g->nz;
   PhaseSpec rc = recomp(nck - 1);
   MSL_TRY(copy_field(k, W, ck + (int64_t)(nck - 1) * k.c.m));
   MSL_TRY(run_phase(k, rc));
-  for (int c = nck - 1; c >= 0; --c) {
-    PhaseSpec rv = reverse(c);
-    if (c >= 1) {
-      PhaseSpec nx = recomp(c - 1);
-      MSL_TRY(copy_field(k, W, ck + (int64_t)(c - 1) * k.c.m));
-      if (pair) {
+  const bool persistent = use_persistent(k, ckpt_every + 1);
+  if (persistent && g->ny == g->nz) {
+    // one cooperative launch carries both fields
+    for (int c = nck - 1; c >= 0; --c) {
+      PhaseSpec rv = reverse(c);
+      if (c >= 1) {
+        PhaseSpec nx = recomp(c - 1);
+        MSL_TRY(copy_field(k, W, ck + (int64_t)(c - 1) * k.c.m));
         MSL_TRY(run_phases(k, rv, &nx));
       } else {
         MSL_TRY(run_phase(k, rv));
-        MSL_TRY(run_phase(k, nx));
       }
-    } else {
-      MSL_TRY(run_phase(k, rv));
+    }
+  } else {
+    // per-pass launches: the recompute of segment c-1 runs on the helper
+    // stream while the reverse sweep over segment c runs on the caller's
+    // stream; recompute(c-1) starts after reverse(c+1) (which read the same
+    // segment buffer) and reverse(c-1) waits for recompute(c-1)
+    Helper* h = nullptr;
+    MSL_TRY(helper_for_current_device(h));
+    Call kh = k;
+    kh.st = h->s;
+    for (int c = nck - 1; c >= 0; --c) {
+      if (c < nck - 1) MSL_TRY(hip_check(hipStreamWaitEvent(k.st, h->join, 0), "hipStreamWaitEvent"));
+      if (c >= 1) {
+        MSL_TRY(hip_check(hipEventRecord(h->fork, k.st), "hipEventRecord"));
+        MSL_TRY(hip_check(hipStreamWaitEvent(kh.st, h->fork, 0), "hipStreamWaitEvent"));
+        MSL_TRY(copy_field(kh, W, ck + (int64_t)(c - 1) * k.c.m));
+        MSL_TRY(run_phase(kh, recomp(c - 1)));
+        MSL_TRY(hip_check(hipEventRecord(h->join, kh.st), "hipEventRecord"));
+      }
+      MSL_TRY(run_phase(k, reverse(c)));
     }
   }
   if (k.c.gT) {
