@@ -258,61 +258,28 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 // ---------------------------------------------------------------------------
 // per-pass launches
 
-template <int N, int AXIS>
-__global__ void __launch_bounds__(128) k_pass(Ctx c, PassDesc pd) {
+template <int N, int AXIS, int KIND>
+__global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   __shared__ float2 lds[1152];
-  constexpr int L = N / 8;
+  constexpr int L = msl::LinePts<N>::L;
   const int g = threadIdx.x / L, j = threadIdx.x % L;
   const int G = blockDim.x / L;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
-  msl::run_line<N, AXIS>(c, pd, group * G + g, j, lds + g * (N + N / 8));
-}
-
-// Two independent passes in one launch (square grids): blocks [0, nba) run
-// `a`, the rest run `b`; each block picks its axis at run time.
-template <int N>
-__global__ void __launch_bounds__(128) k_pass2(Ctx c, PassDesc a, PassDesc b, int nba) {
-  __shared__ float2 lds[1152];
-  constexpr int L = N / 8;
-  const int g = threadIdx.x / L, j = threadIdx.x % L;
-  const int G = blockDim.x / L;
-  const bool second = (int)blockIdx.x >= nba;
-  const PassDesc pd = second ? b : a;
-  const int nb = second ? (int)gridDim.x - nba : nba;
-  const int group = msl::xcd_group(second ? (int)blockIdx.x - nba : (int)blockIdx.x, nb);
-  msl::run_line_any<N>(c, pd, group * G + g, j, lds + g * (N + N / 8));
-}
-
-template <int N>
-hipError_t launch_pass2_t(const Ctx& c, const PassDesc& a, const PassDesc& b, hipStream_t st) {
-  constexpr int L = N / 8;
-  int G = L >= 64 ? 1 : 64 / L;
-  if (G > N) G = N;
-  const int nb = N / G;
-  hipLaunchKernelGGL((k_pass2<N>), dim3(2 * nb), dim3(L * G), 0, st, c, a, b, nb);
-  return hipGetLastError();
-}
-
-hipError_t launch_pass2(const Ctx& c, const PassDesc& a, const PassDesc& b, hipStream_t st) {
-  switch (c.ny) {
-    case 16: return launch_pass2_t<16>(c, a, b, st);
-    case 32: return launch_pass2_t<32>(c, a, b, st);
-    case 64: return launch_pass2_t<64>(c, a, b, st);
-    case 128: return launch_pass2_t<128>(c, a, b, st);
-    case 256: return launch_pass2_t<256>(c, a, b, st);
-    case 512: return launch_pass2_t<512>(c, a, b, st);
-    case 1024: return launch_pass2_t<1024>(c, a, b, st);
-    default: return hipErrorInvalidValue;
-  }
+  msl::run_line<N, AXIS, false, KIND>(c, pd, group * G + g, j, lds + g * (N + N / 8));
 }
 
 template <int N, int AXIS>
 hipError_t launch_pass_t(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const int nlines = AXIS == msl::ROW ? c.ny : c.nz;
-  constexpr int L = N / 8;
+  constexpr int L = msl::LinePts<N>::L;
   int G = L >= 64 ? 1 : 64 / L;
   if (G > nlines) G = nlines;
-  hipLaunchKernelGGL((k_pass<N, AXIS>), dim3(nlines / G), dim3(L * G), 0, st, c, pd);
+  const dim3 grid(nlines / G), block(L * G);
+  switch (msl::pass_kind(pd)) {
+    case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_FWD_MID>), grid, block, 0, st, c, pd); break;
+    case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_REV_MID>), grid, block, 0, st, c, pd); break;
+    default: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_GENERIC>), grid, block, 0, st, c, pd); break;
+  }
   return hipGetLastError();
 }
 
@@ -446,9 +413,12 @@ msl_status run_phases(const Call& k, const PhaseSpec& a, const PhaseSpec* b) {
   }
   for (int p = 0; p < np; ++p) {
     hipError_t e;
-    if (p < npa && p < npb) e = launch_pass2(k.c, msl::phase_pass(a, p), msl::phase_pass(*b, p), k.st);
-    else if (p < npa) e = launch_pass(k.c, msl::phase_pass(a, p), k.st);
-    else e = launch_pass(k.c, msl::phase_pass(*b, p), k.st);
+    if (p >= npa) break;
+    e = launch_pass(k.c, msl::phase_pass(a, p), k.st);
+    if (e != hipSuccess) return hip_check(e, "pass kernel");
+  }
+  for (int p = 0; p < npb; ++p) {
+    hipError_t e = launch_pass(k.c, msl::phase_pass(*b, p), k.st);
     if (e != hipSuccess) return hip_check(e, "pass kernel");
   }
   return MSL_OK;

@@ -132,81 +132,114 @@ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 
+// Points per lane of an N-point line: 8 (one radix-8 butterfly per lane per
+// stage) or 4 (radix-4), chosen per line length.  A line of N points takes
+// L = N / P lanes.
+#ifndef MSL_P4_MIN_N
+#define MSL_P4_MIN_N 4096  // line length from which lines use 4 points per lane
+#endif
+template <int N>
+struct LinePts {
+  static constexpr int P = N >= MSL_P4_MIN_N ? 4 : 8;
+  static constexpr int L = N / P;
+};
+
+template <int P, bool INV>
+__device__ __forceinline__ void dft_p(float2 (&v)[P]) {
+  if constexpr (P == 8) {
+    dft8<INV>(v);
+  } else {
+    float2 y0, y1, y2, y3;
+    dft4<INV>(v[0], v[1], v[2], v[3], y0, y1, y2, y3);
+    v[0] = y0;
+    v[1] = y1;
+    v[2] = y2;
+    v[3] = y3;
+  }
+}
+
 // Per-lane twiddles of one line FFT: lane j of an N-point line needs
-// W_N^{(j mod NS) r N / (8 NS)}, r = 1..7, for every twiddled radix-8 stage
-// (sub-length NS = R0, 8 R0, ...).  They are loaded once per pass into
+// W_N^{(j mod NS) r N / (P NS)}, r = 1..P-1, for every twiddled radix-P stage
+// (sub-length NS = R0, P R0, ...).  They are loaded once per pass into
 // registers, hi and lo parts, and serve the forward and inverse transforms.
 template <int N>
 struct LineTw {
-  static constexpr int LG = ilog2c(N);
-  static constexpr int R0 = (LG % 3 == 0) ? 8 : ((LG % 3 == 1) ? 2 : 4);
-  static constexpr int NST = (LG - ilog2c(R0)) / 3;
-  float2 hi[NST][7];
-  float2 lo[NST][7];
+  static constexpr int P = LinePts<N>::P;
+  static constexpr int LG = ilog2c(N), LP = ilog2c(P);
+  static constexpr int R0LOG = (LG % LP == 0) ? LP : (LG % LP);
+  static constexpr int R0 = 1 << R0LOG;     // first stage radix (no twiddles)
+  static constexpr int NST = (LG - R0LOG) / LP;
+  float2 hi[NST][P - 1];
+  float2 lo[NST][P - 1];
 };
 
 template <int N>
 __device__ __forceinline__ void load_tw(LineTw<N>& tw, const float2* __restrict__ twh,
                                         const float2* __restrict__ twl, int j) {
+  constexpr int P = LineTw<N>::P;
 #pragma unroll
-  for (int s = 0, NS = LineTw<N>::R0; s < LineTw<N>::NST; ++s, NS *= 8) {
+  for (int s = 0, NS = LineTw<N>::R0; s < LineTw<N>::NST; ++s, NS *= P) {
     const int jm = j % NS;
-    const int step = N / (8 * NS);
+    const int step = N / (P * NS);
 #pragma unroll
-    for (int r = 1; r < 8; ++r) {
+    for (int r = 1; r < P; ++r) {
       tw.hi[s][r - 1] = twh[jm * r * step];
       tw.lo[s][r - 1] = twl[jm * r * step];
     }
   }
 }
 
-// Line FFT of N points held by N/8 lanes, 8 points per lane.  On entry and on
-// exit lane j holds element j + t*N/8 in v[t] ("t-layout", natural order).
-// Stockham autosort: a first stage of radix 2, 4 or 8 without twiddles, then
-// radix-8 stages; every stage but the last exchanges through LDS (padded one
-// slot in eight to spread the stride-8 writes over the banks).  All threads
-// of the block call it together (it contains block barriers).
+// Line FFT of N points held by L = N/P lanes, P points per lane.  On entry
+// and on exit lane j holds element j + t*L in v[t] ("t-layout", natural
+// order).  Stockham autosort: a first stage of radix R0 <= P without
+// twiddles, then radix-P stages; every stage but the last exchanges through
+// LDS (padded one slot in eight to spread the strided writes over the
+// banks).  All threads of the block call it together (it has block barriers).
 template <int N, bool INV>
-__device__ __forceinline__ void fft_line(float2 (&v)[8], float2* sh, int j, const LineTw<N>& tw) {
-  constexpr int L = N / 8;
+__device__ __forceinline__ void fft_line(float2 (&v)[LinePts<N>::P], float2* sh, int j, const LineTw<N>& tw) {
+  constexpr int P = LinePts<N>::P;
+  constexpr int L = LinePts<N>::L;
   constexpr int R0 = LineTw<N>::R0;
   // ---- stage 0: radix R0, sub-length 1, trivial twiddles
   __syncthreads();
-  if constexpr (R0 == 8) {
-    dft8<INV>(v);
+  if constexpr (R0 == P) {
+    dft_p<P, INV>(v);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) sh[lds_pad(8 * j + r)] = v[r];
-  } else if constexpr (R0 == 4) {
-    float2 y[4];
-    dft4<INV>(v[0], v[2], v[4], v[6], y[0], y[1], y[2], y[3]);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sh[lds_pad(4 * j + r)] = y[r];
-    dft4<INV>(v[1], v[3], v[5], v[7], y[0], y[1], y[2], y[3]);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sh[lds_pad(4 * (j + L) + r)] = y[r];
+    for (int r = 0; r < P; ++r) sh[lds_pad(P * j + r)] = v[r];
   } else {
+    constexpr int Q = P / R0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float2 a = v[q], b = v[q + 4];
-      dft2<INV>(a, b);
-      sh[lds_pad(2 * (j + q * L))] = a;
-      sh[lds_pad(2 * (j + q * L) + 1)] = b;
+    for (int q = 0; q < Q; ++q) {
+      if constexpr (R0 == 4) {
+        float2 y0, y1, y2, y3;
+        dft4<INV>(v[q], v[q + Q], v[q + 2 * Q], v[q + 3 * Q], y0, y1, y2, y3);
+        const int b = R0 * (j + q * L);
+        sh[lds_pad(b)] = y0;
+        sh[lds_pad(b + 1)] = y1;
+        sh[lds_pad(b + 2)] = y2;
+        sh[lds_pad(b + 3)] = y3;
+      } else {
+        float2 a = v[q], c = v[q + Q];
+        dft2<INV>(a, c);
+        sh[lds_pad(2 * (j + q * L))] = a;
+        sh[lds_pad(2 * (j + q * L) + 1)] = c;
+      }
     }
   }
   __syncthreads();
-  // ---- radix-8 stages with sub-length NS = R0, 8 R0, ...
+  // ---- radix-P stages with sub-length NS = R0, P R0, ...
 #pragma unroll
-  for (int s = 0, NS = R0; s < LineTw<N>::NST; ++s, NS *= 8) {
+  for (int s = 0, NS = R0; s < LineTw<N>::NST; ++s, NS *= P) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = sh[lds_pad(j + t * L)];
+    for (int t = 0; t < P; ++t) v[t] = sh[lds_pad(j + t * L)];
 #pragma unroll
-    for (int r = 1; r < 8; ++r) v[r] = cmul_comp<INV>(v[r], tw.hi[s][r - 1], tw.lo[s][r - 1]);
-    dft8<INV>(v);
-    if (NS * 8 < N) {
-      const int base = (j / NS) * NS * 8 + (j % NS);
+    for (int r = 1; r < P; ++r) v[r] = cmul_comp<INV>(v[r], tw.hi[s][r - 1], tw.lo[s][r - 1]);
+    dft_p<P, INV>(v);
+    if (NS * P < N) {
+      const int base = (j / NS) * NS * P + (j % NS);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 8; ++r) sh[lds_pad(base + r * NS)] = v[r];
+      for (int r = 0; r < P; ++r) sh[lds_pad(base + r * NS)] = v[r];
       __syncthreads();
     }
   }
@@ -271,6 +304,17 @@ __device__ __forceinline__ float phase_arg(float d, const Ctx& c) {
 // ---------------------------------------------------------------------------
 // one line of one pass
 
+// Pass kinds compiled on their own (the executed path only, a fraction of
+// the generic kernel's code); KIND_GENERIC follows the descriptor at run time.
+enum PassKind : int { KIND_GENERIC = 0, KIND_FWD_MID = 1, KIND_REV_MID = 2 };
+
+__host__ __device__ inline int pass_kind(const PassDesc& pd) {
+  if (pd.pre == PRE_PROP && pd.post == POST_PROP && pd.mid == MID_T_FWD && !pd.conj) return KIND_FWD_MID;
+  if (pd.pre == PRE_PROP && pd.post == POST_PROP && pd.mid == MID_T_ADJ && pd.conj) return KIND_REV_MID;
+  return KIND_GENERIC;
+}
+
+
 template <int N, int AXIS>
 __device__ __forceinline__ int64_t line_addr(const Ctx& c, int line, int i) {
   return AXIS == ROW ? (int64_t)line * c.nz + i : (int64_t)i * c.nz + line;
@@ -282,11 +326,12 @@ __device__ __forceinline__ int64_t line_addr(const Ctx& c, int line, int i) {
 // before the grid barrier that separates two passes.
 template <int N>
 struct LineIn {
-  float2 v[8];            // field
-  float dl[8], bt[8];     // delta, beta of the slice
-  float2 ps[8];           // psi_s (adjoint)
-  float gi[8];            // far-field seed (shifted read)
-  float2 hh[8], hl[8];    // propagator factor (1-D paraxial or 2-D exact)
+  static constexpr int P = LinePts<N>::P;
+  float2 v[P];            // field
+  float dl[P], bt[P];     // delta, beta of the slice
+  float2 ps[P];           // psi_s (adjoint)
+  float gi[P];            // far-field seed (shifted read)
+  float2 hh[P], hl[P];    // propagator factor (1-D paraxial or 2-D exact)
   LineTw<N> tw;
 };
 
@@ -294,21 +339,28 @@ __device__ __forceinline__ bool uses_h1d(const PassDesc& pd) {
   return pd.pre == PRE_PROP || pd.post == POST_PROP;
 }
 
-template <int N, int AXIS>
-__device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N>& in) {
-  constexpr int L = N / 8;
+template <int N, int AXIS, int KIND = KIND_GENERIC>
+__device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, int line, int j, LineIn<N>& in) {
+  PassDesc pd = pd_;
+  if constexpr (KIND != KIND_GENERIC) {
+    pd.pre = PRE_PROP;
+    pd.post = POST_PROP;
+    pd.mid = KIND == KIND_FWD_MID ? MID_T_FWD : MID_T_ADJ;
+  }
+  constexpr int L = LinePts<N>::L;
+  constexpr int P = LinePts<N>::P;
   load_tw<N>(in.tw, AXIS == ROW ? c.twz_hi : c.twy_hi, AXIS == ROW ? c.twz_lo : c.twy_lo, j);
   if (uses_h1d(pd)) {
     const float2* hh = AXIS == ROW ? c.hz_hi : c.hy_hi;
     const float2* hl = AXIS == ROW ? c.hz_lo : c.hy_lo;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < P; ++t) {
       in.hh[t] = hh[j + t * L];
       in.hl[t] = hl[j + t * L];
     }
   } else if (pd.post == POST_PROP2D) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < P; ++t) {
       const int64_t e = (int64_t)(j + t * L) * c.nz + line;
       in.hh[t] = c.H_hi[e];
       in.hl[t] = c.H_lo[e];
@@ -318,7 +370,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd, in
     if (AXIS == COL && c.dbT && (pd.slice & 1)) {
       const float2* q = c.dbT + (int64_t)(pd.slice >> 1) * c.m + (int64_t)line * c.ny;
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < P; ++t) {
         const float2 db = q[j + t * L];
         in.dl[t] = db.x;
         in.bt[t] = db.y;
@@ -327,7 +379,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd, in
       const float* dp = c.delta + (int64_t)pd.slice * c.m;
       const float* bp = c.beta + (int64_t)pd.slice * c.m;
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < P; ++t) {
         const int64_t a = line_addr<N, AXIS>(c, line, j + t * L);
         in.dl[t] = dp[a];
         in.bt[t] = bp[a];
@@ -336,11 +388,11 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd, in
   }
   if (pd.mid == MID_T_ADJ) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) in.ps[t] = pd.psi_load[line_addr<N, AXIS>(c, line, j + t * L)];
+    for (int t = 0; t < P; ++t) in.ps[t] = pd.psi_load[line_addr<N, AXIS>(c, line, j + t * L)];
   }
   if (pd.mid == MID_FF_SEED) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < P; ++t) {
       const int i = j + t * L;
       const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
       const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
@@ -376,25 +428,36 @@ __device__ __forceinline__ void field_st(float2* p, float2 v) {
 
 template <int N, int AXIS, bool COH = false>
 __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N>& in) {
-  constexpr int L = N / 8;
+  constexpr int L = LinePts<N>::L;
+  constexpr int P = LinePts<N>::P;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) in.v[t] = field_ld<COH>(pd.src + line_addr<N, AXIS>(c, line, j + t * L));
+  for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + line_addr<N, AXIS>(c, line, j + t * L));
 }
 
 template <int N>
-__device__ __forceinline__ void prop_line(float2 (&v)[8], float2* sh, int j, const LineIn<N>& in, bool conj) {
+__device__ __forceinline__ void prop_line(float2 (&v)[LinePts<N>::P], float2* sh, int j, const LineIn<N>& in,
+                                          bool conj) {
+  constexpr int P = LinePts<N>::P;
   fft_line<N, false>(v, sh, j, in.tw);
 #pragma unroll
-  for (int t = 0; t < 8; ++t) v[t] = cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj);
+  for (int t = 0; t < P; ++t) v[t] = cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj);
   fft_line<N, true>(v, sh, j, in.tw);
 }
 
-template <int N, int AXIS, bool COH = false>
-__device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh,
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC>
+__device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, int line, int j, float2* sh,
                                              LineIn<N>& in) {
-  constexpr int L = N / 8;
+  constexpr int L = LinePts<N>::L;
+  constexpr int P = LinePts<N>::P;
   const float inv_n = 1.0f / (float)N;
-  float2 (&v)[8] = in.v;
+  float2 (&v)[P] = in.v;
+  PassDesc pd = pd_;
+  if constexpr (KIND != KIND_GENERIC) {
+    pd.pre = PRE_PROP;
+    pd.post = POST_PROP;
+    pd.mid = KIND == KIND_FWD_MID ? MID_T_FWD : MID_T_ADJ;
+    pd.conj = KIND == KIND_REV_MID;
+  }
 
   switch (pd.pre) {
     case PRE_PROP: prop_line<N>(v, sh, j, in, pd.conj != 0); break;
@@ -402,7 +465,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, i
     case PRE_IFFT_N:
       fft_line<N, true>(v, sh, j, in.tw);
 #pragma unroll
-      for (int t = 0; t < 8; ++t) v[t] = make_float2(v[t].x * inv_n, v[t].y * inv_n);
+      for (int t = 0; t < P; ++t) v[t] = make_float2(v[t].x * inv_n, v[t].y * inv_n);
       break;
     case PRE_IFFT_U: fft_line<N, true>(v, sh, j, in.tw); break;
     default: break;
@@ -410,18 +473,18 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, i
 
   if (pd.psi_store) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) pd.psi_store[line_addr<N, AXIS>(c, line, j + t * L)] = v[t];
+    for (int t = 0; t < P; ++t) pd.psi_store[line_addr<N, AXIS>(c, line, j + t * L)] = v[t];
   }
 
   if (pd.mid == MID_T_FWD) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < P; ++t)
       v[t] = apply_t(v[t], transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c)));
   } else if (pd.mid == MID_T_ADJ) {
     const int64_t so = (int64_t)pd.slice * c.m;
     const float kdx = c.kdx_hi;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < P; ++t) {
       const int64_t e = so + line_addr<N, AXIS>(c, line, j + t * L);
       const float2 tm1 = transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c));
       const float2 pt = apply_t(in.ps[t], tm1);  // psi'_s = T_s psi_s
@@ -439,7 +502,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, i
     }
   } else if (pd.mid == MID_FF_OUT) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < P; ++t) {
       const int i = j + t * L;
       const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
       const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
@@ -448,7 +511,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, i
     }
   } else if (pd.mid == MID_FF_SEED) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < P; ++t) {
       const float s = 2.0f * c.inv_m * in.gi[t];
       v[t] = make_float2(v[t].x * s, v[t].y * s);
     }
@@ -463,16 +526,16 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd, i
 
   if (pd.dst) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) field_st<COH>(pd.dst + line_addr<N, AXIS>(c, line, j + t * L), v[t]);
+    for (int t = 0; t < P; ++t) field_st<COH>(pd.dst + line_addr<N, AXIS>(c, line, j + t * L), v[t]);
   }
 }
 
-template <int N, int AXIS, bool COH = false>
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC>
 __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
   LineIn<N> in;
   load_field<N, AXIS, COH>(c, pd, line, j, in);
-  load_static<N, AXIS>(c, pd, line, j, in);
-  compute_line<N, AXIS, COH>(c, pd, line, j, sh, in);
+  load_static<N, AXIS, KIND>(c, pd, line, j, in);
+  compute_line<N, AXIS, COH, KIND>(c, pd, line, j, sh, in);
 }
 
 // Either axis, chosen per pass at run time (square grids: both line lengths are N).

@@ -54,7 +54,7 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned epoch, int 
 // Block size and lines per block of one field.
 template <int N>
 struct PersistShape {
-  static constexpr int L = N / 8;
+  static constexpr int L = LinePts<N>::L;
   static constexpr int T0 = N >= 1024 ? 256 : (N >= 512 ? 128 : 64);
   static constexpr int T = T0 < N * L ? T0 : N * L;  // at most N lines per block
   static constexpr int G = T / L;
