@@ -109,7 +109,7 @@ def main():
         msl.far_field_adjoint(g, field, gI, ws=ws, out=gpsi)
         if ev:
             ev[2].record()
-        msl.adjoint(g, D, B, ck, k, gpsi, ws=ws, gd=gd, gb=gb, want_probe=True)
+        msl.adjoint(g, D, B, ck, k, gpsi, ws=ws, gd=gd, gb=gb, want_probe=True, reuse_pack=True)
         if ev:
             ev[3].record()
 

@@ -147,6 +147,12 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field,
                                  const float* grad_intensity, msl_c64* grad_field,
                                  void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* msl_adjoint flags. */
+#define MSL_ADJ_REUSE_SLICE_PACK 1u  /* the workspace still holds the packed copy of the
+                                        slice stack that msl_forward wrote (same geometry,
+                                        delta, beta and workspace; delta and beta unchanged
+                                        since): skip rebuilding it */
+
 /* Gradient of a real loss through the multislice recurrence (reverse sweep
  * of Eq. 1 with checkpoint recomputation).
  *   delta, beta, probe, ckpt, ckpt_every: exactly as given to / produced by
@@ -154,11 +160,12 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field,
  *   grad_field   complex64 [ny][nz]: cotangent of psi_Ns.
  *   grad_delta, grad_beta  float32 [Ns][ny][nz] (either may be NULL):
  *                overwritten with dL/d delta and dL/d beta.
- *   grad_probe   NULL or complex64 [ny][nz]: cotangent of the probe. */
+ *   grad_probe   NULL or complex64 [ny][nz]: cotangent of the probe.
+ *   flags        0 or MSL_ADJ_REUSE_SLICE_PACK (see above); unknown bits are an error. */
 msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* beta,
                        const msl_c64* probe, const msl_c64* ckpt, int32_t ckpt_every,
                        const msl_c64* grad_field, float* grad_delta, float* grad_beta,
-                       msl_c64* grad_probe,
+                       msl_c64* grad_probe, uint32_t flags,
                        void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Select the slice-loop schedule for later calls from this process

@@ -188,36 +188,46 @@ __global__ void k_probe(int ny, int nz, double q, float2* out) {
   out[i] = make_float2((float)c, (float)s);
 }
 
-// Odd slices' (delta, beta) -> dbT[s/2][z][y] (float2), through 16x16 LDS tiles.
+// Odd slices' (delta, beta) -> dbT[s/2][z][y] (float2), through T x T LDS
+// tiles (T = 32, or 16 on 16-wide grids); 256 threads, T/16... rows each.
+template <int T>
 __global__ void __launch_bounds__(256) k_pack_odd(const float* d, const float* b, float2* out, int ny, int nz,
                                                   int nodd) {
-  __shared__ float2 tile[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int z0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+  __shared__ float2 tile[T][T + 1];
+  constexpr int R = 256 / T;  // rows of the tile per pass of the block
+  const int tx = threadIdx.x % T, ty = threadIdx.x / T;
+  const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
   const int64_t m = (int64_t)ny * nz;
   for (int s2 = blockIdx.z; s2 < nodd; s2 += gridDim.z) {
     const int64_t si = (int64_t)(2 * s2 + 1) * m;
-    tile[ty][tx] = make_float2(d[si + (int64_t)(y0 + ty) * nz + z0 + tx], b[si + (int64_t)(y0 + ty) * nz + z0 + tx]);
+    for (int r = ty; r < T; r += R) {
+      const int64_t a = si + (int64_t)(y0 + r) * nz + z0 + tx;
+      tile[r][tx] = make_float2(d[a], b[a]);
+    }
     __syncthreads();
-    out[(int64_t)s2 * m + (int64_t)(z0 + ty) * ny + y0 + tx] = tile[tx][ty];
+    for (int r = ty; r < T; r += R) out[(int64_t)s2 * m + (int64_t)(z0 + r) * ny + y0 + tx] = tile[tx][r];
     __syncthreads();
   }
 }
 
 // gT[s/2][z][y] (float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z] for odd s.
+template <int T>
 __global__ void __launch_bounds__(256) k_unpack_odd(const float2* gT, float* gd, float* gb, int ny, int nz,
                                                     int nodd) {
-  __shared__ float2 tile[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int z0 = blockIdx.x * 16, y0 = blockIdx.y * 16;
+  __shared__ float2 tile[T][T + 1];
+  constexpr int R = 256 / T;
+  const int tx = threadIdx.x % T, ty = threadIdx.x / T;
+  const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
   const int64_t m = (int64_t)ny * nz;
   for (int s2 = blockIdx.z; s2 < nodd; s2 += gridDim.z) {
-    tile[ty][tx] = gT[(int64_t)s2 * m + (int64_t)(z0 + ty) * ny + y0 + tx];
+    for (int r = ty; r < T; r += R) tile[r][tx] = gT[(int64_t)s2 * m + (int64_t)(z0 + r) * ny + y0 + tx];
     __syncthreads();
-    const float2 v = tile[tx][ty];
-    const int64_t o = (int64_t)(2 * s2 + 1) * m + (int64_t)(y0 + ty) * nz + z0 + tx;
-    if (gd) gd[o] = v.x;
-    if (gb) gb[o] = v.y;
+    for (int r = ty; r < T; r += R) {
+      const float2 v = tile[tx][r];
+      const int64_t o = (int64_t)(2 * s2 + 1) * m + (int64_t)(y0 + r) * nz + z0 + tx;
+      if (gd) gd[o] = v.x;
+      if (gb) gb[o] = v.y;
+    }
     __syncthreads();
   }
 }
@@ -436,8 +446,13 @@ msl_status pack_odd(Call& k, const float* delta, const float* beta) {
   const int nodd = odd_slices(k.g);
   if (nodd == 0) return MSL_OK;
   float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
-  dim3 grid(k.g.nz / 16, k.g.ny / 16, nodd < 8192 ? nodd : 8192);
-  hipLaunchKernelGGL(k_pack_odd, grid, dim3(256), 0, k.st, delta, beta, dbT, k.g.ny, k.g.nz, nodd);
+  const unsigned gz = nodd < 8192 ? nodd : 8192;
+  if (k.g.ny >= 32 && k.g.nz >= 32)
+    hipLaunchKernelGGL(k_pack_odd<32>, dim3(k.g.nz / 32, k.g.ny / 32, gz), dim3(256), 0, k.st, delta, beta, dbT,
+                       k.g.ny, k.g.nz, nodd);
+  else
+    hipLaunchKernelGGL(k_pack_odd<16>, dim3(k.g.nz / 16, k.g.ny / 16, gz), dim3(256), 0, k.st, delta, beta, dbT,
+                       k.g.ny, k.g.nz, nodd);
   k.c.dbT = dbT;
   return hip_check(hipGetLastError(), "pack kernel");
 }
@@ -567,8 +582,8 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field, co
 
 msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* beta, const msl_c64* probe,
                        const msl_c64* ckpt, int32_t ckpt_every, const msl_c64* grad_field, float* grad_delta,
-                       float* grad_beta, msl_c64* grad_probe, void* workspace, size_t ws_bytes,
-                       void* hip_stream) {
+                       float* grad_beta, msl_c64* grad_probe, uint32_t flags, void* workspace,
+                       size_t ws_bytes, void* hip_stream) {
   (void)probe;  // the probe is ckpt[0]
   MSL_TRY(check_geometry(g));
   MSL_TRY(check_ptr(delta, 4, "delta"));
@@ -580,6 +595,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   MSL_TRY(check_ptr(grad_delta, 4, "grad_delta", true));
   MSL_TRY(check_ptr(grad_beta, 4, "grad_beta", true));
   MSL_TRY(check_ptr(grad_probe, 8, "grad_probe", true));
+  if (flags & ~MSL_ADJ_REUSE_SLICE_PACK) return fail(MSL_ERR_ARG, "unknown msl_adjoint flags");
   MSL_TRY(check_ws(*g, ckpt_every, workspace, ws_bytes));
   Call k = make_call(*g, ckpt_every, workspace, static_cast<hipStream_t>(hip_stream));
   k.c.delta = delta;
@@ -587,7 +603,11 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   k.c.gdelta = grad_delta;
   k.c.gbeta = grad_beta;
   MSL_TRY(build_tables(k, true));
-  MSL_TRY(pack_odd(k, delta, beta));
+  if (flags & MSL_ADJ_REUSE_SLICE_PACK) {
+    if (odd_slices(*g) > 0) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
+  } else {
+    MSL_TRY(pack_odd(k, delta, beta));
+  }
   const int nodd = odd_slices(*g);
   if (nodd > 0 && (grad_delta || grad_beta)) k.c.gT = reinterpret_cast<float2*>(k.ws + k.L.gT);
   float2* W = reinterpret_cast<float2*>(k.ws + k.L.W);
@@ -658,8 +678,13 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     }
   }
   if (k.c.gT) {
-    dim3 grid(g->nz / 16, g->ny / 16, nodd < 8192 ? nodd : 8192);
-    hipLaunchKernelGGL(k_unpack_odd, grid, dim3(256), 0, k.st, k.c.gT, grad_delta, grad_beta, g->ny, g->nz, nodd);
+    const unsigned gz = nodd < 8192 ? nodd : 8192;
+    if (g->ny >= 32 && g->nz >= 32)
+      hipLaunchKernelGGL(k_unpack_odd<32>, dim3(g->nz / 32, g->ny / 32, gz), dim3(256), 0, k.st, k.c.gT, grad_delta,
+                         grad_beta, g->ny, g->nz, nodd);
+    else
+      hipLaunchKernelGGL(k_unpack_odd<16>, dim3(g->nz / 16, g->ny / 16, gz), dim3(256), 0, k.st, k.c.gT, grad_delta,
+                         grad_beta, g->ny, g->nz, nodd);
     MSL_TRY(hip_check(hipGetLastError(), "unpack kernel"));
   }
   if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));

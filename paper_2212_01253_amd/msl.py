@@ -16,6 +16,7 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsl.so")
 
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = 0, -1, -2, -3, -4
+ADJ_REUSE_SLICE_PACK = 1
 PROP_PARAXIAL, PROP_EXACT = 0, 1
 SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
 
@@ -67,7 +68,7 @@ def lib():
     L.msl_far_field_adjoint.restype = c_int32
     L.msl_far_field_adjoint.argtypes = [G, P, P, P, P, c_size_t, P]
     L.msl_adjoint.restype = c_int32
-    L.msl_adjoint.argtypes = [G, P, P, P, P, c_int32, P, P, P, P, P, c_size_t, P]
+    L.msl_adjoint.argtypes = [G, P, P, P, P, c_int32, P, P, P, P, ctypes.c_uint32, P, c_size_t, P]
     L.msl_set_schedule.restype = c_int32
     L.msl_set_schedule.argtypes = [c_int32]
     L.msl_last_error.restype = ctypes.c_char_p
@@ -208,8 +209,12 @@ def far_field_adjoint(g, field, grad_intensity, ws=None, out=None):
 
 
 def adjoint(g, delta, beta, ckpt, ckpt_every, grad_field, probe=None, ws=None,
-            want_delta=True, want_beta=True, want_probe=True, gd=None, gb=None):
-    """msl_adjoint: returns (dL/d delta, dL/d beta, dL/d probe), None where not wanted."""
+            want_delta=True, want_beta=True, want_probe=True, gd=None, gb=None, reuse_pack=False):
+    """msl_adjoint: returns (dL/d delta, dL/d beta, dL/d probe), None where not wanted.
+
+    ``reuse_pack`` may be set only when ``ws`` is the workspace the matching
+    ``forward`` call used and delta, beta have not changed since.
+    """
     cg = geometry(g)
     ny, nz, ns = cg.ny, cg.nz, cg.n_slices
     dev = delta.device
@@ -227,7 +232,8 @@ def adjoint(g, delta, beta, ckpt, ckpt_every, grad_field, probe=None, ws=None,
         _ptr(ckpt, torch.complex64, (checkpoint_count(cg, ckpt_every), ny, nz), "ckpt"),
         int(ckpt_every), _ptr(grad_field, torch.complex64, (ny, nz), "grad_field"),
         gd.data_ptr() if want_delta else None, gb.data_ptr() if want_beta else None,
-        gp.data_ptr() if gp is not None else None, ws.data_ptr(), ws.numel(), _stream()))
+        gp.data_ptr() if gp is not None else None, ADJ_REUSE_SLICE_PACK if reuse_pack else 0,
+        ws.data_ptr(), ws.numel(), _stream()))
     return (gd if want_delta else None), (gb if want_beta else None), gp
 
 
@@ -241,18 +247,21 @@ class Multislice(torch.autograd.Function):
     def forward(ctx, delta, beta, geom, probe=None, ckpt_every=32):
         cg = geometry(geom)
         k = max(1, min(int(ckpt_every), cg.n_slices))
-        out, ck = forward(cg, delta.contiguous(), beta.contiguous(), probe, ckpt_every=k)
+        ws = workspace(cg, k, delta.device)
+        out, ck = forward(cg, delta.contiguous(), beta.contiguous(), probe, ckpt_every=k, ws=ws)
         ctx.save_for_backward(delta, beta, ck)
-        ctx.cg, ctx.k, ctx.has_probe = cg, k, probe is not None
+        ctx.cg, ctx.k, ctx.has_probe, ctx.ws = cg, k, probe is not None, ws
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
         delta, beta, ck = ctx.saved_tensors
+        # saved tensors are version-checked by autograd, so the forward's pack is still valid
         gd, gb, gp = adjoint(ctx.cg, delta.contiguous(), beta.contiguous(), ck, ctx.k,
-                             grad_out.contiguous(),
+                             grad_out.contiguous(), ws=ctx.ws,
                              want_delta=ctx.needs_input_grad[0], want_beta=ctx.needs_input_grad[1],
-                             want_probe=ctx.has_probe and ctx.needs_input_grad[3])
+                             want_probe=ctx.has_probe and ctx.needs_input_grad[3], reuse_pack=True)
+        ctx.ws = None
         return gd, gb, None, gp, None
 
 

@@ -76,9 +76,12 @@ def test_checkpoint_argument_rules(L):
     assert fwd(L, g, ckpt=FAKE, k=0) == msl.ERR_ARG
     assert fwd(L, g, ckpt=None, k=4) == msl.ERR_ARG
     # the adjoint requires checkpoints
-    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, None, 4, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, None)
+    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, None, 4, FAKE, FAKE, FAKE, None, 0, FAKE, 1 << 40, None)
     assert st == msl.ERR_ARG
-    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, FAKE, 0, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, None)
+    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, FAKE, 0, FAKE, FAKE, FAKE, None, 0, FAKE, 1 << 40, None)
+    assert st == msl.ERR_ARG
+    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, FAKE, 4, FAKE, FAKE, FAKE, None, 6, FAKE, 1 << 40, None)
+    assert "flags" in L.msl_last_error().decode()
     assert st == msl.ERR_ARG
 
 
@@ -92,7 +95,7 @@ def test_workspace_rules(L):
     assert "need" in L.msl_last_error().decode()
     # adjoint workspace grows with the checkpoint interval (segment buffer)
     assert L.msl_workspace_bytes(ctypes.byref(g), 8) > L.msl_workspace_bytes(ctypes.byref(g), 2) > need
-    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, FAKE, 8, FAKE, FAKE, FAKE, None, FAKE,
+    st = L.msl_adjoint(ctypes.byref(g), FAKE, FAKE, None, FAKE, 8, FAKE, FAKE, FAKE, None, 0, FAKE,
                        L.msl_workspace_bytes(ctypes.byref(g), 2), None)
     assert st == msl.ERR_WORKSPACE
 

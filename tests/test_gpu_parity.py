@@ -159,14 +159,15 @@ def test_loss_zero_intensity_pixels(M):
     assert np.allclose(gI.cpu().numpy(), rgI, atol=1e-7)
 
 
-def _grad_case(M, g, d, b, meas, k, sched=1):
+def _grad_case(M, g, d, b, meas, k, sched=1, reuse_pack=False):
     M.set_schedule(sched)
     D, B = dev(d), dev(b)
-    f, ck = M.forward(g, D, B, ckpt_every=k)
-    I = M.far_field(g, f)
-    loss, gI = M.amp_loss(g, I, dev(meas))
-    gpsi = M.far_field_adjoint(g, f, gI)
-    gd, gb, gp = M.adjoint(g, D, B, ck, k, gpsi)
+    ws = M.workspace(g, k)
+    f, ck = M.forward(g, D, B, ckpt_every=k, ws=ws)
+    I = M.far_field(g, f, ws=ws)
+    loss, gI = M.amp_loss(g, I, dev(meas), ws=ws)
+    gpsi = M.far_field_adjoint(g, f, gI, ws=ws)
+    gd, gb, gp = M.adjoint(g, D, B, ck, k, gpsi, ws=ws, reuse_pack=reuse_pack)
     torch.cuda.synchronize()
     return float(loss.cpu()), gd.cpu().numpy(), gb.cpu().numpy(), gp.cpu().numpy()
 
@@ -186,6 +187,17 @@ def test_gradient_parity(M, sched, k):
     assert rel(gd, rd) <= GRAD_TOL
     assert rel(gb, rb) <= GRAD_TOL
     assert rel(gp, rp) <= GRAD_TOL
+
+
+def test_gradient_reusing_the_forward_slice_pack(M):
+    w = synth.parity_small(8)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 33})
+    d, b = w.delta[:33], w.beta[:33]
+    meas = (np.sqrt(O.far_field(g, O.forward(g, d * 1.1, b * 1.1)))).astype(np.float32)
+    a = _grad_case(M, g, d, b, meas, 4)
+    r = _grad_case(M, g, d, b, meas, 4, reuse_pack=True)
+    for x, y in zip(a[1:], r[1:]):
+        assert np.array_equal(x, y)
 
 
 def test_gradient_exact_propagator(M):
