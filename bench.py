@@ -30,6 +30,30 @@ def grad_bytes_per_voxel_slice(k):
     return 24.0 + 8.0 / k + 32.0 + 40.0
 
 
+KERNEL_SOURCES = ("paper_2212_01253_amd/csrc/msl_device.hpp", "paper_2212_01253_amd/csrc/msl_passes.hpp",
+                  "paper_2212_01253_amd/csrc/msl.hip")
+TRAFFIC_PROFILE = "profiles/k_pass_512_bars_512x512x2048.md"
+
+
+def measured_traffic():
+    """HBM bytes per forward-pass launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+        h = hashlib.sha256()
+        for p in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+    except OSError:
+        return None
+    b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    sha = re.search(r"sources_sha256: ([0-9a-f]+)", text)
+    if not b or not sha or sha.group(1) != h.hexdigest():
+        return None
+    return int(b.group(1))
+
+
 def cpu_baseline(w, meas, n_sample):
     import numpy as np
     from oracle import msl_oracle as O
@@ -138,6 +162,9 @@ def main():
     achieved = vs * bpv / (ms / 1e3) / 1e9
     fwd_med = float(np.median(fwd_ms))
     fwd_gbs = vs * (FWD_BYTES + 8.0 / k) / (fwd_med / 1e3) / 1e9
+    pass_bytes = (FWD_BYTES + 8.0 / k) * ny * nz
+    pass_gbs = pass_bytes * ns / (fwd_med / 1e3) / (ns + 1) / 1e9
+    traffic = measured_traffic()
     print(f"# step {ms:.3f} ms: forward {fwd_med:.3f} ms, far field+loss+seed {np.median(mid_ms):.3f} ms, "
           f"adjoint {np.median(adj_ms):.3f} ms", file=sys.stderr, flush=True)
 
@@ -158,13 +185,17 @@ def main():
                    "wavelength_nm": g.wavelength_nm, "alpha_deg": math.degrees(g.alpha_i_rad),
                    "propagator": "paraxial", "ckpt_every": k, "seed": w.seed,
                    "schedule": ["auto", "per_pass", "persistent"][args.schedule]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "line-pass kernels of the whole step (forward, recompute, reverse)",
-                     "bytes_per_voxel_slice": bpv},
-        "forward": {"ms": fwd_med, "voxel_slice_steps_per_s": vs / (fwd_med / 1e3), "achieved_GBs": fwd_gbs,
-                    "frac": fwd_gbs / HBM_PEAK_GBS, "bytes_per_voxel_slice": FWD_BYTES + 8.0 / k},
-        "adjoint_ms": float(np.median(adj_ms)),
+        # dominant kernel: the forward middle line pass (also the recompute's);
+        # per launch = forward time / launches, i.e. kernel plus dispatch gap
+        "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": pass_gbs / HBM_PEAK_GBS,
+                     "traffic": (traffic / 1e9 * ns / (fwd_med / 1e3) / (ns + 1)) if traffic else None,
+                     "kernel": "k_pass<512,*,1> forward line pass (propagate, transmit, propagate)",
+                     "bytes_per_launch": pass_bytes, "us_per_launch": fwd_med * 1e3 / (ns + 1),
+                     "traffic_bytes_per_launch": traffic},
+        "step": {"bytes_per_voxel_slice": bpv, "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS,
+                 "forward_ms": fwd_med, "adjoint_ms": float(np.median(adj_ms)),
+                 "far_field_loss_seed_ms": float(np.median(mid_ms))},
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
