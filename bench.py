@@ -163,7 +163,8 @@ def main():
     fwd_med = float(np.median(fwd_ms))
     fwd_gbs = vs * (FWD_BYTES + 8.0 / k) / (fwd_med / 1e3) / 1e9
     pass_bytes = (FWD_BYTES + 8.0 / k) * ny * nz
-    pass_gbs = pass_bytes * ns / (fwd_med / 1e3) / (ns + 1) / 1e9
+    launch_s = fwd_med / 1e3 / (ns + 1)       # forward launches: Ns + 1 line passes
+    pass_gbs = pass_bytes / launch_s / 1e9
     traffic = measured_traffic()
     print(f"# step {ms:.3f} ms: forward {fwd_med:.3f} ms, far field+loss+seed {np.median(mid_ms):.3f} ms, "
           f"adjoint {np.median(adj_ms):.3f} ms", file=sys.stderr, flush=True)
@@ -189,9 +190,9 @@ def main():
         # per launch = forward time / launches, i.e. kernel plus dispatch gap
         "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": pass_gbs / HBM_PEAK_GBS,
-                     "traffic": (traffic / 1e9 * ns / (fwd_med / 1e3) / (ns + 1)) if traffic else None,
+                     "traffic": (traffic / launch_s / 1e9) if traffic else None,
                      "kernel": "k_pass<512,*,1> forward line pass (propagate, transmit, propagate)",
-                     "bytes_per_launch": pass_bytes, "us_per_launch": fwd_med * 1e3 / (ns + 1),
+                     "bytes_per_launch": pass_bytes, "us_per_launch": launch_s * 1e6,
                      "traffic_bytes_per_launch": traffic},
         "step": {"bytes_per_voxel_slice": bpv, "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS,
                  "forward_ms": fwd_med, "adjoint_ms": float(np.median(adj_ms)),
