@@ -40,7 +40,7 @@ struct Layout {
   size_t twz_hi, twz_lo, twy_hi, twy_lo;
   size_t hz_hi, hz_lo, hy_hi, hy_lo;
   size_t H_hi, H_lo;
-  size_t bar, partials, tmp, dbT, W, G, seg, gT;
+  size_t bar, partials, tmp, fT, dbT, W, WT, G, GT, seg, gT;
   size_t total;
 };
 
@@ -65,12 +65,15 @@ Layout layout(const msl_geometry& g, int k) {
   L.bar = take(8192);
   L.partials = take(kPartials * sizeof(double));
   L.tmp = take(m * 8);
+  L.fT = take(m * 8);  // column-major partner of the forward field
   // paraxial: odd slices' (delta, beta) packed and transposed for the column passes
   const size_t odd = exact ? 0 : (size_t)(g.n_slices / 2);
   L.dbT = take(odd * m * 8);
   if (k >= 1) {
     L.W = take(m * 8);
+    L.WT = take(m * 8);
     L.G = take(m * 8);
+    L.GT = take(m * 8);
     L.seg = take((size_t)(k > 1 ? k - 1 : 0) * m * 8 * 2);  // two segment buffers
     L.gT = take(odd * m * 8);  // odd slices' gradients, same layout as dbT
   }
@@ -230,6 +233,19 @@ __global__ void __launch_bounds__(256) k_unpack_odd(const float2* gT, float* gd,
     }
     __syncthreads();
   }
+}
+
+// Row-major complex field -> column-major copy, through 32 x 32 LDS tiles
+// (16 x 16 on 16-wide grids).
+template <int T>
+__global__ void __launch_bounds__(256) k_to_colmajor(const float2* src, float2* dst, int ny, int nz) {
+  __shared__ float2 tile[T][T + 1];
+  constexpr int R = 256 / T;
+  const int tx = threadIdx.x % T, ty = threadIdx.x / T;
+  const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
+  for (int r = ty; r < T; r += R) tile[r][tx] = src[(int64_t)(y0 + r) * nz + z0 + tx];
+  __syncthreads();
+  for (int r = ty; r < T; r += R) dst[(int64_t)(z0 + r) * ny + y0 + tx] = tile[tx][r];
 }
 
 // Amplitude loss partial sums (FP64) and dL/dI.
@@ -440,6 +456,19 @@ msl_status copy_field(const Call& k, void* dst, const void* src) {
   return hip_check(hipMemcpyAsync(dst, src, (size_t)k.c.m * 8, hipMemcpyDeviceToDevice, k.st), "hipMemcpyAsync");
 }
 
+// Puts a row-major field into the buffer (and layout) the first pass of
+// phase `ph` reads.
+msl_status load_phase_input(const Call& k, const PhaseSpec& ph, const float2* src) {
+  if (msl::phase_first_axis(ph) == msl::ROW) return copy_field(k, ph.field, src);
+  if (k.g.ny >= 32 && k.g.nz >= 32)
+    hipLaunchKernelGGL(k_to_colmajor<32>, dim3(k.g.nz / 32, k.g.ny / 32), dim3(256), 0, k.st, src, ph.fieldT, k.g.ny,
+                       k.g.nz);
+  else
+    hipLaunchKernelGGL(k_to_colmajor<16>, dim3(k.g.nz / 16, k.g.ny / 16), dim3(256), 0, k.st, src, ph.fieldT, k.g.ny,
+                       k.g.nz);
+  return hip_check(hipGetLastError(), "transpose kernel");
+}
+
 int odd_slices(const msl_geometry& g) { return g.propagator == MSL_PROP_PARAXIAL ? g.n_slices / 2 : 0; }
 
 msl_status pack_odd(Call& k, const float* delta, const float* beta) {
@@ -526,6 +555,8 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   ph.s0 = 0;
   ph.s1 = g->n_slices;
   ph.field = f;
+  ph.fieldT = reinterpret_cast<float2*>(k.ws + k.L.fT);
+  ph.inplace = 1;
   ph.ckpt = reinterpret_cast<float2*>(ckpt);
   ph.ckpt_every = ckpt ? ckpt_every : 0;
   return run_phase(k, ph);
@@ -542,7 +573,7 @@ msl_status msl_far_field(const msl_geometry* g, const msl_c64* field, float* int
   MSL_TRY(build_tables(k, false));
   PhaseSpec ph = blank_phase(k, msl::PH_FF);
   ph.ff_src = reinterpret_cast<const float2*>(field);
-  ph.ff_tmp = reinterpret_cast<float2*>(k.ws + k.L.tmp);
+  ph.fieldT = reinterpret_cast<float2*>(k.ws + k.L.tmp);
   return run_phase(k, ph);
 }
 
@@ -576,7 +607,8 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field, co
   MSL_TRY(build_tables(k, false));
   PhaseSpec ph = blank_phase(k, msl::PH_FFADJ);
   ph.ff_src = reinterpret_cast<const float2*>(field);
-  ph.ff_tmp = reinterpret_cast<float2*>(grad_field);
+  ph.field = reinterpret_cast<float2*>(grad_field);
+  ph.fieldT = reinterpret_cast<float2*>(k.ws + k.L.tmp);
   return run_phase(k, ph);
 }
 
@@ -611,10 +643,11 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   const int nodd = odd_slices(*g);
   if (nodd > 0 && (grad_delta || grad_beta)) k.c.gT = reinterpret_cast<float2*>(k.ws + k.L.gT);
   float2* W = reinterpret_cast<float2*>(k.ws + k.L.W);
+  float2* WT = reinterpret_cast<float2*>(k.ws + k.L.WT);
   float2* G = reinterpret_cast<float2*>(k.ws + k.L.G);
+  float2* GT = reinterpret_cast<float2*>(k.ws + k.L.GT);
   float2* seg = reinterpret_cast<float2*>(k.ws + k.L.seg);
   const float2* ck = reinterpret_cast<const float2*>(ckpt);
-  MSL_TRY(copy_field(k, G, grad_field));
   const int ns = g->n_slices;
   const int nck = (ns + ckpt_every - 1) / ckpt_every;
   const int64_t seg_stride = (int64_t)(ckpt_every > 1 ? ckpt_every - 1 : 0) * k.c.m;
@@ -624,6 +657,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     ph.s0 = c * ckpt_every;
     ph.s1 = ph.s0 + ckpt_every < ns ? ph.s0 + ckpt_every : ns;
     ph.field = W;
+    ph.fieldT = WT;
     ph.seg = seg_of(c);
     return ph;
   };
@@ -633,6 +667,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     rv.s1 = rv.s0 + ckpt_every < ns ? rv.s0 + ckpt_every : ns;
     rv.leading = c == nck - 1;
     rv.field = G;
+    rv.fieldT = GT;
     rv.seg = seg_of(c);
     rv.ckpt_c = ck + (int64_t)c * k.c.m;
     return rv;
@@ -640,8 +675,9 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   // Segment c-1 is recomputed from its checkpoint while the reverse sweep runs
   // over segment c: the two fields are independent, so on square grids they
   // share passes (and each pass has twice the lines to spread over the chip).
+  MSL_TRY(load_phase_input(k, reverse(nck - 1), reinterpret_cast<const float2*>(grad_field)));
   PhaseSpec rc = recomp(nck - 1);
-  MSL_TRY(copy_field(k, W, ck + (int64_t)(nck - 1) * k.c.m));
+  MSL_TRY(load_phase_input(k, rc, ck + (int64_t)(nck - 1) * k.c.m));
   MSL_TRY(run_phase(k, rc));
   const bool persistent = use_persistent(k, ckpt_every + 1);
   if (persistent && g->ny == g->nz) {
@@ -650,7 +686,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
       PhaseSpec rv = reverse(c);
       if (c >= 1) {
         PhaseSpec nx = recomp(c - 1);
-        MSL_TRY(copy_field(k, W, ck + (int64_t)(c - 1) * k.c.m));
+        MSL_TRY(load_phase_input(k, nx, ck + (int64_t)(c - 1) * k.c.m));
         MSL_TRY(run_phases(k, rv, &nx));
       } else {
         MSL_TRY(run_phase(k, rv));
@@ -670,7 +706,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
       if (c >= 1) {
         MSL_TRY(hip_check(hipEventRecord(h->fork, k.st), "hipEventRecord"));
         MSL_TRY(hip_check(hipStreamWaitEvent(kh.st, h->fork, 0), "hipStreamWaitEvent"));
-        MSL_TRY(copy_field(kh, W, ck + (int64_t)(c - 1) * k.c.m));
+        MSL_TRY(load_phase_input(kh, recomp(c - 1), ck + (int64_t)(c - 1) * k.c.m));
         MSL_TRY(run_phase(kh, recomp(c - 1)));
         MSL_TRY(hip_check(hipEventRecord(h->join, kh.st), "hipEventRecord"));
       }

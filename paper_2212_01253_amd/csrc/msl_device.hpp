@@ -35,7 +35,13 @@ struct PassDesc {
   float2* dst;          // field written (may equal src; nullptr = not written)
   float2* psi_store;    // store the line before the mid step (nullptr = no)
   const float2* psi_load;  // entrance field psi_s for the adjoint step
+  // layouts of the four field arrays: LAY_R row-major [ny][nz], LAY_C
+  // column-major [nz][ny]; a pass reads its lines from the layout of its own
+  // axis (contiguous) and writes them in the layout of the next pass's axis
+  int src_lay, dst_lay, store_lay, load_lay;
 };
+
+enum Layout : int { LAY_R = 0, LAY_C = 1 };
 
 // Everything a pass reads besides the descriptor.
 struct Ctx {
@@ -315,9 +321,32 @@ __host__ __device__ inline int pass_kind(const PassDesc& pd) {
 }
 
 
+// Element offsets within one [ny][nz] field fit in 32 bits (at most 2^20
+// elements); slice offsets are added to the (uniform) base pointer instead.
+
+// Element i of line `line` of a pass along AXIS: row-major (y, z) offset.
 template <int N, int AXIS>
-__device__ __forceinline__ int64_t line_addr(const Ctx& c, int line, int i) {
-  return AXIS == ROW ? (int64_t)line * c.nz + i : (int64_t)i * c.nz + line;
+__device__ __forceinline__ uint32_t line_addr(const Ctx& c, int line, int i) {
+  return AXIS == ROW ? (uint32_t)line * (uint32_t)c.nz + (uint32_t)i : (uint32_t)i * (uint32_t)c.nz + (uint32_t)line;
+}
+
+// Line `line` of a pass along AXIS in layout `lay` (LAY_R row-major, LAY_C
+// column-major): element i is at base + i * stride.
+struct LineAddr {
+  uint32_t base, stride;
+};
+
+template <int AXIS>
+__device__ __forceinline__ LineAddr line_in(const Ctx& c, int lay, int line) {
+  const uint32_t l = (uint32_t)line;
+  if (AXIS == ROW) return lay == LAY_C ? LineAddr{l, (uint32_t)c.ny} : LineAddr{l * (uint32_t)c.nz, 1u};
+  return lay == LAY_C ? LineAddr{l * (uint32_t)c.ny, 1u} : LineAddr{l, (uint32_t)c.nz};
+}
+
+template <int N, int AXIS>
+__device__ __forceinline__ uint32_t lay_addr(const Ctx& c, int lay, int line, int i) {
+  const LineAddr a = line_in<AXIS>(c, lay, line);
+  return a.base + (uint32_t)i * a.stride;
 }
 
 // Everything a line pass reads, gathered in registers.  Loads are issued
@@ -361,14 +390,14 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
   } else if (pd.post == POST_PROP2D) {
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const int64_t e = (int64_t)(j + t * L) * c.nz + line;
+      const uint32_t e = (uint32_t)(j + t * L) * (uint32_t)c.nz + (uint32_t)line;
       in.hh[t] = c.H_hi[e];
       in.hl[t] = c.H_lo[e];
     }
   }
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
     if (AXIS == COL && c.dbT && (pd.slice & 1)) {
-      const float2* q = c.dbT + (int64_t)(pd.slice >> 1) * c.m + (int64_t)line * c.ny;
+      const float2* q = c.dbT + (int64_t)(pd.slice >> 1) * c.m + (uint32_t)line * (uint32_t)c.ny;
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         const float2 db = q[j + t * L];
@@ -380,7 +409,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
       const float* bp = c.beta + (int64_t)pd.slice * c.m;
 #pragma unroll
       for (int t = 0; t < P; ++t) {
-        const int64_t a = line_addr<N, AXIS>(c, line, j + t * L);
+        const uint32_t a = line_addr<N, AXIS>(c, line, j + t * L);
         in.dl[t] = dp[a];
         in.bt[t] = bp[a];
       }
@@ -388,7 +417,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
   }
   if (pd.mid == MID_T_ADJ) {
 #pragma unroll
-    for (int t = 0; t < P; ++t) in.ps[t] = pd.psi_load[line_addr<N, AXIS>(c, line, j + t * L)];
+    for (int t = 0; t < P; ++t) in.ps[t] = pd.psi_load[lay_addr<N, AXIS>(c, pd.load_lay, line, j + t * L)];
   }
   if (pd.mid == MID_FF_SEED) {
 #pragma unroll
@@ -396,7 +425,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
       const int i = j + t * L;
       const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
       const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
-      in.gi[t] = c.grad_intensity[(int64_t)rs * c.nz + cs];
+      in.gi[t] = c.grad_intensity[(uint32_t)rs * (uint32_t)c.nz + (uint32_t)cs];
     }
   }
 }
@@ -431,7 +460,7 @@ __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int
   constexpr int L = LinePts<N>::L;
   constexpr int P = LinePts<N>::P;
 #pragma unroll
-  for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + line_addr<N, AXIS>(c, line, j + t * L));
+  for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + lay_addr<N, AXIS>(c, pd.src_lay, line, j + t * L));
 }
 
 template <int N>
@@ -473,7 +502,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 
   if (pd.psi_store) {
 #pragma unroll
-    for (int t = 0; t < P; ++t) pd.psi_store[line_addr<N, AXIS>(c, line, j + t * L)] = v[t];
+    for (int t = 0; t < P; ++t) pd.psi_store[lay_addr<N, AXIS>(c, pd.store_lay, line, j + t * L)] = v[t];
   }
 
   if (pd.mid == MID_T_FWD) {
@@ -482,10 +511,13 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
       v[t] = apply_t(v[t], transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c)));
   } else if (pd.mid == MID_T_ADJ) {
     const int64_t so = (int64_t)pd.slice * c.m;
+    float* const gdp = c.gdelta ? c.gdelta + so : nullptr;
+    float* const gbp = c.gbeta ? c.gbeta + so : nullptr;
+    float2* const gtp = c.gT ? c.gT + (int64_t)(pd.slice >> 1) * c.m + (uint32_t)line * (uint32_t)c.ny : nullptr;
     const float kdx = c.kdx_hi;
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const int64_t e = so + line_addr<N, AXIS>(c, line, j + t * L);
+      const uint32_t e = line_addr<N, AXIS>(c, line, j + t * L);
       const float2 tm1 = transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c));
       const float2 pt = apply_t(in.ps[t], tm1);  // psi'_s = T_s psi_s
       const float2 g = v[t];                     // cotangent of psi'_s
@@ -493,10 +525,10 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
       const float cre = __builtin_fmaf(g.x, pt.x, g.y * pt.y);
       const float cim = __builtin_fmaf(g.x, pt.y, -(g.y * pt.x));
       if (AXIS == COL && c.gT && (pd.slice & 1)) {
-        c.gT[(int64_t)(pd.slice >> 1) * c.m + (int64_t)line * c.ny + j + t * L] = make_float2(-kdx * cim, -kdx * cre);
+        gtp[j + t * L] = make_float2(-kdx * cim, -kdx * cre);
       } else {
-        if (c.gdelta) c.gdelta[e] = -kdx * cim;
-        if (c.gbeta) c.gbeta[e] = -kdx * cre;
+        if (gdp) gdp[e] = -kdx * cim;
+        if (gbp) gbp[e] = -kdx * cre;
       }
       v[t] = apply_tconj(g, tm1);
     }
@@ -507,7 +539,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
       const int r = AXIS == ROW ? line : i, col = AXIS == ROW ? i : line;
       const int rs = (r + (c.ny >> 1)) & (c.ny - 1), cs = (col + (c.nz >> 1)) & (c.nz - 1);
       const float p = __builtin_fmaf(v[t].x, v[t].x, v[t].y * v[t].y);
-      c.intensity[(int64_t)rs * c.nz + cs] = p * c.inv_m;
+      c.intensity[(uint32_t)rs * (uint32_t)c.nz + (uint32_t)cs] = p * c.inv_m;
     }
   } else if (pd.mid == MID_FF_SEED) {
 #pragma unroll
@@ -526,7 +558,8 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 
   if (pd.dst) {
 #pragma unroll
-    for (int t = 0; t < P; ++t) field_st<COH>(pd.dst + line_addr<N, AXIS>(c, line, j + t * L), v[t]);
+    for (int t = 0; t < P; ++t)
+      field_st<COH>(pd.dst + lay_addr<N, AXIS>(c, pd.dst_lay, line, j + t * L), v[t]);
   }
 }
 

@@ -27,9 +27,20 @@ enum PhaseKind : int {
   PH_FWD_RECOMP = 1,  // slices [s0, s1): store psi_s, s0 < s < s1, into seg[s - s0 - 1]
   PH_REV = 2,         // reverse sweep over slices s1-1 .. s0 on the cotangent in `field`
   PH_FF = 3,          // far-field intensity of ff_src
-  PH_FFADJ = 4        // far-field adjoint: cotangent of ff_src into ff_tmp
+  PH_FFADJ = 4        // far-field adjoint: cotangent of ff_src into `field`
 };
 
+// Every field lives in two buffers: `field`, row-major, and `fieldT`,
+// column-major.  A pass reads its lines from the buffer of its own axis's
+// layout (rows from `field`, columns from `fieldT`: contiguous either way)
+// and writes them in the layout the next pass reads, so the strided side of
+// each transpose is a write.  A phase's first pass expects its input in its
+// own layout; the last pass of a phase that ends the sweep writes `field`.
+// Segment fields (adjoint) are kept in the layout of their slice's axis, the
+// caller-visible checkpoints row-major.  With `inplace` set a phase instead
+// keeps its field row-major in `field` throughout (column passes read and
+// write it strided); the forward sweep measured faster that way, the adjoint
+// phases with the exchange.
 struct PhaseSpec {
   int kind;
   int exact;          // exact (non-separable) propagator
@@ -37,12 +48,13 @@ struct PhaseSpec {
   int ckpt_every;
   int leading;        // PH_REV: first reverse phase (adds the leading half-propagation)
   int64_t m;
-  float2* field;      // working buffer, transformed in place
+  float2* field;      // row-major buffer of the working field
+  float2* fieldT;     // column-major buffer of the working field
   float2* ckpt;       // PH_FWD_FULL: checkpoint array or nullptr
   float2* seg;        // PH_FWD_RECOMP output / PH_REV input
   const float2* ckpt_c;  // PH_REV: psi_{s0}
-  const float2* ff_src;
-  float2* ff_tmp;
+  const float2* ff_src;  // PH_FF, PH_FFADJ: input field (row-major)
+  int inplace;        // 1: every pass reads and writes `field` row-major (column passes strided)
 };
 
 __host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
@@ -57,7 +69,11 @@ __host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
   }
 }
 
-__host__ __device__ inline PassDesc blank_pass(int axis, const float2* src, float2* dst) {
+__host__ __device__ inline int native_lay(int axis) { return axis == ROW ? LAY_R : LAY_C; }
+
+// A pass along `axis` of phase `ph`: source in the axis's own layout,
+// destination in the other one (the next pass's), or row-major if `final`.
+__host__ __device__ inline PassDesc make_pass(const PhaseSpec& ph, int axis, bool final) {
   PassDesc p;
   p.axis = axis;
   p.pre = PRE_NONE;
@@ -65,10 +81,14 @@ __host__ __device__ inline PassDesc blank_pass(int axis, const float2* src, floa
   p.post = POST_NONE;
   p.conj = 0;
   p.slice = 0;
-  p.src = src;
-  p.dst = dst;
+  p.src_lay = ph.inplace ? LAY_R : native_lay(axis);
+  p.src = p.src_lay == LAY_C ? ph.fieldT : ph.field;
+  p.dst_lay = (final || ph.inplace) ? LAY_R : native_lay(1 - axis);
+  p.dst = p.dst_lay == LAY_C ? ph.fieldT : ph.field;
   p.psi_store = nullptr;
   p.psi_load = nullptr;
+  p.store_lay = LAY_R;
+  p.load_lay = LAY_R;
   return p;
 }
 
@@ -77,18 +97,30 @@ __host__ __device__ inline float2* ckpt_slot(const PhaseSpec& ph, int s) {
   return ph.ckpt + (int64_t)(s / ph.ckpt_every) * ph.m;
 }
 
+// Axis of the first pass of a phase (its input must be in that layout).
+__host__ __device__ inline int phase_first_axis(const PhaseSpec& ph) {
+  if (ph.exact || ph.inplace) return ROW;  // (input is then always row-major)
+  switch (ph.kind) {
+    case PH_FWD_FULL:
+    case PH_FWD_RECOMP: return (ph.s0 & 1) ? COL : ROW;
+    case PH_REV: return ph.leading ? ((ph.ns & 1) ? COL : ROW) : (((ph.s1 - 1) & 1) ? COL : ROW);
+    default: return ROW;
+  }
+}
+
 __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
   const int n = ph.s1 - ph.s0;
-  float2* f = ph.field;
   switch (ph.kind) {
     case PH_FWD_FULL:
       if (!ph.exact) {
-        PassDesc d = blank_pass(((ph.s0 + p) & 1) ? COL : ROW, f, f);
+        const int axis = ((ph.s0 + p) & 1) ? COL : ROW;
+        PassDesc d = make_pass(ph, axis, p == n);
         if (p < n) {
           d.pre = p == 0 ? PRE_NONE : PRE_PROP;
           d.mid = MID_T_FWD;
           d.slice = ph.s0 + p;
           d.psi_store = ckpt_slot(ph, ph.s0 + p);
+          d.store_lay = LAY_R;
           d.post = POST_PROP;
         } else {
           d.pre = PRE_PROP;
@@ -96,26 +128,31 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
         return d;
       } else {
         if (p & 1) {
-          PassDesc d = blank_pass(COL, f, f);
+          PassDesc d = make_pass(ph, COL, false);
           d.post = POST_PROP2D;
           return d;
         }
-        PassDesc d = blank_pass(ROW, f, f);
         const int q = p / 2;
+        PassDesc d = make_pass(ph, ROW, q == n);
         d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
         if (q < n) {
           d.mid = MID_T_FWD;
           d.slice = ph.s0 + q;
           d.psi_store = ckpt_slot(ph, ph.s0 + q);
+          d.store_lay = LAY_R;
           d.post = POST_FFT;
         }
         return d;
       }
     case PH_FWD_RECOMP:
       if (!ph.exact) {
-        PassDesc d = blank_pass(((ph.s0 + p) & 1) ? COL : ROW, f, f);
+        const int axis = ((ph.s0 + p) & 1) ? COL : ROW;
+        PassDesc d = make_pass(ph, axis, false);
         d.pre = p == 0 ? PRE_NONE : PRE_PROP;
-        if (p > 0) d.psi_store = ph.seg + (int64_t)(p - 1) * ph.m;
+        if (p > 0) {
+          d.psi_store = ph.seg + (int64_t)(p - 1) * ph.m;
+          d.store_lay = native_lay(axis);
+        }
         if (p < n - 1) {
           d.mid = MID_T_FWD;
           d.slice = ph.s0 + p;
@@ -126,14 +163,17 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
         return d;
       } else {
         if (p & 1) {
-          PassDesc d = blank_pass(COL, f, f);
+          PassDesc d = make_pass(ph, COL, false);
           d.post = POST_PROP2D;
           return d;
         }
-        PassDesc d = blank_pass(ROW, f, f);
         const int q = p / 2;
+        PassDesc d = make_pass(ph, ROW, false);
         d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
-        if (q > 0) d.psi_store = ph.seg + (int64_t)(q - 1) * ph.m;
+        if (q > 0) {
+          d.psi_store = ph.seg + (int64_t)(q - 1) * ph.m;
+          d.store_lay = LAY_R;
+        }
         if (q < n - 1) {
           d.mid = MID_T_FWD;
           d.slice = ph.s0 + q;
@@ -146,7 +186,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
     case PH_REV: {
       if (ph.leading && p == 0) {
         // precedes the pass of slice ns - 1, so it takes the other axis
-        PassDesc d = blank_pass((!ph.exact && (ph.ns & 1)) ? COL : ROW, f, f);
+        PassDesc d = make_pass(ph, phase_first_axis(ph), false);
         if (ph.exact) d.post = POST_FFT;
         else { d.pre = PRE_PROP; d.conj = 1; }
         return d;
@@ -154,38 +194,48 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       const int q = p - (ph.leading ? 1 : 0);
       if (!ph.exact) {
         const int s = ph.s1 - 1 - q;
-        PassDesc d = blank_pass((s & 1) ? COL : ROW, f, f);
+        const int axis = (s & 1) ? COL : ROW;
+        PassDesc d = make_pass(ph, axis, s == 0);
         d.pre = PRE_PROP;
         d.conj = 1;
         d.mid = MID_T_ADJ;
         d.slice = s;
-        d.psi_load = s == ph.s0 ? ph.ckpt_c : ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
+        if (s == ph.s0) {
+          d.psi_load = ph.ckpt_c;
+          d.load_lay = LAY_R;
+        } else {
+          d.psi_load = ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
+          d.load_lay = native_lay(axis);
+        }
         d.post = s == 0 ? POST_NONE : POST_PROP;
         return d;
       } else {
         const int s = ph.s1 - 1 - q / 2;
         if ((q & 1) == 0) {
-          PassDesc d = blank_pass(COL, f, f);
+          PassDesc d = make_pass(ph, COL, false);
           d.post = POST_PROP2D;
           d.conj = 1;
           return d;
         }
-        PassDesc d = blank_pass(ROW, f, f);
+        PassDesc d = make_pass(ph, ROW, s == 0);
         d.pre = PRE_IFFT_N;
         d.mid = MID_T_ADJ;
         d.slice = s;
         d.psi_load = s == ph.s0 ? ph.ckpt_c : ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
+        d.load_lay = LAY_R;
         d.post = s == 0 ? POST_NONE : POST_FFT;
         return d;
       }
     }
     case PH_FF:
       if (p == 0) {
-        PassDesc d = blank_pass(ROW, ph.ff_src, ph.ff_tmp);
+        PassDesc d = make_pass(ph, ROW, false);
+        d.src = ph.ff_src;
         d.pre = PRE_IFFT_U;
         return d;
       } else {
-        PassDesc d = blank_pass(COL, ph.ff_tmp, nullptr);
+        PassDesc d = make_pass(ph, COL, false);
+        d.dst = nullptr;
         d.pre = PRE_IFFT_U;
         d.mid = MID_FF_OUT;
         return d;
@@ -193,17 +243,18 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
     case PH_FFADJ:
     default:
       if (p == 0) {
-        PassDesc d = blank_pass(ROW, ph.ff_src, ph.ff_tmp);
+        PassDesc d = make_pass(ph, ROW, false);
+        d.src = ph.ff_src;
         d.pre = PRE_IFFT_U;
         return d;
       } else if (p == 1) {
-        PassDesc d = blank_pass(COL, ph.ff_tmp, ph.ff_tmp);
+        PassDesc d = make_pass(ph, COL, false);
         d.pre = PRE_IFFT_U;
         d.mid = MID_FF_SEED;
         d.post = POST_FFT;
         return d;
       } else {
-        PassDesc d = blank_pass(ROW, ph.ff_tmp, ph.ff_tmp);
+        PassDesc d = make_pass(ph, ROW, true);
         d.pre = PRE_FFT;
         return d;
       }

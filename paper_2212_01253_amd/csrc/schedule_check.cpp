@@ -103,18 +103,31 @@ cd tfun(const Engine& E, int s, int64_t e) {
   return std::exp(cd(0, 1) * k * E.g.dx * cd(E.delta[s * m + e], E.beta[s * m + e]));
 }
 
+int g_bad_layout = 0;
+
 void run_pass(Engine& E, const msl::PassDesc& pd) {
   const Geo& g = E.g;
   const int64_t m = (int64_t)g.ny * g.nz;
   const bool row = pd.axis == msl::ROW;
   const int nl = row ? g.ny : g.nz, n = row ? g.nz : g.ny;
   Field* src = resolve(pd.src);
-  Field out = *src;
+  Field* dst = pd.dst ? resolve(pd.dst) : nullptr;
+  // a pass may rewrite its own lines in place, but never read one layout of a
+  // buffer while writing the other (other lines would be overwritten)
+  if (dst == src && pd.dst_lay != pd.src_lay) ++g_bad_layout;
+  // the source is read in the layout of the pass's own axis (contiguous), or
+  // row-major in place
+  if (pd.src_lay != (row ? msl::LAY_R : msl::LAY_C) && !(pd.src_lay == msl::LAY_R && pd.dst_lay == msl::LAY_R))
+    ++g_bad_layout;
   const double k = 2 * M_PI / g.lam;
   for (int line = 0; line < nl; ++line) {
     auto addr = [&](int i) -> int64_t { return row ? (int64_t)line * g.nz + i : (int64_t)i * g.nz + line; };
+    auto laddr = [&](int lay, int i) -> int64_t {
+      const int y = row ? line : i, z = row ? i : line;
+      return lay == msl::LAY_C ? (int64_t)z * g.ny + y : (int64_t)y * g.nz + z;
+    };
     std::vector<cd> v(n);
-    for (int i = 0; i < n; ++i) v[i] = (*src)[addr(i)];
+    for (int i = 0; i < n; ++i) v[i] = (*src)[laddr(pd.src_lay, i)];
     auto prop = [&](bool conj) {
       v = dft(v, -1);
       for (int i = 0; i < n; ++i) {
@@ -132,7 +145,7 @@ void run_pass(Engine& E, const msl::PassDesc& pd) {
     }
     if (pd.psi_store) {
       Field* st = resolve(pd.psi_store);
-      for (int i = 0; i < n; ++i) (*st)[addr(i)] = v[i];
+      for (int i = 0; i < n; ++i) (*st)[laddr(pd.store_lay, i)] = v[i];
     }
     if (pd.mid == msl::MID_T_FWD) {
       for (int i = 0; i < n; ++i) v[i] *= tfun(E, pd.slice, addr(i));
@@ -140,7 +153,7 @@ void run_pass(Engine& E, const msl::PassDesc& pd) {
       Field* ps = resolve(pd.psi_load);
       for (int i = 0; i < n; ++i) {
         const cd T = tfun(E, pd.slice, addr(i));
-        const cd pt = T * (*ps)[addr(i)];
+        const cd pt = T * (*ps)[laddr(pd.load_lay, i)];
         const cd c = std::conj(v[i]) * pt;
         E.gdelta[pd.slice * m + addr(i)] = -k * g.dx * c.imag();
         E.gbeta[pd.slice * m + addr(i)] = -k * g.dx * c.real();
@@ -167,9 +180,9 @@ void run_pass(Engine& E, const msl::PassDesc& pd) {
         break;
       default: break;
     }
-    for (int i = 0; i < n; ++i) out[addr(i)] = v[i];
+    if (dst)
+      for (int i = 0; i < n; ++i) (*dst)[laddr(pd.dst_lay, i)] = v[i];
   }
-  if (pd.dst) *resolve(pd.dst) = out;
 }
 
 void run_phase(Engine& E, const msl::PhaseSpec& ph) {
@@ -243,15 +256,18 @@ int check(const Geo& g, int kck) {
   const int64_t SPAN = 1 << 20;
   auto fake = [&](int slot) { return reinterpret_cast<float2*>((uintptr_t)(SPAN * 64 * (slot + 1))); };
   const int nck = (g.ns + kck - 1) / kck;
+  Arr fieldT{{Field(m)}, fake(6), m}, WT{{Field(m)}, fake(7), m}, GT{{Field(m)}, fake(8), m};
   Arr field{{probe}, fake(0), m}, ckpt{std::vector<Field>(nck, Field(m)), fake(1), m},
       seg{std::vector<Field>(kck > 1 ? 2 * (kck - 1) : 1, Field(m)), fake(2), m}, W{{Field(m)}, fake(3), m},
       G{{Field(m)}, fake(4), m}, tmp{{Field(m)}, fake(5), m};
-  g_arrays = {&field, &ckpt, &seg, &W, &G, &tmp};
+  g_arrays = {&field, &ckpt, &seg, &W, &G, &tmp, &fieldT, &WT, &GT};
 
   // forward with checkpoints
   msl::PhaseSpec ph{};
   ph.kind = msl::PH_FWD_FULL; ph.exact = g.exact; ph.s0 = 0; ph.s1 = g.ns; ph.ns = g.ns; ph.m = m;
-  ph.field = field.base == fake(0) ? fake(0) : nullptr;
+  ph.field = fake(0);
+  ph.fieldT = fake(6);
+  ph.inplace = (g.ns % 2) ? 0 : 1;  // both forward layouts
   ph.ckpt = fake(1); ph.ckpt_every = kck;
   run_phase(E, ph);
 
@@ -273,7 +289,7 @@ int check(const Geo& g, int kck) {
 
   // far field
   msl::PhaseSpec ff{};
-  ff.kind = msl::PH_FF; ff.m = m; ff.ff_src = fake(0); ff.ff_tmp = fake(5);
+  ff.kind = msl::PH_FF; ff.m = m; ff.ff_src = fake(0); ff.fieldT = fake(5);
   run_phase(E, ff);
   Field A = dft2(psi, g, +1);
   std::vector<double> Iref(m);
@@ -284,7 +300,7 @@ int check(const Geo& g, int kck) {
 
   // far-field adjoint into G
   msl::PhaseSpec fa{};
-  fa.kind = msl::PH_FFADJ; fa.m = m; fa.ff_src = fake(0); fa.ff_tmp = fake(4);
+  fa.kind = msl::PH_FFADJ; fa.m = m; fa.ff_src = fake(0); fa.field = fake(4); fa.fieldT = fake(5);
   run_phase(E, fa);
   Field seed(m);
   for (int r = 0; r < g.ny; ++r)
@@ -298,21 +314,35 @@ int check(const Geo& g, int kck) {
   // adjoint with recompute: the same order as the library (segment c-1 is
   // recomputed beside the reverse sweep over segment c, into the other of two
   // segment buffers)
+  // the library's load_phase_input: row-major copy, or column-major when the
+  // phase's first pass is a column pass
+  auto load_input = [&](const msl::PhaseSpec& ph, const Field& src, Field& R, Field& C) {
+    if (msl::phase_first_axis(ph) == msl::ROW) { R = src; return; }
+    for (int y = 0; y < g.ny; ++y)
+      for (int z = 0; z < g.nz; ++z) C[(int64_t)z * g.ny + y] = src[(int64_t)y * g.nz + z];
+  };
   auto recomp = [&](int c) {
     const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
     if (s1 - s0 < 2) return;
-    W.f[0] = ckpt.f[c];
     msl::PhaseSpec rc{};
     rc.kind = msl::PH_FWD_RECOMP; rc.exact = g.exact; rc.s0 = s0; rc.s1 = s1; rc.ns = g.ns; rc.m = m;
-    rc.field = fake(3); rc.seg = fake(2) + (c & 1) * (int64_t)(kck > 1 ? kck - 1 : 0) * m;
+    rc.field = fake(3); rc.fieldT = fake(7);
+    rc.seg = fake(2) + (c & 1) * (int64_t)(kck > 1 ? kck - 1 : 0) * m;
+    load_input(rc, ckpt.f[c], W.f[0], WT.f[0]);
     run_phase(E, rc);
   };
+  {
+    msl::PhaseSpec first{};
+    first.kind = msl::PH_REV; first.exact = g.exact; first.ns = g.ns; first.leading = 1;
+    first.s0 = (nck - 1) * kck; first.s1 = g.ns;
+    load_input(first, G.f[0], G.f[0], GT.f[0]);
+  }
   recomp(nck - 1);
   for (int c = nck - 1; c >= 0; --c) {
     const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
     msl::PhaseSpec rv{};
     rv.kind = msl::PH_REV; rv.exact = g.exact; rv.s0 = s0; rv.s1 = s1; rv.ns = g.ns; rv.m = m;
-    rv.leading = c == nck - 1; rv.field = fake(4);
+    rv.leading = c == nck - 1; rv.field = fake(4); rv.fieldT = fake(8);
     rv.seg = fake(2) + (c & 1) * (int64_t)(kck > 1 ? kck - 1 : 0) * m;
     rv.ckpt_c = fake(1) + (int64_t)c * m;
     run_phase(E, rv);
@@ -336,6 +366,7 @@ int check(const Geo& g, int kck) {
   if (relv(E.gdelta, gd) > 1e-9) { std::printf("grad delta mismatch %g\n", relv(E.gdelta, gd)); ++bad; }
   if (relv(E.gbeta, gb) > 1e-9) { std::printf("grad beta mismatch %g\n", relv(E.gbeta, gb)); ++bad; }
   if (rel(G.f[0], gg) > 1e-10) { std::printf("grad probe mismatch %g\n", rel(G.f[0], gg)); ++bad; }
+  if (g_bad_layout) { std::printf("layout hazard in %d passes\n", g_bad_layout); ++bad; g_bad_layout = 0; }
   std::printf("%s ny=%d nz=%d ns=%d k=%d: field %.1e -> %s\n", g.exact ? "exact" : "paraxial", g.ny, g.nz, g.ns,
               kck, ef, bad ? "FAIL" : "ok");
   return bad;
@@ -346,7 +377,8 @@ int check(const Geo& g, int kck) {
 int main() {
   int bad = 0;
   for (int exact = 0; exact < 2; ++exact) {
-    const int cfg[][4] = {{8, 16, 1, 1}, {8, 16, 5, 2}, {16, 8, 7, 3}, {8, 8, 6, 6}, {16, 16, 9, 4}, {8, 32, 4, 10}};
+    const int cfg[][4] = {{8, 16, 1, 1}, {8, 16, 5, 2}, {16, 8, 7, 3}, {8, 8, 6, 6}, {16, 16, 9, 4}, {8, 32, 4, 10},
+                          {16, 8, 11, 5}, {8, 8, 8, 3}, {16, 16, 2, 1}};
     for (auto& c : cfg) {
       Geo g{c[0], c[1], c[2], 0.9, 1.3, 7.0, 0.15, exact == 1};
       bad += check(g, c[3]);
