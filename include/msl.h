@@ -148,10 +148,10 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field,
                                  void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* msl_adjoint flags. */
-#define MSL_ADJ_REUSE_SLICE_PACK 1u  /* the workspace still holds the packed copy of the
-                                        slice stack that msl_forward wrote (same geometry,
-                                        delta, beta and workspace; delta and beta unchanged
-                                        since): skip rebuilding it */
+#define MSL_ADJ_REUSE_SLICE_PACK 1u  /* the workspace still holds the packed, transposed
+                                        transmissions of the odd slices that msl_forward
+                                        wrote (same geometry, delta, beta and workspace;
+                                        delta and beta unchanged since): skip rebuilding them */
 
 /* Gradient of a real loss through the multislice recurrence (reverse sweep
  * of Eq. 1 with checkpoint recomputation).

@@ -191,21 +191,23 @@ __global__ void k_probe(int ny, int nz, double q, float2* out) {
   out[i] = make_float2((float)c, (float)s);
 }
 
-// Odd slices' (delta, beta) -> dbT[s/2][z][y] (float2), through T x T LDS
-// tiles (T = 32, or 16 on 16-wide grids); 256 threads, T/16... rows each.
+// Odd slices' transmission minus one, T - 1 = exp(i k dx (delta + i beta)) - 1
+// -> dbT[s/2][z][y] (float2), through T x T LDS tiles (T = 32, or 16 on
+// 16-wide grids); 256 threads.  Covers odd slices 2 s2 + 1, s2 in [s2b, s2e).
+// The line passes evaluate T - 1 of the other slices with the same function.
 template <int T>
 __global__ void __launch_bounds__(256) k_pack_odd(const float* d, const float* b, float2* out, int ny, int nz,
-                                                  int nodd) {
+                                                  int s2b, int s2e, msl::Ctx c) {
   __shared__ float2 tile[T][T + 1];
   constexpr int R = 256 / T;  // rows of the tile per pass of the block
   const int tx = threadIdx.x % T, ty = threadIdx.x / T;
   const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
   const int64_t m = (int64_t)ny * nz;
-  for (int s2 = blockIdx.z; s2 < nodd; s2 += gridDim.z) {
+  for (int s2 = s2b + blockIdx.z; s2 < s2e; s2 += gridDim.z) {
     const int64_t si = (int64_t)(2 * s2 + 1) * m;
     for (int r = ty; r < T; r += R) {
       const int64_t a = si + (int64_t)(y0 + r) * nz + z0 + tx;
-      tile[r][tx] = make_float2(d[a], b[a]);
+      tile[r][tx] = msl::transmission_m1(msl::phase_arg(d[a], c), msl::phase_arg(b[a], c));
     }
     __syncthreads();
     for (int r = ty; r < T; r += R) out[(int64_t)s2 * m + (int64_t)(z0 + r) * ny + y0 + tx] = tile[tx][r];
@@ -213,16 +215,17 @@ __global__ void __launch_bounds__(256) k_pack_odd(const float* d, const float* b
   }
 }
 
-// gT[s/2][z][y] (float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z] for odd s.
+// gT[s/2][z][y] (float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z]
+// for odd slices s = 2 s2 + 1, s2 in [s2b, s2e).
 template <int T>
 __global__ void __launch_bounds__(256) k_unpack_odd(const float2* gT, float* gd, float* gb, int ny, int nz,
-                                                    int nodd) {
+                                                    int s2b, int s2e) {
   __shared__ float2 tile[T][T + 1];
   constexpr int R = 256 / T;
   const int tx = threadIdx.x % T, ty = threadIdx.x / T;
   const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
   const int64_t m = (int64_t)ny * nz;
-  for (int s2 = blockIdx.z; s2 < nodd; s2 += gridDim.z) {
+  for (int s2 = s2b + blockIdx.z; s2 < s2e; s2 += gridDim.z) {
     for (int r = ty; r < T; r += R) tile[r][tx] = gT[(int64_t)s2 * m + (int64_t)(z0 + r) * ny + y0 + tx];
     __syncthreads();
     for (int r = ty; r < T; r += R) {
@@ -390,13 +393,16 @@ msl_status build_tables(const Call& k, bool need_prop) {
   return hip_check(hipGetLastError(), "table kernels");
 }
 
-// Helper stream and fork/join events of one device: the adjoint runs the
-// segment recompute on it beside the reverse sweep on the caller's stream.
-// Created on first use and kept for the life of the process (default
-// priority, non-blocking).
+// Helper stream and events of one device.  The adjoint runs side work on it
+// beside the reverse sweep on the caller's stream: the segment recompute and
+// the unpacking of finished gradient slices.  Created on first use
+// and kept for the life of the process (default priority, non-blocking).
+// `mu` is held while a call enqueues work that uses the helper, so calls from
+// several host threads do not interleave their event records and waits.
 struct Helper {
+  std::mutex mu;
   hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
 };
 
 msl_status helper_for_current_device(Helper*& out) {
@@ -408,12 +414,20 @@ msl_status helper_for_current_device(Helper*& out) {
   std::lock_guard<std::mutex> lock(mu);
   Helper& h = helpers[dev];
   if (!h.s) {
+    auto ev = [](hipEvent_t* e) { return hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreateWithFlags"); };
     MSL_TRY(hip_check(hipStreamCreateWithFlags(&h.s, hipStreamNonBlocking), "hipStreamCreateWithFlags"));
-    MSL_TRY(hip_check(hipEventCreateWithFlags(&h.fork, hipEventDisableTiming), "hipEventCreateWithFlags"));
-    MSL_TRY(hip_check(hipEventCreateWithFlags(&h.join, hipEventDisableTiming), "hipEventCreateWithFlags"));
+    MSL_TRY(ev(&h.fork));
+    MSL_TRY(ev(&h.join));
+    MSL_TRY(ev(&h.done));
   }
   out = &h;
   return MSL_OK;
+}
+
+// `dst` waits for the work enqueued on `src` so far.
+msl_status stream_after(hipStream_t dst, hipStream_t src, hipEvent_t e) {
+  MSL_TRY(hip_check(hipEventRecord(e, src), "hipEventRecord"));
+  return hip_check(hipStreamWaitEvent(dst, e, 0), "hipStreamWaitEvent");
 }
 
 bool use_persistent(const Call& k, int np) {
@@ -471,19 +485,45 @@ msl_status load_phase_input(const Call& k, const PhaseSpec& ph, const float2* sr
 
 int odd_slices(const msl_geometry& g) { return g.propagator == MSL_PROP_PARAXIAL ? g.n_slices / 2 : 0; }
 
-msl_status pack_odd(Call& k, const float* delta, const float* beta) {
+// Odd slices among [s0, s1) are 2 s2 + 1 for s2 in [s0 / 2, s1 / 2).
+int odd_begin(int s0) { return s0 >> 1; }
+int odd_end(int s1) { return s1 >> 1; }
+
+// Packs odd slices 2 s2 + 1, s2 in [s2b, s2e), into dbT on stream st.
+msl_status pack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
+  if (s2e <= s2b) return MSL_OK;
+  float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
+  const int n = s2e - s2b;
+  const unsigned gz = n < 8192 ? n : 8192;
+  if (k.g.ny >= 32 && k.g.nz >= 32)
+    hipLaunchKernelGGL(k_pack_odd<32>, dim3(k.g.nz / 32, k.g.ny / 32, gz), dim3(256), 0, st, k.c.delta, k.c.beta,
+                       dbT, k.g.ny, k.g.nz, s2b, s2e, k.c);
+  else
+    hipLaunchKernelGGL(k_pack_odd<16>, dim3(k.g.nz / 16, k.g.ny / 16, gz), dim3(256), 0, st, k.c.delta, k.c.beta,
+                       dbT, k.g.ny, k.g.nz, s2b, s2e, k.c);
+  return hip_check(hipGetLastError(), "pack kernel");
+}
+
+msl_status pack_odd(Call& k) {
   const int nodd = odd_slices(k.g);
   if (nodd == 0) return MSL_OK;
-  float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
-  const unsigned gz = nodd < 8192 ? nodd : 8192;
+  MSL_TRY(pack_odd_range(k, 0, nodd, k.st));
+  k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
+  return MSL_OK;
+}
+
+// Unpacks the gradients of odd slices 2 s2 + 1, s2 in [s2b, s2e), on stream st.
+msl_status unpack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
+  if (s2e <= s2b || !k.c.gT) return MSL_OK;
+  const int n = s2e - s2b;
+  const unsigned gz = n < 8192 ? n : 8192;
   if (k.g.ny >= 32 && k.g.nz >= 32)
-    hipLaunchKernelGGL(k_pack_odd<32>, dim3(k.g.nz / 32, k.g.ny / 32, gz), dim3(256), 0, k.st, delta, beta, dbT,
-                       k.g.ny, k.g.nz, nodd);
+    hipLaunchKernelGGL(k_unpack_odd<32>, dim3(k.g.nz / 32, k.g.ny / 32, gz), dim3(256), 0, st, k.c.gT, k.c.gdelta,
+                       k.c.gbeta, k.g.ny, k.g.nz, s2b, s2e);
   else
-    hipLaunchKernelGGL(k_pack_odd<16>, dim3(k.g.nz / 16, k.g.ny / 16, gz), dim3(256), 0, k.st, delta, beta, dbT,
-                       k.g.ny, k.g.nz, nodd);
-  k.c.dbT = dbT;
-  return hip_check(hipGetLastError(), "pack kernel");
+    hipLaunchKernelGGL(k_unpack_odd<16>, dim3(k.g.nz / 16, k.g.ny / 16, gz), dim3(256), 0, st, k.c.gT, k.c.gdelta,
+                       k.c.gbeta, k.g.ny, k.g.nz, s2b, s2e);
+  return hip_check(hipGetLastError(), "unpack kernel");
 }
 
 PhaseSpec blank_phase(const Call& k, int kind) {
@@ -542,7 +582,6 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   k.c.delta = delta;
   k.c.beta = beta;
   MSL_TRY(build_tables(k, true));
-  MSL_TRY(pack_odd(k, delta, beta));
   float2* f = reinterpret_cast<float2*>(field_out);
   if (probe) {
     MSL_TRY(copy_field(k, f, probe));
@@ -559,6 +598,7 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   ph.inplace = 1;
   ph.ckpt = reinterpret_cast<float2*>(ckpt);
   ph.ckpt_every = ckpt ? ckpt_every : 0;
+  MSL_TRY(pack_odd(k));
   return run_phase(k, ph);
 }
 
@@ -638,7 +678,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   if (flags & MSL_ADJ_REUSE_SLICE_PACK) {
     if (odd_slices(*g) > 0) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
   } else {
-    MSL_TRY(pack_odd(k, delta, beta));
+    MSL_TRY(pack_odd(k));
   }
   const int nodd = odd_slices(*g);
   if (nodd > 0 && (grad_delta || grad_beta)) k.c.gT = reinterpret_cast<float2*>(k.ws + k.L.gT);
@@ -680,6 +720,8 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   MSL_TRY(load_phase_input(k, rc, ck + (int64_t)(nck - 1) * k.c.m));
   MSL_TRY(run_phase(k, rc));
   const bool persistent = use_persistent(k, ckpt_every + 1);
+  auto seg_odd_b = [&](int c) { return odd_begin(c * ckpt_every); };
+  auto seg_odd_e = [&](int c) { return odd_end((c + 1) * ckpt_every < ns ? (c + 1) * ckpt_every : ns); };
   if (persistent && g->ny == g->nz) {
     // one cooperative launch carries both fields
     for (int c = nck - 1; c >= 0; --c) {
@@ -692,36 +734,31 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
         MSL_TRY(run_phase(k, rv));
       }
     }
+    MSL_TRY(unpack_odd_range(k, 0, nodd, k.st));
   } else {
     // per-pass launches: the recompute of segment c-1 runs on the helper
     // stream while the reverse sweep over segment c runs on the caller's
     // stream; recompute(c-1) starts after reverse(c+1) (which read the same
-    // segment buffer) and reverse(c-1) waits for recompute(c-1)
+    // segment buffer) and reverse(c-1) waits for recompute(c-1).  After
+    // recompute(c-1) the helper unpacks the finished gradients of segment c+1.
     Helper* h = nullptr;
     MSL_TRY(helper_for_current_device(h));
+    std::lock_guard<std::mutex> lock(h->mu);
     Call kh = k;
     kh.st = h->s;
     for (int c = nck - 1; c >= 0; --c) {
       if (c < nck - 1) MSL_TRY(hip_check(hipStreamWaitEvent(k.st, h->join, 0), "hipStreamWaitEvent"));
+      MSL_TRY(stream_after(kh.st, k.st, h->fork));
       if (c >= 1) {
-        MSL_TRY(hip_check(hipEventRecord(h->fork, k.st), "hipEventRecord"));
-        MSL_TRY(hip_check(hipStreamWaitEvent(kh.st, h->fork, 0), "hipStreamWaitEvent"));
         MSL_TRY(load_phase_input(kh, recomp(c - 1), ck + (int64_t)(c - 1) * k.c.m));
         MSL_TRY(run_phase(kh, recomp(c - 1)));
         MSL_TRY(hip_check(hipEventRecord(h->join, kh.st), "hipEventRecord"));
       }
+      if (c < nck - 1) MSL_TRY(unpack_odd_range(k, seg_odd_b(c + 1), seg_odd_e(c + 1), kh.st));
       MSL_TRY(run_phase(k, reverse(c)));
     }
-  }
-  if (k.c.gT) {
-    const unsigned gz = nodd < 8192 ? nodd : 8192;
-    if (g->ny >= 32 && g->nz >= 32)
-      hipLaunchKernelGGL(k_unpack_odd<32>, dim3(g->nz / 32, g->ny / 32, gz), dim3(256), 0, k.st, k.c.gT, grad_delta,
-                         grad_beta, g->ny, g->nz, nodd);
-    else
-      hipLaunchKernelGGL(k_unpack_odd<16>, dim3(g->nz / 16, g->ny / 16, gz), dim3(256), 0, k.st, k.c.gT, grad_delta,
-                         grad_beta, g->ny, g->nz, nodd);
-    MSL_TRY(hip_check(hipGetLastError(), "unpack kernel"));
+    MSL_TRY(unpack_odd_range(k, seg_odd_b(0), seg_odd_e(0), k.st));
+    MSL_TRY(stream_after(k.st, kh.st, h->done));
   }
   if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));
   return MSL_OK;

@@ -61,7 +61,7 @@ struct Ctx {
   float* intensity;                 // far-field output (fftshifted) or nullptr
   const float* grad_intensity;      // far-field seed input (fftshifted) or nullptr
   // Odd slices are always transmitted in column passes (paraxial schedule).
-  // For them the workspace may hold (delta, beta) packed and transposed,
+  // For them the workspace may hold T - 1 precomputed and transposed,
   // [Ns/2][nz][ny] float2, and a staging area for their (dL/d delta,
   // dL/d beta) in the same layout, so column passes access both coalesced.
   const float2* dbT;                // or nullptr
@@ -397,12 +397,13 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
   }
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
     if (AXIS == COL && c.dbT && (pd.slice & 1)) {
+      // precomputed T - 1 (real part in dl, imaginary part in bt)
       const float2* q = c.dbT + (int64_t)(pd.slice >> 1) * c.m + (uint32_t)line * (uint32_t)c.ny;
 #pragma unroll
       for (int t = 0; t < P; ++t) {
-        const float2 db = q[j + t * L];
-        in.dl[t] = db.x;
-        in.bt[t] = db.y;
+        const float2 tm = q[j + t * L];
+        in.dl[t] = tm.x;
+        in.bt[t] = tm.y;
       }
     } else {
       const float* dp = c.delta + (int64_t)pd.slice * c.m;
@@ -505,10 +506,19 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
     for (int t = 0; t < P; ++t) pd.psi_store[lay_addr<N, AXIS>(c, pd.store_lay, line, j + t * L)] = v[t];
   }
 
+  float2 tm1[P];  // T - 1 of the slice at this line's points
+  if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
+    if (AXIS == COL && c.dbT && (pd.slice & 1)) {
+#pragma unroll
+      for (int t = 0; t < P; ++t) tm1[t] = make_float2(in.dl[t], in.bt[t]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < P; ++t) tm1[t] = transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c));
+    }
+  }
   if (pd.mid == MID_T_FWD) {
 #pragma unroll
-    for (int t = 0; t < P; ++t)
-      v[t] = apply_t(v[t], transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c)));
+    for (int t = 0; t < P; ++t) v[t] = apply_t(v[t], tm1[t]);
   } else if (pd.mid == MID_T_ADJ) {
     const int64_t so = (int64_t)pd.slice * c.m;
     float* const gdp = c.gdelta ? c.gdelta + so : nullptr;
@@ -518,8 +528,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       const uint32_t e = line_addr<N, AXIS>(c, line, j + t * L);
-      const float2 tm1 = transmission_m1(phase_arg(in.dl[t], c), phase_arg(in.bt[t], c));
-      const float2 pt = apply_t(in.ps[t], tm1);  // psi'_s = T_s psi_s
+      const float2 pt = apply_t(in.ps[t], tm1[t]);  // psi'_s = T_s psi_s
       const float2 g = v[t];                     // cotangent of psi'_s
       // conj(g) * psi' = (gx px + gy py) + i (gx py - gy px)
       const float cre = __builtin_fmaf(g.x, pt.x, g.y * pt.y);
@@ -530,7 +539,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
         if (gdp) gdp[e] = -kdx * cim;
         if (gbp) gbp[e] = -kdx * cre;
       }
-      v[t] = apply_tconj(g, tm1);
+      v[t] = apply_tconj(g, tm1[t]);
     }
   } else if (pd.mid == MID_FF_OUT) {
 #pragma unroll
