@@ -1,10 +1,11 @@
 """Benchmark: multislice forward + adjoint (one gradient evaluation) on one MI355X.
 
 One step = the whole hot path over the 512 x 512 x 2048 bars-on-substrate
-workload (5 nm slices, 0.1 nm wavelength): forward sweep with checkpoints
-every 32 slices, far-field intensity, amplitude loss and its derivative,
-far-field adjoint, and the checkpointed adjoint sweep producing dL/d delta,
-dL/d beta and dL/d probe.  Inputs are resident in HBM before timing starts.
+workload (5 nm slices, 0.1 nm wavelength): slice pack (odd slices'
+transmissions, transposed), forward sweep with checkpoints every 32 slices,
+far-field intensity, amplitude loss and its derivative, far-field adjoint,
+and the checkpointed adjoint sweep producing dL/d delta, dL/d beta and
+dL/d probe.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  `value` is voxel-slice-steps per second of the
 forward + adjoint step (Ny * Nz * Ns / step time).
@@ -21,7 +22,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 FWD_BYTES = 24.0          # per voxel-slice: delta + beta (8 B) + field read and write (16 B)
+
+
+def fwd_flops_per_voxel_slice(n):
+    # one line pass: four n-point complex FFTs (5 n log2 n flops each), two
+    # propagator multiplies and the transmission multiply (6 flops each); the
+    # transmission's exponential is not counted
+    return 4 * 5 * math.log2(n) + 3 * 6
 
 
 def grad_bytes_per_voxel_slice(k):
@@ -35,9 +44,10 @@ KERNEL_SOURCES = ("paper_2212_01253_amd/csrc/msl_device.hpp", "paper_2212_01253_
 TRAFFIC_PROFILE = "profiles/k_pass_512_bars_512x512x2048.md"
 
 
-def measured_traffic():
-    """HBM bytes per forward-pass launch from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+def profile_figures():
+    """(HBM bytes, kernel microseconds) per forward middle-pass launch from the
+    committed rocprofv3 summary, or (None, None) when the kernel sources
+    changed since it was taken."""
     import hashlib
     import re
     try:
@@ -46,12 +56,13 @@ def measured_traffic():
         for p in KERNEL_SOURCES:
             h.update(open(os.path.join(ROOT, p), "rb").read())
     except OSError:
-        return None
+        return None, None
     b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    us = re.search(r"kernel_us_per_launch: ([0-9.]+)", text)
     sha = re.search(r"sources_sha256: ([0-9a-f]+)", text)
-    if not b or not sha or sha.group(1) != h.hexdigest():
-        return None
-    return int(b.group(1))
+    if not b or not us or not sha or sha.group(1) != h.hexdigest():
+        return None, None
+    return int(b.group(1)), float(us.group(1))
 
 
 def cpu_baseline(w, meas, n_sample):
@@ -125,24 +136,27 @@ def main():
     def step(ev=None):
         if ev:
             ev[0].record()
-        msl.forward(g, D, B, None, k, ws=ws, out=field, ckpt=ck)
+        msl.pack_slices(g, D, B, ws)
         if ev:
             ev[1].record()
+        msl.forward(g, D, B, None, k, ws=ws, out=field, ckpt=ck, reuse_pack=True)
+        if ev:
+            ev[2].record()
         msl.far_field(g, field, ws=ws, out=I)
         _, gI = msl.amp_loss(g, I, Mm, ws=ws)
         msl.far_field_adjoint(g, field, gI, ws=ws, out=gpsi)
         if ev:
-            ev[2].record()
+            ev[3].record()
         msl.adjoint(g, D, B, ck, k, gpsi, ws=ws, gd=gd, gb=gb, want_probe=True, reuse_pack=True)
         if ev:
-            ev[3].record()
+            ev[4].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     print(f"# warmup done", file=sys.stderr, flush=True)
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -153,21 +167,28 @@ def main():
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     ms = total_ms / args.steps
-    fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    mid_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    adj_ms = [e[2].elapsed_time(e[3]) for e in evs]
+    pack_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    fwd_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    mid_ms = [e[2].elapsed_time(e[3]) for e in evs]
+    adj_ms = [e[3].elapsed_time(e[4]) for e in evs]
+    step_ms = [e[0].elapsed_time(e[4]) for e in evs]
     vs = ny * nz * ns
     value = vs / (ms / 1e3)
     bpv = grad_bytes_per_voxel_slice(k)
     achieved = vs * bpv / (ms / 1e3) / 1e9
     fwd_med = float(np.median(fwd_ms))
-    fwd_gbs = vs * (FWD_BYTES + 8.0 / k) / (fwd_med / 1e3) / 1e9
+    # the forward region holds the line passes only (plus three table kernels
+    # and the probe, a few microseconds): Ns + 1 launches back to back, so the
+    # per-launch time is kernel duration plus the dispatch gap between launches
     pass_bytes = (FWD_BYTES + 8.0 / k) * ny * nz
-    launch_s = fwd_med / 1e3 / (ns + 1)       # forward launches: Ns + 1 line passes
+    launch_s = fwd_med / 1e3 / (ns + 1)
     pass_gbs = pass_bytes / launch_s / 1e9
-    traffic = measured_traffic()
-    print(f"# step {ms:.3f} ms: forward {fwd_med:.3f} ms, far field+loss+seed {np.median(mid_ms):.3f} ms, "
-          f"adjoint {np.median(adj_ms):.3f} ms", file=sys.stderr, flush=True)
+    pass_tflops = fwd_flops_per_voxel_slice(nz) * ny * nz / launch_s / 1e12
+    traffic, prof_us = profile_figures()
+    fwd_path_ms = float(np.median([a + b + c for a, b, c in zip(pack_ms, fwd_ms, mid_ms)]))
+    print(f"# step {ms:.3f} ms: pack {np.median(pack_ms):.3f} ms, forward {fwd_med:.3f} ms, "
+          f"far field+loss+seed {np.median(mid_ms):.3f} ms, adjoint {np.median(adj_ms):.3f} ms",
+          file=sys.stderr, flush=True)
 
     out = {
         "metric": "multislice voxel-slice-steps/s fwd+adj (c64)",
@@ -193,10 +214,17 @@ def main():
                      "traffic": (traffic / launch_s / 1e9) if traffic else None,
                      "kernel": "k_pass<512,*,1> forward line pass (propagate, transmit, propagate)",
                      "bytes_per_launch": pass_bytes, "us_per_launch": launch_s * 1e6,
-                     "traffic_bytes_per_launch": traffic},
+                     "traffic_bytes_per_launch": traffic, "rocprof_kernel_us": prof_us,
+                     "flops_per_launch": fwd_flops_per_voxel_slice(nz) * ny * nz,
+                     "achieved_TFLOPs": pass_tflops, "fp32_frac": pass_tflops / FP32_PEAK_TFLOPS},
         "step": {"bytes_per_voxel_slice": bpv, "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS,
-                 "forward_ms": fwd_med, "adjoint_ms": float(np.median(adj_ms)),
+                 "ms_p10": float(np.percentile(step_ms, 10)), "ms_p50": float(np.median(step_ms)),
+                 "ms_p90": float(np.percentile(step_ms, 90)),
+                 "pack_ms": float(np.median(pack_ms)), "forward_ms": fwd_med, "adjoint_ms": float(np.median(adj_ms)),
                  "far_field_loss_seed_ms": float(np.median(mid_ms))},
+        # forward path alone (pack, forward sweep, far field, loss): Ny Nz Ns / time
+        "forward_throughput": {"value": vs / (fwd_path_ms / 1e3), "unit": "voxel-slice-steps/s",
+                               "ms": fwd_path_ms},
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)

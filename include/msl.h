@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define MSL_ABI_VERSION 1
+#define MSL_ABI_VERSION 2
 
 typedef struct { float re, im; } msl_c64;
 
@@ -119,10 +119,11 @@ int32_t msl_checkpoint_count(const msl_geometry* g, int32_t ckpt_every);
  *   ckpt         NULL (then ckpt_every must be 0) or complex64
  *                [msl_checkpoint_count][ny][nz]: ckpt[c] receives the
  *                entrance field of slice c * ckpt_every (ckpt[0] = probe).
+ *   flags        0 or MSL_REUSE_SLICE_PACK (below); unknown bits are an error.
  *   workspace    device memory, 256-byte aligned, >= msl_workspace_bytes. */
 msl_status msl_forward(const msl_geometry* g, const float* delta, const float* beta,
                        const msl_c64* probe, msl_c64* field_out,
-                       msl_c64* ckpt, int32_t ckpt_every,
+                       msl_c64* ckpt, int32_t ckpt_every, uint32_t flags,
                        void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Far-field detector intensity of a field [Sec. 1; Fig. 1 caption]:
@@ -147,11 +148,22 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field,
                                  const float* grad_intensity, msl_c64* grad_field,
                                  void* workspace, size_t ws_bytes, void* hip_stream);
 
-/* msl_adjoint flags. */
-#define MSL_ADJ_REUSE_SLICE_PACK 1u  /* the workspace still holds the packed, transposed
-                                        transmissions of the odd slices that msl_forward
-                                        wrote (same geometry, delta, beta and workspace;
-                                        delta and beta unchanged since): skip rebuilding them */
+/* Flag of msl_forward and msl_adjoint: the workspace already holds the slice
+ * pack (below) for this geometry's wavelength and dx and these delta and
+ * beta, written by msl_pack_slices or by an earlier msl_forward / msl_adjoint
+ * call on the same workspace, and delta and beta are unchanged since; the
+ * call skips rebuilding it.  Without the flag every call rebuilds it. */
+#define MSL_REUSE_SLICE_PACK 1u
+
+/* Slice pack: with the paraxial propagator the odd slices are transmitted in
+ * column passes, which read the transmission T - 1 = exp(i k dx (delta +
+ * i beta)) - 1 of those slices precomputed and transposed ([Ns/2][nz][ny]
+ * complex64, in the workspace) so that their accesses coalesce.  This call
+ * writes it (a no-op for the exact propagator, which needs none).  It
+ * depends on delta, beta, the wavelength and dx, not on the incidence angle
+ * or the probe. */
+msl_status msl_pack_slices(const msl_geometry* g, const float* delta, const float* beta,
+                           void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Gradient of a real loss through the multislice recurrence (reverse sweep
  * of Eq. 1 with checkpoint recomputation).
@@ -161,7 +173,7 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field,
  *   grad_delta, grad_beta  float32 [Ns][ny][nz] (either may be NULL):
  *                overwritten with dL/d delta and dL/d beta.
  *   grad_probe   NULL or complex64 [ny][nz]: cotangent of the probe.
- *   flags        0 or MSL_ADJ_REUSE_SLICE_PACK (see above); unknown bits are an error. */
+ *   flags        0 or MSL_REUSE_SLICE_PACK (see above); unknown bits are an error. */
 msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* beta,
                        const msl_c64* probe, const msl_c64* ckpt, int32_t ckpt_every,
                        const msl_c64* grad_field, float* grad_delta, float* grad_beta,

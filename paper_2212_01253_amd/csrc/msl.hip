@@ -566,9 +566,21 @@ int32_t msl_checkpoint_count(const msl_geometry* g, int32_t ckpt_every) {
   return (g->n_slices + ckpt_every - 1) / ckpt_every;
 }
 
+msl_status msl_pack_slices(const msl_geometry* g, const float* delta, const float* beta, void* workspace,
+                           size_t ws_bytes, void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  MSL_TRY(check_ptr(delta, 4, "delta"));
+  MSL_TRY(check_ptr(beta, 4, "beta"));
+  MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
+  Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
+  k.c.delta = delta;
+  k.c.beta = beta;
+  return pack_odd(k);
+}
+
 msl_status msl_forward(const msl_geometry* g, const float* delta, const float* beta, const msl_c64* probe,
-                       msl_c64* field_out, msl_c64* ckpt, int32_t ckpt_every, void* workspace, size_t ws_bytes,
-                       void* hip_stream) {
+                       msl_c64* field_out, msl_c64* ckpt, int32_t ckpt_every, uint32_t flags, void* workspace,
+                       size_t ws_bytes, void* hip_stream) {
   MSL_TRY(check_geometry(g));
   MSL_TRY(check_ptr(delta, 4, "delta"));
   MSL_TRY(check_ptr(beta, 4, "beta"));
@@ -577,6 +589,7 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   MSL_TRY(check_ptr(ckpt, 8, "ckpt", true));
   if (ckpt && ckpt_every < 1) return fail(MSL_ERR_ARG, "ckpt given but ckpt_every < 1");
   if (!ckpt && ckpt_every != 0) return fail(MSL_ERR_ARG, "ckpt_every != 0 but ckpt is NULL");
+  if (flags & ~MSL_REUSE_SLICE_PACK) return fail(MSL_ERR_ARG, "unknown msl_forward flags");
   MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
   Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
   k.c.delta = delta;
@@ -598,7 +611,11 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   ph.inplace = 1;
   ph.ckpt = reinterpret_cast<float2*>(ckpt);
   ph.ckpt_every = ckpt ? ckpt_every : 0;
-  MSL_TRY(pack_odd(k));
+  if (flags & MSL_REUSE_SLICE_PACK) {
+    if (odd_slices(*g) > 0) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
+  } else {
+    MSL_TRY(pack_odd(k));
+  }
   return run_phase(k, ph);
 }
 
@@ -667,7 +684,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   MSL_TRY(check_ptr(grad_delta, 4, "grad_delta", true));
   MSL_TRY(check_ptr(grad_beta, 4, "grad_beta", true));
   MSL_TRY(check_ptr(grad_probe, 8, "grad_probe", true));
-  if (flags & ~MSL_ADJ_REUSE_SLICE_PACK) return fail(MSL_ERR_ARG, "unknown msl_adjoint flags");
+  if (flags & ~MSL_REUSE_SLICE_PACK) return fail(MSL_ERR_ARG, "unknown msl_adjoint flags");
   MSL_TRY(check_ws(*g, ckpt_every, workspace, ws_bytes));
   Call k = make_call(*g, ckpt_every, workspace, static_cast<hipStream_t>(hip_stream));
   k.c.delta = delta;
@@ -675,7 +692,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   k.c.gdelta = grad_delta;
   k.c.gbeta = grad_beta;
   MSL_TRY(build_tables(k, true));
-  if (flags & MSL_ADJ_REUSE_SLICE_PACK) {
+  if (flags & MSL_REUSE_SLICE_PACK) {
     if (odd_slices(*g) > 0) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
   } else {
     MSL_TRY(pack_odd(k));

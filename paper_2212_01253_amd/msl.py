@@ -16,11 +16,11 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsl.so")
 
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = 0, -1, -2, -3, -4
-ADJ_REUSE_SLICE_PACK = 1
+REUSE_SLICE_PACK = 1
 PROP_PARAXIAL, PROP_EXACT = 0, 1
 SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
 
-EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_forward",
+EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_pack_slices", "msl_forward",
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
            "msl_set_schedule", "msl_last_error")
 
@@ -60,7 +60,9 @@ def lib():
     L.msl_checkpoint_count.restype = c_int32
     L.msl_checkpoint_count.argtypes = [G, c_int32]
     L.msl_forward.restype = c_int32
-    L.msl_forward.argtypes = [G, P, P, P, P, P, c_int32, P, c_size_t, P]
+    L.msl_pack_slices.restype = c_int32
+    L.msl_pack_slices.argtypes = [G, P, P, P, c_size_t, P]
+    L.msl_forward.argtypes = [G, P, P, P, P, P, c_int32, ctypes.c_uint32, P, c_size_t, P]
     L.msl_far_field.restype = c_int32
     L.msl_far_field.argtypes = [G, P, P, P, c_size_t, P]
     L.msl_amp_loss.restype = c_int32
@@ -145,8 +147,21 @@ def workspace(g, ckpt_every=0, device="cuda"):
     return ws
 
 
-def forward(g, delta, beta, probe=None, ckpt_every=0, ws=None, out=None, ckpt=None):
-    """msl_forward: returns (psi_Ns complex64 [ny, nz], checkpoints or None)."""
+def pack_slices(g, delta, beta, ws):
+    """msl_pack_slices: writes the odd slices' transmission pack into ``ws``."""
+    cg = geometry(g)
+    ny, nz, ns = cg.ny, cg.nz, cg.n_slices
+    _check(lib().msl_pack_slices(ctypes.byref(cg), _ptr(delta, torch.float32, (ns, ny, nz), "delta"),
+                                 _ptr(beta, torch.float32, (ns, ny, nz), "beta"),
+                                 ws.data_ptr(), ws.numel(), _stream()))
+
+
+def forward(g, delta, beta, probe=None, ckpt_every=0, ws=None, out=None, ckpt=None, reuse_pack=False):
+    """msl_forward: returns (psi_Ns complex64 [ny, nz], checkpoints or None).
+
+    ``reuse_pack`` may be set only when ``ws`` already holds the slice pack of
+    these delta, beta (``pack_slices`` or an earlier call on ``ws``).
+    """
     cg = geometry(g)
     ny, nz, ns = cg.ny, cg.nz, cg.n_slices
     dev = delta.device
@@ -163,7 +178,7 @@ def forward(g, delta, beta, probe=None, ckpt_every=0, ws=None, out=None, ckpt=No
         _ptr(out, torch.complex64, (ny, nz), "out"),
         _ptr(ckpt, torch.complex64, (checkpoint_count(cg, ckpt_every), ny, nz), "ckpt", True)
         if ckpt_every else None,
-        int(ckpt_every), ws.data_ptr(), ws.numel(), _stream())
+        int(ckpt_every), REUSE_SLICE_PACK if reuse_pack else 0, ws.data_ptr(), ws.numel(), _stream())
     _check(st)
     return out, (ckpt if ckpt_every else None)
 
@@ -232,7 +247,7 @@ def adjoint(g, delta, beta, ckpt, ckpt_every, grad_field, probe=None, ws=None,
         _ptr(ckpt, torch.complex64, (checkpoint_count(cg, ckpt_every), ny, nz), "ckpt"),
         int(ckpt_every), _ptr(grad_field, torch.complex64, (ny, nz), "grad_field"),
         gd.data_ptr() if want_delta else None, gb.data_ptr() if want_beta else None,
-        gp.data_ptr() if gp is not None else None, ADJ_REUSE_SLICE_PACK if reuse_pack else 0,
+        gp.data_ptr() if gp is not None else None, REUSE_SLICE_PACK if reuse_pack else 0,
         ws.data_ptr(), ws.numel(), _stream()))
     return (gd if want_delta else None), (gb if want_beta else None), gp
 

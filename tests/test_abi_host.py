@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert msl.abi_version() == 1
+    assert msl.abi_version() == 2
 
 
 def G(**kw):
@@ -49,8 +49,8 @@ def G(**kw):
 FAKE = 0x7F0000000000  # never dereferenced: validation fails first
 
 
-def fwd(L, g, delta=FAKE, beta=FAKE, probe=None, out=FAKE, ckpt=None, k=0, ws=FAKE, wsb=1 << 40):
-    return L.msl_forward(ctypes.byref(g), delta, beta, probe, out, ckpt, k, ws, wsb, None)
+def fwd(L, g, delta=FAKE, beta=FAKE, probe=None, out=FAKE, ckpt=None, k=0, ws=FAKE, wsb=1 << 40, flags=0):
+    return L.msl_forward(ctypes.byref(g), delta, beta, probe, out, ckpt, k, flags, ws, wsb, None)
 
 
 @pytest.mark.parametrize("kw", [dict(ny=15), dict(nz=2048), dict(ny=8), dict(nz=48), dict(n_slices=0),
@@ -73,6 +73,8 @@ def test_null_and_misaligned_pointers(L):
 
 def test_checkpoint_argument_rules(L):
     g = G()
+    assert fwd(L, g, flags=2) == msl.ERR_ARG
+    assert "flags" in L.msl_last_error().decode()
     assert fwd(L, g, ckpt=FAKE, k=0) == msl.ERR_ARG
     assert fwd(L, g, ckpt=None, k=4) == msl.ERR_ARG
     # the adjoint requires checkpoints
@@ -109,6 +111,9 @@ def test_checkpoint_count(L):
 
 def test_other_entry_points_validate(L):
     g = G()
+    assert L.msl_pack_slices(ctypes.byref(g), None, FAKE, FAKE, 1 << 40, None) == msl.ERR_ARG
+    assert L.msl_pack_slices(ctypes.byref(G(nz=48)), FAKE, FAKE, FAKE, 1 << 40, None) == msl.ERR_ARG
+    assert L.msl_pack_slices(ctypes.byref(g), FAKE, FAKE, FAKE, 16, None) == msl.ERR_WORKSPACE
     assert L.msl_far_field(ctypes.byref(g), None, FAKE, FAKE, 1 << 40, None) == msl.ERR_ARG
     assert L.msl_far_field(ctypes.byref(G(ny=3)), FAKE, FAKE, FAKE, 1 << 40, None) == msl.ERR_ARG
     assert L.msl_amp_loss(ctypes.byref(g), FAKE, FAKE, FAKE + 4, None, FAKE, 1 << 40, None) == msl.ERR_ARG

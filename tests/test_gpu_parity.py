@@ -200,6 +200,25 @@ def test_gradient_reusing_the_forward_slice_pack(M):
         assert np.array_equal(x, y)
 
 
+def test_forward_from_a_separate_slice_pack(M):
+    # msl_pack_slices then msl_forward(MSL_REUSE_SLICE_PACK) equals msl_forward
+    # packing by itself, bit for bit; the pack survives a forward with another
+    # probe (it depends on delta, beta, wavelength and dx only)
+    w = synth.parity_small(9)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 37})
+    D, B = dev(w.delta[:37]), dev(w.beta[:37])
+    ws = M.workspace(g, 0)
+    ref, _ = M.forward(g, D, B, ws=ws)
+    ref = ref.cpu().numpy()
+    ws2 = M.workspace(g, 0)
+    M.pack_slices(g, D, B, ws2)
+    p = dev(synth.random_field(64, 64, 3).astype(np.complex64))
+    M.forward(g, D, B, p, ws=ws2, reuse_pack=True)
+    f, _ = M.forward(g, D, B, ws=ws2, reuse_pack=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(f.cpu().numpy(), ref)
+
+
 def test_gradient_exact_propagator(M):
     w = synth.parity_small(6)
     g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 24, "propagator": 1})
