@@ -83,6 +83,24 @@ def cpu_baseline(w, meas, n_sample):
             "cpu": _cpu_model()}
 
 
+def recon_leg():
+    """Seconds from data on the GPU to the first ADAM iterate at or below 1.1 x the loss of the
+    ground truth, on the 256x256x1024 gradient workload, from the plain random initialisation."""
+    from paper_2212_01253_amd import recon, synth
+    p = recon.make_problem()
+    init = synth.random_init(p.region, 4244)
+    adam = recon.Adam()
+    L_truth, res = recon.seconds_to_threshold(p, init, adam=adam)
+    n_it = len(res.losses) - 1
+    g, r = p.geom, p.region
+    return {"secs_to_threshold": res.secs_to_threshold, "iterations": res.iters_to_threshold,
+            "ms_per_iteration": 1e3 * res.times[-1] / max(1, n_it), "loss_truth": L_truth,
+            "threshold": res.threshold, "loss_init": res.losses[0], "loss_final": res.losses[-1],
+            "init": "plain: delta ~ U[0, 3e-5) on the box", "adam_lr": adam.lr,
+            "workload": f"recon_{g.ny}x{g.nz}x{g.n_slices}: box {r['ns']}x{r['ny']}x{r['nz']} "
+                        f"(slices x rows x columns), beta = delta/20, 1e6 photons, checkpoints every 32"}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -103,6 +121,7 @@ def main():
     ap.add_argument("--slices", type=int, default=2048)
     ap.add_argument("--cpu-sample-slices", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction seconds-to-loss leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the multislice recurrence is sequential over slices and "
@@ -226,6 +245,9 @@ def main():
         "forward_throughput": {"value": vs / (fwd_path_ms / 1e3), "unit": "voxel-slice-steps/s",
                                "ms": fwd_path_ms},
     }
+    if not args.no_recon:
+        print("# reconstruction (plain init) ...", file=sys.stderr, flush=True)
+        out["recon"] = recon_leg()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, meas, args.cpu_sample_slices)

@@ -188,6 +188,46 @@ int32_t msl_set_schedule(int32_t schedule);
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* msl_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Reconstruction support [Sec. 4.1]: the paper refines a 3-D object by
+ * minimising the amplitude loss of Eq. (4) with gradients and the ADAM
+ * optimiser (Kingma and Ba, 2014).  The unknowns here are the delta values of
+ * the voxels in one box of the slice stack, with beta tied to delta by a
+ * fixed ratio (beta = beta_over_delta * delta); everything outside the box is
+ * known and left untouched. */
+
+/* Box of unknown voxels: slices [s0, s0 + ns), rows [y0, y0 + ny), columns
+ * [z0, z0 + nz) of the [n_slices][ny][nz] stack.  Parameters theta are
+ * float32 [ns][ny][nz] (row-major over the box). */
+typedef struct {
+  int32_t s0, ns, y0, ny, z0, nz;
+  float beta_over_delta;
+} msl_region;
+
+/* ADAM hyper-parameters; each updated theta is clamped to [lo, hi]. */
+typedef struct {
+  float lr, beta1, beta2, eps, lo, hi;
+} msl_adam;
+
+/* delta[box] = theta, beta[box] = beta_over_delta * theta. */
+msl_status msl_region_scatter(const msl_geometry* g, const msl_region* r, const float* theta,
+                              float* delta, float* beta, void* hip_stream);
+
+/* One ADAM step on theta from the stack gradients of the loss, then the
+ * scatter above with the new theta.  With the box gradient
+ *   gr = grad_scale * (grad_delta[box] + beta_over_delta * grad_beta[box])
+ * (grad_scale rescales a loss that was evaluated up to a constant factor)
+ * and step count t >= 1:
+ *   m = beta1 m + (1 - beta1) gr;  v = beta2 v + (1 - beta2) gr^2;
+ *   theta = clamp(theta - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps), lo, hi).
+ * theta, m, v are float32 [ns][ny][nz] (m = v = 0 before the first step);
+ * grad_delta, grad_beta as written by msl_adjoint (both required). */
+msl_status msl_region_adam_step(const msl_geometry* g, const msl_region* r, const msl_adam* a,
+                                int32_t t, float grad_scale,
+                                const float* grad_delta, const float* grad_beta,
+                                float* theta, float* m, float* v,
+                                float* delta, float* beta, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

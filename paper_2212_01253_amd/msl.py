@@ -22,7 +22,7 @@ SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
 
 EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_pack_slices", "msl_forward",
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
-           "msl_set_schedule", "msl_last_error")
+           "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step")
 
 
 class CGeometry(ctypes.Structure):
@@ -32,6 +32,20 @@ class CGeometry(ctypes.Structure):
                 ("dy_nm", c_double), ("dz_nm", c_double), ("dx_nm", c_double),
                 ("wavelength_nm", c_double), ("alpha_i_rad", c_double),
                 ("propagator", c_int32)]
+
+
+class CRegion(ctypes.Structure):
+    """Mirror of msl_region: box of unknown voxels, beta = beta_over_delta * delta."""
+
+    _fields_ = [("s0", c_int32), ("ns", c_int32), ("y0", c_int32), ("ny", c_int32),
+                ("z0", c_int32), ("nz", c_int32), ("beta_over_delta", ctypes.c_float)]
+
+
+class CAdam(ctypes.Structure):
+    """Mirror of msl_adam."""
+
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("lo", ctypes.c_float), ("hi", ctypes.c_float)]
 
 
 class MslError(RuntimeError):
@@ -75,6 +89,12 @@ def lib():
     L.msl_set_schedule.argtypes = [c_int32]
     L.msl_last_error.restype = ctypes.c_char_p
     L.msl_last_error.argtypes = []
+    R = ctypes.POINTER(CRegion)
+    L.msl_region_scatter.restype = c_int32
+    L.msl_region_scatter.argtypes = [G, R, P, P, P, P]
+    L.msl_region_adam_step.restype = c_int32
+    L.msl_region_adam_step.argtypes = [G, R, ctypes.POINTER(CAdam), c_int32, ctypes.c_float,
+                                       P, P, P, P, P, P, P, P]
     _lib = L
     return L
 
@@ -310,3 +330,39 @@ class AmpLoss(torch.autograd.Function):
     def backward(ctx, gL):
         (gI,) = ctx.saved_tensors
         return gI * gL.to(torch.float32), None, None
+
+
+# ---------------------------------------------------------------------------
+# reconstruction support
+
+def region(r) -> CRegion:
+    """msl_region from a CRegion or a mapping with s0, ns, y0, ny, z0, nz, beta_over_delta."""
+    if isinstance(r, CRegion):
+        return r
+    get = (lambda k: r[k]) if isinstance(r, dict) else (lambda k: getattr(r, k))
+    return CRegion(int(get("s0")), int(get("ns")), int(get("y0")), int(get("ny")), int(get("z0")),
+                   int(get("nz")), float(get("beta_over_delta")))
+
+
+def region_scatter(g, r, theta, delta, beta):
+    """delta[box] = theta, beta[box] = ratio * theta (in place on the stacks)."""
+    cg, cr = geometry(g), region(r)
+    stack = (cg.n_slices, cg.ny, cg.nz)
+    _check(lib().msl_region_scatter(ctypes.byref(cg), ctypes.byref(cr),
+                                    _ptr(theta, torch.float32, (cr.ns, cr.ny, cr.nz), "theta"),
+                                    _ptr(delta, torch.float32, stack, "delta"),
+                                    _ptr(beta, torch.float32, stack, "beta"), _stream()))
+
+
+def region_adam_step(g, r, adam, t, grad_delta, grad_beta, theta, m, v, delta, beta, grad_scale=1.0):
+    """One ADAM step on theta (in place, with m, v) and the scatter of the new theta."""
+    cg, cr = geometry(g), region(r)
+    stack = (cg.n_slices, cg.ny, cg.nz)
+    box = (cr.ns, cr.ny, cr.nz)
+    a = adam if isinstance(adam, CAdam) else CAdam(*[float(x) for x in adam])
+    _check(lib().msl_region_adam_step(
+        ctypes.byref(cg), ctypes.byref(cr), ctypes.byref(a), int(t), float(grad_scale),
+        _ptr(grad_delta, torch.float32, stack, "grad_delta"), _ptr(grad_beta, torch.float32, stack, "grad_beta"),
+        _ptr(theta, torch.float32, box, "theta"), _ptr(m, torch.float32, box, "m"),
+        _ptr(v, torch.float32, box, "v"), _ptr(delta, torch.float32, stack, "delta"),
+        _ptr(beta, torch.float32, stack, "beta"), _stream()))

@@ -1,0 +1,181 @@
+"""Gradient reconstruction driver (arXiv 2212.01253, Sec. 4.1).
+
+The paper refines a 3-D object by minimising the amplitude loss of Eq. (4)
+between a measured (Poisson-noised) detector image and the multislice model,
+with gradients of that loss and the ADAM optimiser.  Here the unknowns are the
+delta values of a box of voxels (beta tied to delta by a fixed ratio) over a
+known stack (the substrate), and one iteration is:
+
+    pack slices -> forward sweep (checkpoints) -> far field -> amplitude loss
+    -> [stop if the loss is at or below the threshold]
+    -> far-field adjoint -> adjoint sweep -> ADAM step on the box (+ scatter)
+
+Every step runs in libmsl's kernels through the C ABI (``msl.py``); this
+module only sequences the calls and reads the loss back once per iteration.
+
+Detector model: counts C ~ Poisson(s I_true) with the photon scale s fixed;
+the loss compares sqrt(s I) with sqrt(C), which is s times the amplitude loss
+of I against sqrt(C / s), so the library's loss is evaluated with the
+measured amplitudes sqrt(C / s) and multiplied by s (and so is its gradient).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import msl, synth
+
+
+@dataclass
+class Adam:
+    lr: float = 1e-5   # chosen once on the 256x256x1024 workload (1e-6 ... 5e-5 tried) and frozen
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-12
+    lo: float = 0.0
+    hi: float = 1e-3
+
+    def c(self):
+        return msl.CAdam(self.lr, self.beta1, self.beta2, self.eps, self.lo, self.hi)
+
+
+@dataclass
+class ReconResult:
+    losses: list = field(default_factory=list)   # detector loss after each evaluation
+    times: list = field(default_factory=list)    # seconds from start when each loss was known
+    iters_to_threshold: int | None = None        # ADAM steps taken before the first iterate at or below it
+    secs_to_threshold: float | None = None
+    threshold: float | None = None
+
+
+class Reconstructor:
+    """Holds the device state of one reconstruction (stacks, workspace, ADAM moments)."""
+
+    def __init__(self, geom, known_delta, known_beta, region, counts, scale, probe=None, ckpt_every=32,
+                 adam: Adam | None = None, device="cuda:0"):
+        self.g = msl.geometry(geom)
+        self.r = msl.region(region)
+        self.adam = adam or Adam()
+        self.k = max(1, min(int(ckpt_every), self.g.n_slices))
+        self.scale = float(scale)
+        dev = torch.device(device)
+        ny, nz, ns = self.g.ny, self.g.nz, self.g.n_slices
+        box = (self.r.ns, self.r.ny, self.r.nz)
+        self.D = torch.as_tensor(np.ascontiguousarray(known_delta, np.float32)).to(dev)
+        self.B = torch.as_tensor(np.ascontiguousarray(known_beta, np.float32)).to(dev)
+        assert tuple(self.D.shape) == (ns, ny, nz) and tuple(self.B.shape) == (ns, ny, nz)
+        amp = np.sqrt(np.asarray(counts, np.float64) / self.scale).astype(np.float32)
+        self.meas = torch.as_tensor(amp).to(dev)
+        self.probe = None if probe is None else torch.as_tensor(np.asarray(probe, np.complex64)).to(dev)
+        self.ws = msl.workspace(self.g, self.k, dev)
+        self.field = torch.empty((ny, nz), dtype=torch.complex64, device=dev)
+        self.ck = torch.empty((msl.checkpoint_count(self.g, self.k), ny, nz), dtype=torch.complex64, device=dev)
+        self.I = torch.empty((ny, nz), dtype=torch.float32, device=dev)
+        self.gpsi = torch.empty((ny, nz), dtype=torch.complex64, device=dev)
+        self.gd = torch.empty((ns, ny, nz), dtype=torch.float32, device=dev)
+        self.gb = torch.empty((ns, ny, nz), dtype=torch.float32, device=dev)
+        self.theta = torch.zeros(box, dtype=torch.float32, device=dev)
+        self.m = torch.zeros(box, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(box, dtype=torch.float32, device=dev)
+        self.t = 0
+        self._gI = None
+
+    def set_theta(self, theta):
+        """Start from theta (box values); resets the ADAM moments."""
+        self.theta.copy_(torch.as_tensor(np.ascontiguousarray(theta, np.float32)))
+        self.m.zero_()
+        self.v.zero_()
+        self.t = 0
+        msl.region_scatter(self.g, self.r, self.theta, self.D, self.B)
+
+    def loss(self):
+        """Forward model and amplitude loss of the current theta against sqrt(C / s): a device
+        float64 scalar, s times smaller than the detector loss."""
+        msl.pack_slices(self.g, self.D, self.B, self.ws)
+        msl.forward(self.g, self.D, self.B, self.probe, self.k, ws=self.ws, out=self.field, ckpt=self.ck,
+                    reuse_pack=True)
+        msl.far_field(self.g, self.field, ws=self.ws, out=self.I)
+        loss, self._gI = msl.amp_loss(self.g, self.I, self.meas, ws=self.ws)
+        return loss
+
+    def gradient_step(self):
+        """Adjoint of the last ``loss()`` and one ADAM step on theta."""
+        msl.far_field_adjoint(self.g, self.field, self._gI, ws=self.ws, out=self.gpsi)
+        msl.adjoint(self.g, self.D, self.B, self.ck, self.k, self.gpsi, probe=self.probe, ws=self.ws,
+                    gd=self.gd, gb=self.gb, want_probe=False, reuse_pack=True)
+        self.t += 1
+        msl.region_adam_step(self.g, self.r, self.adam.c(), self.t, self.gd, self.gb, self.theta, self.m,
+                             self.v, self.D, self.B, grad_scale=self.scale)
+
+    def stack_gradients(self):
+        """(dL/d delta, dL/d beta) of the last ``loss()``, for the detector loss (scaled by s
+        inside the ADAM step, not here); runs the adjoint without updating theta."""
+        msl.far_field_adjoint(self.g, self.field, self._gI, ws=self.ws, out=self.gpsi)
+        msl.adjoint(self.g, self.D, self.B, self.ck, self.k, self.gpsi, probe=self.probe, ws=self.ws,
+                    gd=self.gd, gb=self.gb, want_probe=False, reuse_pack=True)
+        return self.gd, self.gb
+
+    def run(self, theta0, max_iters, threshold=None, log_every=0):
+        """ADAM from theta0 until the loss is <= threshold or max_iters steps; wall-clock timed."""
+        res = ReconResult(threshold=threshold)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.set_theta(theta0)
+        for it in range(max_iters + 1):
+            L = float(self.loss().item()) * self.scale
+            now = time.perf_counter() - t0
+            res.losses.append(L)
+            res.times.append(now)
+            if log_every and it % log_every == 0:
+                print(f"# iter {it}: loss {L:.6g} ({now:.2f} s)", flush=True)
+            if threshold is not None and L <= threshold:
+                res.iters_to_threshold = it
+                res.secs_to_threshold = now
+                break
+            if it == max_iters:
+                break
+            self.gradient_step()
+        return res
+
+
+@dataclass
+class Problem:
+    """A reconstruction workload: what is known, the data, and the ground truth for the threshold."""
+    geom: synth.Geometry
+    region: dict
+    known_delta: np.ndarray
+    known_beta: np.ndarray
+    counts: np.ndarray
+    scale: float
+    truth: np.ndarray        # ground-truth box values (only used for the loss threshold)
+
+
+def make_problem(seed_gt=4242, seed_noise=4243, n=256, n_slices=1024, photons=1e6) -> Problem:
+    """The gradient workload: bars-on-substrate truth, unknown box = all slices and columns of the
+    n/4 rows above the substrate (beta = delta/20), Poisson data at `photons` total from the
+    model's own intensity (computed here by libmsl)."""
+    w = synth.recon_256(seed_gt, n_slices=n_slices, n=n)
+    g = w.geom
+    region = synth.pattern_region(g, n // 4, n // 4)
+    kd, kb = synth.known_stack(w, region)
+    D = torch.from_numpy(w.delta).cuda()
+    B = torch.from_numpy(w.beta).cuda()
+    f, _ = msl.forward(g, D, B)
+    I = msl.far_field(g, f).cpu().numpy()
+    del D, B
+    counts, s = synth.poisson_counts(I, photons, seed_noise)
+    return Problem(g, region, kd, kb, counts, s, synth.box_values(w, region))
+
+
+def seconds_to_threshold(p: Problem, init, factor=1.10, max_iters=5000, adam: Adam | None = None, ckpt_every=32,
+                         log_every=0):
+    """Plain reconstruction from `init`: time to the first iterate whose loss is <= factor * L(truth)."""
+    R = Reconstructor(p.geom, p.known_delta, p.known_beta, p.region, p.counts, p.scale, ckpt_every=ckpt_every,
+                      adam=adam)
+    R.set_theta(p.truth)
+    L_truth = float(R.loss().item()) * p.scale
+    res = R.run(init, max_iters, factor * L_truth, log_every=log_every)
+    return L_truth, res

@@ -191,3 +191,49 @@ def random_measured_amplitude(ny, nz, seed, scale=1.0):
     """Non-negative float32 amplitudes (a stand-in for sqrt of detector counts)."""
     rng = _rng(seed)
     return (np.abs(rng.standard_normal((ny, nz))) * scale).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# reconstruction workload inputs
+
+def pattern_region(geom: Geometry, substrate_rows: int, height: int, beta_over_delta: float = 1.0 / 20.0) -> dict:
+    """Box of unknown voxels: all slices and columns, `height` rows above the substrate."""
+    return {"s0": 0, "ns": geom.n_slices, "y0": substrate_rows, "ny": height, "z0": 0, "nz": geom.nz,
+            "beta_over_delta": beta_over_delta}
+
+
+def known_stack(w: Workload, region: dict):
+    """The workload's stacks with the unknown box zeroed (what the reconstruction knows)."""
+    d, b = w.delta.copy(), w.beta.copy()
+    ix = (slice(region["s0"], region["s0"] + region["ns"]), slice(region["y0"], region["y0"] + region["ny"]),
+          slice(region["z0"], region["z0"] + region["nz"]))
+    d[ix] = 0
+    b[ix] = 0
+    return d, b
+
+
+def box_values(w: Workload, region: dict) -> np.ndarray:
+    """Ground-truth delta on the box, float32 [ns][ny][nz]."""
+    return np.ascontiguousarray(w.delta[region["s0"]:region["s0"] + region["ns"],
+                                        region["y0"]:region["y0"] + region["ny"],
+                                        region["z0"]:region["z0"] + region["nz"]])
+
+
+def random_init(region: dict, seed: int, hi: float = 3e-5) -> np.ndarray:
+    """Plain initial guess: delta ~ U[0, hi) on the box, float32."""
+    return (_rng(seed).random((region["ns"], region["ny"], region["nz"])) * hi).astype(np.float32)
+
+
+def poisson_counts(intensity: np.ndarray, total: float, seed: int):
+    """Detector counts Poisson(s I) with s = total / sum(I); returns (counts float32, s)."""
+    I = np.asarray(intensity, np.float64)
+    s = float(total) / float(I.sum())
+    return _rng(seed).poisson(s * I).astype(np.float32), s
+
+
+def fd_voxels(region: dict, n: int, seed: int) -> np.ndarray:
+    """n distinct random voxel indices (s, y, z) inside the box."""
+    rng = _rng(seed)
+    size = region["ns"] * region["ny"] * region["nz"]
+    flat = rng.choice(size, size=n, replace=False)
+    return np.stack(np.unravel_index(flat, (region["ns"], region["ny"], region["nz"])), axis=1)

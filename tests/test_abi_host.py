@@ -125,3 +125,29 @@ def test_schedule_setter(L):
     assert msl.set_schedule(prev) == msl.SCHED_PER_PASS
     with pytest.raises(msl.MslError):
         msl.set_schedule(7)
+
+
+def test_region_entry_points_validate(L):
+    g = G(n_slices=8)
+    R = ctypes.byref
+    ok = msl.CRegion(0, 8, 2, 4, 0, 64, 0.05)
+    adam = msl.CAdam(1e-6, 0.9, 0.999, 1e-12, 0.0, 1e-3)
+    for bad in (msl.CRegion(0, 9, 2, 4, 0, 64, 0.05), msl.CRegion(-1, 2, 2, 4, 0, 64, 0.05),
+                msl.CRegion(0, 8, 62, 4, 0, 64, 0.05), msl.CRegion(0, 8, 2, 0, 0, 64, 0.05),
+                msl.CRegion(0, 8, 2, 4, 1, 64, 0.05), msl.CRegion(0, 8, 2, 4, 0, 64, float("inf"))):
+        assert L.msl_region_scatter(R(g), R(bad), FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+        assert "region" in L.msl_last_error().decode() or "beta_over_delta" in L.msl_last_error().decode()
+    assert L.msl_region_scatter(R(g), None, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_region_scatter(R(g), R(ok), FAKE + 2, FAKE, FAKE, None) == msl.ERR_ARG
+
+    def step(a=adam, t=1, scale=1.0, gd=FAKE):
+        return L.msl_region_adam_step(R(g), R(ok), R(a) if a is not None else None, t, scale, gd, FAKE, FAKE,
+                                      FAKE, FAKE, FAKE, FAKE, None)
+    assert step(t=0) == msl.ERR_ARG
+    assert step(a=None) == msl.ERR_ARG
+    assert step(a=msl.CAdam(1e-6, 1.0, 0.999, 1e-12, 0.0, 1e-3)) == msl.ERR_ARG
+    assert step(a=msl.CAdam(1e-6, 0.9, 0.999, 0.0, 0.0, 1e-3)) == msl.ERR_ARG
+    assert step(a=msl.CAdam(1e-6, 0.9, 0.999, 1e-12, 1.0, 0.0)) == msl.ERR_ARG
+    assert step(a=msl.CAdam(-1.0, 0.9, 0.999, 1e-12, 0.0, 1.0)) == msl.ERR_ARG
+    assert step(scale=float("nan")) == msl.ERR_ARG
+    assert step(gd=None) == msl.ERR_ARG
