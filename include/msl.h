@@ -189,6 +189,37 @@ int32_t msl_set_schedule(int32_t schedule);
 const char* msl_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Batched forward: many independent instances (own grid, slice count,
+ * wavelength, incidence angle, probe) in one call, each computing the Eq. (1)
+ * recurrence and its far field as msl_forward and msl_far_field do.  The line
+ * passes of all instances of one grid size that are at the same slice run as
+ * one launch, so a batch fills the GPU where one small instance cannot.
+ *
+ * Slice stacks are compact: a pool of the instance's distinct slices plus the
+ * pool index of every slice (elongated samples repeat slices for long runs
+ * along the beam; a dense stack of a large batch would not fit in memory). */
+typedef struct {
+  msl_geometry g;              /* propagator must be MSL_PROP_PARAXIAL */
+  int32_t n_pool;              /* distinct slices, >= 1 */
+  const float* pool_delta;     /* device float32 [n_pool][ny][nz] */
+  const float* pool_beta;      /* device float32 [n_pool][ny][nz] */
+  const int32_t* slice_index;  /* device int32 [n_slices]: pool slice of every slice;
+                                  values outside [0, n_pool) are clamped */
+  const msl_c64* probe;        /* device [ny][nz] entrance field, or NULL: tilted plane wave */
+  msl_c64* field_out;          /* device [ny][nz]: exit wave (also the working field) */
+  float* intensity_out;        /* device [ny][nz] fftshifted far field, or NULL */
+} msl_instance;
+
+/* Workspace bytes msl_forward_batch needs for these instances (0 if any is invalid). */
+size_t msl_batch_workspace_bytes(const msl_instance* inst, int32_t n);
+
+/* Runs every instance of the host array inst[0..n-1] (read during the call
+ * only).  Instances must not share output buffers.  Errors as above; an
+ * exact-propagator instance is MSL_ERR_UNSUPPORTED. */
+msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspace, size_t ws_bytes,
+                             void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Reconstruction support [Sec. 4.1]: the paper refines a 3-D object by
  * minimising the amplitude loss of Eq. (4) with gradients and the ADAM
  * optimiser (Kingma and Ba, 2014).  The unknowns here are the delta values of

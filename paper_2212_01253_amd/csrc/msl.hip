@@ -6,8 +6,10 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "msl.h"
 #include "msl_common.hpp"
@@ -151,20 +153,22 @@ __global__ void k_probe(int ny, int nz, double q, float2* out) {
   out[i] = make_float2((float)c, (float)s);
 }
 
-// Odd slices' transmission minus one, T - 1 = exp(i k dx (delta + i beta)) - 1
-// -> dbT[s/2][z][y] (float2), through T x T LDS tiles (T = 32, or 16 on
-// 16-wide grids); 256 threads.  Covers odd slices 2 s2 + 1, s2 in [s2b, s2e).
-// The line passes evaluate T - 1 of the other slices with the same function.
+// Slices' transmission minus one, T - 1 = exp(i k dx (delta + i beta)) - 1,
+// transposed: slice first + stride * s2 -> out[s2][z][y] (float2), through
+// T x T LDS tiles (T = 32, or 16 on 16-wide grids); 256 threads; s2 in
+// [s2b, s2e).  The odd slices of a stack (first 1, stride 2) or every slice
+// of a pool (first 0, stride 1).  The line passes evaluate T - 1 of the other
+// slices with the same function.
 template <int T>
 __global__ void __launch_bounds__(256) k_pack_odd(const float* d, const float* b, float2* out, int ny, int nz,
-                                                  int s2b, int s2e, msl::Ctx c) {
+                                                  int s2b, int s2e, int first, int stride, msl::Ctx c) {
   __shared__ float2 tile[T][T + 1];
   constexpr int R = 256 / T;  // rows of the tile per pass of the block
   const int tx = threadIdx.x % T, ty = threadIdx.x / T;
   const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
   const int64_t m = (int64_t)ny * nz;
   for (int s2 = s2b + blockIdx.z; s2 < s2e; s2 += gridDim.z) {
-    const int64_t si = (int64_t)(2 * s2 + 1) * m;
+    const int64_t si = (int64_t)(first + stride * s2) * m;
     for (int r = ty; r < T; r += R) {
       const int64_t a = si + (int64_t)(y0 + r) * nz + z0 + tx;
       tile[r][tx] = msl::transmission_m1(msl::phase_arg(d[a], c), msl::phase_arg(b[a], c));
@@ -457,10 +461,10 @@ msl_status pack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
   const unsigned gz = n < 8192 ? n : 8192;
   if (k.g.ny >= 32 && k.g.nz >= 32)
     hipLaunchKernelGGL(k_pack_odd<32>, dim3(k.g.nz / 32, k.g.ny / 32, gz), dim3(256), 0, st, k.c.delta, k.c.beta,
-                       dbT, k.g.ny, k.g.nz, s2b, s2e, k.c);
+                       dbT, k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c);
   else
     hipLaunchKernelGGL(k_pack_odd<16>, dim3(k.g.nz / 16, k.g.ny / 16, gz), dim3(256), 0, st, k.c.delta, k.c.beta,
-                       dbT, k.g.ny, k.g.nz, s2b, s2e, k.c);
+                       dbT, k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c);
   return hip_check(hipGetLastError(), "pack kernel");
 }
 
@@ -493,6 +497,128 @@ PhaseSpec blank_phase(const Call& k, int kind) {
   ph.ns = k.g.n_slices;
   ph.m = k.c.m;
   return ph;
+}
+
+// ---------------------------------------------------------------------------
+// batched forward: one launch per (grid size, slice) over every instance of
+// that grid size still in its slice loop
+
+struct BatchRec {
+  Ctx c;
+  float2* field;
+};
+
+constexpr int kRecChunk = 16;  // records per descriptor-store launch (kernel arguments < 4 KB)
+
+struct RecChunk {
+  BatchRec r[kRecChunk];
+  int n;
+};
+static_assert(sizeof(RecChunk) <= 4096, "kernel arguments are limited to 4 KB");
+
+__global__ void k_store_recs(RecChunk chunk, BatchRec* dst) {
+  if ((int)threadIdx.x < chunk.n) dst[threadIdx.x] = chunk.r[threadIdx.x];
+}
+
+// Middle forward pass (propagate, transmit slice tmpl.slice, propagate) of
+// instances recs[0 .. gridDim.x / groups_per_inst): block b handles line
+// group b mod groups_per_inst of instance b / groups_per_inst (after the
+// XCD-aware renumbering of the whole grid).
+template <int N, int AXIS>
+__global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__ recs, int groups_per_inst,
+                                                    PassDesc tmpl) {
+  __shared__ float2 lds[1152];
+  constexpr int L = msl::LinePts<N>::L;
+  const int g = threadIdx.x / L, j = threadIdx.x % L;
+  const int G = blockDim.x / L;
+  const int gb = msl::xcd_group(blockIdx.x, gridDim.x);
+  const int inst = gb / groups_per_inst;
+  const Ctx c = recs[inst].c;
+  PassDesc pd = tmpl;
+  pd.src = recs[inst].field;
+  pd.dst = recs[inst].field;
+  msl::run_line<N, AXIS, false, msl::KIND_FWD_MID>(c, pd, (gb % groups_per_inst) * G + g, j, lds + g * (N + N / 8));
+}
+
+template <int N, int AXIS>
+hipError_t launch_pass_batch_t(const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl, hipStream_t st) {
+  constexpr int L = msl::LinePts<N>::L;
+  int G = L >= 64 ? 1 : 64 / L;
+  if (G > nlines) G = nlines;
+  const int gpi = nlines / G;
+  hipLaunchKernelGGL((k_pass_batch<N, AXIS>), dim3(n_inst * gpi), dim3(L * G), 0, st, recs, gpi, tmpl);
+  return hipGetLastError();
+}
+
+template <int AXIS>
+hipError_t launch_pass_batch_axis(int n, const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl,
+                                  hipStream_t st) {
+  switch (n) {
+    case 16: return launch_pass_batch_t<16, AXIS>(recs, n_inst, nlines, tmpl, st);
+    case 32: return launch_pass_batch_t<32, AXIS>(recs, n_inst, nlines, tmpl, st);
+    case 64: return launch_pass_batch_t<64, AXIS>(recs, n_inst, nlines, tmpl, st);
+    case 128: return launch_pass_batch_t<128, AXIS>(recs, n_inst, nlines, tmpl, st);
+    case 256: return launch_pass_batch_t<256, AXIS>(recs, n_inst, nlines, tmpl, st);
+    case 512: return launch_pass_batch_t<512, AXIS>(recs, n_inst, nlines, tmpl, st);
+    case 1024: return launch_pass_batch_t<1024, AXIS>(recs, n_inst, nlines, tmpl, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Workspace of a batch: the records, then per instance its tables (twiddles,
+// propagator factors), a scratch field for the far field and the packed
+// transmissions of its pool.
+struct BatchInstLayout {
+  size_t twz_hi, twz_lo, twy_hi, twy_lo, hz_hi, hz_lo, hy_hi, hy_lo, tmp, pack;
+};
+
+struct BatchLayout {
+  size_t recs;
+  std::vector<BatchInstLayout> inst;
+  size_t total;
+};
+
+BatchLayout batch_layout(const msl_instance* inst, int n) {
+  BatchLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
+  L.recs = take((size_t)n * sizeof(BatchRec));
+  L.inst.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const msl_geometry& g = inst[i].g;
+    const size_t m = (size_t)g.ny * g.nz;
+    BatchInstLayout& b = L.inst[i];
+    b.twz_hi = take(g.nz * 8);
+    b.twz_lo = take(g.nz * 8);
+    b.twy_hi = take(g.ny * 8);
+    b.twy_lo = take(g.ny * 8);
+    b.hz_hi = take(g.nz * 8);
+    b.hz_lo = take(g.nz * 8);
+    b.hy_hi = take(g.ny * 8);
+    b.hy_lo = take(g.ny * 8);
+    b.tmp = take(m * 8);
+    b.pack = take((size_t)inst[i].n_pool * m * 8);
+  }
+  L.total = o;
+  return L;
+}
+
+msl_status check_instances(const msl_instance* inst, int n) {
+  if (!inst) return fail(MSL_ERR_ARG, "instance array is NULL");
+  if (n < 1) return fail(MSL_ERR_ARG, "instance count must be >= 1");
+  for (int i = 0; i < n; ++i) {
+    const msl_instance& x = inst[i];
+    const std::string at = "instance " + std::to_string(i) + ": ";
+    if (check_geometry(&x.g) != MSL_OK) return fail(MSL_ERR_ARG, at + g_last_error);
+    if (x.g.propagator != MSL_PROP_PARAXIAL)
+      return fail(MSL_ERR_UNSUPPORTED, at + "the batched forward runs the paraxial propagator only");
+    if (x.n_pool < 1) return fail(MSL_ERR_ARG, at + "n_pool must be >= 1");
+    if (check_ptr(x.pool_delta, 4, "pool_delta") != MSL_OK || check_ptr(x.pool_beta, 4, "pool_beta") != MSL_OK ||
+        check_ptr(x.slice_index, 4, "slice_index") != MSL_OK || check_ptr(x.probe, 8, "probe", true) != MSL_OK ||
+        check_ptr(x.field_out, 8, "field_out") != MSL_OK || check_ptr(x.intensity_out, 4, "intensity_out", true) != MSL_OK)
+      return fail(MSL_ERR_ARG, at + g_last_error);
+  }
+  return MSL_OK;
 }
 
 }  // namespace
@@ -738,6 +864,153 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     MSL_TRY(stream_after(k.st, kh.st, h->done));
   }
   if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));
+  return MSL_OK;
+}
+
+size_t msl_batch_workspace_bytes(const msl_instance* inst, int32_t n) {
+  if (check_instances(inst, n) != MSL_OK) return 0;
+  return batch_layout(inst, n).total;
+}
+
+msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspace, size_t ws_bytes,
+                             void* hip_stream) {
+  MSL_TRY(check_instances(inst, n));
+  const BatchLayout BL = batch_layout(inst, n);
+  if (!workspace) return fail(MSL_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(workspace, kAlign)) return fail(MSL_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (ws_bytes < BL.total)
+    return fail(MSL_ERR_WORKSPACE, "workspace too small: need " + std::to_string(BL.total) + " bytes, got " +
+                                       std::to_string(ws_bytes));
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  BatchRec* drecs = reinterpret_cast<BatchRec*>(ws + BL.recs);
+  // order: grouped by grid, slice count descending within a group, so the
+  // instances still in their slice loop at any pass are a prefix of the group
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const msl_geometry &ga = inst[a].g, &gb = inst[b].g;
+    if (ga.ny != gb.ny) return ga.ny < gb.ny;
+    if (ga.nz != gb.nz) return ga.nz < gb.nz;
+    return ga.n_slices > gb.n_slices;
+  });
+  // per instance: tables, probe, pool pack, record
+  std::vector<BatchRec> recs(n);
+  std::vector<PhaseSpec> phs(n);
+  for (int r = 0; r < n; ++r) {
+    const int i = order[r];
+    const msl_instance& x = inst[i];
+    const msl_geometry& g = x.g;
+    const BatchInstLayout& b = BL.inst[i];
+    auto P = [&](size_t off) { return reinterpret_cast<float2*>(ws + off); };
+    Call k{};
+    k.g = g;
+    k.ws = ws;
+    k.st = st;
+    Ctx& c = k.c;
+    c.ny = g.ny;
+    c.nz = g.nz;
+    c.m = (int64_t)g.ny * g.nz;
+    c.twz_hi = P(b.twz_hi);
+    c.twz_lo = P(b.twz_lo);
+    c.twy_hi = P(b.twy_hi);
+    c.twy_lo = P(b.twy_lo);
+    c.hz_hi = P(b.hz_hi);
+    c.hz_lo = P(b.hz_lo);
+    c.hy_hi = P(b.hy_hi);
+    c.hy_lo = P(b.hy_lo);
+    const double kdx = 2.0 * M_PI / g.wavelength_nm * g.dx_nm;
+    c.kdx_hi = (float)kdx;
+    c.kdx_lo = (float)(kdx - (double)c.kdx_hi);
+    c.inv_m = 1.0f / (float)c.m;
+    c.delta = x.pool_delta;
+    c.beta = x.pool_beta;
+    c.slice_index = x.slice_index;
+    c.n_pool = x.n_pool;
+    c.intensity = x.intensity_out;
+    const int tb = 256;
+    const double kk = 2.0 * M_PI / g.wavelength_nm;
+    hipLaunchKernelGGL(k_twiddles, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, st, g.nz, P(b.twz_hi), P(b.twz_lo));
+    hipLaunchKernelGGL(k_twiddles, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, st, g.ny, P(b.twy_hi), P(b.twy_lo));
+    hipLaunchKernelGGL(k_hpar, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, st, g.nz, g.dz_nm, g.dx_nm, kk, P(b.hz_hi),
+                       P(b.hz_lo));
+    hipLaunchKernelGGL(k_hpar, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, st, g.ny, g.dy_nm, g.dx_nm, kk, P(b.hy_hi),
+                       P(b.hy_lo));
+    MSL_TRY(hip_check(hipGetLastError(), "table kernels"));
+    float2* f = reinterpret_cast<float2*>(x.field_out);
+    if (x.probe) {
+      MSL_TRY(hip_check(hipMemcpyAsync(f, x.probe, (size_t)c.m * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync"));
+    } else {
+      const double q = kk * std::sin(g.alpha_i_rad) * g.dy_nm;
+      hipLaunchKernelGGL(k_probe, dim3((unsigned)((c.m + 255) / 256)), dim3(256), 0, st, g.ny, g.nz, q, f);
+      MSL_TRY(hip_check(hipGetLastError(), "probe kernel"));
+    }
+    float2* pack = P(b.pack);
+    const unsigned gz = x.n_pool < 8192 ? x.n_pool : 8192;
+    if (g.ny >= 32 && g.nz >= 32)
+      hipLaunchKernelGGL(k_pack_odd<32>, dim3(g.nz / 32, g.ny / 32, gz), dim3(256), 0, st, x.pool_delta, x.pool_beta,
+                         pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c);
+    else
+      hipLaunchKernelGGL(k_pack_odd<16>, dim3(g.nz / 16, g.ny / 16, gz), dim3(256), 0, st, x.pool_delta, x.pool_beta,
+                         pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c);
+    MSL_TRY(hip_check(hipGetLastError(), "pack kernel"));
+    c.dbT = pack;
+    recs[r].c = c;
+    recs[r].field = f;
+    PhaseSpec& ph = phs[r];
+    ph = PhaseSpec{};
+    ph.kind = msl::PH_FWD_FULL;
+    ph.ns = g.n_slices;
+    ph.m = c.m;
+    ph.s0 = 0;
+    ph.s1 = g.n_slices;
+    ph.field = f;
+    ph.fieldT = P(b.tmp);
+    ph.inplace = 1;
+  }
+  for (int r0 = 0; r0 < n; r0 += kRecChunk) {
+    RecChunk ch{};
+    ch.n = std::min(kRecChunk, n - r0);
+    for (int q = 0; q < ch.n; ++q) ch.r[q] = recs[r0 + q];
+    hipLaunchKernelGGL(k_store_recs, dim3(1), dim3(kRecChunk), 0, st, ch, drecs + r0);
+  }
+  MSL_TRY(hip_check(hipGetLastError(), "record store kernel"));
+  // groups of equal grid
+  for (int g0 = 0; g0 < n;) {
+    int g1 = g0 + 1;
+    while (g1 < n && inst[order[g1]].g.ny == inst[order[g0]].g.ny && inst[order[g1]].g.nz == inst[order[g0]].g.nz) ++g1;
+    const int ny = inst[order[g0]].g.ny, nz = inst[order[g0]].g.nz;
+    const int max_ns = inst[order[g0]].g.n_slices;
+    for (int r = g0; r < g1; ++r) MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(phs[r], 0), st), "pass kernel"));
+    int active = g1 - g0;  // instances with n_slices > p, a prefix of the group
+    for (int p = 1; p <= max_ns; ++p) {
+      while (active > 0 && inst[order[g0 + active - 1]].g.n_slices <= p) --active;
+      if (active > 0) {
+        const PassDesc tmpl = msl::phase_pass(phs[g0], p);
+        const hipError_t e = tmpl.axis == msl::ROW
+                                 ? launch_pass_batch_axis<msl::ROW>(nz, drecs + g0, active, ny, tmpl, st)
+                                 : launch_pass_batch_axis<msl::COL>(ny, drecs + g0, active, nz, tmpl, st);
+        MSL_TRY(hip_check(e, "batched pass kernel"));
+      }
+      // instances whose slice loop ended at p: their last propagation
+      for (int r = g0 + active; r < g1 && inst[order[r]].g.n_slices >= p; ++r)
+        if (inst[order[r]].g.n_slices == p)
+          MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(phs[r], p), st), "pass kernel"));
+    }
+    g0 = g1;
+  }
+  // far fields
+  for (int r = 0; r < n; ++r) {
+    if (!recs[r].c.intensity) continue;
+    PhaseSpec ff{};
+    ff.kind = msl::PH_FF;
+    ff.m = recs[r].c.m;
+    ff.ns = phs[r].ns;
+    ff.ff_src = recs[r].field;
+    ff.fieldT = phs[r].fieldT;
+    for (int p = 0; p < msl::phase_npasses(ff); ++p)
+      MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(ff, p), st), "far-field kernel"));
+  }
   return MSL_OK;
 }
 

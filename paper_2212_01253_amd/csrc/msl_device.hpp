@@ -66,6 +66,12 @@ struct Ctx {
   // dL/d beta) in the same layout, so column passes access both coalesced.
   const float2* dbT;                // or nullptr
   float2* gT;                       // or nullptr
+  // Compact stacks (batched forward): delta, beta and dbT hold a pool of
+  // n_pool distinct slices and slice s is pool slice slice_index[s] (device
+  // array, values clamped to the pool); dbT then holds T - 1 of every pool
+  // slice.  nullptr: slice s is stack slice s.
+  const int32_t* slice_index;
+  int32_t n_pool;
 };
 
 // ---------------------------------------------------------------------------
@@ -303,6 +309,14 @@ __device__ __forceinline__ float2 apply_tconj(float2 g, float2 tm1) {
                      __builtin_fmaf(-g.x, tm1.y, __builtin_fmaf(g.y, tm1.x, g.y)));
 }
 
+// Element offset of slice s's values in the delta / beta arrays.
+__device__ __forceinline__ int64_t slice_offset(const Ctx& c, int s) {
+  if (!c.slice_index) return (int64_t)s * c.m;
+  int u = c.slice_index[s];
+  u = u < 0 ? 0 : (u >= c.n_pool ? c.n_pool - 1 : u);
+  return (int64_t)u * c.m;
+}
+
 __device__ __forceinline__ float phase_arg(float d, const Ctx& c) {
   return __builtin_fmaf(d, c.kdx_hi, d * c.kdx_lo);
 }
@@ -398,7 +412,8 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
     if (AXIS == COL && c.dbT && (pd.slice & 1)) {
       // precomputed T - 1 (real part in dl, imaginary part in bt)
-      const float2* q = c.dbT + (int64_t)(pd.slice >> 1) * c.m + (uint32_t)line * (uint32_t)c.ny;
+      const int64_t so = c.slice_index ? slice_offset(c, pd.slice) : (int64_t)(pd.slice >> 1) * c.m;
+      const float2* q = c.dbT + so + (uint32_t)line * (uint32_t)c.ny;
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         const float2 tm = q[j + t * L];
@@ -406,8 +421,9 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
         in.bt[t] = tm.y;
       }
     } else {
-      const float* dp = c.delta + (int64_t)pd.slice * c.m;
-      const float* bp = c.beta + (int64_t)pd.slice * c.m;
+      const int64_t so = slice_offset(c, pd.slice);
+      const float* dp = c.delta + so;
+      const float* bp = c.beta + so;
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         const uint32_t a = line_addr<N, AXIS>(c, line, j + t * L);

@@ -22,7 +22,8 @@ SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
 
 EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_pack_slices", "msl_forward",
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
-           "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step")
+           "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
+           "msl_batch_workspace_bytes", "msl_forward_batch")
 
 
 class CGeometry(ctypes.Structure):
@@ -46,6 +47,14 @@ class CAdam(ctypes.Structure):
 
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("lo", ctypes.c_float), ("hi", ctypes.c_float)]
+
+
+class CInstance(ctypes.Structure):
+    """Mirror of msl_instance."""
+
+    _fields_ = [("g", CGeometry), ("n_pool", c_int32), ("pool_delta", c_void_p), ("pool_beta", c_void_p),
+                ("slice_index", c_void_p), ("probe", c_void_p), ("field_out", c_void_p),
+                ("intensity_out", c_void_p)]
 
 
 class MslError(RuntimeError):
@@ -89,6 +98,11 @@ def lib():
     L.msl_set_schedule.argtypes = [c_int32]
     L.msl_last_error.restype = ctypes.c_char_p
     L.msl_last_error.argtypes = []
+    Ip = ctypes.POINTER(CInstance)
+    L.msl_batch_workspace_bytes.restype = c_size_t
+    L.msl_batch_workspace_bytes.argtypes = [Ip, c_int32]
+    L.msl_forward_batch.restype = c_int32
+    L.msl_forward_batch.argtypes = [Ip, c_int32, P, c_size_t, P]
     R = ctypes.POINTER(CRegion)
     L.msl_region_scatter.restype = c_int32
     L.msl_region_scatter.argtypes = [G, R, P, P, P, P]
@@ -366,3 +380,43 @@ def region_adam_step(g, r, adam, t, grad_delta, grad_beta, theta, m, v, delta, b
         _ptr(theta, torch.float32, box, "theta"), _ptr(m, torch.float32, box, "m"),
         _ptr(v, torch.float32, box, "v"), _ptr(delta, torch.float32, stack, "delta"),
         _ptr(beta, torch.float32, stack, "beta"), _stream()))
+
+
+# ---------------------------------------------------------------------------
+# batched forward
+
+def _instances(items):
+    arr = (CInstance * len(items))()
+    for i, it in enumerate(items):
+        cg = geometry(it["geom"])
+        ny, nz, ns = cg.ny, cg.nz, cg.n_slices
+        npool = int(it["pool_delta"].shape[0])
+        arr[i] = CInstance(cg, npool,
+                           _ptr(it["pool_delta"], torch.float32, (npool, ny, nz), "pool_delta"),
+                           _ptr(it["pool_beta"], torch.float32, (npool, ny, nz), "pool_beta"),
+                           _ptr(it["slice_index"], torch.int32, (ns,), "slice_index"),
+                           _ptr(it.get("probe"), torch.complex64, (ny, nz), "probe", True),
+                           _ptr(it["field"], torch.complex64, (ny, nz), "field"),
+                           _ptr(it.get("intensity"), torch.float32, (ny, nz), "intensity", True))
+    return arr
+
+
+def batch_workspace(items, device=None):
+    arr = _instances(items)
+    n = int(lib().msl_batch_workspace_bytes(arr, len(items)))
+    if n == 0:
+        _check(ERR_ARG)
+    dev = device or items[0]["field"].device
+    ws = torch.empty(n + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + n]
+
+
+def forward_batch(items, ws=None):
+    """msl_forward_batch over a list of instances: dicts with geom, pool_delta, pool_beta,
+    slice_index (device int32), field (output), optional probe and intensity (output)."""
+    arr = _instances(items)
+    if ws is None:
+        ws = batch_workspace(items)
+    _check(lib().msl_forward_batch(arr, len(items), ws.data_ptr(), ws.numel(), _stream()))
+    return ws

@@ -67,27 +67,15 @@ def _fill_box(arr, x0, x1, y0, y1, z0, z1, value):
     arr[x0:x1, y0:y1, z0:z1] = value
 
 
-def bars_on_substrate(geom: Geometry, seed: int, *, substrate_rows: int,
-                      n_bars=(3, 8), bar_height=(5, 20), bar_width=(2, 16),
-                      bar_len_frac=(0.25, 1.0), n_lines=(0, 0),
-                      line_height=(2, 40), line_width=(1, 4),
-                      delta_range=None, beta_over_delta=None,
-                      bar_delta=BAR_DELTA, bar_beta=BAR_BETA,
-                      substrate=(SUBSTRATE_DELTA, SUBSTRATE_BETA)) -> Workload:
-    """Substrate slab plus seeded rectangular bars (and optional full-length lines).
-
-    Integer ranges are inclusive.  When ``delta_range`` is given every feature
-    draws its own delta uniformly in that range and beta = delta * beta_over_delta;
-    otherwise all features use (bar_delta, bar_beta).  Later features overwrite
-    earlier ones where they overlap.  Bars start at the substrate surface row.
-    """
+def _draw_features(geom: Geometry, seed: int, *, substrate_rows: int,
+                   n_bars=(3, 8), bar_height=(5, 20), bar_width=(2, 16),
+                   bar_len_frac=(0.25, 1.0), n_lines=(0, 0),
+                   line_height=(2, 40), line_width=(1, 4),
+                   delta_range=None, beta_over_delta=None,
+                   bar_delta=BAR_DELTA, bar_beta=BAR_BETA):
+    """The seeded feature list: (kind, x0, length, y0, y1, z0, width, delta, beta) boxes in draw order."""
     ny, nz, ns = geom.ny, geom.nz, geom.n_slices
     rng = _rng(seed)
-    delta = np.zeros((ns, ny, nz), np.float32)
-    beta = np.zeros((ns, ny, nz), np.float32)
-    sd, sb = substrate
-    delta[:, :substrate_rows, :] = np.float32(sd)
-    beta[:, :substrate_rows, :] = np.float32(sb)
     y_base = substrate_rows
     feats = []
 
@@ -108,8 +96,6 @@ def bars_on_substrate(geom: Geometry, seed: int, *, substrate_rows: int,
         x0 = int(rng.integers(0, ns - ln + 1))
         y1 = min(ny, y_base + h)
         d, b = feature_values()
-        _fill_box(delta, x0, x0 + ln, y_base, y1, z0, z0 + w, np.float32(d))
-        _fill_box(beta, x0, x0 + ln, y_base, y1, z0, z0 + w, np.float32(b))
         feats.append(("bar", x0, ln, y_base, y1, z0, w, d, b))
     nl = int(rng.integers(n_lines[0], n_lines[1] + 1)) if n_lines[1] > 0 else 0
     for _ in range(nl):
@@ -118,10 +104,74 @@ def bars_on_substrate(geom: Geometry, seed: int, *, substrate_rows: int,
         z0 = int(rng.integers(0, nz - w + 1))
         y1 = min(ny, y_base + h)
         d, b = feature_values()
-        _fill_box(delta, 0, ns, y_base, y1, z0, z0 + w, np.float32(d))
-        _fill_box(beta, 0, ns, y_base, y1, z0, z0 + w, np.float32(b))
         feats.append(("line", 0, ns, y_base, y1, z0, w, d, b))
+    return feats
+
+
+def _render_slice(geom, substrate_rows, substrate, feats, x):
+    """delta, beta of slice x (float32 [ny][nz]): substrate, then the features covering x in order."""
+    d = np.zeros((geom.ny, geom.nz), np.float32)
+    b = np.zeros((geom.ny, geom.nz), np.float32)
+    d[:substrate_rows] = np.float32(substrate[0])
+    b[:substrate_rows] = np.float32(substrate[1])
+    for (_, x0, ln, y0, y1, z0, w, fd, fb) in feats:
+        if x0 <= x < x0 + ln:
+            d[y0:y1, z0:z0 + w] = np.float32(fd)
+            b[y0:y1, z0:z0 + w] = np.float32(fb)
+    return d, b
+
+
+def bars_on_substrate(geom: Geometry, seed: int, *, substrate_rows: int,
+                      substrate=(SUBSTRATE_DELTA, SUBSTRATE_BETA), **kw) -> Workload:
+    """Substrate slab plus seeded rectangular bars (and optional full-length lines).
+
+    Integer ranges are inclusive.  When ``delta_range`` is given every feature
+    draws its own delta uniformly in that range and beta = delta * beta_over_delta;
+    otherwise all features use (bar_delta, bar_beta).  Later features overwrite
+    earlier ones where they overlap.  Bars start at the substrate surface row.
+    """
+    feats = _draw_features(geom, seed, substrate_rows=substrate_rows, **kw)
+    ns, ny, nz = geom.n_slices, geom.ny, geom.nz
+    delta = np.zeros((ns, ny, nz), np.float32)
+    beta = np.zeros((ns, ny, nz), np.float32)
+    delta[:, :substrate_rows, :] = np.float32(substrate[0])
+    beta[:, :substrate_rows, :] = np.float32(substrate[1])
+    for (_, x0, ln, y0, y1, z0, w, fd, fb) in feats:
+        _fill_box(delta, x0, x0 + ln, y0, y1, z0, z0 + w, np.float32(fd))
+        _fill_box(beta, x0, x0 + ln, y0, y1, z0, z0 + w, np.float32(fb))
     return Workload(geom, delta, beta, seed, "bars", {"features": feats})
+
+
+@dataclass
+class CompactStack:
+    """A slice stack as a pool of distinct slices plus the pool index of every slice."""
+    geom: Geometry
+    pool_delta: np.ndarray   # float32 [n_unique][ny][nz]
+    pool_beta: np.ndarray
+    index: np.ndarray        # int32 [n_slices]
+    seed: int
+    name: str
+
+    def dense(self):
+        return self.pool_delta[self.index], self.pool_beta[self.index]
+
+
+def compact_bars_on_substrate(geom: Geometry, seed: int, *, substrate_rows: int,
+                              substrate=(SUBSTRATE_DELTA, SUBSTRATE_BETA), **kw) -> CompactStack:
+    """The stack of ``bars_on_substrate`` (same draws) without materialising it: the features
+    are boxes along the beam, so the slice content changes only where a box starts or ends."""
+    feats = _draw_features(geom, seed, substrate_rows=substrate_rows, **kw)
+    ns = geom.n_slices
+    cuts = sorted({0, ns} | {x0 for f in feats for x0 in (f[1],)} | {f[1] + f[2] for f in feats})
+    cuts = [c for c in cuts if 0 <= c <= ns]
+    pd, pb = [], []
+    index = np.zeros(ns, np.int32)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        d, bb = _render_slice(geom, substrate_rows, substrate, feats, a)
+        index[a:b] = len(pd)
+        pd.append(d)
+        pb.append(bb)
+    return CompactStack(geom, np.stack(pd), np.stack(pb), index, seed, "bars")
 
 
 def parity_small(seed: int = 0) -> Workload:
@@ -237,3 +287,36 @@ def fd_voxels(region: dict, n: int, seed: int) -> np.ndarray:
     size = region["ns"] * region["ny"] * region["nz"]
     flat = rng.choice(size, size=n, replace=False)
     return np.stack(np.unravel_index(flat, (region["ns"], region["ny"], region["nz"])), axis=1)
+
+
+# ---------------------------------------------------------------------------
+# batched workload: many instances of the throughput generator
+
+GRID_CHOICES = (128, 256, 512, 1024)
+
+
+def batch_instance(seed: int, grids=GRID_CHOICES, ns_range=(256, 4096), alpha_deg=(0.05, 0.5),
+                   wavelength_nm=(0.08, 0.15)) -> CompactStack:
+    """One instance of the batched workload: grid N from `grids`, Ns ~ U{ns_range}, incidence and
+    wavelength uniform in their ranges, 1 nm pixels, 5 nm slices, and the throughput workload's
+    bars and lines with heights and widths scaled by N / 512 over a substrate of N/4 rows."""
+    rng = _rng(seed)
+    n = int(grids[int(rng.integers(0, len(grids)))])
+    ns = int(rng.integers(ns_range[0], ns_range[1] + 1))
+    alpha = math.radians(float(rng.uniform(*alpha_deg)))
+    lam = float(rng.uniform(*wavelength_nm))
+    g = Geometry(n, n, ns, 1.0, 1.0, 5.0, lam, alpha, 0)
+    f = n / 512.0
+    sc = lambda lo, hi: (max(1, int(round(lo * f))), max(1, int(round(hi * f))))
+    cs = compact_bars_on_substrate(g, seed + 1, substrate_rows=n // 4, n_bars=(8, 32),
+                                   bar_height=sc(2, 40), bar_width=sc(4, 64),
+                                   bar_len_frac=(1.0 / 8.0, 1.0), n_lines=(2, 8),
+                                   line_height=sc(2, 40), line_width=sc(1, 4),
+                                   delta_range=(5e-6, 3e-5), beta_over_delta=1.0 / 20.0)
+    cs.name = f"batch_{n}x{n}x{ns}"
+    return cs
+
+
+def batch_workload(n_instances: int = 96, base_seed: int = 1000, **kw):
+    """The batched workload: instances seeded base_seed + i."""
+    return [batch_instance(base_seed + i, **kw) for i in range(n_instances)]

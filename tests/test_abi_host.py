@@ -151,3 +151,26 @@ def test_region_entry_points_validate(L):
     assert step(a=msl.CAdam(-1.0, 0.9, 0.999, 1e-12, 0.0, 1.0)) == msl.ERR_ARG
     assert step(scale=float("nan")) == msl.ERR_ARG
     assert step(gd=None) == msl.ERR_ARG
+
+
+def test_batch_entry_points_validate(L):
+    def inst(**kw):
+        base = dict(g=G(n_slices=8), n_pool=3, pool_delta=FAKE, pool_beta=FAKE, slice_index=FAKE, probe=None,
+                    field_out=FAKE, intensity_out=None)
+        base.update(kw)
+        return msl.CInstance(**base)
+    arr = (msl.CInstance * 2)(inst(), inst(g=G(ny=32, nz=128, n_slices=3)))
+    need = L.msl_batch_workspace_bytes(arr, 2)
+    assert need > 0
+    assert L.msl_batch_workspace_bytes(arr, 0) == 0
+    assert L.msl_forward_batch(arr, 0, FAKE, need, None) == msl.ERR_ARG
+    assert L.msl_forward_batch(None, 1, FAKE, need, None) == msl.ERR_ARG
+    assert L.msl_forward_batch(arr, 2, FAKE, need - 1, None) == msl.ERR_WORKSPACE
+    assert L.msl_forward_batch(arr, 2, None, need, None) == msl.ERR_WORKSPACE
+    for bad, code in ((inst(g=G(propagator=1)), msl.ERR_UNSUPPORTED), (inst(n_pool=0), msl.ERR_ARG),
+                      (inst(slice_index=None), msl.ERR_ARG), (inst(field_out=FAKE + 4), msl.ERR_ARG),
+                      (inst(g=G(ny=48)), msl.ERR_ARG), (inst(intensity_out=FAKE + 2), msl.ERR_ARG)):
+        arr = (msl.CInstance * 2)(inst(), bad)
+        assert L.msl_forward_batch(arr, 2, FAKE, 1 << 40, None) == code
+        assert L.msl_last_error().decode().startswith("instance 1")
+        assert L.msl_batch_workspace_bytes(arr, 2) == 0
