@@ -101,6 +101,44 @@ def recon_leg():
                         f"(slices x rows x columns), beta = delta/20, 1e6 photons, checkpoints every 32"}
 
 
+def batch_leg(n_inst, steps=3):
+    """Batched forward (msl_forward_batch) over the batched workload: instances seeded 1000 + i,
+    grids 128..1024, 256..4096 slices, per-instance wavelength and incidence; far field included."""
+    import numpy as np
+    import torch
+    from paper_2212_01253_amd import msl, synth
+    stacks = synth.batch_workload(n_inst)
+    items = []
+    for cs in stacks:
+        g = cs.geom
+        items.append({"geom": g, "pool_delta": torch.from_numpy(cs.pool_delta).cuda(),
+                      "pool_beta": torch.from_numpy(cs.pool_beta).cuda(),
+                      "slice_index": torch.from_numpy(cs.index.astype(np.int32)).cuda(),
+                      "field": torch.empty((g.ny, g.nz), dtype=torch.complex64, device="cuda"),
+                      "intensity": torch.empty((g.ny, g.nz), dtype=torch.float32, device="cuda")})
+    ws = msl.batch_workspace(items)
+    msl.forward_batch(items, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        msl.forward_batch(items, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    vs = sum(cs.geom.ny * cs.geom.nz * cs.geom.n_slices for cs in stacks)
+    grids = {}
+    for cs in stacks:
+        grids[cs.geom.ny] = grids.get(cs.geom.ny, 0) + 1
+    return {"value": vs / (ms / 1e3), "unit": "voxel-slice-steps/s", "ms": ms, "instances": n_inst,
+            "voxel_slices": vs, "achieved_GBs": vs * FWD_BYTES / (ms / 1e3) / 1e9,
+            "frac": vs * FWD_BYTES / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "pool_slices": int(sum(cs.pool_delta.shape[0] for cs in stacks)),
+            "instances_per_grid": grids,
+            "workload": "batched forward + far field: instances seeded 1000+i, grids {128,256,512,1024}^2, "
+                        "256..4096 slices of 5 nm, wavelength U[0.08, 0.15] nm, incidence U[0.05, 0.5] deg"}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -122,6 +160,8 @@ def main():
     ap.add_argument("--cpu-sample-slices", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction seconds-to-loss leg")
+    ap.add_argument("--batch", type=int, default=0, metavar="N",
+                    help="also time the batched forward over N instances of the batched workload (96 = full)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the multislice recurrence is sequential over slices and "
@@ -245,6 +285,9 @@ def main():
         "forward_throughput": {"value": vs / (fwd_path_ms / 1e3), "unit": "voxel-slice-steps/s",
                                "ms": fwd_path_ms},
     }
+    if args.batch:
+        print(f"# batched forward ({args.batch} instances) ...", file=sys.stderr, flush=True)
+        out["batch"] = batch_leg(args.batch)
     if not args.no_recon:
         print("# reconstruction (plain init) ...", file=sys.stderr, flush=True)
         out["recon"] = recon_leg()

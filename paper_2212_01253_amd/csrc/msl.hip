@@ -359,14 +359,19 @@ msl_status build_tables(const Call& k, bool need_prop) {
 
 // Helper stream and events of one device.  The adjoint runs side work on it
 // beside the reverse sweep on the caller's stream: the segment recompute and
-// the unpacking of finished gradient slices.  Created on first use
+// the unpacking of finished gradient slices.  The batched forward runs its
+// grid-size groups side by side on the extra streams.  Created on first use
 // and kept for the life of the process (default priority, non-blocking).
 // `mu` is held while a call enqueues work that uses the helper, so calls from
 // several host threads do not interleave their event records and waits.
+constexpr int kBatchStreams = 3;  // extra streams of the batched forward (grid-size groups side by side)
+
 struct Helper {
   std::mutex mu;
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
+  hipStream_t bs[kBatchStreams] = {};
+  hipEvent_t bjoin[kBatchStreams] = {};
 };
 
 msl_status helper_for_current_device(Helper*& out) {
@@ -383,6 +388,10 @@ msl_status helper_for_current_device(Helper*& out) {
     MSL_TRY(ev(&h.fork));
     MSL_TRY(ev(&h.join));
     MSL_TRY(ev(&h.done));
+    for (int i = 0; i < kBatchStreams; ++i) {
+      MSL_TRY(hip_check(hipStreamCreateWithFlags(&h.bs[i], hipStreamNonBlocking), "hipStreamCreateWithFlags"));
+      MSL_TRY(ev(&h.bjoin[i]));
+    }
   }
   out = &h;
   return MSL_OK;
@@ -975,29 +984,49 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
     hipLaunchKernelGGL(k_store_recs, dim3(1), dim3(kRecChunk), 0, st, ch, drecs + r0);
   }
   MSL_TRY(hip_check(hipGetLastError(), "record store kernel"));
-  // groups of equal grid
+  // groups of equal grid; with several groups, each after the first runs on
+  // one of the helper's extra streams (forked from and joined back into st)
+  std::vector<std::pair<int, int>> groups;
   for (int g0 = 0; g0 < n;) {
     int g1 = g0 + 1;
     while (g1 < n && inst[order[g1]].g.ny == inst[order[g0]].g.ny && inst[order[g1]].g.nz == inst[order[g0]].g.nz) ++g1;
+    groups.push_back({g0, g1});
+    g0 = g1;
+  }
+  Helper* h = nullptr;
+  std::unique_lock<std::mutex> lock;
+  const int nextra = std::min((int)groups.size() - 1, kBatchStreams);
+  if (nextra > 0) {
+    MSL_TRY(helper_for_current_device(h));
+    lock = std::unique_lock<std::mutex>(h->mu);
+    MSL_TRY(hip_check(hipEventRecord(h->fork, st), "hipEventRecord"));
+    for (int i = 0; i < nextra; ++i) MSL_TRY(hip_check(hipStreamWaitEvent(h->bs[i], h->fork, 0), "hipStreamWaitEvent"));
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const int g0 = groups[gi].first, g1 = groups[gi].second;
+    const hipStream_t gs = gi == 0 ? st : h->bs[(gi - 1) % kBatchStreams];
     const int ny = inst[order[g0]].g.ny, nz = inst[order[g0]].g.nz;
     const int max_ns = inst[order[g0]].g.n_slices;
-    for (int r = g0; r < g1; ++r) MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(phs[r], 0), st), "pass kernel"));
+    for (int r = g0; r < g1; ++r) MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(phs[r], 0), gs), "pass kernel"));
     int active = g1 - g0;  // instances with n_slices > p, a prefix of the group
     for (int p = 1; p <= max_ns; ++p) {
       while (active > 0 && inst[order[g0 + active - 1]].g.n_slices <= p) --active;
       if (active > 0) {
         const PassDesc tmpl = msl::phase_pass(phs[g0], p);
         const hipError_t e = tmpl.axis == msl::ROW
-                                 ? launch_pass_batch_axis<msl::ROW>(nz, drecs + g0, active, ny, tmpl, st)
-                                 : launch_pass_batch_axis<msl::COL>(ny, drecs + g0, active, nz, tmpl, st);
+                                 ? launch_pass_batch_axis<msl::ROW>(nz, drecs + g0, active, ny, tmpl, gs)
+                                 : launch_pass_batch_axis<msl::COL>(ny, drecs + g0, active, nz, tmpl, gs);
         MSL_TRY(hip_check(e, "batched pass kernel"));
       }
       // instances whose slice loop ended at p: their last propagation
       for (int r = g0 + active; r < g1 && inst[order[r]].g.n_slices >= p; ++r)
         if (inst[order[r]].g.n_slices == p)
-          MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(phs[r], p), st), "pass kernel"));
+          MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(phs[r], p), gs), "pass kernel"));
     }
-    g0 = g1;
+  }
+  for (int i = 0; i < nextra; ++i) {
+    MSL_TRY(hip_check(hipEventRecord(h->bjoin[i], h->bs[i]), "hipEventRecord"));
+    MSL_TRY(hip_check(hipStreamWaitEvent(st, h->bjoin[i], 0), "hipStreamWaitEvent"));
   }
   // far fields
   for (int r = 0; r < n; ++r) {
