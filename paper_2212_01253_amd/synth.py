@@ -320,3 +320,12 @@ def batch_instance(seed: int, grids=GRID_CHOICES, ns_range=(256, 4096), alpha_de
 def batch_workload(n_instances: int = 96, base_seed: int = 1000, **kw):
     """The batched workload: instances seeded base_seed + i."""
     return [batch_instance(base_seed + i, **kw) for i in range(n_instances)]
+
+
+def gaussian_probe(geom: Geometry, waist_nm: float, center_nm: float) -> np.ndarray:
+    """Gaussian beam entering tilted by the incidence angle (the paper's Gaussian probe):
+    exp(-((y - yc) / w)^2) exp(+i k sin(alpha) (y - yc)), uniform along z; complex64 [ny][nz]."""
+    y = np.arange(geom.ny) * geom.dy_nm
+    k = 2.0 * math.pi / geom.wavelength_nm
+    p = np.exp(-((y - center_nm) / waist_nm) ** 2) * np.exp(1j * k * math.sin(geom.alpha_i_rad) * (y - center_nm))
+    return np.repeat(p[:, None], geom.nz, axis=1).astype(np.complex64)
