@@ -253,6 +253,15 @@ msl_status msl_region_scatter(const msl_geometry* g, const msl_region* r, const 
  *   theta = clamp(theta - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps), lo, hi).
  * theta, m, v are float32 [ns][ny][nz] (m = v = 0 before the first step);
  * grad_delta, grad_beta as written by msl_adjoint (both required). */
+/* Nearest-value filter [Sec. 4.1: after some epochs the paper maps every
+ * voxel parameter to the nearest refractive index of the materials present]:
+ * theta[i] = the entry of levels[0 .. n_levels) nearest to theta[i] (distances
+ * in float32; on a tie the lower index wins), then the scatter above.
+ * levels is HOST memory, 1 <= n_levels <= MSL_MAX_LEVELS. */
+#define MSL_MAX_LEVELS 16
+msl_status msl_region_snap(const msl_geometry* g, const msl_region* r, const float* levels, int32_t n_levels,
+                           float* theta, float* delta, float* beta, void* hip_stream);
+
 msl_status msl_region_adam_step(const msl_geometry* g, const msl_region* r, const msl_adam* a,
                                 int32_t t, float grad_scale,
                                 const float* grad_delta, const float* grad_beta,

@@ -124,6 +124,31 @@ def transmission(delta_s, beta_s, geom) -> np.ndarray:
                                  + 1j * np.asarray(beta_s, np.float64)))
 
 
+def transmission_exact_index(delta_s, beta_s, geom) -> np.ndarray:
+    """Slice transmission with the full projection of (1 - n^2) instead of its first order.
+
+    With n = 1 - delta + i beta, (1 - n^2) / 2 = (delta - i beta) - (delta - i beta)^2 / 2; in this
+    convention (the conjugate of Eq. 1's) T = exp(i k dx [(delta + i beta) - (delta + i beta)^2 / 2]).
+    A physics variant for comparisons, not what the library computes.
+    """
+    k = wavenumber(geom)
+    dx = float(_g(geom, "dx_nm"))
+    z = np.asarray(delta_s, np.float64) + 1j * np.asarray(beta_s, np.float64)
+    return np.exp(1j * k * dx * (z - 0.5 * z * z))
+
+
+def forward_exact_index(geom, delta, beta, probe=None):
+    """``forward`` with ``transmission_exact_index``."""
+    ns = int(_g(geom, "n_slices"))
+    H = propagator(geom)
+    psi = (tilted_probe(geom) if probe is None
+           else np.asarray(probe, np.complex128).copy())
+    for s in range(ns):
+        psi = psi * transmission_exact_index(delta[s], beta[s], geom)
+        psi = _ifft2(H * _fft2(psi))
+    return psi
+
+
 def _fft2(x):
     return sfft.fft2(x, workers=WORKERS)
 

@@ -17,6 +17,7 @@ What it computes:
   second moment estimates, bias correction, step lr * mhat / (sqrt(vhat) + eps)),
   followed by a clamp of the parameters to a box [lo, hi] (delta >= 0 is the
   physical range of an index decrement of these materials).
+* ``snap``: the paper's nearest-refractive-index filter on the parameters.
 * ``poisson_loss_scale``: the detector model of the reconstruction workload
   compares sqrt(s * I) with sqrt(counts) for the fixed photon scale s; that
   loss is s times the amplitude loss of I against sqrt(counts / s).
@@ -71,3 +72,13 @@ def adam_step(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, lo=-np
 def poisson_loss_scale(counts, scale):
     """Measured amplitudes for msl amplitude loss: sqrt(counts / s); the detector loss is s times it."""
     return np.sqrt(np.asarray(counts, np.float64) / scale)
+
+
+def snap(theta, levels):
+    """Nearest-value filter (Sec. 4.1): every parameter becomes the nearest of `levels`.
+
+    Distances are taken in float32, the precision in which the library decides; on a tie the
+    lower level index wins."""
+    t = np.asarray(theta, np.float32)[..., None]
+    lv = np.asarray(levels, np.float32)
+    return lv[np.argmin(np.abs(t - lv), axis=-1)]

@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <string>
 
 #include "msl.h"
 #include "msl_common.hpp"
@@ -38,6 +39,30 @@ __global__ void __launch_bounds__(256) k_region_scatter(Box b, float ratio, cons
     const float th = theta[i];
     delta[e] = th;
     beta[e] = ratio * th;
+  }
+}
+
+struct Levels {
+  float v[MSL_MAX_LEVELS];
+  int n;
+};
+
+__global__ void __launch_bounds__(256) k_region_snap(Box b, float ratio, Levels lv, float* __restrict__ theta,
+                                                     float* __restrict__ delta, float* __restrict__ beta) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float th = theta[i];
+    float best = lv.v[0], bd = fabsf(th - lv.v[0]);
+    for (int l = 1; l < lv.n; ++l) {
+      const float dl = fabsf(th - lv.v[l]);
+      if (dl < bd) {
+        bd = dl;
+        best = lv.v[l];
+      }
+    }
+    const int64_t e = box_to_stack(b, i);
+    theta[i] = best;
+    delta[e] = best;
+    beta[e] = ratio * best;
   }
 }
 
@@ -100,6 +125,27 @@ msl_status msl_region_scatter(const msl_geometry* g, const msl_region* r, const 
   hipLaunchKernelGGL(k_region_scatter, dim3(elementwise_blocks(b.n)), dim3(256), 0,
                      static_cast<hipStream_t>(hip_stream), b, r->beta_over_delta, theta, delta, beta);
   return hip_check(hipGetLastError(), "scatter kernel");
+}
+
+msl_status msl_region_snap(const msl_geometry* g, const msl_region* r, const float* levels, int32_t n_levels,
+                           float* theta, float* delta, float* beta, void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  Box b;
+  MSL_TRY(check_region(*g, r, b));
+  if (!levels || n_levels < 1 || n_levels > MSL_MAX_LEVELS)
+    return fail(MSL_ERR_ARG, "levels: need 1 <= n_levels <= " + std::to_string(MSL_MAX_LEVELS) + " values");
+  Levels lv{};
+  lv.n = n_levels;
+  for (int l = 0; l < n_levels; ++l) {
+    if (!std::isfinite(levels[l])) return fail(MSL_ERR_ARG, "levels must be finite");
+    lv.v[l] = levels[l];
+  }
+  MSL_TRY(check_ptr(theta, 4, "theta"));
+  MSL_TRY(check_ptr(delta, 4, "delta"));
+  MSL_TRY(check_ptr(beta, 4, "beta"));
+  hipLaunchKernelGGL(k_region_snap, dim3(elementwise_blocks(b.n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                     b, r->beta_over_delta, lv, theta, delta, beta);
+  return hip_check(hipGetLastError(), "snap kernel");
 }
 
 msl_status msl_region_adam_step(const msl_geometry* g, const msl_region* r, const msl_adam* a, int32_t t,

@@ -23,7 +23,7 @@ SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
 EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_pack_slices", "msl_forward",
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
            "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
-           "msl_batch_workspace_bytes", "msl_forward_batch")
+           "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap")
 
 
 class CGeometry(ctypes.Structure):
@@ -106,6 +106,8 @@ def lib():
     R = ctypes.POINTER(CRegion)
     L.msl_region_scatter.restype = c_int32
     L.msl_region_scatter.argtypes = [G, R, P, P, P, P]
+    L.msl_region_snap.restype = c_int32
+    L.msl_region_snap.argtypes = [G, R, ctypes.POINTER(ctypes.c_float), c_int32, P, P, P, P]
     L.msl_region_adam_step.restype = c_int32
     L.msl_region_adam_step.argtypes = [G, R, ctypes.POINTER(CAdam), c_int32, ctypes.c_float,
                                        P, P, P, P, P, P, P, P]
@@ -366,6 +368,17 @@ def region_scatter(g, r, theta, delta, beta):
                                     _ptr(theta, torch.float32, (cr.ns, cr.ny, cr.nz), "theta"),
                                     _ptr(delta, torch.float32, stack, "delta"),
                                     _ptr(beta, torch.float32, stack, "beta"), _stream()))
+
+
+def region_snap(g, r, levels, theta, delta, beta):
+    """theta <- nearest of `levels` (host floats), then the scatter into delta, beta."""
+    cg, cr = geometry(g), region(r)
+    stack = (cg.n_slices, cg.ny, cg.nz)
+    lv = (ctypes.c_float * len(levels))(*[float(x) for x in levels])
+    _check(lib().msl_region_snap(ctypes.byref(cg), ctypes.byref(cr), lv, len(levels),
+                                 _ptr(theta, torch.float32, (cr.ns, cr.ny, cr.nz), "theta"),
+                                 _ptr(delta, torch.float32, stack, "delta"),
+                                 _ptr(beta, torch.float32, stack, "beta"), _stream()))
 
 
 def region_adam_step(g, r, adam, t, grad_delta, grad_beta, theta, m, v, delta, beta, grad_scale=1.0):

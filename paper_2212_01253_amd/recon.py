@@ -118,8 +118,14 @@ class Reconstructor:
                     gd=self.gd, gb=self.gb, want_probe=False, reuse_pack=True)
         return self.gd, self.gb
 
-    def run(self, theta0, max_iters, threshold=None, log_every=0):
-        """ADAM from theta0 until the loss is <= threshold or max_iters steps; wall-clock timed."""
+    def snap(self, levels):
+        """The paper's nearest-index filter: theta <- nearest of `levels` (resets nothing else)."""
+        msl.region_snap(self.g, self.r, levels, self.theta, self.D, self.B)
+
+    def run(self, theta0, max_iters, threshold=None, log_every=0, snap_levels=None, snap_every=0):
+        """ADAM from theta0 until the loss is <= threshold or max_iters steps; wall-clock timed.
+        With snap_levels and snap_every, every snap_every-th step is followed by the
+        nearest-index filter (the paper applies it after 20 epochs)."""
         res = ReconResult(threshold=threshold)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -138,6 +144,8 @@ class Reconstructor:
             if it == max_iters:
                 break
             self.gradient_step()
+            if snap_levels is not None and snap_every and self.t % snap_every == 0:
+                self.snap(snap_levels)
         return res
 
 

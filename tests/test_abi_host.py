@@ -174,3 +174,16 @@ def test_batch_entry_points_validate(L):
         assert L.msl_forward_batch(arr, 2, FAKE, 1 << 40, None) == code
         assert L.msl_last_error().decode().startswith("instance 1")
         assert L.msl_batch_workspace_bytes(arr, 2) == 0
+
+
+def test_snap_validates(L):
+    g = G(n_slices=8)
+    ok = msl.CRegion(0, 8, 2, 4, 0, 64, 0.05)
+    lv = (ctypes.c_float * 17)(*range(17))
+    R = ctypes.byref
+    assert L.msl_region_snap(R(g), R(ok), lv, 0, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_region_snap(R(g), R(ok), lv, 17, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_region_snap(R(g), R(ok), None, 2, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    nan = (ctypes.c_float * 2)(0.0, float("nan"))
+    assert L.msl_region_snap(R(g), R(ok), nan, 2, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_region_snap(R(g), R(ok), lv, 2, FAKE + 2, FAKE, FAKE, None) == msl.ERR_ARG

@@ -138,3 +138,18 @@ def test_reconstruction_reduces_the_loss(M):
     res = R.run(init, 300, threshold=1.1 * L_ref)
     print("L0", res.losses[0], "L_truth", L_ref, "iterations", res.iters_to_threshold, "final", res.losses[-1])
     assert res.iters_to_threshold is not None and res.losses[-1] <= 1.1 * L_ref
+
+
+def test_region_snap_matches_the_oracle_bitwise(M):
+    import torch
+    rng = np.random.default_rng(9)
+    levels = [0.0, 7.6e-6, 1.5e-5, 3e-5]
+    th = rng.uniform(-1e-5, 4e-5, (5, 24, 50)).astype(np.float32)
+    D = dev(rng.random((9, 64, 64)).astype(np.float32))
+    B = dev(rng.random((9, 64, 64)).astype(np.float32))
+    T = dev(th)
+    M.region_snap(GEOM, REGION, levels, T, D, B)
+    torch.cuda.synchronize()
+    ref = RO.snap(th, levels)
+    assert np.array_equal(T.cpu().numpy(), ref)
+    assert np.array_equal(D.cpu().numpy()[RO.box_slices(REGION)], ref)

@@ -397,3 +397,23 @@ def test_far_field_adjoint_finite_differences():
     eps = 1e-6
     fd = (loss(psi + eps * dz) - loss(psi - eps * dz)) / (2 * eps)
     assert abs(fd - np.real(np.vdot(gpsi, dz))) < 1e-7 * abs(fd)
+
+
+# --- exact projection of (1 - n^2): physics variant (oracle only) ------------
+
+def test_exact_index_uniform_slab_closed_form():
+    # a uniform slab: the field is the vacuum field times exp(i k L [(d + i b) - (d + i b)^2 / 2])
+    g = geom(16, 16, 40, dx=5.0, lam=0.1, alpha=0.003)
+    d0, b0 = 3e-5, 1.5e-6
+    vac = O.forward(g, Repeat(np.zeros((16, 16))), Repeat(np.zeros((16, 16))))
+    got = O.forward_exact_index(g, Repeat(np.full((16, 16), d0)), Repeat(np.full((16, 16), b0)))
+    k, L = 2 * math.pi / 0.1, 40 * 5.0
+    z = d0 + 1j * b0
+    assert np.allclose(got, vac * np.exp(1j * k * L * (z - z * z / 2)), rtol=1e-12, atol=1e-13)
+    # against the first-order model the phase differs by k L (d^2 - b^2) / 2 (2.9e-4 rad at
+    # 2048 slices of 5 nm, d = 3e-5: beyond the 2e-5 field tolerance, hence one reading for both sides)
+    first = O.forward(g, Repeat(np.full((16, 16), d0)), Repeat(np.full((16, 16), b0)))
+    ratio = got / first
+    assert np.allclose(np.angle(ratio), -k * L * (d0 * d0 - b0 * b0) / 2, rtol=1e-9, atol=0)
+    assert np.allclose(np.abs(ratio), np.exp(k * L * d0 * b0), rtol=1e-12)
+    assert 2048 * 5.0 * k * 3e-5 ** 2 / 2 == pytest.approx(2.9e-4, rel=0.02)

@@ -98,3 +98,15 @@ def test_poisson_scale_identity():
     Ldet = np.sum((np.sqrt(s * I) - np.sqrt(C.astype(np.float64))) ** 2)
     L, _, _ = O.amp_loss(I, R.poisson_loss_scale(C, s))
     assert s * L == pytest.approx(Ldet, rel=1e-12)
+
+
+def test_snap_picks_the_nearest_level_by_brute_force():
+    rng = np.random.default_rng(8)
+    levels = [0.0, 7.6e-6, 1.5e-5, 3e-5]
+    th = rng.uniform(-1e-5, 4e-5, 500).astype(np.float32)
+    th[:4] = [3.8e-6, 1.13e-5, 2.25e-5, -0.0]   # near midpoints and zero
+    got = R.snap(th, levels)
+    for t, s in zip(th, got):
+        dists = [abs(float(np.float32(t) - np.float32(l))) for l in levels]
+        best = min(range(len(levels)), key=lambda i: (dists[i], i))
+        assert s == np.float32(levels[best])
