@@ -1,0 +1,110 @@
+/*
+ * msl_nn.h -- C ABI of the learned-initialiser kernels in libmsl.
+ *
+ * The reconstruction of arXiv 2212.01253 (Sec. 4.1) starts ADAM from an
+ * initial guess.  These kernels train and run a small convolutional network
+ * that maps a far-field log-intensity image to an initial delta cross-section
+ * (a learned initial guess; not part of the paper).  Matrix products run on
+ * the MI355X matrix cores in bfloat16 with float32 accumulation.
+ *
+ * Layouts: activations are float32 [C][B][H][W] (channel-major, so a
+ * convolution is one matrix product over all images of a batch); bfloat16
+ * values are uint16_t holding the upper half of the IEEE float32 pattern,
+ * rounded to nearest even.  All arrays are caller-owned DEVICE memory; every
+ * call only enqueues on hip_stream.  Arguments are validated on the host; on
+ * an error nothing is enqueued and msl_last_error() (msl.h) describes it.
+ */
+#ifndef MSL_NN_H
+#define MSL_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "msl.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[m][n] = beta * C[m][n] + sum_k op(A)[m][k] op(B)[k][n] (+ bias[m]) (then max(0, .) if relu).
+ * op(A)[m][k] = transA ? A[k * lda + m] : A[m * lda + k]   (bfloat16)
+ * op(B)[k][n] = transB ? B[n * ldb + k] : B[k * ldb + n]   (bfloat16)
+ * C float32 with row stride ldc; C16 (optional) receives C rounded to bfloat16 with the same
+ * stride; bias (optional) float32 [M].  M, N, K >= 1. */
+msl_status msl_nn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t transA,
+                            const uint16_t* B, int32_t ldb, int32_t transB, float* C, int32_t ldc, float beta,
+                            const float* bias, int32_t relu, uint16_t* C16, void* hip_stream);
+
+/* 3x3 patches, zero padding 1, stride 1 or 2: x float32 [C][B][H][W] ->
+ * col bfloat16 [C*9][B*Ho*Wo] with Ho = H/stride, Wo = W/stride (H, W divisible by stride);
+ * row c*9 + 3*(dy+1) + (dx+1), column (b*Ho + i)*Wo + j holds x[c][b][stride*i+dy][stride*j+dx]. */
+msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* x,
+                            uint16_t* col, void* hip_stream);
+
+/* Adjoint of msl_nn_im2col3x3: dx[c][b][y][x] = sum of the col entries that sampled it
+ * (col float32 [C*9][B*Ho*Wo]); dx is overwritten. */
+msl_status msl_nn_col2im3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* col,
+                            float* dx, void* hip_stream);
+
+/* Nearest 2x upsampling [C][B][H][W] -> [C][B][2H][2W] (y may be a channel slice of a larger
+ * array: it is written at y with the [C][B][2H][2W] layout), and its adjoint (sum of the four). */
+msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const float* x, float* y,
+                            void* hip_stream);
+msl_status msl_nn_upsample2_adjoint(int32_t C, int32_t B, int32_t H, int32_t W, const float* dy, float* dx,
+                                    void* hip_stream);
+
+/* Row pooling by f: x [B][H][W] -> y [B][H/f][W], y = mean of f consecutive rows; and its adjoint. */
+msl_status msl_nn_rowpool(int32_t B, int32_t H, int32_t W, int32_t f, const float* x, float* y, void* hip_stream);
+msl_status msl_nn_rowpool_adjoint(int32_t B, int32_t H, int32_t W, int32_t f, const float* dy, float* dx,
+                                  void* hip_stream);
+
+/* Elementwise helpers over n floats: dy[i] = y[i] > 0 ? dy[i] : 0 (ReLU backward);
+ * y[i] += x[i]; y16[i] = bfloat16(x[i]). */
+msl_status msl_nn_relu_adjoint(int64_t n, const float* y, float* dy, void* hip_stream);
+msl_status msl_nn_add(int64_t n, const float* x, float* y, void* hip_stream);
+msl_status msl_nn_to_bf16(int64_t n, const float* x, uint16_t* y16, void* hip_stream);
+
+/* out[m] = sum_n X[m * N + n] (float32 sums of float32 rows; bias gradients). */
+msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, void* hip_stream);
+
+/* Mean squared error over n values: loss_out[0] (double, device) = sum (p - t)^2 / n,
+ * grad[i] = 2 (p - t) / n (float32; may be NULL). */
+msl_status msl_nn_mse(int64_t n, const float* pred, const float* target, float* grad, double* loss_out,
+                      void* hip_stream);
+
+/* ADAM step over n float32 weights (as msl_region_adam_step, without the clamp), then the
+ * bfloat16 copy w16 of the new weights (may be NULL); t >= 1. */
+msl_status msl_nn_adam(int64_t n, float* w, const float* g, float* m, float* v, uint16_t* w16, float lr,
+                       float beta1, float beta2, float eps, int32_t t, void* hip_stream);
+
+/* out[i] = a * log(x[i] + eps) + b (float32; the network's input map of an intensity image). */
+msl_status msl_nn_logmap(int64_t n, const float* x, float eps, float a, float b, float* out, void* hip_stream);
+
+/* ---- training samples: slice pools of bars on a substrate, rendered on the device ----
+ * Sample i has nf[i] boxes (at most MSL_NN_MAX_BOXES) and np[i] pool slices.  Box f of sample
+ * i is boxes[(i * MSL_NN_MAX_BOXES + f) * 8 + 0..7] = {x0, x1, y0, y1, z0, z1, delta, beta}
+ * (slice range [x0, x1), rows [y0, y1), columns [z0, z1), as floats holding integers and the
+ * two values); pool slice u of sample i starts at slice cuts[i * MSL_NN_MAX_CUTS + u].  Pool
+ * slice u is the substrate (rows [0, substrate_rows): sub_delta, sub_beta; zero above) with
+ * every box active at its first slice written over it in order.  Pools are written at
+ * pool_delta + pool_off[i] * ny * nz (float32 [np[i]][ny][nz]; the same for pool_beta).
+ * All arrays device memory. */
+#define MSL_NN_MAX_BOXES 64
+#define MSL_NN_MAX_CUTS 132
+msl_status msl_nn_render_pools(int32_t n_samples, int32_t ny, int32_t nz, int32_t substrate_rows, float sub_delta,
+                               float sub_beta, const float* boxes, const int32_t* nf, const int32_t* cuts,
+                               const int32_t* np, const int64_t* pool_off, int32_t max_pool, float* pool_delta,
+                               float* pool_beta, void* hip_stream);
+
+/* Length-weighted mean of pool slices over a box of rows: for every sample i,
+ * out[i][r][z] = scale * sum_u w[i * MSL_NN_MAX_CUTS + u] * pool[pool_off[i] + u][y0 + r][z]
+ * for r < rows, u < np[i] (out float32 [n_samples][rows][nz]). */
+msl_status msl_nn_pool_average(int32_t n_samples, int32_t ny, int32_t nz, int32_t y0, int32_t rows,
+                               const float* w, const int32_t* np, const int64_t* pool_off, int32_t max_pool,
+                               const float* pool, float scale, float* out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSL_NN_H */

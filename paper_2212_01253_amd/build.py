@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("msl.hip", "msl_recon.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("msl.hip", "msl_recon.hip", "msl_nn.hip")]
 OUT = os.path.join(HERE, "libmsl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1,0 +1,511 @@
+// libmsl learned-initialiser kernels (C ABI in include/msl_nn.h): a bfloat16
+// matrix-core product with float32 accumulation and the data movement a small
+// convolutional network needs around it (3x3 patch extraction and its adjoint,
+// upsampling, row pooling, ReLU backward, ADAM, loss).
+//
+// The product is tiled for CDNA 64-wide wavefronts: a 256-thread workgroup
+// owns a 64 x 128 tile of C, each of its four wavefronts a 32 x 64 part as two
+// 32 x 32 accumulators of the 32x32x8 bfloat16 MFMA; tiles of A and B pass
+// through LDS with k contiguous, so every lane fetches its four k values of an
+// MFMA operand with one 8-byte read.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <algorithm>
+#include <cstdint>
+#include <string>
+
+#include "msl.h"
+#include "msl_common.hpp"
+#include "msl_nn.h"
+
+using namespace msl_host;
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// float32 -> bfloat16, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+constexpr int TM = 64, TN = 128, TK = 32, KP = TK + 4;
+
+struct GemmArgs {
+  int M, N, K, lda, transA, ldb, transB, ldc, relu;
+  float beta;
+  const uint16_t* A;
+  const uint16_t* B;
+  float* C;
+  const float* bias;
+  uint16_t* C16;
+};
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM][KP];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][KP];  // [n][k]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  f32x16 acc0 = {}, acc1 = {};
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+#pragma unroll
+    for (int r = 0; r < (TM * TK) / 256; ++r) {
+      const int e = tid + 256 * r;
+      const int mm = g.transA ? e % TM : e / TK, kk = g.transA ? e / TM : e % TK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      uint16_t val = 0;
+      if (gm < g.M && gk < g.K) val = g.A[g.transA ? (int64_t)gk * g.lda + gm : (int64_t)gm * g.lda + gk];
+      As[mm][kk] = val;
+    }
+#pragma unroll
+    for (int r = 0; r < (TN * TK) / 256; ++r) {
+      const int e = tid + 256 * r;
+      const int nn = g.transB ? e / TK : e % TN, kk = g.transB ? e % TK : e / TN;
+      const int gk = k0 + kk, gn = n0 + nn;
+      uint16_t val = 0;
+      if (gk < g.K && gn < g.N) val = g.B[g.transB ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn];
+      Bs[nn][kk] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 8) {
+      const int kq = ks + 4 * (lane >> 5);
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[wm + (lane & 31)][kq]);
+      const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&Bs[wn + (lane & 31)][kq]);
+      const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(&Bs[wn + 32 + (lane & 31)][kq]);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b1, acc1, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // accumulator element 4i + j of lane l is C[8i + 4(l / 32) + j][l % 32] of the 32 x 32 tile
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int n = n0 + wn + 32 * h + (lane & 31);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + wm + 8 * i + 4 * (lane >> 5) + j;
+        if (m < g.M && n < g.N) {
+          float v = h ? acc1[4 * i + j] : acc0[4 * i + j];
+          const int64_t o = (int64_t)m * g.ldc + n;
+          if (g.beta != 0.0f) v = __builtin_fmaf(g.beta, g.C[o], v);
+          if (g.bias) v += g.bias[m];
+          if (g.relu) v = fmaxf(v, 0.0f);
+          g.C[o] = v;
+          if (g.C16) g.C16[o] = to_bf16(v);
+        }
+      }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_im2col(int C, int B, int H, int W, int s, const float* __restrict__ x,
+                                                uint16_t* __restrict__ col) {
+  const int Ho = H / s, Wo = W / s;
+  const int64_t ncol = (int64_t)B * Ho * Wo, total = (int64_t)C * 9 * ncol;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ncol, n = e % ncol;
+    const int c = (int)(r / 9), t = (int)(r % 9), dy = t / 3 - 1, dx = t % 3 - 1;
+    const int j = (int)(n % Wo), i = (int)((n / Wo) % Ho), b = (int)(n / ((int64_t)Wo * Ho));
+    const int y = s * i + dy, xx = s * j + dx;
+    float v = 0.0f;
+    if (y >= 0 && y < H && xx >= 0 && xx < W) v = x[(((int64_t)c * B + b) * H + y) * W + xx];
+    col[e] = to_bf16(v);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_col2im(int C, int B, int H, int W, int s, const float* __restrict__ col,
+                                                float* __restrict__ dx) {
+  const int Ho = H / s, Wo = W / s;
+  const int64_t ncol = (int64_t)B * Ho * Wo, total = (int64_t)C * B * H * W;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int xx = (int)(e % W), y = (int)((e / W) % H), b = (int)((e / ((int64_t)W * H)) % B);
+    const int c = (int)(e / ((int64_t)W * H * B));
+    float acc = 0.0f;
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3 - 1, dxx = t % 3 - 1;
+      const int yi = y - dy, xj = xx - dxx;
+      if (yi < 0 || xj < 0 || yi % s || xj % s) continue;
+      const int i = yi / s, j = xj / s;
+      if (i >= Ho || j >= Wo) continue;
+      acc += col[((int64_t)c * 9 + t) * ncol + ((int64_t)b * Ho + i) * Wo + j];
+    }
+    dx[e] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_upsample2(int64_t total, int H, int W, const float* __restrict__ x,
+                                                   float* __restrict__ y) {
+  // total = C * B * (2H) * (2W) output elements
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int X = (int)(e % (2 * W)), Y = (int)((e / (2 * W)) % (2 * H));
+    const int64_t cb = e / ((int64_t)4 * H * W);
+    y[e] = x[(cb * H + Y / 2) * W + X / 2];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_upsample2_adj(int64_t total, int H, int W, const float* __restrict__ dy,
+                                                       float* __restrict__ dx) {
+  // total = C * B * H * W input elements
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % W), i = (int)((e / W) % H);
+    const int64_t cb = e / ((int64_t)H * W);
+    const float* p = dy + (cb * 2 * H + 2 * i) * (2 * W) + 2 * j;
+    dx[e] = (p[0] + p[1]) + (p[2 * W] + p[2 * W + 1]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rowpool(int64_t total, int H, int W, int f, const float* __restrict__ x,
+                                                 float* __restrict__ y) {
+  const int Hp = H / f;
+  const float inv = 1.0f / (float)f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int w = (int)(e % W), r = (int)((e / W) % Hp);
+    const int64_t b = e / ((int64_t)W * Hp);
+    float acc = 0.0f;
+    for (int q = 0; q < f; ++q) acc += x[(b * H + (int64_t)f * r + q) * W + w];
+    y[e] = acc * inv;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rowpool_adj(int64_t total, int H, int W, int f, const float* __restrict__ dy,
+                                                     float* __restrict__ dx) {
+  const int Hp = H / f;
+  const float inv = 1.0f / (float)f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int w = (int)(e % W), Y = (int)((e / W) % H);
+    const int64_t b = e / ((int64_t)W * H);
+    dx[e] = dy[(b * Hp + Y / f) * W + w] * inv;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_relu_adj(int64_t n, const float* __restrict__ y, float* __restrict__ dy) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    if (!(y[e] > 0.0f)) dy[e] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_add(int64_t n, const float* __restrict__ x, float* __restrict__ y) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    y[e] += x[e];
+}
+
+__global__ void __launch_bounds__(256) k_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = to_bf16(x[e]);
+}
+
+// one workgroup per row; fixed summation order (deterministic)
+__global__ void __launch_bounds__(256) k_rowsum(int N, const float* __restrict__ X, float* __restrict__ out) {
+  __shared__ float red[256];
+  const float* row = X + (int64_t)blockIdx.x * N;
+  float acc = 0.0f;
+  for (int n = threadIdx.x; n < N; n += 256) acc += row[n];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// one workgroup; FP64 sum in a fixed order
+__global__ void __launch_bounds__(1024) k_mse(int64_t n, const float* __restrict__ p, const float* __restrict__ t,
+                                              float* __restrict__ grad, double* __restrict__ loss) {
+  __shared__ double red[1024];
+  const double inv = 1.0 / (double)n;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += 1024) {
+    const double d = (double)p[e] - (double)t[e];
+    acc += d * d;
+    if (grad) grad[e] = (float)(2.0 * d * inv);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = red[0] * inv;
+}
+
+__global__ void __launch_bounds__(256) k_adam_flat(int64_t n, float* __restrict__ w, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v,
+                                                   uint16_t* __restrict__ w16, float lr, float b1, float b2,
+                                                   float eps, float c1, float c2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[e];
+    const float mi = __builtin_fmaf(b1, m[e], (1.0f - b1) * gi);
+    const float vi = __builtin_fmaf(b2, v[e], (1.0f - b2) * (gi * gi));
+    const float wi = w[e] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    m[e] = mi;
+    v[e] = vi;
+    w[e] = wi;
+    if (w16) w16[e] = to_bf16(wi);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_logmap(int64_t n, const float* __restrict__ x, float eps, float a, float b,
+                                                float* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = __builtin_fmaf(a, logf(x[e] + eps), b);
+}
+
+// grid: x = row-column blocks of one slice, y = pool slice, z = sample
+__global__ void __launch_bounds__(256) k_render(int ny, int nz, int sub_rows, float sub_d, float sub_b,
+                                                const float* __restrict__ boxes, const int32_t* __restrict__ nf,
+                                                const int32_t* __restrict__ cuts, const int32_t* __restrict__ np,
+                                                const int64_t* __restrict__ off, float* __restrict__ pd,
+                                                float* __restrict__ pb) {
+  const int i = blockIdx.z, u = blockIdx.y;
+  if (u >= np[i]) return;
+  const int64_t m = (int64_t)ny * nz;
+  const float x = (float)cuts[i * MSL_NN_MAX_CUTS + u];
+  const float* bx = boxes + (int64_t)i * MSL_NN_MAX_BOXES * 8;
+  const int nb = nf[i];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const float y = (float)(e / nz), z = (float)(e % nz);
+    float d = y < (float)sub_rows ? sub_d : 0.0f, b = y < (float)sub_rows ? sub_b : 0.0f;
+    for (int f = 0; f < nb; ++f) {
+      const float* q = bx + 8 * f;
+      if (x >= q[0] && x < q[1] && y >= q[2] && y < q[3] && z >= q[4] && z < q[5]) {
+        d = q[6];
+        b = q[7];
+      }
+    }
+    const int64_t o = (off[i] + u) * m + e;
+    pd[o] = d;
+    pb[o] = b;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pool_average(int ny, int nz, int y0, int rows, const float* __restrict__ w,
+                                                      const int32_t* __restrict__ np, const int64_t* __restrict__ off,
+                                                      const float* __restrict__ pool, float scale,
+                                                      float* __restrict__ out) {
+  const int i = blockIdx.y;
+  const int64_t m = (int64_t)ny * nz, n = (int64_t)rows * nz;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t src = (int64_t)(y0 + e / nz) * nz + e % nz;
+    float acc = 0.0f;
+    for (int u = 0; u < np[i]; ++u) acc = __builtin_fmaf(w[i * MSL_NN_MAX_CUTS + u], pool[(off[i] + u) * m + src], acc);
+    out[(int64_t)i * n + e] = scale * acc;
+  }
+}
+
+unsigned blocks_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 65536 ? b : 65536);
+}
+
+msl_status need(bool ok, const char* what) { return ok ? MSL_OK : fail(MSL_ERR_ARG, what); }
+
+msl_status launched(const char* what) { return hip_check(hipGetLastError(), what); }
+
+}  // namespace
+
+extern "C" {
+
+msl_status msl_nn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t transA,
+                            const uint16_t* B, int32_t ldb, int32_t transB, float* C, int32_t ldc, float beta,
+                            const float* bias, int32_t relu, uint16_t* C16, void* hip_stream) {
+  MSL_TRY(need(M >= 1 && N >= 1 && K >= 1, "gemm: M, N, K must be >= 1"));
+  MSL_TRY(need(lda >= (transA ? M : K) && ldb >= (transB ? K : N) && ldc >= N, "gemm: leading dimension too small"));
+  MSL_TRY(need(std::isfinite(beta), "gemm: beta must be finite"));
+  MSL_TRY(check_ptr(A, 2, "A"));
+  MSL_TRY(check_ptr(B, 2, "B"));
+  MSL_TRY(check_ptr(C, 4, "C"));
+  MSL_TRY(check_ptr(bias, 4, "bias", true));
+  MSL_TRY(check_ptr(C16, 2, "C16", true));
+  GemmArgs g{M, N, K, lda, transA ? 1 : 0, ldb, transB ? 1 : 0, ldc, relu ? 1 : 0, beta, A, B, C, bias, C16};
+  const dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM);
+  MSL_TRY(need(grid.y <= 65535, "gemm: M too large"));
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, static_cast<hipStream_t>(hip_stream), g);
+  return launched("gemm kernel");
+}
+
+msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* x,
+                            uint16_t* col, void* hip_stream) {
+  MSL_TRY(need(C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
+                   W % stride == 0, "im2col: need C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(col, 2, "col"));
+  const int64_t total = (int64_t)C * 9 * B * (H / stride) * (W / stride);
+  hipLaunchKernelGGL(k_im2col, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), C, B, H, W,
+                     stride, x, col);
+  return launched("im2col kernel");
+}
+
+msl_status msl_nn_col2im3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* col, float* dx,
+                            void* hip_stream) {
+  MSL_TRY(need(C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
+                   W % stride == 0, "col2im: need C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
+  MSL_TRY(check_ptr(col, 4, "col"));
+  MSL_TRY(check_ptr(dx, 4, "dx"));
+  const int64_t total = (int64_t)C * B * H * W;
+  hipLaunchKernelGGL(k_col2im, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), C, B, H, W,
+                     stride, col, dx);
+  return launched("col2im kernel");
+}
+
+msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const float* x, float* y, void* hip_stream) {
+  MSL_TRY(need(C >= 1 && B >= 1 && H >= 1 && W >= 1, "upsample: sizes must be >= 1"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(y, 4, "y"));
+  const int64_t total = (int64_t)C * B * 4 * H * W;
+  hipLaunchKernelGGL(k_upsample2, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), total, H,
+                     W, x, y);
+  return launched("upsample kernel");
+}
+
+msl_status msl_nn_upsample2_adjoint(int32_t C, int32_t B, int32_t H, int32_t W, const float* dy, float* dx,
+                                    void* hip_stream) {
+  MSL_TRY(need(C >= 1 && B >= 1 && H >= 1 && W >= 1, "upsample adjoint: sizes must be >= 1"));
+  MSL_TRY(check_ptr(dy, 4, "dy"));
+  MSL_TRY(check_ptr(dx, 4, "dx"));
+  const int64_t total = (int64_t)C * B * H * W;
+  hipLaunchKernelGGL(k_upsample2_adj, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                     total, H, W, dy, dx);
+  return launched("upsample adjoint kernel");
+}
+
+msl_status msl_nn_rowpool(int32_t B, int32_t H, int32_t W, int32_t f, const float* x, float* y, void* hip_stream) {
+  MSL_TRY(need(B >= 1 && H >= 1 && W >= 1 && f >= 1 && H % f == 0, "rowpool: need f dividing H"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(y, 4, "y"));
+  const int64_t total = (int64_t)B * (H / f) * W;
+  hipLaunchKernelGGL(k_rowpool, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), total, H,
+                     W, f, x, y);
+  return launched("rowpool kernel");
+}
+
+msl_status msl_nn_rowpool_adjoint(int32_t B, int32_t H, int32_t W, int32_t f, const float* dy, float* dx,
+                                  void* hip_stream) {
+  MSL_TRY(need(B >= 1 && H >= 1 && W >= 1 && f >= 1 && H % f == 0, "rowpool adjoint: need f dividing H"));
+  MSL_TRY(check_ptr(dy, 4, "dy"));
+  MSL_TRY(check_ptr(dx, 4, "dx"));
+  const int64_t total = (int64_t)B * H * W;
+  hipLaunchKernelGGL(k_rowpool_adj, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), total,
+                     H, W, f, dy, dx);
+  return launched("rowpool adjoint kernel");
+}
+
+msl_status msl_nn_relu_adjoint(int64_t n, const float* y, float* dy, void* hip_stream) {
+  MSL_TRY(need(n >= 1, "relu adjoint: n must be >= 1"));
+  MSL_TRY(check_ptr(y, 4, "y"));
+  MSL_TRY(check_ptr(dy, 4, "dy"));
+  hipLaunchKernelGGL(k_relu_adj, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, y, dy);
+  return launched("relu adjoint kernel");
+}
+
+msl_status msl_nn_add(int64_t n, const float* x, float* y, void* hip_stream) {
+  MSL_TRY(need(n >= 1, "add: n must be >= 1"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(y, 4, "y"));
+  hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, x, y);
+  return launched("add kernel");
+}
+
+msl_status msl_nn_to_bf16(int64_t n, const float* x, uint16_t* y16, void* hip_stream) {
+  MSL_TRY(need(n >= 1, "to_bf16: n must be >= 1"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(y16, 2, "y16"));
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, x, y16);
+  return launched("bf16 conversion kernel");
+}
+
+msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, void* hip_stream) {
+  MSL_TRY(need(M >= 1 && N >= 1, "rowsum: M, N must be >= 1"));
+  MSL_TRY(check_ptr(X, 4, "X"));
+  MSL_TRY(check_ptr(out, 4, "out"));
+  hipLaunchKernelGGL(k_rowsum, dim3(M), dim3(256), 0, static_cast<hipStream_t>(hip_stream), N, X, out);
+  return launched("rowsum kernel");
+}
+
+msl_status msl_nn_mse(int64_t n, const float* pred, const float* target, float* grad, double* loss_out,
+                      void* hip_stream) {
+  MSL_TRY(need(n >= 1, "mse: n must be >= 1"));
+  MSL_TRY(check_ptr(pred, 4, "pred"));
+  MSL_TRY(check_ptr(target, 4, "target"));
+  MSL_TRY(check_ptr(grad, 4, "grad", true));
+  MSL_TRY(check_ptr(loss_out, 8, "loss_out"));
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(hip_stream), n, pred, target, grad,
+                     loss_out);
+  return launched("mse kernel");
+}
+
+msl_status msl_nn_adam(int64_t n, float* w, const float* g, float* m, float* v, uint16_t* w16, float lr, float beta1,
+                       float beta2, float eps, int32_t t, void* hip_stream) {
+  MSL_TRY(need(n >= 1 && t >= 1, "adam: need n >= 1 and t >= 1"));
+  MSL_TRY(need(std::isfinite(lr) && lr >= 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 &&
+                   std::isfinite(eps) && eps > 0,
+               "adam: need lr >= 0, 0 <= beta1, beta2 < 1, eps > 0"));
+  MSL_TRY(check_ptr(w, 4, "w"));
+  MSL_TRY(check_ptr(g, 4, "g"));
+  MSL_TRY(check_ptr(m, 4, "m"));
+  MSL_TRY(check_ptr(v, 4, "v"));
+  MSL_TRY(check_ptr(w16, 2, "w16", true));
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)t)));
+  hipLaunchKernelGGL(k_adam_flat, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, w, g, m,
+                     v, w16, lr, beta1, beta2, eps, c1, c2);
+  return launched("adam kernel");
+}
+
+msl_status msl_nn_logmap(int64_t n, const float* x, float eps, float a, float b, float* out, void* hip_stream) {
+  MSL_TRY(need(n >= 1 && std::isfinite(eps) && eps > 0 && std::isfinite(a) && std::isfinite(b),
+               "logmap: need n >= 1, eps > 0, finite a, b"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(out, 4, "out"));
+  hipLaunchKernelGGL(k_logmap, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, x, eps, a, b,
+                     out);
+  return launched("logmap kernel");
+}
+
+msl_status msl_nn_render_pools(int32_t n_samples, int32_t ny, int32_t nz, int32_t substrate_rows, float sub_delta,
+                               float sub_beta, const float* boxes, const int32_t* nf, const int32_t* cuts,
+                               const int32_t* np, const int64_t* pool_off, int32_t max_pool, float* pool_delta,
+                               float* pool_beta, void* hip_stream) {
+  MSL_TRY(need(n_samples >= 1 && n_samples <= 65535 && ny >= 1 && nz >= 1 && max_pool >= 1 &&
+                   max_pool <= MSL_NN_MAX_CUTS - 1 && substrate_rows >= 0,
+               "render: need 1 <= n_samples <= 65535, sizes >= 1, 1 <= max_pool < MSL_NN_MAX_CUTS"));
+  MSL_TRY(check_ptr(boxes, 4, "boxes"));
+  MSL_TRY(check_ptr(nf, 4, "nf"));
+  MSL_TRY(check_ptr(cuts, 4, "cuts"));
+  MSL_TRY(check_ptr(np, 4, "np"));
+  MSL_TRY(check_ptr(pool_off, 8, "pool_off"));
+  MSL_TRY(check_ptr(pool_delta, 4, "pool_delta"));
+  MSL_TRY(check_ptr(pool_beta, 4, "pool_beta"));
+  const int64_t m = (int64_t)ny * nz;
+  const unsigned bx = (unsigned)std::min<int64_t>((m + 255) / 256, 256);
+  hipLaunchKernelGGL(k_render, dim3(bx, max_pool, n_samples), dim3(256), 0, static_cast<hipStream_t>(hip_stream), ny,
+                     nz, substrate_rows, sub_delta, sub_beta, boxes, nf, cuts, np, pool_off, pool_delta, pool_beta);
+  return launched("render kernel");
+}
+
+msl_status msl_nn_pool_average(int32_t n_samples, int32_t ny, int32_t nz, int32_t y0, int32_t rows, const float* w,
+                               const int32_t* np, const int64_t* pool_off, int32_t max_pool, const float* pool,
+                               float scale, float* out, void* hip_stream) {
+  MSL_TRY(need(n_samples >= 1 && n_samples <= 65535 && ny >= 1 && nz >= 1 && rows >= 1 && y0 >= 0 && y0 + rows <= ny &&
+                   max_pool >= 1 && max_pool <= MSL_NN_MAX_CUTS - 1,
+               "pool average: need 1 <= n_samples <= 65535, rows inside the grid"));
+  MSL_TRY(check_ptr(w, 4, "w"));
+  MSL_TRY(check_ptr(np, 4, "np"));
+  MSL_TRY(check_ptr(pool_off, 8, "pool_off"));
+  MSL_TRY(check_ptr(pool, 4, "pool"));
+  MSL_TRY(check_ptr(out, 4, "out"));
+  const int64_t n = (int64_t)rows * nz;
+  const unsigned bx = (unsigned)std::min<int64_t>((n + 255) / 256, 256);
+  hipLaunchKernelGGL(k_pool_average, dim3(bx, n_samples), dim3(256), 0, static_cast<hipStream_t>(hip_stream), ny, nz,
+                     y0, rows, w, np, pool_off, pool, scale, out);
+  return launched("pool average kernel");
+}
+
+}  // extern "C"

@@ -329,3 +329,32 @@ def gaussian_probe(geom: Geometry, waist_nm: float, center_nm: float) -> np.ndar
     k = 2.0 * math.pi / geom.wavelength_nm
     p = np.exp(-((y - center_nm) / waist_nm) ** 2) * np.exp(1j * k * math.sin(geom.alpha_i_rad) * (y - center_nm))
     return np.repeat(p[:, None], geom.nz, axis=1).astype(np.complex64)
+
+
+def bar_boxes(geom: Geometry, seed: int, *, substrate_rows: int, **kw):
+    """The feature boxes of ``compact_bars_on_substrate`` (same draws) without rendering:
+    (boxes float32 [nf][8] = x0, x1, y0, y1, z0, z1, delta, beta; cuts int32 [n_pool + 1],
+    pool slice u covering slices [cuts[u], cuts[u + 1]))."""
+    feats = _draw_features(geom, seed, substrate_rows=substrate_rows, **kw)
+    ns = geom.n_slices
+    cuts = sorted({0, ns} | {f[1] for f in feats} | {f[1] + f[2] for f in feats})
+    cuts = [c for c in cuts if 0 <= c <= ns]
+    boxes = np.array([[x0, x0 + ln, y0, y1, z0, z0 + w, d, b] for (_, x0, ln, y0, y1, z0, w, d, b) in feats],
+                     np.float32).reshape(-1, 8)
+    return boxes, np.array(cuts, np.int32)
+
+
+def training_sample(seed: int, n: int = 256, n_slices: int = 1024, alpha_deg=(0.1, 0.4)):
+    """One training sample of the learned initialiser: a throughput-style bars-and-lines sample on an
+    n x n grid (heights and widths scaled by n / 512, substrate n / 4 rows, 5 nm slices, 0.1 nm) at a
+    random incidence in alpha_deg; returns (geometry, boxes, cuts)."""
+    rng = _rng(seed)
+    alpha = math.radians(float(rng.uniform(*alpha_deg)))
+    g = Geometry(n, n, n_slices, 1.0, 1.0, 5.0, 0.1, alpha, 0)
+    f = n / 512.0
+    sc = lambda lo, hi: (max(1, int(round(lo * f))), max(1, int(round(hi * f))))
+    boxes, cuts = bar_boxes(g, seed + 1, substrate_rows=n // 4, n_bars=(8, 32), bar_height=sc(2, 40),
+                            bar_width=sc(4, 64), bar_len_frac=(1.0 / 8.0, 1.0), n_lines=(2, 8),
+                            line_height=sc(2, 40), line_width=sc(1, 4), delta_range=(5e-6, 3e-5),
+                            beta_over_delta=1.0 / 20.0)
+    return g, boxes, cuts

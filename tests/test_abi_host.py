@@ -17,9 +17,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "msl.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(msl_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(msl_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +36,9 @@ def test_exports_every_declared_symbol(L):
     assert len(names) >= 9
     for n in names:
         assert hasattr(L, n), n
-    assert set(names) == set(msl.EXPORTS)
+    from paper_2212_01253_amd import nn
+    assert set(names) == set(msl.EXPORTS) | set(nn.EXPORTS)
+    nn.lib()   # every binding signature resolves
 
 
 def test_abi_version(L):
@@ -187,3 +193,17 @@ def test_snap_validates(L):
     nan = (ctypes.c_float * 2)(0.0, float("nan"))
     assert L.msl_region_snap(R(g), R(ok), nan, 2, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
     assert L.msl_region_snap(R(g), R(ok), lv, 2, FAKE + 2, FAKE, FAKE, None) == msl.ERR_ARG
+
+
+def test_nn_entry_points_validate(L):
+    from paper_2212_01253_amd import nn
+    N = nn.lib()
+    assert N.msl_nn_gemm_bf16(0, 4, 4, FAKE, 4, 0, FAKE, 4, 0, FAKE, 4, 0.0, None, 0, None, None) == msl.ERR_ARG
+    assert N.msl_nn_gemm_bf16(4, 4, 4, FAKE, 3, 0, FAKE, 4, 0, FAKE, 4, 0.0, None, 0, None, None) == msl.ERR_ARG
+    assert N.msl_nn_gemm_bf16(4, 4, 4, FAKE + 1, 4, 0, FAKE, 4, 0, FAKE, 4, 0.0, None, 0, None, None) == msl.ERR_ARG
+    assert N.msl_nn_im2col3x3(2, 1, 5, 4, 2, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_im2col3x3(2, 1, 4, 4, 3, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_rowpool(1, 10, 4, 4, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_adam(8, FAKE, FAKE, FAKE, FAKE, None, 1e-3, 1.0, 0.999, 1e-8, 1, None) == msl.ERR_ARG
+    assert N.msl_nn_adam(8, FAKE, FAKE, FAKE, FAKE, None, 1e-3, 0.9, 0.999, 1e-8, 0, None) == msl.ERR_ARG
+    assert N.msl_nn_mse(0, FAKE, FAKE, None, FAKE, None) == msl.ERR_ARG

@@ -1,0 +1,209 @@
+"""GPU parity of the learned-initialiser kernels and network against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as N
+from oracle import recon_oracle as RO
+from paper_2212_01253_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_01253_amd import nn
+    nn.lib()
+    return nn
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def bf16_bits(x):
+    """bfloat16 bit patterns (int16) of values that are already bfloat16-representable."""
+    f = np.ascontiguousarray(np.asarray(x, np.float32))
+    return (f.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_matches_float64_products(T, ta, tb):
+    import torch
+    rng = np.random.default_rng(1)
+    M, Nn, K = 70, 130, 45
+    a = N.bf16(rng.standard_normal((M, K)))
+    b = N.bf16(rng.standard_normal((K, Nn)))
+    A = a.T.copy() if ta else a
+    Bm = b.T.copy() if tb else b
+    bias = rng.standard_normal(M).astype(np.float32)
+    C0 = rng.standard_normal((M, Nn)).astype(np.float32)
+    C = dev(C0)
+    C16 = torch.zeros((M, Nn), dtype=torch.int16, device="cuda")
+    T.gemm(M, Nn, K, dev(bf16_bits(A)), A.shape[1], ta, dev(bf16_bits(Bm)), Bm.shape[1], tb, C, Nn,
+           beta=0.5, bias=dev(bias), relu=True, C16=C16)
+    torch.cuda.synchronize()
+    ref = np.maximum(a @ b + 0.5 * C0 + bias[:, None], 0)
+    scale = np.abs(a) @ np.abs(b) + 1.0
+    got = C.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 4e-6 * scale)
+    g16 = C16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    assert np.array_equal(g16.view(np.float32), N.bf16(got).astype(np.float32))
+
+
+@pytest.mark.parametrize("s", [1, 2])
+def test_convolution_through_patches_matches_the_oracle(T, s):
+    import torch
+    rng = np.random.default_rng(2)
+    C, B, H, W, O = 5, 2, 12, 8, 7
+    x = rng.standard_normal((C, B, H, W)).astype(np.float32)
+    w = rng.standard_normal((O, C, 3, 3))
+    wb = N.bf16(w)
+    bias = rng.standard_normal(O).astype(np.float32)
+    Ho, Wo = H // s, W // s
+    col = torch.zeros(C * 9 * B * Ho * Wo, dtype=torch.int16, device="cuda")
+    T.im2col(C, B, H, W, s, dev(x), col)
+    y = torch.zeros((O, B, Ho, Wo), dtype=torch.float32, device="cuda")
+    T.gemm(O, B * Ho * Wo, C * 9, dev(bf16_bits(wb.reshape(O, -1))), C * 9, 0, col, B * Ho * Wo, 0, y, B * Ho * Wo,
+           bias=dev(bias))
+    # backward data: dcol = W^T dy, dx = col2im(dcol)
+    dy = N.bf16(rng.standard_normal((O, B, Ho, Wo)))
+    dcol = torch.zeros(C * 9 * B * Ho * Wo, dtype=torch.float32, device="cuda")
+    T.gemm(C * 9, B * Ho * Wo, O, dev(bf16_bits(wb.reshape(O, -1))), C * 9, 1, dev(bf16_bits(dy.reshape(O, -1))),
+           B * Ho * Wo, 0, dcol, B * Ho * Wo)
+    dx = torch.zeros((C, B, H, W), dtype=torch.float32, device="cuda")
+    T.col2im(C, B, H, W, s, dcol, dx)
+    torch.cuda.synchronize()
+    ref = N.conv3x3(N.bf16(x), wb, bias, s)
+    rdx, rdw, _ = N.conv3x3_adjoint(N.bf16(x), wb, dy, s)
+    assert rel(y.cpu().numpy(), ref) <= 1e-6
+    assert rel(dx.cpu().numpy(), rdx) <= 1e-6
+
+
+def test_resampling_and_elementwise_kernels(T):
+    import torch
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((3, 2, 4, 6)).astype(np.float32)
+    y = torch.zeros((3, 2, 8, 12), dtype=torch.float32, device="cuda")
+    T.upsample2(3, 2, 4, 6, dev(x), y)
+    dy = rng.standard_normal((3, 2, 8, 12)).astype(np.float32)
+    dx = torch.zeros((3, 2, 4, 6), dtype=torch.float32, device="cuda")
+    T.upsample2_adjoint(3, 2, 4, 6, dev(dy), dx)
+    p = rng.standard_normal((2, 16, 5)).astype(np.float32)
+    q = torch.zeros((2, 4, 5), dtype=torch.float32, device="cuda")
+    T.rowpool(2, 16, 5, 4, dev(p), q)
+    dq = rng.standard_normal((2, 4, 5)).astype(np.float32)
+    dp = torch.zeros((2, 16, 5), dtype=torch.float32, device="cuda")
+    T.rowpool_adjoint(2, 16, 5, 4, dev(dq), dp)
+    r = dev(rng.standard_normal(1000).astype(np.float32))
+    dr = rng.standard_normal(1000).astype(np.float32)
+    drd = dev(dr)
+    T.relu_adjoint(r, drd)
+    s = torch.zeros(7, dtype=torch.float32, device="cuda")
+    X = rng.standard_normal((7, 333)).astype(np.float32)
+    T.rowsum(7, 333, dev(X), s)
+    pr, tg = rng.standard_normal(5000).astype(np.float32), rng.standard_normal(5000).astype(np.float32)
+    gr = torch.zeros(5000, dtype=torch.float32, device="cuda")
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    T.mse(dev(pr), dev(tg), gr, loss)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), N.upsample2(x).astype(np.float32))
+    assert np.allclose(dx.cpu().numpy(), N.upsample2_adjoint(dy), rtol=1e-6, atol=1e-6)
+    assert np.allclose(q.cpu().numpy(), N.rowpool(p, 4), rtol=1e-6, atol=1e-6)
+    assert np.allclose(dp.cpu().numpy(), N.rowpool_adjoint(dq, 4), rtol=1e-6, atol=0)
+    rr = r.cpu().numpy()
+    assert np.array_equal(drd.cpu().numpy(), np.where(rr > 0, dr, 0).astype(np.float32))
+    assert np.allclose(s.cpu().numpy(), X.astype(np.float64).sum(axis=1), rtol=1e-5, atol=1e-4)
+    L, g = N.mse(pr, tg)
+    assert float(loss.cpu()) == pytest.approx(L, rel=1e-12)
+    assert np.allclose(gr.cpu().numpy(), g, rtol=1e-6, atol=0)
+
+
+def test_weight_adam_matches_the_oracle(T):
+    import torch
+    rng = np.random.default_rng(4)
+    w0 = rng.standard_normal(3000).astype(np.float32)
+    w, m, v = dev(w0), dev(np.zeros(3000, np.float32)), dev(np.zeros(3000, np.float32))
+    w16 = torch.zeros(3000, dtype=torch.int16, device="cuda")
+    rw, rm, rv = w0.astype(np.float64), np.zeros(3000), np.zeros(3000)
+    for t in range(1, 4):
+        g = rng.standard_normal(3000).astype(np.float32)
+        T.adam(w, dev(g), m, v, w16, 1e-3, 0.9, 0.999, 1e-8, t)
+        rw, rm, rv = RO.adam_step(rw, g, rm, rv, t, 1e-3, 0.9, 0.999, 1e-8)
+    torch.cuda.synchronize()
+    got = w.cpu().numpy()
+    assert np.max(np.abs(got - rw)) <= 1e-4 * 1e-3 + 1e-6 * np.abs(rw).max()
+    g16 = w16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    assert np.array_equal(g16.view(np.float32), N.bf16(got).astype(np.float32))
+
+
+def test_rendered_pools_equal_the_host_generator(T):
+    import torch
+    samples = [synth.training_sample(7000 + i, n=64, n_slices=96) for i in range(5)]
+    nfs = [len(b) for _, b, _ in samples]
+    nps = [len(c) - 1 for _, _, c in samples]
+    offs = np.cumsum([0] + nps[:-1]).astype(np.int64)
+    boxes = np.zeros((5, T.MAX_BOXES, 8), np.float32)
+    cuts = np.zeros((5, T.MAX_CUTS), np.int32)
+    wts = np.zeros((5, T.MAX_CUTS), np.float32)
+    for i, (g, b, c) in enumerate(samples):
+        boxes[i, :len(b)] = b
+        cuts[i, :len(c)] = c
+        wts[i, :len(c) - 1] = np.diff(c) / g.n_slices
+    pd = torch.zeros((sum(nps), 64, 64), dtype=torch.float32, device="cuda")
+    pb = torch.zeros_like(pd)
+    T.render_pools(5, 64, 64, 16, synth.SUBSTRATE_DELTA, synth.SUBSTRATE_BETA, dev(boxes), dev(np.array(nfs, np.int32)),
+                   dev(cuts), dev(np.array(nps, np.int32)), dev(offs), max(nps), pd, pb)
+    tgt = torch.zeros((5, 16, 64), dtype=torch.float32, device="cuda")
+    T.pool_average(5, 64, 64, 16, 16, dev(wts), dev(np.array(nps, np.int32)), dev(offs), max(nps), pd, 1e5, tgt)
+    torch.cuda.synchronize()
+    for i, (g, b, c) in enumerate(samples):
+        f = g.ny / 512.0
+        sc = lambda lo, hi: (max(1, int(round(lo * f))), max(1, int(round(hi * f))))
+        cs = synth.compact_bars_on_substrate(g, 7000 + i + 1, substrate_rows=16, n_bars=(8, 32), bar_height=sc(2, 40),
+                                             bar_width=sc(4, 64), bar_len_frac=(1 / 8, 1.0), n_lines=(2, 8),
+                                             line_height=sc(2, 40), line_width=sc(1, 4), delta_range=(5e-6, 3e-5),
+                                             beta_over_delta=1 / 20)
+        assert np.array_equal(pd[offs[i]:offs[i] + nps[i]].cpu().numpy(), cs.pool_delta)
+        assert np.array_equal(pb[offs[i]:offs[i] + nps[i]].cpu().numpy(), cs.pool_beta)
+        d, _ = cs.dense()
+        ref = d[:, 16:32, :].astype(np.float64).mean(axis=0) * 1e5
+        assert np.allclose(tgt[i].cpu().numpy(), ref, rtol=1e-5, atol=1e-6)
+
+
+def test_unet_forward_and_gradients_match_the_oracle(T):
+    import torch
+    from paper_2212_01253_amd import learned
+    net = learned.UNet(c=4, seed=3)
+    rng = np.random.default_rng(5)
+    B, H, W = 2, 32, 32
+    x = rng.standard_normal((1, B, H, W)).astype(np.float32)
+    tgt = rng.standard_normal((B, H // 4, W)).astype(np.float32)
+    # non-zero biases to exercise them
+    host = net.w.cpu().numpy()
+    for name, ci, co, s, act in learned.layer_specs(4):
+        wo, bo, *_ = net.off[name]
+        host[bo:bo + co] = rng.standard_normal(co) * 0.1
+    net.set_flat(host)
+    pred = net.forward(dev(x))
+    loss = net.loss_and_grad(dev(tgt))
+    torch.cuda.synchronize()
+    params = net.params_numpy()
+    rpred, cache = N.unet_forward(params, x.astype(np.float64))
+    rL, dpred = N.mse(rpred, tgt)
+    rg = N.unet_adjoint(params, cache, dpred)
+    print("pred", rel(pred.cpu().numpy(), rpred), "loss", abs(float(loss.cpu()) - rL) / rL)
+    assert rel(pred.cpu().numpy(), rpred) <= 1e-4
+    assert abs(float(loss.cpu()) - rL) <= 1e-4 * rL
+    g = net.grads_numpy()
+    for name in params:
+        e_w, e_b = rel(g[name][0], rg[name][0]), rel(g[name][1], rg[name][1])
+        print(name, e_w, e_b)
+        assert e_w <= 2e-3 and e_b <= 2e-3
