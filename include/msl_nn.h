@@ -35,6 +35,14 @@ msl_status msl_nn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, 
                             const uint16_t* B, int32_t ldb, int32_t transB, float* C, int32_t ldc, float beta,
                             const float* bias, int32_t relu, uint16_t* C16, void* hip_stream);
 
+/* The same product without beta, bias or activation, its K range split into `splits` parts that
+ * run side by side (for small M x N and long K, such as weight gradients): part s writes its
+ * partial product to partials + s * M * N (float32 [splits][M][N], caller-owned scratch), then a
+ * fixed-order sum over the parts writes C.  1 <= splits <= 4096. */
+msl_status msl_nn_gemm_bf16_splitk(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t transA,
+                                   const uint16_t* B, int32_t ldb, int32_t transB, float* C, int32_t ldc,
+                                   int32_t splits, float* partials, void* hip_stream);
+
 /* 3x3 patches, zero padding 1, stride 1 or 2: x float32 [C][B][H][W] ->
  * col bfloat16 [C*9][B*Ho*Wo] with Ho = H/stride, Wo = W/stride (H, W divisible by stride);
  * row c*9 + 3*(dy+1) + (dx+1), column (b*Ho + i)*Wo + j holds x[c][b][stride*i+dy][stride*j+dx]. */
@@ -64,8 +72,9 @@ msl_status msl_nn_relu_adjoint(int64_t n, const float* y, float* dy, void* hip_s
 msl_status msl_nn_add(int64_t n, const float* x, float* y, void* hip_stream);
 msl_status msl_nn_to_bf16(int64_t n, const float* x, uint16_t* y16, void* hip_stream);
 
-/* out[m] = sum_n X[m * N + n] (float32 sums of float32 rows; bias gradients). */
-msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, void* hip_stream);
+/* out[m] = sum_n X[m * N + n] (float32 sums of float32 rows, bias gradients), in a fixed order:
+ * 64 partial sums per row into parts (float32 [M][64], caller-owned scratch), then their sum. */
+msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, float* parts, void* hip_stream);
 
 /* Mean squared error over n values: loss_out[0] (double, device) = sum (p - t)^2 / n,
  * grad[i] = 2 (p - t) / n (float32; may be NULL). */

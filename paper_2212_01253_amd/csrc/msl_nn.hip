@@ -38,6 +38,7 @@ constexpr int TM = 64, TN = 128, TK = 32, KP = TK + 4;
 
 struct GemmArgs {
   int M, N, K, lda, transA, ldb, transB, ldc, relu;
+  int kchunk;  // K range of blockIdx.z: [z * kchunk, min(K, (z + 1) * kchunk)); C offset z * M * ldc
   float beta;
   const uint16_t* A;
   const uint16_t* B;
@@ -53,14 +54,16 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
   f32x16 acc0 = {}, acc1 = {};
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
+  const int kbeg = blockIdx.z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+  float* const Cz = g.C + (int64_t)blockIdx.z * g.M * g.ldc;
+  for (int k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
     for (int r = 0; r < (TM * TK) / 256; ++r) {
       const int e = tid + 256 * r;
       const int mm = g.transA ? e % TM : e / TK, kk = g.transA ? e / TM : e % TK;
       const int gm = m0 + mm, gk = k0 + kk;
       uint16_t val = 0;
-      if (gm < g.M && gk < g.K) val = g.A[g.transA ? (int64_t)gk * g.lda + gm : (int64_t)gm * g.lda + gk];
+      if (gm < g.M && gk < kend) val = g.A[g.transA ? (int64_t)gk * g.lda + gm : (int64_t)gm * g.lda + gk];
       As[mm][kk] = val;
     }
 #pragma unroll
@@ -69,7 +72,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
       const int nn = g.transB ? e / TK : e % TN, kk = g.transB ? e % TK : e / TN;
       const int gk = k0 + kk, gn = n0 + nn;
       uint16_t val = 0;
-      if (gk < g.K && gn < g.N) val = g.B[g.transB ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn];
+      if (gk < kend && gn < g.N) val = g.B[g.transB ? (int64_t)gn * g.ldb + gk : (int64_t)gk * g.ldb + gn];
       Bs[nn][kk] = val;
     }
     __syncthreads();
@@ -96,28 +99,52 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
         if (m < g.M && n < g.N) {
           float v = h ? acc1[4 * i + j] : acc0[4 * i + j];
           const int64_t o = (int64_t)m * g.ldc + n;
-          if (g.beta != 0.0f) v = __builtin_fmaf(g.beta, g.C[o], v);
+          if (g.beta != 0.0f) v = __builtin_fmaf(g.beta, Cz[o], v);
           if (g.bias) v += g.bias[m];
           if (g.relu) v = fmaxf(v, 0.0f);
-          g.C[o] = v;
+          Cz[o] = v;
           if (g.C16) g.C16[o] = to_bf16(v);
         }
       }
   }
 }
 
+// C[i] = sum over the parts s of P[s][i], in order
+__global__ void __launch_bounds__(256) k_sum_parts(int64_t mn, int parts, const float* __restrict__ P, int M, int N,
+                                                   int ldc, float* __restrict__ C) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0.0f;
+    for (int s = 0; s < parts; ++s) acc += P[(int64_t)s * mn + e];
+    C[(e / N) * ldc + e % N] = acc;
+  }
+}
+
+// grid: y = patch row r = c * 9 + tap, x over the columns; two columns per thread (one 4-byte store)
 __global__ void __launch_bounds__(256) k_im2col(int C, int B, int H, int W, int s, const float* __restrict__ x,
                                                 uint16_t* __restrict__ col) {
-  const int Ho = H / s, Wo = W / s;
-  const int64_t ncol = (int64_t)B * Ho * Wo, total = (int64_t)C * 9 * ncol;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / ncol, n = e % ncol;
-    const int c = (int)(r / 9), t = (int)(r % 9), dy = t / 3 - 1, dx = t % 3 - 1;
-    const int j = (int)(n % Wo), i = (int)((n / Wo) % Ho), b = (int)(n / ((int64_t)Wo * Ho));
-    const int y = s * i + dy, xx = s * j + dx;
-    float v = 0.0f;
-    if (y >= 0 && y < H && xx >= 0 && xx < W) v = x[(((int64_t)c * B + b) * H + y) * W + xx];
-    col[e] = to_bf16(v);
+  const unsigned Ho = H / s, Wo = W / s, ncol = (unsigned)B * Ho * Wo;
+  const int r = blockIdx.y, c = r / 9, t = r % 9, dy = t / 3 - 1, dx = t % 3 - 1;
+  const float* xc = x + (int64_t)c * B * H * W;
+  uint16_t* out = col + (int64_t)r * ncol;
+  for (unsigned n0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x); n0 < ncol; n0 += 2 * gridDim.x * blockDim.x) {
+    uint16_t v2[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const unsigned n = n0 + q;
+      float v = 0.0f;
+      if (n < ncol) {
+        const unsigned j = n % Wo, i = (n / Wo) % Ho, b = n / (Wo * Ho);
+        const int y = s * (int)i + dy, xx = s * (int)j + dx;
+        if (y >= 0 && y < H && xx >= 0 && xx < W) v = xc[((int64_t)b * H + y) * W + xx];
+      }
+      v2[q] = to_bf16(v);
+    }
+    if (n0 + 1 < ncol && ((reinterpret_cast<uintptr_t>(out + n0) & 3) == 0)) {
+      *reinterpret_cast<uint32_t*>(out + n0) = (uint32_t)v2[0] | ((uint32_t)v2[1] << 16);
+    } else {
+      out[n0] = v2[0];
+      if (n0 + 1 < ncol) out[n0 + 1] = v2[1];
+    }
   }
 }
 
@@ -201,15 +228,31 @@ __global__ void __launch_bounds__(256) k_to_bf16(int64_t n, const float* __restr
     y[e] = to_bf16(x[e]);
 }
 
-// one workgroup per row; fixed summation order (deterministic)
-__global__ void __launch_bounds__(256) k_rowsum(int N, const float* __restrict__ X, float* __restrict__ out) {
+// row sums in two fixed-order stages: grid (parts, M) partial sums of column chunks, then one
+// workgroup per row over the parts (deterministic)
+constexpr int kRowParts = 64;
+
+__global__ void __launch_bounds__(256) k_rowsum_parts(int N, const float* __restrict__ X, float* __restrict__ part) {
   __shared__ float red[256];
-  const float* row = X + (int64_t)blockIdx.x * N;
+  const int chunk = (N + kRowParts - 1) / kRowParts;
+  const int n0 = blockIdx.x * chunk, n1 = min(N, n0 + chunk);
+  const float* row = X + (int64_t)blockIdx.y * N;
   float acc = 0.0f;
-  for (int n = threadIdx.x; n < N; n += 256) acc += row[n];
+  for (int n = n0 + threadIdx.x; n < n1; n += 256) acc += row[n];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y * kRowParts + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(64) k_rowsum_final(const float* __restrict__ part, float* __restrict__ out) {
+  __shared__ float red[64];
+  red[threadIdx.x] = part[blockIdx.x * kRowParts + threadIdx.x];
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -324,11 +367,35 @@ msl_status msl_nn_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, 
   MSL_TRY(check_ptr(C, 4, "C"));
   MSL_TRY(check_ptr(bias, 4, "bias", true));
   MSL_TRY(check_ptr(C16, 2, "C16", true));
-  GemmArgs g{M, N, K, lda, transA ? 1 : 0, ldb, transB ? 1 : 0, ldc, relu ? 1 : 0, beta, A, B, C, bias, C16};
+  GemmArgs g{M, N, K, lda, transA ? 1 : 0, ldb, transB ? 1 : 0, ldc, relu ? 1 : 0, K, beta, A, B, C, bias, C16};
   const dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM);
   MSL_TRY(need(grid.y <= 65535, "gemm: M too large"));
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, static_cast<hipStream_t>(hip_stream), g);
   return launched("gemm kernel");
+}
+
+msl_status msl_nn_gemm_bf16_splitk(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t transA,
+                                   const uint16_t* B, int32_t ldb, int32_t transB, float* C, int32_t ldc,
+                                   int32_t splits, float* partials, void* hip_stream) {
+  MSL_TRY(need(M >= 1 && N >= 1 && K >= 1, "gemm: M, N, K must be >= 1"));
+  MSL_TRY(need(lda >= (transA ? M : K) && ldb >= (transB ? K : N) && ldc >= N, "gemm: leading dimension too small"));
+  MSL_TRY(need(splits >= 1 && splits <= 4096, "gemm: splits must be in [1, 4096]"));
+  MSL_TRY(check_ptr(A, 2, "A"));
+  MSL_TRY(check_ptr(B, 2, "B"));
+  MSL_TRY(check_ptr(C, 4, "C"));
+  MSL_TRY(check_ptr(partials, 4, "partials"));
+  // K range per part: a multiple of the K tile
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + TK - 1) / TK * TK;
+  const int parts = (K + kchunk - 1) / kchunk;
+  GemmArgs g{M, N, K, lda, transA ? 1 : 0, ldb, transB ? 1 : 0, N, 0, kchunk, 0.0f, A, B, partials, nullptr, nullptr};
+  const dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, parts);
+  MSL_TRY(need(grid.y <= 65535, "gemm: M too large"));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+  const int64_t mn = (int64_t)M * N;
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, M, N, ldc, C);
+  return launched("split gemm kernels");
 }
 
 msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* x,
@@ -337,9 +404,11 @@ msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t 
                    W % stride == 0, "im2col: need C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
   MSL_TRY(check_ptr(x, 4, "x"));
   MSL_TRY(check_ptr(col, 2, "col"));
-  const int64_t total = (int64_t)C * 9 * B * (H / stride) * (W / stride);
-  hipLaunchKernelGGL(k_im2col, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), C, B, H, W,
-                     stride, x, col);
+  const int64_t ncol = (int64_t)B * (H / stride) * (W / stride);
+  MSL_TRY(need(ncol < (1ll << 31) && C * 9 <= 65535, "im2col: too many columns or channels"));
+  const unsigned bx = (unsigned)std::min<int64_t>((ncol / 2 + 255) / 256 + 1, 8192);
+  hipLaunchKernelGGL(k_im2col, dim3(bx, C * 9), dim3(256), 0, static_cast<hipStream_t>(hip_stream), C, B, H, W, stride,
+                     x, col);
   return launched("im2col kernel");
 }
 
@@ -421,12 +490,16 @@ msl_status msl_nn_to_bf16(int64_t n, const float* x, uint16_t* y16, void* hip_st
   return launched("bf16 conversion kernel");
 }
 
-msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, void* hip_stream) {
+msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, float* parts, void* hip_stream) {
   MSL_TRY(need(M >= 1 && N >= 1, "rowsum: M, N must be >= 1"));
   MSL_TRY(check_ptr(X, 4, "X"));
   MSL_TRY(check_ptr(out, 4, "out"));
-  hipLaunchKernelGGL(k_rowsum, dim3(M), dim3(256), 0, static_cast<hipStream_t>(hip_stream), N, X, out);
-  return launched("rowsum kernel");
+  MSL_TRY(need(M <= 65535, "rowsum: M too large"));
+  MSL_TRY(check_ptr(parts, 4, "parts"));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_rowsum_parts, dim3(kRowParts, M), dim3(256), 0, st, N, X, parts);
+  hipLaunchKernelGGL(k_rowsum_final, dim3(M), dim3(64), 0, st, parts, out);
+  return launched("rowsum kernels");
 }
 
 msl_status msl_nn_mse(int64_t n, const float* pred, const float* target, float* grad, double* loss_out,

@@ -26,6 +26,7 @@ import torch
 from . import msl, nn, synth
 
 BF16 = nn.BF16
+SPLIT_PARTS = 512   # most parts of a split weight-gradient product
 
 
 def layer_specs(c=32):
@@ -128,6 +129,14 @@ class UNet:
         b["dcol"] = torch.zeros(kmax * nmax, dtype=torch.float32, device=d)
         comax = max(co for _, _, co, _, _ in self.specs)
         b["dy16"] = torch.zeros(comax * nmax, dtype=BF16, device=d)
+        need = 0
+        for name, ci, co, s, act in self.specs:
+            # pixel level of the layer's output (its gradient's columns)
+            lvl = {"e1a": 0, "e1b": 0, "e2a": 1, "e2b": 1, "e3a": 2, "e3b": 2, "e4a": 3, "e4b": 3,
+                   "d3": 2, "d2": 1, "d1": 0, "out": 0}[name]
+            npix = B * hw[lvl][0] * hw[lvl][1]
+            need = max(need, max(1, min(SPLIT_PARTS, npix // 1024)) * co * ci * 9)
+        b["parts"] = torch.zeros(need, dtype=torch.float32, device=d)
         # gradient buffers with the activations' shapes
         for k in ("e1a", "cat1", "e2a", "cat2", "e3a", "cat3", "e4a", "e4", "d3", "d2", "d1", "out"):
             b["d_" + k] = torch.zeros_like(b[k])
@@ -162,10 +171,12 @@ class UNet:
         dy16 = bf["dy16"][:co * N]
         nn.to_bf16(dy, dy16)
         w16, _, gw, gb = self._wb(name)
-        nn.rowsum(co, N, dy, gb)
+        nn.rowsum(co, N, dy, gb, bf["parts"])
         col = bf["col"][:ci * 9 * N]
         nn.im2col(ci, B, H, W, s, x, col)
-        nn.gemm(co, ci * 9, N, dy16, N, 0, col, N, 1, gw, ci * 9)
+        # weight gradient: a short, wide product over the long pixel axis, split along it
+        splits = max(1, min(SPLIT_PARTS, N // 1024))
+        nn.gemm_splitk(co, ci * 9, N, dy16, N, 0, col, N, 1, gw, ci * 9, splits, bf["parts"])
         if dx is not None:
             dcol = bf["dcol"][:ci * 9 * N]
             nn.gemm(ci * 9, N, co, w16, ci * 9, 1, dy16, N, 0, dcol, N)
@@ -238,3 +249,120 @@ class UNet:
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1
         nn.adam(self.w, self.g, self.m, self.v, self.w16, lr, beta1, beta2, eps, self.t)
+
+
+# ---------------------------------------------------------------------------
+# training data from the forward model
+
+INPUT_A = 0.25   # network input: INPUT_A * log(I + eps_of(n))
+
+
+def eps_of(n):
+    """Intensity floor of the input map: one photon of a 1e6-photon image of an n x n unit field."""
+    return n * n / 1e6
+
+
+def slice_index_of(cuts):
+    """Pool index of every slice from the pool boundaries."""
+    return np.repeat(np.arange(len(cuts) - 1, dtype=np.int32), np.diff(cuts))
+
+
+class TrainingSet:
+    """Network inputs [S][n][n] and targets [S][rows/f... rows][n] on the device, from the model."""
+
+    def __init__(self, n_samples, seed0=20000, n=256, n_slices=1024, rows=None, f=4, chunk=128, log=False):
+        self.n, self.f = n, f
+        self.rows = rows or n // 4            # unknown rows: the n/4 rows above the n/4-row substrate
+        dev = torch.device("cuda")
+        self.x = torch.zeros((n_samples, n, n), dtype=torch.float32, device=dev)
+        self.y = torch.zeros((n_samples, self.rows, n), dtype=torch.float32, device=dev)
+        t0 = time.perf_counter()
+        for c0 in range(0, n_samples, chunk):
+            ids = list(range(c0, min(n_samples, c0 + chunk)))
+            smp = [synth.training_sample(seed0 + i, n=n, n_slices=n_slices) for i in ids]
+            k = len(smp)
+            nps = np.array([len(c) - 1 for _, _, c in smp], np.int32)
+            offs = np.concatenate([[0], np.cumsum(nps)[:-1]]).astype(np.int64)
+            boxes = np.zeros((k, nn.MAX_BOXES, 8), np.float32)
+            cuts = np.zeros((k, nn.MAX_CUTS), np.int32)
+            wts = np.zeros((k, nn.MAX_CUTS), np.float32)
+            nfs = np.zeros(k, np.int32)
+            for q, (g, b, c) in enumerate(smp):
+                boxes[q, :len(b)] = b
+                nfs[q] = len(b)
+                cuts[q, :len(c)] = c
+                wts[q, :len(c) - 1] = np.diff(c) / g.n_slices
+            pd = torch.empty((int(nps.sum()), n, n), dtype=torch.float32, device=dev)
+            pb = torch.empty_like(pd)
+            T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+            Tn, Toff = T(nps), T(offs)
+            nn.render_pools(k, n, n, n // 4, synth.SUBSTRATE_DELTA, synth.SUBSTRATE_BETA, T(boxes), T(nfs), T(cuts),
+                            Tn, Toff, int(nps.max()), pd, pb)
+            nn.pool_average(k, n, n, n // 4, self.rows, T(wts), Tn, Toff, int(nps.max()), pd, 1e5,
+                            self.y[ids[0]:ids[-1] + 1])
+            I = torch.empty((k, n, n), dtype=torch.float32, device=dev)
+            items = []
+            for q, (g, b, c) in enumerate(smp):
+                items.append({"geom": g, "pool_delta": pd[offs[q]:offs[q] + nps[q]],
+                              "pool_beta": pb[offs[q]:offs[q] + nps[q]], "slice_index": T(slice_index_of(c)),
+                              "field": torch.empty((n, n), dtype=torch.complex64, device=dev), "intensity": I[q]})
+            msl.forward_batch(items)
+            nn.logmap(I, eps_of(n), INPUT_A, 0.0, self.x[ids[0]:ids[-1] + 1])
+            if log and (c0 // chunk) % 20 == 0:
+                torch.cuda.synchronize()
+                print(f"# training set: {c0 + k}/{n_samples} samples ({time.perf_counter() - t0:.1f} s)", flush=True)
+        torch.cuda.synchronize()
+        self.seconds = time.perf_counter() - t0
+
+    def __len__(self):
+        return self.x.shape[0]
+
+
+def train(net, data, steps, batch=32, lr=1e-3, seed=1, log_every=0, val=None):
+    """ADAM on the mean squared error over random minibatches; returns the loss history."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = data.n
+    xb = torch.empty((1, batch, n, n), dtype=torch.float32, device="cuda")
+    yb = torch.empty((batch, data.rows, n), dtype=torch.float32, device="cuda")
+    hist = []
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = torch.from_numpy(rng.choice(len(data), size=batch, replace=False)).cuda()
+        torch.index_select(data.x, 0, idx, out=xb[0])
+        torch.index_select(data.y, 0, idx, out=yb)
+        net.forward(xb)
+        L = net.loss_and_grad(yb)
+        net.adam_step(lr)
+        if log_every and (it % log_every == 0 or it == steps - 1):
+            Lh = float(L.item())
+            hist.append((it, Lh))
+            msg = f"# step {it}: loss {Lh:.5f} ({time.perf_counter() - t0:.1f} s)"
+            if val is not None:
+                msg += f", validation {evaluate(net, val, batch):.5f}"
+            print(msg, flush=True)
+    torch.cuda.synchronize()
+    return hist, time.perf_counter() - t0
+
+
+def predict(net, x, batch=64):
+    """Network output for inputs x [S][n][n] in batches; returns [S][rows][n] (device)."""
+    S, n = x.shape[0], x.shape[1]
+    out = []
+    for s0 in range(0, S, batch):
+        xb = x[s0:s0 + batch].unsqueeze(0).contiguous()
+        out.append(net.forward(xb).clone())
+    return torch.cat(out)
+
+
+def evaluate(net, data, batch=64):
+    """Mean squared error of the network on a data set (library loss kernel per batch)."""
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    total, count = 0.0, 0
+    for s0 in range(0, len(data), batch):
+        xb = data.x[s0:s0 + batch].unsqueeze(0).contiguous()
+        pred = net.forward(xb)
+        nn.mse(pred, data.y[s0:s0 + batch].contiguous(), None, loss)
+        k = xb.shape[1]
+        total += float(loss.item()) * k
+        count += k
+    return total / count

@@ -13,7 +13,7 @@ import torch
 
 from . import msl
 
-EXPORTS = ("msl_nn_gemm_bf16", "msl_nn_im2col3x3", "msl_nn_col2im3x3", "msl_nn_upsample2",
+EXPORTS = ("msl_nn_gemm_bf16", "msl_nn_gemm_bf16_splitk", "msl_nn_im2col3x3", "msl_nn_col2im3x3", "msl_nn_upsample2",
            "msl_nn_upsample2_adjoint", "msl_nn_rowpool", "msl_nn_rowpool_adjoint", "msl_nn_relu_adjoint",
            "msl_nn_add", "msl_nn_to_bf16", "msl_nn_rowsum", "msl_nn_mse", "msl_nn_adam", "msl_nn_logmap",
            "msl_nn_render_pools", "msl_nn_pool_average")
@@ -32,6 +32,7 @@ def lib():
         I = c_int32
         sig = {
             "msl_nn_gemm_bf16": [I, I, I, P, I, I, P, I, I, P, I, c_float, P, I, P, P],
+            "msl_nn_gemm_bf16_splitk": [I, I, I, P, I, I, P, I, I, P, I, I, P, P],
             "msl_nn_im2col3x3": [I, I, I, I, I, P, P, P],
             "msl_nn_col2im3x3": [I, I, I, I, I, P, P, P],
             "msl_nn_upsample2": [I, I, I, I, P, P, P],
@@ -41,7 +42,7 @@ def lib():
             "msl_nn_relu_adjoint": [c_int64, P, P, P],
             "msl_nn_add": [c_int64, P, P, P],
             "msl_nn_to_bf16": [c_int64, P, P, P],
-            "msl_nn_rowsum": [I, I, P, P, P],
+            "msl_nn_rowsum": [I, I, P, P, P, P],
             "msl_nn_mse": [c_int64, P, P, P, P, P],
             "msl_nn_adam": [c_int64, P, P, P, P, P, c_float, c_float, c_float, c_float, I, P],
             "msl_nn_logmap": [c_int64, P, c_float, c_float, c_float, P, P],
@@ -83,6 +84,11 @@ def gemm(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, beta=0.0, bias=None, r
                                _p(C16, BF16), _s()))
 
 
+def gemm_splitk(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, splits, partials):
+    _ck(lib().msl_nn_gemm_bf16_splitk(M, N, K, _p(A, BF16), lda, int(transA), _p(B, BF16), ldb, int(transB),
+                                      _p(C, torch.float32), ldc, int(splits), _p(partials, torch.float32), _s()))
+
+
 def im2col(C, B, H, W, stride, x, col):
     _ck(lib().msl_nn_im2col3x3(C, B, H, W, stride, _p(x, torch.float32), _p(col, BF16), _s()))
 
@@ -119,8 +125,9 @@ def to_bf16(x, y16):
     _ck(lib().msl_nn_to_bf16(x.numel(), _p(x, torch.float32), _p(y16, BF16), _s()))
 
 
-def rowsum(M, N, X, out):
-    _ck(lib().msl_nn_rowsum(M, N, _p(X, torch.float32), _p(out, torch.float32), _s()))
+def rowsum(M, N, X, out, parts):
+    """parts: float32 scratch of at least M * 64 values."""
+    _ck(lib().msl_nn_rowsum(M, N, _p(X, torch.float32), _p(out, torch.float32), _p(parts, torch.float32), _s()))
 
 
 def mse(pred, target, grad, loss):

@@ -187,3 +187,43 @@ def seconds_to_threshold(p: Problem, init, factor=1.10, max_iters=5000, adam: Ad
     L_truth = float(R.loss().item()) * p.scale
     res = R.run(init, max_iters, factor * L_truth, log_every=log_every)
     return L_truth, res
+
+
+def learned_initial_guess(net, p: Problem):
+    """Box values from the network: the measured counts as an intensity estimate (counts / s)
+    through the network's input map, the predicted cross-section (rows x columns, in units of
+    1e-5) clamped at 0 and repeated along the beam over the box's slices."""
+    from . import learned, nn
+    n = p.geom.ny
+    I = torch.from_numpy(np.ascontiguousarray(p.counts / p.scale, np.float32)).cuda()
+    x = torch.empty((1, 1, n, n), dtype=torch.float32, device="cuda")
+    nn.logmap(I, learned.eps_of(n), learned.INPUT_A, 0.0, x)
+    pred = net.forward(x)[0].cpu().numpy().astype(np.float64) * 1e-5
+    cs = np.clip(pred, 0.0, None).astype(np.float32)
+    return np.ascontiguousarray(np.broadcast_to(cs, (p.region["ns"],) + cs.shape))
+
+
+def seconds_to_threshold_learned(p: Problem, net, plain_init, factor=1.10, max_iters=5000, adam: Adam | None = None,
+                                 ckpt_every=32, log_every=0):
+    """Learned start with an error judge: network inference, then the losses of the learned and the
+    plain start are compared and ADAM runs from the lower one (the plain start is the fallback when
+    the learned guess is worse or not finite).  The reported seconds include inference and judging.
+    Returns (L_truth, result, chose_learned, loss_learned, loss_plain)."""
+    R = Reconstructor(p.geom, p.known_delta, p.known_beta, p.region, p.counts, p.scale, ckpt_every=ckpt_every,
+                      adam=adam)
+    R.set_theta(p.truth)
+    L_truth = float(R.loss().item()) * p.scale
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    guess = learned_initial_guess(net, p)
+    R.set_theta(guess)
+    L_learned = float(R.loss().item()) * p.scale
+    R.set_theta(plain_init)
+    L_plain = float(R.loss().item()) * p.scale
+    chose = bool(np.isfinite(L_learned) and L_learned < L_plain)
+    t_judge = time.perf_counter() - t0
+    res = R.run(guess if chose else plain_init, max_iters, factor * L_truth, log_every=log_every)
+    res.times = [t + t_judge for t in res.times]
+    if res.secs_to_threshold is not None:
+        res.secs_to_threshold += t_judge
+    return L_truth, res, chose, L_learned, L_plain

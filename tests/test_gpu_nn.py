@@ -108,7 +108,7 @@ def test_resampling_and_elementwise_kernels(T):
     T.relu_adjoint(r, drd)
     s = torch.zeros(7, dtype=torch.float32, device="cuda")
     X = rng.standard_normal((7, 333)).astype(np.float32)
-    T.rowsum(7, 333, dev(X), s)
+    T.rowsum(7, 333, dev(X), s, torch.zeros(7 * 64, dtype=torch.float32, device="cuda"))
     pr, tg = rng.standard_normal(5000).astype(np.float32), rng.standard_normal(5000).astype(np.float32)
     gr = torch.zeros(5000, dtype=torch.float32, device="cuda")
     loss = torch.zeros((), dtype=torch.float64, device="cuda")
@@ -200,10 +200,28 @@ def test_unet_forward_and_gradients_match_the_oracle(T):
     rL, dpred = N.mse(rpred, tgt)
     rg = N.unet_adjoint(params, cache, dpred)
     print("pred", rel(pred.cpu().numpy(), rpred), "loss", abs(float(loss.cpu()) - rL) / rL)
-    assert rel(pred.cpu().numpy(), rpred) <= 1e-4
+    assert rel(pred.cpu().numpy(), rpred) <= 1e-5
     assert abs(float(loss.cpu()) - rL) <= 1e-4 * rL
     g = net.grads_numpy()
     for name in params:
         e_w, e_b = rel(g[name][0], rg[name][0]), rel(g[name][1], rg[name][1])
         print(name, e_w, e_b)
-        assert e_w <= 2e-3 and e_b <= 2e-3
+        assert e_w <= 1e-5 and e_b <= 1e-5   # measured <= 2.4e-7
+
+
+@pytest.mark.parametrize("ta,tb,splits", [(0, 1, 7), (0, 0, 1), (1, 1, 33)])
+def test_split_gemm_matches_float64_products(T, ta, tb, splits):
+    import torch
+    rng = np.random.default_rng(6)
+    M, Nn, K = 40, 70, 5000
+    a = N.bf16(rng.standard_normal((M, K)))
+    b = N.bf16(rng.standard_normal((K, Nn)))
+    A = a.T.copy() if ta else a
+    Bm = b.T.copy() if tb else b
+    C = torch.zeros((M, Nn), dtype=torch.float32, device="cuda")
+    parts = torch.zeros(splits * M * Nn, dtype=torch.float32, device="cuda")
+    T.gemm_splitk(M, Nn, K, dev(bf16_bits(A)), A.shape[1], ta, dev(bf16_bits(Bm)), Bm.shape[1], tb, C, Nn, splits,
+                  parts)
+    torch.cuda.synchronize()
+    scale = np.abs(a) @ np.abs(b)
+    assert np.all(np.abs(C.cpu().numpy() - a @ b) <= 4e-6 * scale)
