@@ -139,6 +139,20 @@ def batch_leg(n_inst, steps=3):
                         "256..4096 slices of 5 nm, wavelength U[0.08, 0.15] nm, incidence U[0.05, 0.5] deg"}
 
 
+def learned_leg():
+    """Learned initialiser (U-Net, bfloat16 matrix cores): trained on model samples (not timed),
+    then the reconstruction of the same workload as recon_leg from its start, timed from data on
+    the GPU including inference and the judge that falls back to the plain start."""
+    from paper_2212_01253_amd import learned, recon, synth
+    net, info = learned.train_initialiser()
+    p = recon.make_problem()
+    init = synth.random_init(p.region, 4244)
+    L_truth, res, chose, L_learned, L_plain = recon.seconds_to_threshold_learned(p, net, init)
+    info.update({"secs_to_threshold": res.secs_to_threshold, "iterations": res.iters_to_threshold,
+                 "loss_learned_start": L_learned, "loss_plain_start": L_plain, "used_learned_start": chose})
+    return info
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -160,6 +174,7 @@ def main():
     ap.add_argument("--cpu-sample-slices", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction seconds-to-loss leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-initialiser leg")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
                     help="also time the batched forward over N instances of the batched workload (96 = full)")
     args = ap.parse_args()
@@ -291,6 +306,13 @@ def main():
     if not args.no_recon:
         print("# reconstruction (plain init) ...", file=sys.stderr, flush=True)
         out["recon"] = recon_leg()
+        if not args.no_learned:
+            print("# learned initialiser: training, then reconstruction from its start ...", file=sys.stderr,
+                  flush=True)
+            try:
+                out["recon"]["learned"] = learned_leg()
+            except Exception as e:   # report, keep the line
+                out["recon"]["learned"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, meas, args.cpu_sample_slices)

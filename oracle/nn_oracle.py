@@ -102,10 +102,10 @@ def mse(p, t):
 # ---------------------------------------------------------------------------
 # the network: a four-level U-Net, channels c, 2c, 4c, 8c
 
-def layer_specs(c=32):
+def layer_specs(c=32, in_ch=2):
     """(name, in channels, out channels, stride, relu) of every convolution, in order."""
     c1, c2, c3, c4 = c, 2 * c, 4 * c, 8 * c
-    return [("e1a", 1, c1, 1, True), ("e1b", c1, c1, 1, True),
+    return [("e1a", in_ch, c1, 1, True), ("e1b", c1, c1, 1, True),
             ("e2a", c1, c2, 2, True), ("e2b", c2, c2, 1, True),
             ("e3a", c2, c3, 2, True), ("e3b", c3, c3, 1, True),
             ("e4a", c3, c4, 2, True), ("e4b", c4, c4, 1, True),
@@ -113,8 +113,9 @@ def layer_specs(c=32):
             ("out", c1, 1, 1, False)]
 
 
-def unet_forward(params, x, rows_per_output=4, quantize=True):
-    """x [1][B][H][W] -> pred [B][H/rows_per_output][W]; params[name] = (w [O][C][3][3], bias [O]).
+def unet_forward(params, x, rows_per_output=4, quantize=True, offset=None):
+    """x [C][B][H][W] -> pred [B][H/rows_per_output][W] (+ offset [H/rows_per_output][W]);
+    params[name] = (w [O][C][3][3], bias [O]).
     Returns (pred, cache) for ``unet_adjoint``.  quantize=False skips the bfloat16 rounding
     (the exact function, for finite-difference checks)."""
     q = bf16 if quantize else (lambda a: np.asarray(a, np.float64))
@@ -137,6 +138,8 @@ def unet_forward(params, x, rows_per_output=4, quantize=True):
     d1 = conv("d1", np.concatenate([upsample2(d2), e1]), 1, True)
     out = conv("out", d1, 1, False)
     pred = rowpool(out[0], rows_per_output)
+    if offset is not None:
+        pred = pred + np.asarray(offset, np.float64)[None]
     cache["shapes"] = {"e4": e4.shape[0], "d3": d3.shape[0], "d2": d2.shape[0]}
     return pred, cache
 

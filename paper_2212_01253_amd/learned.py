@@ -4,7 +4,10 @@ A four-level U-Net (channels c, 2c, 4c, 8c; 3x3 convolutions, stride-2
 convolutions down, nearest 2x upsampling and skip concatenation up) maps the
 far-field log-intensity image of a sample (Ny x Nz) to the delta cross-section
 of the unknown rows (mean over the beam direction, rows pooled 4:1), which is
-extruded along the beam as the ADAM starting point.  Every layer runs in
+extruded along the beam as the ADAM starting point.  A second input channel
+holds the row coordinate (a convolutional network is otherwise blind to
+absolute position, and the cross-section's rows are heights), and the output
+is a correction to a fixed offset map (the training targets' mean).  Every layer runs in
 libmsl's kernels (``nn.py``): convolutions are bfloat16 matrix-core products
 (weights x 3x3 patches) with float32 accumulation; master weights, activations
 and gradients are float32.  This module only sequences the calls and owns the
@@ -29,10 +32,10 @@ BF16 = nn.BF16
 SPLIT_PARTS = 512   # most parts of a split weight-gradient product
 
 
-def layer_specs(c=32):
+def layer_specs(c=32, in_ch=2):
     """(name, in channels, out channels, stride, relu) of every convolution, in order."""
     c1, c2, c3, c4 = c, 2 * c, 4 * c, 8 * c
-    return [("e1a", 1, c1, 1, True), ("e1b", c1, c1, 1, True),
+    return [("e1a", in_ch, c1, 1, True), ("e1b", c1, c1, 1, True),
             ("e2a", c1, c2, 2, True), ("e2b", c2, c2, 1, True),
             ("e3a", c2, c3, 2, True), ("e3b", c3, c3, 1, True),
             ("e4a", c3, c4, 2, True), ("e4b", c4, c4, 1, True),
@@ -46,6 +49,7 @@ class UNet:
     def __init__(self, c=32, rows_per_output=4, device="cuda:0", seed=0):
         self.c, self.f, self.dev = c, rows_per_output, torch.device(device)
         self.specs = layer_specs(c)
+        self.offset = None   # [rows][W] added to every output (set_offset)
         self.off = {}
         o = 0
         for name, ci, co, s, act in self.specs:
@@ -109,7 +113,9 @@ class UNet:
         z = lambda *shape: torch.zeros(shape, dtype=torch.float32, device=d)
         hw = [(H, W), (H // 2, W // 2), (H // 4, W // 4), (H // 8, W // 8)]
         b = {"key": key}
-        b["x"] = z(1, B, H, W)
+        b["x"] = z(2, B, H, W)
+        ramp = torch.linspace(-1.0, 1.0, H, device=d)   # channel 1: the row coordinate
+        b["x"][1].copy_(ramp.view(1, H, 1).expand(B, H, W))
         b["e1a"] = z(c1, B, *hw[0])
         b["cat1"] = z(c2 + c1, B, *hw[0])          # [up(d2); e1]
         b["e2a"] = z(c2, B, *hw[1])
@@ -188,7 +194,7 @@ class UNet:
             B, H, W = x.shape[1], x.shape[2], x.shape[3]
         bf = self._buffers(B, H, W)
         if x is not None:
-            bf["x"].copy_(x)
+            bf["x"][0].copy_(x[0])
         c1, c2, c3, c4 = self.c, 2 * self.c, 4 * self.c, 8 * self.c
         e1 = bf["cat1"][c2:]
         e2 = bf["cat2"][c3:]
@@ -209,7 +215,17 @@ class UNet:
         self._conv("d1", bf["cat1"], bf["d1"], B, H, W)
         self._conv("out", bf["d1"], bf["out"], B, H, W)
         nn.rowpool(B, H, W, self.f, bf["out"], bf["pred"])
+        if self.offset is not None:
+            if "offset" not in bf:
+                bf["offset"] = self.offset.unsqueeze(0).expand(B, -1, -1).contiguous()
+            nn.add_(bf["offset"], bf["pred"])
         return bf["pred"]
+
+    def set_offset(self, offset):
+        """Fixed map [rows][W] added to the output (None: no offset)."""
+        self.offset = None if offset is None else offset.to(self.dev).float().contiguous()
+        if self._bufs is not None:
+            self._bufs.pop("offset", None)
 
     def backward(self, dpred):
         """Parameter gradients (into self.g) of a loss with dL/dpred, after ``forward``."""
@@ -318,6 +334,14 @@ class TrainingSet:
         return self.x.shape[0]
 
 
+def mean_target(data, chunk=256):
+    """Mean of the training targets, [rows][n] (the network's output offset)."""
+    acc = torch.zeros(data.y.shape[1:], dtype=torch.float64, device=data.y.device)
+    for s0 in range(0, len(data), chunk):
+        acc += data.y[s0:s0 + chunk].double().sum(0)
+    return (acc / len(data)).float()
+
+
 def train(net, data, steps, batch=32, lr=1e-3, seed=1, log_every=0, val=None):
     """ADAM on the mean squared error over random minibatches; returns the loss history."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -366,3 +390,24 @@ def evaluate(net, data, batch=64):
         total += float(loss.item()) * k
         count += k
     return total / count
+
+
+def train_initialiser(n_samples=4096, steps=300, batch=32, lr=1e-3, n=256, n_slices=1024, seed=0, log_every=0,
+                      n_val=256):
+    """Training set from the model, the network with the targets' mean as output offset, ADAM.
+    Returns (net, info) with the data and training times and the validation error of the network
+    next to that of the offset alone (the population-mean cross-section)."""
+    data = TrainingSet(n_samples, n=n, n_slices=n_slices)
+    val = TrainingSet(n_val, seed0=900000, n=n, n_slices=n_slices)
+    net = UNet(c=32, seed=seed)
+    mt = mean_target(data)
+    net.set_offset(mt)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    nn.mse(mt.unsqueeze(0).expand(len(val), -1, -1).contiguous(), val.y, None, loss)
+    base = float(loss.item())
+    hist, secs = train(net, data, steps, batch=batch, lr=lr, log_every=log_every)
+    info = {"samples": n_samples, "steps": steps, "batch": batch, "lr": lr, "data_seconds": data.seconds,
+            "train_seconds": secs, "ms_per_step": 1e3 * secs / max(1, steps), "params": net.n_params,
+            "val_mse": evaluate(net, val), "val_mse_mean_map": base}
+    del data, val
+    return net, info

@@ -345,16 +345,14 @@ def bar_boxes(geom: Geometry, seed: int, *, substrate_rows: int, **kw):
 
 
 def training_sample(seed: int, n: int = 256, n_slices: int = 1024, alpha_deg=(0.1, 0.4)):
-    """One training sample of the learned initialiser: a throughput-style bars-and-lines sample on an
-    n x n grid (heights and widths scaled by n / 512, substrate n / 4 rows, 5 nm slices, 0.1 nm) at a
-    random incidence in alpha_deg; returns (geometry, boxes, cuts)."""
+    """One training sample of the learned initialiser: the reconstruction workload's generator
+    (``recon_256``: bars and lines over an n/4-row substrate, 5 nm slices, 0.1 nm) on an n x n grid
+    at a random incidence in alpha_deg; returns (geometry, boxes, cuts)."""
     rng = _rng(seed)
     alpha = math.radians(float(rng.uniform(*alpha_deg)))
     g = Geometry(n, n, n_slices, 1.0, 1.0, 5.0, 0.1, alpha, 0)
-    f = n / 512.0
-    sc = lambda lo, hi: (max(1, int(round(lo * f))), max(1, int(round(hi * f))))
-    boxes, cuts = bar_boxes(g, seed + 1, substrate_rows=n // 4, n_bars=(8, 32), bar_height=sc(2, 40),
-                            bar_width=sc(4, 64), bar_len_frac=(1.0 / 8.0, 1.0), n_lines=(2, 8),
-                            line_height=sc(2, 40), line_width=sc(1, 4), delta_range=(5e-6, 3e-5),
+    boxes, cuts = bar_boxes(g, seed + 1, substrate_rows=n // 4, n_bars=(8, 32), bar_height=(2, 40),
+                            bar_width=(4, 64), bar_len_frac=(1.0 / 8.0, 1.0), n_lines=(2, 8),
+                            line_height=(2, 40), line_width=(1, 4), delta_range=(5e-6, 3e-5),
                             beta_over_delta=1.0 / 20.0)
     return g, boxes, cuts

@@ -73,7 +73,7 @@ def test_unet_gradient_matches_finite_differences():
     rng = np.random.default_rng(5)
     c = 2
     params = small_params(rng, c)
-    x = rng.standard_normal((1, 2, 16, 16))
+    x = rng.standard_normal((2, 2, 16, 16))
     t = rng.standard_normal((2, 4, 16))
 
     def loss(p):
