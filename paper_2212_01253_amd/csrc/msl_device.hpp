@@ -150,9 +150,12 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 #ifndef MSL_P4_MIN_N
 #define MSL_P4_MIN_N 4096  // line length from which lines use 4 points per lane
 #endif
+#ifndef MSL_P8_MIN_N
+#define MSL_P8_MIN_N 512   // shorter lines use 4 points per lane (twice the lanes per line)
+#endif
 template <int N>
 struct LinePts {
-  static constexpr int P = N >= MSL_P4_MIN_N ? 4 : 8;
+  static constexpr int P = (N >= MSL_P4_MIN_N || N < MSL_P8_MIN_N) ? 4 : 8;
   static constexpr int L = N / P;
 };
 

@@ -411,3 +411,36 @@ def train_initialiser(n_samples=4096, steps=300, batch=32, lr=1e-3, n=256, n_sli
             "val_mse": evaluate(net, val), "val_mse_mean_map": base}
     del data, val
     return net, info
+
+
+def _speed(batch, steps=5):
+    """Times training steps and forward passes of the 256 x 256 network at a batch size."""
+    net = UNet(c=32, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(1, batch, 256, 256, device="cuda", generator=g) * 0.1
+    y = torch.randn(batch, 64, 256, device="cuda", generator=g) * 0.1
+    for _ in range(2):
+        net.forward(x)
+        net.loss_and_grad(y)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        net.forward(x)
+        net.loss_and_grad(y)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    t = time.perf_counter()
+    for _ in range(steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    df = (time.perf_counter() - t) / steps
+    print(f"batch {batch}: training step {dt * 1e3:.1f} ms, forward {df * 1e3:.1f} ms", flush=True)
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="learned initialiser: timing of the network's passes")
+    ap.add_argument("--speed", type=int, default=32, metavar="BATCH")
+    _speed(ap.parse_args().speed)
