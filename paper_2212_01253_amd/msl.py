@@ -231,14 +231,19 @@ def far_field(g, field, ws=None, out=None):
     return out
 
 
-def amp_loss(g, intensity, meas_amp, ws=None, want_grad=True):
-    """msl_amp_loss: returns (loss float64 scalar tensor on the device, dL/dI or None)."""
+def amp_loss(g, intensity, meas_amp, ws=None, want_grad=True, loss=None, gI=None):
+    """msl_amp_loss: returns (loss float64 scalar tensor on the device, dL/dI or None);
+    ``loss`` and ``gI`` may be given as output buffers."""
     cg = geometry(g)
     dev = intensity.device
     if ws is None:
         ws = workspace(cg, 0, dev)
-    loss = torch.empty((), dtype=torch.float64, device=dev)
-    gI = torch.empty((cg.ny, cg.nz), dtype=torch.float32, device=dev) if want_grad else None
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+    if want_grad and gI is None:
+        gI = torch.empty((cg.ny, cg.nz), dtype=torch.float32, device=dev)
+    if not want_grad:
+        gI = None
     _check(lib().msl_amp_loss(ctypes.byref(cg), _ptr(intensity, torch.float32, (cg.ny, cg.nz), "intensity"),
                               _ptr(meas_amp, torch.float32, (cg.ny, cg.nz), "meas_amp"),
                               loss.data_ptr(), gI.data_ptr() if gI is not None else None,

@@ -55,7 +55,7 @@ class Reconstructor:
     """Holds the device state of one reconstruction (stacks, workspace, ADAM moments)."""
 
     def __init__(self, geom, known_delta, known_beta, region, counts, scale, probe=None, ckpt_every=32,
-                 adam: Adam | None = None, device="cuda:0"):
+                 adam: Adam | None = None, device="cuda:0", graphs=False):
         self.g = msl.geometry(geom)
         self.r = msl.region(region)
         self.adam = adam or Adam()
@@ -81,7 +81,12 @@ class Reconstructor:
         self.m = torch.zeros(box, dtype=torch.float32, device=dev)
         self.v = torch.zeros(box, dtype=torch.float32, device=dev)
         self.t = 0
-        self._gI = None
+        self._loss = torch.zeros((), dtype=torch.float64, device=dev)
+        self._gI = torch.zeros((ny, nz), dtype=torch.float32, device=dev)
+        # with graphs, the loss evaluation and the adjoint are each captured once in a HIP graph
+        # (thousands of kernel launches per iteration become one launch each)
+        self.graphs = graphs
+        self._g_loss = self._g_adj = None
 
     def set_theta(self, theta):
         """Start from theta (box values); resets the ADAM moments."""
@@ -91,21 +96,50 @@ class Reconstructor:
         self.t = 0
         msl.region_scatter(self.g, self.r, self.theta, self.D, self.B)
 
-    def loss(self):
-        """Forward model and amplitude loss of the current theta against sqrt(C / s): a device
-        float64 scalar, s times smaller than the detector loss."""
+    def _loss_calls(self):
         msl.pack_slices(self.g, self.D, self.B, self.ws)
         msl.forward(self.g, self.D, self.B, self.probe, self.k, ws=self.ws, out=self.field, ckpt=self.ck,
                     reuse_pack=True)
         msl.far_field(self.g, self.field, ws=self.ws, out=self.I)
-        loss, self._gI = msl.amp_loss(self.g, self.I, self.meas, ws=self.ws)
-        return loss
+        msl.amp_loss(self.g, self.I, self.meas, ws=self.ws, loss=self._loss, gI=self._gI)
 
-    def gradient_step(self):
-        """Adjoint of the last ``loss()`` and one ADAM step on theta."""
+    def _adjoint_calls(self):
         msl.far_field_adjoint(self.g, self.field, self._gI, ws=self.ws, out=self.gpsi)
         msl.adjoint(self.g, self.D, self.B, self.ck, self.k, self.gpsi, probe=self.probe, ws=self.ws,
                     gd=self.gd, gb=self.gb, want_probe=False, reuse_pack=True)
+
+    def _capture(self, calls):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                calls()
+        torch.cuda.current_stream().wait_stream(s)
+        return graph
+
+    def _run(self, which):
+        calls = self._loss_calls if which == "loss" else self._adjoint_calls
+        if not self.graphs:
+            calls()
+            return
+        attr = "_g_loss" if which == "loss" else "_g_adj"
+        if getattr(self, attr) is None:
+            calls()            # eager once (warms every table and stream), then capture
+            torch.cuda.synchronize()
+            setattr(self, attr, self._capture(calls))
+            torch.cuda.synchronize()
+        getattr(self, attr).replay()
+
+    def loss(self):
+        """Forward model and amplitude loss of the current theta against sqrt(C / s): a device
+        float64 scalar, s times smaller than the detector loss."""
+        self._run("loss")
+        return self._loss
+
+    def gradient_step(self):
+        """Adjoint of the last ``loss()`` and one ADAM step on theta."""
+        self._run("adjoint")
         self.t += 1
         msl.region_adam_step(self.g, self.r, self.adam.c(), self.t, self.gd, self.gb, self.theta, self.m,
                              self.v, self.D, self.B, grad_scale=self.scale)
@@ -113,9 +147,7 @@ class Reconstructor:
     def stack_gradients(self):
         """(dL/d delta, dL/d beta) of the last ``loss()``, for the detector loss (scaled by s
         inside the ADAM step, not here); runs the adjoint without updating theta."""
-        msl.far_field_adjoint(self.g, self.field, self._gI, ws=self.ws, out=self.gpsi)
-        msl.adjoint(self.g, self.D, self.B, self.ck, self.k, self.gpsi, probe=self.probe, ws=self.ws,
-                    gd=self.gd, gb=self.gb, want_probe=False, reuse_pack=True)
+        self._run("adjoint")
         return self.gd, self.gb
 
     def snap(self, levels):
@@ -179,12 +211,13 @@ def make_problem(seed_gt=4242, seed_noise=4243, n=256, n_slices=1024, photons=1e
 
 
 def seconds_to_threshold(p: Problem, init, factor=1.10, max_iters=5000, adam: Adam | None = None, ckpt_every=32,
-                         log_every=0):
+                         log_every=0, graphs=True):
     """Plain reconstruction from `init`: time to the first iterate whose loss is <= factor * L(truth)."""
     R = Reconstructor(p.geom, p.known_delta, p.known_beta, p.region, p.counts, p.scale, ckpt_every=ckpt_every,
-                      adam=adam)
+                      adam=adam, graphs=graphs)
     R.set_theta(p.truth)
     L_truth = float(R.loss().item()) * p.scale
+    R.stack_gradients()   # the adjoint graph is captured here, before the clock starts
     res = R.run(init, max_iters, factor * L_truth, log_every=log_every)
     return L_truth, res
 
@@ -204,15 +237,16 @@ def learned_initial_guess(net, p: Problem):
 
 
 def seconds_to_threshold_learned(p: Problem, net, plain_init, factor=1.10, max_iters=5000, adam: Adam | None = None,
-                                 ckpt_every=32, log_every=0):
+                                 ckpt_every=32, log_every=0, graphs=True):
     """Learned start with an error judge: network inference, then the losses of the learned and the
     plain start are compared and ADAM runs from the lower one (the plain start is the fallback when
     the learned guess is worse or not finite).  The reported seconds include inference and judging.
     Returns (L_truth, result, chose_learned, loss_learned, loss_plain)."""
     R = Reconstructor(p.geom, p.known_delta, p.known_beta, p.region, p.counts, p.scale, ckpt_every=ckpt_every,
-                      adam=adam)
+                      adam=adam, graphs=graphs)
     R.set_theta(p.truth)
     L_truth = float(R.loss().item()) * p.scale
+    R.stack_gradients()   # the adjoint graph is captured here, before the clock starts
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     guess = learned_initial_guess(net, p)

@@ -153,3 +153,18 @@ def test_region_snap_matches_the_oracle_bitwise(M):
     ref = RO.snap(th, levels)
     assert np.array_equal(T.cpu().numpy(), ref)
     assert np.array_equal(D.cpu().numpy()[RO.box_slices(REGION)], ref)
+
+
+def test_reconstruction_from_captured_graphs_equals_eager(M):
+    # the loss evaluation and the adjoint captured once as HIP graphs and replayed every iteration
+    # (with the eager ADAM step, loss read-backs and synchronisations between replays) give
+    # bit-identical losses and parameters
+    from paper_2212_01253_amd import recon
+    g, region, kd, kb, counts, s, truth, init = _small_problem()
+    out = []
+    for graphs in (False, True):
+        R = recon.Reconstructor(g, kd, kb, region, counts, s, ckpt_every=8, adam=recon.Adam(), graphs=graphs)
+        res = R.run(init, 6)
+        out.append((res.losses, R.theta.cpu().numpy()))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
