@@ -220,6 +220,37 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
                              void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Object rotation [Eq. 2-3; Sec. 2]: the paper rotates the sample's index
+ * volume into the lab frame (pitch by the incidence angle about the
+ * horizontal axis, yaw by the in-plane angle about the surface normal) and
+ * propagates a straight beam through it.  This library's default reading
+ * tilts the beam instead (see the probe above); this call builds the literal
+ * lab-frame stack for comparison or for angles the tilt does not cover.
+ *
+ * Axes in library order (slice axis a = the paper's Z, row y = Y, column
+ * z = X).  A lab voxel (s, j, l) sits at u = (s dx, j dy, l dz) - lab_pivot;
+ * its sample-frame position is v = M u + sample_pivot with M the product of
+ * the paper's pitch and yaw matrices in this axis order,
+ *   a' =  cos(p) cos(w) a + sin(p) y - cos(p) sin(w) z
+ *   y' = -sin(p) cos(w) a + cos(p) y + sin(p) sin(w) z
+ *   z' =  sin(w) a                   + cos(w) z
+ * (p = pitch, w = yaw; with p > 0 the sample surface rises along the beam),
+ * and delta, beta there are trilinear interpolates of the sample volume
+ * (voxel (i, j, k) of the sample at (i da, j dy, k dz); zero outside it). */
+typedef struct {
+  int32_t na, ny, nz;                /* sample voxels along a (beam-wise length), y (normal), z */
+  double da_nm, dy_nm, dz_nm;        /* sample voxel pitch (nm), > 0 */
+  double pivot_a_nm, pivot_y_nm, pivot_z_nm;  /* sample pivot, nm from voxel (0, 0, 0) */
+} msl_sample_grid;
+
+/* delta, beta float32 [g->n_slices][g->ny][g->nz] (lab frame, written) from
+ * delta_s, beta_s float32 [s->na][s->ny][s->nz] (sample frame). */
+msl_status msl_rotate_object(const msl_geometry* g, double lab_pivot_a_nm, double lab_pivot_y_nm,
+                             double lab_pivot_z_nm, const msl_sample_grid* s, double pitch_rad, double yaw_rad,
+                             const float* delta_s, const float* beta_s, float* delta, float* beta,
+                             void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Reconstruction support [Sec. 4.1]: the paper refines a 3-D object by
  * minimising the amplitude loss of Eq. (4) with gradients and the ADAM
  * optimiser (Kingma and Ba, 2014).  The unknowns here are the delta values of

@@ -149,6 +149,36 @@ def forward_exact_index(geom, delta, beta, probe=None):
     return psi
 
 
+def rotation_matrix(pitch, yaw):
+    """Sample-frame offset of a lab-frame offset, axes in library order (slice axis a = the paper's
+    Z, row y = Y, column z = X): the paper's pitch and yaw rotations (Eq. 2-3) applied to the lab
+    position, R_pitch(pitch) R_yaw(yaw) in (X, Y, Z), re-indexed to (Z, Y, X)."""
+    cp, sp, cw, sw = math.cos(pitch), math.sin(pitch), math.cos(yaw), math.sin(yaw)
+    return np.array([[cp * cw, sp, -cp * sw],
+                     [-sp * cw, cp, sp * sw],
+                     [sw, 0.0, cw]])
+
+
+def rotate_object(geom, lab_pivot, sample, pitch, yaw, delta_s, beta_s):
+    """Lab-frame slice stacks [Ns][ny][nz] of a sample-frame volume (Eq. 2-3 taken literally):
+    lab voxel (s, j, l) at u = (s dx, j dy, l dz) - lab_pivot takes the trilinear interpolate of the
+    sample volume at M u + sample pivot (sample voxel (i, j, k) at (i da, j dy, k dz), zero outside)."""
+    from scipy.ndimage import map_coordinates
+    ns, ny, nz = int(_g(geom, "n_slices")), int(_g(geom, "ny")), int(_g(geom, "nz"))
+    d = [float(_g(geom, "dx_nm")), float(_g(geom, "dy_nm")), float(_g(geom, "dz_nm"))]
+    S, J, L = np.meshgrid(np.arange(ns), np.arange(ny), np.arange(nz), indexing="ij")
+    u = np.stack([S * d[0] - lab_pivot[0], J * d[1] - lab_pivot[1], L * d[2] - lab_pivot[2]])
+    M = rotation_matrix(pitch, yaw)
+    v = np.einsum("ij,j...->i...", M, u)
+    piv = [sample["pivot_a_nm"], sample["pivot_y_nm"], sample["pivot_z_nm"]]
+    pit = [sample["da_nm"], sample["dy_nm"], sample["dz_nm"]]
+    idx = np.stack([(v[i] + piv[i]) / pit[i] for i in range(3)])
+    out = []
+    for vol in (delta_s, beta_s):
+        out.append(map_coordinates(np.asarray(vol, np.float64), idx, order=1, mode="grid-constant", cval=0.0))
+    return out[0], out[1]
+
+
 def _fft2(x):
     return sfft.fft2(x, workers=WORKERS)
 

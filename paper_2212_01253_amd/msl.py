@@ -23,7 +23,7 @@ SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
 EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_pack_slices", "msl_forward",
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
            "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
-           "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap")
+           "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap", "msl_rotate_object")
 
 
 class CGeometry(ctypes.Structure):
@@ -47,6 +47,13 @@ class CAdam(ctypes.Structure):
 
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("lo", ctypes.c_float), ("hi", ctypes.c_float)]
+
+
+class CSampleGrid(ctypes.Structure):
+    """Mirror of msl_sample_grid."""
+
+    _fields_ = [("na", c_int32), ("ny", c_int32), ("nz", c_int32), ("da_nm", c_double), ("dy_nm", c_double),
+                ("dz_nm", c_double), ("pivot_a_nm", c_double), ("pivot_y_nm", c_double), ("pivot_z_nm", c_double)]
 
 
 class CInstance(ctypes.Structure):
@@ -98,6 +105,9 @@ def lib():
     L.msl_set_schedule.argtypes = [c_int32]
     L.msl_last_error.restype = ctypes.c_char_p
     L.msl_last_error.argtypes = []
+    L.msl_rotate_object.restype = c_int32
+    L.msl_rotate_object.argtypes = [G, c_double, c_double, c_double, ctypes.POINTER(CSampleGrid), c_double, c_double,
+                                    P, P, P, P, P]
     Ip = ctypes.POINTER(CInstance)
     L.msl_batch_workspace_bytes.restype = c_size_t
     L.msl_batch_workspace_bytes.argtypes = [Ip, c_int32]
@@ -438,3 +448,24 @@ def forward_batch(items, ws=None):
         ws = batch_workspace(items)
     _check(lib().msl_forward_batch(arr, len(items), ws.data_ptr(), ws.numel(), _stream()))
     return ws
+
+
+def rotate_object(g, lab_pivot, sample_grid, pitch_rad, yaw_rad, delta_s, beta_s, delta=None, beta=None):
+    """msl_rotate_object: lab-frame stacks [Ns][ny][nz] from a sample-frame volume; sample_grid is a
+    CSampleGrid or a dict of its fields; lab_pivot = (a, y, z) in nm."""
+    cg = geometry(g)
+    sg = sample_grid if isinstance(sample_grid, CSampleGrid) else CSampleGrid(**sample_grid)
+    dev = delta_s.device
+    shape = (cg.n_slices, cg.ny, cg.nz)
+    if delta is None:
+        delta = torch.empty(shape, dtype=torch.float32, device=dev)
+    if beta is None:
+        beta = torch.empty(shape, dtype=torch.float32, device=dev)
+    sshape = (sg.na, sg.ny, sg.nz)
+    _check(lib().msl_rotate_object(ctypes.byref(cg), float(lab_pivot[0]), float(lab_pivot[1]), float(lab_pivot[2]),
+                                   ctypes.byref(sg), float(pitch_rad), float(yaw_rad),
+                                   _ptr(delta_s, torch.float32, sshape, "delta_s"),
+                                   _ptr(beta_s, torch.float32, sshape, "beta_s"),
+                                   _ptr(delta, torch.float32, shape, "delta"),
+                                   _ptr(beta, torch.float32, shape, "beta"), _stream()))
+    return delta, beta

@@ -207,3 +207,16 @@ def test_nn_entry_points_validate(L):
     assert N.msl_nn_adam(8, FAKE, FAKE, FAKE, FAKE, None, 1e-3, 1.0, 0.999, 1e-8, 1, None) == msl.ERR_ARG
     assert N.msl_nn_adam(8, FAKE, FAKE, FAKE, FAKE, None, 1e-3, 0.9, 0.999, 1e-8, 0, None) == msl.ERR_ARG
     assert N.msl_nn_mse(0, FAKE, FAKE, None, FAKE, None) == msl.ERR_ARG
+
+
+def test_rotation_validates(L):
+    g = G()
+    R = ctypes.byref
+    ok = msl.CSampleGrid(4, 4, 4, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0)
+    assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, None, 0.0, 0.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    bad = msl.CSampleGrid(0, 4, 4, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0)
+    assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, R(bad), 0.0, 0.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    bad = msl.CSampleGrid(4, 4, 4, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)
+    assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, R(bad), 0.0, 0.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, R(ok), float("nan"), 0.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, R(ok), 0.0, 0.0, FAKE + 1, FAKE, FAKE, FAKE, None) == msl.ERR_ARG

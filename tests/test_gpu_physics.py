@@ -45,7 +45,7 @@ def fresnel_averaged(alpha, w0, k):
 
 
 @pytest.fixture(scope="module")
-def M():
+def M():   # the binding module
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -89,3 +89,62 @@ def test_fresnel_reflectivity_on_the_gpu(M, alpha_deg):
     assert abs(R - R1) < 1e-3
     # measured: |R - Fresnel| <= 0.0073 (at 0.24 deg, on the steep edge above the critical angle)
     assert abs(R - RF) < 0.02
+
+
+def test_object_rotation_matches_the_oracle(M):
+    import torch
+    rng = np.random.default_rng(3)
+    s = {"na": 40, "ny": 30, "nz": 20, "da_nm": 5.0, "dy_nm": 1.0, "dz_nm": 1.5,
+         "pivot_a_nm": 100.0, "pivot_y_nm": 12.0, "pivot_z_nm": 15.0}
+    d_s = rng.random((40, 30, 20)).astype(np.float32)
+    b_s = rng.random((40, 30, 20)).astype(np.float32)
+    g = synth.Geometry(32, 16, 48, 1.0, 1.0, 4.0, 0.1, 0.0, 0)
+    lab_pivot = (96.0, 14.0, 8.0)
+    for pitch, yaw in [(0.0, 0.0), (0.02, 0.0), (0.01, 0.3), (-0.05, -1.0)]:
+        dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        dl, bl = M.rotate_object(g, lab_pivot, s, pitch, yaw, dev(d_s), dev(b_s))
+        torch.cuda.synchronize()
+        rd, rb = O.rotate_object(g, lab_pivot, s, pitch, yaw, d_s, b_s)
+        # float32 positions and weights: agreement to ~1e-5 of the unit-range values
+        assert np.max(np.abs(dl.cpu().numpy() - rd)) <= 2e-5, (pitch, yaw)
+        assert np.max(np.abs(bl.cpu().numpy() - rb)) <= 2e-5, (pitch, yaw)
+        assert np.any(rd > 0) and np.any(rd == 0)   # the sample covers part of the lab box
+
+
+@pytest.mark.parametrize("alpha_deg", [0.12, 0.18, 0.24, 0.30])
+def test_fresnel_reflectivity_with_the_object_tilted(M, alpha_deg):
+    """Eq. 2-3 taken literally: a straight Gaussian beam and the flat substrate pitched by the
+    incidence angle (msl_rotate_object) reflect the Fresnel fraction too, into the specular
+    direction 2 alpha above the direct beam (the beam-tilt reading gives the same physics)."""
+    import torch
+    ny, nz, dy, dx, lam, w0, h0 = 1024, 16, 2.0, 50.0, 0.1, 75.0, 150.0
+    a = math.radians(alpha_deg)
+    k = 2 * math.pi / lam
+    ns = int(math.ceil((2 * h0 + 3 * w0) / math.tan(a) / dx))
+    g = synth.Geometry(ny, nz, ns, dy, 1.0, dx, lam, 0.0, 0)
+    # the sample: a substrate below y' = 2000 nm, uniform along the beam and across (two voxels
+    # a billion nm apart along those axes); lab row 300 nm is the surface at the first slice
+    nys = 1600
+    sd = np.zeros((2, nys, 2), np.float32)
+    sb = np.zeros_like(sd)
+    sd[:, :1000] = SUB_D
+    sb[:, :1000] = SUB_B
+    s = {"na": 2, "ny": nys, "nz": 2, "da_nm": 1e9, "dy_nm": dy, "dz_nm": 1e9,
+         "pivot_a_nm": 0.0, "pivot_y_nm": 2000.0, "pivot_z_nm": 0.0}
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    D, B = M.rotate_object(g, (0.0, 300.0, 0.0), s, a, 0.0, dev(sd), dev(sb))
+    sponge = 128   # lab-frame absorbing rows: the refracted beam must not wrap round
+    ramp = (1e-4 * np.cos(0.5 * math.pi * np.arange(sponge) / sponge) ** 2).astype(np.float32)
+    B[:, :sponge, :] += dev(ramp).view(1, sponge, 1)
+    probe = synth.gaussian_probe(g, w0, 300.0 + h0)
+    f, _ = M.forward(g, D, B, dev(probe))
+    I = M.far_field(g, f).cpu().numpy().astype(np.float64)
+    m = k * math.sin(a) * ny * dy / (2 * math.pi)     # rows between the direct and the tilt direction
+    R = float(I[int(round(ny // 2 + m)) + 1:].sum() / np.sum(np.abs(probe.astype(np.complex128)) ** 2))
+    RF = fresnel_averaged(a, w0, k)
+    peak = int(np.argmax(I.sum(axis=1)))
+    print(f"alpha {alpha_deg} deg: R {R:.4f}, Fresnel {RF:.4f}, brightest row {peak}, specular {ny // 2 + 2 * m:.1f}")
+    # measured |R - Fresnel| <= 0.0065
+    assert abs(R - RF) < 0.02
+    if RF > 0.5:
+        assert abs(peak - (ny // 2 + 2 * m)) <= 6
