@@ -293,6 +293,17 @@ msl_status msl_region_scatter(const msl_geometry* g, const msl_region* r, const 
 msl_status msl_region_snap(const msl_geometry* g, const msl_region* r, const float* levels, int32_t n_levels,
                            float* theta, float* delta, float* beta, void* hip_stream);
 
+/* Shrink-wrap support [Sec. 4.1, with Marchesini et al. 2003]: the box
+ * parameters are blurred with a separable Gaussian (standard deviations
+ * sigma_a, sigma_y, sigma_z in voxels, >= 0; kernel truncated at
+ * radius floor(3 sigma + 1/2), normalised, zero outside the box), every
+ * parameter whose blurred |theta| is not above threshold times the largest
+ * blurred value is set to 0, and the result is scattered as above.
+ * scratch: float32, 2 * ns * ny * nz + 1024 values (device). */
+msl_status msl_region_shrinkwrap(const msl_geometry* g, const msl_region* r, float sigma_a, float sigma_y,
+                                 float sigma_z, float threshold, float* theta, float* scratch, float* delta,
+                                 float* beta, void* hip_stream);
+
 msl_status msl_region_adam_step(const msl_geometry* g, const msl_region* r, const msl_adam* a,
                                 int32_t t, float grad_scale,
                                 const float* grad_delta, const float* grad_beta,

@@ -18,6 +18,9 @@ What it computes:
   followed by a clamp of the parameters to a box [lo, hi] (delta >= 0 is the
   physical range of an index decrement of these materials).
 * ``snap``: the paper's nearest-refractive-index filter on the parameters.
+* ``shrinkwrap``: the shrink-wrap support (Marchesini et al. 2003, cited in
+  Sec. 4.1): blur |theta| with a Gaussian, keep what exceeds a fraction of
+  the largest blurred value.
 * ``poisson_loss_scale``: the detector model of the reconstruction workload
   compares sqrt(s * I) with sqrt(counts) for the fixed photon scale s; that
   loss is s times the amplitude loss of I against sqrt(counts / s).
@@ -82,3 +85,14 @@ def snap(theta, levels):
     t = np.asarray(theta, np.float32)[..., None]
     lv = np.asarray(levels, np.float32)
     return lv[np.argmin(np.abs(t - lv), axis=-1)]
+
+
+def shrinkwrap(theta, sigmas, threshold):
+    """(theta with zeros outside the support, blurred |theta|) for the shrink-wrap support."""
+    from scipy.ndimage import gaussian_filter1d
+    b = np.abs(np.asarray(theta, np.float64))
+    for axis, sg in enumerate(sigmas):
+        if sg > 0:
+            b = gaussian_filter1d(b, sg, axis=axis, mode="constant", cval=0.0, truncate=3.0)
+    keep = b > threshold * b.max()
+    return np.where(keep, theta, 0.0), b

@@ -85,6 +85,71 @@ __global__ void __launch_bounds__(256) k_rotate(Rot r, const float* __restrict__
   }
 }
 
+// ---- shrink-wrap: separable Gaussian blur of |theta|, global max, threshold mask
+
+struct Blur {
+  int n[3];          // box extents (a, y, z)
+  int axis, radius;
+  float w[64];       // normalised weights w[0 .. radius]
+};
+
+__global__ void __launch_bounds__(256) k_blur(Blur b, int take_abs, const float* __restrict__ in,
+                                              float* __restrict__ out) {
+  const int64_t total = (int64_t)b.n[0] * b.n[1] * b.n[2];
+  const int64_t stride = b.axis == 0 ? (int64_t)b.n[1] * b.n[2] : (b.axis == 1 ? b.n[2] : 1);
+  const int len = b.n[b.axis];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int pos = (int)((e / stride) % len);
+    float acc = 0.0f;
+    for (int k = -b.radius; k <= b.radius; ++k) {
+      const int q = pos + k;
+      if (q < 0 || q >= len) continue;
+      const float v = in[e + (int64_t)k * stride];
+      acc = __builtin_fmaf(b.w[k < 0 ? -k : k], take_abs ? fabsf(v) : v, acc);
+    }
+    out[e] = acc;
+  }
+}
+
+// per-block maxima, then one block over them (max is order-independent)
+__global__ void __launch_bounds__(256) k_max_parts(int64_t n, const float* __restrict__ x, float* __restrict__ part) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, x[e]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(1024) k_max_final(int n, float* __restrict__ part) {
+  __shared__ float red[1024];
+  red[threadIdx.x] = (int)threadIdx.x < n ? part[threadIdx.x] : 0.0f;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[1023] = red[0];   // the maximum, read by k_wrap
+}
+
+__global__ void __launch_bounds__(256) k_wrap(Box b, float ratio, float thr, const float* __restrict__ blurred,
+                                              const float* __restrict__ part, float* __restrict__ theta,
+                                              float* __restrict__ delta, float* __restrict__ beta) {
+  const float cut = thr * part[1023];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float th = blurred[i] > cut ? theta[i] : 0.0f;
+    const int64_t e = box_to_stack(b, i);
+    theta[i] = th;
+    delta[e] = th;
+    beta[e] = ratio * th;
+  }
+}
+
 struct Levels {
   float v[MSL_MAX_LEVELS];
   int n;
@@ -213,6 +278,54 @@ msl_status msl_rotate_object(const msl_geometry* g, double lab_pivot_a_nm, doubl
   hipLaunchKernelGGL(k_rotate, dim3(elementwise_blocks(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), r,
                      delta_s, beta_s, delta, beta);
   return hip_check(hipGetLastError(), "rotation kernel");
+}
+
+msl_status msl_region_shrinkwrap(const msl_geometry* g, const msl_region* r, float sigma_a, float sigma_y,
+                                 float sigma_z, float threshold, float* theta, float* scratch, float* delta,
+                                 float* beta, void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  Box bx;
+  MSL_TRY(check_region(*g, r, bx));
+  const float sig[3] = {sigma_a, sigma_y, sigma_z};
+  for (int d = 0; d < 3; ++d)
+    if (!(std::isfinite(sig[d]) && sig[d] >= 0.0f && sig[d] <= 20.0f))
+      return fail(MSL_ERR_ARG, "shrink-wrap: sigmas must be in [0, 20] voxels");
+  if (!(std::isfinite(threshold) && threshold >= 0.0f && threshold < 1.0f))
+    return fail(MSL_ERR_ARG, "shrink-wrap: threshold must be in [0, 1)");
+  MSL_TRY(check_ptr(theta, 4, "theta"));
+  MSL_TRY(check_ptr(scratch, 4, "scratch"));
+  MSL_TRY(check_ptr(delta, 4, "delta"));
+  MSL_TRY(check_ptr(beta, 4, "beta"));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  float* b0 = scratch;
+  float* b1 = scratch + bx.n;
+  float* part = scratch + 2 * bx.n;
+  const unsigned blocks = elementwise_blocks(bx.n);
+  const float* src = theta;
+  float* dst = b0;
+  for (int d = 0; d < 3; ++d) {
+    Blur bl{};
+    bl.n[0] = r->ns;
+    bl.n[1] = r->ny;
+    bl.n[2] = r->nz;
+    bl.axis = d;
+    bl.radius = (int)(3.0f * sig[d] + 0.5f);
+    double wsum = 0.0, w[64];
+    for (int k = 0; k <= bl.radius; ++k) {
+      w[k] = sig[d] > 0.0f ? std::exp(-0.5 * (double)k * k / ((double)sig[d] * sig[d])) : (k == 0 ? 1.0 : 0.0);
+      wsum += k == 0 ? w[k] : 2.0 * w[k];
+    }
+    for (int k = 0; k <= bl.radius; ++k) bl.w[k] = (float)(w[k] / wsum);
+    hipLaunchKernelGGL(k_blur, dim3(blocks), dim3(256), 0, st, bl, d == 0 ? 1 : 0, src, dst);
+    src = dst;
+    dst = dst == b0 ? b1 : b0;
+  }
+  const unsigned mparts = blocks < 1023 ? blocks : 1023;
+  hipLaunchKernelGGL(k_max_parts, dim3(mparts), dim3(256), 0, st, bx.n, src, part);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(1024), 0, st, (int)mparts, part);
+  hipLaunchKernelGGL(k_wrap, dim3(blocks), dim3(256), 0, st, bx, r->beta_over_delta, threshold, src, part, theta, delta,
+                     beta);
+  return hip_check(hipGetLastError(), "shrink-wrap kernels");
 }
 
 msl_status msl_region_snap(const msl_geometry* g, const msl_region* r, const float* levels, int32_t n_levels,

@@ -23,7 +23,8 @@ SCHED_AUTO, SCHED_PER_PASS, SCHED_PERSISTENT = 0, 1, 2
 EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "msl_pack_slices", "msl_forward",
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
            "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
-           "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap", "msl_rotate_object")
+           "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap", "msl_rotate_object",
+           "msl_region_shrinkwrap")
 
 
 class CGeometry(ctypes.Structure):
@@ -116,6 +117,9 @@ def lib():
     R = ctypes.POINTER(CRegion)
     L.msl_region_scatter.restype = c_int32
     L.msl_region_scatter.argtypes = [G, R, P, P, P, P]
+    L.msl_region_shrinkwrap.restype = c_int32
+    L.msl_region_shrinkwrap.argtypes = [G, R, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        P, P, P, P, P]
     L.msl_region_snap.restype = c_int32
     L.msl_region_snap.argtypes = [G, R, ctypes.POINTER(ctypes.c_float), c_int32, P, P, P, P]
     L.msl_region_adam_step.restype = c_int32
@@ -394,6 +398,21 @@ def region_snap(g, r, levels, theta, delta, beta):
                                  _ptr(theta, torch.float32, (cr.ns, cr.ny, cr.nz), "theta"),
                                  _ptr(delta, torch.float32, stack, "delta"),
                                  _ptr(beta, torch.float32, stack, "beta"), _stream()))
+
+
+def region_shrinkwrap(g, r, sigmas, threshold, theta, delta, beta, scratch=None):
+    """Shrink-wrap support on theta (in place) and the scatter; sigmas = (a, y, z) in voxels."""
+    cg, cr = geometry(g), region(r)
+    stack = (cg.n_slices, cg.ny, cg.nz)
+    n = cr.ns * cr.ny * cr.nz
+    if scratch is None:
+        scratch = torch.empty(2 * n + 1024, dtype=torch.float32, device=theta.device)
+    _check(lib().msl_region_shrinkwrap(ctypes.byref(cg), ctypes.byref(cr), float(sigmas[0]), float(sigmas[1]),
+                                       float(sigmas[2]), float(threshold),
+                                       _ptr(theta, torch.float32, (cr.ns, cr.ny, cr.nz), "theta"),
+                                       _ptr(scratch, torch.float32, (2 * n + 1024,), "scratch"),
+                                       _ptr(delta, torch.float32, stack, "delta"),
+                                       _ptr(beta, torch.float32, stack, "beta"), _stream()))
 
 
 def region_adam_step(g, r, adam, t, grad_delta, grad_beta, theta, m, v, delta, beta, grad_scale=1.0):

@@ -154,10 +154,18 @@ class Reconstructor:
         """The paper's nearest-index filter: theta <- nearest of `levels` (resets nothing else)."""
         msl.region_snap(self.g, self.r, levels, self.theta, self.D, self.B)
 
-    def run(self, theta0, max_iters, threshold=None, log_every=0, snap_levels=None, snap_every=0):
+    def shrinkwrap(self, sigmas, threshold):
+        """Shrink-wrap support on theta: zero where the blurred |theta| is not above threshold x max."""
+        if getattr(self, "_sw_scratch", None) is None:
+            self._sw_scratch = torch.empty(2 * self.theta.numel() + 1024, dtype=torch.float32, device=self.theta.device)
+        msl.region_shrinkwrap(self.g, self.r, sigmas, threshold, self.theta, self.D, self.B, self._sw_scratch)
+
+    def run(self, theta0, max_iters, threshold=None, log_every=0, snap_levels=None, snap_every=0,
+            wrap_every=0, wrap_sigmas=(0.0, 1.5, 1.5), wrap_threshold=0.1):
         """ADAM from theta0 until the loss is <= threshold or max_iters steps; wall-clock timed.
         With snap_levels and snap_every, every snap_every-th step is followed by the
-        nearest-index filter (the paper applies it after 20 epochs)."""
+        nearest-index filter (the paper applies it after 20 epochs); with wrap_every, every
+        wrap_every-th step by the shrink-wrap support (the paper: every 20 epochs)."""
         res = ReconResult(threshold=threshold)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -178,6 +186,8 @@ class Reconstructor:
             self.gradient_step()
             if snap_levels is not None and snap_every and self.t % snap_every == 0:
                 self.snap(snap_levels)
+            if wrap_every and self.t % wrap_every == 0:
+                self.shrinkwrap(wrap_sigmas, wrap_threshold)
         return res
 
 

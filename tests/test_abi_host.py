@@ -220,3 +220,13 @@ def test_rotation_validates(L):
     assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, R(bad), 0.0, 0.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
     assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, R(ok), float("nan"), 0.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
     assert L.msl_rotate_object(R(g), 0.0, 0.0, 0.0, R(ok), 0.0, 0.0, FAKE + 1, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+
+
+def test_shrinkwrap_validates(L):
+    g = G(n_slices=8)
+    ok = msl.CRegion(0, 8, 2, 4, 0, 64, 0.05)
+    R = ctypes.byref
+    assert L.msl_region_shrinkwrap(R(g), R(ok), -1.0, 1.0, 1.0, 0.2, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_region_shrinkwrap(R(g), R(ok), 1.0, 21.0, 1.0, 0.2, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_region_shrinkwrap(R(g), R(ok), 1.0, 1.0, 1.0, 1.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert L.msl_region_shrinkwrap(R(g), R(ok), 1.0, 1.0, 1.0, 0.2, FAKE, None, FAKE, FAKE, None) == msl.ERR_ARG

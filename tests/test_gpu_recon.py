@@ -168,3 +168,21 @@ def test_reconstruction_from_captured_graphs_equals_eager(M):
         out.append((res.losses, R.theta.cpu().numpy()))
     assert out[0][0] == out[1][0]
     assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_region_shrinkwrap_matches_the_oracle(M):
+    import torch
+    rng = np.random.default_rng(11)
+    th = (rng.random((5, 24, 50)) * 3e-5).astype(np.float32)
+    th[:, :, 20:30] *= 8.0                       # a bright band: the support forms around it
+    D = dev(rng.random((9, 64, 64)).astype(np.float32))
+    B = dev(rng.random((9, 64, 64)).astype(np.float32))
+    T = dev(th)
+    M.region_shrinkwrap(GEOM, REGION, (1.0, 1.5, 2.0), 0.3, T, D, B)
+    torch.cuda.synchronize()
+    ref, blur = RO.shrinkwrap(th.astype(np.float64), (1.0, 1.5, 2.0), 0.3)
+    got = T.cpu().numpy()
+    band = np.abs(blur - 0.3 * blur.max()) <= 1e-5 * blur.max()   # float32 blur may decide either way
+    assert np.array_equal(got[~band], ref[~band].astype(np.float32))
+    assert 0 < np.count_nonzero(got) < got.size
+    assert np.array_equal(D.cpu().numpy()[RO.box_slices(REGION)], got)

@@ -110,3 +110,21 @@ def test_snap_picks_the_nearest_level_by_brute_force():
         dists = [abs(float(np.float32(t) - np.float32(l))) for l in levels]
         best = min(range(len(levels)), key=lambda i: (dists[i], i))
         assert s == np.float32(levels[best])
+
+
+def test_shrinkwrap_properties():
+    rng = np.random.default_rng(10)
+    th = rng.standard_normal((6, 10, 12))
+    # no blur: the support is |theta| above the fraction of its maximum
+    out, b = R.shrinkwrap(th, (0, 0, 0), 0.4)
+    assert np.array_equal(out, np.where(np.abs(th) > 0.4 * np.abs(th).max(), th, 0.0))
+    # the blur of an interior impulse keeps its sum and is symmetric
+    imp = np.zeros((21, 21, 21))
+    imp[10, 10, 10] = 1.0
+    _, b = R.shrinkwrap(imp, (1.5, 2.0, 1.0), 0.0)
+    assert b.sum() == pytest.approx(1.0, rel=1e-12)
+    assert np.allclose(b, b[::-1, ::-1, ::-1]) and b[10, 10, 10] == b.max()
+    # a higher threshold keeps a subset
+    lo, _ = R.shrinkwrap(th, (1.0, 1.0, 1.0), 0.2)
+    hi, _ = R.shrinkwrap(th, (1.0, 1.0, 1.0), 0.5)
+    assert np.all((hi != 0) <= (lo != 0)) and np.count_nonzero(hi) < np.count_nonzero(lo)
