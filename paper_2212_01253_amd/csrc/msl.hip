@@ -824,6 +824,24 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     rv.ckpt_c = ck + (int64_t)c * k.c.m;
     return rv;
   };
+  if (ckpt_every == 1) {
+    // every entrance field is a checkpoint: one reverse sweep reads them
+    // directly (row-major), nothing is recomputed
+    PhaseSpec rv = blank_phase(k, msl::PH_REV);
+    rv.s0 = 0;
+    rv.s1 = ns;
+    rv.leading = 1;
+    rv.field = G;
+    rv.fieldT = GT;
+    rv.seg = const_cast<float2*>(ck) + k.c.m;   // slice s >= 1 at ck[s] (only read)
+    rv.ckpt_c = ck;
+    rv.seg_row_major = 1;
+    MSL_TRY(load_phase_input(k, rv, reinterpret_cast<const float2*>(grad_field)));
+    MSL_TRY(run_phase(k, rv));
+    MSL_TRY(unpack_odd_range(k, 0, nodd, k.st));
+    if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));
+    return MSL_OK;
+  }
   // Segment c-1 is recomputed from its checkpoint while the reverse sweep runs
   // over segment c: the two fields are independent, so on square grids they
   // share passes (and each pass has twice the lines to spread over the chip).

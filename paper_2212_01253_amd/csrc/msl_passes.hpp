@@ -55,6 +55,8 @@ struct PhaseSpec {
   const float2* ckpt_c;  // PH_REV: psi_{s0}
   const float2* ff_src;  // PH_FF, PH_FFADJ: input field (row-major)
   int inplace;        // 1: every pass reads and writes `field` row-major (column passes strided)
+  int seg_row_major;  // PH_REV: `seg` holds row-major fields (the forward's checkpoints) instead of
+                      // fields in the layout of each slice's pass axis (the recompute's segment)
 };
 
 __host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
@@ -205,7 +207,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
           d.load_lay = LAY_R;
         } else {
           d.psi_load = ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
-          d.load_lay = native_lay(axis);
+          d.load_lay = ph.seg_row_major ? LAY_R : native_lay(axis);
         }
         d.post = s == 0 ? POST_NONE : POST_PROP;
         return d;

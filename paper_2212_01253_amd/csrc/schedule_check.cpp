@@ -331,14 +331,22 @@ int check(const Geo& g, int kck) {
     load_input(rc, ckpt.f[c], W.f[0], WT.f[0]);
     run_phase(E, rc);
   };
-  {
+  if (kck == 1) {
+    // the library's direct sweep: every entrance field is a checkpoint, read row-major
+    msl::PhaseSpec rv{};
+    rv.kind = msl::PH_REV; rv.exact = g.exact; rv.s0 = 0; rv.s1 = g.ns; rv.ns = g.ns; rv.m = m;
+    rv.leading = 1; rv.field = fake(4); rv.fieldT = fake(8);
+    rv.seg = fake(1) + m; rv.ckpt_c = fake(1); rv.seg_row_major = 1;
+    load_input(rv, G.f[0], G.f[0], GT.f[0]);
+    run_phase(E, rv);
+  } else {
     msl::PhaseSpec first{};
     first.kind = msl::PH_REV; first.exact = g.exact; first.ns = g.ns; first.leading = 1;
     first.s0 = (nck - 1) * kck; first.s1 = g.ns;
     load_input(first, G.f[0], G.f[0], GT.f[0]);
   }
-  recomp(nck - 1);
-  for (int c = nck - 1; c >= 0; --c) {
+  if (kck > 1) recomp(nck - 1);
+  for (int c = nck - 1; c >= 0 && kck > 1; --c) {
     const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
     msl::PhaseSpec rv{};
     rv.kind = msl::PH_REV; rv.exact = g.exact; rv.s0 = s0; rv.s1 = s1; rv.ns = g.ns; rv.m = m;
