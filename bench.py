@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction seconds-to-loss leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initialiser leg")
+    ap.add_argument("--no-every-slice", action="store_true",
+                    help="skip the extra timing with a checkpoint at every slice (no recompute)")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
                     help="also time the batched forward over N instances of the batched workload (96 = full)")
     args = ap.parse_args()
@@ -300,6 +302,36 @@ def main():
         "forward_throughput": {"value": vs / (fwd_path_ms / 1e3), "unit": "voxel-slice-steps/s",
                                "ms": fwd_path_ms},
     }
+    if not args.no_every_slice and k != 1:
+        # the same step with a checkpoint at every slice: the adjoint reads the stored
+        # fields and skips the recompute, at Ns Ny Nz complex values of checkpoint memory
+        del ck
+        torch.cuda.empty_cache()
+        ws1 = msl.workspace(g, 1, dev)
+        ck1 = torch.empty((msl.checkpoint_count(g, 1), ny, nz), dtype=torch.complex64, device=dev)
+
+        def step1():
+            msl.pack_slices(g, D, B, ws1)
+            msl.forward(g, D, B, None, 1, ws=ws1, out=field, ckpt=ck1, reuse_pack=True)
+            msl.far_field(g, field, ws=ws1, out=I)
+            _, gI1 = msl.amp_loss(g, I, Mm, ws=ws1)
+            msl.far_field_adjoint(g, field, gI1, ws=ws1, out=gpsi)
+            msl.adjoint(g, D, B, ck1, 1, gpsi, ws=ws1, gd=gd, gb=gb, want_probe=True, reuse_pack=True)
+
+        for _ in range(args.warmup):
+            step1()
+        torch.cuda.synchronize()
+        t_start.record()
+        for _ in range(args.steps):
+            step1()
+        t_end.record()
+        torch.cuda.synchronize()
+        ms1 = t_start.elapsed_time(t_end) / args.steps
+        out["every_slice_checkpointed"] = {"ckpt_every": 1, "ms_per_step": ms1, "value": vs / (ms1 / 1e3),
+                                           "checkpoint_bytes": ck1.numel() * 8}
+        print(f"# checkpoint at every slice: {ms1:.3f} ms/step", file=sys.stderr, flush=True)
+        del ck1, ws1
+        torch.cuda.empty_cache()
     if args.batch:
         print(f"# batched forward ({args.batch} instances) ...", file=sys.stderr, flush=True)
         out["batch"] = batch_leg(args.batch)
