@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define MSL_ABI_VERSION 2
+#define MSL_ABI_VERSION 3
 
 typedef struct { float re, im; } msl_c64;
 
@@ -184,6 +184,42 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
  * (process-wide; not synchronised with calls running on other threads).
  * Returns the previous setting, or MSL_ERR_ARG for an unknown value. */
 int32_t msl_set_schedule(int32_t schedule);
+
+/* ---- launch shape and its autotuner ----
+ * The line passes run as workgroups of several lines each.  Entry e of
+ * lines_per_group is the number of 2^e-point lines per workgroup (e = 4..10;
+ * 0 = the library default: one 64-lane wavefront's worth of lanes; other
+ * entries must be 0).  Allowed values are powers of two up to the limit set by
+ * the 256-thread workgroup and the workgroup's line buffers in LDS:
+ * 2^e = 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2, 1024: 1.
+ * batch_streams: how many grid-size groups msl_forward_batch runs side by side
+ * (1..4; 0 = 4).  The setting is process-wide, applies to later calls, and is
+ * not synchronised with calls running on other threads. */
+#define MSL_TUNE_SLOTS 11
+typedef struct {
+  int32_t lines_per_group[MSL_TUNE_SLOTS];
+  int32_t batch_streams;
+} msl_tuning;
+
+/* Validate and apply a launch shape (nothing changes on an error). */
+msl_status msl_set_tuning(const msl_tuning* t);
+/* The launch shape in effect. */
+msl_status msl_get_tuning(msl_tuning* t);
+
+/* Autotuner of the launch shape for one geometry: times msl_forward (no
+ * probe, no checkpoints) on the caller's delta and beta (device
+ * [Ns][ny][nz] f32) for every allowed lines-per-workgroup value of the
+ * nz-point slot, keeps the fastest, then the same for the ny-point slot
+ * (when ny != nz).  Each candidate runs once untimed and then `reps` times
+ * (1..1000) between two HIP events on hip_stream; the call blocks until the
+ * search ends.  field_scratch: device complex64 [ny][nz], overwritten.
+ * workspace: as for msl_forward (at least msl_workspace_bytes(g, 0)).  On
+ * success the fastest shape stays in effect and is copied to *best (may be
+ * NULL), its mean forward time in ms to *best_ms (may be NULL); on an error
+ * the previous shape is restored. */
+msl_status msl_autotune_forward(const msl_geometry* g, const float* delta, const float* beta,
+                                msl_c64* field_scratch, void* workspace, size_t ws_bytes, int32_t reps,
+                                void* hip_stream, msl_tuning* best, float* best_ms);
 
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* msl_last_error(void);

@@ -26,6 +26,13 @@ namespace {
 
 int g_schedule = MSL_SCHED_AUTO;
 
+// Launch shape of the line-pass kernels (msl_set_tuning): lines of length 2^e
+// per workgroup, 0 = the default (one wavefront's worth of lanes).
+int g_lines_per_group[MSL_TUNE_SLOTS] = {};
+int g_batch_streams = 0;  // 0: default (every extra stream)
+
+constexpr int kLdsSlots = 1152;  // float2 slots of a line-pass workgroup's LDS (two 512-point lines)
+
 constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -253,7 +260,7 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 
 template <int N, int AXIS, int KIND>
 __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
-  __shared__ float2 lds[1152];
+  __shared__ float2 lds[kLdsSlots];
   constexpr int L = msl::LinePts<N>::L;
   const int g = threadIdx.x / L, j = threadIdx.x % L;
   const int G = blockDim.x / L;
@@ -261,12 +268,27 @@ __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   msl::run_line<N, AXIS, false, KIND>(c, pd, group * G + g, j, lds + g * (N + N / 8));
 }
 
+// Lines per workgroup: at most 256 threads (the kernels' launch bound) and
+// the line exchange buffers within the kLdsSlots-slot LDS array.
+int max_lines_per_group(int n) {
+  const int L = n / (n >= MSL_P8_MIN_N && n < MSL_P4_MIN_N ? 8 : 4);
+  return std::min(256 / L, kLdsSlots / (n + n / 8));
+}
+
+int lines_per_group(int n, int nlines) {
+  const int L = n / (n >= MSL_P8_MIN_N && n < MSL_P4_MIN_N ? 8 : 4);
+  int G = g_lines_per_group[__builtin_ctz((unsigned)n)];
+  if (G <= 0) G = L >= 64 ? 1 : 64 / L;
+  G = std::min(G, max_lines_per_group(n));
+  return std::min(G, nlines);
+}
+
 template <int N, int AXIS>
 hipError_t launch_pass_t(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const int nlines = AXIS == msl::ROW ? c.ny : c.nz;
   constexpr int L = msl::LinePts<N>::L;
-  int G = L >= 64 ? 1 : 64 / L;
-  if (G > nlines) G = nlines;
+  static_assert(L == N / (N >= MSL_P8_MIN_N && N < MSL_P4_MIN_N ? 8 : 4), "lines_per_group assumes this split");
+  const int G = lines_per_group(N, nlines);
   const dim3 grid(nlines / G), block(L * G);
   switch (msl::pass_kind(pd)) {
     case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_FWD_MID>), grid, block, 0, st, c, pd); break;
@@ -536,7 +558,7 @@ __global__ void k_store_recs(RecChunk chunk, BatchRec* dst) {
 template <int N, int AXIS>
 __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__ recs, int groups_per_inst,
                                                     PassDesc tmpl) {
-  __shared__ float2 lds[1152];
+  __shared__ float2 lds[kLdsSlots];
   constexpr int L = msl::LinePts<N>::L;
   const int g = threadIdx.x / L, j = threadIdx.x % L;
   const int G = blockDim.x / L;
@@ -552,8 +574,7 @@ __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__
 template <int N, int AXIS>
 hipError_t launch_pass_batch_t(const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl, hipStream_t st) {
   constexpr int L = msl::LinePts<N>::L;
-  int G = L >= 64 ? 1 : 64 / L;
-  if (G > nlines) G = nlines;
+  const int G = lines_per_group(N, nlines);
   const int gpi = nlines / G;
   hipLaunchKernelGGL((k_pass_batch<N, AXIS>), dim3(n_inst * gpi), dim3(L * G), 0, st, recs, gpi, tmpl);
   return hipGetLastError();
@@ -649,6 +670,98 @@ int32_t msl_set_schedule(int32_t schedule) {
   const int prev = g_schedule;
   g_schedule = schedule;
   return prev;
+}
+
+msl_status msl_set_tuning(const msl_tuning* t) {
+  if (!t) return fail(MSL_ERR_ARG, "tuning is NULL");
+  for (int e = 0; e < MSL_TUNE_SLOTS; ++e) {
+    const int v = t->lines_per_group[e];
+    if (v == 0) continue;
+    const int hi = e >= 4 ? max_lines_per_group(1 << e) : 0;
+    if (v < 0 || (v & (v - 1)) != 0 || v > hi)
+      return fail(MSL_ERR_ARG, "lines_per_group[" + std::to_string(e) + "] = " + std::to_string(v) +
+                                   ": must be 0 or a power of two <= " + std::to_string(hi));
+  }
+  if (t->batch_streams < 0 || t->batch_streams > kBatchStreams + 1)
+    return fail(MSL_ERR_ARG, "batch_streams must be in [0, " + std::to_string(kBatchStreams + 1) + "]");
+  for (int e = 0; e < MSL_TUNE_SLOTS; ++e) g_lines_per_group[e] = t->lines_per_group[e];
+  g_batch_streams = t->batch_streams;
+  return MSL_OK;
+}
+
+msl_status msl_get_tuning(msl_tuning* t) {
+  if (!t) return fail(MSL_ERR_ARG, "tuning is NULL");
+  for (int e = 0; e < MSL_TUNE_SLOTS; ++e) t->lines_per_group[e] = g_lines_per_group[e];
+  t->batch_streams = g_batch_streams;
+  return MSL_OK;
+}
+
+msl_status msl_autotune_forward(const msl_geometry* g, const float* delta, const float* beta, msl_c64* field_scratch,
+                                void* workspace, size_t ws_bytes, int32_t reps, void* hip_stream, msl_tuning* best,
+                                float* best_ms) {
+  MSL_TRY(check_geometry(g));
+  if (!field_scratch) return fail(MSL_ERR_ARG, "field_scratch is NULL");
+  if (reps < 1 || reps > 1000) return fail(MSL_ERR_ARG, "reps must be in [1, 1000]");
+  msl_tuning saved;
+  MSL_TRY(msl_get_tuning(&saved));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MSL_TRY(hip_check(hipEventCreate(&e0), "hipEventCreate"));
+  const msl_status ce = hip_check(hipEventCreate(&e1), "hipEventCreate");
+  if (ce != MSL_OK) {
+    (void)hipEventDestroy(e0);
+    return ce;
+  }
+  auto forward = [&]() {
+    return msl_forward(g, delta, beta, nullptr, field_scratch, nullptr, 0, 0u, workspace, ws_bytes, hip_stream);
+  };
+  // one untimed forward, then `reps` timed back to back
+  auto time_forward = [&](float& ms) -> msl_status {
+    MSL_TRY(forward());
+    MSL_TRY(hip_check(hipEventRecord(e0, st), "hipEventRecord"));
+    for (int r = 0; r < reps; ++r) MSL_TRY(forward());
+    MSL_TRY(hip_check(hipEventRecord(e1, st), "hipEventRecord"));
+    MSL_TRY(hip_check(hipEventSynchronize(e1), "hipEventSynchronize"));
+    MSL_TRY(hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime"));
+    ms /= (float)reps;
+    return MSL_OK;
+  };
+  // one slot at a time (row passes use the nz-point slot, column passes the
+  // ny-point one), every power of two up to the slot's limit
+  auto search = [&](float& t_best) -> msl_status {
+    const int slots[2] = {__builtin_ctz((unsigned)g->nz), __builtin_ctz((unsigned)g->ny)};
+    MSL_TRY(time_forward(t_best));
+    for (int q = 0; q < 2; ++q) {
+      const int e = slots[q];
+      if (q == 1 && e == slots[0]) break;
+      const int keep = g_lines_per_group[e];
+      const int current = lines_per_group(1 << e, 1 << 30);  // the shape in effect, timed already
+      int best_v = keep;
+      for (int v = 1; v <= max_lines_per_group(1 << e); v *= 2) {
+        if (v == current) continue;
+        g_lines_per_group[e] = v;
+        float t = 0.0f;
+        MSL_TRY(time_forward(t));
+        if (t < t_best) {
+          t_best = t;
+          best_v = v;
+        }
+      }
+      g_lines_per_group[e] = best_v;
+    }
+    return MSL_OK;
+  };
+  float t_best = 0.0f;
+  const msl_status st_search = search(t_best);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st_search != MSL_OK) {
+    (void)msl_set_tuning(&saved);
+    return st_search;
+  }
+  if (best) MSL_TRY(msl_get_tuning(best));
+  if (best_ms) *best_ms = t_best;
+  return MSL_OK;
 }
 
 size_t msl_workspace_bytes(const msl_geometry* g, int32_t ckpt_every) {
@@ -1013,7 +1126,7 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
   }
   Helper* h = nullptr;
   std::unique_lock<std::mutex> lock;
-  const int nextra = std::min((int)groups.size() - 1, kBatchStreams);
+  const int nextra = std::min((int)groups.size() - 1, g_batch_streams > 0 ? g_batch_streams - 1 : kBatchStreams);
   if (nextra > 0) {
     MSL_TRY(helper_for_current_device(h));
     lock = std::unique_lock<std::mutex>(h->mu);
@@ -1022,7 +1135,7 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
   }
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const int g0 = groups[gi].first, g1 = groups[gi].second;
-    const hipStream_t gs = gi == 0 ? st : h->bs[(gi - 1) % kBatchStreams];
+    const hipStream_t gs = (gi == 0 || nextra == 0) ? st : h->bs[(gi - 1) % nextra];
     const int ny = inst[order[g0]].g.ny, nz = inst[order[g0]].g.nz;
     const int max_ns = inst[order[g0]].g.n_slices;
     for (int r = g0; r < g1; ++r) MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(phs[r], 0), gs), "pass kernel"));

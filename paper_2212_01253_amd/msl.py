@@ -24,7 +24,15 @@ EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "ms
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
            "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
            "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap", "msl_rotate_object",
-           "msl_region_shrinkwrap")
+           "msl_region_shrinkwrap", "msl_set_tuning", "msl_get_tuning", "msl_autotune_forward")
+
+TUNE_SLOTS = 11  # MSL_TUNE_SLOTS
+
+
+class CTuning(ctypes.Structure):
+    """Mirror of msl_tuning."""
+
+    _fields_ = [("lines_per_group", c_int32 * 11), ("batch_streams", c_int32)]
 
 
 class CGeometry(ctypes.Structure):
@@ -104,6 +112,13 @@ def lib():
     L.msl_adjoint.argtypes = [G, P, P, P, P, c_int32, P, P, P, P, ctypes.c_uint32, P, c_size_t, P]
     L.msl_set_schedule.restype = c_int32
     L.msl_set_schedule.argtypes = [c_int32]
+    T = ctypes.POINTER(CTuning)
+    L.msl_set_tuning.restype = c_int32
+    L.msl_set_tuning.argtypes = [T]
+    L.msl_get_tuning.restype = c_int32
+    L.msl_get_tuning.argtypes = [T]
+    L.msl_autotune_forward.restype = c_int32
+    L.msl_autotune_forward.argtypes = [G, P, P, P, P, c_size_t, c_int32, P, T, ctypes.POINTER(ctypes.c_float)]
     L.msl_last_error.restype = ctypes.c_char_p
     L.msl_last_error.argtypes = []
     L.msl_rotate_object.restype = c_int32
@@ -174,6 +189,48 @@ def set_schedule(mode: int) -> int:
     if r < 0:
         _check(r)
     return r
+
+
+def _tuning_dict(t):
+    return {"lines_per_group": {1 << e: int(t.lines_per_group[e]) for e in range(4, TUNE_SLOTS)},
+            "batch_streams": int(t.batch_streams)}
+
+
+def get_tuning() -> dict:
+    """msl_get_tuning: {"lines_per_group": {line length: value (0 = default)}, "batch_streams": n}."""
+    t = CTuning()
+    _check(lib().msl_get_tuning(ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def set_tuning(lines_per_group=None, batch_streams=0):
+    """msl_set_tuning; lines_per_group maps line lengths (16 .. 1024) to values."""
+    t = CTuning()
+    for n, v in (lines_per_group or {}).items():
+        n = int(n)
+        e = n.bit_length() - 1
+        if n < 1 or (1 << e) != n or e >= TUNE_SLOTS:
+            raise ValueError(f"line length {n} is not a power of two below 2^{TUNE_SLOTS}")
+        t.lines_per_group[e] = int(v)
+    t.batch_streams = int(batch_streams)
+    _check(lib().msl_set_tuning(ctypes.byref(t)))
+
+
+def autotune_forward(g, delta, beta, ws=None, reps=3, scratch=None):
+    """msl_autotune_forward: returns (tuning dict now in effect, mean forward ms)."""
+    cg = geometry(g)
+    ny, nz, ns = cg.ny, cg.nz, cg.n_slices
+    if ws is None:
+        ws = workspace(cg, 0, delta.device)
+    if scratch is None:
+        scratch = torch.empty((ny, nz), dtype=torch.complex64, device=delta.device)
+    t = CTuning()
+    ms = ctypes.c_float()
+    _check(lib().msl_autotune_forward(
+        ctypes.byref(cg), _ptr(delta, torch.float32, (ns, ny, nz), "delta"),
+        _ptr(beta, torch.float32, (ns, ny, nz), "beta"), _ptr(scratch, torch.complex64, (ny, nz), "scratch"),
+        ws.data_ptr(), ws.numel(), int(reps), _stream(), ctypes.byref(t), ctypes.byref(ms)))
+    return _tuning_dict(t), float(ms.value)
 
 
 def workspace_bytes(g, ckpt_every=0) -> int:

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert msl.abi_version() == 2
+    assert msl.abi_version() == 3
 
 
 def G(**kw):
@@ -230,3 +230,32 @@ def test_shrinkwrap_validates(L):
     assert L.msl_region_shrinkwrap(R(g), R(ok), 1.0, 21.0, 1.0, 0.2, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
     assert L.msl_region_shrinkwrap(R(g), R(ok), 1.0, 1.0, 1.0, 1.0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
     assert L.msl_region_shrinkwrap(R(g), R(ok), 1.0, 1.0, 1.0, 0.2, FAKE, None, FAKE, FAKE, None) == msl.ERR_ARG
+
+
+def test_tuning_validates_and_round_trips(L):
+    before = msl.get_tuning()
+    try:
+        msl.set_tuning({512: 2, 256: 4, 128: 1, 16: 64}, batch_streams=2)
+        t = msl.get_tuning()
+        assert t["lines_per_group"][512] == 2 and t["lines_per_group"][256] == 4
+        assert t["lines_per_group"][128] == 1 and t["lines_per_group"][16] == 64
+        assert t["lines_per_group"][1024] == 0 and t["batch_streams"] == 2
+        bad = [({512: 3}, 0), ({512: 4}, 0), ({1024: 2}, 0), ({256: -1}, 0), ({8: 1}, 0), ({}, 5), ({}, -1)]
+        for lpg, bs in bad:
+            with pytest.raises(msl.MslError):
+                msl.set_tuning(lpg, batch_streams=bs)
+            assert msl.get_tuning() == t      # nothing changes on an error
+    finally:
+        msl.set_tuning({n: v for n, v in before["lines_per_group"].items()}, before["batch_streams"])
+    assert msl.get_tuning() == before
+
+
+def test_autotune_validates(L):
+    g = G()
+    f = ctypes.c_float()
+    st = L.msl_autotune_forward(ctypes.byref(g), FAKE, FAKE, None, FAKE, 1 << 40, 3, None, None, ctypes.byref(f))
+    assert st == msl.ERR_ARG                              # no scratch field
+    st = L.msl_autotune_forward(ctypes.byref(g), FAKE, FAKE, FAKE, FAKE, 1 << 40, 0, None, None, ctypes.byref(f))
+    assert st == msl.ERR_ARG                              # reps < 1
+    st = L.msl_autotune_forward(ctypes.byref(G(ny=48)), FAKE, FAKE, FAKE, FAKE, 1 << 40, 3, None, None, None)
+    assert st == msl.ERR_ARG                              # not a power of two
