@@ -155,15 +155,16 @@ def test_region_snap_matches_the_oracle_bitwise(M):
     assert np.array_equal(D.cpu().numpy()[RO.box_slices(REGION)], ref)
 
 
-def test_reconstruction_from_captured_graphs_equals_eager(M):
+@pytest.mark.parametrize("k", [8, 1])
+def test_reconstruction_from_captured_graphs_equals_eager(M, k):
     # the loss evaluation and the adjoint captured once as HIP graphs and replayed every iteration
     # (with the eager ADAM step, loss read-backs and synchronisations between replays) give
-    # bit-identical losses and parameters
+    # bit-identical losses and parameters; k = 1 runs the adjoint without recompute
     from paper_2212_01253_amd import recon
     g, region, kd, kb, counts, s, truth, init = _small_problem()
     out = []
     for graphs in (False, True):
-        R = recon.Reconstructor(g, kd, kb, region, counts, s, ckpt_every=8, adam=recon.Adam(), graphs=graphs)
+        R = recon.Reconstructor(g, kd, kb, region, counts, s, ckpt_every=k, adam=recon.Adam(), graphs=graphs)
         res = R.run(init, 6)
         out.append((res.losses, R.theta.cpu().numpy()))
     assert out[0][0] == out[1][0]
