@@ -5,7 +5,10 @@ uses, against the FP64 oracle on the same float32 inputs: exit field relative
 L2 <= 2e-5 and far-field intensity relative L2 <= 1e-4.  The oracle needs
 about a minute of host CPU here.  A gradient check at the gradient workload's
 full size (256 x 256 x 1024, checkpoints every 32 slices) compares the GPU
-gradient with the oracle's on 16 sampled voxels and on its relative L2 norm.
+gradient with the oracle's on 16 sampled voxels and on its relative L2 norm;
+the benchmark's own gradient step (512 x 512 x 2048, slice pack reused,
+checkpoints every 32 slices, and again with one at every slice) gets the same
+comparison.
 """
 import math
 import time
@@ -88,3 +91,50 @@ def test_gradient_256x256x1024(M):
     assert abs(L - rL) <= 1e-4 * rL
     assert rel(gd, rd) <= 1e-3 and rel(gb, rb) <= 1e-3 and rel(gp, rp) <= 1e-3
     assert worst <= 1e-3
+
+
+@pytest.mark.timeout(900)
+def test_gradient_512x512x2048_as_benchmarked(M):
+    # the benchmark's gradient step (slice pack, forward with checkpoints every 32 slices reusing
+    # the pack, far field, loss, far-field adjoint, adjoint reusing the pack) at its full size,
+    # against the oracle's gradient; the same step with a checkpoint at every slice (no recompute)
+    w = synth.throughput_512()
+    g = w.geom
+    rng = np.random.default_rng(2214)
+    t0 = time.time()
+    meas = (np.sqrt(O.far_field(g, O.forward(g, w.delta * 1.05, w.beta * 1.05)))
+            * (1 + 0.05 * rng.random((g.ny, g.nz)))).astype(np.float32)
+    print(f"measured amplitudes {time.time() - t0:.1f} s", flush=True)
+    D = torch.from_numpy(w.delta).cuda()
+    B = torch.from_numpy(w.beta).cuda()
+    Mm = torch.from_numpy(meas).cuda()
+    out = {}
+    for k in (32, 1):
+        ws = M.workspace(g, k, "cuda")
+        M.pack_slices(g, D, B, ws)
+        f, ck = M.forward(g, D, B, None, k, ws=ws, reuse_pack=True)
+        I = M.far_field(g, f, ws=ws)
+        loss, gI = M.amp_loss(g, I, Mm, ws=ws)
+        gpsi = M.far_field_adjoint(g, f, gI, ws=ws)
+        gd, gb, gp = M.adjoint(g, D, B, ck, k, gpsi, ws=ws, want_probe=True, reuse_pack=True)
+        torch.cuda.synchronize()
+        out[k] = (float(loss.cpu()), gd.cpu().numpy(), gb.cpu().numpy(), gp.cpu().numpy())
+        del ws, ck, f, I, gI, gpsi, gd, gb, gp
+        torch.cuda.empty_cache()
+    del D, B, Mm
+    L, gd, gb, gp = out[32]
+    t0 = time.time()
+    rL, rd, rb, rp, _, _ = O.loss_and_gradient(g, w.delta, w.beta, meas)
+    pick = np.random.default_rng(2215)
+    idx = [tuple(int(pick.integers(0, n)) for n in w.delta.shape) for _ in range(16)]
+    scale = np.sqrt(np.mean(rd ** 2))
+    worst = max(abs(gd[i] - rd[i]) / scale for i in idx)
+    print(f"oracle {time.time() - t0:.1f} s; loss {abs(L - rL) / rL:.2e}; grad delta {rel(gd, rd):.2e} "
+          f"beta {rel(gb, rb):.2e} probe {rel(gp, rp):.2e}; sampled voxels {worst:.2e}", flush=True)
+    assert abs(L - rL) <= 1e-4 * rL
+    assert rel(gd, rd) <= 1e-3 and rel(gb, rb) <= 1e-3 and rel(gp, rp) <= 1e-3
+    assert worst <= 1e-3
+    L1, gd1, gb1, gp1 = out[1]
+    print(f"every-slice checkpoints: bitwise equal {np.array_equal(gd1, gd) and np.array_equal(gb1, gb)}", flush=True)
+    assert L1 == L
+    assert rel(gd1, gd) <= 1e-6 and rel(gb1, gb) <= 1e-6 and rel(gp1, gp) <= 1e-6
