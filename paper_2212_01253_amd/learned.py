@@ -406,9 +406,18 @@ def train_initialiser(n_samples=4096, steps=300, batch=32, lr=1e-3, n=256, n_sli
     nn.mse(mt.unsqueeze(0).expand(len(val), -1, -1).contiguous(), val.y, None, loss)
     base = float(loss.item())
     hist, secs = train(net, data, steps, batch=batch, lr=lr, log_every=log_every)
+    # A cyclic shift of the structure across the beam (along z) leaves the far-field intensity
+    # unchanged, so where a feature sits in z cannot be read from the image; what an image
+    # determines is shift-invariant, such as the row profile (the mean over z of each row).
+    # Its error is reported beside the per-pixel one, for the network and for the mean map.
+    pred = predict(net, val.x)
+    rt = val.y.mean(dim=2)
+    row_net = float(((pred.mean(dim=2) - rt) ** 2).mean())
+    row_mean = float(((mt.mean(dim=1).unsqueeze(0) - rt) ** 2).mean())
     info = {"samples": n_samples, "steps": steps, "batch": batch, "lr": lr, "data_seconds": data.seconds,
             "train_seconds": secs, "ms_per_step": 1e3 * secs / max(1, steps), "params": net.n_params,
-            "val_mse": evaluate(net, val), "val_mse_mean_map": base}
+            "val_mse": evaluate(net, val), "val_mse_mean_map": base,
+            "val_row_profile_mse": row_net, "val_row_profile_mse_mean_map": row_mean}
     del data, val
     return net, info
 

@@ -417,3 +417,21 @@ def test_exact_index_uniform_slab_closed_form():
     assert np.allclose(np.angle(ratio), -k * L * (d0 * d0 - b0 * b0) / 2, rtol=1e-9, atol=0)
     assert np.allclose(np.abs(ratio), np.exp(k * L * d0 * b0), rtol=1e-12)
     assert 2048 * 5.0 * k * 3e-5 ** 2 / 2 == pytest.approx(2.9e-4, rel=0.02)
+
+
+# --- translation across the beam ----------------------------------------------
+
+@pytest.mark.parametrize("prop", [0, 1])
+def test_far_field_invariant_under_shift_across_the_beam(prop):
+    # the incident wave does not depend on z and the grid is periodic, so moving the structure
+    # cyclically along z moves the exit field along z and changes the far field by a phase ramp
+    # only: the intensity is unchanged; a shift along y (towards or away from the substrate and
+    # across the tilted wave) does change it
+    g = geom(32, 32, 24, dx=5.0, alpha=math.radians(0.3), prop=prop)
+    d, b = synth.random_stack(32, 32, 24, 17)
+    I0 = O.far_field(g, O.forward(g, d, b))
+    for sh in (1, 5, 13):
+        I1 = O.far_field(g, O.forward(g, np.roll(d, sh, axis=2), np.roll(b, sh, axis=2)))
+        assert np.max(np.abs(I1 - I0)) <= 1e-12 * np.max(I0)
+    I2 = O.far_field(g, O.forward(g, np.roll(d, 3, axis=1), np.roll(b, 3, axis=1)))
+    assert np.max(np.abs(I2 - I0)) > 1e-6 * np.max(I0)
