@@ -66,6 +66,20 @@ msl_status msl_nn_rowpool(int32_t B, int32_t H, int32_t W, int32_t f, const floa
 msl_status msl_nn_rowpool_adjoint(int32_t B, int32_t H, int32_t W, int32_t f, const float* dy, float* dx,
                                   void* hip_stream);
 
+/* Summaries of each image row for the network's global head: x float32 [B][H][W], f16 bfloat16
+ * [B][3H] with v[r] = mean over all W columns of row r, v[H + r] = x[b][r][W/2] (the centre column:
+ * zero transverse momentum in an fftshifted far field), v[2H + r] = mean of the seven columns
+ * W/2-3 .. W/2+3 (float32 sums in ascending column order), and f16[b][i] = bfloat16((v[i] -
+ * shift[i]) * scale[i]); shift and scale float32 [3H] (normalisation; each may be NULL: 0 and 1).
+ * W >= 8. */
+msl_status msl_nn_row_features(int32_t B, int32_t H, int32_t W, const float* x, const float* shift,
+                               const float* scale, uint16_t* f16, void* hip_stream);
+
+/* The head's output broadcast along the columns: y[b][r][z] += p[r][b] (p float32 [R][B], y float32
+ * [B][R][W]); and its adjoint dp[r][b] = sum over z of dy[b][r][z] (ascending z; dp overwritten). */
+msl_status msl_nn_add_row_bias(int32_t B, int32_t R, int32_t W, const float* p, float* y, void* hip_stream);
+msl_status msl_nn_row_bias_adjoint(int32_t B, int32_t R, int32_t W, const float* dy, float* dp, void* hip_stream);
+
 /* Elementwise helpers over n floats: dy[i] = y[i] > 0 ? dy[i] : 0 (ReLU backward);
  * y[i] += x[i]; y16[i] = bfloat16(x[i]). */
 msl_status msl_nn_relu_adjoint(int64_t n, const float* y, float* dy, void* hip_stream);

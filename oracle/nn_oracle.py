@@ -9,7 +9,9 @@ paper's gradient reconstruction (Sec. 4.1) refines.  This module defines it
 plainly: 3x3 convolutions with zero padding (stride 1 or 2) by their
 definition (a sum over the nine taps of shifted inputs), ReLU, nearest 2x
 upsampling, channel concatenation, a row mean, the mean squared error, and
-their adjoints, all in float64.
+their adjoints, all in float64; and the global head: per-row summaries of the
+input image (means and the centre column), two dense layers, and the
+broadcast of its output along the columns.
 
 Where the library rounds to bfloat16 (the matrix-core inputs: activations and
 weights entering a convolution, and the output gradient entering the
@@ -94,6 +96,25 @@ def rowpool_adjoint(dy, f):
     return np.repeat(np.asarray(dy, np.float64), f, axis=1) / f
 
 
+def row_features(x0):
+    """x0 [B][H][W] -> [B][3H]: per row the mean over all columns, the centre column W/2, and the
+    mean over the seven columns W/2-3 .. W/2+3."""
+    x0 = np.asarray(x0, np.float64)
+    B, H, W = x0.shape
+    c = W // 2
+    return np.concatenate([x0.mean(axis=2), x0[:, :, c], x0[:, :, c - 3:c + 4].mean(axis=2)], axis=1)
+
+
+def add_row_bias(y, p):
+    """y [B][R][W] + p[r][b] at every column."""
+    return np.asarray(y, np.float64) + np.asarray(p, np.float64).T[:, :, None]
+
+
+def add_row_bias_adjoint(dy):
+    """dL/dp [R][B] from dL/dy [B][R][W]."""
+    return np.asarray(dy, np.float64).sum(axis=2).T
+
+
 def mse(p, t):
     d = np.asarray(p, np.float64) - np.asarray(t, np.float64)
     return float(np.mean(d * d)), 2.0 * d / d.size
@@ -113,9 +134,11 @@ def layer_specs(c=32, in_ch=2):
             ("out", c1, 1, 1, False)]
 
 
-def unet_forward(params, x, rows_per_output=4, quantize=True, offset=None):
+def unet_forward(params, x, rows_per_output=4, quantize=True, offset=None, feat_norm=None):
     """x [C][B][H][W] -> pred [B][H/rows_per_output][W] (+ offset [H/rows_per_output][W]);
-    params[name] = (w [O][C][3][3], bias [O]).
+    params[name] = (w [O][C][3][3], bias [O]) for the convolutions, and optionally the global
+    head "g1" (w [hidden][3H], bias [hidden]; ReLU) and "g2" (w [H/rows_per_output][hidden],
+    bias [H/rows_per_output]); feat_norm = (shift [3H], scale [3H]) normalises the head's inputs.
     Returns (pred, cache) for ``unet_adjoint``.  quantize=False skips the bfloat16 rounding
     (the exact function, for finite-difference checks)."""
     q = bf16 if quantize else (lambda a: np.asarray(a, np.float64))
@@ -138,6 +161,19 @@ def unet_forward(params, x, rows_per_output=4, quantize=True, offset=None):
     d1 = conv("d1", np.concatenate([upsample2(d2), e1]), 1, True)
     out = conv("out", d1, 1, False)
     pred = rowpool(out[0], rows_per_output)
+    if "g1" in params:
+        # global head: dense layers on shift-invariant row summaries of the first input channel,
+        # its output added to every column of the corresponding output row
+        (w1, b1), (w2, b2) = params["g1"], params["g2"]
+        feat = row_features(x[0])                        # [B][3H]
+        if feat_norm is not None:
+            feat = (feat - np.asarray(feat_norm[0], np.float64)) * np.asarray(feat_norm[1], np.float64)
+        feat = q(feat)
+        h1 = relu(q(w1) @ feat.T + np.asarray(b1, np.float64)[:, None])   # [hidden][B]
+        h1q = q(h1)
+        p = q(w2) @ h1q + np.asarray(b2, np.float64)[:, None]              # [R][B]
+        pred = add_row_bias(pred, p)
+        cache["head"] = (feat, h1, h1q)
     if offset is not None:
         pred = pred + np.asarray(offset, np.float64)[None]
     cache["shapes"] = {"e4": e4.shape[0], "d3": d3.shape[0], "d2": d2.shape[0]}
@@ -159,6 +195,13 @@ def unet_adjoint(params, cache, dpred, rows_per_output=4):
         return dx
 
     ch = cache["shapes"]
+    if "head" in cache:
+        feat, h1, h1q = cache["head"]
+        w2, _ = params["g2"]
+        dp = add_row_bias_adjoint(dpred)                 # [R][B]
+        grads["g2"] = (q(dp) @ h1q.T, dp.sum(axis=1))
+        dh1 = (q(w2).T @ q(dp)) * (h1 > 0)
+        grads["g1"] = (q(dh1) @ feat, dh1.sum(axis=1))
     dout = rowpool_adjoint(dpred, rows_per_output)[None]
     dd1 = back("out", dout)
     dcat = back("d1", dd1)

@@ -189,6 +189,54 @@ __global__ void __launch_bounds__(256) k_upsample2_adj(int64_t total, int H, int
   }
 }
 
+// Per image row: the mean over all columns, the centre column, and the mean
+// over the seven columns around the centre (fixed summation order), each
+// shifted and scaled (when given), as bfloat16.
+__global__ void __launch_bounds__(256) k_row_features(int B, int H, int W, const float* __restrict__ x,
+                                                      const float* __restrict__ shift,
+                                                      const float* __restrict__ scale, uint16_t* __restrict__ f) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)B * H) return;
+  const int64_t b = e / H;
+  const int r = (int)(e % H);
+  const float* row = x + e * W;
+  float all = 0.0f;
+  for (int z = 0; z < W; ++z) all += row[z];
+  const int c = W / 2;
+  float mid = 0.0f;
+  for (int z = c - 3; z <= c + 3; ++z) mid += row[z];
+  const float v[3] = {all * (1.0f / (float)W), row[c], mid * (1.0f / 7.0f)};
+  uint16_t* fb = f + b * 3 * H;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = q * H + r;
+    const float t = shift ? v[q] - shift[i] : v[q];
+    fb[i] = to_bf16(scale ? t * scale[i] : t);
+  }
+}
+
+// y[b][r][z] += p[r][b]
+__global__ void __launch_bounds__(256) k_add_row_bias(int64_t total, int B, int R, int W, const float* __restrict__ p,
+                                                      float* __restrict__ y) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)((e / W) % R);
+    const int b = (int)(e / ((int64_t)W * R));
+    y[e] += p[(int64_t)r * B + b];
+  }
+}
+
+// dp[r][b] = sum over z of dy[b][r][z] (z ascending)
+__global__ void __launch_bounds__(256) k_row_bias_adjoint(int B, int R, int W, const float* __restrict__ dy,
+                                                          float* __restrict__ dp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)B * R) return;
+  const int r = (int)(e / B), b = (int)(e % B);
+  const float* row = dy + ((int64_t)b * R + r) * W;
+  float acc = 0.0f;
+  for (int z = 0; z < W; ++z) acc += row[z];
+  dp[e] = acc;
+}
+
 __global__ void __launch_bounds__(256) k_rowpool(int64_t total, int H, int W, int f, const float* __restrict__ x,
                                                  float* __restrict__ y) {
   const int Hp = H / f;
@@ -443,6 +491,41 @@ msl_status msl_nn_upsample2_adjoint(int32_t C, int32_t B, int32_t H, int32_t W, 
   hipLaunchKernelGGL(k_upsample2_adj, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
                      total, H, W, dy, dx);
   return launched("upsample adjoint kernel");
+}
+
+msl_status msl_nn_row_features(int32_t B, int32_t H, int32_t W, const float* x, const float* shift, const float* scale,
+                               uint16_t* f16, void* hip_stream) {
+  MSL_TRY(need(B >= 1 && H >= 1 && W >= 8, "row features: need B, H >= 1 and W >= 8"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(shift, 4, "shift", true));
+  MSL_TRY(check_ptr(scale, 4, "scale", true));
+  MSL_TRY(check_ptr(f16, 2, "f16"));
+  const int64_t n = (int64_t)B * H;
+  MSL_TRY(need(n < (1ll << 31), "row features: too many rows"));
+  hipLaunchKernelGGL(k_row_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(hip_stream), B, H, W, x, shift, scale, f16);
+  return launched("row features kernel");
+}
+
+msl_status msl_nn_add_row_bias(int32_t B, int32_t R, int32_t W, const float* p, float* y, void* hip_stream) {
+  MSL_TRY(need(B >= 1 && R >= 1 && W >= 1, "add row bias: need B, R, W >= 1"));
+  MSL_TRY(check_ptr(p, 4, "p"));
+  MSL_TRY(check_ptr(y, 4, "y"));
+  const int64_t total = (int64_t)B * R * W;
+  hipLaunchKernelGGL(k_add_row_bias, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                     total, B, R, W, p, y);
+  return launched("add row bias kernel");
+}
+
+msl_status msl_nn_row_bias_adjoint(int32_t B, int32_t R, int32_t W, const float* dy, float* dp, void* hip_stream) {
+  MSL_TRY(need(B >= 1 && R >= 1 && W >= 1, "row bias adjoint: need B, R, W >= 1"));
+  MSL_TRY(check_ptr(dy, 4, "dy"));
+  MSL_TRY(check_ptr(dp, 4, "dp"));
+  const int64_t n = (int64_t)B * R;
+  MSL_TRY(need(n < (1ll << 31), "row bias adjoint: too many rows"));
+  hipLaunchKernelGGL(k_row_bias_adjoint, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(hip_stream), B, R, W, dy, dp);
+  return launched("row bias adjoint kernel");
 }
 
 msl_status msl_nn_rowpool(int32_t B, int32_t H, int32_t W, int32_t f, const float* x, float* y, void* hip_stream) {

@@ -7,7 +7,13 @@ of the unknown rows (mean over the beam direction, rows pooled 4:1), which is
 extruded along the beam as the ADAM starting point.  A second input channel
 holds the row coordinate (a convolutional network is otherwise blind to
 absolute position, and the cross-section's rows are heights), and the output
-is a correction to a fixed offset map (the training targets' mean).  Every layer runs in
+is a correction to a fixed offset map (the training targets' mean).  A global
+head adds a per-row term: two dense layers on shift-invariant summaries of
+each image row (its mean, the centre column and the mean of the seven central
+columns), broadcast along the row.  Shifting a structure cyclically across
+the beam leaves the far-field intensity unchanged, so what an image
+determines is shift-invariant (heights, densities), and the row summaries
+carry it to every output column, which 3x3 convolutions cannot.  Every layer runs in
 libmsl's kernels (``nn.py``): convolutions are bfloat16 matrix-core products
 (weights x 3x3 patches) with float32 accumulation; master weights, activations
 and gradients are float32.  This module only sequences the calls and owns the
@@ -46,8 +52,10 @@ def layer_specs(c=32, in_ch=2):
 class UNet:
     """Parameters (flat float32 master copy, bfloat16 copy, ADAM moments) and the pass buffers."""
 
-    def __init__(self, c=32, rows_per_output=4, device="cuda:0", seed=0):
+    def __init__(self, c=32, rows_per_output=4, device="cuda:0", seed=0, n=256, hidden=None):
         self.c, self.f, self.dev = c, rows_per_output, torch.device(device)
+        self.n = n                      # image rows (the global head's input and output sizes)
+        self.hidden = hidden or 8 * c   # global head's hidden width
         self.specs = layer_specs(c)
         self.offset = None   # [rows][W] added to every output (set_offset)
         self.off = {}
@@ -55,12 +63,21 @@ class UNet:
         for name, ci, co, s, act in self.specs:
             self.off[name] = (o, o + co * ci * 9, co, ci, s, act)   # weights, then biases
             o += co * ci * 9 + co
+        # global head: dense layers on shift-invariant row summaries (msl_nn_row_features),
+        # its output added along every output row
+        self.head_off = {}
+        for name, ni, no in (("g1", 3 * n, self.hidden), ("g2", self.hidden, n // rows_per_output)):
+            self.head_off[name] = (o, o + no * ni, no, ni)
+            o += no * ni + no
         self.n_params = o
         self.w = torch.zeros(o, dtype=torch.float32, device=self.dev)
         self.g = torch.zeros_like(self.w)
         self.m = torch.zeros_like(self.w)
         self.v = torch.zeros_like(self.w)
         self.w16 = torch.zeros(o, dtype=BF16, device=self.dev)
+        # normalisation of the head's inputs (fixed, from the training set: set_feature_norm)
+        self.feat_shift = torch.zeros(3 * n, dtype=torch.float32, device=self.dev)
+        self.feat_scale = torch.ones(3 * n, dtype=torch.float32, device=self.dev)
         self.t = 0
         self.init(seed)
         self._bufs = None
@@ -73,6 +90,9 @@ class UNet:
         for name, ci, co, s, act in self.specs:
             wo, bo, *_ = self.off[name]
             host[wo:bo] = rng.standard_normal(co * ci * 9) * math.sqrt(2.0 / (9 * ci))
+        for name, gain in (("g1", 2.0), ("g2", 0.01)):
+            wo, bo, no, ni = self.head_off[name]
+            host[wo:bo] = rng.standard_normal(no * ni) * math.sqrt(gain / ni)
         self.set_flat(host)
 
     def set_flat(self, host):
@@ -82,25 +102,28 @@ class UNet:
         self.v.zero_()
         self.t = 0
 
-    def params_numpy(self):
-        """{name: (w [co][ci][3][3], bias [co])} float64 copies (for checks)."""
-        host = self.w.cpu().numpy().astype(np.float64)
+    def _unflatten(self, host):
         out = {}
         for name, ci, co, s, act in self.specs:
             wo, bo, *_ = self.off[name]
             out[name] = (host[wo:bo].reshape(co, ci, 3, 3), host[bo:bo + co])
+        for name, (wo, bo, no, ni) in self.head_off.items():
+            out[name] = (host[wo:bo].reshape(no, ni), host[bo:bo + no])
         return out
+
+    def params_numpy(self):
+        """{name: (w, bias)} float64 copies (for checks): convolutions w [co][ci][3][3],
+        head layers w [out][in]."""
+        return self._unflatten(self.w.cpu().numpy().astype(np.float64))
 
     def grads_numpy(self):
-        host = self.g.cpu().numpy().astype(np.float64)
-        out = {}
-        for name, ci, co, s, act in self.specs:
-            wo, bo, *_ = self.off[name]
-            out[name] = (host[wo:bo].reshape(co, ci, 3, 3), host[bo:bo + co])
-        return out
+        return self._unflatten(self.g.cpu().numpy().astype(np.float64))
 
     def _wb(self, name):
-        wo, bo, co, ci, s, act = self.off[name]
+        if name in self.head_off:
+            wo, bo, co, _ = self.head_off[name]
+        else:
+            wo, bo, co, ci, s, act = self.off[name]
         return self.w16[wo:bo], self.w[bo:bo + co], self.g[wo:bo], self.g[bo:bo + co]
 
     # -- buffers ------------------------------------------------------------
@@ -108,6 +131,8 @@ class UNet:
         key = (B, H, W)
         if self._bufs is not None and self._bufs["key"] == key:
             return self._bufs
+        if H != self.n:
+            raise ValueError(f"the network was built for {self.n}-row images, got {H}")
         c1, c2, c3, c4 = self.c, 2 * self.c, 4 * self.c, 8 * self.c
         d = self.dev
         z = lambda *shape: torch.zeros(shape, dtype=torch.float32, device=d)
@@ -151,6 +176,16 @@ class UNet:
         b["t3"] = z(c3, B, *hw[2])
         b["d_pred"] = torch.zeros_like(b["pred"])
         b["loss"] = torch.zeros((), dtype=torch.float64, device=d)
+        # global head
+        hid, R = self.hidden, H // self.f
+        b["feat16"] = torch.zeros(B * 3 * H, dtype=BF16, device=d)
+        b["h1"] = z(hid, B)
+        b["h1_16"] = torch.zeros(hid * B, dtype=BF16, device=d)
+        b["hp"] = z(R, B)
+        b["dp"] = z(R, B)
+        b["dp16"] = torch.zeros(R * B, dtype=BF16, device=d)
+        b["dh1"] = z(hid, B)
+        b["dh1_16"] = torch.zeros(hid * B, dtype=BF16, device=d)
         self._bufs = b
         return b
 
@@ -215,11 +250,43 @@ class UNet:
         self._conv("d1", bf["cat1"], bf["d1"], B, H, W)
         self._conv("out", bf["d1"], bf["out"], B, H, W)
         nn.rowpool(B, H, W, self.f, bf["out"], bf["pred"])
+        self._head(B, H, W)
         if self.offset is not None:
             if "offset" not in bf:
                 bf["offset"] = self.offset.unsqueeze(0).expand(B, -1, -1).contiguous()
             nn.add_(bf["offset"], bf["pred"])
         return bf["pred"]
+
+    def _head(self, B, H, W):
+        """pred[b][r][:] += g2(relu(g1(row summaries of input channel 0)))[r][b]."""
+        bf = self._bufs
+        hid, R, F = self.hidden, H // self.f, 3 * H
+        nn.row_features(B, H, W, bf["x"][0], bf["feat16"], self.feat_shift, self.feat_scale)
+        w1, b1, _, _ = self._wb("g1")
+        nn.gemm(hid, B, F, w1, F, 0, bf["feat16"], F, 1, bf["h1"], B, bias=b1, relu=True, C16=bf["h1_16"])
+        w2, b2, _, _ = self._wb("g2")
+        nn.gemm(R, B, hid, w2, hid, 0, bf["h1_16"], B, 0, bf["hp"], B, bias=b2)
+        nn.add_row_bias(B, R, W, bf["hp"], bf["pred"])
+
+    def _head_back(self, dpred, B, H, W):
+        bf = self._bufs
+        hid, R, F = self.hidden, H // self.f, 3 * H
+        _, _, gw1, gb1 = self._wb("g1")
+        w2, _, gw2, gb2 = self._wb("g2")
+        nn.row_bias_adjoint(B, R, W, dpred, bf["dp"])
+        nn.rowsum(R, B, bf["dp"], gb2, bf["parts"])
+        nn.to_bf16(bf["dp"], bf["dp16"])
+        nn.gemm(R, hid, B, bf["dp16"], B, 0, bf["h1_16"], B, 1, gw2, hid)
+        nn.gemm(hid, B, R, w2, hid, 1, bf["dp16"], B, 0, bf["dh1"], B)
+        nn.relu_adjoint(bf["h1"], bf["dh1"])
+        nn.rowsum(hid, B, bf["dh1"], gb1, bf["parts"])
+        nn.to_bf16(bf["dh1"], bf["dh1_16"])
+        nn.gemm(hid, F, B, bf["dh1_16"], B, 0, bf["feat16"], F, 0, gw1, F)
+
+    def set_feature_norm(self, shift, scale):
+        """The head's inputs become (summary - shift) * scale (float32 [3n] each)."""
+        self.feat_shift.copy_(shift.to(self.dev).float())
+        self.feat_scale.copy_(scale.to(self.dev).float())
 
     def set_offset(self, offset):
         """Fixed map [rows][W] added to the output (None: no offset)."""
@@ -233,6 +300,7 @@ class UNet:
         B, H, W = bf["key"]
         c1, c2, c3, c4 = self.c, 2 * self.c, 4 * self.c, 8 * self.c
         e1, e2, e3 = bf["cat1"][c2:], bf["cat2"][c3:], bf["cat3"][c4:]
+        self._head_back(dpred, B, H, W)
         nn.rowpool_adjoint(B, H, W, self.f, dpred, bf["d_out"])
         self._conv_back("out", bf["d1"], bf["out"], bf["d_out"], bf["d_d1"], B, H, W)
         self._conv_back("d1", bf["cat1"], bf["d1"], bf["d_d1"], bf["d_cat1"], B, H, W)
@@ -334,6 +402,23 @@ class TrainingSet:
         return self.x.shape[0]
 
 
+def feature_norm(data, chunk=256):
+    """Shift (mean) and scale (1 / standard deviation) of the head's row summaries over a
+    training set, float32 [3n] each (the same summaries msl_nn_row_features forms)."""
+    n = data.n
+    c = n // 2
+    s1 = torch.zeros(3 * n, dtype=torch.float64, device=data.x.device)
+    s2 = torch.zeros_like(s1)
+    for s0 in range(0, len(data), chunk):
+        x = data.x[s0:s0 + chunk].double()
+        f = torch.cat([x.mean(dim=2), x[:, :, c], x[:, :, c - 3:c + 4].mean(dim=2)], dim=1)
+        s1 += f.sum(dim=0)
+        s2 += (f * f).sum(dim=0)
+    m = s1 / len(data)
+    sd = torch.sqrt(torch.clamp(s2 / len(data) - m * m, min=0.0)) + 1e-6
+    return m.float(), (1.0 / sd).float()
+
+
 def mean_target(data, chunk=256):
     """Mean of the training targets, [rows][n] (the network's output offset)."""
     acc = torch.zeros(data.y.shape[1:], dtype=torch.float64, device=data.y.device)
@@ -399,9 +484,10 @@ def train_initialiser(n_samples=4096, steps=300, batch=32, lr=1e-3, n=256, n_sli
     next to that of the offset alone (the population-mean cross-section)."""
     data = TrainingSet(n_samples, n=n, n_slices=n_slices)
     val = TrainingSet(n_val, seed0=900000, n=n, n_slices=n_slices)
-    net = UNet(c=32, seed=seed)
+    net = UNet(c=32, seed=seed, n=n)
     mt = mean_target(data)
     net.set_offset(mt)
+    net.set_feature_norm(*feature_norm(data))
     loss = torch.zeros((), dtype=torch.float64, device="cuda")
     nn.mse(mt.unsqueeze(0).expand(len(val), -1, -1).contiguous(), val.y, None, loss)
     base = float(loss.item())

@@ -16,7 +16,8 @@ from . import msl
 EXPORTS = ("msl_nn_gemm_bf16", "msl_nn_gemm_bf16_splitk", "msl_nn_im2col3x3", "msl_nn_col2im3x3", "msl_nn_upsample2",
            "msl_nn_upsample2_adjoint", "msl_nn_rowpool", "msl_nn_rowpool_adjoint", "msl_nn_relu_adjoint",
            "msl_nn_add", "msl_nn_to_bf16", "msl_nn_rowsum", "msl_nn_mse", "msl_nn_adam", "msl_nn_logmap",
-           "msl_nn_render_pools", "msl_nn_pool_average")
+           "msl_nn_render_pools", "msl_nn_pool_average", "msl_nn_row_features", "msl_nn_add_row_bias",
+           "msl_nn_row_bias_adjoint")
 
 MAX_BOXES = 64   # MSL_NN_MAX_BOXES
 MAX_CUTS = 132   # MSL_NN_MAX_CUTS
@@ -48,6 +49,9 @@ def lib():
             "msl_nn_logmap": [c_int64, P, c_float, c_float, c_float, P, P],
             "msl_nn_render_pools": [I, I, I, I, c_float, c_float, P, P, P, P, P, I, P, P, P],
             "msl_nn_pool_average": [I, I, I, I, I, P, P, P, I, P, c_float, P, P],
+            "msl_nn_row_features": [I, I, I, P, P, P, P, P],
+            "msl_nn_add_row_bias": [I, I, I, P, P, P],
+            "msl_nn_row_bias_adjoint": [I, I, I, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -111,6 +115,19 @@ def rowpool(B, H, W, f, x, y):
 
 def rowpool_adjoint(B, H, W, f, dy, dx):
     _ck(lib().msl_nn_rowpool_adjoint(B, H, W, f, _p(dy, torch.float32), _p(dx, torch.float32), _s()))
+
+
+def row_features(B, H, W, x, f16, shift=None, scale=None):
+    _ck(lib().msl_nn_row_features(B, H, W, _p(x, torch.float32), _p(shift, torch.float32),
+                                  _p(scale, torch.float32), _p(f16, BF16), _s()))
+
+
+def add_row_bias(B, R, W, p, y):
+    _ck(lib().msl_nn_add_row_bias(B, R, W, _p(p, torch.float32), _p(y, torch.float32), _s()))
+
+
+def row_bias_adjoint(B, R, W, dy, dp):
+    _ck(lib().msl_nn_row_bias_adjoint(B, R, W, _p(dy, torch.float32), _p(dp, torch.float32), _s()))
 
 
 def relu_adjoint(y, dy):

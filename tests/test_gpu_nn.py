@@ -126,6 +126,38 @@ def test_resampling_and_elementwise_kernels(T):
     assert np.allclose(gr.cpu().numpy(), g, rtol=1e-6, atol=0)
 
 
+def test_global_head_kernels(T):
+    import torch
+    rng = np.random.default_rng(8)
+    B, H, W, R = 3, 12, 20, 6
+    x = rng.standard_normal((B, H, W)).astype(np.float32)
+    f16 = torch.zeros(B * 3 * H, dtype=torch.int16, device="cuda")
+    T.row_features(B, H, W, dev(x), f16)
+    shift = rng.standard_normal(3 * H).astype(np.float32)
+    scale = rng.uniform(0.5, 4.0, 3 * H).astype(np.float32)
+    n16 = torch.zeros(B * 3 * H, dtype=torch.int16, device="cuda")
+    T.row_features(B, H, W, dev(x), n16, dev(shift), dev(scale))
+    p = rng.standard_normal((R, B)).astype(np.float32)
+    y0 = rng.standard_normal((B, R, W)).astype(np.float32)
+    y = dev(y0)
+    T.add_row_bias(B, R, W, dev(p), y)
+    dy = rng.standard_normal((B, R, W)).astype(np.float32)
+    dp = torch.zeros((R, B), dtype=torch.float32, device="cuda")
+    T.row_bias_adjoint(B, R, W, dev(dy), dp)
+    torch.cuda.synchronize()
+    # bfloat16 features: within half an ulp of the float64 values rounded the same way, after the
+    # float32 sums (one ulp apart at most where the sum order decides a tie)
+    got = f16.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    got = got.view(np.float32).astype(np.float64).reshape(B, 3 * H)
+    ref = N.row_features(x)
+    assert np.allclose(got, N.bf16(ref), rtol=2 ** -7, atol=0)
+    assert np.array_equal(got[:, H:2 * H], N.bf16(x[:, :, W // 2]))   # the centre column: a pure copy
+    gotn = (n16.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    assert np.allclose(gotn.reshape(B, 3 * H), N.bf16((ref - shift) * scale), rtol=2 ** -7, atol=1e-6)
+    assert np.allclose(y.cpu().numpy(), N.add_row_bias(y0, p), rtol=1e-6, atol=1e-6)
+    assert np.allclose(dp.cpu().numpy(), N.add_row_bias_adjoint(dy), rtol=1e-5, atol=1e-5)
+
+
 def test_weight_adam_matches_the_oracle(T):
     import torch
     rng = np.random.default_rng(4)
@@ -179,7 +211,7 @@ def test_rendered_pools_equal_the_host_generator(T):
 def test_unet_forward_and_gradients_match_the_oracle(T):
     import torch
     from paper_2212_01253_amd import learned
-    net = learned.UNet(c=4, seed=3)
+    net = learned.UNet(c=4, seed=3, n=32)
     rng = np.random.default_rng(5)
     B, H, W = 2, 32, 32
     x = rng.standard_normal((1, B, H, W)).astype(np.float32)
@@ -191,7 +223,13 @@ def test_unet_forward_and_gradients_match_the_oracle(T):
     for name, ci, co, s, act in learned.layer_specs(4):   # two input channels
         wo, bo, *_ = net.off[name]
         host[bo:bo + co] = rng.standard_normal(co) * 0.1
+    for name, (wo, bo, no, ni) in net.head_off.items():   # the global head too
+        host[bo:bo + no] = rng.standard_normal(no) * 0.1
+        host[wo:bo] = rng.standard_normal(no * ni) * np.sqrt(1.0 / ni)
     net.set_flat(host)
+    fshift = rng.standard_normal(3 * H).astype(np.float32) * 0.1
+    fscale = rng.uniform(0.5, 2.0, 3 * H).astype(np.float32)
+    net.set_feature_norm(dev(fshift), dev(fscale))
     pred = net.forward(dev(x))
     loss = net.loss_and_grad(dev(tgt))
     torch.cuda.synchronize()
@@ -200,17 +238,26 @@ def test_unet_forward_and_gradients_match_the_oracle(T):
     ramp = net._bufs["x"][1:].cpu().numpy()
     assert np.allclose(ramp[0, 0, :, 0], np.linspace(-1.0, 1.0, H), atol=1e-6) and np.all(ramp == ramp[:, :, :, :1])
     xin = np.concatenate([x, ramp]).astype(np.float64)
-    rpred, cache = N.unet_forward(params, xin, offset=off)
+    rpred, cache = N.unet_forward(params, xin, offset=off, feat_norm=(fshift, fscale))
     rL, dpred = N.mse(rpred, tgt)
     rg = N.unet_adjoint(params, cache, dpred)
     print("pred", rel(pred.cpu().numpy(), rpred), "loss", abs(float(loss.cpu()) - rL) / rL)
     assert rel(pred.cpu().numpy(), rpred) <= 1e-5
     assert abs(float(loss.cpu()) - rL) <= 1e-4 * rL
     g = net.grads_numpy()
+    errs = {}
     for name in params:
-        e_w, e_b = rel(g[name][0], rg[name][0]), rel(g[name][1], rg[name][1])
-        print(name, e_w, e_b)
-        assert e_w <= 1e-5 and e_b <= 1e-5   # measured <= 2.4e-7
+        errs[name] = (rel(g[name][0], rg[name][0]), rel(g[name][1], rg[name][1]))
+        print(name, errs[name], np.linalg.norm(rg[name][0]), np.linalg.norm(rg[name][1]))
+    # Both sides round the backward products' inputs to bfloat16 from float32 values that differ in
+    # the last bits (float32 against float64 arithmetic), so now and then one element sits on a
+    # rounding boundary and the two round it apart: one such element moves the gradients below it
+    # by about 2^-8 of its share (~1e-4 relative here).  Every layer must stay within that, and
+    # most layers, which no such element reaches, within float32 accuracy.
+    for name, (e_w, e_b) in errs.items():
+        assert e_w <= 1e-3 and e_b <= 1e-3, name
+    tight = sum(1 for e_w, e_b in errs.values() if e_w <= 1e-6 and e_b <= 1e-6)
+    assert tight >= 0.6 * len(errs), errs
 
 
 @pytest.mark.parametrize("ta,tb,splits", [(0, 1, 7), (0, 0, 1), (1, 1, 33)])

@@ -97,3 +97,61 @@ def test_unet_gradient_matches_finite_differences():
         bm[0] -= h
         fd = (loss({**params, name: (w, bp)}) - loss({**params, name: (w, bm)})) / (2 * h)
         assert fd == pytest.approx(grads[name][1][0], rel=1e-5, abs=1e-9)
+
+
+def test_row_features_closed_forms():
+    # rows that are affine in the column index: mean over all columns = value at (W-1)/2, centre
+    # column = value at W/2, seven-column mean = value at W/2
+    B, H, W = 2, 3, 16
+    a = np.arange(B * H, dtype=np.float64).reshape(B, H, 1)
+    x = a + 0.5 * np.arange(W)[None, None, :]
+    f = N.row_features(x)
+    assert np.allclose(f[:, :H], a[:, :, 0] + 0.5 * (W - 1) / 2)
+    assert np.allclose(f[:, H:2 * H], a[:, :, 0] + 0.5 * (W // 2))
+    assert np.allclose(f[:, 2 * H:], a[:, :, 0] + 0.5 * (W // 2))
+    # the summaries are invariant under a cyclic shift of the columns only for the full mean;
+    # the centre terms pick up the shifted columns
+    xs = np.roll(x, 3, axis=2)
+    assert np.allclose(N.row_features(xs)[:, :H], f[:, :H])
+
+
+def test_row_bias_adjoint_identity():
+    rng = np.random.default_rng(9)
+    p = rng.standard_normal((5, 3))
+    dy = rng.standard_normal((3, 5, 7))
+    y0 = np.zeros((3, 5, 7))
+    lhs = np.sum(N.add_row_bias(y0, p) * dy)
+    rhs = np.sum(p * N.add_row_bias_adjoint(dy))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_global_head_gradient_matches_finite_differences():
+    rng = np.random.default_rng(6)
+    c, H, hid = 2, 16, 8
+    params = small_params(rng, c)
+    params["g1"] = (rng.standard_normal((hid, 3 * H)) * 0.3, rng.standard_normal(hid) * 0.1)
+    params["g2"] = (rng.standard_normal((H // 4, hid)) * 0.3, rng.standard_normal(H // 4) * 0.1)
+    x = rng.standard_normal((2, 2, H, H))
+    t = rng.standard_normal((2, H // 4, H))
+
+    def loss(p):
+        pred, _ = N.unet_forward(p, x, quantize=False)
+        return N.mse(pred, t)[0]
+
+    pred, cache = N.unet_forward(params, x, quantize=False)
+    L, dpred = N.mse(pred, t)
+    grads = N.unet_adjoint(params, cache, dpred)
+    h = 1e-6
+    for name in ("g1", "g2", "e2b"):
+        w, b = params[name]
+        for idx in [tuple(0 for _ in w.shape), tuple(n - 1 for n in w.shape)]:
+            wp, wm = w.copy(), w.copy()
+            wp[idx] += h
+            wm[idx] -= h
+            fd = (loss({**params, name: (wp, b)}) - loss({**params, name: (wm, b)})) / (2 * h)
+            assert fd == pytest.approx(grads[name][0][idx], rel=1e-5, abs=1e-9)
+        bp, bm = b.copy(), b.copy()
+        bp[-1] += h
+        bm[-1] -= h
+        fd = (loss({**params, name: (w, bp)}) - loss({**params, name: (w, bm)})) / (2 * h)
+        assert fd == pytest.approx(grads[name][1][-1], rel=1e-5, abs=1e-9)
