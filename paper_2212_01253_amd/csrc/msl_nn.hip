@@ -119,31 +119,38 @@ __global__ void __launch_bounds__(256) k_sum_parts(int64_t mn, int parts, const 
   }
 }
 
-// grid: y = patch row r = c * 9 + tap, x over the columns; two columns per thread (one 4-byte store)
-__global__ void __launch_bounds__(256) k_im2col(int C, int B, int H, int W, int s, const float* __restrict__ x,
+// grid: y = patch row r = c * 9 + tap, x over groups of output image rows (b, i).  A thread
+// writes eight consecutive columns j of one output row (one 16-byte store when they are whole and
+// aligned); cpr threads cover a row, 256 / cpr rows share a workgroup.
+__global__ void __launch_bounds__(256) k_im2col(int C, int B, int H, int W, int s, int cpr, const float* __restrict__ x,
                                                 uint16_t* __restrict__ col) {
-  const unsigned Ho = H / s, Wo = W / s, ncol = (unsigned)B * Ho * Wo;
+  const int Ho = H / s, Wo = W / s;
+  const int64_t ncol = (int64_t)B * Ho * Wo;
   const int r = blockIdx.y, c = r / 9, t = r % 9, dy = t / 3 - 1, dx = t % 3 - 1;
-  const float* xc = x + (int64_t)c * B * H * W;
-  uint16_t* out = col + (int64_t)r * ncol;
-  for (unsigned n0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x); n0 < ncol; n0 += 2 * gridDim.x * blockDim.x) {
-    uint16_t v2[2];
+  const int rpb = 256 / cpr;
+  const int rowid = blockIdx.x * rpb + (int)threadIdx.x / cpr;  // output image row b * Ho + i
+  if (rowid >= B * Ho) return;
+  const int b = rowid / Ho, i = rowid % Ho;
+  const int y = s * i + dy;
+  const bool row_ok = y >= 0 && y < H;
+  const float* xr = x + ((int64_t)c * B + b) * H * W + (int64_t)(row_ok ? y : 0) * W;
+  uint16_t* o = col + (int64_t)r * ncol + (int64_t)rowid * Wo;
+  for (int j0 = 8 * ((int)threadIdx.x % cpr); j0 < Wo; j0 += 8 * cpr) {
+    uint16_t v[8];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const unsigned n = n0 + q;
-      float v = 0.0f;
-      if (n < ncol) {
-        const unsigned j = n % Wo, i = (n / Wo) % Ho, b = n / (Wo * Ho);
-        const int y = s * (int)i + dy, xx = s * (int)j + dx;
-        if (y >= 0 && y < H && xx >= 0 && xx < W) v = xc[((int64_t)b * H + y) * W + xx];
-      }
-      v2[q] = to_bf16(v);
+    for (int q = 0; q < 8; ++q) {
+      const int jj = j0 + q, xx = s * jj + dx;
+      v[q] = to_bf16(row_ok && jj < Wo && xx >= 0 && xx < W ? xr[xx] : 0.0f);
     }
-    if (n0 + 1 < ncol && ((reinterpret_cast<uintptr_t>(out + n0) & 3) == 0)) {
-      *reinterpret_cast<uint32_t*>(out + n0) = (uint32_t)v2[0] | ((uint32_t)v2[1] << 16);
+    if (j0 + 8 <= Wo && (reinterpret_cast<uintptr_t>(o + j0) & 15) == 0) {
+      uint4 w;
+      w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+      w.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+      w.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+      w.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+      *reinterpret_cast<uint4*>(o + j0) = w;
     } else {
-      out[n0] = v2[0];
-      if (n0 + 1 < ncol) out[n0 + 1] = v2[1];
+      for (int q = 0; q < 8 && j0 + q < Wo; ++q) o[j0 + q] = v[q];
     }
   }
 }
@@ -454,9 +461,14 @@ msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t 
   MSL_TRY(check_ptr(col, 2, "col"));
   const int64_t ncol = (int64_t)B * (H / stride) * (W / stride);
   MSL_TRY(need(ncol < (1ll << 31) && C * 9 <= 65535, "im2col: too many columns or channels"));
-  const unsigned bx = (unsigned)std::min<int64_t>((ncol / 2 + 255) / 256 + 1, 8192);
+  const int Wo = W / stride, rows = B * (H / stride);
+  const int cpr = std::min(32, (Wo + 7) / 8);   // threads per output row (a power of two or fewer)
+  int cp = 1;
+  while (cp < cpr) cp *= 2;
+  const int rpb = 256 / cp;
+  const unsigned bx = (unsigned)((rows + rpb - 1) / rpb);
   hipLaunchKernelGGL(k_im2col, dim3(bx, C * 9), dim3(256), 0, static_cast<hipStream_t>(hip_stream), C, B, H, W, stride,
-                     x, col);
+                     cp, x, col);
   return launched("im2col kernel");
 }
 
