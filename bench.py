@@ -177,8 +177,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initialiser leg")
     ap.add_argument("--no-every-slice", action="store_true",
                     help="skip the extra timing with a checkpoint at every slice (no recompute)")
-    ap.add_argument("--batch", type=int, default=0, metavar="N",
-                    help="also time the batched forward over N instances of the batched workload (96 = full)")
+    ap.add_argument("--batch", type=int, default=96, metavar="N",
+                    help="also time the batched forward over N instances of the batched workload (96 = full, 0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the multislice recurrence is sequential over slices and "
