@@ -54,6 +54,30 @@ msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t 
 msl_status msl_nn_col2im3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* col,
                             float* dx, void* hip_stream);
 
+/* 3x3 convolution, zero padding 1, stride 1 or 2, as an implicit matrix-core product (the patch
+ * matrix of msl_nn_im2col3x3 is formed tile by tile while loading, never stored):
+ * y[o][b][i][j] = act(sum_c sum_t w16[o][9c + t] bf16(x[c][b][s i + dy][s j + dx]) + bias[o]),
+ * t = 3 (dy + 1) + (dx + 1); x float32 [C][B][H][W], w16 bfloat16 [Co][9C], bias float32 [Co] or
+ * NULL, relu 0/1, y float32 [Co][B][H/s][W/s].  Bit for bit the product of msl_nn_gemm_bf16 with
+ * the patch matrix. */
+msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const uint16_t* w16,
+                          const float* x, const float* bias, int32_t relu, float* y, void* hip_stream);
+
+/* Its input gradient, also implicit: dx[c][b][y][x] = sum over o and taps t of w16[o][9c + t] dy16[o][b][i][j]
+ * where s i + dy = y and s j + dx = x (dy16 bfloat16 [Co][B][H/s][W/s]; dx float32 [C][B][H][W],
+ * overwritten). */
+msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
+                                  const uint16_t* w16, const uint16_t* dy16, float* dx, void* hip_stream);
+
+/* Its weight gradient, implicit as well: dw[o][9c + t] = sum over output pixels p of dy16[o][p] times the
+ * patch value (c, t) at p (x rounded to bfloat16 as in the forward); the pixel sum is split into
+ * `splits` parts written to partials (float32 [splits][Co][9C], caller-owned scratch) and then
+ * summed in order into dw (float32 [Co][9C]) -- bit for bit msl_nn_gemm_bf16_splitk of dy16 and
+ * the patch matrix.  1 <= splits <= 4096. */
+msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
+                                     const uint16_t* dy16, const float* x, float* dw, int32_t splits, float* partials,
+                                     void* hip_stream);
+
 /* Nearest 2x upsampling [C][B][H][W] -> [C][B][2H][2W] (y may be a channel slice of a larger
  * array: it is written at y with the [C][B][2H][2W] layout), and its adjoint (sum of the four). */
 msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const float* x, float* y,

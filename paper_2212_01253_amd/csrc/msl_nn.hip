@@ -109,6 +109,299 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolutions as implicit products: the same tiles, LDS layout and MFMA
+// sequence as k_gemm_bf16, with the patch operand formed while it is loaded
+// (no patch matrix in memory).  k runs over (channel, tap), tap = 3 (dy + 1) +
+// (dx + 1), in the patch matrix's row order, so the forward product is the
+// explicit one bit for bit.
+
+struct ConvArgs {
+  int Co, C, B, H, W, s, Ho, Wo, relu;
+  int K;      // GEMM depth: C * 9 (forward) or Co * 9 (input gradient)
+  int64_t N;  // GEMM columns: B * Ho * Wo (forward) or B * H * W (input gradient)
+  const uint16_t* w16;  // [Co][C * 9]
+  const float* x;       // forward input [C][B][H][W]
+  const uint16_t* dy16; // input gradient: output gradient [Co][B][Ho][Wo], bfloat16
+  const float* bias;
+  float* y;             // forward output [Co][B][Ho][Wo] or input gradient [C][B][H][W]
+};
+
+// Stores v[0..3] and v[4..7] as two 8-byte LDS writes.
+__device__ __forceinline__ void lds_store8(uint16_t* dst, const uint16_t (&v)[8]) {
+  uint2 a, b;
+  a.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+  a.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+  b.x = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+  b.y = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+  *reinterpret_cast<uint2*>(dst) = a;
+  *reinterpret_cast<uint2*>(dst + 4) = b;
+}
+
+__device__ __forceinline__ void mfma_tile(const uint16_t (&As)[TM][KP], const uint16_t (&Bs)[TN][KP], int wm, int wn,
+                                          int lane, f32x16& acc0, f32x16& acc1) {
+#pragma unroll
+  for (int ks = 0; ks < TK; ks += 8) {
+    const int kq = ks + 4 * (lane >> 5);
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[wm + (lane & 31)][kq]);
+    const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&Bs[wn + (lane & 31)][kq]);
+    const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(&Bs[wn + 32 + (lane & 31)][kq]);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b1, acc1, 0, 0, 0);
+  }
+}
+
+// y = act(conv(x) + bias): M = Co, N = B Ho Wo, K = C 9.  Thread t loads
+// weight row m0 + t/4, k 8 (t mod 4) .. +8, and the 16 patch values of
+// pixel n0 + t mod 128 at k 16 (t / 128) .. +16.
+__global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][KP];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * TM;
+  const int64_t n0 = (int64_t)blockIdx.x * TN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  f32x16 acc0 = {}, acc1 = {};
+  const int nl = tid % TN, kh = tid / TN;
+  const int64_t n = n0 + nl;
+  const bool n_ok = n < a.N;
+  int b = 0, i = 0, j = 0;
+  if (n_ok) {
+    j = (int)(n % a.Wo);
+    const int64_t t = n / a.Wo;
+    i = (int)(t % a.Ho);
+    b = (int)(t / a.Ho);
+  }
+  const int y0 = a.s * i - 1, x0 = a.s * j - 1;   // window corner (dy = dx = -1)
+  const int64_t cstride = (int64_t)a.B * a.H * a.W;
+  const float* xb = a.x + (int64_t)b * a.H * a.W;
+  const bool w_vec = (a.K & 7) == 0 && (reinterpret_cast<uintptr_t>(a.w16) & 15) == 0;
+  for (int k0 = 0; k0 < a.K; k0 += TK) {
+    {
+      const int m = tid >> 2, kq = (tid & 3) * 8;
+      const int gm = m0 + m, gk = k0 + kq;
+      uint16_t v[8];
+      if (w_vec && gm < a.Co && gk + 8 <= a.K) {
+        const uint4 u = *reinterpret_cast<const uint4*>(a.w16 + (int64_t)gm * a.K + gk);
+        v[0] = (uint16_t)u.x; v[1] = (uint16_t)(u.x >> 16); v[2] = (uint16_t)u.y; v[3] = (uint16_t)(u.y >> 16);
+        v[4] = (uint16_t)u.z; v[5] = (uint16_t)(u.z >> 16); v[6] = (uint16_t)u.w; v[7] = (uint16_t)(u.w >> 16);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (gm < a.Co && gk + q < a.K) ? a.w16[(int64_t)gm * a.K + gk + q] : (uint16_t)0;
+      }
+      lds_store8(&As[m][kq], v);
+    }
+    {
+      const int kb = k0 + kh * 16;
+      int c = kb / 9, tap = kb - 9 * c;
+      uint16_t v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        float val = 0.0f;
+        const int yy = y0 + tap / 3, xx = x0 + tap % 3;
+        if (n_ok && kb + q < a.K && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          val = xb[(int64_t)c * cstride + (int64_t)yy * a.W + xx];
+        v[q] = to_bf16(val);
+        if (++tap == 9) {
+          tap = 0;
+          ++c;
+        }
+      }
+      uint16_t lo[8], hi[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        lo[q] = v[q];
+        hi[q] = v[q + 8];
+      }
+      lds_store8(&Bs[nl][kh * 16], lo);
+      lds_store8(&Bs[nl][kh * 16 + 8], hi);
+    }
+    __syncthreads();
+    mfma_tile(As, Bs, wm, wn, lane, acc0, acc1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t nn = n0 + wn + 32 * h + (lane & 31);
+#pragma unroll
+    for (int i4 = 0; i4 < 4; ++i4)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int m = m0 + wm + 8 * i4 + 4 * (lane >> 5) + jj;
+        if (m < a.Co && nn < a.N) {
+          float v = h ? acc1[4 * i4 + jj] : acc0[4 * i4 + jj];
+          if (a.bias) v += a.bias[m];
+          if (a.relu) v = fmaxf(v, 0.0f);
+          a.y[(int64_t)m * a.N + nn] = v;
+        }
+      }
+  }
+}
+
+// dx = sum over (co, tap) of W[co][c 9 + tap] dy[co][b][(y - dy)/s][(x - dx)/s] (terms whose
+// source position is whole and inside): M = C, N = B H W, K = Co 9, k = 9 co + tap.
+__global__ void __launch_bounds__(256) k_conv_bwd_data(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][KP];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * TM;
+  const int64_t n0 = (int64_t)blockIdx.x * TN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  f32x16 acc0 = {}, acc1 = {};
+  const int nl = tid % TN, kh = tid / TN;
+  const int64_t n = n0 + nl;
+  const bool n_ok = n < a.N;
+  int b = 0, yq = 0, xq = 0;
+  if (n_ok) {
+    xq = (int)(n % a.W);
+    const int64_t t = n / a.W;
+    yq = (int)(t % a.H);
+    b = (int)(t / a.H);
+  }
+  const int64_t ostride = (int64_t)a.B * a.Ho * a.Wo;
+  const uint16_t* db = a.dy16 + (int64_t)b * a.Ho * a.Wo;
+  const int KC = a.C * 9;   // weight row length
+  for (int k0 = 0; k0 < a.K; k0 += TK) {
+    {
+      // A[m = c][k = 9 co + tap] = w16[co][9 c + tap]
+      const int m = tid >> 2, kq = (tid & 3) * 8;
+      const int gm = m0 + m, gk = k0 + kq;
+      uint16_t v[8];
+      int co = gk / 9, tap = gk - 9 * co;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        v[q] = (gm < a.C && gk + q < a.K) ? a.w16[(int64_t)co * KC + 9 * gm + tap] : (uint16_t)0;
+        if (++tap == 9) {
+          tap = 0;
+          ++co;
+        }
+      }
+      lds_store8(&As[m][kq], v);
+    }
+    {
+      const int kb = k0 + kh * 16;
+      int co = kb / 9, tap = kb - 9 * co;
+      uint16_t v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        uint16_t val = 0;
+        const int yy = yq - (tap / 3 - 1), xx = xq - (tap % 3 - 1);
+        if (n_ok && kb + q < a.K && yy >= 0 && xx >= 0 && yy % a.s == 0 && xx % a.s == 0) {
+          const int ii = yy / a.s, jj = xx / a.s;
+          if (ii < a.Ho && jj < a.Wo) val = db[(int64_t)co * ostride + (int64_t)ii * a.Wo + jj];
+        }
+        v[q] = val;
+        if (++tap == 9) {
+          tap = 0;
+          ++co;
+        }
+      }
+      uint16_t lo[8], hi[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        lo[q] = v[q];
+        hi[q] = v[q + 8];
+      }
+      lds_store8(&Bs[nl][kh * 16], lo);
+      lds_store8(&Bs[nl][kh * 16 + 8], hi);
+    }
+    __syncthreads();
+    mfma_tile(As, Bs, wm, wn, lane, acc0, acc1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t nn = n0 + wn + 32 * h + (lane & 31);
+#pragma unroll
+    for (int i4 = 0; i4 < 4; ++i4)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int m = m0 + wm + 8 * i4 + 4 * (lane >> 5) + jj;
+        if (m < a.C && nn < a.N) a.y[(int64_t)m * a.N + nn] = h ? acc1[4 * i4 + jj] : acc0[4 * i4 + jj];
+      }
+  }
+}
+
+// Weight gradient, split along the pixels like msl_nn_gemm_bf16_splitk:
+// part z accumulates dW[o][9c + t] over pixels [z kchunk, (z + 1) kchunk) into
+// partials + z Co 9C.  M = Co, N = 9C, K = B Ho Wo.  Thread t loads dy row
+// m0 + t/4, pixels 8 (t mod 4) .. +8, and the patch values of pixel t mod 32
+// for the 16 (channel, tap) columns n0 + 16 (t / 32) .. +16.
+__global__ void __launch_bounds__(256) k_conv_bwd_weight(ConvArgs a, int kchunk, float* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][KP];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  f32x16 acc0 = {}, acc1 = {};
+  const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = kbeg + kchunk < npix ? kbeg + kchunk : npix;
+  const int NC = a.C * 9;
+  const int64_t cstride = (int64_t)a.B * a.H * a.W;
+  const bool dy_vec = (npix & 7) == 0 && (reinterpret_cast<uintptr_t>(a.dy16) & 15) == 0;
+  const int kk = tid & 31, nq = (tid >> 5) * 16;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+    {
+      const int m = tid >> 2, kq = (tid & 3) * 8;
+      const int gm = m0 + m;
+      const int64_t gk = k0 + kq;
+      uint16_t v[8];
+      if (dy_vec && gm < a.Co && gk + 8 <= kend) {
+        const uint4 u = *reinterpret_cast<const uint4*>(a.dy16 + (int64_t)gm * npix + gk);
+        v[0] = (uint16_t)u.x; v[1] = (uint16_t)(u.x >> 16); v[2] = (uint16_t)u.y; v[3] = (uint16_t)(u.y >> 16);
+        v[4] = (uint16_t)u.z; v[5] = (uint16_t)(u.z >> 16); v[6] = (uint16_t)u.w; v[7] = (uint16_t)(u.w >> 16);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (gm < a.Co && gk + q < kend) ? a.dy16[(int64_t)gm * npix + gk + q] : (uint16_t)0;
+      }
+      lds_store8(&As[m][kq], v);
+    }
+    {
+      const int64_t p = k0 + kk;
+      const bool p_ok = p < kend;
+      int b = 0, i = 0, j = 0;
+      if (p_ok) {
+        j = (int)(p % a.Wo);
+        const int64_t t = p / a.Wo;
+        i = (int)(t % a.Ho);
+        b = (int)(t / a.Ho);
+      }
+      const int y0 = a.s * i - 1, x0 = a.s * j - 1;
+      const float* xb = a.x + (int64_t)b * a.H * a.W;
+      const int nb = n0 + nq;
+      int c = nb / 9, tap = nb - 9 * c;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        float val = 0.0f;
+        const int yy = y0 + tap / 3, xx = x0 + tap % 3;
+        if (p_ok && nb + q < NC && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+          val = xb[(int64_t)c * cstride + (int64_t)yy * a.W + xx];
+        Bs[nq + q][kk] = to_bf16(val);
+        if (++tap == 9) {
+          tap = 0;
+          ++c;
+        }
+      }
+    }
+    __syncthreads();
+    mfma_tile(As, Bs, wm, wn, lane, acc0, acc1);
+    __syncthreads();
+  }
+  float* const P = partials + (int64_t)blockIdx.z * a.Co * NC;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int n = n0 + wn + 32 * h + (lane & 31);
+#pragma unroll
+    for (int i4 = 0; i4 < 4; ++i4)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int m = m0 + wm + 8 * i4 + 4 * (lane >> 5) + jj;
+        if (m < a.Co && n < NC) P[(int64_t)m * NC + n] = h ? acc1[4 * i4 + jj] : acc0[4 * i4 + jj];
+      }
+  }
+}
+
 // C[i] = sum over the parts s of P[s][i], in order
 __global__ void __launch_bounds__(256) k_sum_parts(int64_t mn, int parts, const float* __restrict__ P, int M, int N,
                                                    int ldc, float* __restrict__ C) {
@@ -451,6 +744,76 @@ msl_status msl_nn_gemm_bf16_splitk(int32_t M, int32_t N, int32_t K, const uint16
   const int64_t mn = (int64_t)M * N;
   hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, M, N, ldc, C);
   return launched("split gemm kernels");
+}
+
+msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const uint16_t* w16,
+                          const float* x, const float* bias, int32_t relu, float* y, void* hip_stream) {
+  MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
+                   W % stride == 0, "conv: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
+  MSL_TRY(check_ptr(w16, 2, "w16"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(bias, 4, "bias", true));
+  MSL_TRY(check_ptr(y, 4, "y"));
+  ConvArgs a{};
+  a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
+  a.relu = relu ? 1 : 0;
+  a.K = C * 9;
+  a.N = (int64_t)B * a.Ho * a.Wo;
+  MSL_TRY(need((int64_t)C * 9 < (1 << 30) && a.N < (1ll << 40), "conv: sizes too large"));
+  a.w16 = w16; a.x = x; a.bias = bias; a.y = y;
+  const dim3 grid((unsigned)((a.N + TN - 1) / TN), (unsigned)((Co + TM - 1) / TM));
+  MSL_TRY(need(grid.y <= 65535, "conv: too many output channels"));
+  hipLaunchKernelGGL(k_conv_fwd, grid, dim3(256), 0, static_cast<hipStream_t>(hip_stream), a);
+  return launched("conv kernel");
+}
+
+msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
+                                  const uint16_t* w16, const uint16_t* dy16, float* dx, void* hip_stream) {
+  MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
+                   W % stride == 0, "conv adjoint: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
+  MSL_TRY(check_ptr(w16, 2, "w16"));
+  MSL_TRY(check_ptr(dy16, 2, "dy16"));
+  MSL_TRY(check_ptr(dx, 4, "dx"));
+  ConvArgs a{};
+  a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
+  a.K = Co * 9;
+  a.N = (int64_t)B * H * W;
+  MSL_TRY(need((int64_t)Co * 9 < (1 << 30) && a.N < (1ll << 40), "conv adjoint: sizes too large"));
+  a.w16 = w16; a.dy16 = dy16; a.y = dx;
+  const dim3 grid((unsigned)((a.N + TN - 1) / TN), (unsigned)((C + TM - 1) / TM));
+  MSL_TRY(need(grid.y <= 65535, "conv adjoint: too many input channels"));
+  hipLaunchKernelGGL(k_conv_bwd_data, grid, dim3(256), 0, static_cast<hipStream_t>(hip_stream), a);
+  return launched("conv adjoint kernel");
+}
+
+msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
+                                     const uint16_t* dy16, const float* x, float* dw, int32_t splits, float* partials,
+                                     void* hip_stream) {
+  MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
+                   W % stride == 0, "conv weight gradient: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
+  MSL_TRY(need(splits >= 1 && splits <= 4096, "conv weight gradient: splits must be in [1, 4096]"));
+  MSL_TRY(check_ptr(dy16, 2, "dy16"));
+  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(dw, 4, "dw"));
+  MSL_TRY(check_ptr(partials, 4, "partials"));
+  ConvArgs a{};
+  a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
+  a.dy16 = dy16; a.x = x;
+  const int64_t npix = (int64_t)B * a.Ho * a.Wo;
+  MSL_TRY(need(npix < (1ll << 40) && (int64_t)C * 9 < (1 << 30), "conv weight gradient: sizes too large"));
+  // pixel range per part: a multiple of the K tile (the split of msl_nn_gemm_bf16_splitk)
+  int64_t kchunk = (npix + splits - 1) / splits;
+  kchunk = (kchunk + TK - 1) / TK * TK;
+  MSL_TRY(need(kchunk < (1ll << 31), "conv weight gradient: too few parts"));
+  const int parts = (int)((npix + kchunk - 1) / kchunk);
+  const int NC = C * 9;
+  const dim3 grid((unsigned)((NC + TN - 1) / TN), (unsigned)((Co + TM - 1) / TM), (unsigned)parts);
+  MSL_TRY(need(grid.y <= 65535 && grid.z <= 65535, "conv weight gradient: too many channels or parts"));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_conv_bwd_weight, grid, dim3(256), 0, st, a, (int)kchunk, partials);
+  const int64_t mn = (int64_t)Co * NC;
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, Co, NC, NC, dw);
+  return launched("conv weight gradient kernels");
 }
 
 msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* x,

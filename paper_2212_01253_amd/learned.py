@@ -13,10 +13,10 @@ each image row (its mean, the centre column and the mean of the seven central
 columns), broadcast along the row.  Shifting a structure cyclically across
 the beam leaves the far-field intensity unchanged, so what an image
 determines is shift-invariant (heights, densities), and the row summaries
-carry it to every output column, which 3x3 convolutions cannot.  Every layer runs in
-libmsl's kernels (``nn.py``): convolutions are bfloat16 matrix-core products
-(weights x 3x3 patches) with float32 accumulation; master weights, activations
-and gradients are float32.  This module only sequences the calls and owns the
+carry it to every output column, which 3x3 convolutions cannot.  Every layer
+runs in libmsl's kernels (``nn.py``): convolutions are bfloat16 matrix-core
+products (weights x 3x3 patches, formed while loading) with float32
+accumulation; master weights, activations and gradients are float32.  This module only sequences the calls and owns the
 buffers.
 
 Training data come from the model itself: samples of the bars-on-substrate
@@ -60,16 +60,22 @@ class UNet:
         self.offset = None   # [rows][W] added to every output (set_offset)
         self.off = {}
         o = 0
+        n_real = 0
         for name, ci, co, s, act in self.specs:
+            o = (o + 7) // 8 * 8   # weight rows start 16-byte aligned (vector loads in the products)
             self.off[name] = (o, o + co * ci * 9, co, ci, s, act)   # weights, then biases
             o += co * ci * 9 + co
+            n_real += co * ci * 9 + co
         # global head: dense layers on shift-invariant row summaries (msl_nn_row_features),
         # its output added along every output row
         self.head_off = {}
         for name, ni, no in (("g1", 3 * n, self.hidden), ("g2", self.hidden, n // rows_per_output)):
+            o = (o + 7) // 8 * 8
             self.head_off[name] = (o, o + no * ni, no, ni)
             o += no * ni + no
-        self.n_params = o
+            n_real += no * ni + no
+        self.n_params = n_real   # parameters (the flat arrays also hold alignment gaps, always zero)
+        self.n_flat = o
         self.w = torch.zeros(o, dtype=torch.float32, device=self.dev)
         self.g = torch.zeros_like(self.w)
         self.m = torch.zeros_like(self.w)
@@ -86,7 +92,7 @@ class UNet:
     def init(self, seed):
         """He-normal weights (seeded host draws), zero biases."""
         rng = np.random.Generator(np.random.PCG64(seed))
-        host = np.zeros(self.n_params, np.float32)
+        host = np.zeros(self.n_flat, np.float32)
         for name, ci, co, s, act in self.specs:
             wo, bo, *_ = self.off[name]
             host[wo:bo] = rng.standard_normal(co * ci * 9) * math.sqrt(2.0 / (9 * ci))
@@ -154,10 +160,7 @@ class UNet:
         b["d1"] = z(c1, B, *hw[0])
         b["out"] = z(1, B, H, W)
         b["pred"] = z(B, H // self.f, W)
-        kmax = max(ci * 9 for _, ci, _, _, _ in self.specs)
         nmax = B * H * W
-        b["col"] = torch.zeros(kmax * nmax, dtype=BF16, device=d)
-        b["dcol"] = torch.zeros(kmax * nmax, dtype=torch.float32, device=d)
         comax = max(co for _, _, co, _, _ in self.specs)
         b["dy16"] = torch.zeros(comax * nmax, dtype=BF16, device=d)
         need = 0
@@ -191,15 +194,10 @@ class UNet:
 
     # -- layers -------------------------------------------------------------
     def _conv(self, name, x, y, B, H, W):
-        """y = act(W * patches(x) + b); x [ci][B][H][W] -> y [co][B][H/s][W/s]."""
+        """y = act(W * patches(x) + b); x [ci][B][H][W] -> y [co][B][H/s][W/s] (implicit product)."""
         wo, bo, co, ci, s, act = self.off[name]
-        bf = self._bufs
-        Ho, Wo = H // s, W // s
-        N = B * Ho * Wo
-        col = bf["col"][:ci * 9 * N]
-        nn.im2col(ci, B, H, W, s, x, col)
         w16, bias, _, _ = self._wb(name)
-        nn.gemm(co, N, ci * 9, w16, ci * 9, 0, col, N, 0, y, N, bias=bias, relu=act)
+        nn.conv3x3(co, ci, B, H, W, s, w16, x, y, bias=bias, relu=act)
 
     def _conv_back(self, name, x, y, dy, dx, B, H, W):
         """Weight and bias gradients of layer `name` into self.g; dx (may be None) = dL/dx."""
@@ -213,15 +211,11 @@ class UNet:
         nn.to_bf16(dy, dy16)
         w16, _, gw, gb = self._wb(name)
         nn.rowsum(co, N, dy, gb, bf["parts"])
-        col = bf["col"][:ci * 9 * N]
-        nn.im2col(ci, B, H, W, s, x, col)
         # weight gradient: a short, wide product over the long pixel axis, split along it
         splits = max(1, min(SPLIT_PARTS, N // 1024))
-        nn.gemm_splitk(co, ci * 9, N, dy16, N, 0, col, N, 1, gw, ci * 9, splits, bf["parts"])
+        nn.conv3x3_weight_grad(co, ci, B, H, W, s, dy16, x, gw, splits, bf["parts"])
         if dx is not None:
-            dcol = bf["dcol"][:ci * 9 * N]
-            nn.gemm(ci * 9, N, co, w16, ci * 9, 1, dy16, N, 0, dcol, N)
-            nn.col2im(ci, B, H, W, s, dcol, dx)
+            nn.conv3x3_adjoint(co, ci, B, H, W, s, w16, dy16, dx)
 
     def forward(self, x=None, B=None, H=256, W=256):
         """Network output for the input already in the buffer x (or copied from `x`)."""

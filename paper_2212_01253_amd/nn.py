@@ -17,7 +17,7 @@ EXPORTS = ("msl_nn_gemm_bf16", "msl_nn_gemm_bf16_splitk", "msl_nn_im2col3x3", "m
            "msl_nn_upsample2_adjoint", "msl_nn_rowpool", "msl_nn_rowpool_adjoint", "msl_nn_relu_adjoint",
            "msl_nn_add", "msl_nn_to_bf16", "msl_nn_rowsum", "msl_nn_mse", "msl_nn_adam", "msl_nn_logmap",
            "msl_nn_render_pools", "msl_nn_pool_average", "msl_nn_row_features", "msl_nn_add_row_bias",
-           "msl_nn_row_bias_adjoint")
+           "msl_nn_row_bias_adjoint", "msl_nn_conv3x3", "msl_nn_conv3x3_adjoint", "msl_nn_conv3x3_weight_grad")
 
 MAX_BOXES = 64   # MSL_NN_MAX_BOXES
 MAX_CUTS = 132   # MSL_NN_MAX_CUTS
@@ -52,6 +52,9 @@ def lib():
             "msl_nn_row_features": [I, I, I, P, P, P, P, P],
             "msl_nn_add_row_bias": [I, I, I, P, P, P],
             "msl_nn_row_bias_adjoint": [I, I, I, P, P, P],
+            "msl_nn_conv3x3": [I, I, I, I, I, I, P, P, P, I, P, P],
+            "msl_nn_conv3x3_adjoint": [I, I, I, I, I, I, P, P, P, P],
+            "msl_nn_conv3x3_weight_grad": [I, I, I, I, I, I, P, P, P, I, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -91,6 +94,21 @@ def gemm(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, beta=0.0, bias=None, r
 def gemm_splitk(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, splits, partials):
     _ck(lib().msl_nn_gemm_bf16_splitk(M, N, K, _p(A, BF16), lda, int(transA), _p(B, BF16), ldb, int(transB),
                                       _p(C, torch.float32), ldc, int(splits), _p(partials, torch.float32), _s()))
+
+
+def conv3x3(Co, C, B, H, W, stride, w16, x, y, bias=None, relu=False):
+    _ck(lib().msl_nn_conv3x3(Co, C, B, H, W, stride, _p(w16, BF16), _p(x, torch.float32), _p(bias, torch.float32),
+                             int(relu), _p(y, torch.float32), _s()))
+
+
+def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx):
+    _ck(lib().msl_nn_conv3x3_adjoint(Co, C, B, H, W, stride, _p(w16, BF16), _p(dy16, BF16), _p(dx, torch.float32),
+                                     _s()))
+
+
+def conv3x3_weight_grad(Co, C, B, H, W, stride, dy16, x, dw, splits, partials):
+    _ck(lib().msl_nn_conv3x3_weight_grad(Co, C, B, H, W, stride, _p(dy16, BF16), _p(x, torch.float32),
+                                         _p(dw, torch.float32), int(splits), _p(partials, torch.float32), _s()))
 
 
 def im2col(C, B, H, W, stride, x, col):

@@ -87,6 +87,46 @@ def test_convolution_through_patches_matches_the_oracle(T, s):
     assert rel(dx.cpu().numpy(), rdx) <= 1e-6
 
 
+@pytest.mark.parametrize("C,B,H,W,O,s", [(5, 2, 12, 8, 7, 1), (5, 2, 12, 8, 7, 2), (2, 3, 16, 16, 70, 1),
+                                         (16, 2, 8, 24, 9, 2), (8, 1, 32, 32, 4, 1)])
+def test_implicit_convolution(T, C, B, H, W, O, s):
+    # the implicit products equal the explicit ones (patch matrix, then product; split product for
+    # the weight gradient) bit for bit, and match the oracle; so does the input gradient
+    import torch
+    rng = np.random.default_rng(C * 100 + O)
+    x = rng.standard_normal((C, B, H, W)).astype(np.float32)
+    w = rng.standard_normal((O, C, 3, 3))
+    wb = N.bf16(w)
+    w16 = dev(bf16_bits(wb.reshape(O, -1)))
+    bias = rng.standard_normal(O).astype(np.float32)
+    Ho, Wo = H // s, W // s
+    n = B * Ho * Wo
+    col = torch.zeros(C * 9 * n, dtype=torch.int16, device="cuda")
+    T.im2col(C, B, H, W, s, dev(x), col)
+    y_exp = torch.zeros((O, B, Ho, Wo), dtype=torch.float32, device="cuda")
+    T.gemm(O, n, C * 9, w16, C * 9, 0, col, n, 0, y_exp, n, bias=dev(bias), relu=True)
+    y = torch.zeros((O, B, Ho, Wo), dtype=torch.float32, device="cuda")
+    T.conv3x3(O, C, B, H, W, s, w16, dev(x), y, bias=dev(bias), relu=True)
+    dy = N.bf16(rng.standard_normal((O, B, Ho, Wo)))
+    dy16 = dev(bf16_bits(dy))
+    dx = torch.full((C, B, H, W), float("nan"), dtype=torch.float32, device="cuda")
+    T.conv3x3_adjoint(O, C, B, H, W, s, w16, dy16, dx)
+    splits = 3
+    parts = torch.zeros(splits * O * C * 9, dtype=torch.float32, device="cuda")
+    dw_exp = torch.zeros((O, C * 9), dtype=torch.float32, device="cuda")
+    T.gemm_splitk(O, C * 9, n, dy16, n, 0, col, n, 1, dw_exp, C * 9, splits, parts)
+    dw = torch.full((O, C * 9), float("nan"), dtype=torch.float32, device="cuda")
+    T.conv3x3_weight_grad(O, C, B, H, W, s, dy16, dev(x), dw, splits, parts)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), y_exp.cpu().numpy())
+    assert np.array_equal(dw.cpu().numpy(), dw_exp.cpu().numpy())
+    ref = np.maximum(N.conv3x3(N.bf16(x), wb, bias, s), 0.0)
+    rdx, rdw, _ = N.conv3x3_adjoint(N.bf16(x), wb, dy, s)
+    assert rel(y.cpu().numpy(), ref) <= 1e-6
+    assert rel(dx.cpu().numpy(), rdx) <= 1e-6
+    assert rel(dw.cpu().numpy(), rdw.reshape(O, C * 9)) <= 1e-6
+
+
 def test_resampling_and_elementwise_kernels(T):
     import torch
     rng = np.random.default_rng(3)
