@@ -8,7 +8,9 @@ full size (256 x 256 x 1024, checkpoints every 32 slices) compares the GPU
 gradient with the oracle's on 16 sampled voxels and on its relative L2 norm;
 the benchmark's own gradient step (512 x 512 x 2048, slice pack reused,
 checkpoints every 32 slices, and again with one at every slice) gets the same
-comparison.
+comparison.  The batched workload (96 instances in one call, as benchmarked)
+is compared with the oracle on the instance with the fewest slices of every
+grid size.
 """
 import math
 import time
@@ -138,3 +140,48 @@ def test_gradient_512x512x2048_as_benchmarked(M):
     print(f"every-slice checkpoints: bitwise equal {np.array_equal(gd1, gd) and np.array_equal(gb1, gb)}", flush=True)
     assert L1 == L
     assert rel(gd1, gd) <= 1e-6 and rel(gb1, gb) <= 1e-6 and rel(gp1, gp) <= 1e-6
+
+
+class _Slices:
+    """Slice s of a compact stack as the oracle reads it (no dense copy)."""
+
+    def __init__(self, pool, index):
+        self.pool, self.index = pool, index
+
+    def __getitem__(self, s):
+        return self.pool[self.index[s]]
+
+
+@pytest.mark.timeout(900)
+def test_batched_workload_as_benchmarked_sampled_instances(M):
+    # the benchmark's batched forward (all 96 instances in one call), then the oracle on the
+    # instance with the fewest slices of every grid size and on the longest 512-point one
+    stacks = synth.batch_workload(96)
+    items = []
+    for cs in stacks:
+        g = cs.geom
+        items.append({"geom": g, "pool_delta": torch.from_numpy(cs.pool_delta).cuda(),
+                      "pool_beta": torch.from_numpy(cs.pool_beta).cuda(),
+                      "slice_index": torch.from_numpy(cs.index.astype(np.int32)).cuda(),
+                      "field": torch.empty((g.ny, g.nz), dtype=torch.complex64, device="cuda"),
+                      "intensity": torch.empty((g.ny, g.nz), dtype=torch.float32, device="cuda")})
+    ws = M.batch_workspace(items)
+    M.forward_batch(items, ws)
+    torch.cuda.synchronize()
+    pick = {}
+    for i, cs in enumerate(stacks):
+        n = cs.geom.ny
+        if n not in pick or cs.geom.n_slices < stacks[pick[n]].geom.n_slices:
+            pick[n] = i
+    assert sorted(pick) == [128, 256, 512, 1024]
+    longest = max((i for i, cs in enumerate(stacks) if cs.geom.ny == 512), key=lambda i: stacks[i].geom.n_slices)
+    for n, i in sorted(pick.items()) + [(512, longest)]:
+        cs, it = stacks[i], items[i]
+        t0 = time.time()
+        rf = O.forward(cs.geom, _Slices(cs.pool_delta, cs.index), _Slices(cs.pool_beta, cs.index))
+        rI = O.far_field(cs.geom, rf)
+        ef = rel(it["field"].cpu().numpy(), rf)
+        ei = rel(it["intensity"].cpu().numpy(), rI)
+        print(f"instance {i} ({cs.name}): oracle {time.time() - t0:.1f} s; field {ef:.2e} intensity {ei:.2e}",
+              flush=True)
+        assert ef <= 2e-5 and ei <= 1e-4
