@@ -52,7 +52,7 @@ def run_forward(M, g, d, b, probe=None, k=0, sched=1):
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
-@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
 def test_parity_64x64x128(M, sched, seed):
     w = synth.parity_small(seed)
     f, I, _ = run_forward(M, w.geom, w.delta, w.beta, sched=sched)
