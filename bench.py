@@ -182,7 +182,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the multislice recurrence is sequential over slices and "
-              f"this build has no multi-GPU path); got --gpus {args.gpus}", file=sys.stderr)
+              f"the library has no multi-GPU path); got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
