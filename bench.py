@@ -101,9 +101,10 @@ def recon_leg():
                         f"(slices x rows x columns), beta = delta/20, 1e6 photons, checkpoints every 32"}
 
 
-def batch_leg(n_inst, steps=3):
+def batch_leg(n_inst, steps=3, autotune=False):
     """Batched forward (msl_forward_batch) over the batched workload: instances seeded 1000 + i,
-    grids 128..1024, 256..4096 slices, per-instance wavelength and incidence; far field included."""
+    grids 128..1024, 256..4096 slices, per-instance wavelength and incidence; far field included.
+    With autotune, msl_autotune_batch picks the launch shape first (untimed)."""
     import numpy as np
     import torch
     from paper_2212_01253_amd import msl, synth
@@ -117,6 +118,9 @@ def batch_leg(n_inst, steps=3):
                       "field": torch.empty((g.ny, g.nz), dtype=torch.complex64, device="cuda"),
                       "intensity": torch.empty((g.ny, g.nz), dtype=torch.float32, device="cuda")})
     ws = msl.batch_workspace(items)
+    tuning = None
+    if autotune:
+        tuning, _ = msl.autotune_batch(items, ws, reps=1)
     msl.forward_batch(items, ws)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -134,7 +138,7 @@ def batch_leg(n_inst, steps=3):
             "voxel_slices": vs, "achieved_GBs": vs * FWD_BYTES / (ms / 1e3) / 1e9,
             "frac": vs * FWD_BYTES / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "pool_slices": int(sum(cs.pool_delta.shape[0] for cs in stacks)),
-            "instances_per_grid": grids,
+            "instances_per_grid": grids, "tuning": tuning or msl.get_tuning(),
             "workload": "batched forward + far field: instances seeded 1000+i, grids {128,256,512,1024}^2, "
                         "256..4096 slices of 5 nm, wavelength U[0.08, 0.15] nm, incidence U[0.05, 0.5] deg"}
 
@@ -177,6 +181,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initialiser leg")
     ap.add_argument("--no-every-slice", action="store_true",
                     help="skip the extra timing with a checkpoint at every slice (no recompute)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shapes with the library's autotuner before the timed runs")
     ap.add_argument("--batch", type=int, default=96, metavar="N",
                     help="also time the batched forward over N instances of the batched workload (96 = full, 0 = skip)")
     args = ap.parse_args()
@@ -202,6 +208,9 @@ def main():
     B = torch.from_numpy(w.beta).to(dev)
     Mm = torch.from_numpy(meas).to(dev)
     ws = msl.workspace(g, k, dev)
+    if args.autotune:
+        print("# autotuning the launch shape ...", file=sys.stderr, flush=True)
+        msl.autotune_forward(g, D, B, ws=ws, reps=3)
     field = torch.empty((ny, nz), dtype=torch.complex64, device=dev)
     ck = torch.empty((msl.checkpoint_count(g, k), ny, nz), dtype=torch.complex64, device=dev)
     gd = torch.empty_like(D)
@@ -297,7 +306,7 @@ def main():
                  "ms_p10": float(np.percentile(step_ms, 10)), "ms_p50": float(np.median(step_ms)),
                  "ms_p90": float(np.percentile(step_ms, 90)),
                  "pack_ms": float(np.median(pack_ms)), "forward_ms": fwd_med, "adjoint_ms": float(np.median(adj_ms)),
-                 "far_field_loss_seed_ms": float(np.median(mid_ms))},
+                 "far_field_loss_seed_ms": float(np.median(mid_ms)), "tuning": msl.get_tuning()},
         # forward path alone (pack, forward sweep, far field, loss): Ny Nz Ns / time
         "forward_throughput": {"value": vs / (fwd_path_ms / 1e3), "unit": "voxel-slice-steps/s",
                                "ms": fwd_path_ms},
@@ -334,7 +343,7 @@ def main():
         torch.cuda.empty_cache()
     if args.batch:
         print(f"# batched forward ({args.batch} instances) ...", file=sys.stderr, flush=True)
-        out["batch"] = batch_leg(args.batch)
+        out["batch"] = batch_leg(args.batch, autotune=args.autotune)
     if not args.no_recon:
         print("# reconstruction (plain init) ...", file=sys.stderr, flush=True)
         out["recon"] = recon_leg()

@@ -255,6 +255,14 @@ size_t msl_batch_workspace_bytes(const msl_instance* inst, int32_t n);
 msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspace, size_t ws_bytes,
                              void* hip_stream);
 
+/* Launch-shape autotuner for a batch, as msl_autotune_forward (msl_set_tuning): times
+ * msl_forward_batch over inst[0..n) for every batch_streams value (1..4), keeps the fastest,
+ * then every allowed lines-per-workgroup value of each line length the instances use, one
+ * length at a time.  The instances' outputs are overwritten by the timed runs; workspace as
+ * for msl_forward_batch; blocks until the search ends. */
+msl_status msl_autotune_batch(const msl_instance* inst, int32_t n, void* workspace, size_t ws_bytes, int32_t reps,
+                              void* hip_stream, msl_tuning* best, float* best_ms);
+
 /* ------------------------------------------------------------------------
  * Object rotation [Eq. 2-3; Sec. 2]: the paper rotates the sample's index
  * volume into the lab frame (pitch by the incidence angle about the

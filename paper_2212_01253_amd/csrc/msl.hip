@@ -653,6 +653,83 @@ msl_status check_instances(const msl_instance* inst, int n) {
 
 }  // namespace
 
+// Coordinate search over the launch shape for a unit of work `run` enqueues on
+// st: first the number of grid-size groups side by side (when tune_streams),
+// then the lines per workgroup of each slot in turn, every allowed value;
+// each candidate runs once untimed and then `reps` times between two events.
+// The fastest setting stays in effect; on an error the previous one returns.
+template <class Run>
+msl_status autotune_shapes(Run run, hipStream_t st, int reps, const int* slots, int nslots, bool tune_streams,
+                           msl_tuning* best, float* best_ms) {
+  msl_tuning saved;
+  MSL_TRY(msl_get_tuning(&saved));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MSL_TRY(hip_check(hipEventCreate(&e0), "hipEventCreate"));
+  const msl_status ce = hip_check(hipEventCreate(&e1), "hipEventCreate");
+  if (ce != MSL_OK) {
+    (void)hipEventDestroy(e0);
+    return ce;
+  }
+  auto time_run = [&](float& ms) -> msl_status {
+    MSL_TRY(run());
+    MSL_TRY(hip_check(hipEventRecord(e0, st), "hipEventRecord"));
+    for (int r = 0; r < reps; ++r) MSL_TRY(run());
+    MSL_TRY(hip_check(hipEventRecord(e1, st), "hipEventRecord"));
+    MSL_TRY(hip_check(hipEventSynchronize(e1), "hipEventSynchronize"));
+    MSL_TRY(hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime"));
+    ms /= (float)reps;
+    return MSL_OK;
+  };
+  auto search = [&](float& t_best) -> msl_status {
+    MSL_TRY(time_run(t_best));
+    if (tune_streams) {
+      const int keep = g_batch_streams;
+      const int current = keep > 0 ? keep : kBatchStreams + 1;
+      int best_v = keep;
+      for (int v = 1; v <= kBatchStreams + 1; ++v) {
+        if (v == current) continue;
+        g_batch_streams = v;
+        float t = 0.0f;
+        MSL_TRY(time_run(t));
+        if (t < t_best) {
+          t_best = t;
+          best_v = v;
+        }
+      }
+      g_batch_streams = best_v;
+    }
+    for (int q = 0; q < nslots; ++q) {
+      const int e = slots[q];
+      const int keep = g_lines_per_group[e];
+      const int current = lines_per_group(1 << e, 1 << 30);  // the shape in effect, timed already
+      int best_v = keep;
+      for (int v = 1; v <= max_lines_per_group(1 << e); v *= 2) {
+        if (v == current) continue;
+        g_lines_per_group[e] = v;
+        float t = 0.0f;
+        MSL_TRY(time_run(t));
+        if (t < t_best) {
+          t_best = t;
+          best_v = v;
+        }
+      }
+      g_lines_per_group[e] = best_v;
+    }
+    return MSL_OK;
+  };
+  float t_best = 0.0f;
+  const msl_status st_search = search(t_best);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st_search != MSL_OK) {
+    (void)msl_set_tuning(&saved);
+    return st_search;
+  }
+  if (best) MSL_TRY(msl_get_tuning(best));
+  if (best_ms) *best_ms = t_best;
+  return MSL_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 
@@ -702,66 +779,26 @@ msl_status msl_autotune_forward(const msl_geometry* g, const float* delta, const
   MSL_TRY(check_geometry(g));
   if (!field_scratch) return fail(MSL_ERR_ARG, "field_scratch is NULL");
   if (reps < 1 || reps > 1000) return fail(MSL_ERR_ARG, "reps must be in [1, 1000]");
-  msl_tuning saved;
-  MSL_TRY(msl_get_tuning(&saved));
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  MSL_TRY(hip_check(hipEventCreate(&e0), "hipEventCreate"));
-  const msl_status ce = hip_check(hipEventCreate(&e1), "hipEventCreate");
-  if (ce != MSL_OK) {
-    (void)hipEventDestroy(e0);
-    return ce;
-  }
-  auto forward = [&]() {
+  auto run = [&]() {
     return msl_forward(g, delta, beta, nullptr, field_scratch, nullptr, 0, 0u, workspace, ws_bytes, hip_stream);
   };
-  // one untimed forward, then `reps` timed back to back
-  auto time_forward = [&](float& ms) -> msl_status {
-    MSL_TRY(forward());
-    MSL_TRY(hip_check(hipEventRecord(e0, st), "hipEventRecord"));
-    for (int r = 0; r < reps; ++r) MSL_TRY(forward());
-    MSL_TRY(hip_check(hipEventRecord(e1, st), "hipEventRecord"));
-    MSL_TRY(hip_check(hipEventSynchronize(e1), "hipEventSynchronize"));
-    MSL_TRY(hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime"));
-    ms /= (float)reps;
-    return MSL_OK;
-  };
-  // one slot at a time (row passes use the nz-point slot, column passes the
-  // ny-point one), every power of two up to the slot's limit
-  auto search = [&](float& t_best) -> msl_status {
-    const int slots[2] = {__builtin_ctz((unsigned)g->nz), __builtin_ctz((unsigned)g->ny)};
-    MSL_TRY(time_forward(t_best));
-    for (int q = 0; q < 2; ++q) {
-      const int e = slots[q];
-      if (q == 1 && e == slots[0]) break;
-      const int keep = g_lines_per_group[e];
-      const int current = lines_per_group(1 << e, 1 << 30);  // the shape in effect, timed already
-      int best_v = keep;
-      for (int v = 1; v <= max_lines_per_group(1 << e); v *= 2) {
-        if (v == current) continue;
-        g_lines_per_group[e] = v;
-        float t = 0.0f;
-        MSL_TRY(time_forward(t));
-        if (t < t_best) {
-          t_best = t;
-          best_v = v;
-        }
-      }
-      g_lines_per_group[e] = best_v;
+  const int slots[2] = {__builtin_ctz((unsigned)g->nz), __builtin_ctz((unsigned)g->ny)};
+  return autotune_shapes(run, static_cast<hipStream_t>(hip_stream), reps, slots, 2, false, best, best_ms);
+}
+
+msl_status msl_autotune_batch(const msl_instance* inst, int32_t n, void* workspace, size_t ws_bytes, int32_t reps,
+                              void* hip_stream, msl_tuning* best, float* best_ms) {
+  MSL_TRY(check_instances(inst, n));
+  if (reps < 1 || reps > 1000) return fail(MSL_ERR_ARG, "reps must be in [1, 1000]");
+  auto run = [&]() { return msl_forward_batch(inst, n, workspace, ws_bytes, hip_stream); };
+  std::vector<int> slots;
+  for (int i = 0; i < n; ++i)
+    for (int d : {inst[i].g.nz, inst[i].g.ny}) {
+      const int e = __builtin_ctz((unsigned)d);
+      if (std::find(slots.begin(), slots.end(), e) == slots.end()) slots.push_back(e);
     }
-    return MSL_OK;
-  };
-  float t_best = 0.0f;
-  const msl_status st_search = search(t_best);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st_search != MSL_OK) {
-    (void)msl_set_tuning(&saved);
-    return st_search;
-  }
-  if (best) MSL_TRY(msl_get_tuning(best));
-  if (best_ms) *best_ms = t_best;
-  return MSL_OK;
+  return autotune_shapes(run, static_cast<hipStream_t>(hip_stream), reps, slots.data(), (int)slots.size(), true, best,
+                         best_ms);
 }
 
 size_t msl_workspace_bytes(const msl_geometry* g, int32_t ckpt_every) {

@@ -24,7 +24,8 @@ EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "ms
            "msl_far_field", "msl_amp_loss", "msl_far_field_adjoint", "msl_adjoint",
            "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
            "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap", "msl_rotate_object",
-           "msl_region_shrinkwrap", "msl_set_tuning", "msl_get_tuning", "msl_autotune_forward")
+           "msl_region_shrinkwrap", "msl_set_tuning", "msl_get_tuning", "msl_autotune_forward",
+           "msl_autotune_batch")
 
 TUNE_SLOTS = 11  # MSL_TUNE_SLOTS
 
@@ -129,6 +130,9 @@ def lib():
     L.msl_batch_workspace_bytes.argtypes = [Ip, c_int32]
     L.msl_forward_batch.restype = c_int32
     L.msl_forward_batch.argtypes = [Ip, c_int32, P, c_size_t, P]
+    L.msl_autotune_batch.restype = c_int32
+    L.msl_autotune_batch.argtypes = [Ip, c_int32, P, c_size_t, c_int32, P, ctypes.POINTER(CTuning),
+                                     ctypes.POINTER(ctypes.c_float)]
     R = ctypes.POINTER(CRegion)
     L.msl_region_scatter.restype = c_int32
     L.msl_region_scatter.argtypes = [G, R, P, P, P, P]
@@ -514,6 +518,19 @@ def batch_workspace(items, device=None):
     ws = torch.empty(n + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
     return ws[off:off + n]
+
+
+def autotune_batch(items, ws=None, reps=1):
+    """msl_autotune_batch: returns (tuning dict now in effect, mean batch ms); overwrites the
+    items' outputs."""
+    arr = _instances(items)
+    if ws is None:
+        ws = batch_workspace(items)
+    t = CTuning()
+    ms = ctypes.c_float()
+    _check(lib().msl_autotune_batch(arr, len(items), ws.data_ptr(), ws.numel(), int(reps), _stream(),
+                                    ctypes.byref(t), ctypes.byref(ms)))
+    return _tuning_dict(t), float(ms.value)
 
 
 def forward_batch(items, ws=None):

@@ -273,3 +273,4 @@ def test_autotune_validates(L):
     assert st == msl.ERR_ARG                              # reps < 1
     st = L.msl_autotune_forward(ctypes.byref(G(ny=48)), FAKE, FAKE, FAKE, FAKE, 1 << 40, 3, None, None, None)
     assert st == msl.ERR_ARG                              # not a power of two
+    assert L.msl_autotune_batch(None, 1, FAKE, 1 << 40, 1, None, None, None) == msl.ERR_ARG   # no instances

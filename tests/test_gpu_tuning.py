@@ -91,6 +91,38 @@ def test_batch_streams_and_shapes_give_identical_fields(M):
     M.set_tuning({})
 
 
+def test_batch_autotune_picks_allowed_settings_and_keeps_results(M):
+    import torch
+    specs = [(64, 64, 30), (128, 128, 17), (32, 32, 9), (256, 256, 8)]
+    items = []
+    for i, (ny, nz, ns) in enumerate(specs):
+        g = synth.Geometry(ny, nz, ns, 1.0, 1.0, 5.0, 0.1, np.radians(0.2), 0)
+        cs = synth.compact_bars_on_substrate(g, 400 + i, substrate_rows=ny // 4, n_bars=(2, 5),
+                                             bar_height=(1, ny // 8), bar_width=(1, nz // 4),
+                                             bar_len_frac=(0.125, 1.0), n_lines=(1, 2),
+                                             delta_range=(5e-6, 3e-5), beta_over_delta=0.05)
+        items.append({"geom": g, "pool_delta": dev(cs.pool_delta), "pool_beta": dev(cs.pool_beta),
+                      "slice_index": dev(cs.index.astype(np.int32)), "probe": None,
+                      "field": torch.empty((ny, nz), dtype=torch.complex64, device="cuda"),
+                      "intensity": torch.empty((ny, nz), dtype=torch.float32, device="cuda")})
+    M.set_tuning({})
+    M.forward_batch(items)
+    torch.cuda.synchronize()
+    ref = [(it["field"].cpu().numpy(), it["intensity"].cpu().numpy()) for it in items]
+    t, ms = M.autotune_batch(items, reps=1)
+    print(t, ms)
+    assert ms > 0 and 0 <= t["batch_streams"] <= 4
+    for n in (32, 64, 128, 256):
+        v = t["lines_per_group"][n]
+        assert v == 0 or (v & (v - 1) == 0 and 1 <= v <= LIMIT[n])
+    assert M.get_tuning() == t
+    M.forward_batch(items)
+    torch.cuda.synchronize()
+    for it, (rf, rI) in zip(items, ref):
+        assert np.array_equal(it["field"].cpu().numpy(), rf) and np.array_equal(it["intensity"].cpu().numpy(), rI)
+    M.set_tuning({})
+
+
 def test_autotune_picks_an_allowed_shape_and_keeps_results(M):
     g, d, b = stack(256, 256, 64, 5)
     M.set_tuning({})
