@@ -204,6 +204,7 @@ def throughput_512(seed: int = 2212, n_slices: int = 2048, n: int = 512) -> Work
                           line_height=(2, 40), line_width=(1, 4),
                           delta_range=(5e-6, 3e-5), beta_over_delta=1.0 / 20.0)
     w.name = f"bars_{n}x{n}x{n_slices}"
+    w.seed = seed   # the workload's seed (incidence draw; the features use seed + 1)
     return w
 
 
