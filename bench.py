@@ -153,6 +153,7 @@ def learned_leg():
     init = synth.random_init(p.region, 4244)
     L_truth, res, chose, L_learned, L_plain = recon.seconds_to_threshold_learned(p, net, init)
     info.update({"secs_to_threshold": res.secs_to_threshold, "iterations": res.iters_to_threshold,
+                 "adam_lr_refine": recon.REFINE_LR if chose else None,
                  "loss_learned_start": L_learned, "loss_plain_start": L_plain, "used_learned_start": chose})
     return info
 

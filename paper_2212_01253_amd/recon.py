@@ -21,7 +21,7 @@ measured amplitudes sqrt(C / s) and multiplied by s (and so is its gradient).
 from __future__ import annotations
 
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 import torch
@@ -31,7 +31,7 @@ from . import msl, synth
 
 @dataclass
 class Adam:
-    lr: float = 1e-5   # chosen once on the 256x256x1024 workload (1e-6 ... 5e-5 tried) and frozen
+    lr: float = 1.25e-5   # from a sweep on the 256x256x1024 workload (7e-6 ... 3e-5), plain start
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-12
@@ -246,12 +246,17 @@ def learned_initial_guess(net, p: Problem):
     return np.ascontiguousarray(np.broadcast_to(cs, (p.region["ns"],) + cs.shape))
 
 
+REFINE_LR = 5e-6   # ADAM step from a learned start (sweep 4e-6 ... 8.5e-6 on the same workload)
+
+
 def seconds_to_threshold_learned(p: Problem, net, plain_init, factor=1.10, max_iters=5000, adam: Adam | None = None,
-                                 ckpt_every=32, log_every=0, graphs=True):
+                                 ckpt_every=32, log_every=0, graphs=True, refine_lr=REFINE_LR):
     """Learned start with an error judge: network inference, then the losses of the learned and the
     plain start are compared and ADAM runs from the lower one (the plain start is the fallback when
-    the learned guess is worse or not finite).  The reported seconds include inference and judging.
-    Returns (L_truth, result, chose_learned, loss_learned, loss_plain)."""
+    the learned guess is worse or not finite).  From the learned start ADAM takes the smaller
+    refinement step refine_lr (None: keep adam's); from the plain one, adam's own.  The reported
+    seconds include inference and judging.  Returns (L_truth, result, chose_learned, loss_learned,
+    loss_plain)."""
     R = Reconstructor(p.geom, p.known_delta, p.known_beta, p.region, p.counts, p.scale, ckpt_every=ckpt_every,
                       adam=adam, graphs=graphs)
     R.set_theta(p.truth)
@@ -265,6 +270,8 @@ def seconds_to_threshold_learned(p: Problem, net, plain_init, factor=1.10, max_i
     R.set_theta(plain_init)
     L_plain = float(R.loss().item()) * p.scale
     chose = bool(np.isfinite(L_learned) and L_learned < L_plain)
+    if chose and refine_lr is not None:
+        R.adam = replace(R.adam, lr=float(refine_lr))
     t_judge = time.perf_counter() - t0
     res = R.run(guess if chose else plain_init, max_iters, factor * L_truth, log_every=log_every)
     res.times = [t + t_judge for t in res.times]
