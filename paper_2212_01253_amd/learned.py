@@ -471,7 +471,7 @@ def evaluate(net, data, batch=64):
     return total / count
 
 
-def train_initialiser(n_samples=8192, steps=800, batch=32, lr=1e-3, n=256, n_slices=1024, seed=0, log_every=0,
+def train_initialiser(n_samples=50000, steps=800, batch=32, lr=1e-3, n=256, n_slices=1024, seed=0, log_every=0,
                       n_val=256):
     """Training set from the model, the network with the targets' mean as output offset, ADAM.
     Returns (net, info) with the data and training times and the validation error of the network
