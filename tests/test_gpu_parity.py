@@ -247,3 +247,45 @@ def test_autograd_wrappers(M):
     assert abs(float(L.detach().cpu()) - rL) <= 1e-4 * rL
     assert rel(d.grad.cpu().numpy(), rd) <= GRAD_TOL
     assert rel(b.grad.cpu().numpy(), rb) <= GRAD_TOL
+
+
+def _random_case(seed):
+    """A seeded geometry: independent row and column counts, pitches, slice count, checkpoint
+    interval, propagator and probe (None or a random field)."""
+    rng = np.random.default_rng(seed)
+    ny, nz = (int(v) for v in rng.choice([16, 32, 64, 128, 256], 2))
+    ns = int(rng.integers(2, 49))
+    k = int(rng.choice([1, 2, 5, 16, ns]))
+    prop = int(rng.integers(0, 2))
+    g = synth.Geometry(ny, nz, ns, float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.5, 2.0)),
+                       float(rng.uniform(2.0, 20.0)), float(rng.uniform(0.08, 0.15)),
+                       math.radians(float(rng.uniform(0.05, 0.5))), prop)
+    d, b = synth.random_stack(ny, nz, ns, seed + 1, 3e-5, 2e-6)
+    probe = None if rng.random() < 0.5 else synth.random_field(ny, nz, seed + 2)
+    return g, d, b, probe, k
+
+
+@pytest.mark.parametrize("seed", range(7000, 7012))
+def test_random_geometries_forward_and_gradient(M, seed):
+    g, d, b, probe, k = _random_case(seed)
+    M.set_schedule(1)
+    D, B = dev(d), dev(b)
+    P = None if probe is None else dev(probe.astype(np.complex64))
+    ws = M.workspace(g, k)
+    f, ck = M.forward(g, D, B, P, k, ws=ws)
+    I = M.far_field(g, f, ws=ws)
+    rf = O.forward(g, d, b, None if probe is None else probe.astype(np.complex128))
+    rI = O.far_field(g, rf)
+    meas = (np.sqrt(O.far_field(g, O.forward(g, d * 1.1, b * 1.1,
+                                             None if probe is None else probe.astype(np.complex128))))
+            * (1 + 0.05 * np.random.default_rng(seed).random((g.ny, g.nz)))).astype(np.float32)
+    loss, gI = M.amp_loss(g, I, dev(meas), ws=ws)
+    gpsi = M.far_field_adjoint(g, f, gI, ws=ws)
+    gd, gb, gp = M.adjoint(g, D, B, ck, k, gpsi, probe=P, ws=ws)
+    torch.cuda.synchronize()
+    rL, rd, rb, rp, _, _ = O.loss_and_gradient(g, d, b, meas, None if probe is None else probe.astype(np.complex128))
+    errs = (rel(f.cpu().numpy(), rf), rel(I.cpu().numpy(), rI), abs(float(loss.cpu()) - rL) / rL,
+            rel(gd.cpu().numpy(), rd), rel(gb.cpu().numpy(), rb), rel(gp.cpu().numpy(), rp))
+    print(seed, g.ny, g.nz, g.n_slices, k, g.propagator, probe is not None, ["%.1e" % e for e in errs])
+    assert errs[0] <= FIELD_TOL and errs[1] <= INT_TOL and errs[2] <= 1e-4
+    assert errs[3] <= GRAD_TOL and errs[4] <= GRAD_TOL and errs[5] <= GRAD_TOL
