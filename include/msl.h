@@ -40,11 +40,13 @@
  * intensities and measured amplitudes are float32 [ny][nz] in fftshifted order.
  *
  * Memory and ownership: every array argument is DEVICE memory owned by the
- * caller.  The library allocates nothing; it builds its tables (FFT
+ * caller.  The library allocates no device memory; it builds its tables (FFT
  * twiddles, propagator, probe) in the caller's workspace on every call, so it
- * keeps no state between calls and calls on different streams with different
+ * keeps no data between calls and calls on different streams with different
  * workspaces may overlap.  Calls that share a workspace or an output must be
- * ordered by the caller.
+ * ordered by the caller.  Process-wide are only the execution settings
+ * (msl_set_schedule, msl_set_tuning) and, per device, the helper streams and
+ * events the adjoint and the batched forward create on first use.
  *
  * Asynchrony: every call only enqueues work on `hip_stream` (a hipStream_t
  * passed as void*, NULL = the null stream) and returns.  Faults during
