@@ -4,6 +4,7 @@ import pytest
 
 from oracle import msl_oracle as O
 from paper_2212_01253_amd import synth
+from parity_gates import check_forward, fmt
 
 pytestmark = pytest.mark.gpu
 
@@ -82,9 +83,7 @@ def test_batch_matches_the_oracle(M):
         d, b = cs.dense()
         rf = O.forward(cs.geom, d, b)
         rI = O.far_field(cs.geom, rf)
-        print(cs.geom.ny, cs.geom.nz, cs.geom.n_slices, rel(f, rf), rel(I, rI))
-        assert rel(f, rf) <= 2e-5
-        assert rel(I, rI) <= 1e-4
+        print(cs.geom.ny, cs.geom.nz, cs.geom.n_slices, fmt(check_forward(f, rf, I, rI, what=str(cs.geom))))
 
 
 def test_slice_index_is_clamped_to_the_pool(M):

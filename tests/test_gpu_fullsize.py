@@ -2,7 +2,8 @@
 
 The benchmark's forward sweep, in the launch configuration the benchmark
 uses, against the FP64 oracle on the same float32 inputs: exit field relative
-L2 <= 2e-5 and far-field intensity relative L2 <= 1e-4.  The oracle needs
+L2 <= 2e-5 and far-field intensity relative L2 <= 1e-4, and element by
+element (every field element, every far-field amplitude; parity_gates.py).  The oracle needs
 about a minute of host CPU here.  A gradient check at the gradient workload's
 full size (256 x 256 x 1024, checkpoints every 32 slices) compares the GPU
 gradient with the oracle's on 16 sampled voxels and on its relative L2 norm;
@@ -20,6 +21,7 @@ import pytest
 
 from oracle import msl_oracle as O
 from paper_2212_01253_amd import synth
+from parity_gates import check_forward, fmt
 
 torch = pytest.importorskip("torch")
 
@@ -57,10 +59,8 @@ def test_forward_512x512x2048(M):
     t0 = time.time()
     rf = O.forward(g, w.delta, w.beta)
     rI = O.far_field(g, rf)
-    ef, ei = rel(f, rf), rel(I, rI)
-    print(f"oracle {time.time() - t0:.1f} s; field rel-L2 {ef:.3e}, intensity rel-L2 {ei:.3e}", flush=True)
-    assert ef <= 2e-5
-    assert ei <= 1e-4
+    print(f"oracle {time.time() - t0:.1f} s", flush=True)
+    print(fmt(check_forward(f, rf, I, rI)), flush=True)
 
 
 @pytest.mark.timeout(900)
@@ -180,8 +180,6 @@ def test_batched_workload_as_benchmarked_sampled_instances(M):
         t0 = time.time()
         rf = O.forward(cs.geom, _Slices(cs.pool_delta, cs.index), _Slices(cs.pool_beta, cs.index))
         rI = O.far_field(cs.geom, rf)
-        ef = rel(it["field"].cpu().numpy(), rf)
-        ei = rel(it["intensity"].cpu().numpy(), rI)
-        print(f"instance {i} ({cs.name}): oracle {time.time() - t0:.1f} s; field {ef:.2e} intensity {ei:.2e}",
-              flush=True)
-        assert ef <= 2e-5 and ei <= 1e-4
+        print(f"instance {i} ({cs.name}): oracle {time.time() - t0:.1f} s", flush=True)
+        errs = check_forward(it["field"].cpu().numpy(), rf, it["intensity"].cpu().numpy(), rI, what=f"instance {i}")
+        print(f"instance {i}: {fmt(errs)}", flush=True)

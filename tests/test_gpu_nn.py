@@ -298,6 +298,24 @@ def test_unet_forward_and_gradients_match_the_oracle(T):
         assert e_w <= 1e-3 and e_b <= 1e-3, name
     tight = sum(1 for e_w, e_b in errs.values() if e_w <= 1e-6 and e_b <= 1e-6)
     assert tight >= 0.6 * len(errs), errs
+    # Against the unquantised FP64 network (no bfloat16 rounding anywhere): the bfloat16 network
+    # differs by first-order product rounding only.  Every quantised product rounds both of its
+    # operands to bfloat16 (unit roundoff u = 2^-9), a relative error of at most 2u per product;
+    # along the longest path, 12 convolutions and the head's 2 dense layers forward, then as many
+    # products backward, so with unit amplification per layer the output is within 2 * 14 u and
+    # the gradients within 2 * 28 u of the exact network's.
+    u = 2.0 ** -9
+    xpred, xcache = N.unet_forward(params, xin, offset=off, feat_norm=(fshift, fscale), quantize=False)
+    _, xdpred = N.mse(xpred, tgt)
+    xg = N.unet_adjoint(params, xcache, xdpred)
+    e_pred = rel(pred.cpu().numpy(), xpred)
+    gv = np.concatenate([np.concatenate([g[n][0].ravel(), g[n][1].ravel()]) for n in params])
+    xv = np.concatenate([np.concatenate([xg[n][0].ravel(), xg[n][1].ravel()]) for n in params])
+    e_grad = rel(gv, xv)
+    print(f"against the unquantised network: prediction {e_pred:.2e} (bound {28 * u:.2e}), "
+          f"gradients {e_grad:.2e} (bound {56 * u:.2e})")
+    assert e_pred <= 2 * 14 * u
+    assert e_grad <= 2 * 28 * u
 
 
 @pytest.mark.parametrize("ta,tb,splits", [(0, 1, 7), (0, 0, 1), (1, 1, 33)])

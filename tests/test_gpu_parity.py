@@ -2,7 +2,9 @@
 
 Tolerances: exit field relative L2 <= 2e-5 and far-field intensity relative
 L2 <= 1e-4 (complex64 on the GPU against complex128 on the CPU from the same
-float32 inputs).  Gradients: relative L2 <= 1e-3.
+float32 inputs), and element by element: every field element and every
+far-field amplitude sqrt(I) within the bounds that follow from the float32
+error model (parity_gates.py).  Gradients: relative L2 <= 1e-3.
 """
 import math
 
@@ -11,6 +13,7 @@ import pytest
 
 from oracle import msl_oracle as O
 from paper_2212_01253_amd import synth
+from parity_gates import check_field, check_forward, check_intensity, fmt
 
 torch = pytest.importorskip("torch")
 
@@ -58,9 +61,7 @@ def test_parity_64x64x128(M, sched, seed):
     f, I, _ = run_forward(M, w.geom, w.delta, w.beta, sched=sched)
     rf = O.forward(w.geom, w.delta, w.beta)
     rI = O.far_field(w.geom, rf)
-    print(f"seed {seed} sched {sched}: field {rel(f, rf):.3e} intensity {rel(I, rI):.3e}")
-    assert rel(f, rf) <= FIELD_TOL
-    assert rel(I, rI) <= INT_TOL
+    print(f"seed {seed} sched {sched}: {fmt(check_forward(f, rf, I, rI))}")
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
@@ -73,8 +74,7 @@ def test_size_sweep(M, sched, ny, nz, ns):
     f, I, _ = run_forward(M, g, d, b, probe=p, sched=sched)
     rf = O.forward(g, d, b, p.astype(np.complex128))
     rI = O.far_field(g, rf)
-    assert rel(f, rf) <= FIELD_TOL, rel(f, rf)
-    assert rel(I, rI) <= INT_TOL, rel(I, rI)
+    print(f"{ny}x{nz}x{ns}: {fmt(check_forward(f, rf, I, rI))}")
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
@@ -83,8 +83,7 @@ def test_exact_propagator(M, sched):
     g = synth.Geometry(**{**w.geom.as_dict(), "propagator": 1})
     f, I, _ = run_forward(M, g, w.delta, w.beta, sched=sched)
     rf = O.forward(g, w.delta, w.beta)
-    assert rel(f, rf) <= FIELD_TOL
-    assert rel(I, O.far_field(g, rf)) <= INT_TOL
+    print(fmt(check_forward(f, rf, I, O.far_field(g, rf))))
     # and it is a different model from the paraxial one
     assert rel(rf, O.forward(w.geom, w.delta, w.beta)) > 1e-3
 
@@ -97,8 +96,8 @@ def test_checkpoints_hold_entrance_fields(M):
     rf, kept = O.forward(g, d, b, keep=True)
     assert ck.shape == (6, 64, 64)
     for c in range(6):
-        assert rel(ck[c], kept[7 * c]) <= FIELD_TOL
-    assert rel(f, rf) <= FIELD_TOL
+        check_field(ck[c], kept[7 * c], what=f"checkpoint {c}")
+    check_field(f, rf)
 
 
 def test_vacuum_composition_on_gpu(M):
@@ -109,7 +108,7 @@ def test_vacuum_composition_on_gpu(M):
     z = np.zeros((16, ny, nz), np.float32)
     f16, _, _ = run_forward(M, g, z, z, probe=p)
     f1, _, _ = run_forward(M, g1, z[:1], z[:1], probe=p)
-    assert rel(f16, f1) <= FIELD_TOL
+    check_field(f16, f1)
 
 
 def test_parseval_on_gpu(M):
@@ -139,7 +138,7 @@ def test_far_field_and_loss(M):
     torch.cuda.synchronize()
     rI = O.far_field(g, psi.astype(np.complex128))
     L, _, rgI = O.amp_loss(I.cpu().numpy().astype(np.float64), meas)
-    assert rel(I.cpu().numpy(), rI) <= INT_TOL
+    check_intensity(I.cpu().numpy(), rI)
     assert abs(float(loss.cpu()) - L) <= 1e-9 * abs(L)
     assert rel(gI.cpu().numpy(), rgI) <= 1e-6
     rg = O.far_field_adjoint(g, psi.astype(np.complex128), gI.cpu().numpy().astype(np.float64))
@@ -287,5 +286,6 @@ def test_random_geometries_forward_and_gradient(M, seed):
     errs = (rel(f.cpu().numpy(), rf), rel(I.cpu().numpy(), rI), abs(float(loss.cpu()) - rL) / rL,
             rel(gd.cpu().numpy(), rd), rel(gb.cpu().numpy(), rb), rel(gp.cpu().numpy(), rp))
     print(seed, g.ny, g.nz, g.n_slices, k, g.propagator, probe is not None, ["%.1e" % e for e in errs])
+    print(seed, fmt(check_forward(f.cpu().numpy(), rf, I.cpu().numpy(), rI)))
     assert errs[0] <= FIELD_TOL and errs[1] <= INT_TOL and errs[2] <= 1e-4
     assert errs[3] <= GRAD_TOL and errs[4] <= GRAD_TOL and errs[5] <= GRAD_TOL
