@@ -128,6 +128,26 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
                        msl_c64* ckpt, int32_t ckpt_every, uint32_t flags,
                        void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* Forward without allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Computes exactly what msl_forward computes (same
+ * arguments and outputs, no workspace, no flags) and enqueues the same kind of
+ * work, but its tables (FFT twiddles, propagator) live in a fixed device array
+ * of MSL_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends; the call allocates and frees nothing.  It builds no slice
+ * pack: the odd slices' column passes evaluate their transmission from
+ * delta and beta directly (the same arithmetic, slower memory access).
+ * Limits: the exact propagator's table must fit, i.e. ny * nz <= 512 * 512
+ * with MSL_PROP_EXACT (any valid paraxial geometry fits); a larger request
+ * returns MSL_ERR_UNSUPPORTED before anything is enqueued.  All calls on one
+ * GPU share its array, which keeps the last call's tables: calls that overlap
+ * on one GPU (other streams, other host threads) race and must be ordered by
+ * the caller.  The schedule setting is ignored (always one launch per pass). */
+#define MSL_NOALLOC_SCRATCH_BYTES ((size_t)(8 * 1024 * 8 + 2 * 512 * 512 * 8))
+msl_status msl_forward_noalloc(const msl_geometry* g, const float* delta, const float* beta,
+                               const msl_c64* probe, msl_c64* field_out,
+                               msl_c64* ckpt, int32_t ckpt_every, void* hip_stream);
+
 /* Far-field detector intensity of a field [Sec. 1; Fig. 1 caption]:
  * intensity[r][c] = |A|^2 / (ny nz) at fftshifted position (r, c), float32. */
 msl_status msl_far_field(const msl_geometry* g, const msl_c64* field, float* intensity,

@@ -328,10 +328,10 @@ struct Call {
   hipStream_t st;
 };
 
-Call make_call(const msl_geometry& g, int k, void* ws, hipStream_t st) {
+Call make_call(const msl_geometry& g, const Layout& lay, void* ws, hipStream_t st) {
   Call k_{};
   k_.g = g;
-  k_.L = layout(g, k);
+  k_.L = lay;
   k_.ws = static_cast<char*>(ws);
   k_.st = st;
   Ctx& c = k_.c;
@@ -356,6 +356,8 @@ Call make_call(const msl_geometry& g, int k, void* ws, hipStream_t st) {
   c.inv_m = 1.0f / (float)c.m;
   return k_;
 }
+
+Call make_call(const msl_geometry& g, int k, void* ws, hipStream_t st) { return make_call(g, layout(g, k), ws, st); }
 
 msl_status build_tables(const Call& k, bool need_prop) {
   const msl_geometry& g = k.g;
@@ -731,6 +733,65 @@ msl_status autotune_shapes(Run run, hipStream_t st, int reps, const int* slots, 
 }
 
 // ---------------------------------------------------------------------------
+// Forward without allocation (msl_forward_noalloc): the tables live in a
+// fixed-size device array instead of the caller's workspace.  Each GPU the
+// library runs on holds its own copy of the array until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name on the host is not a device address).
+
+constexpr size_t kNoAllocLineTable = 1024 * sizeof(float2);         // a line table of up to 1024 points
+constexpr size_t kNoAllocHTable = (size_t)512 * 512 * sizeof(float2);  // exact propagator, up to 512 x 512
+constexpr size_t kNoAllocBytes = 8 * kNoAllocLineTable + 2 * kNoAllocHTable;
+static_assert(kNoAllocBytes == MSL_NOALLOC_SCRATCH_BYTES, "msl.h states the scratch size");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// Table regions of msl_forward_noalloc inside the scratch array (the layout
+// fields of the workspace regions it does not use stay 0).
+Layout noalloc_layout(const msl_geometry& g) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
+  L.twz_hi = take(g.nz * 8);
+  L.twz_lo = take(g.nz * 8);
+  L.twy_hi = take(g.ny * 8);
+  L.twy_lo = take(g.ny * 8);
+  L.hz_hi = take(g.nz * 8);
+  L.hz_lo = take(g.nz * 8);
+  L.hy_hi = take(g.ny * 8);
+  L.hy_lo = take(g.ny * 8);
+  const bool exact = g.propagator == MSL_PROP_EXACT;
+  const size_t m = (size_t)g.ny * g.nz;
+  L.H_hi = take(exact ? m * 8 : 0);
+  L.H_lo = take(exact ? m * 8 : 0);
+  L.total = o;
+  return L;
+}
+
+// Device address of the scratch array on the current device, looked up on the
+// first call on that device and kept.
+msl_status noalloc_scratch(char*& out) {
+  static std::mutex mu;
+  static void* ptr[64] = {};
+  int dev = 0;
+  MSL_TRY(hip_check(hipGetDevice(&dev), "hipGetDevice"));
+  if (dev < 0 || dev >= 64) return fail(MSL_ERR_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    MSL_TRY(hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+    if (!p) return fail(MSL_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    ptr[dev] = p;
+  }
+  out = static_cast<char*>(ptr[dev]);
+  return MSL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 
 extern "C" {
@@ -862,6 +923,52 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
     MSL_TRY(pack_odd(k));
   }
   return run_phase(k, ph);
+}
+
+msl_status msl_forward_noalloc(const msl_geometry* g, const float* delta, const float* beta, const msl_c64* probe,
+                               msl_c64* field_out, msl_c64* ckpt, int32_t ckpt_every, void* hip_stream) {
+  MSL_TRY(check_geometry(g));
+  MSL_TRY(check_ptr(delta, 4, "delta"));
+  MSL_TRY(check_ptr(beta, 4, "beta"));
+  MSL_TRY(check_ptr(probe, 8, "probe", true));
+  MSL_TRY(check_ptr(field_out, 8, "field_out"));
+  MSL_TRY(check_ptr(ckpt, 8, "ckpt", true));
+  if (ckpt && ckpt_every < 1) return fail(MSL_ERR_ARG, "ckpt given but ckpt_every < 1");
+  if (!ckpt && ckpt_every != 0) return fail(MSL_ERR_ARG, "ckpt_every != 0 but ckpt is NULL");
+  const Layout lay = noalloc_layout(*g);
+  if (lay.total > kNoAllocBytes)
+    return fail(MSL_ERR_UNSUPPORTED, "msl_forward_noalloc: the tables of a " + std::to_string(g->ny) + " x " +
+                                         std::to_string(g->nz) + " grid need " + std::to_string(lay.total) +
+                                         " bytes, more than its fixed scratch of " + std::to_string(kNoAllocBytes) +
+                                         " (the exact propagator's table fits grids up to 512 x 512 points)");
+  char* base = nullptr;
+  MSL_TRY(noalloc_scratch(base));
+  Call k = make_call(*g, lay, base, static_cast<hipStream_t>(hip_stream));
+  k.c.delta = delta;
+  k.c.beta = beta;
+  MSL_TRY(build_tables(k, true));
+  float2* f = reinterpret_cast<float2*>(field_out);
+  if (probe) {
+    MSL_TRY(copy_field(k, f, probe));
+  } else {
+    const double q = 2.0 * M_PI / g->wavelength_nm * std::sin(g->alpha_i_rad) * g->dy_nm;
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)((k.c.m + 255) / 256)), dim3(256), 0, k.st, g->ny, g->nz, q, f);
+    MSL_TRY(hip_check(hipGetLastError(), "probe kernel"));
+  }
+  // No slice pack (it would not fit a fixed scratch): column passes evaluate
+  // the transmission of their slices from the caller's stack, with the same
+  // arithmetic as the pack.  Always one launch per pass.
+  PhaseSpec ph = blank_phase(k, msl::PH_FWD_FULL);
+  ph.s0 = 0;
+  ph.s1 = g->n_slices;
+  ph.field = f;
+  ph.fieldT = nullptr;
+  ph.inplace = 1;
+  ph.ckpt = reinterpret_cast<float2*>(ckpt);
+  ph.ckpt_every = ckpt ? ckpt_every : 0;
+  const int np = msl::phase_npasses(ph);
+  for (int p = 0; p < np; ++p) MSL_TRY(hip_check(launch_pass(k.c, msl::phase_pass(ph, p), k.st), "pass kernel"));
+  return MSL_OK;
 }
 
 msl_status msl_far_field(const msl_geometry* g, const msl_c64* field, float* intensity, void* workspace,

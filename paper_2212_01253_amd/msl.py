@@ -25,7 +25,7 @@ EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "ms
            "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
            "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap", "msl_rotate_object",
            "msl_region_shrinkwrap", "msl_set_tuning", "msl_get_tuning", "msl_autotune_forward",
-           "msl_autotune_batch")
+           "msl_autotune_batch", "msl_forward_noalloc")
 
 TUNE_SLOTS = 11  # MSL_TUNE_SLOTS
 
@@ -103,6 +103,8 @@ def lib():
     L.msl_pack_slices.restype = c_int32
     L.msl_pack_slices.argtypes = [G, P, P, P, c_size_t, P]
     L.msl_forward.argtypes = [G, P, P, P, P, P, c_int32, ctypes.c_uint32, P, c_size_t, P]
+    L.msl_forward_noalloc.restype = c_int32
+    L.msl_forward_noalloc.argtypes = [G, P, P, P, P, P, c_int32, P]
     L.msl_far_field.restype = c_int32
     L.msl_far_field.argtypes = [G, P, P, P, c_size_t, P]
     L.msl_amp_loss.restype = c_int32
@@ -291,6 +293,27 @@ def forward(g, delta, beta, probe=None, ckpt_every=0, ws=None, out=None, ckpt=No
         if ckpt_every else None,
         int(ckpt_every), REUSE_SLICE_PACK if reuse_pack else 0, ws.data_ptr(), ws.numel(), _stream())
     _check(st)
+    return out, (ckpt if ckpt_every else None)
+
+
+def forward_noalloc(g, delta, beta, probe=None, ckpt_every=0, out=None, ckpt=None):
+    """msl_forward_noalloc: as ``forward`` without a workspace (the library's fixed
+    per-GPU scratch holds its tables); returns (psi_Ns, checkpoints or None)."""
+    cg = geometry(g)
+    ny, nz, ns = cg.ny, cg.nz, cg.n_slices
+    dev = delta.device
+    if out is None:
+        out = torch.empty((ny, nz), dtype=torch.complex64, device=dev)
+    if ckpt_every and ckpt is None:
+        ckpt = torch.empty((checkpoint_count(cg, ckpt_every), ny, nz), dtype=torch.complex64, device=dev)
+    _check(lib().msl_forward_noalloc(
+        ctypes.byref(cg), _ptr(delta, torch.float32, (ns, ny, nz), "delta"),
+        _ptr(beta, torch.float32, (ns, ny, nz), "beta"),
+        _ptr(probe, torch.complex64, (ny, nz), "probe", True),
+        _ptr(out, torch.complex64, (ny, nz), "out"),
+        _ptr(ckpt, torch.complex64, (checkpoint_count(cg, ckpt_every), ny, nz), "ckpt", True)
+        if ckpt_every else None,
+        int(ckpt_every), _stream()))
     return out, (ckpt if ckpt_every else None)
 
 

@@ -274,3 +274,19 @@ def test_autotune_validates(L):
     st = L.msl_autotune_forward(ctypes.byref(G(ny=48)), FAKE, FAKE, FAKE, FAKE, 1 << 40, 3, None, None, None)
     assert st == msl.ERR_ARG                              # not a power of two
     assert L.msl_autotune_batch(None, 1, FAKE, 1 << 40, 1, None, None, None) == msl.ERR_ARG   # no instances
+
+
+def test_forward_noalloc_validates(L):
+    def nf(g, delta=FAKE, beta=FAKE, probe=None, out=FAKE, ckpt=None, k=0):
+        return L.msl_forward_noalloc(ctypes.byref(g), delta, beta, probe, out, ckpt, k, None)
+
+    assert nf(G(ny=15)) == msl.ERR_ARG
+    assert nf(G(), delta=None) == msl.ERR_ARG
+    assert nf(G(), out=FAKE + 4) == msl.ERR_ARG
+    assert nf(G(), probe=FAKE + 4) == msl.ERR_ARG
+    assert nf(G(), ckpt=FAKE, k=0) == msl.ERR_ARG
+    assert nf(G(), ckpt=None, k=3) == msl.ERR_ARG
+    # beyond the fixed scratch: the exact propagator's 2-D table of grids above 512 x 512
+    for ny, nz in ((1024, 1024), (512, 1024)):
+        assert nf(G(ny=ny, nz=nz, propagator=1)) == msl.ERR_UNSUPPORTED
+        assert "scratch" in L.msl_last_error().decode()
