@@ -207,6 +207,20 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
  * Returns the previous setting, or MSL_ERR_ARG for an unknown value. */
 int32_t msl_set_schedule(int32_t schedule);
 
+/* Outcome of the last msl_forward, msl_far_field, msl_far_field_adjoint or
+ * msl_adjoint call on `workspace` (each of them restarts it): waits for
+ * hip_stream, then returns MSL_OK, or MSL_ERR_HIP if a grid barrier of the
+ * persistent schedule gave up waiting.  That wait is bounded (it polls at most
+ * the spin limit below, then raises an error word and lets the grid drain);
+ * the call's results are then not valid, and its working field is overwritten
+ * with NaN.  Errors of the per-pass schedule surface as HIP errors instead. */
+msl_status msl_workspace_status(void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Polls the persistent schedule's barrier makes before it gives up
+ * (process-wide, default 2^22, far beyond any healthy wait; >= 0).  Returns the
+ * previous value, or MSL_ERR_ARG.  A small value forces the failure path. */
+int32_t msl_set_barrier_spin_limit(int32_t polls);
+
 /* ---- launch shape and its autotuner ----
  * The line passes run as workgroups of several lines each.  Entry e of
  * lines_per_group is the number of 2^e-point lines per workgroup (e = 4..10;

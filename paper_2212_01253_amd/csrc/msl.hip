@@ -31,6 +31,9 @@ int g_schedule = MSL_SCHED_AUTO;
 int g_lines_per_group[MSL_TUNE_SLOTS] = {};
 int g_batch_streams = 0;  // 0: default (every extra stream)
 
+// Polls of the persistent schedule's bounded barrier wait (msl_set_barrier_spin_limit).
+unsigned g_spin_limit = msl::kDefaultSpinLimit;
+
 constexpr int kLdsSlots = 1152;  // float2 slots of a line-pass workgroup's LDS (two 512-point lines)
 
 constexpr size_t kAlign = 256;
@@ -52,6 +55,7 @@ Layout layout(const msl_geometry& g, int k) {
   const size_t m = (size_t)g.ny * g.nz;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
+  L.bar = take(8192);  // first, at offset 0: msl_workspace_status finds its status word without the geometry
   L.twz_hi = take(g.nz * 8);
   L.twz_lo = take(g.nz * 8);
   L.twy_hi = take(g.ny * 8);
@@ -63,7 +67,6 @@ Layout layout(const msl_geometry& g, int k) {
   const bool exact = g.propagator == MSL_PROP_EXACT;
   L.H_hi = take(exact ? m * 8 : 0);
   L.H_lo = take(exact ? m * 8 : 0);
-  L.bar = take(8192);
   L.partials = take(kPartials * sizeof(double));
   L.tmp = take(m * 8);
   L.fT = take(m * 8);  // column-major partner of the forward field
@@ -443,7 +446,7 @@ msl_status run_phases(const Call& k, const PhaseSpec& a, const PhaseSpec* b) {
   if (np == 0) return MSL_OK;
   unsigned* bar = reinterpret_cast<unsigned*>(k.ws + k.L.bar);
   if (use_persistent(k, np)) {
-    hipError_t e = msl::launch_persistent(k.c, a, npa, npb > 0 ? b : nullptr, npb, bar, k.st);
+    hipError_t e = msl::launch_persistent(k.c, a, npa, npb > 0 ? b : nullptr, npb, bar, g_spin_limit, k.st);
     if (e == hipSuccess) return MSL_OK;
     if (g_schedule == MSL_SCHED_PERSISTENT) return hip_check(e, "persistent pass kernel");
     (void)hipGetLastError();  // AUTO: the per-pass schedule below does the same work
@@ -462,6 +465,12 @@ msl_status run_phases(const Call& k, const PhaseSpec& a, const PhaseSpec* b) {
 }
 
 msl_status run_phase(const Call& k, const PhaseSpec& ph) { return run_phases(k, ph, nullptr); }
+
+// Start of a call that runs phases: its workspace status word (msl_workspace_status) restarts at 0.
+msl_status clear_status(const Call& k) {
+  hipLaunchKernelGGL(msl::k_clear_status, dim3(1), dim3(64), 0, k.st, reinterpret_cast<unsigned*>(k.ws + k.L.bar));
+  return hip_check(hipGetLastError(), "status kernel");
+}
 
 msl_status copy_field(const Call& k, void* dst, const void* src) {
   return hip_check(hipMemcpyAsync(dst, src, (size_t)k.c.m * 8, hipMemcpyDeviceToDevice, k.st), "hipMemcpyAsync");
@@ -810,6 +819,30 @@ int32_t msl_set_schedule(int32_t schedule) {
   return prev;
 }
 
+int32_t msl_set_barrier_spin_limit(int32_t polls) {
+  if (polls < 0) {
+    g_last_error = "spin limit must be >= 0, got " + std::to_string(polls);
+    return MSL_ERR_ARG;
+  }
+  const int32_t prev = (int32_t)std::min<unsigned>(g_spin_limit, 0x7fffffffu);
+  g_spin_limit = (unsigned)polls;
+  return prev;
+}
+
+msl_status msl_workspace_status(void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!workspace) return fail(MSL_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(workspace, kAlign)) return fail(MSL_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (ws_bytes < 8192) return fail(MSL_ERR_WORKSPACE, "workspace too small to hold a status word");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  MSL_TRY(hip_check(hipStreamSynchronize(st), "hipStreamSynchronize"));
+  unsigned w[2] = {0u, 0u};
+  MSL_TRY(hip_check(hipMemcpy(w, workspace, sizeof w, hipMemcpyDeviceToHost), "hipMemcpy"));
+  if (w[1] != 0u)
+    return fail(MSL_ERR_HIP, "a grid barrier of the persistent schedule gave up waiting (bounded spin) in the last "
+                             "call on this workspace; its results are not valid (the working field holds NaN)");
+  return MSL_OK;
+}
+
 msl_status msl_set_tuning(const msl_tuning* t) {
   if (!t) return fail(MSL_ERR_ARG, "tuning is NULL");
   for (int e = 0; e < MSL_TUNE_SLOTS; ++e) {
@@ -900,6 +933,7 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
   k.c.delta = delta;
   k.c.beta = beta;
+  MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, true));
   float2* f = reinterpret_cast<float2*>(field_out);
   if (probe) {
@@ -979,6 +1013,7 @@ msl_status msl_far_field(const msl_geometry* g, const msl_c64* field, float* int
   MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
   Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
   k.c.intensity = intensity;
+  MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, false));
   PhaseSpec ph = blank_phase(k, msl::PH_FF);
   ph.ff_src = reinterpret_cast<const float2*>(field);
@@ -1013,6 +1048,7 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field, co
   MSL_TRY(check_ws(*g, 0, workspace, ws_bytes));
   Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
   k.c.grad_intensity = grad_intensity;
+  MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, false));
   PhaseSpec ph = blank_phase(k, msl::PH_FFADJ);
   ph.ff_src = reinterpret_cast<const float2*>(field);
@@ -1043,6 +1079,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   k.c.beta = beta;
   k.c.gdelta = grad_delta;
   k.c.gbeta = grad_beta;
+  MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, true));
   if (flags & MSL_REUSE_SLICE_PACK) {
     if (odd_slices(*g) > 0) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);

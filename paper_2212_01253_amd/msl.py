@@ -25,7 +25,7 @@ EXPORTS = ("msl_abi_version", "msl_workspace_bytes", "msl_checkpoint_count", "ms
            "msl_set_schedule", "msl_last_error", "msl_region_scatter", "msl_region_adam_step",
            "msl_batch_workspace_bytes", "msl_forward_batch", "msl_region_snap", "msl_rotate_object",
            "msl_region_shrinkwrap", "msl_set_tuning", "msl_get_tuning", "msl_autotune_forward",
-           "msl_autotune_batch", "msl_forward_noalloc")
+           "msl_autotune_batch", "msl_forward_noalloc", "msl_workspace_status", "msl_set_barrier_spin_limit")
 
 TUNE_SLOTS = 11  # MSL_TUNE_SLOTS
 
@@ -115,6 +115,10 @@ def lib():
     L.msl_adjoint.argtypes = [G, P, P, P, P, c_int32, P, P, P, P, ctypes.c_uint32, P, c_size_t, P]
     L.msl_set_schedule.restype = c_int32
     L.msl_set_schedule.argtypes = [c_int32]
+    L.msl_workspace_status.restype = c_int32
+    L.msl_workspace_status.argtypes = [P, c_size_t, P]
+    L.msl_set_barrier_spin_limit.restype = c_int32
+    L.msl_set_barrier_spin_limit.argtypes = [c_int32]
     T = ctypes.POINTER(CTuning)
     L.msl_set_tuning.restype = c_int32
     L.msl_set_tuning.argtypes = [T]
@@ -192,6 +196,20 @@ def abi_version():
 
 def set_schedule(mode: int) -> int:
     r = lib().msl_set_schedule(int(mode))
+    if r < 0:
+        _check(r)
+    return r
+
+
+def workspace_status(ws):
+    """msl_workspace_status: raises MslError if the last phase-running call on ``ws`` is invalid
+    (a persistent-schedule barrier gave up); waits for the current stream."""
+    _check(lib().msl_workspace_status(ws.data_ptr(), ws.numel(), _stream()))
+
+
+def set_barrier_spin_limit(polls: int) -> int:
+    """msl_set_barrier_spin_limit: returns the previous limit."""
+    r = lib().msl_set_barrier_spin_limit(int(polls))
     if r < 0:
         _check(r)
     return r

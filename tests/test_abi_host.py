@@ -290,3 +290,13 @@ def test_forward_noalloc_validates(L):
     for ny, nz in ((1024, 1024), (512, 1024)):
         assert nf(G(ny=ny, nz=nz, propagator=1)) == msl.ERR_UNSUPPORTED
         assert "scratch" in L.msl_last_error().decode()
+
+
+def test_status_query_and_spin_limit_validate(L):
+    assert L.msl_workspace_status(None, 1 << 20, None) == msl.ERR_WORKSPACE
+    assert L.msl_workspace_status(FAKE + 128, 1 << 20, None) == msl.ERR_WORKSPACE
+    assert L.msl_workspace_status(FAKE, 4096, None) == msl.ERR_WORKSPACE
+    assert L.msl_set_barrier_spin_limit(-1) == msl.ERR_ARG
+    prev = L.msl_set_barrier_spin_limit(7)
+    assert prev == 1 << 22
+    assert L.msl_set_barrier_spin_limit(prev) == 7

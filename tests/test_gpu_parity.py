@@ -47,9 +47,12 @@ def dev(a):
 
 def run_forward(M, g, d, b, probe=None, k=0, sched=1):
     M.set_schedule(sched)
+    ws = M.workspace(g, k)
     f, ck = M.forward(g, dev(d), dev(b), None if probe is None else dev(probe.astype(np.complex64)),
-                      ckpt_every=k)
-    I = M.far_field(g, f)
+                      ckpt_every=k, ws=ws)
+    M.workspace_status(ws)   # raises if a persistent barrier gave up
+    I = M.far_field(g, f, ws=ws)
+    M.workspace_status(ws)
     torch.cuda.synchronize()
     return f.cpu().numpy(), I.cpu().numpy(), (None if ck is None else ck.cpu().numpy())
 
@@ -163,10 +166,12 @@ def _grad_case(M, g, d, b, meas, k, sched=1, reuse_pack=False):
     D, B = dev(d), dev(b)
     ws = M.workspace(g, k)
     f, ck = M.forward(g, D, B, ckpt_every=k, ws=ws)
+    M.workspace_status(ws)
     I = M.far_field(g, f, ws=ws)
     loss, gI = M.amp_loss(g, I, dev(meas), ws=ws)
     gpsi = M.far_field_adjoint(g, f, gI, ws=ws)
     gd, gb, gp = M.adjoint(g, D, B, ck, k, gpsi, ws=ws, reuse_pack=reuse_pack)
+    M.workspace_status(ws)
     torch.cuda.synchronize()
     return float(loss.cpu()), gd.cpu().numpy(), gb.cpu().numpy(), gp.cpu().numpy()
 
@@ -289,3 +294,31 @@ def test_random_geometries_forward_and_gradient(M, seed):
     print(seed, fmt(check_forward(f.cpu().numpy(), rf, I.cpu().numpy(), rI)))
     assert errs[0] <= FIELD_TOL and errs[1] <= INT_TOL and errs[2] <= 1e-4
     assert errs[3] <= GRAD_TOL and errs[4] <= GRAD_TOL and errs[5] <= GRAD_TOL
+
+
+def test_persistent_barrier_that_gives_up_is_reported(M):
+    # the host forces the bounded barrier wait to give up (spin limit 0: a block that finds
+    # the others not yet arrived raises the error word at once); every kernel still exits
+    # normally, the status query reports the failure and the working field holds NaN; with
+    # the limit restored the same call is valid again and equals the per-pass schedule
+    w = synth.parity_small(2)
+    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": 24})
+    D, B = dev(w.delta[:24]), dev(w.beta[:24])
+    ws = M.workspace(g, 0)
+    prev = M.set_barrier_spin_limit(0)
+    try:
+        M.set_schedule(2)
+        f, _ = M.forward(g, D, B, ws=ws)
+        with pytest.raises(M.MslError) as e:
+            M.workspace_status(ws)
+        assert e.value.status == M.ERR_HIP and "barrier" in str(e.value)
+        assert torch.isnan(f).all()
+    finally:
+        M.set_barrier_spin_limit(prev)
+    f, _ = M.forward(g, D, B, ws=ws)
+    M.workspace_status(ws)
+    M.set_schedule(1)
+    ref, _ = M.forward(g, D, B, ws=ws)
+    M.workspace_status(ws)
+    torch.cuda.synchronize()
+    check_field(f.cpu().numpy(), ref.cpu().numpy().astype(np.complex128))
