@@ -222,12 +222,13 @@ msl_status msl_workspace_status(void* workspace, size_t ws_bytes, void* hip_stre
 int32_t msl_set_barrier_spin_limit(int32_t polls);
 
 /* ---- launch shape and its autotuner ----
- * The line passes run as workgroups of several lines each.  Entry e of
- * lines_per_group is the number of 2^e-point lines per workgroup (e = 4..10;
- * 0 = the library default: one 64-lane wavefront's worth of lanes; other
- * entries must be 0).  Allowed values are powers of two up to the limit set by
- * the 256-thread workgroup and the workgroup's line buffers in LDS:
- * 2^e = 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2, 1024: 1.
+ * The line passes run as workgroups of several neighbouring lines each.
+ * Entry e of lines_per_group is the number of 2^e-point lines per workgroup
+ * (e = 4..10; 0 = the library default: one 64-lane wavefront's worth of
+ * lanes and at least two lines; other entries must be 0).  Allowed values are
+ * powers of two up to the limit set by the 256-thread workgroup and the
+ * workgroup's line buffers in LDS:
+ * 2^e = 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 4, 1024: 2.
  * batch_streams: how many grid-size groups msl_forward_batch runs side by side
  * (1..4; 0 = 4).  The setting is process-wide, applies to later calls, and is
  * not synchronised with calls running on other threads. */

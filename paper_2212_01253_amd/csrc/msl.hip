@@ -34,7 +34,7 @@ int g_batch_streams = 0;  // 0: default (every extra stream)
 // Polls of the persistent schedule's bounded barrier wait (msl_set_barrier_spin_limit).
 unsigned g_spin_limit = msl::kDefaultSpinLimit;
 
-constexpr int kLdsSlots = 1152;  // float2 slots of a line-pass workgroup's LDS (two 512-point lines)
+constexpr int kLdsSlots = 4 * msl::line_lds<512>();  // float2 slots of a line-pass workgroup's LDS (four 512-point lines)
 
 constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -44,7 +44,7 @@ struct Layout {
   size_t twz_hi, twz_lo, twy_hi, twy_lo;
   size_t hz_hi, hz_lo, hy_hi, hy_lo;
   size_t H_hi, H_lo;
-  size_t bar, partials, tmp, fT, dbT, W, WT, G, GT, seg, gT;
+  size_t bar, partials, tmp, dbT, W, G, seg, gT;
   size_t total;
 };
 
@@ -68,17 +68,14 @@ Layout layout(const msl_geometry& g, int k) {
   L.H_hi = take(exact ? m * 8 : 0);
   L.H_lo = take(exact ? m * 8 : 0);
   L.partials = take(kPartials * sizeof(double));
-  L.tmp = take(m * 8);
-  L.fT = take(m * 8);  // column-major partner of the forward field
-  // paraxial: odd slices' (delta, beta) packed and transposed for the column passes
+  L.tmp = take(m * 8);  // tiled working field of the forward, the far field and its adjoint
+  // paraxial: the odd slices' transmissions T - 1, tiled, for the column passes
   const size_t odd = exact ? 0 : (size_t)(g.n_slices / 2);
   L.dbT = take(odd * m * 8);
   if (k >= 1) {
-    L.W = take(m * 8);
-    L.WT = take(m * 8);
-    L.G = take(m * 8);
-    L.GT = take(m * 8);
-    L.seg = take((size_t)(k > 1 ? k - 1 : 0) * m * 8 * 2);  // two segment buffers
+    L.W = take(m * 8);  // tiled working field of the segment recompute
+    L.G = take(m * 8);  // tiled working field of the reverse sweep (the cotangent)
+    L.seg = take((size_t)(k > 1 ? k - 1 : 0) * m * 8 * 2);  // two tiled segment buffers
     L.gT = take(odd * m * 8);  // odd slices' gradients, same layout as dbT
   }
   L.total = o;
@@ -164,65 +161,64 @@ __global__ void k_probe(int ny, int nz, double q, float2* out) {
 }
 
 // Slices' transmission minus one, T - 1 = exp(i k dx (delta + i beta)) - 1,
-// transposed: slice first + stride * s2 -> out[s2][z][y] (float2), through
-// T x T LDS tiles (T = 32, or 16 on 16-wide grids); 256 threads; s2 in
-// [s2b, s2e).  The odd slices of a stack (first 1, stride 2) or every slice
-// of a pool (first 0, stride 1).  The line passes evaluate T - 1 of the other
-// slices with the same function.
-template <int T>
-__global__ void __launch_bounds__(256) k_pack_odd(const float* d, const float* b, float2* out, int ny, int nz,
-                                                  int s2b, int s2e, int first, int stride, msl::Ctx c) {
-  __shared__ float2 tile[T][T + 1];
-  constexpr int R = 256 / T;  // rows of the tile per pass of the block
-  const int tx = threadIdx.x % T, ty = threadIdx.x / T;
-  const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
+// into the 2x2-tiled layout: slice first + stride * s2 -> out[s2], s2 in
+// [s2b, s2e); one thread per 2x2 tile (two 8-byte reads of each stack, one
+// 32-byte write).  The odd slices of a stack (first 1, stride 2) or every
+// slice of a pool (first 0, stride 1).  The line passes evaluate T - 1 of the
+// other slices with the same function.
+__global__ void __launch_bounds__(256) k_pack_tiled(const float* d, const float* b, float2* out, int ny, int nz,
+                                                    int s2b, int s2e, int first, int stride, msl::Ctx c) {
   const int64_t m = (int64_t)ny * nz;
-  for (int s2 = s2b + blockIdx.z; s2 < s2e; s2 += gridDim.z) {
-    const int64_t si = (int64_t)(first + stride * s2) * m;
-    for (int r = ty; r < T; r += R) {
-      const int64_t a = si + (int64_t)(y0 + r) * nz + z0 + tx;
-      tile[r][tx] = msl::transmission_m1(msl::phase_arg(d[a], c), msl::phase_arg(b[a], c));
+  const int tiles = (int)(m >> 2), tz = nz >> 1;
+  for (int s2 = s2b + blockIdx.y; s2 < s2e; s2 += gridDim.y) {
+    const float* ds = d + (int64_t)(first + stride * s2) * m;
+    const float* bs = b + (int64_t)(first + stride * s2) * m;
+    float2* o = out + (int64_t)s2 * m;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += gridDim.x * blockDim.x) {
+      const int64_t e = (int64_t)(2 * (t / tz)) * nz + 2 * (t % tz);
+      o[4 * (int64_t)t + 0] = msl::transmission_m1(msl::phase_arg(ds[e], c), msl::phase_arg(bs[e], c));
+      o[4 * (int64_t)t + 1] = msl::transmission_m1(msl::phase_arg(ds[e + 1], c), msl::phase_arg(bs[e + 1], c));
+      o[4 * (int64_t)t + 2] = msl::transmission_m1(msl::phase_arg(ds[e + nz], c), msl::phase_arg(bs[e + nz], c));
+      o[4 * (int64_t)t + 3] =
+          msl::transmission_m1(msl::phase_arg(ds[e + nz + 1], c), msl::phase_arg(bs[e + nz + 1], c));
     }
-    __syncthreads();
-    for (int r = ty; r < T; r += R) out[(int64_t)s2 * m + (int64_t)(z0 + r) * ny + y0 + tx] = tile[tx][r];
-    __syncthreads();
   }
 }
 
-// gT[s/2][z][y] (float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z]
-// for odd slices s = 2 s2 + 1, s2 in [s2b, s2e).
-template <int T>
-__global__ void __launch_bounds__(256) k_unpack_odd(const float2* gT, float* gd, float* gb, int ny, int nz,
-                                                    int s2b, int s2e) {
-  __shared__ float2 tile[T][T + 1];
-  constexpr int R = 256 / T;
-  const int tx = threadIdx.x % T, ty = threadIdx.x / T;
-  const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
+// gT[s2] (tiled float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z]
+// row-major for odd slices s = 2 s2 + 1, s2 in [s2b, s2e); one thread per tile.
+__global__ void __launch_bounds__(256) k_unpack_tiled(const float2* gT, float* gd, float* gb, int ny, int nz,
+                                                      int s2b, int s2e) {
   const int64_t m = (int64_t)ny * nz;
-  for (int s2 = s2b + blockIdx.z; s2 < s2e; s2 += gridDim.z) {
-    for (int r = ty; r < T; r += R) tile[r][tx] = gT[(int64_t)s2 * m + (int64_t)(z0 + r) * ny + y0 + tx];
-    __syncthreads();
-    for (int r = ty; r < T; r += R) {
-      const float2 v = tile[tx][r];
-      const int64_t o = (int64_t)(2 * s2 + 1) * m + (int64_t)(y0 + r) * nz + z0 + tx;
-      if (gd) gd[o] = v.x;
-      if (gb) gb[o] = v.y;
+  const int tiles = (int)(m >> 2), tz = nz >> 1;
+  for (int s2 = s2b + blockIdx.y; s2 < s2e; s2 += gridDim.y) {
+    const float2* q = gT + (int64_t)s2 * m;
+    const int64_t so = (int64_t)(2 * s2 + 1) * m;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += gridDim.x * blockDim.x) {
+      const int64_t e = so + (int64_t)(2 * (t / tz)) * nz + 2 * (t % tz);
+      const float2 v0 = q[4 * (int64_t)t], v1 = q[4 * (int64_t)t + 1], v2 = q[4 * (int64_t)t + 2],
+                   v3 = q[4 * (int64_t)t + 3];
+      if (gd) {
+        gd[e] = v0.x;
+        gd[e + 1] = v1.x;
+        gd[e + nz] = v2.x;
+        gd[e + nz + 1] = v3.x;
+      }
+      if (gb) {
+        gb[e] = v0.y;
+        gb[e + 1] = v1.y;
+        gb[e + nz] = v2.y;
+        gb[e + nz + 1] = v3.y;
+      }
     }
-    __syncthreads();
   }
 }
 
-// Row-major complex field -> column-major copy, through 32 x 32 LDS tiles
-// (16 x 16 on 16-wide grids).
-template <int T>
-__global__ void __launch_bounds__(256) k_to_colmajor(const float2* src, float2* dst, int ny, int nz) {
-  __shared__ float2 tile[T][T + 1];
-  constexpr int R = 256 / T;
-  const int tx = threadIdx.x % T, ty = threadIdx.x / T;
-  const int z0 = blockIdx.x * T, y0 = blockIdx.y * T;
-  for (int r = ty; r < T; r += R) tile[r][tx] = src[(int64_t)(y0 + r) * nz + z0 + tx];
-  __syncthreads();
-  for (int r = ty; r < T; r += R) dst[(int64_t)(z0 + r) * ny + y0 + tx] = tile[tx][r];
+// Launch shape of the tile kernels over n slices of an ny x nz grid.
+dim3 tile_grid(int ny, int nz, int n) {
+  const int64_t tiles = (int64_t)ny * nz / 4;
+  const unsigned gx = (unsigned)std::min<int64_t>((tiles + 255) / 256, 4096);
+  return dim3(gx, (unsigned)std::min(n, 8192));
 }
 
 // Amplitude loss partial sums (FP64) and dL/dI.
@@ -261,27 +257,35 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 // ---------------------------------------------------------------------------
 // per-pass launches
 
+// Thread t of a workgroup of G lines works on line t mod G at lane t / G:
+// neighbouring threads take neighbouring lines, so each load and store of a
+// wavefront covers whole 2x2 tiles of the tiled working fields.
 template <int N, int AXIS, int KIND>
 __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   __shared__ float2 lds[kLdsSlots];
   constexpr int L = msl::LinePts<N>::L;
-  const int g = threadIdx.x / L, j = threadIdx.x % L;
   const int G = blockDim.x / L;
+  const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
-  msl::run_line<N, AXIS, false, KIND>(c, pd, group * G + g, j, lds + g * (N + N / 8));
+  msl::run_line<N, AXIS, false, KIND>(c, pd, group * G + g, j, lds + g * msl::line_lds<N>());
 }
 
 // Lines per workgroup: at most 256 threads (the kernels' launch bound) and
 // the line exchange buffers within the kLdsSlots-slot LDS array.
 int max_lines_per_group(int n) {
   const int L = n / (n >= MSL_P8_MIN_N && n < MSL_P4_MIN_N ? 8 : 4);
-  return std::min(256 / L, kLdsSlots / (n + n / 8));
+  const int lds = n + n / 8 + 1;  // msl::line_lds<n>()
+  int G = 1;
+  while (2 * G * L <= 256 && 2 * G * lds <= kLdsSlots) G *= 2;
+  return G;
 }
 
+// Default: one 64-lane wavefront's worth of lanes, and at least two lines
+// (the two lines of a row or column of tiles).
 int lines_per_group(int n, int nlines) {
   const int L = n / (n >= MSL_P8_MIN_N && n < MSL_P4_MIN_N ? 8 : 4);
   int G = g_lines_per_group[__builtin_ctz((unsigned)n)];
-  if (G <= 0) G = L >= 64 ? 1 : 64 / L;
+  if (G <= 0) G = L >= 32 ? 2 : 64 / L;
   G = std::min(G, max_lines_per_group(n));
   return std::min(G, nlines);
 }
@@ -476,19 +480,6 @@ msl_status copy_field(const Call& k, void* dst, const void* src) {
   return hip_check(hipMemcpyAsync(dst, src, (size_t)k.c.m * 8, hipMemcpyDeviceToDevice, k.st), "hipMemcpyAsync");
 }
 
-// Puts a row-major field into the buffer (and layout) the first pass of
-// phase `ph` reads.
-msl_status load_phase_input(const Call& k, const PhaseSpec& ph, const float2* src) {
-  if (msl::phase_first_axis(ph) == msl::ROW) return copy_field(k, ph.field, src);
-  if (k.g.ny >= 32 && k.g.nz >= 32)
-    hipLaunchKernelGGL(k_to_colmajor<32>, dim3(k.g.nz / 32, k.g.ny / 32), dim3(256), 0, k.st, src, ph.fieldT, k.g.ny,
-                       k.g.nz);
-  else
-    hipLaunchKernelGGL(k_to_colmajor<16>, dim3(k.g.nz / 16, k.g.ny / 16), dim3(256), 0, k.st, src, ph.fieldT, k.g.ny,
-                       k.g.nz);
-  return hip_check(hipGetLastError(), "transpose kernel");
-}
-
 int odd_slices(const msl_geometry& g) { return g.propagator == MSL_PROP_PARAXIAL ? g.n_slices / 2 : 0; }
 
 // Odd slices among [s0, s1) are 2 s2 + 1 for s2 in [s0 / 2, s1 / 2).
@@ -499,14 +490,8 @@ int odd_end(int s1) { return s1 >> 1; }
 msl_status pack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
   if (s2e <= s2b) return MSL_OK;
   float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
-  const int n = s2e - s2b;
-  const unsigned gz = n < 8192 ? n : 8192;
-  if (k.g.ny >= 32 && k.g.nz >= 32)
-    hipLaunchKernelGGL(k_pack_odd<32>, dim3(k.g.nz / 32, k.g.ny / 32, gz), dim3(256), 0, st, k.c.delta, k.c.beta,
-                       dbT, k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c);
-  else
-    hipLaunchKernelGGL(k_pack_odd<16>, dim3(k.g.nz / 16, k.g.ny / 16, gz), dim3(256), 0, st, k.c.delta, k.c.beta,
-                       dbT, k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c);
+  hipLaunchKernelGGL(k_pack_tiled, tile_grid(k.g.ny, k.g.nz, s2e - s2b), dim3(256), 0, st, k.c.delta, k.c.beta, dbT,
+                     k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c);
   return hip_check(hipGetLastError(), "pack kernel");
 }
 
@@ -521,14 +506,8 @@ msl_status pack_odd(Call& k) {
 // Unpacks the gradients of odd slices 2 s2 + 1, s2 in [s2b, s2e), on stream st.
 msl_status unpack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
   if (s2e <= s2b || !k.c.gT) return MSL_OK;
-  const int n = s2e - s2b;
-  const unsigned gz = n < 8192 ? n : 8192;
-  if (k.g.ny >= 32 && k.g.nz >= 32)
-    hipLaunchKernelGGL(k_unpack_odd<32>, dim3(k.g.nz / 32, k.g.ny / 32, gz), dim3(256), 0, st, k.c.gT, k.c.gdelta,
-                       k.c.gbeta, k.g.ny, k.g.nz, s2b, s2e);
-  else
-    hipLaunchKernelGGL(k_unpack_odd<16>, dim3(k.g.nz / 16, k.g.ny / 16, gz), dim3(256), 0, st, k.c.gT, k.c.gdelta,
-                       k.c.gbeta, k.g.ny, k.g.nz, s2b, s2e);
+  hipLaunchKernelGGL(k_unpack_tiled, tile_grid(k.g.ny, k.g.nz, s2e - s2b), dim3(256), 0, st, k.c.gT, k.c.gdelta,
+                     k.c.gbeta, k.g.ny, k.g.nz, s2b, s2e);
   return hip_check(hipGetLastError(), "unpack kernel");
 }
 
@@ -571,15 +550,16 @@ __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__
                                                     PassDesc tmpl) {
   __shared__ float2 lds[kLdsSlots];
   constexpr int L = msl::LinePts<N>::L;
-  const int g = threadIdx.x / L, j = threadIdx.x % L;
   const int G = blockDim.x / L;
+  const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int gb = msl::xcd_group(blockIdx.x, gridDim.x);
   const int inst = gb / groups_per_inst;
   const Ctx c = recs[inst].c;
   PassDesc pd = tmpl;
   pd.src = recs[inst].field;
   pd.dst = recs[inst].field;
-  msl::run_line<N, AXIS, false, msl::KIND_FWD_MID>(c, pd, (gb % groups_per_inst) * G + g, j, lds + g * (N + N / 8));
+  msl::run_line<N, AXIS, false, msl::KIND_FWD_MID>(c, pd, (gb % groups_per_inst) * G + g, j,
+                                                   lds + g * msl::line_lds<N>());
 }
 
 template <int N, int AXIS>
@@ -936,19 +916,21 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, true));
   float2* f = reinterpret_cast<float2*>(field_out);
-  if (probe) {
-    MSL_TRY(copy_field(k, f, probe));
-  } else {
+  const float2* in = reinterpret_cast<const float2*>(probe);
+  if (!probe) {
     const double q = 2.0 * M_PI / g->wavelength_nm * std::sin(g->alpha_i_rad) * g->dy_nm;
     hipLaunchKernelGGL(k_probe, dim3((unsigned)((k.c.m + 255) / 256)), dim3(256), 0, k.st, g->ny, g->nz, q, f);
     MSL_TRY(hip_check(hipGetLastError(), "probe kernel"));
+    in = f;
   }
+  // the first pass reads the probe (row-major), the passes work on the tiled
+  // working field, the last one writes the exit wave row-major
   PhaseSpec ph = blank_phase(k, msl::PH_FWD_FULL);
   ph.s0 = 0;
   ph.s1 = g->n_slices;
-  ph.field = f;
-  ph.fieldT = reinterpret_cast<float2*>(k.ws + k.L.fT);
-  ph.inplace = 1;
+  ph.field = reinterpret_cast<float2*>(k.ws + k.L.tmp);
+  ph.in_rm = in;
+  ph.out_rm = f;
   ph.ckpt = reinterpret_cast<float2*>(ckpt);
   ph.ckpt_every = ckpt ? ckpt_every : 0;
   if (flags & MSL_REUSE_SLICE_PACK) {
@@ -982,22 +964,24 @@ msl_status msl_forward_noalloc(const msl_geometry* g, const float* delta, const 
   k.c.beta = beta;
   MSL_TRY(build_tables(k, true));
   float2* f = reinterpret_cast<float2*>(field_out);
-  if (probe) {
-    MSL_TRY(copy_field(k, f, probe));
-  } else {
+  const float2* in = reinterpret_cast<const float2*>(probe);
+  if (!probe) {
     const double q = 2.0 * M_PI / g->wavelength_nm * std::sin(g->alpha_i_rad) * g->dy_nm;
     hipLaunchKernelGGL(k_probe, dim3((unsigned)((k.c.m + 255) / 256)), dim3(256), 0, k.st, g->ny, g->nz, q, f);
     MSL_TRY(hip_check(hipGetLastError(), "probe kernel"));
+    in = nullptr;
   }
-  // No slice pack (it would not fit a fixed scratch): column passes evaluate
-  // the transmission of their slices from the caller's stack, with the same
-  // arithmetic as the pack.  Always one launch per pass.
+  // No slice pack and no tiled working field (neither would fit a fixed
+  // scratch): the passes work on the exit-wave array itself, row-major, and
+  // the column passes evaluate the transmission of their slices from the
+  // caller's stack, with the same arithmetic as the pack.  Always one launch
+  // per pass.
   PhaseSpec ph = blank_phase(k, msl::PH_FWD_FULL);
   ph.s0 = 0;
   ph.s1 = g->n_slices;
   ph.field = f;
-  ph.fieldT = nullptr;
-  ph.inplace = 1;
+  ph.in_rm = in;
+  ph.rowmajor = 1;
   ph.ckpt = reinterpret_cast<float2*>(ckpt);
   ph.ckpt_every = ckpt ? ckpt_every : 0;
   const int np = msl::phase_npasses(ph);
@@ -1016,8 +1000,8 @@ msl_status msl_far_field(const msl_geometry* g, const msl_c64* field, float* int
   MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, false));
   PhaseSpec ph = blank_phase(k, msl::PH_FF);
-  ph.ff_src = reinterpret_cast<const float2*>(field);
-  ph.fieldT = reinterpret_cast<float2*>(k.ws + k.L.tmp);
+  ph.in_rm = reinterpret_cast<const float2*>(field);
+  ph.field = reinterpret_cast<float2*>(k.ws + k.L.tmp);
   return run_phase(k, ph);
 }
 
@@ -1051,9 +1035,9 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field, co
   MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, false));
   PhaseSpec ph = blank_phase(k, msl::PH_FFADJ);
-  ph.ff_src = reinterpret_cast<const float2*>(field);
-  ph.field = reinterpret_cast<float2*>(grad_field);
-  ph.fieldT = reinterpret_cast<float2*>(k.ws + k.L.tmp);
+  ph.in_rm = reinterpret_cast<const float2*>(field);
+  ph.field = reinterpret_cast<float2*>(k.ws + k.L.tmp);
+  ph.out_rm = reinterpret_cast<float2*>(grad_field);
   return run_phase(k, ph);
 }
 
@@ -1089,9 +1073,9 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   const int nodd = odd_slices(*g);
   if (nodd > 0 && (grad_delta || grad_beta)) k.c.gT = reinterpret_cast<float2*>(k.ws + k.L.gT);
   float2* W = reinterpret_cast<float2*>(k.ws + k.L.W);
-  float2* WT = reinterpret_cast<float2*>(k.ws + k.L.WT);
   float2* G = reinterpret_cast<float2*>(k.ws + k.L.G);
-  float2* GT = reinterpret_cast<float2*>(k.ws + k.L.GT);
+  const float2* gin = reinterpret_cast<const float2*>(grad_field);
+  float2* gout = reinterpret_cast<float2*>(grad_probe);
   float2* seg = reinterpret_cast<float2*>(k.ws + k.L.seg);
   const float2* ck = reinterpret_cast<const float2*>(ckpt);
   const int ns = g->n_slices;
@@ -1103,7 +1087,7 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     ph.s0 = c * ckpt_every;
     ph.s1 = ph.s0 + ckpt_every < ns ? ph.s0 + ckpt_every : ns;
     ph.field = W;
-    ph.fieldT = WT;
+    ph.in_rm = ck + (int64_t)c * k.c.m;  // the first pass reads the checkpoint
     ph.seg = seg_of(c);
     return ph;
   };
@@ -1113,7 +1097,8 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     rv.s1 = rv.s0 + ckpt_every < ns ? rv.s0 + ckpt_every : ns;
     rv.leading = c == nck - 1;
     rv.field = G;
-    rv.fieldT = GT;
+    rv.in_rm = c == nck - 1 ? gin : nullptr;   // the cotangent of the exit wave enters the first reverse phase
+    rv.out_rm = c == 0 ? gout : nullptr;       // the probe's cotangent leaves the last one
     rv.seg = seg_of(c);
     rv.ckpt_c = ck + (int64_t)c * k.c.m;
     return rv;
@@ -1126,23 +1111,19 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     rv.s1 = ns;
     rv.leading = 1;
     rv.field = G;
-    rv.fieldT = GT;
+    rv.in_rm = gin;
+    rv.out_rm = gout;
     rv.seg = const_cast<float2*>(ck) + k.c.m;   // slice s >= 1 at ck[s] (only read)
     rv.ckpt_c = ck;
     rv.seg_row_major = 1;
-    MSL_TRY(load_phase_input(k, rv, reinterpret_cast<const float2*>(grad_field)));
     MSL_TRY(run_phase(k, rv));
     MSL_TRY(unpack_odd_range(k, 0, nodd, k.st));
-    if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));
     return MSL_OK;
   }
   // Segment c-1 is recomputed from its checkpoint while the reverse sweep runs
   // over segment c: the two fields are independent, so on square grids they
   // share passes (and each pass has twice the lines to spread over the chip).
-  MSL_TRY(load_phase_input(k, reverse(nck - 1), reinterpret_cast<const float2*>(grad_field)));
-  PhaseSpec rc = recomp(nck - 1);
-  MSL_TRY(load_phase_input(k, rc, ck + (int64_t)(nck - 1) * k.c.m));
-  MSL_TRY(run_phase(k, rc));
+  MSL_TRY(run_phase(k, recomp(nck - 1)));
   const bool persistent = use_persistent(k, ckpt_every + 1);
   auto seg_odd_b = [&](int c) { return odd_begin(c * ckpt_every); };
   auto seg_odd_e = [&](int c) { return odd_end((c + 1) * ckpt_every < ns ? (c + 1) * ckpt_every : ns); };
@@ -1152,7 +1133,6 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
       PhaseSpec rv = reverse(c);
       if (c >= 1) {
         PhaseSpec nx = recomp(c - 1);
-        MSL_TRY(load_phase_input(k, nx, ck + (int64_t)(c - 1) * k.c.m));
         MSL_TRY(run_phases(k, rv, &nx));
       } else {
         MSL_TRY(run_phase(k, rv));
@@ -1174,7 +1154,6 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
       if (c < nck - 1) MSL_TRY(hip_check(hipStreamWaitEvent(k.st, h->join, 0), "hipStreamWaitEvent"));
       MSL_TRY(stream_after(kh.st, k.st, h->fork));
       if (c >= 1) {
-        MSL_TRY(load_phase_input(kh, recomp(c - 1), ck + (int64_t)(c - 1) * k.c.m));
         MSL_TRY(run_phase(kh, recomp(c - 1)));
         MSL_TRY(hip_check(hipEventRecord(h->join, kh.st), "hipEventRecord"));
       }
@@ -1184,7 +1163,6 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
     MSL_TRY(unpack_odd_range(k, seg_odd_b(0), seg_odd_e(0), k.st));
     MSL_TRY(stream_after(k.st, kh.st, h->done));
   }
-  if (grad_probe) MSL_TRY(copy_field(k, grad_probe, G));
   return MSL_OK;
 }
 
@@ -1259,25 +1237,20 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
                        P(b.hy_lo));
     MSL_TRY(hip_check(hipGetLastError(), "table kernels"));
     float2* f = reinterpret_cast<float2*>(x.field_out);
-    if (x.probe) {
-      MSL_TRY(hip_check(hipMemcpyAsync(f, x.probe, (size_t)c.m * 8, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync"));
-    } else {
+    const float2* in = reinterpret_cast<const float2*>(x.probe);
+    if (!x.probe) {
       const double q = kk * std::sin(g.alpha_i_rad) * g.dy_nm;
       hipLaunchKernelGGL(k_probe, dim3((unsigned)((c.m + 255) / 256)), dim3(256), 0, st, g.ny, g.nz, q, f);
       MSL_TRY(hip_check(hipGetLastError(), "probe kernel"));
+      in = f;
     }
     float2* pack = P(b.pack);
-    const unsigned gz = x.n_pool < 8192 ? x.n_pool : 8192;
-    if (g.ny >= 32 && g.nz >= 32)
-      hipLaunchKernelGGL(k_pack_odd<32>, dim3(g.nz / 32, g.ny / 32, gz), dim3(256), 0, st, x.pool_delta, x.pool_beta,
-                         pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c);
-    else
-      hipLaunchKernelGGL(k_pack_odd<16>, dim3(g.nz / 16, g.ny / 16, gz), dim3(256), 0, st, x.pool_delta, x.pool_beta,
-                         pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c);
+    hipLaunchKernelGGL(k_pack_tiled, tile_grid(g.ny, g.nz, x.n_pool), dim3(256), 0, st, x.pool_delta, x.pool_beta,
+                       pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c);
     MSL_TRY(hip_check(hipGetLastError(), "pack kernel"));
     c.dbT = pack;
     recs[r].c = c;
-    recs[r].field = f;
+    recs[r].field = P(b.tmp);  // tiled working field
     PhaseSpec& ph = phs[r];
     ph = PhaseSpec{};
     ph.kind = msl::PH_FWD_FULL;
@@ -1285,9 +1258,9 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
     ph.m = c.m;
     ph.s0 = 0;
     ph.s1 = g.n_slices;
-    ph.field = f;
-    ph.fieldT = P(b.tmp);
-    ph.inplace = 1;
+    ph.field = P(b.tmp);
+    ph.in_rm = in;
+    ph.out_rm = f;
   }
   for (int r0 = 0; r0 < n; r0 += kRecChunk) {
     RecChunk ch{};
@@ -1347,8 +1320,8 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
     ff.kind = msl::PH_FF;
     ff.m = recs[r].c.m;
     ff.ns = phs[r].ns;
-    ff.ff_src = recs[r].field;
-    ff.fieldT = phs[r].fieldT;
+    ff.in_rm = phs[r].out_rm;   // the exit wave (row-major); the working field is free again
+    ff.field = phs[r].field;
     for (int p = 0; p < msl::phase_npasses(ff); ++p)
       MSL_TRY(hip_check(launch_pass(recs[r].c, msl::phase_pass(ff, p), st), "far-field kernel"));
   }

@@ -35,13 +35,12 @@ struct PassDesc {
   float2* dst;          // field written (may equal src; nullptr = not written)
   float2* psi_store;    // store the line before the mid step (nullptr = no)
   const float2* psi_load;  // entrance field psi_s for the adjoint step
-  // layouts of the four field arrays: LAY_R row-major [ny][nz], LAY_C
-  // column-major [nz][ny]; a pass reads its lines from the layout of its own
-  // axis (contiguous) and writes them in the layout of the next pass's axis
+  // layouts of the four field arrays: LAY_R row-major [ny][nz] (caller
+  // arrays), LAY_T 2x2-tiled (working fields; see tile_addr)
   int src_lay, dst_lay, store_lay, load_lay;
 };
 
-enum Layout : int { LAY_R = 0, LAY_C = 1 };
+enum Layout : int { LAY_R = 0, LAY_T = 1 };
 
 // Everything a pass reads besides the descriptor.
 struct Ctx {
@@ -61,15 +60,16 @@ struct Ctx {
   float* intensity;                 // far-field output (fftshifted) or nullptr
   const float* grad_intensity;      // far-field seed input (fftshifted) or nullptr
   // Odd slices are always transmitted in column passes (paraxial schedule).
-  // For them the workspace may hold T - 1 precomputed and transposed,
-  // [Ns/2][nz][ny] float2, and a staging area for their (dL/d delta,
-  // dL/d beta) in the same layout, so column passes access both coalesced.
+  // For them the workspace may hold T - 1 precomputed, [Ns/2] tiled fields
+  // (float2), and a staging area for their (dL/d delta, dL/d beta) in the
+  // same layout, so column passes access both in whole 32-byte tiles instead
+  // of striding through the caller's row-major stacks.
   const float2* dbT;                // or nullptr
   float2* gT;                       // or nullptr
   // Compact stacks (batched forward): delta, beta and dbT hold a pool of
   // n_pool distinct slices and slice s is pool slice slice_index[s] (device
   // array, values clamped to the pool); dbT then holds T - 1 of every pool
-  // slice.  nullptr: slice s is stack slice s.
+  // slice and every pass reads it.  nullptr: slice s is stack slice s.
   const int32_t* slice_index;
   int32_t n_pool;
 };
@@ -332,6 +332,7 @@ __device__ __forceinline__ float phase_arg(float d, const Ctx& c) {
 enum PassKind : int { KIND_GENERIC = 0, KIND_FWD_MID = 1, KIND_REV_MID = 2 };
 
 __host__ __device__ inline int pass_kind(const PassDesc& pd) {
+  if (pd.src_lay != LAY_T || pd.dst_lay != LAY_T || !pd.dst) return KIND_GENERIC;
   if (pd.pre == PRE_PROP && pd.post == POST_PROP && pd.mid == MID_T_FWD && !pd.conj) return KIND_FWD_MID;
   if (pd.pre == PRE_PROP && pd.post == POST_PROP && pd.mid == MID_T_ADJ && pd.conj) return KIND_REV_MID;
   return KIND_GENERIC;
@@ -347,23 +348,31 @@ __device__ __forceinline__ uint32_t line_addr(const Ctx& c, int line, int i) {
   return AXIS == ROW ? (uint32_t)line * (uint32_t)c.nz + (uint32_t)i : (uint32_t)i * (uint32_t)c.nz + (uint32_t)line;
 }
 
-// Line `line` of a pass along AXIS in layout `lay` (LAY_R row-major, LAY_C
-// column-major): element i is at base + i * stride.
-struct LineAddr {
-  uint32_t base, stride;
-};
-
-template <int AXIS>
-__device__ __forceinline__ LineAddr line_in(const Ctx& c, int lay, int line) {
-  const uint32_t l = (uint32_t)line;
-  if (AXIS == ROW) return lay == LAY_C ? LineAddr{l, (uint32_t)c.ny} : LineAddr{l * (uint32_t)c.nz, 1u};
-  return lay == LAY_C ? LineAddr{l * (uint32_t)c.ny, 1u} : LineAddr{l, (uint32_t)c.nz};
+// Offset of element (r, col) in the 2x2-tiled layout: the tile of rows 2a,
+// 2a+1 and columns 2b, 2b+1 is 4 consecutive elements (row-major inside the
+// tile), tiles row-major over the grid.  A row pass over rows 2a and 2a+1 and
+// a column pass over columns 2b and 2b+1 both read whole tiles.
+__device__ __forceinline__ uint32_t tile_addr(const Ctx& c, uint32_t r, uint32_t col) {
+  return ((((r >> 1) * ((uint32_t)c.nz >> 1)) + (col >> 1)) << 2) + ((r & 1u) << 1) + (col & 1u);
 }
 
+// Element i of line `line` of a pass along AXIS in layout `lay`.
 template <int N, int AXIS>
 __device__ __forceinline__ uint32_t lay_addr(const Ctx& c, int lay, int line, int i) {
-  const LineAddr a = line_in<AXIS>(c, lay, line);
-  return a.base + (uint32_t)i * a.stride;
+  const uint32_t r = AXIS == ROW ? (uint32_t)line : (uint32_t)i;
+  const uint32_t col = AXIS == ROW ? (uint32_t)i : (uint32_t)line;
+  return lay == LAY_T ? tile_addr(c, r, col) : r * (uint32_t)c.nz + col;
+}
+
+// Float2 slots of one line's exchange buffer in LDS: a radix-8 pad every
+// eight slots, and an odd length so that neighbouring lines start on
+// different banks.
+template <int N>
+constexpr int line_lds() { return N + N / 8 + 1; }
+
+// Whether slice `slice` reads its precomputed T - 1 (the slice pack).
+__device__ __forceinline__ bool uses_pack(const Ctx& c, int slice) {
+  return c.dbT && (c.slice_index || (slice & 1));
 }
 
 // Everything a line pass reads, gathered in registers.  Loads are issued
@@ -413,13 +422,13 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
     }
   }
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
-    if (AXIS == COL && c.dbT && (pd.slice & 1)) {
-      // precomputed T - 1 (real part in dl, imaginary part in bt)
+    if (uses_pack(c, pd.slice)) {
+      // precomputed T - 1 (real part in dl, imaginary part in bt), tiled
       const int64_t so = c.slice_index ? slice_offset(c, pd.slice) : (int64_t)(pd.slice >> 1) * c.m;
-      const float2* q = c.dbT + so + (uint32_t)line * (uint32_t)c.ny;
+      const float2* q = c.dbT + so;
 #pragma unroll
       for (int t = 0; t < P; ++t) {
-        const float2 tm = q[j + t * L];
+        const float2 tm = q[lay_addr<N, AXIS>(c, LAY_T, line, j + t * L)];
         in.dl[t] = tm.x;
         in.bt[t] = tm.y;
       }
@@ -475,12 +484,13 @@ __device__ __forceinline__ void field_st(float2* p, float2 v) {
   }
 }
 
-template <int N, int AXIS, bool COH = false>
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC>
 __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N>& in) {
   constexpr int L = LinePts<N>::L;
   constexpr int P = LinePts<N>::P;
+  const int lay = KIND != KIND_GENERIC ? (int)LAY_T : pd.src_lay;  // the specialised kinds work on tiled fields
 #pragma unroll
-  for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + lay_addr<N, AXIS>(c, pd.src_lay, line, j + t * L));
+  for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + lay_addr<N, AXIS>(c, lay, line, j + t * L));
 }
 
 template <int N>
@@ -506,6 +516,8 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
     pd.post = POST_PROP;
     pd.mid = KIND == KIND_FWD_MID ? MID_T_FWD : MID_T_ADJ;
     pd.conj = KIND == KIND_REV_MID;
+    pd.src_lay = LAY_T;
+    pd.dst_lay = LAY_T;
   }
 
   switch (pd.pre) {
@@ -527,7 +539,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 
   float2 tm1[P];  // T - 1 of the slice at this line's points
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
-    if (AXIS == COL && c.dbT && (pd.slice & 1)) {
+    if (uses_pack(c, pd.slice)) {
 #pragma unroll
       for (int t = 0; t < P; ++t) tm1[t] = make_float2(in.dl[t], in.bt[t]);
     } else {
@@ -542,7 +554,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
     const int64_t so = (int64_t)pd.slice * c.m;
     float* const gdp = c.gdelta ? c.gdelta + so : nullptr;
     float* const gbp = c.gbeta ? c.gbeta + so : nullptr;
-    float2* const gtp = c.gT ? c.gT + (int64_t)(pd.slice >> 1) * c.m + (uint32_t)line * (uint32_t)c.ny : nullptr;
+    float2* const gtp = c.gT ? c.gT + (int64_t)(pd.slice >> 1) * c.m : nullptr;
     const float kdx = c.kdx_hi;
 #pragma unroll
     for (int t = 0; t < P; ++t) {
@@ -552,8 +564,8 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
       // conj(g) * psi' = (gx px + gy py) + i (gx py - gy px)
       const float cre = __builtin_fmaf(g.x, pt.x, g.y * pt.y);
       const float cim = __builtin_fmaf(g.x, pt.y, -(g.y * pt.x));
-      if (AXIS == COL && c.gT && (pd.slice & 1)) {
-        gtp[j + t * L] = make_float2(-kdx * cim, -kdx * cre);
+      if (c.gT && (pd.slice & 1)) {
+        gtp[lay_addr<N, AXIS>(c, LAY_T, line, j + t * L)] = make_float2(-kdx * cim, -kdx * cre);
       } else {
         if (gdp) gdp[e] = -kdx * cim;
         if (gbp) gbp[e] = -kdx * cre;
@@ -594,7 +606,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC>
 __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
   LineIn<N> in;
-  load_field<N, AXIS, COH>(c, pd, line, j, in);
+  load_field<N, AXIS, COH, KIND>(c, pd, line, j, in);
   load_static<N, AXIS, KIND>(c, pd, line, j, in);
   compute_line<N, AXIS, COH, KIND>(c, pd, line, j, sh, in);
 }

@@ -10,8 +10,9 @@
 // ONE pass over lines of one axis: propagate, transmit, propagate.  That is
 // one field round trip and one global exchange per slice instead of two.
 // Slice s is always transmitted in a pass of axis s mod 2 (rows for even
-// slices, columns for odd ones), in every phase, so the odd slices' inputs
-// and gradients can be kept in a column-friendly layout.
+// slices, columns for odd ones), in every phase, so the odd slices'
+// precomputed transmissions and their gradients can be kept apart from the
+// caller's row-major stacks, in the tiled layout the column passes read well.
 //
 // Exact angular-spectrum propagator.  It does not factorise; each slice takes
 // a row pass (z-IFFT, transmission, z-FFT) and a column pass (y-FFT, H, y-IFFT)
@@ -23,24 +24,24 @@
 namespace msl {
 
 enum PhaseKind : int {
-  PH_FWD_FULL = 0,    // slices [s0, s1) from the field in `field`, ending with psi_{s1}
+  PH_FWD_FULL = 0,    // slices [s0, s1) from psi_{s0}, ending with psi_{s1}
   PH_FWD_RECOMP = 1,  // slices [s0, s1): store psi_s, s0 < s < s1, into seg[s - s0 - 1]
-  PH_REV = 2,         // reverse sweep over slices s1-1 .. s0 on the cotangent in `field`
-  PH_FF = 3,          // far-field intensity of ff_src
-  PH_FFADJ = 4        // far-field adjoint: cotangent of ff_src into `field`
+  PH_REV = 2,         // reverse sweep over slices s1-1 .. s0 on the cotangent
+  PH_FF = 3,          // far-field intensity of the field in in_rm
+  PH_FFADJ = 4        // far-field adjoint: cotangent of the field in in_rm, into out_rm
 };
 
-// Every field lives in two buffers: `field`, row-major, and `fieldT`,
-// column-major.  A pass reads its lines from the buffer of its own axis's
-// layout (rows from `field`, columns from `fieldT`: contiguous either way)
-// and writes them in the layout the next pass reads, so the strided side of
-// each transpose is a write.  A phase's first pass expects its input in its
-// own layout; the last pass of a phase that ends the sweep writes `field`.
-// Segment fields (adjoint) are kept in the layout of their slice's axis, the
-// caller-visible checkpoints row-major.  With `inplace` set a phase instead
-// keeps its field row-major in `field` throughout (column passes read and
-// write it strided); the forward sweep measured faster that way, the adjoint
-// phases with the exchange.
+// A phase works on one field, its working field, held 2x2-tiled (LAY_T: the
+// 2x2 block of rows 2a, 2a+1 and columns 2b, 2b+1 in 32 consecutive bytes), so
+// that row passes and column passes both read and write whole 32-byte
+// segments when each workgroup takes neighbouring lines.  Every pass reads
+// its lines from the working field and writes them back in place (a tile
+// holds elements of two lines, never one element twice).  Caller arrays stay
+// row-major: a phase's first pass may read its input from a row-major array
+// (`in_rm`) and its last pass may write its result to one (`out_rm`).
+// Checkpoints are row-major (caller arrays), segment fields tiled.  With
+// `rowmajor` set the working field is itself row-major (used where no
+// workspace holds a tiled buffer).
 struct PhaseSpec {
   int kind;
   int exact;          // exact (non-separable) propagator
@@ -48,15 +49,15 @@ struct PhaseSpec {
   int ckpt_every;
   int leading;        // PH_REV: first reverse phase (adds the leading half-propagation)
   int64_t m;
-  float2* field;      // row-major buffer of the working field
-  float2* fieldT;     // column-major buffer of the working field
-  float2* ckpt;       // PH_FWD_FULL: checkpoint array or nullptr
-  float2* seg;        // PH_FWD_RECOMP output / PH_REV input
-  const float2* ckpt_c;  // PH_REV: psi_{s0}
-  const float2* ff_src;  // PH_FF, PH_FFADJ: input field (row-major)
-  int inplace;        // 1: every pass reads and writes `field` row-major (column passes strided)
-  int seg_row_major;  // PH_REV: `seg` holds row-major fields (the forward's checkpoints) instead of
-                      // fields in the layout of each slice's pass axis (the recompute's segment)
+  float2* field;          // working field
+  const float2* in_rm;    // row-major input of the first pass, or nullptr (the working field holds it)
+  float2* out_rm;         // row-major output of the last pass, or nullptr (the working field)
+  float2* ckpt;           // PH_FWD_FULL: checkpoint array or nullptr
+  float2* seg;            // PH_FWD_RECOMP output / PH_REV input
+  const float2* ckpt_c;   // PH_REV: psi_{s0} (row-major)
+  int rowmajor;           // the working field is row-major instead of tiled
+  int seg_row_major;      // PH_REV: `seg` holds row-major fields (the forward's checkpoints) instead of
+                          // tiled segment fields (the recompute's)
 };
 
 __host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
@@ -71,11 +72,10 @@ __host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
   }
 }
 
-__host__ __device__ inline int native_lay(int axis) { return axis == ROW ? LAY_R : LAY_C; }
+__host__ __device__ inline int work_lay(const PhaseSpec& ph) { return ph.rowmajor ? LAY_R : LAY_T; }
 
-// A pass along `axis` of phase `ph`: source in the axis's own layout,
-// destination in the other one (the next pass's), or row-major if `final`.
-__host__ __device__ inline PassDesc make_pass(const PhaseSpec& ph, int axis, bool final) {
+// A pass along `axis`, the first and/or the last of its phase.
+__host__ __device__ inline PassDesc make_pass(const PhaseSpec& ph, int axis, bool first, bool last) {
   PassDesc p;
   p.axis = axis;
   p.pre = PRE_NONE;
@@ -83,10 +83,21 @@ __host__ __device__ inline PassDesc make_pass(const PhaseSpec& ph, int axis, boo
   p.post = POST_NONE;
   p.conj = 0;
   p.slice = 0;
-  p.src_lay = ph.inplace ? LAY_R : native_lay(axis);
-  p.src = p.src_lay == LAY_C ? ph.fieldT : ph.field;
-  p.dst_lay = (final || ph.inplace) ? LAY_R : native_lay(1 - axis);
-  p.dst = p.dst_lay == LAY_C ? ph.fieldT : ph.field;
+  const int wl = work_lay(ph);
+  if (first && ph.in_rm) {
+    p.src = ph.in_rm;
+    p.src_lay = LAY_R;
+  } else {
+    p.src = ph.field;
+    p.src_lay = wl;
+  }
+  if (last && ph.out_rm) {
+    p.dst = ph.out_rm;
+    p.dst_lay = LAY_R;
+  } else {
+    p.dst = ph.field;
+    p.dst_lay = wl;
+  }
   p.psi_store = nullptr;
   p.psi_load = nullptr;
   p.store_lay = LAY_R;
@@ -99,9 +110,9 @@ __host__ __device__ inline float2* ckpt_slot(const PhaseSpec& ph, int s) {
   return ph.ckpt + (int64_t)(s / ph.ckpt_every) * ph.m;
 }
 
-// Axis of the first pass of a phase (its input must be in that layout).
+// Axis of the first pass of a phase.
 __host__ __device__ inline int phase_first_axis(const PhaseSpec& ph) {
-  if (ph.exact || ph.inplace) return ROW;  // (input is then always row-major)
+  if (ph.exact) return ROW;
   switch (ph.kind) {
     case PH_FWD_FULL:
     case PH_FWD_RECOMP: return (ph.s0 & 1) ? COL : ROW;
@@ -112,11 +123,14 @@ __host__ __device__ inline int phase_first_axis(const PhaseSpec& ph) {
 
 __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
   const int n = ph.s1 - ph.s0;
+  const int np = phase_npasses(ph);
+  const bool first = p == 0, last = p == np - 1;
+  const int wl = work_lay(ph);
   switch (ph.kind) {
     case PH_FWD_FULL:
       if (!ph.exact) {
         const int axis = ((ph.s0 + p) & 1) ? COL : ROW;
-        PassDesc d = make_pass(ph, axis, p == n);
+        PassDesc d = make_pass(ph, axis, first, last);
         if (p < n) {
           d.pre = p == 0 ? PRE_NONE : PRE_PROP;
           d.mid = MID_T_FWD;
@@ -130,12 +144,12 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
         return d;
       } else {
         if (p & 1) {
-          PassDesc d = make_pass(ph, COL, false);
+          PassDesc d = make_pass(ph, COL, first, last);
           d.post = POST_PROP2D;
           return d;
         }
         const int q = p / 2;
-        PassDesc d = make_pass(ph, ROW, q == n);
+        PassDesc d = make_pass(ph, ROW, first, last);
         d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
         if (q < n) {
           d.mid = MID_T_FWD;
@@ -149,11 +163,11 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
     case PH_FWD_RECOMP:
       if (!ph.exact) {
         const int axis = ((ph.s0 + p) & 1) ? COL : ROW;
-        PassDesc d = make_pass(ph, axis, false);
+        PassDesc d = make_pass(ph, axis, first, false);
         d.pre = p == 0 ? PRE_NONE : PRE_PROP;
         if (p > 0) {
           d.psi_store = ph.seg + (int64_t)(p - 1) * ph.m;
-          d.store_lay = native_lay(axis);
+          d.store_lay = wl;
         }
         if (p < n - 1) {
           d.mid = MID_T_FWD;
@@ -165,16 +179,16 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
         return d;
       } else {
         if (p & 1) {
-          PassDesc d = make_pass(ph, COL, false);
+          PassDesc d = make_pass(ph, COL, first, false);
           d.post = POST_PROP2D;
           return d;
         }
         const int q = p / 2;
-        PassDesc d = make_pass(ph, ROW, false);
+        PassDesc d = make_pass(ph, ROW, first, false);
         d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
         if (q > 0) {
           d.psi_store = ph.seg + (int64_t)(q - 1) * ph.m;
-          d.store_lay = LAY_R;
+          d.store_lay = wl;
         }
         if (q < n - 1) {
           d.mid = MID_T_FWD;
@@ -188,7 +202,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
     case PH_REV: {
       if (ph.leading && p == 0) {
         // precedes the pass of slice ns - 1, so it takes the other axis
-        PassDesc d = make_pass(ph, phase_first_axis(ph), false);
+        PassDesc d = make_pass(ph, phase_first_axis(ph), first, last);
         if (ph.exact) d.post = POST_FFT;
         else { d.pre = PRE_PROP; d.conj = 1; }
         return d;
@@ -197,7 +211,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       if (!ph.exact) {
         const int s = ph.s1 - 1 - q;
         const int axis = (s & 1) ? COL : ROW;
-        PassDesc d = make_pass(ph, axis, s == 0);
+        PassDesc d = make_pass(ph, axis, first, last);
         d.pre = PRE_PROP;
         d.conj = 1;
         d.mid = MID_T_ADJ;
@@ -207,36 +221,40 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
           d.load_lay = LAY_R;
         } else {
           d.psi_load = ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
-          d.load_lay = ph.seg_row_major ? LAY_R : native_lay(axis);
+          d.load_lay = ph.seg_row_major ? LAY_R : wl;
         }
         d.post = s == 0 ? POST_NONE : POST_PROP;
         return d;
       } else {
         const int s = ph.s1 - 1 - q / 2;
         if ((q & 1) == 0) {
-          PassDesc d = make_pass(ph, COL, false);
+          PassDesc d = make_pass(ph, COL, first, last);
           d.post = POST_PROP2D;
           d.conj = 1;
           return d;
         }
-        PassDesc d = make_pass(ph, ROW, s == 0);
+        PassDesc d = make_pass(ph, ROW, first, last);
         d.pre = PRE_IFFT_N;
         d.mid = MID_T_ADJ;
         d.slice = s;
-        d.psi_load = s == ph.s0 ? ph.ckpt_c : ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
-        d.load_lay = LAY_R;
+        if (s == ph.s0) {
+          d.psi_load = ph.ckpt_c;
+          d.load_lay = LAY_R;
+        } else {
+          d.psi_load = ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
+          d.load_lay = ph.seg_row_major ? LAY_R : wl;
+        }
         d.post = s == 0 ? POST_NONE : POST_FFT;
         return d;
       }
     }
     case PH_FF:
       if (p == 0) {
-        PassDesc d = make_pass(ph, ROW, false);
-        d.src = ph.ff_src;
+        PassDesc d = make_pass(ph, ROW, first, false);
         d.pre = PRE_IFFT_U;
         return d;
       } else {
-        PassDesc d = make_pass(ph, COL, false);
+        PassDesc d = make_pass(ph, COL, false, false);
         d.dst = nullptr;
         d.pre = PRE_IFFT_U;
         d.mid = MID_FF_OUT;
@@ -245,18 +263,17 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
     case PH_FFADJ:
     default:
       if (p == 0) {
-        PassDesc d = make_pass(ph, ROW, false);
-        d.src = ph.ff_src;
+        PassDesc d = make_pass(ph, ROW, first, false);
         d.pre = PRE_IFFT_U;
         return d;
       } else if (p == 1) {
-        PassDesc d = make_pass(ph, COL, false);
+        PassDesc d = make_pass(ph, COL, false, false);
         d.pre = PRE_IFFT_U;
         d.mid = MID_FF_SEED;
         d.post = POST_FFT;
         return d;
       } else {
-        PassDesc d = make_pass(ph, ROW, true);
+        PassDesc d = make_pass(ph, ROW, false, last);
         d.pre = PRE_FFT;
         return d;
       }

@@ -58,14 +58,15 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned epoch, int 
   }
 }
 
-// Block size and lines per block of one field.
+// Block size and lines per block of one field (neighbouring lines, which
+// share the tiles of the working field).
 template <int N>
 struct PersistShape {
   static constexpr int L = LinePts<N>::L;
-  static constexpr int T0 = N >= 1024 ? 256 : (N >= 512 ? 128 : 64);
+  static constexpr int T0 = N >= 1024 ? 256 : 128;
   static constexpr int T = T0 < N * L ? T0 : N * L;  // at most N lines per block
   static constexpr int G = T / L;
-  static constexpr int LDS = G * (N + N / 8);
+  static constexpr int LDS = G * line_lds<N>();
 };
 
 // Blocks [0, nbA) run phase A, blocks [nbA, gridDim.x) run phase B (if npB > 0).
@@ -74,14 +75,14 @@ __global__ void __launch_bounds__(256) k_persist(Ctx c, PhaseSpec A, PhaseSpec B
                                                  unsigned* bar, int rounds, unsigned spin_limit) {
   using S = PersistShape<N>;
   __shared__ float2 lds[S::LDS];
-  const int g = threadIdx.x / S::L, j = threadIdx.x % S::L;
+  const int g = threadIdx.x % S::G, j = threadIdx.x / S::G;
   const bool second = (int)blockIdx.x >= nbA;
   const PhaseSpec ph = second ? B : A;
   const int np_mine = second ? npB : npA;
   const int np_all = npA > npB ? npA : npB;
   const int nb = second ? (int)gridDim.x - nbA : nbA;
   const int bid = xcd_group(second ? (int)blockIdx.x - nbA : (int)blockIdx.x, nb);
-  float2* sh = lds + g * (N + N / 8);
+  float2* sh = lds + g * line_lds<N>();
   for (int p = 0; p < np_all; ++p) {
     if (p < np_mine) {
       const PassDesc pd = phase_pass(ph, p);
@@ -173,7 +174,7 @@ hipError_t launch_persistent_n(const Ctx& c, const PhaseSpec& a, int npa, const 
   if (e != hipSuccess) return e;
   const int64_t m = c.m;
   hipLaunchKernelGGL(k_fold_barrier_error, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, bar, pa.field,
-                     pa.fieldT, fields == 2 ? pb.field : nullptr, fields == 2 ? pb.fieldT : nullptr, m);
+                     pa.out_rm, fields == 2 ? pb.field : nullptr, fields == 2 ? pb.out_rm : nullptr, m);
   return hipGetLastError();
 }
 

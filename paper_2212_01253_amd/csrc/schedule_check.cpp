@@ -115,16 +115,18 @@ void run_pass(Engine& E, const msl::PassDesc& pd) {
   // a pass may rewrite its own lines in place, but never read one layout of a
   // buffer while writing the other (other lines would be overwritten)
   if (dst == src && pd.dst_lay != pd.src_lay) ++g_bad_layout;
-  // the source is read in the layout of the pass's own axis (contiguous), or
-  // row-major in place
-  if (pd.src_lay != (row ? msl::LAY_R : msl::LAY_C) && !(pd.src_lay == msl::LAY_R && pd.dst_lay == msl::LAY_R))
+  if ((pd.src_lay != msl::LAY_R && pd.src_lay != msl::LAY_T) || (pd.dst && pd.dst_lay != msl::LAY_R &&
+                                                                 pd.dst_lay != msl::LAY_T))
     ++g_bad_layout;
   const double k = 2 * M_PI / g.lam;
   for (int line = 0; line < nl; ++line) {
     auto addr = [&](int i) -> int64_t { return row ? (int64_t)line * g.nz + i : (int64_t)i * g.nz + line; };
+    // row-major, or the 2x2-tiled layout of the library's working fields (the
+    // same index map as msl::tile_addr, written out here on its own)
     auto laddr = [&](int lay, int i) -> int64_t {
-      const int y = row ? line : i, z = row ? i : line;
-      return lay == msl::LAY_C ? (int64_t)z * g.ny + y : (int64_t)y * g.nz + z;
+      const int64_t y = row ? line : i, z = row ? i : line;
+      if (lay == msl::LAY_T) return ((y / 2) * (g.nz / 2) + z / 2) * 4 + (y % 2) * 2 + z % 2;
+      return y * g.nz + z;
     };
     std::vector<cd> v(n);
     for (int i = 0; i < n; ++i) v[i] = (*src)[laddr(pd.src_lay, i)];
@@ -256,18 +258,28 @@ int check(const Geo& g, int kck) {
   const int64_t SPAN = 1 << 20;
   auto fake = [&](int slot) { return reinterpret_cast<float2*>((uintptr_t)(SPAN * 64 * (slot + 1))); };
   const int nck = (g.ns + kck - 1) / kck;
-  Arr fieldT{{Field(m)}, fake(6), m}, WT{{Field(m)}, fake(7), m}, GT{{Field(m)}, fake(8), m};
-  Arr field{{probe}, fake(0), m}, ckpt{std::vector<Field>(nck, Field(m)), fake(1), m},
+  // row-major caller arrays: probe, exit wave, checkpoints, cotangent in, probe cotangent out;
+  // working fields (tiled unless a phase is row-major): field, W, G, tmp; segments tiled
+  Arr probeA{{probe}, fake(10), m}, out{{Field(m)}, fake(9), m}, gfield{{Field(m)}, fake(11), m},
+      gprobe{{Field(m)}, fake(12), m};
+  Arr field{{Field(m)}, fake(0), m}, ckpt{std::vector<Field>(nck, Field(m)), fake(1), m},
       seg{std::vector<Field>(kck > 1 ? 2 * (kck - 1) : 1, Field(m)), fake(2), m}, W{{Field(m)}, fake(3), m},
       G{{Field(m)}, fake(4), m}, tmp{{Field(m)}, fake(5), m};
-  g_arrays = {&field, &ckpt, &seg, &W, &G, &tmp, &fieldT, &WT, &GT};
+  g_arrays = {&field, &ckpt, &seg, &W, &G, &tmp, &probeA, &out, &gfield, &gprobe};
 
-  // forward with checkpoints
+  // forward with checkpoints: tiled working field between row-major probe and
+  // exit wave, or (odd slice counts) row-major on the exit-wave array itself
   msl::PhaseSpec ph{};
   ph.kind = msl::PH_FWD_FULL; ph.exact = g.exact; ph.s0 = 0; ph.s1 = g.ns; ph.ns = g.ns; ph.m = m;
-  ph.field = fake(0);
-  ph.fieldT = fake(6);
-  ph.inplace = (g.ns % 2) ? 0 : 1;  // both forward layouts
+  if (g.ns % 2) {
+    out.f[0] = probe;
+    ph.field = fake(9);
+    ph.rowmajor = 1;
+  } else {
+    ph.field = fake(0);
+    ph.in_rm = fake(10);
+    ph.out_rm = fake(9);
+  }
   ph.ckpt = fake(1); ph.ckpt_every = kck;
   run_phase(E, ph);
 
@@ -280,16 +292,16 @@ int check(const Geo& g, int kck) {
     psi = prop2(psi, g, false);
   }
   int bad = 0;
-  const double ef = rel(field.f[0], psi);
+  const double ef = rel(out.f[0], psi);
   if (ef > 1e-10) { std::printf("forward mismatch %g\n", ef); ++bad; }
   for (int c = 0; c < nck; ++c) {
     const double e = rel(ckpt.f[c], kept[c * kck]);
     if (e > 1e-10) { std::printf("checkpoint %d mismatch %g\n", c, e); ++bad; }
   }
 
-  // far field
+  // far field of the exit wave
   msl::PhaseSpec ff{};
-  ff.kind = msl::PH_FF; ff.m = m; ff.ff_src = fake(0); ff.fieldT = fake(5);
+  ff.kind = msl::PH_FF; ff.m = m; ff.in_rm = fake(9); ff.field = fake(5);
   run_phase(E, ff);
   Field A = dft2(psi, g, +1);
   std::vector<double> Iref(m);
@@ -298,9 +310,9 @@ int check(const Geo& g, int kck) {
       Iref[(int64_t)((r + g.ny / 2) % g.ny) * g.nz + (c + g.nz / 2) % g.nz] = std::norm(A[(int64_t)r * g.nz + c]) / m;
   if (relv(E.inten, Iref) > 1e-10) { std::printf("far field mismatch\n"); ++bad; }
 
-  // far-field adjoint into G
+  // far-field adjoint into the row-major cotangent array
   msl::PhaseSpec fa{};
-  fa.kind = msl::PH_FFADJ; fa.m = m; fa.ff_src = fake(0); fa.field = fake(4); fa.fieldT = fake(5);
+  fa.kind = msl::PH_FFADJ; fa.m = m; fa.in_rm = fake(9); fa.field = fake(5); fa.out_rm = fake(11);
   run_phase(E, fa);
   Field seed(m);
   for (int r = 0; r < g.ny; ++r)
@@ -309,48 +321,37 @@ int check(const Geo& g, int kck) {
       seed[(int64_t)r * g.nz + c] = 2.0 * gi * A[(int64_t)r * g.nz + c] / double(m);
     }
   Field gref = dft2(seed, g, -1);
-  if (rel(G.f[0], gref) > 1e-10) { std::printf("far-field adjoint mismatch %g\n", rel(G.f[0], gref)); ++bad; }
+  if (rel(gfield.f[0], gref) > 1e-10) { std::printf("far-field adjoint mismatch %g\n", rel(gfield.f[0], gref)); ++bad; }
 
   // adjoint with recompute: the same order as the library (segment c-1 is
   // recomputed beside the reverse sweep over segment c, into the other of two
-  // segment buffers)
-  // the library's load_phase_input: row-major copy, or column-major when the
-  // phase's first pass is a column pass
-  auto load_input = [&](const msl::PhaseSpec& ph, const Field& src, Field& R, Field& C) {
-    if (msl::phase_first_axis(ph) == msl::ROW) { R = src; return; }
-    for (int y = 0; y < g.ny; ++y)
-      for (int z = 0; z < g.nz; ++z) C[(int64_t)z * g.ny + y] = src[(int64_t)y * g.nz + z];
-  };
+  // segment buffers); the first reverse phase reads the cotangent array, the
+  // last writes the probe's cotangent
   auto recomp = [&](int c) {
     const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
     if (s1 - s0 < 2) return;
     msl::PhaseSpec rc{};
     rc.kind = msl::PH_FWD_RECOMP; rc.exact = g.exact; rc.s0 = s0; rc.s1 = s1; rc.ns = g.ns; rc.m = m;
-    rc.field = fake(3); rc.fieldT = fake(7);
+    rc.field = fake(3); rc.in_rm = fake(1) + (int64_t)c * m;
     rc.seg = fake(2) + (c & 1) * (int64_t)(kck > 1 ? kck - 1 : 0) * m;
-    load_input(rc, ckpt.f[c], W.f[0], WT.f[0]);
     run_phase(E, rc);
   };
   if (kck == 1) {
     // the library's direct sweep: every entrance field is a checkpoint, read row-major
     msl::PhaseSpec rv{};
     rv.kind = msl::PH_REV; rv.exact = g.exact; rv.s0 = 0; rv.s1 = g.ns; rv.ns = g.ns; rv.m = m;
-    rv.leading = 1; rv.field = fake(4); rv.fieldT = fake(8);
+    rv.leading = 1; rv.field = fake(4); rv.in_rm = fake(11); rv.out_rm = fake(12);
     rv.seg = fake(1) + m; rv.ckpt_c = fake(1); rv.seg_row_major = 1;
-    load_input(rv, G.f[0], G.f[0], GT.f[0]);
     run_phase(E, rv);
-  } else {
-    msl::PhaseSpec first{};
-    first.kind = msl::PH_REV; first.exact = g.exact; first.ns = g.ns; first.leading = 1;
-    first.s0 = (nck - 1) * kck; first.s1 = g.ns;
-    load_input(first, G.f[0], G.f[0], GT.f[0]);
   }
   if (kck > 1) recomp(nck - 1);
   for (int c = nck - 1; c >= 0 && kck > 1; --c) {
     const int s0 = c * kck, s1 = std::min(s0 + kck, g.ns);
     msl::PhaseSpec rv{};
     rv.kind = msl::PH_REV; rv.exact = g.exact; rv.s0 = s0; rv.s1 = s1; rv.ns = g.ns; rv.m = m;
-    rv.leading = c == nck - 1; rv.field = fake(4); rv.fieldT = fake(8);
+    rv.leading = c == nck - 1; rv.field = fake(4);
+    rv.in_rm = c == nck - 1 ? fake(11) : nullptr;
+    rv.out_rm = c == 0 ? fake(12) : nullptr;
     rv.seg = fake(2) + (c & 1) * (int64_t)(kck > 1 ? kck - 1 : 0) * m;
     rv.ckpt_c = fake(1) + (int64_t)c * m;
     run_phase(E, rv);
@@ -373,7 +374,7 @@ int check(const Geo& g, int kck) {
   }
   if (relv(E.gdelta, gd) > 1e-9) { std::printf("grad delta mismatch %g\n", relv(E.gdelta, gd)); ++bad; }
   if (relv(E.gbeta, gb) > 1e-9) { std::printf("grad beta mismatch %g\n", relv(E.gbeta, gb)); ++bad; }
-  if (rel(G.f[0], gg) > 1e-10) { std::printf("grad probe mismatch %g\n", rel(G.f[0], gg)); ++bad; }
+  if (rel(gprobe.f[0], gg) > 1e-10) { std::printf("grad probe mismatch %g\n", rel(gprobe.f[0], gg)); ++bad; }
   if (g_bad_layout) { std::printf("layout hazard in %d passes\n", g_bad_layout); ++bad; g_bad_layout = 0; }
   std::printf("%s ny=%d nz=%d ns=%d k=%d: field %.1e -> %s\n", g.exact ? "exact" : "paraxial", g.ny, g.nz, g.ns,
               kck, ef, bad ? "FAIL" : "ok");

@@ -254,7 +254,7 @@ def test_tuning_validates_and_round_trips(L):
         assert t["lines_per_group"][512] == 2 and t["lines_per_group"][256] == 4
         assert t["lines_per_group"][128] == 1 and t["lines_per_group"][16] == 64
         assert t["lines_per_group"][1024] == 0 and t["batch_streams"] == 2
-        bad = [({512: 3}, 0), ({512: 4}, 0), ({1024: 2}, 0), ({256: -1}, 0), ({8: 1}, 0), ({}, 5), ({}, -1)]
+        bad = [({512: 3}, 0), ({512: 8}, 0), ({1024: 4}, 0), ({256: -1}, 0), ({8: 1}, 0), ({}, 5), ({}, -1)]
         for lpg, bs in bad:
             with pytest.raises(msl.MslError):
                 msl.set_tuning(lpg, batch_streams=bs)
