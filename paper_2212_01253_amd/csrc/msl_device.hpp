@@ -342,12 +342,6 @@ __host__ __device__ inline int pass_kind(const PassDesc& pd) {
 // Element offsets within one [ny][nz] field fit in 32 bits (at most 2^20
 // elements); slice offsets are added to the (uniform) base pointer instead.
 
-// Element i of line `line` of a pass along AXIS: row-major (y, z) offset.
-template <int N, int AXIS>
-__device__ __forceinline__ uint32_t line_addr(const Ctx& c, int line, int i) {
-  return AXIS == ROW ? (uint32_t)line * (uint32_t)c.nz + (uint32_t)i : (uint32_t)i * (uint32_t)c.nz + (uint32_t)line;
-}
-
 // Offset of element (r, col) in the 2x2-tiled layout: the tile of rows 2a,
 // 2a+1 and columns 2b, 2b+1 is 4 consecutive elements (row-major inside the
 // tile), tiles row-major over the grid.  A row pass over rows 2a and 2a+1 and
@@ -356,12 +350,22 @@ __device__ __forceinline__ uint32_t tile_addr(const Ctx& c, uint32_t r, uint32_t
   return ((((r >> 1) * ((uint32_t)c.nz >> 1)) + (col >> 1)) << 2) + ((r & 1u) << 1) + (col & 1u);
 }
 
-// Element i of line `line` of a pass along AXIS in layout `lay`.
+// The elements j + t L (t = 0 .. P-1) of line `line` of a pass along AXIS in
+// layout `lay` are at base + t * stride: in both layouts a step of L (even)
+// along the line moves by a fixed offset (row-major: L along a row, L nz
+// along a column; tiled: 2 L along a row, L nz along a column).
+struct LineAddr {
+  uint32_t base, stride;
+};
+
 template <int N, int AXIS>
-__device__ __forceinline__ uint32_t lay_addr(const Ctx& c, int lay, int line, int i) {
-  const uint32_t r = AXIS == ROW ? (uint32_t)line : (uint32_t)i;
-  const uint32_t col = AXIS == ROW ? (uint32_t)i : (uint32_t)line;
-  return lay == LAY_T ? tile_addr(c, r, col) : r * (uint32_t)c.nz + col;
+__device__ __forceinline__ LineAddr line_at(const Ctx& c, int lay, int line, int j) {
+  constexpr uint32_t L = (uint32_t)LinePts<N>::L;
+  const uint32_t r = AXIS == ROW ? (uint32_t)line : (uint32_t)j;
+  const uint32_t col = AXIS == ROW ? (uint32_t)j : (uint32_t)line;
+  const uint32_t base = lay == LAY_T ? tile_addr(c, r, col) : r * (uint32_t)c.nz + col;
+  const uint32_t stride = AXIS == ROW ? (lay == LAY_T ? 2 * L : L) : L * (uint32_t)c.nz;
+  return LineAddr{base, stride};
 }
 
 // Float2 slots of one line's exchange buffer in LDS: a radix-8 pad every
@@ -426,9 +430,10 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
       // precomputed T - 1 (real part in dl, imaginary part in bt), tiled
       const int64_t so = c.slice_index ? slice_offset(c, pd.slice) : (int64_t)(pd.slice >> 1) * c.m;
       const float2* q = c.dbT + so;
+      const LineAddr a = line_at<N, AXIS>(c, LAY_T, line, j);
 #pragma unroll
       for (int t = 0; t < P; ++t) {
-        const float2 tm = q[lay_addr<N, AXIS>(c, LAY_T, line, j + t * L)];
+        const float2 tm = q[a.base + (uint32_t)t * a.stride];
         in.dl[t] = tm.x;
         in.bt[t] = tm.y;
       }
@@ -436,17 +441,18 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
       const int64_t so = slice_offset(c, pd.slice);
       const float* dp = c.delta + so;
       const float* bp = c.beta + so;
+      const LineAddr a = line_at<N, AXIS>(c, LAY_R, line, j);
 #pragma unroll
       for (int t = 0; t < P; ++t) {
-        const uint32_t a = line_addr<N, AXIS>(c, line, j + t * L);
-        in.dl[t] = dp[a];
-        in.bt[t] = bp[a];
+        in.dl[t] = dp[a.base + (uint32_t)t * a.stride];
+        in.bt[t] = bp[a.base + (uint32_t)t * a.stride];
       }
     }
   }
   if (pd.mid == MID_T_ADJ) {
+    const LineAddr a = line_at<N, AXIS>(c, pd.load_lay, line, j);
 #pragma unroll
-    for (int t = 0; t < P; ++t) in.ps[t] = pd.psi_load[lay_addr<N, AXIS>(c, pd.load_lay, line, j + t * L)];
+    for (int t = 0; t < P; ++t) in.ps[t] = pd.psi_load[a.base + (uint32_t)t * a.stride];
   }
   if (pd.mid == MID_FF_SEED) {
 #pragma unroll
@@ -489,8 +495,9 @@ __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int
   constexpr int L = LinePts<N>::L;
   constexpr int P = LinePts<N>::P;
   const int lay = KIND != KIND_GENERIC ? (int)LAY_T : pd.src_lay;  // the specialised kinds work on tiled fields
+  const LineAddr a = line_at<N, AXIS>(c, lay, line, j);
 #pragma unroll
-  for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + lay_addr<N, AXIS>(c, lay, line, j + t * L));
+  for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + a.base + (uint32_t)t * a.stride);
 }
 
 template <int N>
@@ -533,8 +540,9 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   if (pd.psi_store) {
+    const LineAddr a = line_at<N, AXIS>(c, pd.store_lay, line, j);
 #pragma unroll
-    for (int t = 0; t < P; ++t) pd.psi_store[lay_addr<N, AXIS>(c, pd.store_lay, line, j + t * L)] = v[t];
+    for (int t = 0; t < P; ++t) pd.psi_store[a.base + (uint32_t)t * a.stride] = v[t];
   }
 
   float2 tm1[P];  // T - 1 of the slice at this line's points
@@ -556,16 +564,18 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
     float* const gbp = c.gbeta ? c.gbeta + so : nullptr;
     float2* const gtp = c.gT ? c.gT + (int64_t)(pd.slice >> 1) * c.m : nullptr;
     const float kdx = c.kdx_hi;
+    const LineAddr ar = line_at<N, AXIS>(c, LAY_R, line, j);
+    const LineAddr at = line_at<N, AXIS>(c, LAY_T, line, j);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const uint32_t e = line_addr<N, AXIS>(c, line, j + t * L);
+      const uint32_t e = ar.base + (uint32_t)t * ar.stride;
       const float2 pt = apply_t(in.ps[t], tm1[t]);  // psi'_s = T_s psi_s
       const float2 g = v[t];                     // cotangent of psi'_s
       // conj(g) * psi' = (gx px + gy py) + i (gx py - gy px)
       const float cre = __builtin_fmaf(g.x, pt.x, g.y * pt.y);
       const float cim = __builtin_fmaf(g.x, pt.y, -(g.y * pt.x));
       if (c.gT && (pd.slice & 1)) {
-        gtp[lay_addr<N, AXIS>(c, LAY_T, line, j + t * L)] = make_float2(-kdx * cim, -kdx * cre);
+        gtp[at.base + (uint32_t)t * at.stride] = make_float2(-kdx * cim, -kdx * cre);
       } else {
         if (gdp) gdp[e] = -kdx * cim;
         if (gbp) gbp[e] = -kdx * cre;
@@ -597,9 +607,9 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   if (pd.dst) {
+    const LineAddr a = line_at<N, AXIS>(c, pd.dst_lay, line, j);
 #pragma unroll
-    for (int t = 0; t < P; ++t)
-      field_st<COH>(pd.dst + lay_addr<N, AXIS>(c, pd.dst_lay, line, j + t * L), v[t]);
+    for (int t = 0; t < P; ++t) field_st<COH>(pd.dst + a.base + (uint32_t)t * a.stride, v[t]);
   }
 }
 
