@@ -162,10 +162,12 @@ __global__ void k_probe(int ny, int nz, double q, float2* out) {
 
 // Slices' transmission minus one, T - 1 = exp(i k dx (delta + i beta)) - 1,
 // into the 2x2-tiled layout: slice first + stride * s2 -> out[s2], s2 in
-// [s2b, s2e); one thread per 2x2 tile (two 8-byte reads of each stack, one
-// 32-byte write).  The odd slices of a stack (first 1, stride 2) or every
-// slice of a pool (first 0, stride 1).  The line passes evaluate T - 1 of the
-// other slices with the same function.
+// [s2b, s2e); one thread per 2x2 tile (two 8-byte reads of each stack when
+// VEC, i.e. both stacks 8-byte aligned, else four 4-byte reads; two 16-byte
+// writes).  The odd slices of a stack (first 1, stride 2) or every slice of a
+// pool (first 0, stride 1).  The line passes evaluate T - 1 of the other
+// slices with the same function.
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_pack_tiled(const float* d, const float* b, float2* out, int ny, int nz,
                                                     int s2b, int s2e, int first, int stride, msl::Ctx c) {
   const int64_t m = (int64_t)ny * nz;
@@ -173,42 +175,72 @@ __global__ void __launch_bounds__(256) k_pack_tiled(const float* d, const float*
   for (int s2 = s2b + blockIdx.y; s2 < s2e; s2 += gridDim.y) {
     const float* ds = d + (int64_t)(first + stride * s2) * m;
     const float* bs = b + (int64_t)(first + stride * s2) * m;
-    float2* o = out + (int64_t)s2 * m;
+    float4* o = reinterpret_cast<float4*>(out + (int64_t)s2 * m);
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += gridDim.x * blockDim.x) {
       const int64_t e = (int64_t)(2 * (t / tz)) * nz + 2 * (t % tz);
-      o[4 * (int64_t)t + 0] = msl::transmission_m1(msl::phase_arg(ds[e], c), msl::phase_arg(bs[e], c));
-      o[4 * (int64_t)t + 1] = msl::transmission_m1(msl::phase_arg(ds[e + 1], c), msl::phase_arg(bs[e + 1], c));
-      o[4 * (int64_t)t + 2] = msl::transmission_m1(msl::phase_arg(ds[e + nz], c), msl::phase_arg(bs[e + nz], c));
-      o[4 * (int64_t)t + 3] =
-          msl::transmission_m1(msl::phase_arg(ds[e + nz + 1], c), msl::phase_arg(bs[e + nz + 1], c));
+      float2 d0, d1, b0, b1;  // (row 2a, row 2a + 1) x (column 2b, 2b + 1)
+      if constexpr (VEC) {
+        d0 = *reinterpret_cast<const float2*>(ds + e);
+        d1 = *reinterpret_cast<const float2*>(ds + e + nz);
+        b0 = *reinterpret_cast<const float2*>(bs + e);
+        b1 = *reinterpret_cast<const float2*>(bs + e + nz);
+      } else {
+        d0 = make_float2(ds[e], ds[e + 1]);
+        d1 = make_float2(ds[e + nz], ds[e + nz + 1]);
+        b0 = make_float2(bs[e], bs[e + 1]);
+        b1 = make_float2(bs[e + nz], bs[e + nz + 1]);
+      }
+      const float2 t0 = msl::transmission_m1(msl::phase_arg(d0.x, c), msl::phase_arg(b0.x, c));
+      const float2 t1 = msl::transmission_m1(msl::phase_arg(d0.y, c), msl::phase_arg(b0.y, c));
+      const float2 t2 = msl::transmission_m1(msl::phase_arg(d1.x, c), msl::phase_arg(b1.x, c));
+      const float2 t3 = msl::transmission_m1(msl::phase_arg(d1.y, c), msl::phase_arg(b1.y, c));
+      o[2 * (int64_t)t] = make_float4(t0.x, t0.y, t1.x, t1.y);
+      o[2 * (int64_t)t + 1] = make_float4(t2.x, t2.y, t3.x, t3.y);
     }
   }
 }
 
+// Packs slices first + stride * s2, s2 in [s2b, s2e), of (d, b) into out (tiled).
+hipError_t launch_pack(const float* d, const float* b, float2* out, int ny, int nz, int s2b, int s2e, int first,
+                       int stride, const msl::Ctx& c, hipStream_t st);
+
 // gT[s2] (tiled float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z]
-// row-major for odd slices s = 2 s2 + 1, s2 in [s2b, s2e); one thread per tile.
+// row-major for odd slices s = 2 s2 + 1, s2 in [s2b, s2e); one thread per tile
+// (two 16-byte reads; 8-byte writes when VEC, i.e. both outputs 8-byte
+// aligned, else 4-byte writes).
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_unpack_tiled(const float2* gT, float* gd, float* gb, int ny, int nz,
                                                       int s2b, int s2e) {
   const int64_t m = (int64_t)ny * nz;
   const int tiles = (int)(m >> 2), tz = nz >> 1;
   for (int s2 = s2b + blockIdx.y; s2 < s2e; s2 += gridDim.y) {
-    const float2* q = gT + (int64_t)s2 * m;
+    const float4* q = reinterpret_cast<const float4*>(gT + (int64_t)s2 * m);
     const int64_t so = (int64_t)(2 * s2 + 1) * m;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += gridDim.x * blockDim.x) {
       const int64_t e = so + (int64_t)(2 * (t / tz)) * nz + 2 * (t % tz);
-      const float2 v0 = q[4 * (int64_t)t], v1 = q[4 * (int64_t)t + 1], v2 = q[4 * (int64_t)t + 2],
-                   v3 = q[4 * (int64_t)t + 3];
-      if (gd) {
-        gd[e] = v0.x;
-        gd[e + 1] = v1.x;
-        gd[e + nz] = v2.x;
-        gd[e + nz + 1] = v3.x;
-      }
-      if (gb) {
-        gb[e] = v0.y;
-        gb[e + 1] = v1.y;
-        gb[e + nz] = v2.y;
-        gb[e + nz + 1] = v3.y;
+      const float4 u = q[2 * (int64_t)t], w = q[2 * (int64_t)t + 1];  // (d, b) at (0,0), (0,1) | (1,0), (1,1)
+      if constexpr (VEC) {
+        if (gd) {
+          *reinterpret_cast<float2*>(gd + e) = make_float2(u.x, u.z);
+          *reinterpret_cast<float2*>(gd + e + nz) = make_float2(w.x, w.z);
+        }
+        if (gb) {
+          *reinterpret_cast<float2*>(gb + e) = make_float2(u.y, u.w);
+          *reinterpret_cast<float2*>(gb + e + nz) = make_float2(w.y, w.w);
+        }
+      } else {
+        if (gd) {
+          gd[e] = u.x;
+          gd[e + 1] = u.z;
+          gd[e + nz] = w.x;
+          gd[e + nz + 1] = w.z;
+        }
+        if (gb) {
+          gb[e] = u.y;
+          gb[e + 1] = u.w;
+          gb[e + nz] = w.y;
+          gb[e + nz + 1] = w.w;
+        }
       }
     }
   }
@@ -219,6 +251,16 @@ dim3 tile_grid(int ny, int nz, int n) {
   const int64_t tiles = (int64_t)ny * nz / 4;
   const unsigned gx = (unsigned)std::min<int64_t>((tiles + 255) / 256, 4096);
   return dim3(gx, (unsigned)std::min(n, 8192));
+}
+
+hipError_t launch_pack(const float* d, const float* b, float2* out, int ny, int nz, int s2b, int s2e, int first,
+                       int stride, const msl::Ctx& c, hipStream_t st) {
+  const dim3 grid = tile_grid(ny, nz, s2e - s2b);
+  if (aligned(d, 8) && aligned(b, 8))
+    hipLaunchKernelGGL(k_pack_tiled<true>, grid, dim3(256), 0, st, d, b, out, ny, nz, s2b, s2e, first, stride, c);
+  else
+    hipLaunchKernelGGL(k_pack_tiled<false>, grid, dim3(256), 0, st, d, b, out, ny, nz, s2b, s2e, first, stride, c);
+  return hipGetLastError();
 }
 
 // Amplitude loss partial sums (FP64) and dL/dI.
@@ -490,9 +532,7 @@ int odd_end(int s1) { return s1 >> 1; }
 msl_status pack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
   if (s2e <= s2b) return MSL_OK;
   float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
-  hipLaunchKernelGGL(k_pack_tiled, tile_grid(k.g.ny, k.g.nz, s2e - s2b), dim3(256), 0, st, k.c.delta, k.c.beta, dbT,
-                     k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c);
-  return hip_check(hipGetLastError(), "pack kernel");
+  return hip_check(launch_pack(k.c.delta, k.c.beta, dbT, k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c, st), "pack kernel");
 }
 
 msl_status pack_odd(Call& k) {
@@ -506,8 +546,13 @@ msl_status pack_odd(Call& k) {
 // Unpacks the gradients of odd slices 2 s2 + 1, s2 in [s2b, s2e), on stream st.
 msl_status unpack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
   if (s2e <= s2b || !k.c.gT) return MSL_OK;
-  hipLaunchKernelGGL(k_unpack_tiled, tile_grid(k.g.ny, k.g.nz, s2e - s2b), dim3(256), 0, st, k.c.gT, k.c.gdelta,
-                     k.c.gbeta, k.g.ny, k.g.nz, s2b, s2e);
+  const dim3 grid = tile_grid(k.g.ny, k.g.nz, s2e - s2b);
+  if (aligned(k.c.gdelta, 8) && aligned(k.c.gbeta, 8))   // (a NULL output counts as aligned)
+    hipLaunchKernelGGL(k_unpack_tiled<true>, grid, dim3(256), 0, st, k.c.gT, k.c.gdelta, k.c.gbeta, k.g.ny, k.g.nz,
+                       s2b, s2e);
+  else
+    hipLaunchKernelGGL(k_unpack_tiled<false>, grid, dim3(256), 0, st, k.c.gT, k.c.gdelta, k.c.gbeta, k.g.ny, k.g.nz,
+                       s2b, s2e);
   return hip_check(hipGetLastError(), "unpack kernel");
 }
 
@@ -1245,9 +1290,8 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
       in = f;
     }
     float2* pack = P(b.pack);
-    hipLaunchKernelGGL(k_pack_tiled, tile_grid(g.ny, g.nz, x.n_pool), dim3(256), 0, st, x.pool_delta, x.pool_beta,
-                       pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c);
-    MSL_TRY(hip_check(hipGetLastError(), "pack kernel"));
+    MSL_TRY(hip_check(launch_pack(x.pool_delta, x.pool_beta, pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c, st),
+                      "pack kernel"));
     c.dbT = pack;
     recs[r].c = c;
     recs[r].field = P(b.tmp);  // tiled working field
