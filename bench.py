@@ -23,6 +23,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
+# VALU issue ceiling without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-instructions per second (a wave64 instruction is 64 lane-instructions, 4 cycles)
+VALU_PEAK_TLANES = 256 * 4 * 16 * 2.4e9 / 1e12
 FWD_BYTES = 24.0          # per voxel-slice: delta + beta (8 B) + field read and write (16 B)
 
 
@@ -45,9 +48,10 @@ TRAFFIC_PROFILE = "profiles/k_pass_512_bars_512x512x2048.md"
 
 
 def profile_figures():
-    """(HBM bytes, kernel microseconds) per forward middle-pass launch from the
-    committed rocprofv3 summary, or (None, None) when the kernel sources
-    changed since it was taken."""
+    """Figures of the forward middle pass from the committed rocprofv3 summary, or {} when the
+    kernel sources changed since it was taken: HBM bytes per launch (FETCH_SIZE + WRITE_SIZE,
+    calibrated), kernel microseconds per launch, executed VALU instructions per wavefront
+    (SQ_INSTS_VALU / SQ_WAVES) of the row and the column pass, wavefronts per launch."""
     import hashlib
     import re
     try:
@@ -56,31 +60,57 @@ def profile_figures():
         for p in KERNEL_SOURCES:
             h.update(open(os.path.join(ROOT, p), "rb").read())
     except OSError:
-        return None, None
-    b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
-    us = re.search(r"kernel_us_per_launch: ([0-9.]+)", text)
+        return {}
     sha = re.search(r"sources_sha256: ([0-9a-f]+)", text)
-    if not b or not us or not sha or sha.group(1) != h.hexdigest():
-        return None, None
-    return int(b.group(1)), float(us.group(1))
+    if not sha or sha.group(1) != h.hexdigest():
+        return {}
+    out = {}
+    for key, conv in (("traffic_bytes_per_launch", int), ("kernel_us_per_launch", float),
+                      ("valu_per_wave_row", float), ("valu_per_wave_column", float), ("waves_per_launch", int)):
+        m = re.search(key + r": ([0-9.]+)", text)
+        if m:
+            out[key] = conv(m.group(1))
+    return out
 
 
-def cpu_baseline(w, meas, n_sample):
+def cpu_baseline(w, meas):
+    """The FP64 oracle (forward, far field, loss, adjoint with every field kept) timed on this
+    host: the full throughput workload (all slices) is the reported value; beside it the parity
+    workload in full, one gradient of the gradient workload, and single-thread runs."""
     import numpy as np
     from oracle import msl_oracle as O
     from paper_2212_01253_amd import synth
-    g = synth.Geometry(**{**w.geom.as_dict(), "n_slices": n_sample})
-    d = np.ascontiguousarray(w.delta[:n_sample])
-    b = np.ascontiguousarray(w.beta[:n_sample])
-    t0 = time.perf_counter()
-    O.loss_and_gradient(g, d, b, meas)
-    dt = time.perf_counter() - t0
-    vs = g.ny * g.nz * n_sample
-    return {"value": vs / dt, "unit": "voxel-slice-steps/s", "cores": O.WORKERS, "kind": "oracle",
-            "sample": f"FP64 oracle forward+far field+loss+adjoint (all fields kept) on the first "
-                      f"{n_sample} of the {w.geom.n_slices} slices of the same {g.ny}x{g.nz} workload: "
-                      f"{dt:.2f} s",
-            "cpu": _cpu_model()}
+
+    def timed(g, d, b, m):
+        t0 = time.perf_counter()
+        O.loss_and_gradient(g, d, b, m)
+        dt = time.perf_counter() - t0
+        vs = g.ny * g.nz * g.n_slices
+        return {"voxel_slices": vs, "seconds": dt, "value": vs / dt, "threads": O.WORKERS}
+
+    legs = {}
+    g = w.geom
+    legs["throughput_full"] = timed(g, w.delta, w.beta, meas)
+    p1 = synth.parity_small(0)
+    m1 = synth.random_measured_amplitude(p1.geom.ny, p1.geom.nz, 78, 1.0)
+    legs["parity_full"] = timed(p1.geom, p1.delta, p1.beta, m1)
+    r4 = synth.recon_256()
+    m4 = synth.random_measured_amplitude(r4.geom.ny, r4.geom.nz, 79, 1.0)
+    legs["gradient_workload_one_gradient"] = timed(r4.geom, r4.delta, r4.beta, m4)
+    keep = O.WORKERS
+    try:
+        O.WORKERS = 1
+        legs["parity_full_1_thread"] = timed(p1.geom, p1.delta, p1.beta, m1)
+        g64 = synth.Geometry(**{**g.as_dict(), "n_slices": 64})
+        legs["throughput_64_slices_1_thread"] = timed(g64, w.delta[:64], w.beta[:64], meas)
+    finally:
+        O.WORKERS = keep
+    full = legs["throughput_full"]
+    return {"value": full["value"], "unit": "voxel-slice-steps/s", "cores": O.WORKERS, "kind": "oracle",
+            "sample": f"FP64 oracle forward + far field + loss + adjoint (all fields kept) on the whole "
+                      f"{g.ny}x{g.nz}x{g.n_slices} workload: {full['seconds']:.2f} s; SciPy FFTs on "
+                      f"{O.WORKERS} threads, NumPy elementwise work on one",
+            "cpu": _cpu_model(), "legs": legs}
 
 
 def recon_leg():
@@ -158,6 +188,34 @@ def learned_leg():
     return info
 
 
+def roofline(pass_bytes, launch_s, traffic, prof, ny, nz, pass_gbs, pass_tflops, prof_us):
+    """Roofline of the forward middle pass against both of its ceilings: HBM bandwidth (its
+    algorithmic bytes at 8 TB/s) and VALU issue (its executed lane-instructions at the unpacked
+    FP32 rate).  `bound` names the ceiling that allows less, i.e. whose floor time is longer."""
+    hbm = {"achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pass_gbs / HBM_PEAK_GBS,
+           "floor_us": pass_bytes / (HBM_PEAK_GBS * 1e9) * 1e6}
+    roof = {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": pass_gbs / HBM_PEAK_GBS, "traffic": (traffic / launch_s / 1e9) if traffic else None,
+            "kernel": "k_pass<512,*,1> forward line pass (propagate, transmit, propagate)",
+            "bytes_per_launch": pass_bytes, "us_per_launch": launch_s * 1e6, "traffic_bytes_per_launch": traffic,
+            "rocprof_kernel_us": prof_us, "hbm": hbm,
+            "flops_per_launch": fwd_flops_per_voxel_slice(nz) * ny * nz, "achieved_TFLOPs": pass_tflops,
+            "fp32_frac": pass_tflops / FP32_PEAK_TFLOPS, "valu": None}
+    vr, vc, waves = prof.get("valu_per_wave_row"), prof.get("valu_per_wave_column"), prof.get("waves_per_launch")
+    if vr and vc and waves:
+        per_wave = 0.5 * (vr + vc)   # the sweep alternates row and column passes
+        lanes = per_wave * waves * 64
+        achieved = lanes / launch_s / 1e12
+        roof["valu"] = {"instr_per_wave_row": vr, "instr_per_wave_column": vc, "waves_per_launch": waves,
+                        "lane_instr_per_launch": lanes, "achieved": achieved, "peak": VALU_PEAK_TLANES,
+                        "unit": "Tlane-instr/s", "frac": achieved / VALU_PEAK_TLANES,
+                        "floor_us": lanes / (VALU_PEAK_TLANES * 1e12) * 1e6}
+        if roof["valu"]["floor_us"] > hbm["floor_us"]:
+            roof.update({"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TLANES, "unit": "Tlane-instr/s",
+                         "frac": achieved / VALU_PEAK_TLANES})
+    return roof
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -176,7 +234,6 @@ def main():
     ap.add_argument("--ckpt-every", type=int, default=32)
     ap.add_argument("--schedule", type=int, default=0, help="0 auto, 1 per-pass launches, 2 persistent")
     ap.add_argument("--slices", type=int, default=2048)
-    ap.add_argument("--cpu-sample-slices", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction seconds-to-loss leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initialiser leg")
@@ -270,7 +327,8 @@ def main():
     launch_s = fwd_med / 1e3 / (ns + 1)
     pass_gbs = pass_bytes / launch_s / 1e9
     pass_tflops = fwd_flops_per_voxel_slice(nz) * ny * nz / launch_s / 1e12
-    traffic, prof_us = profile_figures()
+    prof = profile_figures()
+    traffic, prof_us = prof.get("traffic_bytes_per_launch"), prof.get("kernel_us_per_launch")
     fwd_path_ms = float(np.median([a + b + c for a, b, c in zip(pack_ms, fwd_ms, mid_ms)]))
     print(f"# step {ms:.3f} ms: pack {np.median(pack_ms):.3f} ms, forward {fwd_med:.3f} ms, "
           f"far field+loss+seed {np.median(mid_ms):.3f} ms, adjoint {np.median(adj_ms):.3f} ms",
@@ -295,14 +353,7 @@ def main():
                    "schedule": ["auto", "per_pass", "persistent"][args.schedule]},
         # dominant kernel: the forward middle line pass (also the recompute's);
         # per launch = forward time / launches, i.e. kernel plus dispatch gap
-        "roofline": {"bound": "hbm", "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": pass_gbs / HBM_PEAK_GBS,
-                     "traffic": (traffic / launch_s / 1e9) if traffic else None,
-                     "kernel": "k_pass<512,*,1> forward line pass (propagate, transmit, propagate)",
-                     "bytes_per_launch": pass_bytes, "us_per_launch": launch_s * 1e6,
-                     "traffic_bytes_per_launch": traffic, "rocprof_kernel_us": prof_us,
-                     "flops_per_launch": fwd_flops_per_voxel_slice(nz) * ny * nz,
-                     "achieved_TFLOPs": pass_tflops, "fp32_frac": pass_tflops / FP32_PEAK_TFLOPS},
+        "roofline": roofline(pass_bytes, launch_s, traffic, prof, ny, nz, pass_gbs, pass_tflops, prof_us),
         "step": {"bytes_per_voxel_slice": bpv, "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS,
                  "ms_p10": float(np.percentile(step_ms, 10)), "ms_p50": float(np.median(step_ms)),
                  "ms_p90": float(np.percentile(step_ms, 90)),
@@ -357,7 +408,7 @@ def main():
                 out["recon"]["learned"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, meas, args.cpu_sample_slices)
+        out["cpu_baseline"] = cpu_baseline(w, meas)
     print(json.dumps(out), flush=True)
 
 

@@ -32,10 +32,26 @@ def test_profile_figures_follow_the_kernel_sources(tmp_path, monkeypatch):
     got = bench.profile_figures()
     text = open(os.path.join(ROOT, bench.TRAFFIC_PROFILE)).read()
     assert "traffic_bytes_per_launch:" in text and "sources_sha256:" in text
-    if got != (None, None):
-        b, us = got
-        assert 6.0e6 < b < 8.0e6 and 5.0 < us < 20.0
+    if got:
+        assert 6.0e6 < got["traffic_bytes_per_launch"] < 8.0e6 and 5.0 < got["kernel_us_per_launch"] < 20.0
+        assert 500 < got["valu_per_wave_row"] < 4000 and 500 < got["valu_per_wave_column"] < 4000
+        assert got["waves_per_launch"] == 512
     other = tmp_path / "other.hip"
     other.write_text("// not the kernel source\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCES", (str(other),))
-    assert bench.profile_figures() == (None, None)
+    assert bench.profile_figures() == {}
+
+
+def test_roofline_names_the_binding_ceiling():
+    # VALU floor 512 waves x 1600 instructions x 64 lanes at 39.3e12/s = 1.33 us is longer
+    # than the HBM floor of 6.36 MB at 8 TB/s = 0.79 us: the pass is issue-bound ("alu")
+    prof = {"valu_per_wave_row": 1700.0, "valu_per_wave_column": 1500.0, "waves_per_launch": 512,
+            "traffic_bytes_per_launch": 6.6e6, "kernel_us_per_launch": 8.0}
+    r = bench.roofline(6356992.0, 8e-6, 6.6e6, prof, 512, 512, 6356992.0 / 8e-6 / 1e9, 6.0, 8.0)
+    assert r["bound"] == "alu" and r["unit"] == "Tlane-instr/s"
+    assert r["valu"]["floor_us"] == pytest.approx(512 * 1600 * 64 / 39.3216e12 * 1e6)
+    assert r["frac"] == pytest.approx(r["valu"]["floor_us"] / 8.0)
+    assert r["hbm"]["frac"] == pytest.approx(6356992.0 / 8e-6 / 8e12)
+    # without the counters the HBM ceiling is the only one reported
+    r = bench.roofline(6356992.0, 8e-6, None, {}, 512, 512, 6356992.0 / 8e-6 / 1e9, 6.0, None)
+    assert r["bound"] == "hbm" and r["valu"] is None and r["traffic"] is None
