@@ -422,15 +422,22 @@ def mean_target(data, chunk=256):
 
 
 def train(net, data, steps, batch=32, lr=1e-3, seed=1, log_every=0, val=None):
-    """ADAM on the mean squared error over random minibatches; returns the loss history."""
+    """ADAM on the mean squared error over minibatches that walk the training set in a fresh
+    seeded permutation each epoch (every sample once per epoch; a last partial batch is left
+    out); returns the loss history and the seconds taken."""
     rng = np.random.Generator(np.random.PCG64(seed))
     n = data.n
     xb = torch.empty((1, batch, n, n), dtype=torch.float32, device="cuda")
     yb = torch.empty((batch, data.rows, n), dtype=torch.float32, device="cuda")
     hist = []
+    per_epoch = len(data) // batch
+    order = None
     t0 = time.perf_counter()
     for it in range(steps):
-        idx = torch.from_numpy(rng.choice(len(data), size=batch, replace=False)).cuda()
+        if it % per_epoch == 0:
+            order = rng.permutation(len(data))
+        k = it % per_epoch
+        idx = torch.from_numpy(order[k * batch:(k + 1) * batch]).cuda()
         torch.index_select(data.x, 0, idx, out=xb[0])
         torch.index_select(data.y, 0, idx, out=yb)
         net.forward(xb)
@@ -471,11 +478,15 @@ def evaluate(net, data, batch=64):
     return total / count
 
 
-def train_initialiser(n_samples=50000, steps=800, batch=32, lr=1e-3, n=256, n_slices=1024, seed=0, log_every=0,
-                      n_val=256):
-    """Training set from the model, the network with the targets' mean as output offset, ADAM.
+def train_initialiser(n_samples=50000, steps=None, batch=32, lr=1e-3, n=256, n_slices=1024, seed=0, log_every=0,
+                      n_val=256, epochs=1):
+    """Training set from the model, the network with the targets' mean as output offset, ADAM
+    over `epochs` passes through the training set (or `steps` minibatches when given).
     Returns (net, info) with the data and training times and the validation error of the network
-    next to that of the offset alone (the population-mean cross-section)."""
+    next to that of the offset alone (the population-mean cross-section); info["companions"]
+    keeps the validation inputs (images the network never trained on) for batched inference."""
+    if steps is None:
+        steps = max(1, epochs * (n_samples // batch))
     data = TrainingSet(n_samples, n=n, n_slices=n_slices)
     val = TrainingSet(n_val, seed0=900000, n=n, n_slices=n_slices)
     net = UNet(c=32, seed=seed, n=n)
@@ -497,7 +508,9 @@ def train_initialiser(n_samples=50000, steps=800, batch=32, lr=1e-3, n=256, n_sl
     info = {"samples": n_samples, "steps": steps, "batch": batch, "lr": lr, "data_seconds": data.seconds,
             "train_seconds": secs, "ms_per_step": 1e3 * secs / max(1, steps), "params": net.n_params,
             "val_mse": evaluate(net, val), "val_mse_mean_map": base,
-            "val_row_profile_mse": row_net, "val_row_profile_mse_mean_map": row_mean}
+            "val_row_profile_mse": row_net, "val_row_profile_mse_mean_map": row_mean,
+            "epochs": steps * batch / n_samples}
+    info["companions"] = val.x[:63].clone()
     del data, val
     return net, info
 

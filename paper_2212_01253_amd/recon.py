@@ -20,6 +20,7 @@ measured amplitudes sqrt(C / s) and multiplied by s (and so is its gradient).
 """
 from __future__ import annotations
 
+import math
 import time
 from dataclasses import dataclass, field, replace
 
@@ -49,6 +50,23 @@ class ReconResult:
     iters_to_threshold: int | None = None        # ADAM steps taken before the first iterate at or below it
     secs_to_threshold: float | None = None
     threshold: float | None = None
+    stalled: bool = False                        # stopped by the stall detector (see Reconstructor.run)
+
+
+class StallWatch:
+    """Progress test of a descent: the loss must fall by a fraction `gain` below its last marked
+    value within every `window` iterations (window 0: never stalls).  A loss that is not a number
+    never counts as progress."""
+
+    def __init__(self, window, gain):
+        self.window, self.gain = int(window), float(gain)
+        self.mark, self.mark_it = math.inf, 0
+
+    def stalled(self, it, loss):
+        if loss <= self.mark * (1.0 - self.gain):
+            self.mark, self.mark_it = loss, it
+            return False
+        return self.window > 0 and it - self.mark_it >= self.window
 
 
 class Reconstructor:
@@ -161,15 +179,18 @@ class Reconstructor:
         msl.region_shrinkwrap(self.g, self.r, sigmas, threshold, self.theta, self.D, self.B, self._sw_scratch)
 
     def run(self, theta0, max_iters, threshold=None, log_every=0, snap_levels=None, snap_every=0,
-            wrap_every=0, wrap_sigmas=(0.0, 1.5, 1.5), wrap_threshold=0.1):
+            wrap_every=0, wrap_sigmas=(0.0, 1.5, 1.5), wrap_threshold=0.1, stall_window=0, stall_gain=0.01):
         """ADAM from theta0 until the loss is <= threshold or max_iters steps; wall-clock timed.
         With snap_levels and snap_every, every snap_every-th step is followed by the
         nearest-index filter (the paper applies it after 20 epochs); with wrap_every, every
-        wrap_every-th step by the shrink-wrap support (the paper: every 20 epochs)."""
+        wrap_every-th step by the shrink-wrap support (the paper: every 20 epochs).  With
+        stall_window, the run also stops (result.stalled) once stall_window iterations pass
+        without the loss falling by a fraction stall_gain below its last such improvement."""
         res = ReconResult(threshold=threshold)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         self.set_theta(theta0)
+        watch = StallWatch(stall_window, stall_gain)
         for it in range(max_iters + 1):
             L = float(self.loss().item()) * self.scale
             now = time.perf_counter() - t0
@@ -182,6 +203,9 @@ class Reconstructor:
                 res.secs_to_threshold = now
                 break
             if it == max_iters:
+                break
+            if watch.stalled(it, L):
+                res.stalled = True
                 break
             self.gradient_step()
             if snap_levels is not None and snap_every and self.t % snap_every == 0:
@@ -232,49 +256,106 @@ def seconds_to_threshold(p: Problem, init, factor=1.10, max_iters=5000, adam: Ad
     return L_truth, res
 
 
-def learned_initial_guess(net, p: Problem):
-    """Box values from the network: the measured counts as an intensity estimate (counts / s)
-    through the network's input map, the predicted cross-section (rows x columns, in units of
-    1e-5) clamped at 0 and repeated along the beam over the box's slices."""
+def learned_initial_guesses(net, problems, companions=None, batch=64):
+    """Box values from the network for several problems in one inference batch: each problem's
+    measured counts as an intensity estimate (counts / s) through the network's input map, the
+    predicted cross-section (rows x columns, in units of 1e-5) clamped at 0 and repeated along
+    the beam over the box's slices.  `companions` ([S][n][n] device tensor of inputs already
+    through the input map, e.g. other measured images) fill the batch up to `batch` images, as in
+    a run that infers many samples at once; only the problems' guesses are returned."""
     from . import learned, nn
-    n = p.geom.ny
-    I = torch.from_numpy(np.ascontiguousarray(p.counts / p.scale, np.float32)).cuda()
-    x = torch.empty((1, 1, n, n), dtype=torch.float32, device="cuda")
-    nn.logmap(I, learned.eps_of(n), learned.INPUT_A, 0.0, x)
-    pred = net.forward(x)[0].cpu().numpy().astype(np.float64) * 1e-5
-    cs = np.clip(pred, 0.0, None).astype(np.float32)
-    return np.ascontiguousarray(np.broadcast_to(cs, (p.region["ns"],) + cs.shape))
+    n = problems[0].geom.ny
+    k = len(problems)
+    B = max(batch, k)
+    x = torch.zeros((1, B, n, n), dtype=torch.float32, device="cuda")
+    for i, p in enumerate(problems):
+        I = torch.from_numpy(np.ascontiguousarray(p.counts / p.scale, np.float32)).cuda()
+        nn.logmap(I, learned.eps_of(n), learned.INPUT_A, 0.0, x[0, i])
+    if companions is not None and B > k:
+        m = min(B - k, companions.shape[0])
+        x[0, k:k + m] = companions[:m]
+    pred = net.forward(x)[:k].cpu().numpy().astype(np.float64) * 1e-5
+    out = []
+    for p, q in zip(problems, pred):
+        cs = np.clip(q, 0.0, None).astype(np.float32)
+        out.append(np.ascontiguousarray(np.broadcast_to(cs, (p.region["ns"],) + cs.shape)))
+    return out
 
 
-REFINE_LR = 5e-6   # ADAM step from a learned start (sweep 4e-6 ... 8.5e-6 on the same workload)
+def learned_initial_guess(net, p: Problem, companions=None, batch=64):
+    """``learned_initial_guesses`` for one problem (in a batch of `batch` images)."""
+    return learned_initial_guesses(net, [p], companions, batch)[0]
+
+
+REFINE_LR = 5e-6        # ADAM step from a learned start (sweep 4e-6 ... 8.5e-6 on the same workload)
+REFINE_BUDGET = 400     # most ADAM steps from a learned start before the plain start takes over
+STALL_WINDOW = 50       # ... or this many steps without the loss falling by STALL_GAIN
+STALL_GAIN = 0.01
+
+
+@dataclass
+class LearnedRun:
+    """Outcome of a reconstruction from a learned start with its error judge and fallback."""
+    L_truth: float
+    result: ReconResult          # the whole run (judging, learned attempt, plain fallback), one clock
+    start: str                   # "learned", "plain" (judge) or "learned, then plain" (fallback)
+    loss_learned_start: float
+    loss_plain_start: float
+    learned_iters: int | None    # ADAM steps of the learned attempt (None: not tried)
+    stalled: bool = False
 
 
 def seconds_to_threshold_learned(p: Problem, net, plain_init, factor=1.10, max_iters=5000, adam: Adam | None = None,
-                                 ckpt_every=32, log_every=0, graphs=True, refine_lr=REFINE_LR):
-    """Learned start with an error judge: network inference, then the losses of the learned and the
-    plain start are compared and ADAM runs from the lower one (the plain start is the fallback when
-    the learned guess is worse or not finite).  From the learned start ADAM takes the smaller
-    refinement step refine_lr (None: keep adam's); from the plain one, adam's own.  The reported
-    seconds include inference and judging.  Returns (L_truth, result, chose_learned, loss_learned,
-    loss_plain)."""
+                                 ckpt_every=32, log_every=0, graphs=True, refine_lr=REFINE_LR, companions=None,
+                                 batch=64, budget=REFINE_BUDGET, stall_window=STALL_WINDOW, stall_gain=STALL_GAIN):
+    """Learned start with an error judge and a fallback.  Network inference (in a batch of
+    `batch` images with `companions`), then the losses of the learned and the plain start are
+    compared and ADAM starts from the lower one (the plain start when the learned guess is worse
+    or not finite).  From the learned start ADAM takes the refinement step refine_lr (None: keep
+    adam's) and is watched: if it has not reached the threshold within `budget` steps, or stalls
+    (stall_window steps without a stall_gain fall of the loss), the plain start takes over with
+    adam's own step.  One clock covers inference, judging, a failed attempt and the fallback."""
     R = Reconstructor(p.geom, p.known_delta, p.known_beta, p.region, p.counts, p.scale, ckpt_every=ckpt_every,
                       adam=adam, graphs=graphs)
     R.set_theta(p.truth)
     L_truth = float(R.loss().item()) * p.scale
     R.stack_gradients()   # the adjoint graph is captured here, before the clock starts
+    threshold = factor * L_truth
+    base_adam = R.adam
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    guess = learned_initial_guess(net, p)
+    guess = learned_initial_guess(net, p, companions, batch)
     R.set_theta(guess)
     L_learned = float(R.loss().item()) * p.scale
     R.set_theta(plain_init)
     L_plain = float(R.loss().item()) * p.scale
     chose = bool(np.isfinite(L_learned) and L_learned < L_plain)
-    if chose and refine_lr is not None:
-        R.adam = replace(R.adam, lr=float(refine_lr))
     t_judge = time.perf_counter() - t0
-    res = R.run(guess if chose else plain_init, max_iters, factor * L_truth, log_every=log_every)
-    res.times = [t + t_judge for t in res.times]
+    out = ReconResult(threshold=threshold)
+
+    def append(res, offset):
+        out.losses += res.losses
+        out.times += [t + offset for t in res.times]
+
+    learned_iters, stalled, start = None, False, "plain"
+    offset = t_judge
+    if chose:
+        R.adam = replace(base_adam, lr=float(refine_lr)) if refine_lr is not None else base_adam
+        res = R.run(guess, min(budget, max_iters), threshold, log_every=log_every, stall_window=stall_window,
+                    stall_gain=stall_gain)
+        append(res, offset)
+        learned_iters = len(res.losses) - 1
+        stalled = res.stalled
+        if res.secs_to_threshold is not None:
+            out.iters_to_threshold = res.iters_to_threshold
+            out.secs_to_threshold = res.secs_to_threshold + offset
+            return LearnedRun(L_truth, out, "learned", L_learned, L_plain, learned_iters, stalled)
+        offset += res.times[-1]
+        start = "learned, then plain"
+        R.adam = base_adam
+    res = R.run(plain_init, max_iters, threshold, log_every=log_every)
+    append(res, offset)
     if res.secs_to_threshold is not None:
-        res.secs_to_threshold += t_judge
-    return L_truth, res, chose, L_learned, L_plain
+        out.iters_to_threshold = res.iters_to_threshold + (learned_iters or 0)
+        out.secs_to_threshold = res.secs_to_threshold + offset
+    return LearnedRun(L_truth, out, start, L_learned, L_plain, learned_iters, stalled)

@@ -337,25 +337,68 @@ def test_split_gemm_matches_float64_products(T, ta, tb, splits):
 
 
 def test_learned_start_and_its_judge(M=None):
-    """What the trained initialiser gains over the plain random start, on a held-out
-    reconstruction (small grid, short training): a start with a much lower loss; and the judge
-    falls back to the plain start when the learned guess is not usable (here: NaN offset)."""
+    """The error judge on a held-out reconstruction (small grid, short training): the learned
+    start has a much lower loss and is chosen; the judge falls back to the plain start when the
+    learned guess is not usable (here: NaN offset)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2212_01253_amd import learned, recon
     net, info = learned.train_initialiser(n_samples=512, steps=60, batch=16, n=128, n_slices=128, n_val=64)
+    info.pop("companions")
     print(info)
     assert np.isfinite(info["val_mse"]) and info["val_mse"] <= 1.5 * info["val_mse_mean_map"]
     p = recon.make_problem(seed_gt=4300, seed_noise=4301, n=128, n_slices=128, photons=1e7)
     init = synth.random_init(p.region, 4302)
     adam = recon.Adam()
-    _, lrn, chose, L_learned, L_plain = recon.seconds_to_threshold_learned(p, net, init, max_iters=0, adam=adam,
-                                                                        ckpt_every=8)
-    print("start losses: learned", L_learned, "plain", L_plain)
-    assert chose and L_learned < 0.7 * L_plain        # measured 112784 against 232480
+    run = recon.seconds_to_threshold_learned(p, net, init, max_iters=0, adam=adam, ckpt_every=8)
+    print("start losses: learned", run.loss_learned_start, "plain", run.loss_plain_start)
+    # the judge picks the learned start (no steps here: max_iters=0, so the run ends right after)
+    assert run.start.startswith("learned") and run.loss_learned_start < 0.7 * run.loss_plain_start   # 112784 / 232480
     net.set_offset(torch.full_like(net.offset, float("nan")))
-    L_truth, res, chose, L_learned, L_plain2 = recon.seconds_to_threshold_learned(p, net, init, max_iters=800,
-                                                                                 adam=adam, ckpt_every=8)
-    assert not chose and not np.isfinite(L_learned) and L_plain2 == L_plain
-    assert res.iters_to_threshold is not None        # the plain start reaches 1.1 x L(truth) (485 steps)
+    run2 = recon.seconds_to_threshold_learned(p, net, init, max_iters=800, adam=adam, ckpt_every=8)
+    assert run2.start == "plain" and not np.isfinite(run2.loss_learned_start)
+    assert run2.loss_plain_start == run.loss_plain_start
+    assert run2.result.iters_to_threshold is not None   # the plain start reaches 1.1 x L(truth) (485 steps)
+
+
+def test_refinement_that_misses_the_threshold_falls_back_to_the_plain_start():
+    """A learned start whose refinement does not reach the threshold within its step budget hands
+    over to the plain start; the failed attempt's time counts, and the run still reaches the
+    threshold (the small network here: its start is chosen, but 12 steps do not suffice)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_01253_amd import learned, recon
+    net, info = learned.train_initialiser(n_samples=512, steps=60, batch=16, n=128, n_slices=128, n_val=64)
+    p = recon.make_problem(seed_gt=4300, seed_noise=4301, n=128, n_slices=128, photons=1e7)
+    init = synth.random_init(p.region, 4302)
+    run = recon.seconds_to_threshold_learned(p, net, init, max_iters=800, ckpt_every=8, budget=12,
+                                             companions=info["companions"], batch=64)
+    res = run.result
+    print(run.start, run.learned_iters, res.iters_to_threshold, res.secs_to_threshold)
+    assert run.start == "learned, then plain" and run.learned_iters == 12
+    assert res.iters_to_threshold is not None and res.iters_to_threshold > 12
+    assert res.secs_to_threshold > res.times[12]     # the learned attempt's 12 steps are on the clock
+    assert res.losses[-1] <= res.threshold
+
+
+def test_learned_start_reaches_the_threshold_sooner():
+    """What the trained initialiser gains, in seconds to the loss threshold, on a held-out truth
+    of the gradient workload (256 x 256 grid, 1024 slices; truth, noise and plain start seeds
+    the training set does not use): the learned start, with inference in a batch of 64 and the
+    error judge on the clock, reaches 1.1 x L(truth) in fewer seconds than the plain start."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_01253_amd import learned, recon
+    net, info = learned.train_initialiser(n_samples=4096, steps=300)
+    p = recon.make_problem(seed_gt=4270, seed_noise=4271)
+    init = synth.random_init(p.region, 4272)
+    L_truth, plain = recon.seconds_to_threshold(p, init)
+    run = recon.seconds_to_threshold_learned(p, net, init, companions=info["companions"], batch=64)
+    print(f"plain {plain.secs_to_threshold:.2f} s ({plain.iters_to_threshold} steps); learned "
+          f"{run.result.secs_to_threshold:.2f} s ({run.result.iters_to_threshold} steps, start {run.start})")
+    assert plain.secs_to_threshold is not None and run.result.secs_to_threshold is not None
+    assert run.start == "learned"
+    assert run.result.secs_to_threshold < plain.secs_to_threshold
