@@ -302,14 +302,18 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 // Thread t of a workgroup of G lines works on line t mod G at lane t / G:
 // neighbouring threads take neighbouring lines, so each load and store of a
 // wavefront covers whole 2x2 tiles of the tiled working fields.
+// The specialised middle passes take the transmission of a row pass (even
+// slice) from the caller's stack and that of a column pass (odd slice) from the
+// slice pack, which launch_pass_t makes sure exists.
 template <int N, int AXIS, int KIND>
 __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   __shared__ float2 lds[kLdsSlots];
   constexpr int L = msl::LinePts<N>::L;
+  constexpr int TS = KIND == msl::KIND_GENERIC ? msl::TS_RUNTIME : (AXIS == msl::COL ? msl::TS_PACK : msl::TS_STACK);
   const int G = blockDim.x / L;
   const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
-  msl::run_line<N, AXIS, false, KIND>(c, pd, group * G + g, j, lds + g * msl::line_lds<N>());
+  msl::run_line<N, AXIS, false, KIND, TS>(c, pd, group * G + g, j, lds + g * msl::line_lds<N>());
 }
 
 // Lines per workgroup: at most 256 threads (the kernels' launch bound) and
@@ -339,7 +343,12 @@ hipError_t launch_pass_t(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   static_assert(L == N / (N >= MSL_P8_MIN_N && N < MSL_P4_MIN_N ? 8 : 4), "lines_per_group assumes this split");
   const int G = lines_per_group(N, nlines);
   const dim3 grid(nlines / G), block(L * G);
-  switch (msl::pass_kind(pd)) {
+  int kind = msl::pass_kind(pd);
+  // the specialised kinds' transmission source (see k_pass): row passes of even slices from the
+  // stack (no batch pool index), column passes of odd slices from the pack
+  const bool ts_ok = AXIS == msl::ROW ? (!c.slice_index && (pd.slice & 1) == 0) : (c.dbT && (pd.slice & 1));
+  if (!ts_ok) kind = msl::KIND_GENERIC;
+  switch (kind) {
     case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_FWD_MID>), grid, block, 0, st, c, pd); break;
     case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_REV_MID>), grid, block, 0, st, c, pd); break;
     default: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_GENERIC>), grid, block, 0, st, c, pd); break;
@@ -603,8 +612,8 @@ __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__
   PassDesc pd = tmpl;
   pd.src = recs[inst].field;
   pd.dst = recs[inst].field;
-  msl::run_line<N, AXIS, false, msl::KIND_FWD_MID>(c, pd, (gb % groups_per_inst) * G + g, j,
-                                                   lds + g * msl::line_lds<N>());
+  msl::run_line<N, AXIS, false, msl::KIND_FWD_MID, msl::TS_PACK>(c, pd, (gb % groups_per_inst) * G + g, j,
+                                                                lds + g * msl::line_lds<N>());
 }
 
 template <int N, int AXIS>

@@ -374,8 +374,18 @@ __device__ __forceinline__ LineAddr line_at(const Ctx& c, int lay, int line, int
 template <int N>
 constexpr int line_lds() { return N + N / 8 + 1; }
 
+// Where a pass takes the transmission T - 1 of its slice from: decided per
+// pass at run time, or fixed at compile time for kernels that serve only one
+// case (the slice pack: the paraxial column passes and the batched passes; the
+// caller's stack: the paraxial row passes), which then carry no code for the
+// other.
+enum TSource : int { TS_RUNTIME = 0, TS_PACK = 1, TS_STACK = 2 };
+
 // Whether slice `slice` reads its precomputed T - 1 (the slice pack).
+template <int TS = TS_RUNTIME>
 __device__ __forceinline__ bool uses_pack(const Ctx& c, int slice) {
+  if constexpr (TS == TS_PACK) return true;
+  if constexpr (TS == TS_STACK) return false;
   return c.dbT && (c.slice_index || (slice & 1));
 }
 
@@ -398,7 +408,7 @@ __device__ __forceinline__ bool uses_h1d(const PassDesc& pd) {
   return pd.pre == PRE_PROP || pd.post == POST_PROP;
 }
 
-template <int N, int AXIS, int KIND = KIND_GENERIC>
+template <int N, int AXIS, int KIND = KIND_GENERIC, int TS = TS_RUNTIME>
 __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, int line, int j, LineIn<N>& in) {
   PassDesc pd = pd_;
   if constexpr (KIND != KIND_GENERIC) {
@@ -426,7 +436,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
     }
   }
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
-    if (uses_pack(c, pd.slice)) {
+    if (uses_pack<TS>(c, pd.slice)) {
       // precomputed T - 1 (real part in dl, imaginary part in bt), tiled
       const int64_t so = c.slice_index ? slice_offset(c, pd.slice) : (int64_t)(pd.slice >> 1) * c.m;
       const float2* q = c.dbT + so;
@@ -510,7 +520,7 @@ __device__ __forceinline__ void prop_line(float2 (&v)[LinePts<N>::P], float2* sh
   fft_line<N, true>(v, sh, j, in.tw);
 }
 
-template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC>
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME>
 __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, int line, int j, float2* sh,
                                              LineIn<N>& in) {
   constexpr int L = LinePts<N>::L;
@@ -547,7 +557,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 
   float2 tm1[P];  // T - 1 of the slice at this line's points
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
-    if (uses_pack(c, pd.slice)) {
+    if (uses_pack<TS>(c, pd.slice)) {
 #pragma unroll
       for (int t = 0; t < P; ++t) tm1[t] = make_float2(in.dl[t], in.bt[t]);
     } else {
@@ -613,12 +623,12 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 }
 
-template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC>
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME>
 __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
   LineIn<N> in;
   load_field<N, AXIS, COH, KIND>(c, pd, line, j, in);
-  load_static<N, AXIS, KIND>(c, pd, line, j, in);
-  compute_line<N, AXIS, COH, KIND>(c, pd, line, j, sh, in);
+  load_static<N, AXIS, KIND, TS>(c, pd, line, j, in);
+  compute_line<N, AXIS, COH, KIND, TS>(c, pd, line, j, sh, in);
 }
 
 // Either axis, chosen per pass at run time (square grids: both line lengths are N).
