@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define MSL_ABI_VERSION 3
+#define MSL_ABI_VERSION 4
 
 typedef struct { float re, im; } msl_c64;
 
@@ -222,19 +222,30 @@ msl_status msl_workspace_status(void* workspace, size_t ws_bytes, void* hip_stre
 int32_t msl_set_barrier_spin_limit(int32_t polls);
 
 /* ---- launch shape and its autotuner ----
- * The line passes run as workgroups of several neighbouring lines each.
+ * The line passes run as workgroups of several neighbouring lines each, every
+ * line held by N / P lanes at P points per lane.
+ * Entry e of points_per_lane is P for 2^e-point lines: 4 (radix-4 stages,
+ * e >= 4) or 8 (radix-8 stages, e >= 6); 0 = the library default (8 from 512
+ * points up, 4 below); other entries must be 0.  P changes the order of the
+ * FFT's float32 operations, so results differ in the last bits between
+ * settings (both within the parity tolerances).  The persistent schedule
+ * (MSL_SCHED_PERSISTENT) always uses the default.
  * Entry e of lines_per_group is the number of 2^e-point lines per workgroup
  * (e = 4..10; 0 = the library default: one 64-lane wavefront's worth of
  * lanes and at least two lines; other entries must be 0).  Allowed values are
  * powers of two up to the limit set by the 256-thread workgroup and the
- * workgroup's line buffers in LDS:
- * 2^e = 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 4, 1024: 2.
+ * workgroup's line buffers in LDS: at 8 points per lane
+ * 2^e = 64: 16, 128: 8, 256: 4, 512: 4, 1024: 2; at 4 points per lane
+ * 2^e = 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2, 1024: 1.
+ * The lines per workgroup only deal lines to the hardware: at one P every
+ * allowed value gives bit-identical results.
  * batch_streams: how many grid-size groups msl_forward_batch runs side by side
  * (1..4; 0 = 4).  The setting is process-wide, applies to later calls, and is
  * not synchronised with calls running on other threads. */
 #define MSL_TUNE_SLOTS 11
 typedef struct {
   int32_t lines_per_group[MSL_TUNE_SLOTS];
+  int32_t points_per_lane[MSL_TUNE_SLOTS];
   int32_t batch_streams;
 } msl_tuning;
 
@@ -245,8 +256,8 @@ msl_status msl_get_tuning(msl_tuning* t);
 
 /* Autotuner of the launch shape for one geometry: times msl_forward (no
  * probe, no checkpoints) on the caller's delta and beta (device
- * [Ns][ny][nz] f32) for every allowed lines-per-workgroup value of the
- * nz-point slot, keeps the fastest, then the same for the ny-point slot
+ * [Ns][ny][nz] f32) for every allowed (points per lane, lines per workgroup)
+ * pair of the nz-point slot, keeps the fastest, then the same for the ny-point slot
  * (when ny != nz).  Each candidate runs once untimed and then `reps` times
  * (1..1000) between two HIP events on hip_stream; the call blocks until the
  * search ends.  field_scratch: device complex64 [ny][nz], overwritten.
@@ -294,7 +305,7 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
 
 /* Launch-shape autotuner for a batch, as msl_autotune_forward (msl_set_tuning): times
  * msl_forward_batch over inst[0..n) for every batch_streams value (1..4), keeps the fastest,
- * then every allowed lines-per-workgroup value of each line length the instances use, one
+ * then every allowed (points per lane, lines per workgroup) pair of each line length the instances use, one
  * length at a time.  The instances' outputs are overwritten by the timed runs; workspace as
  * for msl_forward_batch; blocks until the search ends. */
 msl_status msl_autotune_batch(const msl_instance* inst, int32_t n, void* workspace, size_t ws_bytes, int32_t reps,

@@ -29,6 +29,7 @@ int g_schedule = MSL_SCHED_AUTO;
 // Launch shape of the line-pass kernels (msl_set_tuning): lines of length 2^e
 // per workgroup, 0 = the default (one wavefront's worth of lanes).
 int g_lines_per_group[MSL_TUNE_SLOTS] = {};
+int g_points_per_lane[MSL_TUNE_SLOTS] = {};  // 0: default (default_points_per_lane)
 int g_batch_streams = 0;  // 0: default (every extra stream)
 
 // Polls of the persistent schedule's bounded barrier wait (msl_set_barrier_spin_limit).
@@ -305,21 +306,33 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 // The specialised middle passes take the transmission of a row pass (even
 // slice) from the caller's stack and that of a column pass (odd slice) from the
 // slice pack, which launch_pass_t makes sure exists.
-template <int N, int AXIS, int KIND>
+template <int N, int P, int AXIS, int KIND>
 __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   __shared__ float2 lds[kLdsSlots];
-  constexpr int L = msl::LinePts<N>::L;
+  constexpr int L = N / P;
   constexpr int TS = KIND == msl::KIND_GENERIC ? msl::TS_RUNTIME : (AXIS == msl::COL ? msl::TS_PACK : msl::TS_STACK);
   const int G = blockDim.x / L;
   const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
-  msl::run_line<N, AXIS, false, KIND, TS>(c, pd, group * G + g, j, lds + g * msl::line_lds<N>());
+  msl::run_line<N, AXIS, false, KIND, TS, P>(c, pd, group * G + g, j, lds + g * msl::line_lds<N>());
 }
 
-// Lines per workgroup: at most 256 threads (the kernels' launch bound) and
-// the line exchange buffers within the kLdsSlots-slot LDS array.
-int max_lines_per_group(int n) {
-  const int L = n / (n >= MSL_P8_MIN_N && n < MSL_P4_MIN_N ? 8 : 4);
+// Points per lane of the per-pass and batch line kernels for n-point lines:
+// the msl_set_tuning choice, else 8 from 512 points up and 4 below (the
+// persistent schedule keeps that default).
+int default_points_per_lane(int n) { return n >= 512 ? 8 : 4; }
+static_assert(msl::LinePts<256>::P == 4 && msl::LinePts<512>::P == 8 && msl::LinePts<1024>::P == 8,
+              "the persistent schedule's lines split as default_points_per_lane says");
+int points_per_lane(int n) {
+  const int p = g_points_per_lane[__builtin_ctz((unsigned)n)];
+  return p > 0 ? p : default_points_per_lane(n);
+}
+
+// Lines per workgroup of n-point lines at p points per lane: at most 256
+// threads (the kernels' launch bound) and the line exchange buffers within the
+// kLdsSlots-slot LDS array.
+int max_lines_per_group(int n, int p) {
+  const int L = n / p;
   const int lds = n + n / 8 + 1;  // msl::line_lds<n>()
   int G = 1;
   while (2 * G * L <= 256 && 2 * G * lds <= kLdsSlots) G *= 2;
@@ -329,18 +342,18 @@ int max_lines_per_group(int n) {
 // Default: one 64-lane wavefront's worth of lanes, and at least two lines
 // (the two lines of a row or column of tiles).
 int lines_per_group(int n, int nlines) {
-  const int L = n / (n >= MSL_P8_MIN_N && n < MSL_P4_MIN_N ? 8 : 4);
+  const int p = points_per_lane(n);
+  const int L = n / p;
   int G = g_lines_per_group[__builtin_ctz((unsigned)n)];
   if (G <= 0) G = L >= 32 ? 2 : 64 / L;
-  G = std::min(G, max_lines_per_group(n));
+  G = std::min(G, max_lines_per_group(n, p));
   return std::min(G, nlines);
 }
 
-template <int N, int AXIS>
-hipError_t launch_pass_t(const Ctx& c, const PassDesc& pd, hipStream_t st) {
+template <int N, int P, int AXIS>
+hipError_t launch_pass_tp(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const int nlines = AXIS == msl::ROW ? c.ny : c.nz;
-  constexpr int L = msl::LinePts<N>::L;
-  static_assert(L == N / (N >= MSL_P8_MIN_N && N < MSL_P4_MIN_N ? 8 : 4), "lines_per_group assumes this split");
+  constexpr int L = N / P;
   const int G = lines_per_group(N, nlines);
   const dim3 grid(nlines / G), block(L * G);
   int kind = msl::pass_kind(pd);
@@ -349,11 +362,20 @@ hipError_t launch_pass_t(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const bool ts_ok = AXIS == msl::ROW ? (!c.slice_index && (pd.slice & 1) == 0) : (c.dbT && (pd.slice & 1));
   if (!ts_ok) kind = msl::KIND_GENERIC;
   switch (kind) {
-    case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_FWD_MID>), grid, block, 0, st, c, pd); break;
-    case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_REV_MID>), grid, block, 0, st, c, pd); break;
-    default: hipLaunchKernelGGL((k_pass<N, AXIS, msl::KIND_GENERIC>), grid, block, 0, st, c, pd); break;
+    case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_FWD_MID>), grid, block, 0, st, c, pd); break;
+    case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_REV_MID>), grid, block, 0, st, c, pd); break;
+    default: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_GENERIC>), grid, block, 0, st, c, pd); break;
   }
   return hipGetLastError();
+}
+
+// Lines of 64 points and more run at 4 or 8 points per lane, shorter ones at 4.
+template <int N, int AXIS>
+hipError_t launch_pass_t(const Ctx& c, const PassDesc& pd, hipStream_t st) {
+  if constexpr (N >= 64) {
+    if (points_per_lane(N) == 8) return launch_pass_tp<N, 8, AXIS>(c, pd, st);
+  }
+  return launch_pass_tp<N, 4, AXIS>(c, pd, st);
 }
 
 template <int AXIS>
@@ -599,11 +621,11 @@ __global__ void k_store_recs(RecChunk chunk, BatchRec* dst) {
 // instances recs[0 .. gridDim.x / groups_per_inst): block b handles line
 // group b mod groups_per_inst of instance b / groups_per_inst (after the
 // XCD-aware renumbering of the whole grid).
-template <int N, int AXIS>
+template <int N, int P, int AXIS>
 __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__ recs, int groups_per_inst,
                                                     PassDesc tmpl) {
   __shared__ float2 lds[kLdsSlots];
-  constexpr int L = msl::LinePts<N>::L;
+  constexpr int L = N / P;
   const int G = blockDim.x / L;
   const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int gb = msl::xcd_group(blockIdx.x, gridDim.x);
@@ -612,17 +634,25 @@ __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__
   PassDesc pd = tmpl;
   pd.src = recs[inst].field;
   pd.dst = recs[inst].field;
-  msl::run_line<N, AXIS, false, msl::KIND_FWD_MID, msl::TS_PACK>(c, pd, (gb % groups_per_inst) * G + g, j,
-                                                                lds + g * msl::line_lds<N>());
+  msl::run_line<N, AXIS, false, msl::KIND_FWD_MID, msl::TS_PACK, P>(c, pd, (gb % groups_per_inst) * G + g, j,
+                                                                   lds + g * msl::line_lds<N>());
+}
+
+template <int N, int P, int AXIS>
+hipError_t launch_pass_batch_tp(const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl, hipStream_t st) {
+  constexpr int L = N / P;
+  const int G = lines_per_group(N, nlines);
+  const int gpi = nlines / G;
+  hipLaunchKernelGGL((k_pass_batch<N, P, AXIS>), dim3(n_inst * gpi), dim3(L * G), 0, st, recs, gpi, tmpl);
+  return hipGetLastError();
 }
 
 template <int N, int AXIS>
 hipError_t launch_pass_batch_t(const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl, hipStream_t st) {
-  constexpr int L = msl::LinePts<N>::L;
-  const int G = lines_per_group(N, nlines);
-  const int gpi = nlines / G;
-  hipLaunchKernelGGL((k_pass_batch<N, AXIS>), dim3(n_inst * gpi), dim3(L * G), 0, st, recs, gpi, tmpl);
-  return hipGetLastError();
+  if constexpr (N >= 64) {
+    if (points_per_lane(N) == 8) return launch_pass_batch_tp<N, 8, AXIS>(recs, n_inst, nlines, tmpl, st);
+  }
+  return launch_pass_batch_tp<N, 4, AXIS>(recs, n_inst, nlines, tmpl, st);
 }
 
 template <int AXIS>
@@ -700,7 +730,8 @@ msl_status check_instances(const msl_instance* inst, int n) {
 
 // Coordinate search over the launch shape for a unit of work `run` enqueues on
 // st: first the number of grid-size groups side by side (when tune_streams),
-// then the lines per workgroup of each slot in turn, every allowed value;
+// then the points per lane and lines per workgroup of each slot in turn, every
+// allowed pair;
 // each candidate runs once untimed and then `reps` times between two events.
 // The fastest setting stays in effect; on an error the previous one returns.
 template <class Run>
@@ -744,21 +775,28 @@ msl_status autotune_shapes(Run run, hipStream_t st, int reps, const int* slots, 
       g_batch_streams = best_v;
     }
     for (int q = 0; q < nslots; ++q) {
-      const int e = slots[q];
-      const int keep = g_lines_per_group[e];
-      const int current = lines_per_group(1 << e, 1 << 30);  // the shape in effect, timed already
-      int best_v = keep;
-      for (int v = 1; v <= max_lines_per_group(1 << e); v *= 2) {
-        if (v == current) continue;
-        g_lines_per_group[e] = v;
-        float t = 0.0f;
-        MSL_TRY(time_run(t));
-        if (t < t_best) {
-          t_best = t;
-          best_v = v;
+      const int e = slots[q], n = 1 << e;
+      const int keep_v = g_lines_per_group[e], keep_p = g_points_per_lane[e];
+      // the shape in effect, timed already
+      const int cur_v = lines_per_group(n, 1 << 30), cur_p = points_per_lane(n);
+      int best_v = keep_v, best_p = keep_p;
+      for (int p : {4, 8}) {
+        if (p == 8 && n < 64) continue;
+        for (int v = 1; v <= max_lines_per_group(n, p); v *= 2) {
+          if (v == cur_v && p == cur_p) continue;
+          g_points_per_lane[e] = p;
+          g_lines_per_group[e] = v;
+          float t = 0.0f;
+          MSL_TRY(time_run(t));
+          if (t < t_best) {
+            t_best = t;
+            best_v = v;
+            best_p = p;
+          }
         }
       }
       g_lines_per_group[e] = best_v;
+      g_points_per_lane[e] = best_p;
     }
     return MSL_OK;
   };
@@ -880,23 +918,35 @@ msl_status msl_workspace_status(void* workspace, size_t ws_bytes, void* hip_stre
 msl_status msl_set_tuning(const msl_tuning* t) {
   if (!t) return fail(MSL_ERR_ARG, "tuning is NULL");
   for (int e = 0; e < MSL_TUNE_SLOTS; ++e) {
+    const int p = t->points_per_lane[e];
+    const bool p_ok = p == 0 || (e >= 4 && p == 4) || (e >= 6 && p == 8);
+    if (!p_ok)
+      return fail(MSL_ERR_ARG, "points_per_lane[" + std::to_string(e) + "] = " + std::to_string(p) +
+                                   ": must be 0, 4 (lines of 16 points and more) or 8 (64 points and more)");
     const int v = t->lines_per_group[e];
     if (v == 0) continue;
-    const int hi = e >= 4 ? max_lines_per_group(1 << e) : 0;
+    const int hi = e >= 4 ? max_lines_per_group(1 << e, p > 0 ? p : default_points_per_lane(1 << e)) : 0;
     if (v < 0 || (v & (v - 1)) != 0 || v > hi)
       return fail(MSL_ERR_ARG, "lines_per_group[" + std::to_string(e) + "] = " + std::to_string(v) +
-                                   ": must be 0 or a power of two <= " + std::to_string(hi));
+                                   ": must be 0 or a power of two <= " + std::to_string(hi) +
+                                   " at that points_per_lane");
   }
   if (t->batch_streams < 0 || t->batch_streams > kBatchStreams + 1)
     return fail(MSL_ERR_ARG, "batch_streams must be in [0, " + std::to_string(kBatchStreams + 1) + "]");
-  for (int e = 0; e < MSL_TUNE_SLOTS; ++e) g_lines_per_group[e] = t->lines_per_group[e];
+  for (int e = 0; e < MSL_TUNE_SLOTS; ++e) {
+    g_lines_per_group[e] = t->lines_per_group[e];
+    g_points_per_lane[e] = t->points_per_lane[e];
+  }
   g_batch_streams = t->batch_streams;
   return MSL_OK;
 }
 
 msl_status msl_get_tuning(msl_tuning* t) {
   if (!t) return fail(MSL_ERR_ARG, "tuning is NULL");
-  for (int e = 0; e < MSL_TUNE_SLOTS; ++e) t->lines_per_group[e] = g_lines_per_group[e];
+  for (int e = 0; e < MSL_TUNE_SLOTS; ++e) {
+    t->lines_per_group[e] = g_lines_per_group[e];
+    t->points_per_lane[e] = g_points_per_lane[e];
+  }
   t->batch_streams = g_batch_streams;
   return MSL_OK;
 }

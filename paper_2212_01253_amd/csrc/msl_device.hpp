@@ -177,9 +177,8 @@ __device__ __forceinline__ void dft_p(float2 (&v)[P]) {
 // W_N^{(j mod NS) r N / (P NS)}, r = 1..P-1, for every twiddled radix-P stage
 // (sub-length NS = R0, P R0, ...).  They are loaded once per pass into
 // registers, hi and lo parts, and serve the forward and inverse transforms.
-template <int N>
+template <int N, int P = LinePts<N>::P>
 struct LineTw {
-  static constexpr int P = LinePts<N>::P;
   static constexpr int LG = ilog2c(N), LP = ilog2c(P);
   static constexpr int R0LOG = (LG % LP == 0) ? LP : (LG % LP);
   static constexpr int R0 = 1 << R0LOG;     // first stage radix (no twiddles)
@@ -188,12 +187,11 @@ struct LineTw {
   float2 lo[NST][P - 1];
 };
 
-template <int N>
-__device__ __forceinline__ void load_tw(LineTw<N>& tw, const float2* __restrict__ twh,
+template <int N, int P = LinePts<N>::P>
+__device__ __forceinline__ void load_tw(LineTw<N, P>& tw, const float2* __restrict__ twh,
                                         const float2* __restrict__ twl, int j) {
-  constexpr int P = LineTw<N>::P;
 #pragma unroll
-  for (int s = 0, NS = LineTw<N>::R0; s < LineTw<N>::NST; ++s, NS *= P) {
+  for (int s = 0, NS = LineTw<N, P>::R0; s < LineTw<N, P>::NST; ++s, NS *= P) {
     const int jm = j % NS;
     const int step = N / (P * NS);
 #pragma unroll
@@ -210,11 +208,10 @@ __device__ __forceinline__ void load_tw(LineTw<N>& tw, const float2* __restrict_
 // twiddles, then radix-P stages; every stage but the last exchanges through
 // LDS (padded one slot in eight to spread the strided writes over the
 // banks).  All threads of the block call it together (it has block barriers).
-template <int N, bool INV>
-__device__ __forceinline__ void fft_line(float2 (&v)[LinePts<N>::P], float2* sh, int j, const LineTw<N>& tw) {
-  constexpr int P = LinePts<N>::P;
-  constexpr int L = LinePts<N>::L;
-  constexpr int R0 = LineTw<N>::R0;
+template <int N, bool INV, int P = LinePts<N>::P>
+__device__ __forceinline__ void fft_line(float2 (&v)[P], float2* sh, int j, const LineTw<N, P>& tw) {
+  constexpr int L = N / P;
+  constexpr int R0 = LineTw<N, P>::R0;
   // ---- stage 0: radix R0, sub-length 1, trivial twiddles
   __syncthreads();
   if constexpr (R0 == P) {
@@ -244,7 +241,7 @@ __device__ __forceinline__ void fft_line(float2 (&v)[LinePts<N>::P], float2* sh,
   __syncthreads();
   // ---- radix-P stages with sub-length NS = R0, P R0, ...
 #pragma unroll
-  for (int s = 0, NS = R0; s < LineTw<N>::NST; ++s, NS *= P) {
+  for (int s = 0, NS = R0; s < LineTw<N, P>::NST; ++s, NS *= P) {
 #pragma unroll
     for (int t = 0; t < P; ++t) v[t] = sh[lds_pad(j + t * L)];
 #pragma unroll
@@ -358,9 +355,9 @@ struct LineAddr {
   uint32_t base, stride;
 };
 
-template <int N, int AXIS>
+template <int N, int AXIS, int P = LinePts<N>::P>
 __device__ __forceinline__ LineAddr line_at(const Ctx& c, int lay, int line, int j) {
-  constexpr uint32_t L = (uint32_t)LinePts<N>::L;
+  constexpr uint32_t L = (uint32_t)(N / P);
   const uint32_t r = AXIS == ROW ? (uint32_t)line : (uint32_t)j;
   const uint32_t col = AXIS == ROW ? (uint32_t)j : (uint32_t)line;
   const uint32_t base = lay == LAY_T ? tile_addr(c, r, col) : r * (uint32_t)c.nz + col;
@@ -393,32 +390,30 @@ __device__ __forceinline__ bool uses_pack(const Ctx& c, int slice) {
 // together at the top of the pass (one memory latency instead of one per
 // FFT stage); inputs that do not depend on the previous pass can be fetched
 // before the grid barrier that separates two passes.
-template <int N>
+template <int N, int P = LinePts<N>::P>
 struct LineIn {
-  static constexpr int P = LinePts<N>::P;
   float2 v[P];            // field
   float dl[P], bt[P];     // delta, beta of the slice
   float2 ps[P];           // psi_s (adjoint)
   float gi[P];            // far-field seed (shifted read)
   float2 hh[P], hl[P];    // propagator factor (1-D paraxial or 2-D exact)
-  LineTw<N> tw;
+  LineTw<N, P> tw;
 };
 
 __device__ __forceinline__ bool uses_h1d(const PassDesc& pd) {
   return pd.pre == PRE_PROP || pd.post == POST_PROP;
 }
 
-template <int N, int AXIS, int KIND = KIND_GENERIC, int TS = TS_RUNTIME>
-__device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, int line, int j, LineIn<N>& in) {
+template <int N, int AXIS, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P>
+__device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, int line, int j, LineIn<N, P>& in) {
   PassDesc pd = pd_;
   if constexpr (KIND != KIND_GENERIC) {
     pd.pre = PRE_PROP;
     pd.post = POST_PROP;
     pd.mid = KIND == KIND_FWD_MID ? MID_T_FWD : MID_T_ADJ;
   }
-  constexpr int L = LinePts<N>::L;
-  constexpr int P = LinePts<N>::P;
-  load_tw<N>(in.tw, AXIS == ROW ? c.twz_hi : c.twy_hi, AXIS == ROW ? c.twz_lo : c.twy_lo, j);
+  constexpr int L = N / P;
+  load_tw<N, P>(in.tw, AXIS == ROW ? c.twz_hi : c.twy_hi, AXIS == ROW ? c.twz_lo : c.twy_lo, j);
   if (uses_h1d(pd)) {
     const float2* hh = AXIS == ROW ? c.hz_hi : c.hy_hi;
     const float2* hl = AXIS == ROW ? c.hz_lo : c.hy_lo;
@@ -440,7 +435,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
       // precomputed T - 1 (real part in dl, imaginary part in bt), tiled
       const int64_t so = c.slice_index ? slice_offset(c, pd.slice) : (int64_t)(pd.slice >> 1) * c.m;
       const float2* q = c.dbT + so;
-      const LineAddr a = line_at<N, AXIS>(c, LAY_T, line, j);
+      const LineAddr a = line_at<N, AXIS, P>(c, LAY_T, line, j);
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         const float2 tm = q[a.base + (uint32_t)t * a.stride];
@@ -451,7 +446,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
       const int64_t so = slice_offset(c, pd.slice);
       const float* dp = c.delta + so;
       const float* bp = c.beta + so;
-      const LineAddr a = line_at<N, AXIS>(c, LAY_R, line, j);
+      const LineAddr a = line_at<N, AXIS, P>(c, LAY_R, line, j);
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         in.dl[t] = dp[a.base + (uint32_t)t * a.stride];
@@ -460,7 +455,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
     }
   }
   if (pd.mid == MID_T_ADJ) {
-    const LineAddr a = line_at<N, AXIS>(c, pd.load_lay, line, j);
+    const LineAddr a = line_at<N, AXIS, P>(c, pd.load_lay, line, j);
 #pragma unroll
     for (int t = 0; t < P; ++t) in.ps[t] = pd.psi_load[a.base + (uint32_t)t * a.stride];
   }
@@ -500,31 +495,26 @@ __device__ __forceinline__ void field_st(float2* p, float2 v) {
   }
 }
 
-template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC>
-__device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N>& in) {
-  constexpr int L = LinePts<N>::L;
-  constexpr int P = LinePts<N>::P;
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int P = LinePts<N>::P>
+__device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int line, int j, LineIn<N, P>& in) {
   const int lay = KIND != KIND_GENERIC ? (int)LAY_T : pd.src_lay;  // the specialised kinds work on tiled fields
-  const LineAddr a = line_at<N, AXIS>(c, lay, line, j);
+  const LineAddr a = line_at<N, AXIS, P>(c, lay, line, j);
 #pragma unroll
   for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + a.base + (uint32_t)t * a.stride);
 }
 
-template <int N>
-__device__ __forceinline__ void prop_line(float2 (&v)[LinePts<N>::P], float2* sh, int j, const LineIn<N>& in,
-                                          bool conj) {
-  constexpr int P = LinePts<N>::P;
-  fft_line<N, false>(v, sh, j, in.tw);
+template <int N, int P = LinePts<N>::P>
+__device__ __forceinline__ void prop_line(float2 (&v)[P], float2* sh, int j, const LineIn<N, P>& in, bool conj) {
+  fft_line<N, false, P>(v, sh, j, in.tw);
 #pragma unroll
   for (int t = 0; t < P; ++t) v[t] = cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj);
-  fft_line<N, true>(v, sh, j, in.tw);
+  fft_line<N, true, P>(v, sh, j, in.tw);
 }
 
-template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME>
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P>
 __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, int line, int j, float2* sh,
-                                             LineIn<N>& in) {
-  constexpr int L = LinePts<N>::L;
-  constexpr int P = LinePts<N>::P;
+                                             LineIn<N, P>& in) {
+  constexpr int L = N / P;
   const float inv_n = 1.0f / (float)N;
   float2 (&v)[P] = in.v;
   PassDesc pd = pd_;
@@ -538,19 +528,19 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   switch (pd.pre) {
-    case PRE_PROP: prop_line<N>(v, sh, j, in, pd.conj != 0); break;
-    case PRE_FFT: fft_line<N, false>(v, sh, j, in.tw); break;
+    case PRE_PROP: prop_line<N, P>(v, sh, j, in, pd.conj != 0); break;
+    case PRE_FFT: fft_line<N, false, P>(v, sh, j, in.tw); break;
     case PRE_IFFT_N:
-      fft_line<N, true>(v, sh, j, in.tw);
+      fft_line<N, true, P>(v, sh, j, in.tw);
 #pragma unroll
       for (int t = 0; t < P; ++t) v[t] = make_float2(v[t].x * inv_n, v[t].y * inv_n);
       break;
-    case PRE_IFFT_U: fft_line<N, true>(v, sh, j, in.tw); break;
+    case PRE_IFFT_U: fft_line<N, true, P>(v, sh, j, in.tw); break;
     default: break;
   }
 
   if (pd.psi_store) {
-    const LineAddr a = line_at<N, AXIS>(c, pd.store_lay, line, j);
+    const LineAddr a = line_at<N, AXIS, P>(c, pd.store_lay, line, j);
 #pragma unroll
     for (int t = 0; t < P; ++t) pd.psi_store[a.base + (uint32_t)t * a.stride] = v[t];
   }
@@ -574,8 +564,8 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
     float* const gbp = c.gbeta ? c.gbeta + so : nullptr;
     float2* const gtp = c.gT ? c.gT + (int64_t)(pd.slice >> 1) * c.m : nullptr;
     const float kdx = c.kdx_hi;
-    const LineAddr ar = line_at<N, AXIS>(c, LAY_R, line, j);
-    const LineAddr at = line_at<N, AXIS>(c, LAY_T, line, j);
+    const LineAddr ar = line_at<N, AXIS, P>(c, LAY_R, line, j);
+    const LineAddr at = line_at<N, AXIS, P>(c, LAY_T, line, j);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       const uint32_t e = ar.base + (uint32_t)t * ar.stride;
@@ -610,32 +600,32 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   switch (pd.post) {
-    case POST_PROP: prop_line<N>(v, sh, j, in, pd.conj != 0); break;
-    case POST_FFT: fft_line<N, false>(v, sh, j, in.tw); break;
-    case POST_PROP2D: prop_line<N>(v, sh, j, in, pd.conj != 0); break;  // H[ky][kz] / ny loaded in hh, hl
+    case POST_PROP: prop_line<N, P>(v, sh, j, in, pd.conj != 0); break;
+    case POST_FFT: fft_line<N, false, P>(v, sh, j, in.tw); break;
+    case POST_PROP2D: prop_line<N, P>(v, sh, j, in, pd.conj != 0); break;  // H[ky][kz] / ny loaded in hh, hl
     default: break;
   }
 
   if (pd.dst) {
-    const LineAddr a = line_at<N, AXIS>(c, pd.dst_lay, line, j);
+    const LineAddr a = line_at<N, AXIS, P>(c, pd.dst_lay, line, j);
 #pragma unroll
     for (int t = 0; t < P; ++t) field_st<COH>(pd.dst + a.base + (uint32_t)t * a.stride, v[t]);
   }
 }
 
-template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME>
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P>
 __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
-  LineIn<N> in;
-  load_field<N, AXIS, COH, KIND>(c, pd, line, j, in);
-  load_static<N, AXIS, KIND, TS>(c, pd, line, j, in);
-  compute_line<N, AXIS, COH, KIND, TS>(c, pd, line, j, sh, in);
+  LineIn<N, P> in;
+  load_field<N, AXIS, COH, KIND, P>(c, pd, line, j, in);
+  load_static<N, AXIS, KIND, TS, P>(c, pd, line, j, in);
+  compute_line<N, AXIS, COH, KIND, TS, P>(c, pd, line, j, sh, in);
 }
 
 // Either axis, chosen per pass at run time (square grids: both line lengths are N).
-template <int N, bool COH = false>
+template <int N, bool COH = false, int P = LinePts<N>::P>
 __device__ __forceinline__ void run_line_any(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
-  if (pd.axis == ROW) run_line<N, ROW, COH>(c, pd, line, j, sh);
-  else run_line<N, COL, COH>(c, pd, line, j, sh);
+  if (pd.axis == ROW) run_line<N, ROW, COH, KIND_GENERIC, TS_RUNTIME, P>(c, pd, line, j, sh);
+  else run_line<N, COL, COH, KIND_GENERIC, TS_RUNTIME, P>(c, pd, line, j, sh);
 }
 
 // Workgroups are dealt to the XCDs round robin; give each XCD a contiguous

@@ -33,7 +33,7 @@ TUNE_SLOTS = 11  # MSL_TUNE_SLOTS
 class CTuning(ctypes.Structure):
     """Mirror of msl_tuning."""
 
-    _fields_ = [("lines_per_group", c_int32 * 11), ("batch_streams", c_int32)]
+    _fields_ = [("lines_per_group", c_int32 * 11), ("points_per_lane", c_int32 * 11), ("batch_streams", c_int32)]
 
 
 class CGeometry(ctypes.Structure):
@@ -217,27 +217,40 @@ def set_barrier_spin_limit(polls: int) -> int:
 
 def _tuning_dict(t):
     return {"lines_per_group": {1 << e: int(t.lines_per_group[e]) for e in range(4, TUNE_SLOTS)},
+            "points_per_lane": {1 << e: int(t.points_per_lane[e]) for e in range(4, TUNE_SLOTS)},
             "batch_streams": int(t.batch_streams)}
 
 
 def get_tuning() -> dict:
-    """msl_get_tuning: {"lines_per_group": {line length: value (0 = default)}, "batch_streams": n}."""
+    """msl_get_tuning: {"lines_per_group": {line length: value (0 = default)},
+    "points_per_lane": {line length: 4, 8 or 0 = default}, "batch_streams": n}."""
     t = CTuning()
     _check(lib().msl_get_tuning(ctypes.byref(t)))
     return _tuning_dict(t)
 
 
-def set_tuning(lines_per_group=None, batch_streams=0):
-    """msl_set_tuning; lines_per_group maps line lengths (16 .. 1024) to values."""
+def _slot(n):
+    n = int(n)
+    e = n.bit_length() - 1
+    if n < 1 or (1 << e) != n or e >= TUNE_SLOTS:
+        raise ValueError(f"line length {n} is not a power of two below 2^{TUNE_SLOTS}")
+    return e
+
+
+def set_tuning(lines_per_group=None, batch_streams=0, points_per_lane=None):
+    """msl_set_tuning; lines_per_group and points_per_lane map line lengths (16 .. 1024) to values."""
     t = CTuning()
     for n, v in (lines_per_group or {}).items():
-        n = int(n)
-        e = n.bit_length() - 1
-        if n < 1 or (1 << e) != n or e >= TUNE_SLOTS:
-            raise ValueError(f"line length {n} is not a power of two below 2^{TUNE_SLOTS}")
-        t.lines_per_group[e] = int(v)
+        t.lines_per_group[_slot(n)] = int(v)
+    for n, v in (points_per_lane or {}).items():
+        t.points_per_lane[_slot(n)] = int(v)
     t.batch_streams = int(batch_streams)
     _check(lib().msl_set_tuning(ctypes.byref(t)))
+
+
+def restore_tuning(t: dict):
+    """Apply a dict get_tuning returned."""
+    set_tuning(t["lines_per_group"], t["batch_streams"], t["points_per_lane"])
 
 
 def autotune_forward(g, delta, beta, ws=None, reps=3, scratch=None):

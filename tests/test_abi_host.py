@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert msl.abi_version() == 3
+    assert msl.abi_version() == 4
 
 
 def G(**kw):
@@ -249,18 +249,28 @@ def test_shrinkwrap_validates(L):
 def test_tuning_validates_and_round_trips(L):
     before = msl.get_tuning()
     try:
-        msl.set_tuning({512: 2, 256: 4, 128: 1, 16: 64}, batch_streams=2)
+        msl.set_tuning({512: 2, 256: 4, 128: 1, 16: 64}, batch_streams=2, points_per_lane={512: 4, 64: 8})
         t = msl.get_tuning()
         assert t["lines_per_group"][512] == 2 and t["lines_per_group"][256] == 4
         assert t["lines_per_group"][128] == 1 and t["lines_per_group"][16] == 64
         assert t["lines_per_group"][1024] == 0 and t["batch_streams"] == 2
-        bad = [({512: 3}, 0), ({512: 8}, 0), ({1024: 4}, 0), ({256: -1}, 0), ({8: 1}, 0), ({}, 5), ({}, -1)]
-        for lpg, bs in bad:
+        assert t["points_per_lane"][512] == 4 and t["points_per_lane"][64] == 8 and t["points_per_lane"][256] == 0
+        # group limits at 8 points per lane: 64: 16, 128: 8, 256: 4, 512: 4, 1024: 2;
+        # at 4: 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2, 1024: 1
+        msl.set_tuning({512: 4, 1024: 2, 64: 16})
+        msl.set_tuning({512: 2, 1024: 1, 16: 64, 32: 32}, points_per_lane={512: 4, 1024: 4, 16: 4, 32: 4})
+        msl.set_tuning({256: 4, 128: 8}, points_per_lane={256: 8, 128: 8})
+        msl.restore_tuning(t)
+        bad = [({512: 3}, 0, {}), ({512: 8}, 0, {}), ({1024: 4}, 0, {}), ({256: -1}, 0, {}), ({8: 1}, 0, {}),
+               ({}, 5, {}), ({}, -1, {}),
+               ({}, 0, {512: 2}), ({}, 0, {512: 16}), ({}, 0, {32: 8}), ({}, 0, {16: 8}), ({}, 0, {8: 4}),
+               ({}, 0, {256: -4}), ({512: 4}, 0, {512: 4}), ({1024: 2}, 0, {1024: 4}), ({64: 32}, 0, {64: 8})]
+        for lpg, bs, ppl in bad:
             with pytest.raises(msl.MslError):
-                msl.set_tuning(lpg, batch_streams=bs)
+                msl.set_tuning(lpg, batch_streams=bs, points_per_lane=ppl)
             assert msl.get_tuning() == t      # nothing changes on an error
     finally:
-        msl.set_tuning({n: v for n, v in before["lines_per_group"].items()}, before["batch_streams"])
+        msl.restore_tuning(before)
     assert msl.get_tuning() == before
 
 

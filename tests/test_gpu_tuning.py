@@ -1,18 +1,33 @@
 """GPU checks of the launch-shape settings and their autotuner.
 
 The number of lines a workgroup handles changes only how lines are dealt to
-the hardware, never the arithmetic of a line, so every allowed shape must give
-bit-identical fields; the same holds for how many grid-size groups of a batch
-run side by side.
+the hardware, never the arithmetic of a line, so at one points-per-lane
+setting every allowed number of lines per workgroup must give bit-identical
+fields; the same holds for how many grid-size groups of a batch run side by
+side.  The points per lane (radix-4 or radix-8 FFT stages) change the order
+of the float32 operations: each setting is held to the FP64 oracle by the
+parity gates.
 """
 import numpy as np
 import pytest
 
+from oracle import msl_oracle as O
 from paper_2212_01253_amd import synth
+from parity_gates import check_field, check_forward
 
 pytestmark = pytest.mark.gpu
 
-LIMIT = {16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2, 1024: 1}
+
+def limit(n, p):
+    """Largest lines per workgroup: 256 threads and four 512-point line buffers of LDS."""
+    lanes, lds, slots, g = n // p, n + n // 8 + 1, 4 * (512 + 64 + 1), 1
+    while 2 * g * lanes <= 256 and 2 * g * lds <= slots:
+        g *= 2
+    return g
+
+
+def radices(n):
+    return (4, 8) if n >= 64 else (4,)
 
 
 @pytest.fixture(scope="module")
@@ -24,7 +39,7 @@ def M():
     msl.lib()
     before = msl.get_tuning()
     yield msl
-    msl.set_tuning(before["lines_per_group"], before["batch_streams"])
+    msl.restore_tuning(before)
 
 
 def dev(x):
@@ -34,8 +49,8 @@ def dev(x):
 
 def stack(ny, nz, ns, seed):
     g = synth.Geometry(ny, nz, ns, 1.0, 1.0, 5.0, 0.1, np.radians(0.3), 0)
-    d, b = synth.random_stack(ny, nz, ns, seed)
-    return g, dev(d), dev(b)
+    d, b = synth.random_stack(ny, nz, ns, seed, 3e-5, 2e-6)
+    return g, d, b
 
 
 def fwd(M, g, d, b):
@@ -45,93 +60,117 @@ def fwd(M, g, d, b):
     return f.cpu().numpy()
 
 
-@pytest.mark.parametrize("ny,nz,ns", [(512, 512, 9), (256, 256, 12), (128, 128, 20), (64, 128, 15), (32, 16, 7)])
+@pytest.mark.parametrize("ny,nz,ns", [(512, 512, 9), (256, 256, 12), (128, 128, 20), (64, 128, 15), (32, 16, 7),
+                                      (1024, 64, 5)])
 def test_every_shape_gives_identical_fields(M, ny, nz, ns):
-    g, d, b = stack(ny, nz, ns, 11)
-    M.set_tuning({})
-    ref = fwd(M, g, d, b)
-    for n in sorted({ny, nz}):
-        v = 1
-        while v <= LIMIT[n]:
-            M.set_tuning({n: v})
-            got = fwd(M, g, d, b)
-            print(ny, nz, n, v)
-            assert np.array_equal(got, ref), (ny, nz, n, v)
-            v *= 2
+    g, dn, bn = stack(ny, nz, ns, 11)
+    d, b = dev(dn), dev(bn)
+    rf = O.forward(g, dn, bn)
+    lens = sorted({ny, nz})
+    for p in (4, 8):
+        ppl = {n: p for n in lens if p in radices(n)}
+        M.set_tuning({}, points_per_lane=ppl)
+        ref = fwd(M, g, d, b)
+        e, r = check_field(ref, rf, what=f"points per lane {ppl}")
+        print(ny, nz, ppl, f"field {e:.2e} gates {r:.2f}")
+        for n in lens:
+            pn = ppl.get(n, 4 if n < 512 else 8)
+            v = 1
+            while v <= limit(n, pn):
+                M.set_tuning({n: v}, points_per_lane=ppl)
+                got = fwd(M, g, d, b)
+                assert np.array_equal(got, ref), (ny, nz, n, v, ppl)
+                v *= 2
     M.set_tuning({})
 
 
-def test_batch_streams_and_shapes_give_identical_fields(M):
+def batch_items(M, specs, seed0):
     import torch
-    specs = [(64, 64, 30), (128, 128, 17), (32, 32, 9), (128, 128, 5), (256, 256, 8)]
     items = []
     for i, (ny, nz, ns) in enumerate(specs):
         g = synth.Geometry(ny, nz, ns, 1.0, 1.0, 5.0, 0.1, np.radians(0.2), 0)
-        cs = synth.compact_bars_on_substrate(g, 300 + i, substrate_rows=ny // 4, n_bars=(2, 5),
+        cs = synth.compact_bars_on_substrate(g, seed0 + i, substrate_rows=ny // 4, n_bars=(2, 5),
                                              bar_height=(1, ny // 8), bar_width=(1, nz // 4),
                                              bar_len_frac=(0.125, 1.0), n_lines=(1, 2),
                                              delta_range=(5e-6, 3e-5), beta_over_delta=0.05)
-        items.append({"geom": g, "pool_delta": dev(cs.pool_delta), "pool_beta": dev(cs.pool_beta),
+        items.append({"geom": g, "cs": cs, "pool_delta": dev(cs.pool_delta), "pool_beta": dev(cs.pool_beta),
                       "slice_index": dev(cs.index.astype(np.int32)), "probe": None,
                       "field": torch.empty((ny, nz), dtype=torch.complex64, device="cuda"),
                       "intensity": torch.empty((ny, nz), dtype=torch.float32, device="cuda")})
+    return items
 
-    def run():
-        M.forward_batch(items)
-        torch.cuda.synchronize()
-        return [(it["field"].cpu().numpy(), it["intensity"].cpu().numpy()) for it in items]
 
+def run_batch(M, items):
+    import torch
+    M.forward_batch(items)
+    torch.cuda.synchronize()
+    return [(it["field"].cpu().numpy(), it["intensity"].cpu().numpy()) for it in items]
+
+
+def oracle_batch(items):
+    out = []
+    for it in items:
+        d, b = it["cs"].dense()
+        g = it["geom"]
+        rf = O.forward(g, d, b)
+        out.append((rf, O.far_field(g, rf)))
+    return out
+
+
+def test_batch_streams_and_shapes_give_identical_fields(M):
+    items = batch_items(M, [(64, 64, 30), (128, 128, 17), (32, 32, 9), (128, 128, 5), (256, 256, 8)], 300)
     M.set_tuning({})
-    ref = run()
+    ref = run_batch(M, items)
     for lpg, bs in [({}, 1), ({}, 2), ({128: 8, 256: 1}, 4), ({64: 2, 32: 32, 256: 4}, 3)]:
         M.set_tuning(lpg, bs)
-        got = run()
+        got = run_batch(M, items)
         for (f, I), (rf, rI) in zip(got, ref):
             assert np.array_equal(f, rf) and np.array_equal(I, rI), (lpg, bs)
+    # the other radix on every length that has one: within the parity gates, and again
+    # bit-identical over the group shapes
+    ppl = {64: 8, 128: 8, 256: 8}
+    M.set_tuning({}, 0, ppl)
+    ref8 = run_batch(M, items)
+    for (f, I), (rf, rI) in zip(ref8, oracle_batch(items)):
+        check_forward(f, rf, I, rI, what="points per lane 8")
+    M.set_tuning({64: 16, 128: 2, 256: 4}, 2, ppl)
+    for (f, I), (rf, rI) in zip(run_batch(M, items), ref8):
+        assert np.array_equal(f, rf) and np.array_equal(I, rI)
     M.set_tuning({})
 
 
 def test_batch_autotune_picks_allowed_settings_and_keeps_results(M):
-    import torch
-    specs = [(64, 64, 30), (128, 128, 17), (32, 32, 9), (256, 256, 8)]
-    items = []
-    for i, (ny, nz, ns) in enumerate(specs):
-        g = synth.Geometry(ny, nz, ns, 1.0, 1.0, 5.0, 0.1, np.radians(0.2), 0)
-        cs = synth.compact_bars_on_substrate(g, 400 + i, substrate_rows=ny // 4, n_bars=(2, 5),
-                                             bar_height=(1, ny // 8), bar_width=(1, nz // 4),
-                                             bar_len_frac=(0.125, 1.0), n_lines=(1, 2),
-                                             delta_range=(5e-6, 3e-5), beta_over_delta=0.05)
-        items.append({"geom": g, "pool_delta": dev(cs.pool_delta), "pool_beta": dev(cs.pool_beta),
-                      "slice_index": dev(cs.index.astype(np.int32)), "probe": None,
-                      "field": torch.empty((ny, nz), dtype=torch.complex64, device="cuda"),
-                      "intensity": torch.empty((ny, nz), dtype=torch.float32, device="cuda")})
+    items = batch_items(M, [(64, 64, 30), (128, 128, 17), (32, 32, 9), (256, 256, 8)], 400)
     M.set_tuning({})
-    M.forward_batch(items)
-    torch.cuda.synchronize()
-    ref = [(it["field"].cpu().numpy(), it["intensity"].cpu().numpy()) for it in items]
     t, ms = M.autotune_batch(items, reps=1)
     print(t, ms)
     assert ms > 0 and 0 <= t["batch_streams"] <= 4
     for n in (32, 64, 128, 256):
+        p = t["points_per_lane"][n]
+        assert p == 0 or p in radices(n)
         v = t["lines_per_group"][n]
-        assert v == 0 or (v & (v - 1) == 0 and 1 <= v <= LIMIT[n])
+        assert v == 0 or (v & (v - 1) == 0 and 1 <= v <= limit(n, p or 4))
     assert M.get_tuning() == t
-    M.forward_batch(items)
-    torch.cuda.synchronize()
-    for it, (rf, rI) in zip(items, ref):
-        assert np.array_equal(it["field"].cpu().numpy(), rf) and np.array_equal(it["intensity"].cpu().numpy(), rI)
+    for (f, I), (rf, rI) in zip(run_batch(M, items), oracle_batch(items)):
+        check_forward(f, rf, I, rI, what=f"autotuned {t}")
     M.set_tuning({})
 
 
 def test_autotune_picks_an_allowed_shape_and_keeps_results(M):
-    g, d, b = stack(256, 256, 64, 5)
+    g, dn, bn = stack(256, 256, 64, 5)
+    d, b = dev(dn), dev(bn)
     M.set_tuning({})
     ref = fwd(M, g, d, b)
     t, ms = M.autotune_forward(g, d, b, reps=2)
     print(t, ms)
     assert ms > 0
+    p = t["points_per_lane"][256]
+    assert p in (0, 4, 8)
     v = t["lines_per_group"][256]
-    assert v == 0 or (v & (v - 1) == 0 and 1 <= v <= LIMIT[256])
+    assert v == 0 or (v & (v - 1) == 0 and 1 <= v <= limit(256, p or 4))
     assert M.get_tuning() == t
-    assert np.array_equal(fwd(M, g, d, b), ref)
+    got = fwd(M, g, d, b)
+    if p in (0, 4):
+        assert np.array_equal(got, ref)
+    check_field(got, O.forward(g, dn, bn), what=f"autotuned {t}")
     M.set_tuning({})
