@@ -1,8 +1,8 @@
 """Benchmark: multislice forward + adjoint (one gradient evaluation) on one MI355X.
 
 One step = the whole hot path over the 512 x 512 x 2048 bars-on-substrate
-workload (5 nm slices, 0.1 nm wavelength): slice pack (odd slices'
-transmissions, transposed), forward sweep with checkpoints every 32 slices,
+workload (5 nm slices, 0.1 nm wavelength): slice pack (every slice's
+transmission T - 1, tiled), forward sweep with checkpoints every 32 slices,
 far-field intensity, amplitude loss and its derivative, far-field adjoint,
 and the checkpointed adjoint sweep producing dL/d delta, dL/d beta and
 dL/d probe.  Inputs are resident in HBM before timing starts.

@@ -135,8 +135,9 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
  * work, but its tables (FFT twiddles, propagator) live in a fixed device array
  * of MSL_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
  * process ends; the call allocates and frees nothing.  It builds no slice
- * pack: the odd slices' column passes evaluate their transmission from
- * delta and beta directly (the same arithmetic, slower memory access).
+ * pack: every pass evaluates its transmission from delta and beta directly
+ * (the same arithmetic; more work per pass, and strided reads in the column
+ * passes).
  * Limits: the exact propagator's table must fit, i.e. ny * nz <= 512 * 512
  * with MSL_PROP_EXACT (any valid paraxial geometry fits); a larger request
  * returns MSL_ERR_UNSUPPORTED before anything is enqueued.  All calls on one
@@ -177,13 +178,13 @@ msl_status msl_far_field_adjoint(const msl_geometry* g, const msl_c64* field,
  * call skips rebuilding it.  Without the flag every call rebuilds it. */
 #define MSL_REUSE_SLICE_PACK 1u
 
-/* Slice pack: with the paraxial propagator the odd slices are transmitted in
- * column passes, which read the transmission T - 1 = exp(i k dx (delta +
- * i beta)) - 1 of those slices precomputed and transposed ([Ns/2][nz][ny]
- * complex64, in the workspace) so that their accesses coalesce.  This call
- * writes it (a no-op for the exact propagator, which needs none).  It
- * depends on delta, beta, the wavelength and dx, not on the incidence angle
- * or the probe. */
+/* Slice pack: with the paraxial propagator every line pass that transmits
+ * reads the transmission T - 1 = exp(i k dx (delta + i beta)) - 1 of its
+ * slice precomputed ([Ns][ny][nz] complex64 in 2x2 tiles of 32 bytes, in the
+ * workspace): the pass then spends no arithmetic on it, and row and column
+ * passes alike read whole tiles.  This call writes it (a no-op for the exact
+ * propagator, which needs none).  It depends on delta, beta, the wavelength
+ * and dx, not on the incidence angle or the probe. */
 msl_status msl_pack_slices(const msl_geometry* g, const float* delta, const float* beta,
                            void* workspace, size_t ws_bytes, void* hip_stream);
 

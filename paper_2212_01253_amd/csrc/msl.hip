@@ -70,9 +70,9 @@ Layout layout(const msl_geometry& g, int k) {
   L.H_lo = take(exact ? m * 8 : 0);
   L.partials = take(kPartials * sizeof(double));
   L.tmp = take(m * 8);  // tiled working field of the forward, the far field and its adjoint
-  // paraxial: the odd slices' transmissions T - 1, tiled, for the column passes
+  // paraxial: every slice's transmission T - 1, tiled (the slice pack)
   const size_t odd = exact ? 0 : (size_t)(g.n_slices / 2);
-  L.dbT = take(odd * m * 8);
+  L.dbT = take((exact ? 0 : (size_t)g.n_slices) * m * 8);
   if (k >= 1) {
     L.W = take(m * 8);  // tiled working field of the segment recompute
     L.G = take(m * 8);  // tiled working field of the reverse sweep (the cotangent)
@@ -303,14 +303,13 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 // Thread t of a workgroup of G lines works on line t mod G at lane t / G:
 // neighbouring threads take neighbouring lines, so each load and store of a
 // wavefront covers whole 2x2 tiles of the tiled working fields.
-// The specialised middle passes take the transmission of a row pass (even
-// slice) from the caller's stack and that of a column pass (odd slice) from the
-// slice pack, which launch_pass_t makes sure exists.
+// The specialised middle passes take the transmission from the slice pack,
+// which launch_pass_tp makes sure exists.
 template <int N, int P, int AXIS, int KIND>
 __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   __shared__ float2 lds[kLdsSlots];
   constexpr int L = N / P;
-  constexpr int TS = KIND == msl::KIND_GENERIC ? msl::TS_RUNTIME : (AXIS == msl::COL ? msl::TS_PACK : msl::TS_STACK);
+  constexpr int TS = KIND == msl::KIND_GENERIC ? msl::TS_RUNTIME : msl::TS_PACK;
   const int G = blockDim.x / L;
   const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
@@ -357,10 +356,7 @@ hipError_t launch_pass_tp(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const int G = lines_per_group(N, nlines);
   const dim3 grid(nlines / G), block(L * G);
   int kind = msl::pass_kind(pd);
-  // the specialised kinds' transmission source (see k_pass): row passes of even slices from the
-  // stack (no batch pool index), column passes of odd slices from the pack
-  const bool ts_ok = AXIS == msl::ROW ? (!c.slice_index && (pd.slice & 1) == 0) : (c.dbT && (pd.slice & 1));
-  if (!ts_ok) kind = msl::KIND_GENERIC;
+  if (!c.dbT) kind = msl::KIND_GENERIC;  // the specialised kinds read the slice pack
   switch (kind) {
     case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_FWD_MID>), grid, block, 0, st, c, pd); break;
     case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_REV_MID>), grid, block, 0, st, c, pd); break;
@@ -559,18 +555,13 @@ int odd_slices(const msl_geometry& g) { return g.propagator == MSL_PROP_PARAXIAL
 int odd_begin(int s0) { return s0 >> 1; }
 int odd_end(int s1) { return s1 >> 1; }
 
-// Packs odd slices 2 s2 + 1, s2 in [s2b, s2e), into dbT on stream st.
-msl_status pack_odd_range(const Call& k, int s2b, int s2e, hipStream_t st) {
-  if (s2e <= s2b) return MSL_OK;
+// Packs every slice into dbT (paraxial only: the exact schedule needs no pack).
+msl_status pack_slices(Call& k) {
+  if (k.g.propagator != MSL_PROP_PARAXIAL) return MSL_OK;
   float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
-  return hip_check(launch_pack(k.c.delta, k.c.beta, dbT, k.g.ny, k.g.nz, s2b, s2e, 1, 2, k.c, st), "pack kernel");
-}
-
-msl_status pack_odd(Call& k) {
-  const int nodd = odd_slices(k.g);
-  if (nodd == 0) return MSL_OK;
-  MSL_TRY(pack_odd_range(k, 0, nodd, k.st));
-  k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
+  MSL_TRY(hip_check(launch_pack(k.c.delta, k.c.beta, dbT, k.g.ny, k.g.nz, 0, k.g.n_slices, 0, 1, k.c, k.st),
+                    "pack kernel"));
+  k.c.dbT = dbT;
   return MSL_OK;
 }
 
@@ -998,7 +989,7 @@ msl_status msl_pack_slices(const msl_geometry* g, const float* delta, const floa
   Call k = make_call(*g, 0, workspace, static_cast<hipStream_t>(hip_stream));
   k.c.delta = delta;
   k.c.beta = beta;
-  return pack_odd(k);
+  return pack_slices(k);
 }
 
 msl_status msl_forward(const msl_geometry* g, const float* delta, const float* beta, const msl_c64* probe,
@@ -1038,9 +1029,9 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
   ph.ckpt = reinterpret_cast<float2*>(ckpt);
   ph.ckpt_every = ckpt ? ckpt_every : 0;
   if (flags & MSL_REUSE_SLICE_PACK) {
-    if (odd_slices(*g) > 0) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
+    if (g->propagator == MSL_PROP_PARAXIAL) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
   } else {
-    MSL_TRY(pack_odd(k));
+    MSL_TRY(pack_slices(k));
   }
   return run_phase(k, ph);
 }
@@ -1170,9 +1161,9 @@ msl_status msl_adjoint(const msl_geometry* g, const float* delta, const float* b
   MSL_TRY(clear_status(k));
   MSL_TRY(build_tables(k, true));
   if (flags & MSL_REUSE_SLICE_PACK) {
-    if (odd_slices(*g) > 0) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
+    if (g->propagator == MSL_PROP_PARAXIAL) k.c.dbT = reinterpret_cast<const float2*>(k.ws + k.L.dbT);
   } else {
-    MSL_TRY(pack_odd(k));
+    MSL_TRY(pack_slices(k));
   }
   const int nodd = odd_slices(*g);
   if (nodd > 0 && (grad_delta || grad_beta)) k.c.gT = reinterpret_cast<float2*>(k.ws + k.L.gT);

@@ -59,17 +59,18 @@ struct Ctx {
   float inv_m;                      // 1 / (ny nz)
   float* intensity;                 // far-field output (fftshifted) or nullptr
   const float* grad_intensity;      // far-field seed input (fftshifted) or nullptr
-  // Odd slices are always transmitted in column passes (paraxial schedule).
-  // For them the workspace may hold T - 1 precomputed, [Ns/2] tiled fields
-  // (float2), and a staging area for their (dL/d delta, dL/d beta) in the
-  // same layout, so column passes access both in whole 32-byte tiles instead
-  // of striding through the caller's row-major stacks.
+  // Paraxial schedule: the workspace may hold T - 1 of every slice
+  // precomputed, [Ns] tiled fields (float2), so that line passes of either
+  // axis read 32-byte tiles and spend no arithmetic on the transmission.  Odd
+  // slices are transmitted in column passes; gT stages their (dL/d delta,
+  // dL/d beta), [Ns/2] tiled fields, so those passes write whole tiles
+  // instead of striding through the caller's row-major gradient stacks.
   const float2* dbT;                // or nullptr
   float2* gT;                       // or nullptr
   // Compact stacks (batched forward): delta, beta and dbT hold a pool of
   // n_pool distinct slices and slice s is pool slice slice_index[s] (device
   // array, values clamped to the pool); dbT then holds T - 1 of every pool
-  // slice and every pass reads it.  nullptr: slice s is stack slice s.
+  // slice.  nullptr: slice s is stack slice s.
   const int32_t* slice_index;
   int32_t n_pool;
 };
@@ -371,19 +372,17 @@ __device__ __forceinline__ LineAddr line_at(const Ctx& c, int lay, int line, int
 template <int N>
 constexpr int line_lds() { return N + N / 8 + 1; }
 
-// Where a pass takes the transmission T - 1 of its slice from: decided per
-// pass at run time, or fixed at compile time for kernels that serve only one
-// case (the slice pack: the paraxial column passes and the batched passes; the
-// caller's stack: the paraxial row passes), which then carry no code for the
-// other.
-enum TSource : int { TS_RUNTIME = 0, TS_PACK = 1, TS_STACK = 2 };
+// Where a pass takes the transmission T - 1 of its slice from: the slice pack
+// when the caller built one, else the caller's delta and beta stacks (decided
+// at run time), or fixed to the pack at compile time for kernels that serve
+// only passes with a pack (the paraxial and batched middle passes), which then
+// carry no code for evaluating it.
+enum TSource : int { TS_RUNTIME = 0, TS_PACK = 1 };
 
-// Whether slice `slice` reads its precomputed T - 1 (the slice pack).
 template <int TS = TS_RUNTIME>
-__device__ __forceinline__ bool uses_pack(const Ctx& c, int slice) {
+__device__ __forceinline__ bool uses_pack(const Ctx& c) {
   if constexpr (TS == TS_PACK) return true;
-  if constexpr (TS == TS_STACK) return false;
-  return c.dbT && (c.slice_index || (slice & 1));
+  return c.dbT != nullptr;
 }
 
 // Everything a line pass reads, gathered in registers.  Loads are issued
@@ -431,10 +430,9 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
     }
   }
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
-    if (uses_pack<TS>(c, pd.slice)) {
+    if (uses_pack<TS>(c)) {
       // precomputed T - 1 (real part in dl, imaginary part in bt), tiled
-      const int64_t so = c.slice_index ? slice_offset(c, pd.slice) : (int64_t)(pd.slice >> 1) * c.m;
-      const float2* q = c.dbT + so;
+      const float2* q = c.dbT + slice_offset(c, pd.slice);
       const LineAddr a = line_at<N, AXIS, P>(c, LAY_T, line, j);
 #pragma unroll
       for (int t = 0; t < P; ++t) {
@@ -547,7 +545,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 
   float2 tm1[P];  // T - 1 of the slice at this line's points
   if (pd.mid == MID_T_FWD || pd.mid == MID_T_ADJ) {
-    if (uses_pack<TS>(c, pd.slice)) {
+    if (uses_pack<TS>(c)) {
 #pragma unroll
       for (int t = 0; t < P; ++t) tm1[t] = make_float2(in.dl[t], in.bt[t]);
     } else {

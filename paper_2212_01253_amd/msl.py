@@ -292,7 +292,7 @@ def workspace(g, ckpt_every=0, device="cuda"):
 
 
 def pack_slices(g, delta, beta, ws):
-    """msl_pack_slices: writes the odd slices' transmission pack into ``ws``."""
+    """msl_pack_slices: writes every slice's transmission T - 1 (the slice pack) into ``ws``."""
     cg = geometry(g)
     ny, nz, ns = cg.ny, cg.nz, cg.n_slices
     _check(lib().msl_pack_slices(ctypes.byref(cg), _ptr(delta, torch.float32, (ns, ny, nz), "delta"),
