@@ -234,9 +234,10 @@ int32_t msl_set_barrier_spin_limit(int32_t polls);
  * Entry e of lines_per_group is the number of 2^e-point lines per workgroup
  * (e = 4..10; 0 = the library default: one 64-lane wavefront's worth of
  * lanes and at least two lines; other entries must be 0).  Allowed values are
- * powers of two up to the limit set by the 256-thread workgroup and the
- * workgroup's line buffers in LDS: at 8 points per lane
- * 2^e = 64: 16, 128: 8, 256: 4, 512: 4, 1024: 2; at 4 points per lane
+ * powers of two up to the limit set by the 256-thread workgroup (the
+ * workgroup's LDS exchange buffers stay within 64 KiB at every allowed
+ * value): at 8 points per lane
+ * 2^e = 64: 32, 128: 16, 256: 8, 512: 4, 1024: 2; at 4 points per lane
  * 2^e = 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2, 1024: 1.
  * The lines per workgroup only deal lines to the hardware: at one P every
  * allowed value gives bit-identical results.

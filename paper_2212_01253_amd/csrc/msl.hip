@@ -35,7 +35,15 @@ int g_batch_streams = 0;  // 0: default (every extra stream)
 // Polls of the persistent schedule's bounded barrier wait (msl_set_barrier_spin_limit).
 unsigned g_spin_limit = msl::kDefaultSpinLimit;
 
-constexpr int kLdsSlots = 4 * msl::line_lds<512>();  // float2 slots of a line-pass workgroup's LDS (four 512-point lines)
+// LDS of a line-pass workgroup of G n-point lines: two exchange buffers per
+// line (msl::LineLds), the first buffers of all G lines, then the second ones.
+constexpr int kMaxLdsBytes = 64 * 1024;
+int line_pass_lds_bytes(int n, int G) { return 2 * G * (n + n / 8 + 1) * (int)sizeof(float2); }  // msl::line_lds<n>()
+
+template <int N>
+__device__ __forceinline__ msl::LineLds line_buffers(float2* lds, int g, int G) {
+  return msl::LineLds{lds + g * msl::line_lds<N>(), lds + (G + g) * msl::line_lds<N>()};
+}
 
 constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -307,13 +315,13 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 // which launch_pass_tp makes sure exists.
 template <int N, int P, int AXIS, int KIND>
 __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
-  __shared__ float2 lds[kLdsSlots];
+  extern __shared__ float2 lds[];  // line_pass_lds_bytes(N, G)
   constexpr int L = N / P;
   constexpr int TS = KIND == msl::KIND_GENERIC ? msl::TS_RUNTIME : msl::TS_PACK;
   const int G = blockDim.x / L;
   const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
-  msl::run_line<N, AXIS, false, KIND, TS, P>(c, pd, group * G + g, j, lds + g * msl::line_lds<N>());
+  msl::run_line<N, AXIS, false, KIND, TS, P>(c, pd, group * G + g, j, line_buffers<N>(lds, g, G));
 }
 
 // Points per lane of the per-pass and batch line kernels for n-point lines:
@@ -328,13 +336,12 @@ int points_per_lane(int n) {
 }
 
 // Lines per workgroup of n-point lines at p points per lane: at most 256
-// threads (the kernels' launch bound) and the line exchange buffers within the
-// kLdsSlots-slot LDS array.
+// threads (the kernels' launch bound) and at most kMaxLdsBytes of exchange
+// buffers.
 int max_lines_per_group(int n, int p) {
   const int L = n / p;
-  const int lds = n + n / 8 + 1;  // msl::line_lds<n>()
   int G = 1;
-  while (2 * G * L <= 256 && 2 * G * lds <= kLdsSlots) G *= 2;
+  while (2 * G * L <= 256 && line_pass_lds_bytes(n, 2 * G) <= kMaxLdsBytes) G *= 2;
   return G;
 }
 
@@ -357,10 +364,11 @@ hipError_t launch_pass_tp(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const dim3 grid(nlines / G), block(L * G);
   int kind = msl::pass_kind(pd);
   if (!c.dbT) kind = msl::KIND_GENERIC;  // the specialised kinds read the slice pack
+  const unsigned lds = (unsigned)line_pass_lds_bytes(N, G);
   switch (kind) {
-    case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_FWD_MID>), grid, block, 0, st, c, pd); break;
-    case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_REV_MID>), grid, block, 0, st, c, pd); break;
-    default: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_GENERIC>), grid, block, 0, st, c, pd); break;
+    case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_FWD_MID>), grid, block, lds, st, c, pd); break;
+    case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_REV_MID>), grid, block, lds, st, c, pd); break;
+    default: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_GENERIC>), grid, block, lds, st, c, pd); break;
   }
   return hipGetLastError();
 }
@@ -615,7 +623,7 @@ __global__ void k_store_recs(RecChunk chunk, BatchRec* dst) {
 template <int N, int P, int AXIS>
 __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__ recs, int groups_per_inst,
                                                     PassDesc tmpl) {
-  __shared__ float2 lds[kLdsSlots];
+  extern __shared__ float2 lds[];  // line_pass_lds_bytes(N, G)
   constexpr int L = N / P;
   const int G = blockDim.x / L;
   const int g = threadIdx.x % G, j = threadIdx.x / G;
@@ -626,7 +634,7 @@ __global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__
   pd.src = recs[inst].field;
   pd.dst = recs[inst].field;
   msl::run_line<N, AXIS, false, msl::KIND_FWD_MID, msl::TS_PACK, P>(c, pd, (gb % groups_per_inst) * G + g, j,
-                                                                   lds + g * msl::line_lds<N>());
+                                                                   line_buffers<N>(lds, g, G));
 }
 
 template <int N, int P, int AXIS>
@@ -634,7 +642,8 @@ hipError_t launch_pass_batch_tp(const BatchRec* recs, int n_inst, int nlines, co
   constexpr int L = N / P;
   const int G = lines_per_group(N, nlines);
   const int gpi = nlines / G;
-  hipLaunchKernelGGL((k_pass_batch<N, P, AXIS>), dim3(n_inst * gpi), dim3(L * G), 0, st, recs, gpi, tmpl);
+  hipLaunchKernelGGL((k_pass_batch<N, P, AXIS>), dim3(n_inst * gpi), dim3(L * G), (unsigned)line_pass_lds_bytes(N, G),
+                     st, recs, gpi, tmpl);
   return hipGetLastError();
 }
 

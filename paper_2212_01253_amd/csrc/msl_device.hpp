@@ -203,22 +203,41 @@ __device__ __forceinline__ void load_tw(LineTw<N, P>& tw, const float2* __restri
   }
 }
 
+// The two LDS exchange buffers of one line.  Consecutive exchanges of a
+// workgroup alternate between them, so a stage can write its output while
+// other waves still read that stage's input, and each exchange needs one
+// barrier (after the writes) instead of two.
+struct LineLds {
+  float2* a;
+  float2* b;
+};
+
 // Line FFT of N points held by L = N/P lanes, P points per lane.  On entry
 // and on exit lane j holds element j + t*L in v[t] ("t-layout", natural
 // order).  Stockham autosort: a first stage of radix R0 <= P without
 // twiddles, then radix-P stages; every stage but the last exchanges through
 // LDS (padded one slot in eight to spread the strided writes over the
-// banks).  All threads of the block call it together (it has block barriers).
+// banks), exchange e in buffer a for even e, b for odd e.  All threads of the
+// block call it together (it has block barriers).
+//
+// Why one barrier per exchange suffices: the writes of exchange e reuse the
+// buffer of exchange e - 2, whose reads every wave finished before it wrote
+// exchange e - 1 and so before the barrier that follows those writes; the
+// writer of exchange e has passed that barrier.  Successive calls keep the
+// alternation when the exchange count NST is even; for an odd count every
+// call starts on buffer a after a barrier of its own.
 template <int N, bool INV, int P = LinePts<N>::P>
-__device__ __forceinline__ void fft_line(float2 (&v)[P], float2* sh, int j, const LineTw<N, P>& tw) {
+__device__ __forceinline__ void fft_line(float2 (&v)[P], const LineLds& sh, int j, const LineTw<N, P>& tw) {
   constexpr int L = N / P;
   constexpr int R0 = LineTw<N, P>::R0;
-  // ---- stage 0: radix R0, sub-length 1, trivial twiddles
-  __syncthreads();
+  constexpr int NX = LineTw<N, P>::NST;  // exchanges: after stage 0 and after every radix-P stage but the last
+  if constexpr (NX % 2 == 1) __syncthreads();
+  // ---- stage 0: radix R0, sub-length 1, trivial twiddles; writes exchange 0 (buffer a)
+  float2* const w0 = sh.a;
   if constexpr (R0 == P) {
     dft_p<P, INV>(v);
 #pragma unroll
-    for (int r = 0; r < P; ++r) sh[lds_pad(P * j + r)] = v[r];
+    for (int r = 0; r < P; ++r) w0[lds_pad(P * j + r)] = v[r];
   } else {
     constexpr int Q = P / R0;
 #pragma unroll
@@ -227,32 +246,33 @@ __device__ __forceinline__ void fft_line(float2 (&v)[P], float2* sh, int j, cons
         float2 y0, y1, y2, y3;
         dft4<INV>(v[q], v[q + Q], v[q + 2 * Q], v[q + 3 * Q], y0, y1, y2, y3);
         const int b = R0 * (j + q * L);
-        sh[lds_pad(b)] = y0;
-        sh[lds_pad(b + 1)] = y1;
-        sh[lds_pad(b + 2)] = y2;
-        sh[lds_pad(b + 3)] = y3;
+        w0[lds_pad(b)] = y0;
+        w0[lds_pad(b + 1)] = y1;
+        w0[lds_pad(b + 2)] = y2;
+        w0[lds_pad(b + 3)] = y3;
       } else {
         float2 a = v[q], c = v[q + Q];
         dft2<INV>(a, c);
-        sh[lds_pad(2 * (j + q * L))] = a;
-        sh[lds_pad(2 * (j + q * L) + 1)] = c;
+        w0[lds_pad(2 * (j + q * L))] = a;
+        w0[lds_pad(2 * (j + q * L) + 1)] = c;
       }
     }
   }
   __syncthreads();
-  // ---- radix-P stages with sub-length NS = R0, P R0, ...
+  // ---- radix-P stages with sub-length NS = R0, P R0, ...; stage s reads exchange s
 #pragma unroll
-  for (int s = 0, NS = R0; s < LineTw<N, P>::NST; ++s, NS *= P) {
+  for (int s = 0, NS = R0; s < NX; ++s, NS *= P) {
+    const float2* const rd = (s & 1) ? sh.b : sh.a;
 #pragma unroll
-    for (int t = 0; t < P; ++t) v[t] = sh[lds_pad(j + t * L)];
+    for (int t = 0; t < P; ++t) v[t] = rd[lds_pad(j + t * L)];
 #pragma unroll
     for (int r = 1; r < P; ++r) v[r] = cmul_comp<INV>(v[r], tw.hi[s][r - 1], tw.lo[s][r - 1]);
     dft_p<P, INV>(v);
-    if (NS * P < N) {
+    if (s + 1 < NX) {
+      float2* const wr = (s & 1) ? sh.a : sh.b;
       const int base = (j / NS) * NS * P + (j % NS);
-      __syncthreads();
 #pragma unroll
-      for (int r = 0; r < P; ++r) sh[lds_pad(base + r * NS)] = v[r];
+      for (int r = 0; r < P; ++r) wr[lds_pad(base + r * NS)] = v[r];
       __syncthreads();
     }
   }
@@ -502,7 +522,7 @@ __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int
 }
 
 template <int N, int P = LinePts<N>::P>
-__device__ __forceinline__ void prop_line(float2 (&v)[P], float2* sh, int j, const LineIn<N, P>& in, bool conj) {
+__device__ __forceinline__ void prop_line(float2 (&v)[P], const LineLds& sh, int j, const LineIn<N, P>& in, bool conj) {
   fft_line<N, false, P>(v, sh, j, in.tw);
 #pragma unroll
   for (int t = 0; t < P; ++t) v[t] = cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj);
@@ -510,7 +530,7 @@ __device__ __forceinline__ void prop_line(float2 (&v)[P], float2* sh, int j, con
 }
 
 template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P>
-__device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, int line, int j, float2* sh,
+__device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, int line, int j, const LineLds& sh,
                                              LineIn<N, P>& in) {
   constexpr int L = N / P;
   const float inv_n = 1.0f / (float)N;
@@ -612,7 +632,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
 }
 
 template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P>
-__device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
+__device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, const LineLds& sh) {
   LineIn<N, P> in;
   load_field<N, AXIS, COH, KIND, P>(c, pd, line, j, in);
   load_static<N, AXIS, KIND, TS, P>(c, pd, line, j, in);
@@ -621,7 +641,7 @@ __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int l
 
 // Either axis, chosen per pass at run time (square grids: both line lengths are N).
 template <int N, bool COH = false, int P = LinePts<N>::P>
-__device__ __forceinline__ void run_line_any(const Ctx& c, const PassDesc& pd, int line, int j, float2* sh) {
+__device__ __forceinline__ void run_line_any(const Ctx& c, const PassDesc& pd, int line, int j, const LineLds& sh) {
   if (pd.axis == ROW) run_line<N, ROW, COH, KIND_GENERIC, TS_RUNTIME, P>(c, pd, line, j, sh);
   else run_line<N, COL, COH, KIND_GENERIC, TS_RUNTIME, P>(c, pd, line, j, sh);
 }

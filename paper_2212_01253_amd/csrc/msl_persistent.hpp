@@ -66,7 +66,7 @@ struct PersistShape {
   static constexpr int T0 = N >= 1024 ? 256 : 128;
   static constexpr int T = T0 < N * L ? T0 : N * L;  // at most N lines per block
   static constexpr int G = T / L;
-  static constexpr int LDS = G * line_lds<N>();
+  static constexpr int LDS = 2 * G * line_lds<N>();  // two exchange buffers per line
 };
 
 // Blocks [0, nbA) run phase A, blocks [nbA, gridDim.x) run phase B (if npB > 0).
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_persist(Ctx c, PhaseSpec A, PhaseSpec B
   const int np_all = npA > npB ? npA : npB;
   const int nb = second ? (int)gridDim.x - nbA : nbA;
   const int bid = xcd_group(second ? (int)blockIdx.x - nbA : (int)blockIdx.x, nb);
-  float2* sh = lds + g * line_lds<N>();
+  const LineLds sh{lds + g * line_lds<N>(), lds + (S::G + g) * line_lds<N>()};
   for (int p = 0; p < np_all; ++p) {
     if (p < np_mine) {
       const PassDesc pd = phase_pass(ph, p);

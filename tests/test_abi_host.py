@@ -255,16 +255,17 @@ def test_tuning_validates_and_round_trips(L):
         assert t["lines_per_group"][128] == 1 and t["lines_per_group"][16] == 64
         assert t["lines_per_group"][1024] == 0 and t["batch_streams"] == 2
         assert t["points_per_lane"][512] == 4 and t["points_per_lane"][64] == 8 and t["points_per_lane"][256] == 0
-        # group limits at 8 points per lane: 64: 16, 128: 8, 256: 4, 512: 4, 1024: 2;
+        # group limits at 8 points per lane: 64: 32, 128: 16, 256: 8, 512: 4, 1024: 2;
         # at 4: 16: 64, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2, 1024: 1
-        msl.set_tuning({512: 4, 1024: 2, 64: 16})
-        msl.set_tuning({512: 2, 1024: 1, 16: 64, 32: 32}, points_per_lane={512: 4, 1024: 4, 16: 4, 32: 4})
-        msl.set_tuning({256: 4, 128: 8}, points_per_lane={256: 8, 128: 8})
+        msl.set_tuning({512: 4, 1024: 2, 64: 32, 128: 16, 256: 8}, points_per_lane={64: 8, 128: 8, 256: 8})
+        msl.set_tuning({512: 2, 1024: 1, 16: 64, 32: 32, 64: 16, 128: 8, 256: 4},
+                       points_per_lane={512: 4, 1024: 4, 16: 4, 32: 4, 64: 4, 128: 4, 256: 4})
         msl.restore_tuning(t)
         bad = [({512: 3}, 0, {}), ({512: 8}, 0, {}), ({1024: 4}, 0, {}), ({256: -1}, 0, {}), ({8: 1}, 0, {}),
                ({}, 5, {}), ({}, -1, {}),
                ({}, 0, {512: 2}), ({}, 0, {512: 16}), ({}, 0, {32: 8}), ({}, 0, {16: 8}), ({}, 0, {8: 4}),
-               ({}, 0, {256: -4}), ({512: 4}, 0, {512: 4}), ({1024: 2}, 0, {1024: 4}), ({64: 32}, 0, {64: 8})]
+               ({}, 0, {256: -4}), ({512: 4}, 0, {512: 4}), ({1024: 2}, 0, {1024: 4}), ({64: 64}, 0, {64: 8}),
+               ({64: 32}, 0, {64: 4}), ({256: 8}, 0, {}), ({256: 16}, 0, {256: 8})]
         for lpg, bs, ppl in bad:
             with pytest.raises(msl.MslError):
                 msl.set_tuning(lpg, batch_streams=bs, points_per_lane=ppl)

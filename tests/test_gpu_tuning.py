@@ -19,11 +19,8 @@ pytestmark = pytest.mark.gpu
 
 
 def limit(n, p):
-    """Largest lines per workgroup: 256 threads and four 512-point line buffers of LDS."""
-    lanes, lds, slots, g = n // p, n + n // 8 + 1, 4 * (512 + 64 + 1), 1
-    while 2 * g * lanes <= 256 and 2 * g * lds <= slots:
-        g *= 2
-    return g
+    """Largest lines per workgroup: 256 threads of n / p lanes per line."""
+    return 256 // (n // p)
 
 
 def radices(n):
