@@ -169,24 +169,48 @@ __global__ void k_probe(int ny, int nz, double q, float2* out) {
   out[i] = make_float2((float)c, (float)s);
 }
 
+// Tile (a, b) (rows 2a, 2a+1, columns 2b, 2b+1) handled at work index t of a
+// tile kernel, and that tile's index in the output layout.  Row tile order:
+// tiles row by row.  Column tile order: each 64-wide wavefront takes an 8 x 8
+// block of tiles, a fastest, blocks down the columns, so its row-major
+// accesses cover 64-byte runs of 8 rows and its tile accesses 256-byte runs of
+// 8 tiles.  Needs ny / 2 and nz / 2 multiples of 8 (grids of 16 and more).
+struct TileAt {
+  int a, b, out;
+};
+__device__ __forceinline__ TileAt tile_at(int t, int ny, int nz, bool col_order) {
+  if (!col_order) {
+    const int tz = nz >> 1;
+    return TileAt{t / tz, t % tz, t};
+  }
+  const int lane = t & 63, blk = t >> 6, nba = ny >> 4;
+  const int a = (blk % nba) * 8 + (lane & 7), b = (blk / nba) * 8 + (lane >> 3);
+  return TileAt{a, b, b * (ny >> 1) + a};
+}
+
 // Slices' transmission minus one, T - 1 = exp(i k dx (delta + i beta)) - 1,
-// into the 2x2-tiled layout: slice first + stride * s2 -> out[s2], s2 in
-// [s2b, s2e); one thread per 2x2 tile (two 8-byte reads of each stack when
-// VEC, i.e. both stacks 8-byte aligned, else four 4-byte reads; two 16-byte
-// writes).  The odd slices of a stack (first 1, stride 2) or every slice of a
-// pool (first 0, stride 1).  The line passes evaluate T - 1 of the other
-// slices with the same function.
+// into 2x2 tiles: slice first + stride * s2 -> out[s2], s2 in [s2b, s2e), in
+// column tile order for odd slices when col_odd (a stack's pack: those slices
+// are transmitted in column passes), else in row tile order; one thread per
+// tile (two 8-byte reads of each stack when VEC, i.e. both stacks 8-byte
+// aligned, else four 4-byte reads; two 16-byte writes).  Every slice of a
+// stack (first 0, stride 1, col_odd) or of a batch pool (col_odd 0).  Line
+// passes without a pack evaluate T - 1 with the same function.
 template <bool VEC>
 __global__ void __launch_bounds__(256) k_pack_tiled(const float* d, const float* b, float2* out, int ny, int nz,
-                                                    int s2b, int s2e, int first, int stride, msl::Ctx c) {
+                                                    int s2b, int s2e, int first, int stride, int col_odd,
+                                                    msl::Ctx c) {
   const int64_t m = (int64_t)ny * nz;
-  const int tiles = (int)(m >> 2), tz = nz >> 1;
+  const int tiles = (int)(m >> 2);
   for (int s2 = s2b + blockIdx.y; s2 < s2e; s2 += gridDim.y) {
-    const float* ds = d + (int64_t)(first + stride * s2) * m;
-    const float* bs = b + (int64_t)(first + stride * s2) * m;
+    const int sl = first + stride * s2;
+    const bool col_order = col_odd && (sl & 1);
+    const float* ds = d + (int64_t)sl * m;
+    const float* bs = b + (int64_t)sl * m;
     float4* o = reinterpret_cast<float4*>(out + (int64_t)s2 * m);
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += gridDim.x * blockDim.x) {
-      const int64_t e = (int64_t)(2 * (t / tz)) * nz + 2 * (t % tz);
+      const TileAt ta = tile_at(t, ny, nz, col_order);
+      const int64_t e = (int64_t)(2 * ta.a) * nz + 2 * ta.b;
       float2 d0, d1, b0, b1;  // (row 2a, row 2a + 1) x (column 2b, 2b + 1)
       if constexpr (VEC) {
         d0 = *reinterpret_cast<const float2*>(ds + e);
@@ -203,31 +227,32 @@ __global__ void __launch_bounds__(256) k_pack_tiled(const float* d, const float*
       const float2 t1 = msl::transmission_m1(msl::phase_arg(d0.y, c), msl::phase_arg(b0.y, c));
       const float2 t2 = msl::transmission_m1(msl::phase_arg(d1.x, c), msl::phase_arg(b1.x, c));
       const float2 t3 = msl::transmission_m1(msl::phase_arg(d1.y, c), msl::phase_arg(b1.y, c));
-      o[2 * (int64_t)t] = make_float4(t0.x, t0.y, t1.x, t1.y);
-      o[2 * (int64_t)t + 1] = make_float4(t2.x, t2.y, t3.x, t3.y);
+      o[2 * (int64_t)ta.out] = make_float4(t0.x, t0.y, t1.x, t1.y);
+      o[2 * (int64_t)ta.out + 1] = make_float4(t2.x, t2.y, t3.x, t3.y);
     }
   }
 }
 
-// Packs slices first + stride * s2, s2 in [s2b, s2e), of (d, b) into out (tiled).
+// Packs slices first + stride * s2, s2 in [s2b, s2e), of (d, b) into out (k_pack_tiled).
 hipError_t launch_pack(const float* d, const float* b, float2* out, int ny, int nz, int s2b, int s2e, int first,
-                       int stride, const msl::Ctx& c, hipStream_t st);
+                       int stride, int col_odd, const msl::Ctx& c, hipStream_t st);
 
-// gT[s2] (tiled float2: dL/d delta, dL/d beta) -> gdelta, gbeta [s][y][z]
-// row-major for odd slices s = 2 s2 + 1, s2 in [s2b, s2e); one thread per tile
-// (two 16-byte reads; 8-byte writes when VEC, i.e. both outputs 8-byte
-// aligned, else 4-byte writes).
+// gT[s2] (float2 (dL/d delta, dL/d beta) in column tile order) -> gdelta,
+// gbeta [s][y][z] row-major for odd slices s = 2 s2 + 1, s2 in [s2b, s2e);
+// one thread per tile (two 16-byte reads; 8-byte writes when VEC, i.e. both
+// outputs 8-byte aligned, else 4-byte writes).
 template <bool VEC>
 __global__ void __launch_bounds__(256) k_unpack_tiled(const float2* gT, float* gd, float* gb, int ny, int nz,
                                                       int s2b, int s2e) {
   const int64_t m = (int64_t)ny * nz;
-  const int tiles = (int)(m >> 2), tz = nz >> 1;
+  const int tiles = (int)(m >> 2);
   for (int s2 = s2b + blockIdx.y; s2 < s2e; s2 += gridDim.y) {
     const float4* q = reinterpret_cast<const float4*>(gT + (int64_t)s2 * m);
     const int64_t so = (int64_t)(2 * s2 + 1) * m;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += gridDim.x * blockDim.x) {
-      const int64_t e = so + (int64_t)(2 * (t / tz)) * nz + 2 * (t % tz);
-      const float4 u = q[2 * (int64_t)t], w = q[2 * (int64_t)t + 1];  // (d, b) at (0,0), (0,1) | (1,0), (1,1)
+      const TileAt ta = tile_at(t, ny, nz, true);
+      const int64_t e = so + (int64_t)(2 * ta.a) * nz + 2 * ta.b;
+      const float4 u = q[2 * (int64_t)ta.out], w = q[2 * (int64_t)ta.out + 1];  // (d, b) at (0,0), (0,1) | (1,0), (1,1)
       if constexpr (VEC) {
         if (gd) {
           *reinterpret_cast<float2*>(gd + e) = make_float2(u.x, u.z);
@@ -263,12 +288,14 @@ dim3 tile_grid(int ny, int nz, int n) {
 }
 
 hipError_t launch_pack(const float* d, const float* b, float2* out, int ny, int nz, int s2b, int s2e, int first,
-                       int stride, const msl::Ctx& c, hipStream_t st) {
+                       int stride, int col_odd, const msl::Ctx& c, hipStream_t st) {
   const dim3 grid = tile_grid(ny, nz, s2e - s2b);
   if (aligned(d, 8) && aligned(b, 8))
-    hipLaunchKernelGGL(k_pack_tiled<true>, grid, dim3(256), 0, st, d, b, out, ny, nz, s2b, s2e, first, stride, c);
+    hipLaunchKernelGGL(k_pack_tiled<true>, grid, dim3(256), 0, st, d, b, out, ny, nz, s2b, s2e, first, stride,
+                       col_odd, c);
   else
-    hipLaunchKernelGGL(k_pack_tiled<false>, grid, dim3(256), 0, st, d, b, out, ny, nz, s2b, s2e, first, stride, c);
+    hipLaunchKernelGGL(k_pack_tiled<false>, grid, dim3(256), 0, st, d, b, out, ny, nz, s2b, s2e, first, stride,
+                       col_odd, c);
   return hipGetLastError();
 }
 
@@ -567,7 +594,7 @@ int odd_end(int s1) { return s1 >> 1; }
 msl_status pack_slices(Call& k) {
   if (k.g.propagator != MSL_PROP_PARAXIAL) return MSL_OK;
   float2* dbT = reinterpret_cast<float2*>(k.ws + k.L.dbT);
-  MSL_TRY(hip_check(launch_pack(k.c.delta, k.c.beta, dbT, k.g.ny, k.g.nz, 0, k.g.n_slices, 0, 1, k.c, k.st),
+  MSL_TRY(hip_check(launch_pack(k.c.delta, k.c.beta, dbT, k.g.ny, k.g.nz, 0, k.g.n_slices, 0, 1, 1, k.c, k.st),
                     "pack kernel"));
   k.c.dbT = dbT;
   return MSL_OK;
@@ -1349,7 +1376,7 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
       in = f;
     }
     float2* pack = P(b.pack);
-    MSL_TRY(hip_check(launch_pack(x.pool_delta, x.pool_beta, pack, g.ny, g.nz, 0, x.n_pool, 0, 1, c, st),
+    MSL_TRY(hip_check(launch_pack(x.pool_delta, x.pool_beta, pack, g.ny, g.nz, 0, x.n_pool, 0, 1, 0, c, st),
                       "pack kernel"));
     c.dbT = pack;
     recs[r].c = c;

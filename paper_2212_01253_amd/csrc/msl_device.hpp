@@ -36,11 +36,12 @@ struct PassDesc {
   float2* psi_store;    // store the line before the mid step (nullptr = no)
   const float2* psi_load;  // entrance field psi_s for the adjoint step
   // layouts of the four field arrays: LAY_R row-major [ny][nz] (caller
-  // arrays), LAY_T 2x2-tiled (working fields; see tile_addr)
+  // arrays), LAY_T 2x2-tiled (working fields; see tile_addr), LAY_C 2x2
+  // tiles in column order (fields only column passes touch; see tile_addr_c)
   int src_lay, dst_lay, store_lay, load_lay;
 };
 
-enum Layout : int { LAY_R = 0, LAY_T = 1 };
+enum Layout : int { LAY_R = 0, LAY_T = 1, LAY_C = 2 };
 
 // Everything a pass reads besides the descriptor.
 struct Ctx {
@@ -60,10 +61,11 @@ struct Ctx {
   float* intensity;                 // far-field output (fftshifted) or nullptr
   const float* grad_intensity;      // far-field seed input (fftshifted) or nullptr
   // Paraxial schedule: the workspace may hold T - 1 of every slice
-  // precomputed, [Ns] tiled fields (float2), so that line passes of either
-  // axis read 32-byte tiles and spend no arithmetic on the transmission.  Odd
-  // slices are transmitted in column passes; gT stages their (dL/d delta,
-  // dL/d beta), [Ns/2] tiled fields, so those passes write whole tiles
+  // precomputed, [Ns] 2x2-tiled fields (float2), even slices (row passes) in
+  // row tile order, odd slices (column passes) in column tile order, so that
+  // each pass reads its slice contiguously and spends no arithmetic on the
+  // transmission.  gT stages the odd slices' (dL/d delta, dL/d beta), [Ns/2]
+  // fields in column tile order, so those passes write contiguous tiles
   // instead of striding through the caller's row-major gradient stacks.
   const float2* dbT;                // or nullptr
   float2* gT;                       // or nullptr
@@ -368,10 +370,19 @@ __device__ __forceinline__ uint32_t tile_addr(const Ctx& c, uint32_t r, uint32_t
   return ((((r >> 1) * ((uint32_t)c.nz >> 1)) + (col >> 1)) << 2) + ((r & 1u) << 1) + (col & 1u);
 }
 
+// The same 2x2 tiles ordered column by column (tile (a, b) at b ny/2 + a):
+// the tiles of a column pass over columns 2b and 2b+1 are contiguous.  Fields
+// of one slice that only column passes read and write (the odd slices' packed
+// transmissions, stored entrance fields and gradients) use it.
+__device__ __forceinline__ uint32_t tile_addr_c(const Ctx& c, uint32_t r, uint32_t col) {
+  return ((((col >> 1) * ((uint32_t)c.ny >> 1)) + (r >> 1)) << 2) + ((r & 1u) << 1) + (col & 1u);
+}
+
 // The elements j + t L (t = 0 .. P-1) of line `line` of a pass along AXIS in
-// layout `lay` are at base + t * stride: in both layouts a step of L (even)
+// layout `lay` are at base + t * stride: in every layout a step of L (even)
 // along the line moves by a fixed offset (row-major: L along a row, L nz
-// along a column; tiled: 2 L along a row, L nz along a column).
+// along a column; tiled: 2 L along a row, L nz along a column; tiled in
+// column order: L ny along a row, 2 L along a column).
 struct LineAddr {
   uint32_t base, stride;
 };
@@ -381,9 +392,18 @@ __device__ __forceinline__ LineAddr line_at(const Ctx& c, int lay, int line, int
   constexpr uint32_t L = (uint32_t)(N / P);
   const uint32_t r = AXIS == ROW ? (uint32_t)line : (uint32_t)j;
   const uint32_t col = AXIS == ROW ? (uint32_t)j : (uint32_t)line;
+  if (lay == LAY_C) return LineAddr{tile_addr_c(c, r, col), AXIS == ROW ? L * (uint32_t)c.ny : 2 * L};
   const uint32_t base = lay == LAY_T ? tile_addr(c, r, col) : r * (uint32_t)c.nz + col;
   const uint32_t stride = AXIS == ROW ? (lay == LAY_T ? 2 * L : L) : L * (uint32_t)c.nz;
   return LineAddr{base, stride};
+}
+
+// Layout of the slice pack: a single stack's pack holds the odd slices (column
+// passes) in column tile order, a batch pool (slices of either parity) in row
+// tile order.
+template <int AXIS>
+__device__ __forceinline__ int pack_lay(const Ctx& c) {
+  return (AXIS == COL && !c.slice_index) ? (int)LAY_C : (int)LAY_T;
 }
 
 // Float2 slots of one line's exchange buffer in LDS: a radix-8 pad every
@@ -453,7 +473,7 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
     if (uses_pack<TS>(c)) {
       // precomputed T - 1 (real part in dl, imaginary part in bt), tiled
       const float2* q = c.dbT + slice_offset(c, pd.slice);
-      const LineAddr a = line_at<N, AXIS, P>(c, LAY_T, line, j);
+      const LineAddr a = line_at<N, AXIS, P>(c, pack_lay<AXIS>(c), line, j);
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         const float2 tm = q[a.base + (uint32_t)t * a.stride];
@@ -583,7 +603,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
     float2* const gtp = c.gT ? c.gT + (int64_t)(pd.slice >> 1) * c.m : nullptr;
     const float kdx = c.kdx_hi;
     const LineAddr ar = line_at<N, AXIS, P>(c, LAY_R, line, j);
-    const LineAddr at = line_at<N, AXIS, P>(c, LAY_T, line, j);
+    const LineAddr at = line_at<N, AXIS, P>(c, LAY_C, line, j);  // gT: odd slices, column passes
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       const uint32_t e = ar.base + (uint32_t)t * ar.stride;

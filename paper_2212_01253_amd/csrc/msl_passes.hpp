@@ -10,9 +10,10 @@
 // ONE pass over lines of one axis: propagate, transmit, propagate.  That is
 // one field round trip and one global exchange per slice instead of two.
 // Slice s is always transmitted in a pass of axis s mod 2 (rows for even
-// slices, columns for odd ones), in every phase, so the odd slices'
-// precomputed transmissions and their gradients can be kept apart from the
-// caller's row-major stacks, in the tiled layout the column passes read well.
+// slices, columns for odd ones), in every phase, so everything that belongs
+// to one slice (its precomputed transmission, its stored entrance field, the
+// odd slices' gradients) can be laid out for that axis: 2x2 tiles in row
+// order for even slices, in column order for odd ones.
 //
 // Exact angular-spectrum propagator.  It does not factorise; each slice takes
 // a row pass (z-IFFT, transmission, z-FFT) and a column pass (y-FFT, H, y-IFFT)
@@ -73,6 +74,15 @@ __host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
 }
 
 __host__ __device__ inline int work_lay(const PhaseSpec& ph) { return ph.rowmajor ? LAY_R : LAY_T; }
+
+// Layout of a segment field of slice s (its entrance field, stored by the
+// recompute and read by the reverse sweep): in the paraxial schedule both
+// passes run along the slice's own axis, so odd slices' fields are kept in
+// column tile order, which column passes access contiguously.
+__host__ __device__ inline int seg_lay(const PhaseSpec& ph, int s) {
+  if (ph.rowmajor) return LAY_R;
+  return (!ph.exact && (s & 1)) ? LAY_C : LAY_T;
+}
 
 // A pass along `axis`, the first and/or the last of its phase.
 __host__ __device__ inline PassDesc make_pass(const PhaseSpec& ph, int axis, bool first, bool last) {
@@ -167,7 +177,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
         d.pre = p == 0 ? PRE_NONE : PRE_PROP;
         if (p > 0) {
           d.psi_store = ph.seg + (int64_t)(p - 1) * ph.m;
-          d.store_lay = wl;
+          d.store_lay = seg_lay(ph, ph.s0 + p);
         }
         if (p < n - 1) {
           d.mid = MID_T_FWD;
@@ -221,7 +231,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
           d.load_lay = LAY_R;
         } else {
           d.psi_load = ph.seg + (int64_t)(s - ph.s0 - 1) * ph.m;
-          d.load_lay = ph.seg_row_major ? LAY_R : wl;
+          d.load_lay = ph.seg_row_major ? LAY_R : seg_lay(ph, s);
         }
         d.post = s == 0 ? POST_NONE : POST_PROP;
         return d;

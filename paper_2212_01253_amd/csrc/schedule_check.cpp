@@ -118,6 +118,9 @@ void run_pass(Engine& E, const msl::PassDesc& pd) {
   if ((pd.src_lay != msl::LAY_R && pd.src_lay != msl::LAY_T) || (pd.dst && pd.dst_lay != msl::LAY_R &&
                                                                  pd.dst_lay != msl::LAY_T))
     ++g_bad_layout;
+  // fields in column tile order are only ever touched by column passes
+  if ((pd.psi_store && pd.store_lay == msl::LAY_C && row) || (pd.psi_load && pd.load_lay == msl::LAY_C && row))
+    ++g_bad_layout;
   const double k = 2 * M_PI / g.lam;
   for (int line = 0; line < nl; ++line) {
     auto addr = [&](int i) -> int64_t { return row ? (int64_t)line * g.nz + i : (int64_t)i * g.nz + line; };
@@ -126,6 +129,7 @@ void run_pass(Engine& E, const msl::PassDesc& pd) {
     auto laddr = [&](int lay, int i) -> int64_t {
       const int64_t y = row ? line : i, z = row ? i : line;
       if (lay == msl::LAY_T) return ((y / 2) * (g.nz / 2) + z / 2) * 4 + (y % 2) * 2 + z % 2;
+      if (lay == msl::LAY_C) return ((z / 2) * (g.ny / 2) + y / 2) * 4 + (y % 2) * 2 + z % 2;
       return y * g.nz + z;
     };
     std::vector<cd> v(n);
