@@ -402,6 +402,155 @@ __global__ void __launch_bounds__(256) k_conv_bwd_weight(ConvArgs a, int kchunk,
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolutions on halo tiles.  A workgroup owns MT output channels (rows)
+// x NT = 8192 / MT pixels of one image, a TH x TW block of output positions.
+// For every chunk of 16 input channels it stages once, in LDS and as
+// bfloat16, the input block the 3x3 windows of its pixels cover (the halo:
+// (TH - 1) s + 3 rows of (TW - 1) s + 3 positions, each position's 16
+// channels contiguous) and the weights of its rows for those channels (all
+// nine taps); the nine taps then read shifted views of the same staged block,
+// so each input value crosses from memory once per chunk instead of once per
+// tap.  k runs over (tap, channel), one 16-deep MFMA step per tap, as the
+// gfx950 32x32x16 bfloat16 instruction: each of the four wavefronts
+// accumulates a 32-row x 64-pixel part in two 32 x 32 float32 tiles.
+//
+// The same kernel computes the input gradient of a stride-1 convolution: a
+// stride-1 convolution of the output gradient with the weights transposed
+// (input and output channels swapped) and rotated by 180 degrees (flip).
+
+constexpr int HCK = 16;         // input channels per chunk (one MFMA k step per tap)
+constexpr int HCKP = HCK + 8;   // bfloat16 slots per staged position: 48-byte stride, conflict-free 16-byte reads
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct HaloArgs {
+  int M;                 // output channels (rows of the product)
+  int C;                 // input channels
+  int B, H, W, s, Ho, Wo, relu;
+  int TW, TH, tiles_x, tiles_y;
+  int flip;              // weights: 0 w16[m][9 c + tap]; 1 w16[c][9 m + 8 - tap] (input gradient)
+  int ldw;               // row length of w16
+  const uint16_t* w16;
+  const void* x;         // [C][B][H][W], float32 or (xbf16) bfloat16 bits
+  const float* bias;     // [M] or nullptr
+  float* y;              // [M][B][Ho][Wo]
+};
+
+template <bool XBF16>
+__device__ __forceinline__ uint16_t halo_in(const void* x, int64_t i) {
+  if constexpr (XBF16) return static_cast<const uint16_t*>(x)[i];
+  else return to_bf16(static_cast<const float*>(x)[i]);
+}
+
+__device__ __forceinline__ void lds_store16(uint16_t* dst, const uint16_t (&v)[16]) {
+  uint4 a, b;
+  a.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+  a.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+  a.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+  a.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+  b.x = (uint32_t)v[8] | ((uint32_t)v[9] << 16);
+  b.y = (uint32_t)v[10] | ((uint32_t)v[11] << 16);
+  b.z = (uint32_t)v[12] | ((uint32_t)v[13] << 16);
+  b.w = (uint32_t)v[14] | ((uint32_t)v[15] << 16);
+  *reinterpret_cast<uint4*>(dst) = a;
+  *reinterpret_cast<uint4*>(dst + 8) = b;
+}
+
+// LDS bytes of a halo workgroup: the weights [MT][9][16], then the staged positions [HH HW][HCKP].
+int halo_lds_bytes(int MT, int TW, int TH, int s) {
+  const int HW = (TW - 1) * s + 3, HH = (TH - 1) * s + 3;
+  return (MT * 9 * HCK + HH * HW * HCKP) * (int)sizeof(uint16_t);
+}
+
+template <int MT, bool XBF16>
+__global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t halo_smem[];
+  uint16_t* const ws = halo_smem;                   // [MT][9][HCK]
+  uint16_t* const xs = halo_smem + MT * 9 * HCK;    // [HH * HW][HCKP]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * MT;
+  int t = blockIdx.x;
+  const int ox0 = (t % a.tiles_x) * a.TW;
+  t /= a.tiles_x;
+  const int oy0 = (t % a.tiles_y) * a.TH;
+  const int b = t / a.tiles_y;
+  const int HW = (a.TW - 1) * a.s + 3, HH = (a.TH - 1) * a.s + 3, NH = HH * HW;
+  const int iy0 = oy0 * a.s - 1, ix0 = ox0 * a.s - 1;
+  constexpr int MB = MT / 32;              // 32-row blocks per workgroup
+  const int cb = wave % MB, pb = wave / MB;  // this wave's row block and 64-pixel block
+  const int kq = 8 * (lane >> 5);
+  // this lane's two pixels of the tile: n0 (first accumulator) and n0 + 32 (second)
+  const int n0 = pb * 64 + (lane & 31), n1 = n0 + 32;
+  const int ty0 = n0 / a.TW, tx0 = n0 - ty0 * a.TW, ty1 = n1 / a.TW, tx1 = n1 - ty1 * a.TW;
+  const int hoff0 = (ty0 * HW + tx0) * a.s, hoff1 = (ty1 * HW + tx1) * a.s;
+  const int64_t plane = (int64_t)a.H * a.W, cstride = (int64_t)a.B * plane;
+  const int64_t img = (int64_t)b * plane;
+  f32x16 acc0 = {}, acc1 = {};
+  for (int c0 = 0; c0 < a.C; c0 += HCK) {
+    for (int p = tid; p < NH; p += 256) {
+      const int hy = p / HW, hx = p - hy * HW;
+      const int yy = iy0 + hy, xx = ix0 + hx;
+      const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+      const int64_t e = img + (int64_t)yy * a.W + xx;
+      uint16_t v[16];
+#pragma unroll
+      for (int q = 0; q < HCK; ++q) {
+        const int c = c0 + q;
+        v[q] = (in && c < a.C) ? halo_in<XBF16>(a.x, (int64_t)c * cstride + e) : (uint16_t)0;
+      }
+      lds_store16(&xs[p * HCKP], v);
+    }
+    for (int e = tid; e < MT * 9 * 2; e += 256) {
+      const int half = e & 1, mt = e >> 1;
+      const int m = mt / 9, tap = mt - 9 * m;
+      const int gm = m0 + m;
+      uint16_t v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = c0 + 8 * half + q;
+        uint16_t w = 0;
+        if (gm < a.M && c < a.C)
+          w = a.flip ? a.w16[(int64_t)c * a.ldw + 9 * gm + 8 - tap] : a.w16[(int64_t)gm * a.ldw + 9 * c + tap];
+        v[q] = w;
+      }
+      lds_store8(&ws[(m * 9 + tap) * HCK + 8 * half], v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int sh = (tap / 3) * HW + tap % 3;
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&ws[((cb * 32 + (lane & 31)) * 9 + tap) * HCK + kq]);
+      const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&xs[(hoff0 + sh) * HCKP + kq]);
+      const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&xs[(hoff1 + sh) * HCKP + kq]);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // accumulator element 4i + j of lane l: row 8i + 4 (l / 32) + j, pixel l mod 32 of the 32 x 32 tile
+  const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
+  auto store = [&](const f32x16& acc, int ty, int tx) {
+    const int oy = oy0 + ty, ox = ox0 + tx;
+    if (oy >= a.Ho || ox >= a.Wo) return;
+    const int64_t o = ((int64_t)b * a.Ho + oy) * a.Wo + ox;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + cb * 32 + 8 * i + 4 * (lane >> 5) + j;
+        if (m < a.M) {
+          float v = acc[4 * i + j];
+          if (a.bias) v += a.bias[m];
+          if (a.relu) v = fmaxf(v, 0.0f);
+          a.y[(int64_t)m * npix + o] = v;
+        }
+      }
+  };
+  store(acc0, ty0, tx0);
+  store(acc1, ty1, tx1);
+}
+
 // C[i] = sum over the parts s of P[s][i], in order
 __global__ void __launch_bounds__(256) k_sum_parts(int64_t mn, int parts, const float* __restrict__ P, int M, int N,
                                                    int ldc, float* __restrict__ C) {
@@ -700,6 +849,33 @@ msl_status need(bool ok, const char* what) { return ok ? MSL_OK : fail(MSL_ERR_A
 
 msl_status launched(const char* what) { return hip_check(hipGetLastError(), what); }
 
+// Halo-tile shape of a convolution with M output rows and Ho x Wo outputs per image: rows per
+// workgroup 32, 64 or 128 (the fewest blocks, then the least padding), pixels 8192 / MT as a
+// TH x TW block, TW the largest power of two <= min(Wo, 64).
+msl_status launch_conv_halo(HaloArgs a, bool xbf16, hipStream_t st) {
+  const int MT = a.M <= 32 ? 32 : (a.M <= 64 ? 64 : 128);
+  const int NT = 8192 / MT;
+  int TW = 1;
+  while (2 * TW <= std::min(a.Wo, 64)) TW *= 2;
+  a.TW = TW;
+  a.TH = NT / TW;
+  a.tiles_x = (a.Wo + a.TW - 1) / a.TW;
+  a.tiles_y = (a.Ho + a.TH - 1) / a.TH;
+  const int64_t nx = (int64_t)a.tiles_x * a.tiles_y * a.B;
+  const int lds = halo_lds_bytes(MT, a.TW, a.TH, a.s);
+  MSL_TRY(need(nx < (1ll << 31) && (a.M + MT - 1) / MT <= 65535 && lds <= 64 * 1024, "conv: sizes too large"));
+  const dim3 grid((unsigned)nx, (unsigned)((a.M + MT - 1) / MT));
+  switch (MT * 2 + (xbf16 ? 1 : 0)) {
+    case 64: hipLaunchKernelGGL((k_conv_halo<32, false>), grid, dim3(256), lds, st, a); break;
+    case 65: hipLaunchKernelGGL((k_conv_halo<32, true>), grid, dim3(256), lds, st, a); break;
+    case 128: hipLaunchKernelGGL((k_conv_halo<64, false>), grid, dim3(256), lds, st, a); break;
+    case 129: hipLaunchKernelGGL((k_conv_halo<64, true>), grid, dim3(256), lds, st, a); break;
+    case 256: hipLaunchKernelGGL((k_conv_halo<128, false>), grid, dim3(256), lds, st, a); break;
+    default: hipLaunchKernelGGL((k_conv_halo<128, true>), grid, dim3(256), lds, st, a); break;
+  }
+  return launched("conv kernel");
+}
+
 }  // namespace
 
 extern "C" {
@@ -754,17 +930,14 @@ msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W
   MSL_TRY(check_ptr(x, 4, "x"));
   MSL_TRY(check_ptr(bias, 4, "bias", true));
   MSL_TRY(check_ptr(y, 4, "y"));
-  ConvArgs a{};
-  a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
+  MSL_TRY(need((int64_t)C * 9 < (1 << 30) && (int64_t)B * H * W < (1ll << 40), "conv: sizes too large"));
+  HaloArgs a{};
+  a.M = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
   a.relu = relu ? 1 : 0;
-  a.K = C * 9;
-  a.N = (int64_t)B * a.Ho * a.Wo;
-  MSL_TRY(need((int64_t)C * 9 < (1 << 30) && a.N < (1ll << 40), "conv: sizes too large"));
+  a.flip = 0;
+  a.ldw = C * 9;
   a.w16 = w16; a.x = x; a.bias = bias; a.y = y;
-  const dim3 grid((unsigned)((a.N + TN - 1) / TN), (unsigned)((Co + TM - 1) / TM));
-  MSL_TRY(need(grid.y <= 65535, "conv: too many output channels"));
-  hipLaunchKernelGGL(k_conv_fwd, grid, dim3(256), 0, static_cast<hipStream_t>(hip_stream), a);
-  return launched("conv kernel");
+  return launch_conv_halo(a, false, static_cast<hipStream_t>(hip_stream));
 }
 
 msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
@@ -774,6 +947,17 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
   MSL_TRY(check_ptr(w16, 2, "w16"));
   MSL_TRY(check_ptr(dy16, 2, "dy16"));
   MSL_TRY(check_ptr(dx, 4, "dx"));
+  if (stride == 1) {
+    // a stride-1 convolution of dy with the weights transposed and rotated (see k_conv_halo)
+    MSL_TRY(need((int64_t)C * 9 < (1 << 30) && (int64_t)B * H * W < (1ll << 40), "conv adjoint: sizes too large"));
+    HaloArgs h{};
+    h.M = C; h.C = Co; h.B = B; h.H = H; h.W = W; h.s = 1; h.Ho = H; h.Wo = W;
+    h.relu = 0;
+    h.flip = 1;
+    h.ldw = C * 9;
+    h.w16 = w16; h.x = dy16; h.bias = nullptr; h.y = dx;
+    return launch_conv_halo(h, true, static_cast<hipStream_t>(hip_stream));
+  }
   ConvArgs a{};
   a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
   a.K = Co * 9;
