@@ -54,20 +54,31 @@ msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t 
 msl_status msl_nn_col2im3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* col,
                             float* dx, void* hip_stream);
 
-/* 3x3 convolution, zero padding 1, stride 1 or 2, as an implicit matrix-core product (the patch
- * matrix of msl_nn_im2col3x3 is formed tile by tile while loading, never stored):
+/* Scratch the two calls below need for their packed weights: bfloat16 elements (9 pad16(Co) pad16(C),
+ * pad16 rounding up to a multiple of 16), or 0 for invalid sizes. */
+int64_t msl_nn_conv3x3_scratch_elems(int32_t Co, int32_t C);
+
+/* 3x3 convolution, zero padding 1, stride 1 or 2, as an implicit matrix-core product on halo tiles
+ * (no patch matrix in memory):
  * y[o][b][i][j] = act(sum_c sum_t w16[o][9c + t] bf16(x[c][b][s i + dy][s j + dx]) + bias[o]),
  * t = 3 (dy + 1) + (dx + 1); x float32 [C][B][H][W], w16 bfloat16 [Co][9C], bias float32 [Co] or
- * NULL, relu 0/1, y float32 [Co][B][H/s][W/s].  Bit for bit the product of msl_nn_gemm_bf16 with
- * the patch matrix. */
+ * NULL, relu 0/1, y float32 [Co][B][H/s][W/s].  The products and sums are those of
+ * msl_nn_gemm_bf16 with the patch matrix, in another order (over taps, then channels in
+ * chunks of 16), so the two agree to float32 rounding.  wscratch: device, 16-byte aligned,
+ * msl_nn_conv3x3_scratch_elems(Co, C) bfloat16 elements, overwritten (the weights in
+ * [Co][9][pad16(C)] order); the call reads w16 once per call, not once per tile. */
 msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const uint16_t* w16,
-                          const float* x, const float* bias, int32_t relu, float* y, void* hip_stream);
+                          const float* x, const float* bias, int32_t relu, float* y, uint16_t* wscratch,
+                          void* hip_stream);
 
 /* Its input gradient, also implicit: dx[c][b][y][x] = sum over o and taps t of w16[o][9c + t] dy16[o][b][i][j]
  * where s i + dy = y and s j + dx = x (dy16 bfloat16 [Co][B][H/s][W/s]; dx float32 [C][B][H][W],
- * overwritten). */
+ * overwritten).  Stride 1 runs as a convolution of dy16 on halo tiles with the weights transposed
+ * and rotated by 180 degrees (packed into wscratch as for msl_nn_conv3x3; required then); stride 2
+ * as an implicit product over the patch columns (wscratch unused, may be NULL). */
 msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
-                                  const uint16_t* w16, const uint16_t* dy16, float* dx, void* hip_stream);
+                                  const uint16_t* w16, const uint16_t* dy16, float* dx, uint16_t* wscratch,
+                                  void* hip_stream);
 
 /* Its weight gradient, implicit as well: dw[o][9c + t] = sum over output pixels p of dy16[o][p] times the
  * patch value (c, t) at p (x rounded to bfloat16 as in the forward); the pixel sum is split into

@@ -415,6 +415,13 @@ __global__ void __launch_bounds__(256) k_conv_bwd_weight(ConvArgs a, int kchunk,
 // gfx950 32x32x16 bfloat16 instruction: each of the four wavefronts
 // accumulates a 32-row x 64-pixel part in two 32 x 32 float32 tiles.
 //
+// Staging: a thread reads four neighbouring positions of four channels (one
+// 16-byte read per channel, 16-byte aligned groups along the row), swaps the
+// 4 x 4 block in registers and writes each position's four channels as one
+// 8-byte LDS store.  The weights are first packed by k_pack_weights into
+// [row][tap][channel] order (channels padded to a multiple of 16), so a
+// workgroup stages them with 16-byte reads.
+//
 // The same kernel computes the input gradient of a stride-1 convolution: a
 // stride-1 convolution of the output gradient with the weights transposed
 // (input and output channels swapped) and rotated by 180 degrees (flip).
@@ -424,37 +431,60 @@ constexpr int HCKP = HCK + 8;   // bfloat16 slots per staged position: 48-byte s
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+__host__ __device__ inline int pad16(int n) { return (n + 15) / 16 * 16; }
+
+// wp[m][t][c] (c < pad16(Cin), zero beyond Cin) from w16 [Co][9 C]: flip 0 (rows m = o, Cin = C):
+// w16[m][9 c + t]; flip 1 (rows m = c, Cin = Co): w16[c][9 m + 8 - t].
+__global__ void __launch_bounds__(256) k_pack_weights(int Co, int C, int flip, const uint16_t* __restrict__ w16,
+                                                      uint16_t* __restrict__ wp) {
+  const int M = flip ? C : Co, Cin = flip ? Co : C, Cp = pad16(Cin);
+  const int64_t n = (int64_t)M * 9 * Cp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % Cp);
+    const int64_t mt = e / Cp;
+    const int t = (int)(mt % 9), m = (int)(mt / 9);
+    uint16_t v = 0;
+    if (c < Cin) v = flip ? w16[(int64_t)c * 9 * C + 9 * m + 8 - t] : w16[(int64_t)m * 9 * C + 9 * c + t];
+    wp[e] = v;
+  }
+}
+
 struct HaloArgs {
   int M;                 // output channels (rows of the product)
   int C;                 // input channels
   int B, H, W, s, Ho, Wo, relu;
   int TW, TH, tiles_x, tiles_y;
-  int flip;              // weights: 0 w16[m][9 c + tap]; 1 w16[c][9 m + 8 - tap] (input gradient)
-  int ldw;               // row length of w16
-  const uint16_t* w16;
+  int Cp;                // row length of wp per tap: pad16(C)
+  int vec;               // W a multiple of 4 and x aligned: whole 4-position groups read at once
+  const uint16_t* wp;    // packed weights [M][9][Cp] (k_pack_weights)
   const void* x;         // [C][B][H][W], float32 or (xbf16) bfloat16 bits
   const float* bias;     // [M] or nullptr
   float* y;              // [M][B][Ho][Wo]
 };
 
+// Four consecutive values of one channel row as bfloat16 bits: positions x0 .. x0+3 of row `row`
+// (zero outside [0, W)); a 16-byte (float) or 8-byte (bfloat16) read when all four are inside.
 template <bool XBF16>
-__device__ __forceinline__ uint16_t halo_in(const void* x, int64_t i) {
-  if constexpr (XBF16) return static_cast<const uint16_t*>(x)[i];
-  else return to_bf16(static_cast<const float*>(x)[i]);
-}
-
-__device__ __forceinline__ void lds_store16(uint16_t* dst, const uint16_t (&v)[16]) {
-  uint4 a, b;
-  a.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-  a.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-  a.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
-  a.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
-  b.x = (uint32_t)v[8] | ((uint32_t)v[9] << 16);
-  b.y = (uint32_t)v[10] | ((uint32_t)v[11] << 16);
-  b.z = (uint32_t)v[12] | ((uint32_t)v[13] << 16);
-  b.w = (uint32_t)v[14] | ((uint32_t)v[15] << 16);
-  *reinterpret_cast<uint4*>(dst) = a;
-  *reinterpret_cast<uint4*>(dst + 8) = b;
+__device__ __forceinline__ void load4(const void* x, int64_t row, int x0, int W, bool vec, uint16_t (&o)[4]) {
+  if constexpr (XBF16) {
+    const uint16_t* p = static_cast<const uint16_t*>(x) + row;
+    if (vec && x0 >= 0 && x0 + 3 < W) {
+      const uint2 u = *reinterpret_cast<const uint2*>(p + x0);
+      o[0] = (uint16_t)u.x; o[1] = (uint16_t)(u.x >> 16); o[2] = (uint16_t)u.y; o[3] = (uint16_t)(u.y >> 16);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = (x0 + i >= 0 && x0 + i < W) ? p[x0 + i] : (uint16_t)0;
+    }
+  } else {
+    const float* p = static_cast<const float*>(x) + row;
+    if (vec && x0 >= 0 && x0 + 3 < W) {
+      const float4 u = *reinterpret_cast<const float4*>(p + x0);
+      o[0] = to_bf16(u.x); o[1] = to_bf16(u.y); o[2] = to_bf16(u.z); o[3] = to_bf16(u.w);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = (x0 + i >= 0 && x0 + i < W) ? to_bf16(p[x0 + i]) : (uint16_t)0;
+    }
+  }
 }
 
 // LDS bytes of a halo workgroup: the weights [MT][9][16], then the staged positions [HH HW][HCKP].
@@ -475,9 +505,12 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
   t /= a.tiles_x;
   const int oy0 = (t % a.tiles_y) * a.TH;
   const int b = t / a.tiles_y;
-  const int HW = (a.TW - 1) * a.s + 3, HH = (a.TH - 1) * a.s + 3, NH = HH * HW;
+  const int HW = (a.TW - 1) * a.s + 3, HH = (a.TH - 1) * a.s + 3;
   const int iy0 = oy0 * a.s - 1, ix0 = ox0 * a.s - 1;
-  constexpr int MB = MT / 32;              // 32-row blocks per workgroup
+  // staged row = 4-position groups from xa (ix0 rounded down to a multiple of 4)
+  const int xa = ix0 & ~3, ngx = (ix0 + HW - xa + 3) >> 2, nitems = HH * ngx * 4;
+  const bool vec = a.vec != 0;
+  constexpr int MB = MT / 32;        // 32-row blocks per workgroup
   const int cb = wave % MB, pb = wave / MB;  // this wave's row block and 64-pixel block
   const int kq = 8 * (lane >> 5);
   // this lane's two pixels of the tile: n0 (first accumulator) and n0 + 32 (second)
@@ -488,33 +521,40 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
   const int64_t img = (int64_t)b * plane;
   f32x16 acc0 = {}, acc1 = {};
   for (int c0 = 0; c0 < a.C; c0 += HCK) {
-    for (int p = tid; p < NH; p += 256) {
-      const int hy = p / HW, hx = p - hy * HW;
-      const int yy = iy0 + hy, xx = ix0 + hx;
-      const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-      const int64_t e = img + (int64_t)yy * a.W + xx;
-      uint16_t v[16];
+    // input block: item = (row hy, group g, channel quad cq)
+    for (int it = tid; it < nitems; it += 256) {
+      const int cq = it & 3, rg = it >> 2;
+      const int hy = rg / ngx, g = rg - hy * ngx;
+      const int yy = iy0 + hy, xg = xa + 4 * g;
+      uint16_t v[4][4];   // [channel][position]
 #pragma unroll
-      for (int q = 0; q < HCK; ++q) {
-        const int c = c0 + q;
-        v[q] = (in && c < a.C) ? halo_in<XBF16>(a.x, (int64_t)c * cstride + e) : (uint16_t)0;
+      for (int k = 0; k < 4; ++k) {
+        const int c = c0 + 4 * cq + k;
+        if (yy >= 0 && yy < a.H && c < a.C) {
+          load4<XBF16>(a.x, (int64_t)c * cstride + img + (int64_t)yy * a.W, xg, a.W, vec, v[k]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[k][i] = 0;
+        }
       }
-      lds_store16(&xs[p * HCKP], v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int hx = xg + i - ix0;   // staged position in the row
+        if (hx >= 0 && hx < HW) {
+          uint2 u;
+          u.x = (uint32_t)v[0][i] | ((uint32_t)v[1][i] << 16);
+          u.y = (uint32_t)v[2][i] | ((uint32_t)v[3][i] << 16);
+          *reinterpret_cast<uint2*>(&xs[(hy * HW + hx) * HCKP + 4 * cq]) = u;
+        }
+      }
     }
+    // weights: MT rows x 9 taps x two 16-byte halves
     for (int e = tid; e < MT * 9 * 2; e += 256) {
       const int half = e & 1, mt = e >> 1;
-      const int m = mt / 9, tap = mt - 9 * m;
-      const int gm = m0 + m;
-      uint16_t v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int c = c0 + 8 * half + q;
-        uint16_t w = 0;
-        if (gm < a.M && c < a.C)
-          w = a.flip ? a.w16[(int64_t)c * a.ldw + 9 * gm + 8 - tap] : a.w16[(int64_t)gm * a.ldw + 9 * c + tap];
-        v[q] = w;
-      }
-      lds_store8(&ws[(m * 9 + tap) * HCK + 8 * half], v);
+      const int gm = m0 + mt / 9;
+      uint4 u = make_uint4(0u, 0u, 0u, 0u);
+      if (gm < a.M) u = *reinterpret_cast<const uint4*>(a.wp + ((int64_t)m0 * 9 + mt) * a.Cp + c0 + 8 * half);
+      *reinterpret_cast<uint4*>(&ws[mt * HCK + 8 * half]) = u;
     }
     __syncthreads();
 #pragma unroll
@@ -850,9 +890,10 @@ msl_status need(bool ok, const char* what) { return ok ? MSL_OK : fail(MSL_ERR_A
 msl_status launched(const char* what) { return hip_check(hipGetLastError(), what); }
 
 // Halo-tile shape of a convolution with M output rows and Ho x Wo outputs per image: rows per
-// workgroup 32, 64 or 128 (the fewest blocks, then the least padding), pixels 8192 / MT as a
-// TH x TW block, TW the largest power of two <= min(Wo, 64).
-msl_status launch_conv_halo(HaloArgs a, bool xbf16, hipStream_t st) {
+// workgroup 32, 64 or 128 (one block up to 128 rows), pixels 8192 / MT as a TH x TW block, TW the
+// largest power of two <= min(Wo, 64).  Packs the weights into wscratch first (k_pack_weights).
+msl_status launch_conv_halo(HaloArgs a, int Co, int C, int flip, const uint16_t* w16, uint16_t* wscratch, bool xbf16,
+                            hipStream_t st) {
   const int MT = a.M <= 32 ? 32 : (a.M <= 64 ? 64 : 128);
   const int NT = 8192 / MT;
   int TW = 1;
@@ -861,9 +902,14 @@ msl_status launch_conv_halo(HaloArgs a, bool xbf16, hipStream_t st) {
   a.TH = NT / TW;
   a.tiles_x = (a.Wo + a.TW - 1) / a.TW;
   a.tiles_y = (a.Ho + a.TH - 1) / a.TH;
+  a.Cp = pad16(a.C);
+  a.wp = wscratch;
+  a.vec = (a.W % 4 == 0 && aligned(a.x, xbf16 ? 8 : 16)) ? 1 : 0;
   const int64_t nx = (int64_t)a.tiles_x * a.tiles_y * a.B;
   const int lds = halo_lds_bytes(MT, a.TW, a.TH, a.s);
   MSL_TRY(need(nx < (1ll << 31) && (a.M + MT - 1) / MT <= 65535 && lds <= 64 * 1024, "conv: sizes too large"));
+  const int64_t npack = (int64_t)a.M * 9 * a.Cp;
+  hipLaunchKernelGGL(k_pack_weights, dim3(blocks_for(npack)), dim3(256), 0, st, Co, C, flip, w16, wscratch);
   const dim3 grid((unsigned)nx, (unsigned)((a.M + MT - 1) / MT));
   switch (MT * 2 + (xbf16 ? 1 : 0)) {
     case 64: hipLaunchKernelGGL((k_conv_halo<32, false>), grid, dim3(256), lds, st, a); break;
@@ -922,26 +968,32 @@ msl_status msl_nn_gemm_bf16_splitk(int32_t M, int32_t N, int32_t K, const uint16
   return launched("split gemm kernels");
 }
 
+int64_t msl_nn_conv3x3_scratch_elems(int32_t Co, int32_t C) {
+  if (Co < 1 || C < 1) return 0;
+  return (int64_t)9 * pad16(Co) * pad16(C);
+}
+
 msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const uint16_t* w16,
-                          const float* x, const float* bias, int32_t relu, float* y, void* hip_stream) {
+                          const float* x, const float* bias, int32_t relu, float* y, uint16_t* wscratch,
+                          void* hip_stream) {
   MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
                    W % stride == 0, "conv: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
   MSL_TRY(check_ptr(w16, 2, "w16"));
   MSL_TRY(check_ptr(x, 4, "x"));
   MSL_TRY(check_ptr(bias, 4, "bias", true));
   MSL_TRY(check_ptr(y, 4, "y"));
+  MSL_TRY(check_ptr(wscratch, 16, "wscratch"));
   MSL_TRY(need((int64_t)C * 9 < (1 << 30) && (int64_t)B * H * W < (1ll << 40), "conv: sizes too large"));
   HaloArgs a{};
   a.M = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
   a.relu = relu ? 1 : 0;
-  a.flip = 0;
-  a.ldw = C * 9;
-  a.w16 = w16; a.x = x; a.bias = bias; a.y = y;
-  return launch_conv_halo(a, false, static_cast<hipStream_t>(hip_stream));
+  a.x = x; a.bias = bias; a.y = y;
+  return launch_conv_halo(a, Co, C, 0, w16, wscratch, false, static_cast<hipStream_t>(hip_stream));
 }
 
 msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
-                                  const uint16_t* w16, const uint16_t* dy16, float* dx, void* hip_stream) {
+                                  const uint16_t* w16, const uint16_t* dy16, float* dx, uint16_t* wscratch,
+                                  void* hip_stream) {
   MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
                    W % stride == 0, "conv adjoint: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
   MSL_TRY(check_ptr(w16, 2, "w16"));
@@ -949,14 +1001,13 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
   MSL_TRY(check_ptr(dx, 4, "dx"));
   if (stride == 1) {
     // a stride-1 convolution of dy with the weights transposed and rotated (see k_conv_halo)
+    MSL_TRY(check_ptr(wscratch, 16, "wscratch"));
     MSL_TRY(need((int64_t)C * 9 < (1 << 30) && (int64_t)B * H * W < (1ll << 40), "conv adjoint: sizes too large"));
     HaloArgs h{};
     h.M = C; h.C = Co; h.B = B; h.H = H; h.W = W; h.s = 1; h.Ho = H; h.Wo = W;
     h.relu = 0;
-    h.flip = 1;
-    h.ldw = C * 9;
-    h.w16 = w16; h.x = dy16; h.bias = nullptr; h.y = dx;
-    return launch_conv_halo(h, true, static_cast<hipStream_t>(hip_stream));
+    h.x = dy16; h.bias = nullptr; h.y = dx;
+    return launch_conv_halo(h, Co, C, 1, w16, wscratch, true, static_cast<hipStream_t>(hip_stream));
   }
   ConvArgs a{};
   a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;

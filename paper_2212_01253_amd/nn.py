@@ -17,7 +17,8 @@ EXPORTS = ("msl_nn_gemm_bf16", "msl_nn_gemm_bf16_splitk", "msl_nn_im2col3x3", "m
            "msl_nn_upsample2_adjoint", "msl_nn_rowpool", "msl_nn_rowpool_adjoint", "msl_nn_relu_adjoint",
            "msl_nn_add", "msl_nn_to_bf16", "msl_nn_rowsum", "msl_nn_mse", "msl_nn_adam", "msl_nn_logmap",
            "msl_nn_render_pools", "msl_nn_pool_average", "msl_nn_row_features", "msl_nn_add_row_bias",
-           "msl_nn_row_bias_adjoint", "msl_nn_conv3x3", "msl_nn_conv3x3_adjoint", "msl_nn_conv3x3_weight_grad")
+           "msl_nn_row_bias_adjoint", "msl_nn_conv3x3", "msl_nn_conv3x3_adjoint", "msl_nn_conv3x3_weight_grad",
+           "msl_nn_conv3x3_scratch_elems")
 
 MAX_BOXES = 64   # MSL_NN_MAX_BOXES
 MAX_CUTS = 132   # MSL_NN_MAX_CUTS
@@ -52,14 +53,16 @@ def lib():
             "msl_nn_row_features": [I, I, I, P, P, P, P, P],
             "msl_nn_add_row_bias": [I, I, I, P, P, P],
             "msl_nn_row_bias_adjoint": [I, I, I, P, P, P],
-            "msl_nn_conv3x3": [I, I, I, I, I, I, P, P, P, I, P, P],
-            "msl_nn_conv3x3_adjoint": [I, I, I, I, I, I, P, P, P, P],
+            "msl_nn_conv3x3": [I, I, I, I, I, I, P, P, P, I, P, P, P],
+            "msl_nn_conv3x3_adjoint": [I, I, I, I, I, I, P, P, P, P, P],
             "msl_nn_conv3x3_weight_grad": [I, I, I, I, I, I, P, P, P, I, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.restype = c_int32
             f.argtypes = args
+        L.msl_nn_conv3x3_scratch_elems.restype = c_int64
+        L.msl_nn_conv3x3_scratch_elems.argtypes = [I, I]
         _ready = True
     return L
 
@@ -96,14 +99,30 @@ def gemm_splitk(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, splits, partial
                                       _p(C, torch.float32), ldc, int(splits), _p(partials, torch.float32), _s()))
 
 
-def conv3x3(Co, C, B, H, W, stride, w16, x, y, bias=None, relu=False):
+_scratch = {}
+
+
+def conv_scratch(Co, C, device):
+    """Packed-weight scratch of msl_nn_conv3x3 / _adjoint (msl_nn_conv3x3_scratch_elems), one growing
+    buffer per device, reused by every call on it (the calls of one stream run in order)."""
+    n = int(lib().msl_nn_conv3x3_scratch_elems(Co, C))
+    buf = _scratch.get(device)
+    if buf is None or buf.numel() < n:
+        buf = torch.empty(max(n, 1 << 16), dtype=BF16, device=device)
+        _scratch[device] = buf
+    return buf
+
+
+def conv3x3(Co, C, B, H, W, stride, w16, x, y, bias=None, relu=False, scratch=None):
+    ws = scratch if scratch is not None else conv_scratch(Co, C, x.device)
     _ck(lib().msl_nn_conv3x3(Co, C, B, H, W, stride, _p(w16, BF16), _p(x, torch.float32), _p(bias, torch.float32),
-                             int(relu), _p(y, torch.float32), _s()))
+                             int(relu), _p(y, torch.float32), _p(ws, BF16), _s()))
 
 
-def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx):
+def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx, scratch=None):
+    ws = scratch if scratch is not None else conv_scratch(Co, C, dx.device)
     _ck(lib().msl_nn_conv3x3_adjoint(Co, C, B, H, W, stride, _p(w16, BF16), _p(dy16, BF16), _p(dx, torch.float32),
-                                     _s()))
+                                     _p(ws, BF16), _s()))
 
 
 def conv3x3_weight_grad(Co, C, B, H, W, stride, dy16, x, dw, splits, partials):

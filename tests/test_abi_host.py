@@ -213,12 +213,16 @@ def test_nn_entry_points_validate(L):
     assert N.msl_nn_add_row_bias(0, 4, 8, FAKE, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_row_bias_adjoint(2, 0, 8, FAKE, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_row_bias_adjoint(2, 4, 8, None, FAKE, None) == msl.ERR_ARG
-    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 3, FAKE, FAKE, None, 0, FAKE, None) == msl.ERR_ARG      # stride 3
-    assert N.msl_nn_conv3x3(4, 3, 2, 9, 8, 2, FAKE, FAKE, None, 0, FAKE, None) == msl.ERR_ARG      # odd H, stride 2
-    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE + 1, FAKE, None, 0, FAKE, None) == msl.ERR_ARG  # misaligned
-    assert N.msl_nn_conv3x3(0, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, None) == msl.ERR_ARG
-    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, None, FAKE, None) == msl.ERR_ARG
-    assert N.msl_nn_conv3x3_adjoint(4, 0, 2, 8, 8, 1, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 3, FAKE, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG      # stride 3
+    assert N.msl_nn_conv3x3(4, 3, 2, 9, 8, 2, FAKE, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG      # odd H
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE + 1, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG  # misaligned
+    assert N.msl_nn_conv3x3(0, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, None, None) == msl.ERR_ARG      # no scratch
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, FAKE + 8, None) == msl.ERR_ARG  # misaligned
+    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, None, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3_adjoint(4, 0, 2, 8, 8, 1, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, None, None) == msl.ERR_ARG      # no scratch
+    assert N.msl_nn_conv3x3_scratch_elems(20, 3) == 9 * 32 * 16 and N.msl_nn_conv3x3_scratch_elems(0, 3) == 0
     assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 0, FAKE, None) == msl.ERR_ARG   # splits
     assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 2, None, None) == msl.ERR_ARG
 
