@@ -487,6 +487,45 @@ __device__ __forceinline__ void load4(const void* x, int64_t row, int x0, int W,
   }
 }
 
+// Stages channels c0 .. c0+CH-1 (zero beyond C) of the HH x HW input block whose corner is (iy0,
+// ix0) in image `img` (zero outside the image) into xs[(hy HW + hx) CHP + c] as bfloat16.  Item =
+// (row, 4-position group from ix0 rounded down to a multiple of 4, channel quad); each thread reads
+// the four positions of four channels (one 16- or 8-byte read per channel when vec and the group
+// lies inside the row), swaps the 4 x 4 block and writes each position's four channels as one
+// 8-byte LDS store.  All threads of the block call it.
+template <int CH, int CHP, bool XBF16>
+__device__ __forceinline__ void stage_block(uint16_t* xs, const void* x, int C, int c0, int64_t cstride, int64_t img,
+                                            int H, int W, int iy0, int ix0, int HH, int HW, bool vec) {
+  constexpr int NQ = CH / 4;
+  const int xa = ix0 & ~3, ngx = (ix0 + HW - xa + 3) >> 2, nitems = HH * ngx * NQ;
+  for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
+    const int cq = it % NQ, rg = it / NQ;
+    const int hy = rg / ngx, g = rg - hy * ngx;
+    const int yy = iy0 + hy, xg = xa + 4 * g;
+    uint16_t v[4][4];   // [channel][position]
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = c0 + 4 * cq + k;
+      if (yy >= 0 && yy < H && c < C) {
+        load4<XBF16>(x, (int64_t)c * cstride + img + (int64_t)yy * W, xg, W, vec, v[k]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[k][i] = 0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int hx = xg + i - ix0;   // staged position in the row
+      if (hx >= 0 && hx < HW) {
+        uint2 u;
+        u.x = (uint32_t)v[0][i] | ((uint32_t)v[1][i] << 16);
+        u.y = (uint32_t)v[2][i] | ((uint32_t)v[3][i] << 16);
+        *reinterpret_cast<uint2*>(&xs[(hy * HW + hx) * CHP + 4 * cq]) = u;
+      }
+    }
+  }
+}
+
 // LDS bytes of a halo workgroup: the weights [MT][9][16], then the staged positions [HH HW][HCKP].
 int halo_lds_bytes(int MT, int TW, int TH, int s) {
   const int HW = (TW - 1) * s + 3, HH = (TH - 1) * s + 3;
@@ -507,8 +546,6 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
   const int b = t / a.tiles_y;
   const int HW = (a.TW - 1) * a.s + 3, HH = (a.TH - 1) * a.s + 3;
   const int iy0 = oy0 * a.s - 1, ix0 = ox0 * a.s - 1;
-  // staged row = 4-position groups from xa (ix0 rounded down to a multiple of 4)
-  const int xa = ix0 & ~3, ngx = (ix0 + HW - xa + 3) >> 2, nitems = HH * ngx * 4;
   const bool vec = a.vec != 0;
   constexpr int MB = MT / 32;        // 32-row blocks per workgroup
   const int cb = wave % MB, pb = wave / MB;  // this wave's row block and 64-pixel block
@@ -521,33 +558,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
   const int64_t img = (int64_t)b * plane;
   f32x16 acc0 = {}, acc1 = {};
   for (int c0 = 0; c0 < a.C; c0 += HCK) {
-    // input block: item = (row hy, group g, channel quad cq)
-    for (int it = tid; it < nitems; it += 256) {
-      const int cq = it & 3, rg = it >> 2;
-      const int hy = rg / ngx, g = rg - hy * ngx;
-      const int yy = iy0 + hy, xg = xa + 4 * g;
-      uint16_t v[4][4];   // [channel][position]
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = c0 + 4 * cq + k;
-        if (yy >= 0 && yy < a.H && c < a.C) {
-          load4<XBF16>(a.x, (int64_t)c * cstride + img + (int64_t)yy * a.W, xg, a.W, vec, v[k]);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) v[k][i] = 0;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int hx = xg + i - ix0;   // staged position in the row
-        if (hx >= 0 && hx < HW) {
-          uint2 u;
-          u.x = (uint32_t)v[0][i] | ((uint32_t)v[1][i] << 16);
-          u.y = (uint32_t)v[2][i] | ((uint32_t)v[3][i] << 16);
-          *reinterpret_cast<uint2*>(&xs[(hy * HW + hx) * HCKP + 4 * cq]) = u;
-        }
-      }
-    }
+    stage_block<HCK, HCKP, XBF16>(xs, a.x, a.C, c0, cstride, img, a.H, a.W, iy0, ix0, HH, HW, vec);
     // weights: MT rows x 9 taps x two 16-byte halves
     for (int e = tid; e < MT * 9 * 2; e += 256) {
       const int half = e & 1, mt = e >> 1;
@@ -589,6 +600,122 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
   };
   store(acc0, ty0, tx0);
   store(acc1, ty1, tx1);
+}
+
+// Weight gradient on halo tiles: dw[o][9c + t] = sum over output pixels p of dy[o][p] times the
+// input value of channel c under tap t of p (rounded to bfloat16 as in the forward).  A workgroup of
+// three wavefronts owns 32 input channels x 32 output channels and a range of spatial tiles (its
+// part of the pixel sum); wavefront r computes the three taps of kernel row r.  Per tile it stages
+// the input block of its 32 channels (stage_block, positions channel-contiguous) and the output
+// gradient of its 32 output channels at the tile's pixels ([o][pixel]); k runs over the pixels, 16
+// per 32x32x16 MFMA: A = the channels' values under the tap at 16 pixels (8 per lane, gathered from
+// the staged positions), B = dy at those pixels (8 consecutive per lane, one 16-byte LDS read).
+constexpr int WCK = 32;        // input channels per workgroup
+constexpr int WCKP = WCK + 4;  // staged position stride (bfloat16): 72 bytes
+constexpr int WOC = 32;        // output channels per workgroup
+
+struct WgradArgs {
+  int Co, C, B, H, W, s, Ho, Wo;
+  int TW, TH, KT, tiles_x, tiles_y, ntiles, per_part;
+  int vec;
+  const uint16_t* dy16;  // [Co][B][Ho][Wo]
+  const float* x;        // [C][B][H][W]
+  float* partials;       // [parts][Co][9C]
+};
+
+// bfloat16 slots of the staged input block, rounded up to 16 bytes (the dy tile after it is read
+// with 16-byte accesses)
+__host__ __device__ inline int wgrad_xs_slots(int TW, int TH, int s) {
+  const int HW = (TW - 1) * s + 3, HH = (TH - 1) * s + 3;
+  return (HH * HW * WCKP + 7) / 8 * 8;
+}
+
+int wgrad_lds_bytes(int TW, int TH, int s) {
+  return (wgrad_xs_slots(TW, TH, s) + WOC * (TW * TH + 8)) * (int)sizeof(uint16_t);
+}
+
+__global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t wg_smem[];
+  const int HW = (a.TW - 1) * a.s + 3, HH = (a.TH - 1) * a.s + 3;
+  const int DKP = a.KT + 8;                         // row stride of the staged dy tile
+  uint16_t* const xs = wg_smem;                     // [HH * HW][WCKP]
+  uint16_t* const dys = wg_smem + wgrad_xs_slots(a.TW, a.TH, a.s);   // [WOC][DKP]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int c0 = blockIdx.x * WCK, o0 = blockIdx.y * WOC, part = blockIdx.z;
+  const int kq = 8 * (lane >> 5);
+  const int64_t plane = (int64_t)a.H * a.W, cstride = (int64_t)a.B * plane;
+  const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
+  const bool vec = a.vec != 0;
+  const bool dvec = (a.Wo & 7) == 0 && (reinterpret_cast<uintptr_t>(a.dy16) & 15) == 0;
+  f32x16 acc0 = {}, acc1 = {}, acc2 = {};
+  const int t0 = part * a.per_part, t1 = min(a.ntiles, t0 + a.per_part);
+  for (int tile = t0; tile < t1; ++tile) {
+    int t = tile;
+    const int ox0 = (t % a.tiles_x) * a.TW;
+    t /= a.tiles_x;
+    const int oy0 = (t % a.tiles_y) * a.TH;
+    const int b = t / a.tiles_y;
+    const int iy0 = oy0 * a.s - 1, ix0 = ox0 * a.s - 1;
+    stage_block<WCK, WCKP, false>(xs, a.x, a.C, c0, cstride, (int64_t)b * plane, a.H, a.W, iy0, ix0, HH, HW, vec);
+    // dy tile: item = (output channel, 8-pixel group of a tile row)
+    const int ng = a.KT / 8;
+    for (int it = tid; it < WOC * ng; it += blockDim.x) {
+      const int oc = it / ng, g = it - oc * ng;
+      const int n = 8 * g, ty = n / a.TW, tx = n - ty * a.TW;
+      const int o = o0 + oc, oy = oy0 + ty, ox = ox0 + tx;
+      uint4 u = make_uint4(0u, 0u, 0u, 0u);
+      if (o < a.Co && oy < a.Ho) {
+        const uint16_t* src = a.dy16 + (int64_t)o * npix + ((int64_t)b * a.Ho + oy) * a.Wo;
+        if (dvec && ox + 7 < a.Wo) {
+          u = *reinterpret_cast<const uint4*>(src + ox);
+        } else {
+          uint16_t v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = ox + q < a.Wo ? src[ox + q] : (uint16_t)0;
+          u.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+          u.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+          u.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+          u.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+        }
+      }
+      *reinterpret_cast<uint4*>(&dys[oc * DKP + n]) = u;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < a.KT; k0 += 16) {
+      const int n = k0 + kq;                         // this lane's 8 pixels: n .. n+7, one tile row
+      const int ty = n / a.TW, tx = n - ty * a.TW;
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&dys[(lane & 31) * DKP + n]);
+      const int base = ((ty * a.s + wave) * HW + tx * a.s) * WCKP + (lane & 31);
+      const int step = a.s * WCKP;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        bf16x8 av;
+        const uint16_t* src = xs + base + dx * WCKP;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) av[i] = __builtin_bit_cast(__bf16, src[i * step]);
+        if (dx == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc0, 0, 0, 0);
+        else if (dx == 1) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc1, 0, 0, 0);
+        else acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc2, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // accumulator element 4i + j of lane l: channel row 8i + 4 (l / 32) + j, output channel l mod 32
+  const int o = o0 + (lane & 31);
+  if (o >= a.Co) return;
+  const int NC = 9 * a.C;
+  float* const P = a.partials + ((int64_t)part * a.Co + o) * NC;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + 8 * i + 4 * (lane >> 5) + j;
+      if (c < a.C) {
+        P[9 * c + 3 * wave + 0] = acc0[4 * i + j];
+        P[9 * c + 3 * wave + 1] = acc1[4 * i + j];
+        P[9 * c + 3 * wave + 2] = acc2[4 * i + j];
+      }
+    }
 }
 
 // C[i] = sum over the parts s of P[s][i], in order
@@ -1031,6 +1158,37 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
   MSL_TRY(check_ptr(x, 4, "x"));
   MSL_TRY(check_ptr(dw, 4, "dw"));
   MSL_TRY(check_ptr(partials, 4, "partials"));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((W / stride) % 8 == 0) {
+    // halo tiles (k_conv_wgrad_halo): 256 / s pixels per tile, as TH x TW, TW <= 64
+    WgradArgs w{};
+    w.Co = Co; w.C = C; w.B = B; w.H = H; w.W = W; w.s = stride; w.Ho = H / stride; w.Wo = W / stride;
+    int TW = 8;
+    while (2 * TW <= std::min(w.Wo, 64)) TW *= 2;
+    w.TW = TW;
+    w.KT = 256 / stride;
+    w.TH = w.KT / TW;
+    w.tiles_x = (w.Wo + TW - 1) / TW;
+    w.tiles_y = (w.Ho + w.TH - 1) / w.TH;
+    const int64_t ntiles = (int64_t)w.tiles_x * w.tiles_y * B;
+    MSL_TRY(need(ntiles < (1ll << 31) && (int64_t)C * 9 < (1 << 30), "conv weight gradient: sizes too large"));
+    w.ntiles = (int)ntiles;
+    const int cb = (C + WCK - 1) / WCK, ob = (Co + WOC - 1) / WOC;
+    // parts: at most `splits`, enough workgroups to fill the GPU (about 2048), at least one tile each
+    int parts = std::min<int64_t>(splits, ntiles);
+    parts = std::max(1, std::min(parts, (2048 + cb * ob - 1) / (cb * ob)));
+    w.per_part = (int)((ntiles + parts - 1) / parts);
+    parts = (int)((ntiles + w.per_part - 1) / w.per_part);
+    w.vec = (W % 4 == 0 && aligned(x, 16)) ? 1 : 0;
+    w.dy16 = dy16; w.x = x; w.partials = partials;
+    const int lds = wgrad_lds_bytes(w.TW, w.TH, stride);
+    MSL_TRY(need(lds <= 64 * 1024 && cb <= 65535 && ob <= 65535, "conv weight gradient: sizes too large"));
+    hipLaunchKernelGGL(k_conv_wgrad_halo, dim3(cb, ob, parts), dim3(192), lds, st, w);
+    const int64_t mn = (int64_t)Co * 9 * C;
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, Co, 9 * C, 9 * C,
+                       dw);
+    return launched("conv weight gradient kernels");
+  }
   ConvArgs a{};
   a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
   a.dy16 = dy16; a.x = x;
@@ -1044,7 +1202,6 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
   const int NC = C * 9;
   const dim3 grid((unsigned)((NC + TN - 1) / TN), (unsigned)((Co + TM - 1) / TM), (unsigned)parts);
   MSL_TRY(need(grid.y <= 65535 && grid.z <= 65535, "conv weight gradient: too many channels or parts"));
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(k_conv_bwd_weight, grid, dim3(256), 0, st, a, (int)kchunk, partials);
   const int64_t mn = (int64_t)Co * NC;
   hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, Co, NC, NC, dw);

@@ -35,7 +35,7 @@ import torch
 from . import msl, nn, synth
 
 BF16 = nn.BF16
-SPLIT_PARTS = 512   # most parts of a split weight-gradient product
+SPLIT_PARTS = 2048  # most parts of a split weight-gradient product
 
 
 def layer_specs(c=32, in_ch=2):

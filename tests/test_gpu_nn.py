@@ -89,13 +89,15 @@ def test_convolution_through_patches_matches_the_oracle(T, s):
 
 @pytest.mark.parametrize("C,B,H,W,O,s", [(5, 2, 12, 8, 7, 1), (5, 2, 12, 8, 7, 2), (2, 3, 16, 16, 70, 1),
                                          (16, 2, 8, 24, 9, 2), (8, 1, 32, 32, 4, 1), (20, 2, 6, 72, 130, 1),
-                                         (33, 1, 10, 40, 40, 2), (130, 1, 9, 70, 17, 1), (3, 2, 64, 64, 1, 1)])
+                                         (33, 1, 10, 40, 40, 2), (130, 1, 9, 70, 17, 1), (3, 2, 64, 64, 1, 1),
+                                         (24, 2, 20, 48, 40, 2)])
 def test_implicit_convolution(T, C, B, H, W, O, s):
-    # the forward product on halo tiles sums over (tap, channel) in another order than the explicit
-    # one (patch matrix, then product), so the two agree to float32 rounding and both match the
-    # oracle; the split weight-gradient product equals the explicit split product bit for bit; the
-    # input gradient matches the oracle.  Shapes cover ragged tiles (widths 24, 40, 70, 72), channel
-    # counts that are not multiples of the 16-channel chunk and row counts over one 128-row block.
+    # the products on halo tiles sum in another order than the explicit ones (patch matrix, then
+    # product; split product for the weight gradient), so the two agree to float32 rounding, and all
+    # match the oracle; so does the input gradient.  Shapes cover ragged tiles (output widths 24, 40,
+    # 70, 72; heights not multiples of the tile), channel counts that are not multiples of the 16- or
+    # 32-channel chunks, row counts over one 128-row block, and both weight-gradient paths (halo
+    # tiles when the output width is a multiple of 8, the patch-column product otherwise).
     import torch
     rng = np.random.default_rng(C * 100 + O)
     x = rng.standard_normal((C, B, H, W)).astype(np.float32)
@@ -123,7 +125,7 @@ def test_implicit_convolution(T, C, B, H, W, O, s):
     T.conv3x3_weight_grad(O, C, B, H, W, s, dy16, dev(x), dw, splits, parts)
     torch.cuda.synchronize()
     assert rel(y.cpu().numpy(), y_exp.cpu().numpy()) <= 1e-6
-    assert np.array_equal(dw.cpu().numpy(), dw_exp.cpu().numpy())
+    assert rel(dw.cpu().numpy(), dw_exp.cpu().numpy()) <= 1e-6
     ref = np.maximum(N.conv3x3(N.bf16(x), wb, bias, s), 0.0)
     rdx, rdw, _ = N.conv3x3_adjoint(N.bf16(x), wb, dy, s)
     assert rel(y.cpu().numpy(), ref) <= 1e-6
