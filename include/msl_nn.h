@@ -54,7 +54,7 @@ msl_status msl_nn_im2col3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t 
 msl_status msl_nn_col2im3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const float* col,
                             float* dx, void* hip_stream);
 
-/* Scratch the two calls below need for their packed weights: bfloat16 elements (9 pad16(Co) pad16(C),
+/* Scratch the two calls below need for their packed weights: bfloat16 elements (16 pad16(Co) pad16(C),
  * pad16 rounding up to a multiple of 16), or 0 for invalid sizes. */
 int64_t msl_nn_conv3x3_scratch_elems(int32_t Co, int32_t C);
 
@@ -73,9 +73,11 @@ msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W
 
 /* Its input gradient, also implicit: dx[c][b][y][x] = sum over o and taps t of w16[o][9c + t] dy16[o][b][i][j]
  * where s i + dy = y and s j + dx = x (dy16 bfloat16 [Co][B][H/s][W/s]; dx float32 [C][B][H][W],
- * overwritten).  Stride 1 runs as a convolution of dy16 on halo tiles with the weights transposed
- * and rotated by 180 degrees (packed into wscratch as for msl_nn_conv3x3; required then); stride 2
- * as an implicit product over the patch columns (wscratch unused, may be NULL). */
+ * overwritten).  Runs on halo tiles with the weights repacked into wscratch (required): stride 1 as
+ * a convolution of dy16 with the weights transposed and rotated by 180 degrees; stride 2 (dx 8-byte
+ * aligned) split by the parity of (y, x) into a 2x2 convolution of dy16 with 4 C rows (zero weights
+ * where a parity class has no tap).  A stride-2 call with dx not 8-byte aligned runs as an implicit
+ * product over the patch columns instead. */
 msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
                                   const uint16_t* w16, const uint16_t* dy16, float* dx, uint16_t* wscratch,
                                   void* hip_stream);
@@ -83,7 +85,7 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
 /* Its weight gradient, implicit as well: dw[o][9c + t] = sum over output pixels p of dy16[o][p] times the
  * patch value (c, t) at p (x rounded to bfloat16 as in the forward); the pixel sum is split into at
  * most `splits` parts written to partials (float32 [splits][Co][9C], caller-owned scratch) and then
- * summed in order into dw (float32 [Co][9C]).  When the output width W/s is a multiple of 8 the parts
+ * summed in a fixed order into dw (float32 [Co][9C]).  When the output width W/s is a multiple of 8 the parts
  * are ranges of 256/s-pixel halo tiles (as many parts as fill the GPU, at most `splits`), otherwise
  * ranges of pixels of the patch-column product (msl_nn_gemm_bf16_splitk of dy16 and the patch
  * matrix, bit for bit).  1 <= splits <= 4096. */

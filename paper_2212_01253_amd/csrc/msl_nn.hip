@@ -433,18 +433,34 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __host__ __device__ inline int pad16(int n) { return (n + 15) / 16 * 16; }
 
-// wp[m][t][c] (c < pad16(Cin), zero beyond Cin) from w16 [Co][9 C]: flip 0 (rows m = o, Cin = C):
-// w16[m][9 c + t]; flip 1 (rows m = c, Cin = Co): w16[c][9 m + 8 - t].
-__global__ void __launch_bounds__(256) k_pack_weights(int Co, int C, int flip, const uint16_t* __restrict__ w16,
+// wp[m][t][c] (c < pad16(Cin), zero beyond Cin) from w16 [Co][9 C]:
+//   mode 0 (rows m = o, Cin = C, 9 taps): w16[m][9 c + t];
+//   mode 1 (rows m = c, Cin = Co, 9 taps): w16[c][9 m + 8 - t] (stride-1 input gradient);
+//   mode 2 (rows m = 4c + 2py + px, Cin = Co, 4 taps t = 2a + b): w16[c][9 c' + 3 k(py, a) + k(px, b)]
+//   with c' the row's channel, zero where k has no tap (stride-2 input gradient, sub-pixel form).
+__device__ __forceinline__ int sub_tap(int p, int a) { return p == 0 ? (a == 0 ? 1 : -1) : (a == 0 ? 2 : 0); }
+
+__global__ void __launch_bounds__(256) k_pack_weights(int Co, int C, int mode, const uint16_t* __restrict__ w16,
                                                       uint16_t* __restrict__ wp) {
-  const int M = flip ? C : Co, Cin = flip ? Co : C, Cp = pad16(Cin);
-  const int64_t n = (int64_t)M * 9 * Cp;
+  const int M = mode == 0 ? Co : (mode == 1 ? C : 4 * C), Cin = mode == 0 ? C : Co, Cp = pad16(Cin);
+  const int ntap = mode == 2 ? 4 : 9;
+  const int64_t n = (int64_t)M * ntap * Cp;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(e % Cp);
     const int64_t mt = e / Cp;
-    const int t = (int)(mt % 9), m = (int)(mt / 9);
+    const int t = (int)(mt % ntap), m = (int)(mt / ntap);
     uint16_t v = 0;
-    if (c < Cin) v = flip ? w16[(int64_t)c * 9 * C + 9 * m + 8 - t] : w16[(int64_t)m * 9 * C + 9 * c + t];
+    if (c < Cin) {
+      if (mode == 0) {
+        v = w16[(int64_t)m * 9 * C + 9 * c + t];
+      } else if (mode == 1) {
+        v = w16[(int64_t)c * 9 * C + 9 * m + 8 - t];
+      } else {
+        const int ch = m >> 2, py = (m >> 1) & 1, px = m & 1;
+        const int ky = sub_tap(py, t >> 1), kx = sub_tap(px, t & 1);
+        if (ky >= 0 && kx >= 0) v = w16[(int64_t)c * 9 * C + 9 * ch + 3 * ky + kx];
+      }
+    }
     wp[e] = v;
   }
 }
@@ -526,17 +542,26 @@ __device__ __forceinline__ void stage_block(uint16_t* xs, const void* x, int C, 
   }
 }
 
-// LDS bytes of a halo workgroup: the weights [MT][9][16], then the staged positions [HH HW][HCKP].
-int halo_lds_bytes(int MT, int TW, int TH, int s) {
-  const int HW = (TW - 1) * s + 3, HH = (TH - 1) * s + 3;
-  return (MT * 9 * HCK + HH * HW * HCKP) * (int)sizeof(uint16_t);
+// LDS bytes of a halo workgroup: the weights [MT][NTAP][16], then the staged positions [HH HW][HCKP].
+int halo_lds_bytes(int MT, int TW, int TH, int s, bool sub) {
+  const int HW = sub ? TW + 1 : (TW - 1) * s + 3, HH = sub ? TH + 1 : (TH - 1) * s + 3;
+  return (MT * (sub ? 4 : 9) * HCK + HH * HW * HCKP) * (int)sizeof(uint16_t);
 }
 
-template <int MT, bool XBF16>
+// SUB = false: the 3x3 convolution of stride a.s described above.  SUB = true: the input gradient
+// of a stride-2 convolution split by output parity (sub-pixel form).  Input position (2u + py,
+// 2v + px) receives dy[u + a][v + b] through the weight of tap (ky, kx) = (k(py, a), k(px, b)),
+// a, b in {0, 1}, k(0, 0) = 1, k(1, 0) = 2, k(1, 1) = 0 (k(0, 1): no tap); so the gradient is a
+// stride-1 2x2 convolution over dy (window corner at (u, v)) with 4 C rows, row 4c + 2py + px,
+// whose packed weights are zero where there is no tap.  The four rows of a channel land in one
+// lane's accumulator (elements 4i + j, j = 2py + px), which writes the 2 x 2 block of dx at
+// (2u, 2v) as two 8-byte stores.  a.Ho, a.Wo are then the half-resolution grid (dy's size).
+template <int MT, bool XBF16, bool SUB>
 __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
+  constexpr int NTAP = SUB ? 4 : 9;
   extern __shared__ __attribute__((aligned(16))) uint16_t halo_smem[];
-  uint16_t* const ws = halo_smem;                   // [MT][9][HCK]
-  uint16_t* const xs = halo_smem + MT * 9 * HCK;    // [HH * HW][HCKP]
+  uint16_t* const ws = halo_smem;                     // [MT][NTAP][HCK]
+  uint16_t* const xs = halo_smem + MT * NTAP * HCK;   // [HH * HW][HCKP]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int m0 = blockIdx.y * MT;
   int t = blockIdx.x;
@@ -544,8 +569,9 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
   t /= a.tiles_x;
   const int oy0 = (t % a.tiles_y) * a.TH;
   const int b = t / a.tiles_y;
-  const int HW = (a.TW - 1) * a.s + 3, HH = (a.TH - 1) * a.s + 3;
-  const int iy0 = oy0 * a.s - 1, ix0 = ox0 * a.s - 1;
+  const int s = SUB ? 1 : a.s;
+  const int HW = SUB ? a.TW + 1 : (a.TW - 1) * s + 3, HH = SUB ? a.TH + 1 : (a.TH - 1) * s + 3;
+  const int iy0 = SUB ? oy0 : oy0 * s - 1, ix0 = SUB ? ox0 : ox0 * s - 1;
   const bool vec = a.vec != 0;
   constexpr int MB = MT / 32;        // 32-row blocks per workgroup
   const int cb = wave % MB, pb = wave / MB;  // this wave's row block and 64-pixel block
@@ -553,25 +579,26 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
   // this lane's two pixels of the tile: n0 (first accumulator) and n0 + 32 (second)
   const int n0 = pb * 64 + (lane & 31), n1 = n0 + 32;
   const int ty0 = n0 / a.TW, tx0 = n0 - ty0 * a.TW, ty1 = n1 / a.TW, tx1 = n1 - ty1 * a.TW;
-  const int hoff0 = (ty0 * HW + tx0) * a.s, hoff1 = (ty1 * HW + tx1) * a.s;
+  const int hoff0 = (ty0 * HW + tx0) * s, hoff1 = (ty1 * HW + tx1) * s;
   const int64_t plane = (int64_t)a.H * a.W, cstride = (int64_t)a.B * plane;
   const int64_t img = (int64_t)b * plane;
   f32x16 acc0 = {}, acc1 = {};
   for (int c0 = 0; c0 < a.C; c0 += HCK) {
     stage_block<HCK, HCKP, XBF16>(xs, a.x, a.C, c0, cstride, img, a.H, a.W, iy0, ix0, HH, HW, vec);
-    // weights: MT rows x 9 taps x two 16-byte halves
-    for (int e = tid; e < MT * 9 * 2; e += 256) {
+    // weights: MT rows x NTAP taps x two 16-byte halves
+    for (int e = tid; e < MT * NTAP * 2; e += 256) {
       const int half = e & 1, mt = e >> 1;
-      const int gm = m0 + mt / 9;
+      const int gm = m0 + mt / NTAP;
       uint4 u = make_uint4(0u, 0u, 0u, 0u);
-      if (gm < a.M) u = *reinterpret_cast<const uint4*>(a.wp + ((int64_t)m0 * 9 + mt) * a.Cp + c0 + 8 * half);
+      if (gm < a.M) u = *reinterpret_cast<const uint4*>(a.wp + ((int64_t)m0 * NTAP + mt) * a.Cp + c0 + 8 * half);
       *reinterpret_cast<uint4*>(&ws[mt * HCK + 8 * half]) = u;
     }
     __syncthreads();
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int sh = (tap / 3) * HW + tap % 3;
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&ws[((cb * 32 + (lane & 31)) * 9 + tap) * HCK + kq]);
+    for (int tap = 0; tap < NTAP; ++tap) {
+      const int sh = SUB ? (tap >> 1) * HW + (tap & 1) : (tap / 3) * HW + tap % 3;
+      const bf16x8 av =
+          *reinterpret_cast<const bf16x8*>(&ws[((cb * 32 + (lane & 31)) * NTAP + tap) * HCK + kq]);
       const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&xs[(hoff0 + sh) * HCKP + kq]);
       const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&xs[(hoff1 + sh) * HCKP + kq]);
       acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
@@ -580,23 +607,39 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
     __syncthreads();
   }
   // accumulator element 4i + j of lane l: row 8i + 4 (l / 32) + j, pixel l mod 32 of the 32 x 32 tile
-  const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
   auto store = [&](const f32x16& acc, int ty, int tx) {
     const int oy = oy0 + ty, ox = ox0 + tx;
     if (oy >= a.Ho || ox >= a.Wo) return;
-    const int64_t o = ((int64_t)b * a.Ho + oy) * a.Wo + ox;
+    if constexpr (SUB) {
+      // rows 4c + j: channel c = (row block + 8i + 4 (l / 32)) / 4, parity class j
+      const int W2 = 2 * a.Wo;
+      const int64_t npix2 = (int64_t)a.B * 4 * a.Ho * a.Wo;
+      const int64_t o = ((int64_t)b * 2 * a.Ho + 2 * oy) * W2 + 2 * ox;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = m0 + cb * 32 + 8 * i + 4 * (lane >> 5) + j;
-        if (m < a.M) {
-          float v = acc[4 * i + j];
-          if (a.bias) v += a.bias[m];
-          if (a.relu) v = fmaxf(v, 0.0f);
-          a.y[(int64_t)m * npix + o] = v;
+      for (int i = 0; i < 4; ++i) {
+        const int c = (m0 + cb * 32 + 8 * i + 4 * (lane >> 5)) >> 2;
+        if (4 * c < a.M) {
+          float* const d = a.y + (int64_t)c * npix2 + o;
+          *reinterpret_cast<float2*>(d) = make_float2(acc[4 * i + 0], acc[4 * i + 1]);
+          *reinterpret_cast<float2*>(d + W2) = make_float2(acc[4 * i + 2], acc[4 * i + 3]);
         }
       }
+    } else {
+      const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
+      const int64_t o = ((int64_t)b * a.Ho + oy) * a.Wo + ox;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int m = m0 + cb * 32 + 8 * i + 4 * (lane >> 5) + j;
+          if (m < a.M) {
+            float v = acc[4 * i + j];
+            if (a.bias) v += a.bias[m];
+            if (a.relu) v = fmaxf(v, 0.0f);
+            a.y[(int64_t)m * npix + o] = v;
+          }
+        }
+    }
   };
   store(acc0, ty0, tx0);
   store(acc1, ty1, tx1);
@@ -718,12 +761,31 @@ __global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
     }
 }
 
-// C[i] = sum over the parts s of P[s][i], in order
+// C[i] = sum over the parts s of P[s][i].  A workgroup takes 16 consecutive elements; its 16 thread
+// slices each sum the parts s = slice, slice + 16, ... of every element (four independent loads in
+// flight per thread), then slice sums are added in slice order, so the result does not depend on the
+// launch and many parts over few elements still fill the GPU.
 __global__ void __launch_bounds__(256) k_sum_parts(int64_t mn, int parts, const float* __restrict__ P, int M, int N,
                                                    int ldc, float* __restrict__ C) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+  __shared__ float part_sum[16][17];
+  const int ei = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + ei;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  if (e < mn) {
+    int s = sl;
+    for (; s + 48 < parts; s += 64) {
+      a0 += P[(int64_t)s * mn + e];
+      a1 += P[(int64_t)(s + 16) * mn + e];
+      a2 += P[(int64_t)(s + 32) * mn + e];
+      a3 += P[(int64_t)(s + 48) * mn + e];
+    }
+    for (; s < parts; s += 16) a0 += P[(int64_t)s * mn + e];
+  }
+  part_sum[sl][ei] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (sl == 0 && e < mn) {
     float acc = 0.0f;
-    for (int s = 0; s < parts; ++s) acc += P[(int64_t)s * mn + e];
+    for (int q = 0; q < 16; ++q) acc += part_sum[q][ei];
     C[(e / N) * ldc + e % N] = acc;
   }
 }
@@ -784,24 +846,44 @@ __global__ void __launch_bounds__(256) k_col2im(int C, int B, int H, int W, int 
   }
 }
 
-__global__ void __launch_bounds__(256) k_upsample2(int64_t total, int H, int W, const float* __restrict__ x,
+// Nearest 2x upsampling, one thread per input element x[r][w] (r over C B H rows): it writes the
+// 2 x 2 block y[2r + d][2w .. 2w+1] (output row 2r + d of [C][B][2H][2W] is row r's copy d), as
+// 8-byte stores when y is 8-byte aligned.  IDX: the index type (32-bit when the sizes allow).
+template <typename IDX>
+__global__ void __launch_bounds__(256) k_upsample2(IDX total, int W, int vec, const float* __restrict__ x,
                                                    float* __restrict__ y) {
-  // total = C * B * (2H) * (2W) output elements
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int X = (int)(e % (2 * W)), Y = (int)((e / (2 * W)) % (2 * H));
-    const int64_t cb = e / ((int64_t)4 * H * W);
-    y[e] = x[(cb * H + Y / 2) * W + X / 2];
+  for (IDX e = (IDX)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (IDX)gridDim.x * blockDim.x) {
+    const IDX r = e / W, w = e - r * W;
+    const float v = x[e];
+    float* const o = y + 2 * r * (2 * (IDX)W) + 2 * w;
+    if (vec) {
+      *reinterpret_cast<float2*>(o) = make_float2(v, v);
+      *reinterpret_cast<float2*>(o + 2 * W) = make_float2(v, v);
+    } else {
+      o[0] = v;
+      o[1] = v;
+      o[2 * W] = v;
+      o[2 * W + 1] = v;
+    }
   }
 }
 
-__global__ void __launch_bounds__(256) k_upsample2_adj(int64_t total, int H, int W, const float* __restrict__ dy,
+// Its adjoint: dx[r][w] = (dy[2r][2w] + dy[2r][2w+1]) + (dy[2r+1][2w] + dy[2r+1][2w+1]).
+template <typename IDX>
+__global__ void __launch_bounds__(256) k_upsample2_adj(IDX total, int W, int vec, const float* __restrict__ dy,
                                                        float* __restrict__ dx) {
-  // total = C * B * H * W input elements
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e % W), i = (int)((e / W) % H);
-    const int64_t cb = e / ((int64_t)H * W);
-    const float* p = dy + (cb * 2 * H + 2 * i) * (2 * W) + 2 * j;
-    dx[e] = (p[0] + p[1]) + (p[2 * W] + p[2 * W + 1]);
+  for (IDX e = (IDX)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (IDX)gridDim.x * blockDim.x) {
+    const IDX r = e / W, w = e - r * W;
+    const float* const p = dy + 2 * r * (2 * (IDX)W) + 2 * w;
+    float2 a, b;
+    if (vec) {
+      a = *reinterpret_cast<const float2*>(p);
+      b = *reinterpret_cast<const float2*>(p + 2 * W);
+    } else {
+      a = make_float2(p[0], p[1]);
+      b = make_float2(p[2 * W], p[2 * W + 1]);
+    }
+    dx[e] = (a.x + a.y) + (b.x + b.y);
   }
 }
 
@@ -1018,9 +1100,11 @@ msl_status launched(const char* what) { return hip_check(hipGetLastError(), what
 
 // Halo-tile shape of a convolution with M output rows and Ho x Wo outputs per image: rows per
 // workgroup 32, 64 or 128 (one block up to 128 rows), pixels 8192 / MT as a TH x TW block, TW the
-// largest power of two <= min(Wo, 64).  Packs the weights into wscratch first (k_pack_weights).
-msl_status launch_conv_halo(HaloArgs a, int Co, int C, int flip, const uint16_t* w16, uint16_t* wscratch, bool xbf16,
+// largest power of two <= min(Wo, 64).  Packs the weights into wscratch first (k_pack_weights,
+// mode 0 forward, 1 stride-1 input gradient, 2 stride-2 input gradient in sub-pixel form).
+msl_status launch_conv_halo(HaloArgs a, int Co, int C, int mode, const uint16_t* w16, uint16_t* wscratch, bool xbf16,
                             hipStream_t st) {
+  const bool sub = mode == 2;
   const int MT = a.M <= 32 ? 32 : (a.M <= 64 ? 64 : 128);
   const int NT = 8192 / MT;
   int TW = 1;
@@ -1033,18 +1117,22 @@ msl_status launch_conv_halo(HaloArgs a, int Co, int C, int flip, const uint16_t*
   a.wp = wscratch;
   a.vec = (a.W % 4 == 0 && aligned(a.x, xbf16 ? 8 : 16)) ? 1 : 0;
   const int64_t nx = (int64_t)a.tiles_x * a.tiles_y * a.B;
-  const int lds = halo_lds_bytes(MT, a.TW, a.TH, a.s);
+  const int lds = halo_lds_bytes(MT, a.TW, a.TH, a.s, sub);
   MSL_TRY(need(nx < (1ll << 31) && (a.M + MT - 1) / MT <= 65535 && lds <= 64 * 1024, "conv: sizes too large"));
-  const int64_t npack = (int64_t)a.M * 9 * a.Cp;
-  hipLaunchKernelGGL(k_pack_weights, dim3(blocks_for(npack)), dim3(256), 0, st, Co, C, flip, w16, wscratch);
+  const int64_t npack = (int64_t)a.M * (sub ? 4 : 9) * a.Cp;
+  hipLaunchKernelGGL(k_pack_weights, dim3(blocks_for(npack)), dim3(256), 0, st, Co, C, mode, w16, wscratch);
   const dim3 grid((unsigned)nx, (unsigned)((a.M + MT - 1) / MT));
-  switch (MT * 2 + (xbf16 ? 1 : 0)) {
-    case 64: hipLaunchKernelGGL((k_conv_halo<32, false>), grid, dim3(256), lds, st, a); break;
-    case 65: hipLaunchKernelGGL((k_conv_halo<32, true>), grid, dim3(256), lds, st, a); break;
-    case 128: hipLaunchKernelGGL((k_conv_halo<64, false>), grid, dim3(256), lds, st, a); break;
-    case 129: hipLaunchKernelGGL((k_conv_halo<64, true>), grid, dim3(256), lds, st, a); break;
-    case 256: hipLaunchKernelGGL((k_conv_halo<128, false>), grid, dim3(256), lds, st, a); break;
-    default: hipLaunchKernelGGL((k_conv_halo<128, true>), grid, dim3(256), lds, st, a); break;
+  switch (MT * 4 + (xbf16 ? 2 : 0) + (sub ? 1 : 0)) {
+    case 128: hipLaunchKernelGGL((k_conv_halo<32, false, false>), grid, dim3(256), lds, st, a); break;
+    case 130: hipLaunchKernelGGL((k_conv_halo<32, true, false>), grid, dim3(256), lds, st, a); break;
+    case 131: hipLaunchKernelGGL((k_conv_halo<32, true, true>), grid, dim3(256), lds, st, a); break;
+    case 256: hipLaunchKernelGGL((k_conv_halo<64, false, false>), grid, dim3(256), lds, st, a); break;
+    case 258: hipLaunchKernelGGL((k_conv_halo<64, true, false>), grid, dim3(256), lds, st, a); break;
+    case 259: hipLaunchKernelGGL((k_conv_halo<64, true, true>), grid, dim3(256), lds, st, a); break;
+    case 512: hipLaunchKernelGGL((k_conv_halo<128, false, false>), grid, dim3(256), lds, st, a); break;
+    case 514: hipLaunchKernelGGL((k_conv_halo<128, true, false>), grid, dim3(256), lds, st, a); break;
+    case 515: hipLaunchKernelGGL((k_conv_halo<128, true, true>), grid, dim3(256), lds, st, a); break;
+    default: return fail(MSL_ERR_ARG, "conv: no kernel for this shape");
   }
   return launched("conv kernel");
 }
@@ -1091,13 +1179,14 @@ msl_status msl_nn_gemm_bf16_splitk(int32_t M, int32_t N, int32_t K, const uint16
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
   const int64_t mn = (int64_t)M * N;
-  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, M, N, ldc, C);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((mn + 15) / 16)), dim3(256), 0, st, mn, parts, partials, M, N, ldc,
+                     C);
   return launched("split gemm kernels");
 }
 
 int64_t msl_nn_conv3x3_scratch_elems(int32_t Co, int32_t C) {
   if (Co < 1 || C < 1) return 0;
-  return (int64_t)9 * pad16(Co) * pad16(C);
+  return (int64_t)16 * pad16(Co) * pad16(C);
 }
 
 msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const uint16_t* w16,
@@ -1126,15 +1215,19 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
   MSL_TRY(check_ptr(w16, 2, "w16"));
   MSL_TRY(check_ptr(dy16, 2, "dy16"));
   MSL_TRY(check_ptr(dx, 4, "dx"));
-  if (stride == 1) {
-    // a stride-1 convolution of dy with the weights transposed and rotated (see k_conv_halo)
+  if (stride == 1 || aligned(dx, 8)) {
+    // stride 1: a stride-1 convolution of dy with the weights transposed and rotated; stride 2: the
+    // sub-pixel form, a 2x2 convolution over dy with 4 C rows (see k_conv_halo)
     MSL_TRY(check_ptr(wscratch, 16, "wscratch"));
     MSL_TRY(need((int64_t)C * 9 < (1 << 30) && (int64_t)B * H * W < (1ll << 40), "conv adjoint: sizes too large"));
     HaloArgs h{};
-    h.M = C; h.C = Co; h.B = B; h.H = H; h.W = W; h.s = 1; h.Ho = H; h.Wo = W;
+    h.M = stride == 1 ? C : 4 * C;
+    h.C = Co; h.B = B; h.s = 1;
+    h.H = H / stride; h.W = W / stride;   // the input of this product: dy
+    h.Ho = H / stride; h.Wo = W / stride; // its output grid (half resolution for stride 2)
     h.relu = 0;
     h.x = dy16; h.bias = nullptr; h.y = dx;
-    return launch_conv_halo(h, Co, C, 1, w16, wscratch, true, static_cast<hipStream_t>(hip_stream));
+    return launch_conv_halo(h, Co, C, stride == 1 ? 1 : 2, w16, wscratch, true, static_cast<hipStream_t>(hip_stream));
   }
   ConvArgs a{};
   a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
@@ -1185,8 +1278,8 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
     MSL_TRY(need(lds <= 64 * 1024 && cb <= 65535 && ob <= 65535, "conv weight gradient: sizes too large"));
     hipLaunchKernelGGL(k_conv_wgrad_halo, dim3(cb, ob, parts), dim3(192), lds, st, w);
     const int64_t mn = (int64_t)Co * 9 * C;
-    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, Co, 9 * C, 9 * C,
-                       dw);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((mn + 15) / 16)), dim3(256), 0, st, mn, parts, partials, Co,
+                       9 * C, 9 * C, dw);
     return launched("conv weight gradient kernels");
   }
   ConvArgs a{};
@@ -1204,7 +1297,8 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
   MSL_TRY(need(grid.y <= 65535 && grid.z <= 65535, "conv weight gradient: too many channels or parts"));
   hipLaunchKernelGGL(k_conv_bwd_weight, grid, dim3(256), 0, st, a, (int)kchunk, partials);
   const int64_t mn = (int64_t)Co * NC;
-  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn)), dim3(256), 0, st, mn, parts, partials, Co, NC, NC, dw);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((mn + 15) / 16)), dim3(256), 0, st, mn, parts, partials, Co, NC,
+                     NC, dw);
   return launched("conv weight gradient kernels");
 }
 
@@ -1243,9 +1337,13 @@ msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const fl
   MSL_TRY(need(C >= 1 && B >= 1 && H >= 1 && W >= 1, "upsample: sizes must be >= 1"));
   MSL_TRY(check_ptr(x, 4, "x"));
   MSL_TRY(check_ptr(y, 4, "y"));
-  const int64_t total = (int64_t)C * B * 4 * H * W;
-  hipLaunchKernelGGL(k_upsample2, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), total, H,
-                     W, x, y);
+  const int64_t total = (int64_t)C * B * H * W;   // input elements
+  const int vec = aligned(y, 8) ? 1 : 0;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (4 * total < (1ll << 31))
+    hipLaunchKernelGGL(k_upsample2<int32_t>, dim3(blocks_for(total)), dim3(256), 0, st, (int32_t)total, W, vec, x, y);
+  else
+    hipLaunchKernelGGL(k_upsample2<int64_t>, dim3(blocks_for(total)), dim3(256), 0, st, total, W, vec, x, y);
   return launched("upsample kernel");
 }
 
@@ -1255,8 +1353,13 @@ msl_status msl_nn_upsample2_adjoint(int32_t C, int32_t B, int32_t H, int32_t W, 
   MSL_TRY(check_ptr(dy, 4, "dy"));
   MSL_TRY(check_ptr(dx, 4, "dx"));
   const int64_t total = (int64_t)C * B * H * W;
-  hipLaunchKernelGGL(k_upsample2_adj, dim3(blocks_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
-                     total, H, W, dy, dx);
+  const int vec = aligned(dy, 8) ? 1 : 0;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (4 * total < (1ll << 31))
+    hipLaunchKernelGGL(k_upsample2_adj<int32_t>, dim3(blocks_for(total)), dim3(256), 0, st, (int32_t)total, W, vec, dy,
+                       dx);
+  else
+    hipLaunchKernelGGL(k_upsample2_adj<int64_t>, dim3(blocks_for(total)), dim3(256), 0, st, total, W, vec, dy, dx);
   return launched("upsample adjoint kernel");
 }
 
