@@ -86,7 +86,7 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
  * patch value (c, t) at p (x rounded to bfloat16 as in the forward); the pixel sum is split into at
  * most `splits` parts written to partials (float32 [splits][Co][9C], caller-owned scratch) and then
  * summed in a fixed order into dw (float32 [Co][9C]).  When the output width W/s is a multiple of 8 the parts
- * are ranges of 256/s-pixel halo tiles (as many parts as fill the GPU, at most `splits`), otherwise
+ * are ranges of 128/s-pixel halo tiles (as many parts as fill the GPU, at most `splits`), otherwise
  * ranges of pixels of the patch-column product (msl_nn_gemm_bf16_splitk of dy16 and the patch
  * matrix, bit for bit).  1 <= splits <= 4096. */
 msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,

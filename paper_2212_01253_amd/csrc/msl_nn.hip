@@ -1253,13 +1253,13 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
   MSL_TRY(check_ptr(partials, 4, "partials"));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if ((W / stride) % 8 == 0) {
-    // halo tiles (k_conv_wgrad_halo): 256 / s pixels per tile, as TH x TW, TW <= 64
+    // halo tiles (k_conv_wgrad_halo): 128 / s pixels per tile, as TH x TW, TW <= 64
     WgradArgs w{};
     w.Co = Co; w.C = C; w.B = B; w.H = H; w.W = W; w.s = stride; w.Ho = H / stride; w.Wo = W / stride;
     int TW = 8;
     while (2 * TW <= std::min(w.Wo, 64)) TW *= 2;
     w.TW = TW;
-    w.KT = 256 / stride;
+    w.KT = 128 / stride;   // smaller tiles: less LDS per workgroup, more of them per CU
     w.TH = w.KT / TW;
     w.tiles_x = (w.Wo + TW - 1) / TW;
     w.tiles_y = (w.Ho + w.TH - 1) / w.TH;
