@@ -125,6 +125,14 @@ msl_status msl_nn_relu_adjoint(int64_t n, const float* y, float* dy, void* hip_s
 msl_status msl_nn_add(int64_t n, const float* x, float* y, void* hip_stream);
 msl_status msl_nn_to_bf16(int64_t n, const float* x, uint16_t* y16, void* hip_stream);
 
+/* One layer's output gradient made ready for its backward products, in one pass over dy (float32
+ * [M][N], read only): g = dy where y > 0, else 0 (the ReLU adjoint; y float32 [M][N], or NULL for no
+ * activation); dy16[m][n] = bfloat16(g) and bias_grad[m] = sum_n g (fixed-order sums, as
+ * msl_nn_rowsum; parts: float32 scratch of at least 64 M).  dy16 equals msl_nn_relu_adjoint then
+ * msl_nn_to_bf16 bit for bit; bias_grad is msl_nn_rowsum of g summed in another fixed order. */
+msl_status msl_nn_grad_prep(int32_t M, int32_t N, const float* y, const float* dy, uint16_t* dy16, float* bias_grad,
+                            float* parts, void* hip_stream);
+
 /* out[m] = sum_n X[m * N + n] (float32 sums of float32 rows, bias gradients), in a fixed order:
  * 64 partial sums per row into parts (float32 [M][64], caller-owned scratch), then their sum. */
 msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, float* parts, void* hip_stream);

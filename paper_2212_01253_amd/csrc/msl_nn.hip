@@ -1005,6 +1005,51 @@ __global__ void __launch_bounds__(64) k_rowsum_final(const float* __restrict__ p
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// Output-gradient preparation of one layer's backward, in one pass: g = dy masked by y > 0 (when y
+// is given: the ReLU adjoint), written as bfloat16 to dy16, and the partial row sums of g (bias
+// gradient; rows of N columns, kRowParts column chunks each, finished by k_rowsum_final).  dy is
+// read only.  VEC: N a multiple of 4 and the arrays aligned, four columns per access.
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_grad_prep(int N, int chunk, const float* __restrict__ y,
+                                                   const float* __restrict__ dy, uint16_t* __restrict__ dy16,
+                                                   float* __restrict__ part) {
+  __shared__ float red[256];
+  const int n0 = blockIdx.x * chunk, n1 = min(N, n0 + chunk);
+  const int64_t row = (int64_t)blockIdx.y * N;
+  float acc = 0.0f;
+  if constexpr (VEC) {
+    for (int n = n0 + 4 * (int)threadIdx.x; n < n1; n += 4 * 256) {
+      float4 g = *reinterpret_cast<const float4*>(dy + row + n);
+      if (y) {
+        const float4 v = *reinterpret_cast<const float4*>(y + row + n);
+        if (!(v.x > 0.0f)) g.x = 0.0f;
+        if (!(v.y > 0.0f)) g.y = 0.0f;
+        if (!(v.z > 0.0f)) g.z = 0.0f;
+        if (!(v.w > 0.0f)) g.w = 0.0f;
+      }
+      uint2 u;
+      u.x = (uint32_t)to_bf16(g.x) | ((uint32_t)to_bf16(g.y) << 16);
+      u.y = (uint32_t)to_bf16(g.z) | ((uint32_t)to_bf16(g.w) << 16);
+      *reinterpret_cast<uint2*>(dy16 + row + n) = u;
+      acc += (g.x + g.y) + (g.z + g.w);
+    }
+  } else {
+    for (int n = n0 + (int)threadIdx.x; n < n1; n += 256) {
+      float g = dy[row + n];
+      if (y && !(y[row + n] > 0.0f)) g = 0.0f;
+      dy16[row + n] = to_bf16(g);
+      acc += g;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y * kRowParts + blockIdx.x] = red[0];
+}
+
 // one workgroup; FP64 sum in a fixed order
 __global__ void __launch_bounds__(1024) k_mse(int64_t n, const float* __restrict__ p, const float* __restrict__ t,
                                               float* __restrict__ grad, double* __restrict__ loss) {
@@ -1453,6 +1498,25 @@ msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, float
   hipLaunchKernelGGL(k_rowsum_parts, dim3(kRowParts, M), dim3(256), 0, st, N, X, parts);
   hipLaunchKernelGGL(k_rowsum_final, dim3(M), dim3(64), 0, st, parts, out);
   return launched("rowsum kernels");
+}
+
+msl_status msl_nn_grad_prep(int32_t M, int32_t N, const float* y, const float* dy, uint16_t* dy16, float* bias_grad,
+                            float* parts, void* hip_stream) {
+  MSL_TRY(need(M >= 1 && N >= 1 && M <= 65535, "grad prep: need 1 <= M <= 65535 and N >= 1"));
+  MSL_TRY(check_ptr(y, 4, "y", true));
+  MSL_TRY(check_ptr(dy, 4, "dy"));
+  MSL_TRY(check_ptr(dy16, 2, "dy16"));
+  MSL_TRY(check_ptr(bias_grad, 4, "bias_grad"));
+  MSL_TRY(check_ptr(parts, 4, "parts"));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const bool vec = N % 4 == 0 && aligned(dy, 16) && aligned(dy16, 8) && (!y || aligned(y, 16));
+  int chunk = (N + kRowParts - 1) / kRowParts;
+  if (vec) chunk = (chunk + 3) / 4 * 4;
+  const dim3 grid(kRowParts, M);
+  if (vec) hipLaunchKernelGGL(k_grad_prep<true>, grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
+  else hipLaunchKernelGGL(k_grad_prep<false>, grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
+  hipLaunchKernelGGL(k_rowsum_final, dim3(M), dim3(64), 0, st, parts, bias_grad);
+  return launched("gradient preparation kernels");
 }
 
 msl_status msl_nn_mse(int64_t n, const float* pred, const float* target, float* grad, double* loss_out,

@@ -205,12 +205,10 @@ class UNet:
         bf = self._bufs
         Ho, Wo = H // s, W // s
         N = B * Ho * Wo
-        if act:
-            nn.relu_adjoint(y, dy)
         dy16 = bf["dy16"][:co * N]
-        nn.to_bf16(dy, dy16)
         w16, _, gw, gb = self._wb(name)
-        nn.rowsum(co, N, dy, gb, bf["parts"])
+        # ReLU adjoint, bfloat16 copy and bias gradient in one pass (dy itself is not rewritten)
+        nn.grad_prep(co, N, y if act else None, dy, dy16, gb, bf["parts"])
         # weight gradient: a short, wide product over the long pixel axis, split along it
         splits = max(1, min(SPLIT_PARTS, N // 1024))
         nn.conv3x3_weight_grad(co, ci, B, H, W, s, dy16, x, gw, splits, bf["parts"])
@@ -515,6 +513,31 @@ def train_initialiser(n_samples=50000, steps=None, batch=32, lr=1e-3, n=256, n_s
     return net, info
 
 
+def step_flops(net, batch, H=256, W=256):
+    """Multiply-add flops (2 per product) of one forward pass and of one training step: every
+    convolution's product in the forward; in the backward, its weight gradient and (all layers but
+    the first, whose input needs none) its input gradient; the global head's two dense layers the
+    same way.  Elementwise work is not counted."""
+    fwd = bwd = 0.0
+    h, w = H, W
+    for name, ci, co, s, _ in net.specs:
+        if name == "d3":
+            h, w = H // 4, W // 4   # decoder levels follow the upsampling
+        elif name == "d2":
+            h, w = H // 2, W // 2
+        elif name == "d1":
+            h, w = H, W
+        h, w = h // s, w // s
+        f = 2.0 * co * ci * 9 * batch * h * w
+        fwd += f
+        bwd += f if name == "e1a" else 2 * f
+    for name, (o0, o1, no, ni) in net.head_off.items():
+        f = 2.0 * no * ni * batch
+        fwd += f
+        bwd += 2 * f
+    return fwd, fwd + bwd
+
+
 def _speed(batch, steps=5):
     """Times training steps and forward passes of the 256 x 256 network at a batch size."""
     net = UNet(c=32, seed=0)
@@ -538,7 +561,9 @@ def _speed(batch, steps=5):
         net.forward(x)
     torch.cuda.synchronize()
     df = (time.perf_counter() - t) / steps
-    print(f"batch {batch}: training step {dt * 1e3:.1f} ms, forward {df * 1e3:.1f} ms", flush=True)
+    ff, ft = step_flops(net, batch)
+    print(f"batch {batch}: training step {dt * 1e3:.1f} ms ({ft / dt / 1e12:.0f} TFLOP/s of {ft / 1e12:.2f} TFLOP), "
+          f"forward {df * 1e3:.1f} ms ({ff / df / 1e12:.0f} TFLOP/s)", flush=True)
 
 
 if __name__ == "__main__":

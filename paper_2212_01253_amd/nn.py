@@ -18,7 +18,7 @@ EXPORTS = ("msl_nn_gemm_bf16", "msl_nn_gemm_bf16_splitk", "msl_nn_im2col3x3", "m
            "msl_nn_add", "msl_nn_to_bf16", "msl_nn_rowsum", "msl_nn_mse", "msl_nn_adam", "msl_nn_logmap",
            "msl_nn_render_pools", "msl_nn_pool_average", "msl_nn_row_features", "msl_nn_add_row_bias",
            "msl_nn_row_bias_adjoint", "msl_nn_conv3x3", "msl_nn_conv3x3_adjoint", "msl_nn_conv3x3_weight_grad",
-           "msl_nn_conv3x3_scratch_elems")
+           "msl_nn_conv3x3_scratch_elems", "msl_nn_grad_prep")
 
 MAX_BOXES = 64   # MSL_NN_MAX_BOXES
 MAX_CUTS = 132   # MSL_NN_MAX_CUTS
@@ -56,6 +56,7 @@ def lib():
             "msl_nn_conv3x3": [I, I, I, I, I, I, P, P, P, I, P, P, P],
             "msl_nn_conv3x3_adjoint": [I, I, I, I, I, I, P, P, P, P, P],
             "msl_nn_conv3x3_weight_grad": [I, I, I, I, I, I, P, P, P, I, P, P],
+            "msl_nn_grad_prep": [I, I, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -123,6 +124,12 @@ def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx, scratch=None):
     ws = scratch if scratch is not None else conv_scratch(Co, C, dx.device)
     _ck(lib().msl_nn_conv3x3_adjoint(Co, C, B, H, W, stride, _p(w16, BF16), _p(dy16, BF16), _p(dx, torch.float32),
                                      _p(ws, BF16), _s()))
+
+
+def grad_prep(M, N, y, dy, dy16, bias_grad, parts):
+    """msl_nn_grad_prep: dy16 = bf16(dy masked by y > 0, or unmasked when y is None), bias_grad = row sums."""
+    _ck(lib().msl_nn_grad_prep(M, N, _p(y, torch.float32), _p(dy, torch.float32), _p(dy16, BF16),
+                               _p(bias_grad, torch.float32), _p(parts, torch.float32), _s()))
 
 
 def conv3x3_weight_grad(Co, C, B, H, W, stride, dy16, x, dw, splits, partials):

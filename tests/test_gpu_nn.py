@@ -172,6 +172,31 @@ def test_resampling_and_elementwise_kernels(T):
     assert np.allclose(gr.cpu().numpy(), g, rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("M,N", [(7, 333), (5, 4096), (3, 1030)])
+def test_gradient_preparation_in_one_pass(T, M, N):
+    # msl_nn_grad_prep: the same bfloat16 copy as the ReLU adjoint followed by the conversion, bit
+    # for bit, and the row sums of the masked gradient (other summation order: float32 rounding);
+    # with y None no mask.  dy is left as it was.  N = 4096 takes the four-column path, 333 and 1030
+    # the single-column one (1030 is not a multiple of 4).
+    import torch
+    rng = np.random.default_rng(M * 1000 + N)
+    y = rng.standard_normal((M, N)).astype(np.float32)
+    dy = rng.standard_normal((M, N)).astype(np.float32)
+    parts = torch.zeros(M * 64, dtype=torch.float32, device="cuda")
+    for relu in (True, False):
+        dyd = dev(dy)
+        d16 = torch.zeros(M * N, dtype=torch.int16, device="cuda")
+        gb = torch.zeros(M, dtype=torch.float32, device="cuda")
+        T.grad_prep(M, N, dev(y) if relu else None, dyd, d16, gb, parts)
+        g = np.where(y > 0, dy, 0).astype(np.float32) if relu else dy
+        ref16 = torch.zeros(M * N, dtype=torch.int16, device="cuda")
+        T.to_bf16(dev(g), ref16)
+        torch.cuda.synchronize()
+        assert np.array_equal(dyd.cpu().numpy(), dy)
+        assert np.array_equal(d16.cpu().numpy(), ref16.cpu().numpy())
+        assert np.allclose(gb.cpu().numpy(), g.astype(np.float64).sum(axis=1), rtol=1e-5, atol=1e-4)
+
+
 def test_global_head_kernels(T):
     import torch
     rng = np.random.default_rng(8)
