@@ -250,6 +250,9 @@ def main():
                     help="skip the extra timing with a checkpoint at every slice (no recompute)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shapes with the library's autotuner before the timed runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run eight plain 2 MiB device-to-device copies (the reference kernel that "
+                         "calibrates the FETCH_SIZE / WRITE_SIZE counters of a profile)")
     ap.add_argument("--batch", type=int, default=96, metavar="N",
                     help="also time the batched forward over N instances of the batched workload (96 = full, 0 = skip)")
     args = ap.parse_args()
@@ -270,6 +273,12 @@ def main():
     print(f"# workload {w.name}: alpha {math.degrees(g.alpha_i_rad):.4f} deg", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 18, dtype=torch.float64, device=dev)   # 2 MiB
+        dst = torch.empty_like(src)
+        for _ in range(8):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     msl.set_schedule(args.schedule)
     D = torch.from_numpy(w.delta).to(dev)
     B = torch.from_numpy(w.beta).to(dev)
