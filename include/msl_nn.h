@@ -138,9 +138,10 @@ msl_status msl_nn_grad_prep(int32_t M, int32_t N, const float* y, const float* d
 msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, float* parts, void* hip_stream);
 
 /* Mean squared error over n values: loss_out[0] (double, device) = sum (p - t)^2 / n,
- * grad[i] = 2 (p - t) / n (float32; may be NULL). */
+ * grad[i] = 2 (p - t) / n (float32; may be NULL).  The sum is FP64 in a fixed order: 256 chunk
+ * sums into parts (double, device scratch of at least 256), then their sum. */
 msl_status msl_nn_mse(int64_t n, const float* pred, const float* target, float* grad, double* loss_out,
-                      void* hip_stream);
+                      double* parts, void* hip_stream);
 
 /* ADAM step over n float32 weights (as msl_region_adam_step, without the clamp), then the
  * bfloat16 copy w16 of the new weights (may be NULL); t >= 1. */

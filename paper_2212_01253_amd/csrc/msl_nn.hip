@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
 // the staged positions), B = dy at those pixels (8 consecutive per lane, one 16-byte LDS read).
 constexpr int WCK = 32;        // input channels per workgroup
 constexpr int WCKP = WCK + 4;  // staged position stride (bfloat16): 72 bytes
-constexpr int WOC = 32;        // output channels per workgroup
+constexpr int WOC = 32;        // output channels per workgroup tile (a workgroup takes one or two)
 
 struct WgradArgs {
   int Co, C, B, H, W, s, Ho, Wo;
@@ -673,24 +673,30 @@ __host__ __device__ inline int wgrad_xs_slots(int TW, int TH, int s) {
   return (HH * HW * WCKP + 7) / 8 * 8;
 }
 
-int wgrad_lds_bytes(int TW, int TH, int s) {
-  return (wgrad_xs_slots(TW, TH, s) + WOC * (TW * TH + 8)) * (int)sizeof(uint16_t);
+int wgrad_lds_bytes(int TW, int TH, int s, int ot) {
+  return (wgrad_xs_slots(TW, TH, s) + ot * WOC * (TW * TH + 8)) * (int)sizeof(uint16_t);
 }
 
+template <int OT>
 __global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
+  constexpr int NOC = 32 * OT;                      // output channels of this workgroup
   extern __shared__ __attribute__((aligned(16))) uint16_t wg_smem[];
   const int HW = (a.TW - 1) * a.s + 3, HH = (a.TH - 1) * a.s + 3;
   const int DKP = a.KT + 8;                         // row stride of the staged dy tile
   uint16_t* const xs = wg_smem;                     // [HH * HW][WCKP]
-  uint16_t* const dys = wg_smem + wgrad_xs_slots(a.TW, a.TH, a.s);   // [WOC][DKP]
+  uint16_t* const dys = wg_smem + wgrad_xs_slots(a.TW, a.TH, a.s);   // [NOC][DKP]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int c0 = blockIdx.x * WCK, o0 = blockIdx.y * WOC, part = blockIdx.z;
+  const int c0 = blockIdx.x * WCK, o0 = blockIdx.y * NOC, part = blockIdx.z;
   const int kq = 8 * (lane >> 5);
   const int64_t plane = (int64_t)a.H * a.W, cstride = (int64_t)a.B * plane;
   const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
   const bool vec = a.vec != 0;
   const bool dvec = (a.Wo & 7) == 0 && (reinterpret_cast<uintptr_t>(a.dy16) & 15) == 0;
-  f32x16 acc0 = {}, acc1 = {}, acc2 = {};
+  f32x16 acc[3][OT];                                // [tap column dx][output-channel tile]
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+    for (int ot = 0; ot < OT; ++ot) acc[dx][ot] = f32x16{};
   const int t0 = part * a.per_part, t1 = min(a.ntiles, t0 + a.per_part);
   for (int tile = t0; tile < t1; ++tile) {
     int t = tile;
@@ -702,7 +708,7 @@ __global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
     stage_block<WCK, WCKP, false>(xs, a.x, a.C, c0, cstride, (int64_t)b * plane, a.H, a.W, iy0, ix0, HH, HW, vec);
     // dy tile: item = (output channel, 8-pixel group of a tile row)
     const int ng = a.KT / 8;
-    for (int it = tid; it < WOC * ng; it += blockDim.x) {
+    for (int it = tid; it < NOC * ng; it += blockDim.x) {
       const int oc = it / ng, g = it - oc * ng;
       const int n = 8 * g, ty = n / a.TW, tx = n - ty * a.TW;
       const int o = o0 + oc, oy = oy0 + ty, ox = ox0 + tx;
@@ -727,7 +733,10 @@ __global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
     for (int k0 = 0; k0 < a.KT; k0 += 16) {
       const int n = k0 + kq;                         // this lane's 8 pixels: n .. n+7, one tile row
       const int ty = n / a.TW, tx = n - ty * a.TW;
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&dys[(lane & 31) * DKP + n]);
+      bf16x8 bv[OT];
+#pragma unroll
+      for (int ot = 0; ot < OT; ++ot)
+        bv[ot] = *reinterpret_cast<const bf16x8*>(&dys[(32 * ot + (lane & 31)) * DKP + n]);
       const int base = ((ty * a.s + wave) * HW + tx * a.s) * WCKP + (lane & 31);
       const int step = a.s * WCKP;
 #pragma unroll
@@ -736,29 +745,32 @@ __global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
         const uint16_t* src = xs + base + dx * WCKP;
 #pragma unroll
         for (int i = 0; i < 8; ++i) av[i] = __builtin_bit_cast(__bf16, src[i * step]);
-        if (dx == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc0, 0, 0, 0);
-        else if (dx == 1) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc1, 0, 0, 0);
-        else acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc2, 0, 0, 0);
+#pragma unroll
+        for (int ot = 0; ot < OT; ++ot)
+          acc[dx][ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[ot], acc[dx][ot], 0, 0, 0);
       }
     }
     __syncthreads();
   }
   // accumulator element 4i + j of lane l: channel row 8i + 4 (l / 32) + j, output channel l mod 32
-  const int o = o0 + (lane & 31);
-  if (o >= a.Co) return;
   const int NC = 9 * a.C;
-  float* const P = a.partials + ((int64_t)part * a.Co + o) * NC;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int ot = 0; ot < OT; ++ot) {
+    const int o = o0 + 32 * ot + (lane & 31);
+    if (o >= a.Co) continue;
+    float* const P = a.partials + ((int64_t)part * a.Co + o) * NC;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = c0 + 8 * i + 4 * (lane >> 5) + j;
-      if (c < a.C) {
-        P[9 * c + 3 * wave + 0] = acc0[4 * i + j];
-        P[9 * c + 3 * wave + 1] = acc1[4 * i + j];
-        P[9 * c + 3 * wave + 2] = acc2[4 * i + j];
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = c0 + 8 * i + 4 * (lane >> 5) + j;
+        if (c < a.C) {
+          P[9 * c + 3 * wave + 0] = acc[0][ot][4 * i + j];
+          P[9 * c + 3 * wave + 1] = acc[1][ot][4 * i + j];
+          P[9 * c + 3 * wave + 2] = acc[2][ot][4 * i + j];
+        }
       }
-    }
+  }
 }
 
 // C[i] = sum over the parts s of P[s][i].  A workgroup takes 16 consecutive elements; its 16 thread
@@ -1050,24 +1062,42 @@ __global__ void __launch_bounds__(256) k_grad_prep(int N, int chunk, const float
   if (threadIdx.x == 0) part[blockIdx.y * kRowParts + blockIdx.x] = red[0];
 }
 
-// one workgroup; FP64 sum in a fixed order
-__global__ void __launch_bounds__(1024) k_mse(int64_t n, const float* __restrict__ p, const float* __restrict__ t,
-                                              float* __restrict__ grad, double* __restrict__ loss) {
-  __shared__ double red[1024];
+// Mean squared error in two fixed-order stages: kMseParts workgroups each sum the squared
+// differences of one contiguous chunk in FP64 (and write the gradient), then one workgroup adds
+// the partial sums in order.
+constexpr int kMseParts = 256;
+
+__global__ void __launch_bounds__(256) k_mse_parts(int64_t n, int64_t chunk, const float* __restrict__ p,
+                                                   const float* __restrict__ t, float* __restrict__ grad,
+                                                   double* __restrict__ part) {
+  __shared__ double red[256];
   const double inv = 1.0 / (double)n;
+  const int64_t e0 = (int64_t)blockIdx.x * chunk, e1 = min(n, e0 + chunk);
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < n; e += 1024) {
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
     const double d = (double)p[e] - (double)t[e];
     acc += d * d;
     if (grad) grad[e] = (float)(2.0 * d * inv);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) loss[0] = red[0] * inv;
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_mse_final(int64_t n, const double* __restrict__ part,
+                                                   double* __restrict__ loss) {
+  __shared__ double red[256];
+  red[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = red[0] / (double)n;
 }
 
 __global__ void __launch_bounds__(256) k_adam_flat(int64_t n, float* __restrict__ w, const float* __restrict__ g,
@@ -1311,7 +1341,10 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
     const int64_t ntiles = (int64_t)w.tiles_x * w.tiles_y * B;
     MSL_TRY(need(ntiles < (1ll << 31) && (int64_t)C * 9 < (1 << 30), "conv weight gradient: sizes too large"));
     w.ntiles = (int)ntiles;
-    const int cb = (C + WCK - 1) / WCK, ob = (Co + WOC - 1) / WOC;
+    // two output-channel tiles per workgroup when there are 64 or more output channels: each staged
+    // input block then feeds twice the products
+    const int ot = Co >= 2 * WOC ? 2 : 1;
+    const int cb = (C + WCK - 1) / WCK, ob = (Co + ot * WOC - 1) / (ot * WOC);
     // parts: at most `splits`, enough workgroups to fill the GPU (about 2048), at least one tile each
     int parts = std::min<int64_t>(splits, ntiles);
     parts = std::max(1, std::min(parts, (2048 + cb * ob - 1) / (cb * ob)));
@@ -1319,9 +1352,10 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
     parts = (int)((ntiles + w.per_part - 1) / w.per_part);
     w.vec = (W % 4 == 0 && aligned(x, 16)) ? 1 : 0;
     w.dy16 = dy16; w.x = x; w.partials = partials;
-    const int lds = wgrad_lds_bytes(w.TW, w.TH, stride);
+    const int lds = wgrad_lds_bytes(w.TW, w.TH, stride, ot);
     MSL_TRY(need(lds <= 64 * 1024 && cb <= 65535 && ob <= 65535, "conv weight gradient: sizes too large"));
-    hipLaunchKernelGGL(k_conv_wgrad_halo, dim3(cb, ob, parts), dim3(192), lds, st, w);
+    if (ot == 2) hipLaunchKernelGGL(k_conv_wgrad_halo<2>, dim3(cb, ob, parts), dim3(192), lds, st, w);
+    else hipLaunchKernelGGL(k_conv_wgrad_halo<1>, dim3(cb, ob, parts), dim3(192), lds, st, w);
     const int64_t mn = (int64_t)Co * 9 * C;
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((mn + 15) / 16)), dim3(256), 0, st, mn, parts, partials, Co,
                        9 * C, 9 * C, dw);
@@ -1520,15 +1554,18 @@ msl_status msl_nn_grad_prep(int32_t M, int32_t N, const float* y, const float* d
 }
 
 msl_status msl_nn_mse(int64_t n, const float* pred, const float* target, float* grad, double* loss_out,
-                      void* hip_stream) {
+                      double* parts, void* hip_stream) {
   MSL_TRY(need(n >= 1, "mse: n must be >= 1"));
   MSL_TRY(check_ptr(pred, 4, "pred"));
   MSL_TRY(check_ptr(target, 4, "target"));
   MSL_TRY(check_ptr(grad, 4, "grad", true));
   MSL_TRY(check_ptr(loss_out, 8, "loss_out"));
-  hipLaunchKernelGGL(k_mse, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(hip_stream), n, pred, target, grad,
-                     loss_out);
-  return launched("mse kernel");
+  MSL_TRY(check_ptr(parts, 8, "parts"));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t chunk = (n + kMseParts - 1) / kMseParts;
+  hipLaunchKernelGGL(k_mse_parts, dim3(kMseParts), dim3(256), 0, st, n, chunk, pred, target, grad, parts);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, st, n, parts, loss_out);
+  return launched("mse kernels");
 }
 
 msl_status msl_nn_adam(int64_t n, float* w, const float* g, float* m, float* v, uint16_t* w16, float lr, float beta1,

@@ -45,7 +45,7 @@ def lib():
             "msl_nn_add": [c_int64, P, P, P],
             "msl_nn_to_bf16": [c_int64, P, P, P],
             "msl_nn_rowsum": [I, I, P, P, P, P],
-            "msl_nn_mse": [c_int64, P, P, P, P, P],
+            "msl_nn_mse": [c_int64, P, P, P, P, P, P],
             "msl_nn_adam": [c_int64, P, P, P, P, P, c_float, c_float, c_float, c_float, I, P],
             "msl_nn_logmap": [c_int64, P, c_float, c_float, c_float, P, P],
             "msl_nn_render_pools": [I, I, I, I, c_float, c_float, P, P, P, P, P, I, P, P, P],
@@ -191,9 +191,16 @@ def rowsum(M, N, X, out, parts):
     _ck(lib().msl_nn_rowsum(M, N, _p(X, torch.float32), _p(out, torch.float32), _p(parts, torch.float32), _s()))
 
 
+_mse_parts = {}
+
+
 def mse(pred, target, grad, loss):
+    parts = _mse_parts.get(pred.device)
+    if parts is None:
+        parts = torch.empty(256, dtype=torch.float64, device=pred.device)
+        _mse_parts[pred.device] = parts
     _ck(lib().msl_nn_mse(pred.numel(), _p(pred, torch.float32), _p(target, torch.float32),
-                         _p(grad, torch.float32), _p(loss, torch.float64), _s()))
+                         _p(grad, torch.float32), _p(loss, torch.float64), _p(parts, torch.float64), _s()))
 
 
 def adam(w, g, m, v, w16, lr, beta1, beta2, eps, t):

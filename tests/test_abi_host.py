@@ -206,7 +206,8 @@ def test_nn_entry_points_validate(L):
     assert N.msl_nn_rowpool(1, 10, 4, 4, FAKE, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_adam(8, FAKE, FAKE, FAKE, FAKE, None, 1e-3, 1.0, 0.999, 1e-8, 1, None) == msl.ERR_ARG
     assert N.msl_nn_adam(8, FAKE, FAKE, FAKE, FAKE, None, 1e-3, 0.9, 0.999, 1e-8, 0, None) == msl.ERR_ARG
-    assert N.msl_nn_mse(0, FAKE, FAKE, None, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_mse(0, FAKE, FAKE, None, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_mse(8, FAKE, FAKE, None, FAKE, None, None) == msl.ERR_ARG     # no scratch
     assert N.msl_nn_row_features(2, 4, 6, FAKE, None, None, FAKE, None) == msl.ERR_ARG       # W < 8
     assert N.msl_nn_row_features(2, 4, 8, FAKE, None, None, FAKE + 1, None) == msl.ERR_ARG  # misaligned
     assert N.msl_nn_row_features(2, 4, 8, FAKE, FAKE + 2, None, FAKE, None) == msl.ERR_ARG  # misaligned
