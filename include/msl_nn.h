@@ -77,10 +77,11 @@ msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W
  * a convolution of dy16 with the weights transposed and rotated by 180 degrees; stride 2 (dx 8-byte
  * aligned) split by the parity of (y, x) into a 2x2 convolution of dy16 with 4 C rows (zero weights
  * where a parity class has no tap).  A stride-2 call with dx not 8-byte aligned runs as an implicit
- * product over the patch columns instead. */
+ * product over the patch columns instead.  accumulate 1: dx += the gradient instead of dx = (the
+ * gradient of a layer whose input also feeds a skip connection; needs the halo path). */
 msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
-                                  const uint16_t* w16, const uint16_t* dy16, float* dx, uint16_t* wscratch,
-                                  void* hip_stream);
+                                  const uint16_t* w16, const uint16_t* dy16, float* dx, int32_t accumulate,
+                                  uint16_t* wscratch, void* hip_stream);
 
 /* Its weight gradient, implicit as well: dw[o][9c + t] = sum over output pixels p of dy16[o][p] times the
  * patch value (c, t) at p (x rounded to bfloat16 as in the forward); the pixel sum is split into at

@@ -472,6 +472,7 @@ struct HaloArgs {
   int TW, TH, tiles_x, tiles_y;
   int Cp;                // row length of wp per tap: pad16(C)
   int vec;               // W a multiple of 4 and x aligned: whole 4-position groups read at once
+  int accum;             // add the result to y instead of overwriting it
   const uint16_t* wp;    // packed weights [M][9][Cp] (k_pack_weights)
   const void* x;         // [C][B][H][W], float32 or (xbf16) bfloat16 bits
   const float* bias;     // [M] or nullptr
@@ -620,8 +621,14 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
         const int c = (m0 + cb * 32 + 8 * i + 4 * (lane >> 5)) >> 2;
         if (4 * c < a.M) {
           float* const d = a.y + (int64_t)c * npix2 + o;
-          *reinterpret_cast<float2*>(d) = make_float2(acc[4 * i + 0], acc[4 * i + 1]);
-          *reinterpret_cast<float2*>(d + W2) = make_float2(acc[4 * i + 2], acc[4 * i + 3]);
+          float2 u0 = make_float2(acc[4 * i + 0], acc[4 * i + 1]), u1 = make_float2(acc[4 * i + 2], acc[4 * i + 3]);
+          if (a.accum) {
+            const float2 p0 = *reinterpret_cast<const float2*>(d), p1 = *reinterpret_cast<const float2*>(d + W2);
+            u0 = make_float2(p0.x + u0.x, p0.y + u0.y);
+            u1 = make_float2(p1.x + u1.x, p1.y + u1.y);
+          }
+          *reinterpret_cast<float2*>(d) = u0;
+          *reinterpret_cast<float2*>(d + W2) = u1;
         }
       }
     } else {
@@ -636,6 +643,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
             float v = acc[4 * i + j];
             if (a.bias) v += a.bias[m];
             if (a.relu) v = fmaxf(v, 0.0f);
+            if (a.accum) v += a.y[(int64_t)m * npix + o];
             a.y[(int64_t)m * npix + o] = v;
           }
         }
@@ -1283,8 +1291,8 @@ msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W
 }
 
 msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
-                                  const uint16_t* w16, const uint16_t* dy16, float* dx, uint16_t* wscratch,
-                                  void* hip_stream) {
+                                  const uint16_t* w16, const uint16_t* dy16, float* dx, int32_t accumulate,
+                                  uint16_t* wscratch, void* hip_stream) {
   MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
                    W % stride == 0, "conv adjoint: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
   MSL_TRY(check_ptr(w16, 2, "w16"));
@@ -1301,9 +1309,11 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
     h.H = H / stride; h.W = W / stride;   // the input of this product: dy
     h.Ho = H / stride; h.Wo = W / stride; // its output grid (half resolution for stride 2)
     h.relu = 0;
+    h.accum = accumulate ? 1 : 0;
     h.x = dy16; h.bias = nullptr; h.y = dx;
     return launch_conv_halo(h, Co, C, stride == 1 ? 1 : 2, w16, wscratch, true, static_cast<hipStream_t>(hip_stream));
   }
+  MSL_TRY(need(!accumulate, "conv adjoint: accumulate needs dx 8-byte aligned"));
   ConvArgs a{};
   a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
   a.K = Co * 9;

@@ -174,9 +174,6 @@ class UNet:
         # gradient buffers with the activations' shapes
         for k in ("e1a", "cat1", "e2a", "cat2", "e3a", "cat3", "e4a", "e4", "d3", "d2", "d1", "out"):
             b["d_" + k] = torch.zeros_like(b[k])
-        b["t1"] = z(c1, B, *hw[0])   # encoder gradient parts before the skip sum
-        b["t2"] = z(c2, B, *hw[1])
-        b["t3"] = z(c3, B, *hw[2])
         b["d_pred"] = torch.zeros_like(b["pred"])
         b["loss"] = torch.zeros((), dtype=torch.float64, device=d)
         # global head
@@ -199,8 +196,9 @@ class UNet:
         w16, bias, _, _ = self._wb(name)
         nn.conv3x3(co, ci, B, H, W, s, w16, x, y, bias=bias, relu=act)
 
-    def _conv_back(self, name, x, y, dy, dx, B, H, W):
-        """Weight and bias gradients of layer `name` into self.g; dx (may be None) = dL/dx."""
+    def _conv_back(self, name, x, y, dy, dx, B, H, W, accumulate=False):
+        """Weight and bias gradients of layer `name` into self.g; dx (may be None) = dL/dx, or
+        dx += dL/dx with accumulate (an input that also feeds a skip connection)."""
         wo, bo, co, ci, s, act = self.off[name]
         bf = self._bufs
         Ho, Wo = H // s, W // s
@@ -213,7 +211,7 @@ class UNet:
         splits = max(1, min(SPLIT_PARTS, N // 1024))
         nn.conv3x3_weight_grad(co, ci, B, H, W, s, dy16, x, gw, splits, bf["parts"])
         if dx is not None:
-            nn.conv3x3_adjoint(co, ci, B, H, W, s, w16, dy16, dx)
+            nn.conv3x3_adjoint(co, ci, B, H, W, s, w16, dy16, dx, accumulate=accumulate)
 
     def forward(self, x=None, B=None, H=256, W=256):
         """Network output for the input already in the buffer x (or copied from `x`)."""
@@ -304,14 +302,12 @@ class UNet:
         # encoder: skip gradients are the second parts of the concatenations
         de3, de2, de1 = bf["d_cat3"][c4:], bf["d_cat2"][c3:], bf["d_cat1"][c2:]
         self._conv_back("e4b", bf["e4a"], bf["e4"], bf["d_e4"], bf["d_e4a"], B, H // 8, W // 8)
-        self._conv_back("e4a", e3, bf["e4a"], bf["d_e4a"], bf["t3"], B, H // 4, W // 4)
-        nn.add_(bf["t3"], de3)
+        # each stride-2 layer's input gradient is added onto the skip gradient of the same tensor
+        self._conv_back("e4a", e3, bf["e4a"], bf["d_e4a"], de3, B, H // 4, W // 4, accumulate=True)
         self._conv_back("e3b", bf["e3a"], e3, de3, bf["d_e3a"], B, H // 4, W // 4)
-        self._conv_back("e3a", e2, bf["e3a"], bf["d_e3a"], bf["t2"], B, H // 2, W // 2)
-        nn.add_(bf["t2"], de2)
+        self._conv_back("e3a", e2, bf["e3a"], bf["d_e3a"], de2, B, H // 2, W // 2, accumulate=True)
         self._conv_back("e2b", bf["e2a"], e2, de2, bf["d_e2a"], B, H // 2, W // 2)
-        self._conv_back("e2a", e1, bf["e2a"], bf["d_e2a"], bf["t1"], B, H, W)
-        nn.add_(bf["t1"], de1)
+        self._conv_back("e2a", e1, bf["e2a"], bf["d_e2a"], de1, B, H, W, accumulate=True)
         self._conv_back("e1b", bf["e1a"], e1, de1, bf["d_e1a"], B, H, W)
         self._conv_back("e1a", bf["x"], bf["e1a"], bf["d_e1a"], None, B, H, W)
 

@@ -54,7 +54,7 @@ def lib():
             "msl_nn_add_row_bias": [I, I, I, P, P, P],
             "msl_nn_row_bias_adjoint": [I, I, I, P, P, P],
             "msl_nn_conv3x3": [I, I, I, I, I, I, P, P, P, I, P, P, P],
-            "msl_nn_conv3x3_adjoint": [I, I, I, I, I, I, P, P, P, P, P],
+            "msl_nn_conv3x3_adjoint": [I, I, I, I, I, I, P, P, P, I, P, P],
             "msl_nn_conv3x3_weight_grad": [I, I, I, I, I, I, P, P, P, I, P, P],
             "msl_nn_grad_prep": [I, I, P, P, P, P, P, P],
         }
@@ -120,10 +120,10 @@ def conv3x3(Co, C, B, H, W, stride, w16, x, y, bias=None, relu=False, scratch=No
                              int(relu), _p(y, torch.float32), _p(ws, BF16), _s()))
 
 
-def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx, scratch=None):
+def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx, scratch=None, accumulate=False):
     ws = scratch if scratch is not None else conv_scratch(Co, C, dx.device)
     _ck(lib().msl_nn_conv3x3_adjoint(Co, C, B, H, W, stride, _p(w16, BF16), _p(dy16, BF16), _p(dx, torch.float32),
-                                     _p(ws, BF16), _s()))
+                                     int(accumulate), _p(ws, BF16), _s()))
 
 
 def grad_prep(M, N, y, dy, dy16, bias_grad, parts):

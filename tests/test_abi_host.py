@@ -220,9 +220,10 @@ def test_nn_entry_points_validate(L):
     assert N.msl_nn_conv3x3(0, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, None, None) == msl.ERR_ARG      # no scratch
     assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, FAKE + 8, None) == msl.ERR_ARG  # misaligned
-    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, None, FAKE, FAKE, None) == msl.ERR_ARG
-    assert N.msl_nn_conv3x3_adjoint(4, 0, 2, 8, 8, 1, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
-    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, None, None) == msl.ERR_ARG      # no scratch
+    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, None, FAKE, 0, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3_adjoint(4, 0, 2, 8, 8, 1, FAKE, FAKE, FAKE, 0, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 0, None, None) == msl.ERR_ARG   # no scratch
+    assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 2, FAKE, FAKE, FAKE + 4, 1, FAKE, None) == msl.ERR_ARG  # accumulate, dx misaligned
     assert N.msl_nn_conv3x3_scratch_elems(20, 3) == 16 * 32 * 16 and N.msl_nn_conv3x3_scratch_elems(0, 3) == 0
     assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 0, FAKE, None) == msl.ERR_ARG   # splits
     assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 2, None, None) == msl.ERR_ARG

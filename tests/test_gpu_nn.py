@@ -117,6 +117,8 @@ def test_implicit_convolution(T, C, B, H, W, O, s):
     dy16 = dev(bf16_bits(dy))
     dx = torch.full((C, B, H, W), float("nan"), dtype=torch.float32, device="cuda")
     T.conv3x3_adjoint(O, C, B, H, W, s, w16, dy16, dx)
+    dx2 = dx.clone()
+    T.conv3x3_adjoint(O, C, B, H, W, s, w16, dy16, dx2, accumulate=True)   # dx2 = dx + dx, exactly
     splits = 3
     parts = torch.zeros(splits * O * C * 9, dtype=torch.float32, device="cuda")
     dw_exp = torch.zeros((O, C * 9), dtype=torch.float32, device="cuda")
@@ -130,6 +132,7 @@ def test_implicit_convolution(T, C, B, H, W, O, s):
     rdx, rdw, _ = N.conv3x3_adjoint(N.bf16(x), wb, dy, s)
     assert rel(y.cpu().numpy(), ref) <= 1e-6
     assert rel(dx.cpu().numpy(), rdx) <= 1e-6
+    assert np.array_equal(dx2.cpu().numpy(), 2 * dx.cpu().numpy())
     assert rel(dw.cpu().numpy(), rdw.reshape(O, C * 9)) <= 1e-6
 
 
