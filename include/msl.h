@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define MSL_ABI_VERSION 4
+#define MSL_ABI_VERSION 5
 
 typedef struct { float re, im; } msl_c64;
 
@@ -144,7 +144,7 @@ msl_status msl_forward(const msl_geometry* g, const float* delta, const float* b
  * GPU share its array, which keeps the last call's tables: calls that overlap
  * on one GPU (other streams, other host threads) race and must be ordered by
  * the caller.  The schedule setting is ignored (always one launch per pass). */
-#define MSL_NOALLOC_SCRATCH_BYTES ((size_t)(8 * 1024 * 8 + 2 * 512 * 512 * 8))
+#define MSL_NOALLOC_SCRATCH_BYTES ((size_t)(4 * 64 * 1024 * 8 + 2 * 512 * 512 * 8))
 msl_status msl_forward_noalloc(const msl_geometry* g, const float* delta, const float* beta,
                                const msl_c64* probe, msl_c64* field_out,
                                msl_c64* ckpt, int32_t ckpt_every, void* hip_stream);

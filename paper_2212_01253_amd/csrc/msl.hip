@@ -50,8 +50,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout (byte offsets, each region 256-byte aligned).
 struct Layout {
-  size_t twz_hi, twz_lo, twy_hi, twy_lo;
-  size_t hz_hi, hz_lo, hy_hi, hy_lo;
+  size_t twz, twy, hz, hy;  // line tables, [DITHER][n] float2
   size_t H_hi, H_lo;
   size_t bar, partials, tmp, dbT, W, G, seg, gT;
   size_t total;
@@ -65,14 +64,10 @@ Layout layout(const msl_geometry& g, int k) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
   L.bar = take(8192);  // first, at offset 0: msl_workspace_status finds its status word without the geometry
-  L.twz_hi = take(g.nz * 8);
-  L.twz_lo = take(g.nz * 8);
-  L.twy_hi = take(g.ny * 8);
-  L.twy_lo = take(g.ny * 8);
-  L.hz_hi = take(g.nz * 8);
-  L.hz_lo = take(g.nz * 8);
-  L.hy_hi = take(g.ny * 8);
-  L.hy_lo = take(g.ny * 8);
+  L.twz = take((size_t)msl::DITHER * g.nz * 8);
+  L.twy = take((size_t)msl::DITHER * g.ny * 8);
+  L.hz = take((size_t)msl::DITHER * g.nz * 8);
+  L.hy = take((size_t)msl::DITHER * g.ny * 8);
   const bool exact = g.propagator == MSL_PROP_EXACT;
   L.H_hi = take(exact ? m * 8 : 0);
   L.H_lo = take(exact ? m * 8 : 0);
@@ -103,7 +98,37 @@ msl_status check_ws(const msl_geometry& g, int k, const void* ws, size_t ws_byte
 
 
 // ---------------------------------------------------------------------------
-// table builders (FP64 arithmetic, results split into float32 hi + lo)
+// table builders (FP64 arithmetic; line tables as cycles of single float32
+// values, the exact propagator split into float32 hi + lo)
+
+// Writes out[i * stride], i < DITHER: the cycle of float32 values that stands
+// for x, each one of the two float32 neighbours of x, picked by a first-order
+// sigma-delta modulator (the one that keeps the running sum of the errors
+// smaller; ties take the lower), so that every partial sum of the errors over
+// the cycle stays within one ulp.  A representable x is used as is.
+__device__ inline void cycle_store(double x, float* out, int64_t stride) {
+  const float f = (float)x;
+  if ((double)f == x) {
+    for (int i = 0; i < msl::DITHER; ++i) out[i * stride] = f;
+    return;
+  }
+  const float lo = (double)f < x ? f : nextafterf(f, -INFINITY);
+  const float hi = nextafterf(lo, INFINITY);
+  double e = 0.0;
+  for (int i = 0; i < msl::DITHER; ++i) {
+    const double el = e + ((double)lo - x), eh = e + ((double)hi - x);
+    const bool up = fabs(eh) < fabs(el);
+    out[i * stride] = up ? hi : lo;
+    e = up ? eh : el;
+  }
+}
+
+// Element i of an n-element line table [DITHER][n] float2.
+__device__ inline void cycle_store2(double re, double im, float2* tab, int n, int i) {
+  float* const b = reinterpret_cast<float*>(tab) + 2 * (int64_t)i;
+  cycle_store(re, b, 2 * (int64_t)n);
+  cycle_store(im, b + 1, 2 * (int64_t)n);
+}
 
 __device__ inline void split_store(double re, double im, float2* hi, float2* lo, int64_t i) {
   const float hr = (float)re, hm = (float)im;
@@ -118,24 +143,25 @@ __device__ inline double kfreq(int m, int n, double d) {
   return 2.0 * M_PI * (double)f / ((double)n * d);
 }
 
-// Twiddles W_n^e = exp(-2 pi i e / n), e < n.
-__global__ void k_twiddles(int n, float2* hi, float2* lo) {
+// Twiddles W_n^e = exp(-2 pi i e / n), e < n, as a [DITHER][n] cycle table.
+__global__ void k_twiddles(int n, float2* tab) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double s, c;
   sincospi(-2.0 * (double)e / (double)n, &s, &c);
-  split_store(c, s, hi, lo, e);
+  cycle_store2(c, s, tab, n, e);
 }
 
-// Paraxial one-axis propagator factor exp(+i dx kq^2 / 2k) / n.
-__global__ void k_hpar(int n, double d, double dx, double k, float2* hi, float2* lo) {
+// Paraxial one-axis propagator factor exp(+i dx kq^2 / 2k) / n, as a
+// [DITHER][n] cycle table.
+__global__ void k_hpar(int n, double d, double dx, double k, float2* tab) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   const double q = kfreq(m, n, d);
   const double ph = dx * q * q / (2.0 * k);
   double s, c;
   sincos(ph, &s, &c);
-  split_store(c / n, s / n, hi, lo, m);
+  cycle_store2(c / n, s / n, tab, n, m);
 }
 
 // Exact angular-spectrum propagator H[my][mz] / ny.
@@ -450,14 +476,10 @@ Call make_call(const msl_geometry& g, const Layout& lay, void* ws, hipStream_t s
   c.ny = g.ny;
   c.nz = g.nz;
   c.m = (int64_t)g.ny * g.nz;
-  c.twz_hi = P(k_.L.twz_hi);
-  c.twz_lo = P(k_.L.twz_lo);
-  c.twy_hi = P(k_.L.twy_hi);
-  c.twy_lo = P(k_.L.twy_lo);
-  c.hz_hi = P(k_.L.hz_hi);
-  c.hz_lo = P(k_.L.hz_lo);
-  c.hy_hi = P(k_.L.hy_hi);
-  c.hy_lo = P(k_.L.hy_lo);
+  c.twz = P(k_.L.twz);
+  c.twy = P(k_.L.twy);
+  c.hz = P(k_.L.hz);
+  c.hy = P(k_.L.hy);
   c.H_hi = P(k_.L.H_hi);
   c.H_lo = P(k_.L.H_lo);
   const double kk = 2.0 * M_PI / g.wavelength_nm;
@@ -474,15 +496,15 @@ msl_status build_tables(const Call& k, bool need_prop) {
   const msl_geometry& g = k.g;
   auto P = [&](size_t off) { return reinterpret_cast<float2*>(k.ws + off); };
   const int tb = 256;
-  hipLaunchKernelGGL(k_twiddles, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, k.st, g.nz, P(k.L.twz_hi), P(k.L.twz_lo));
-  hipLaunchKernelGGL(k_twiddles, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, k.st, g.ny, P(k.L.twy_hi), P(k.L.twy_lo));
+  hipLaunchKernelGGL(k_twiddles, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, k.st, g.nz, P(k.L.twz));
+  hipLaunchKernelGGL(k_twiddles, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, k.st, g.ny, P(k.L.twy));
   if (need_prop) {
     const double kk = 2.0 * M_PI / g.wavelength_nm;
     if (g.propagator == MSL_PROP_PARAXIAL) {
       hipLaunchKernelGGL(k_hpar, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, k.st, g.nz, g.dz_nm, g.dx_nm, kk,
-                         P(k.L.hz_hi), P(k.L.hz_lo));
+                         P(k.L.hz));
       hipLaunchKernelGGL(k_hpar, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, k.st, g.ny, g.dy_nm, g.dx_nm, kk,
-                         P(k.L.hy_hi), P(k.L.hy_lo));
+                         P(k.L.hy));
     } else {
       const int64_t m = (int64_t)g.ny * g.nz;
       hipLaunchKernelGGL(k_hexact, dim3((unsigned)((m + tb - 1) / tb)), dim3(tb), 0, k.st, g.ny, g.nz, g.dy_nm,
@@ -701,7 +723,7 @@ hipError_t launch_pass_batch_axis(int n, const BatchRec* recs, int n_inst, int n
 // propagator factors), a scratch field for the far field and the packed
 // transmissions of its pool.
 struct BatchInstLayout {
-  size_t twz_hi, twz_lo, twy_hi, twy_lo, hz_hi, hz_lo, hy_hi, hy_lo, tmp, pack;
+  size_t twz, twy, hz, hy, tmp, pack;
 };
 
 struct BatchLayout {
@@ -720,14 +742,10 @@ BatchLayout batch_layout(const msl_instance* inst, int n) {
     const msl_geometry& g = inst[i].g;
     const size_t m = (size_t)g.ny * g.nz;
     BatchInstLayout& b = L.inst[i];
-    b.twz_hi = take(g.nz * 8);
-    b.twz_lo = take(g.nz * 8);
-    b.twy_hi = take(g.ny * 8);
-    b.twy_lo = take(g.ny * 8);
-    b.hz_hi = take(g.nz * 8);
-    b.hz_lo = take(g.nz * 8);
-    b.hy_hi = take(g.ny * 8);
-    b.hy_lo = take(g.ny * 8);
+    b.twz = take((size_t)msl::DITHER * g.nz * 8);
+    b.twy = take((size_t)msl::DITHER * g.ny * 8);
+    b.hz = take((size_t)msl::DITHER * g.nz * 8);
+    b.hy = take((size_t)msl::DITHER * g.ny * 8);
     b.tmp = take(m * 8);
     b.pack = take((size_t)inst[i].n_pool * m * 8);
   }
@@ -847,9 +865,9 @@ msl_status autotune_shapes(Run run, hipStream_t st, int reps, const int* slots, 
 // code reaches it only through the address hipGetSymbolAddress returns for the
 // current device (the array's name on the host is not a device address).
 
-constexpr size_t kNoAllocLineTable = 1024 * sizeof(float2);         // a line table of up to 1024 points
+constexpr size_t kNoAllocLineTable = (size_t)msl::DITHER * 1024 * sizeof(float2);  // a line table, up to 1024 points
 constexpr size_t kNoAllocHTable = (size_t)512 * 512 * sizeof(float2);  // exact propagator, up to 512 x 512
-constexpr size_t kNoAllocBytes = 8 * kNoAllocLineTable + 2 * kNoAllocHTable;
+constexpr size_t kNoAllocBytes = 4 * kNoAllocLineTable + 2 * kNoAllocHTable;
 static_assert(kNoAllocBytes == MSL_NOALLOC_SCRATCH_BYTES, "msl.h states the scratch size");
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
@@ -862,14 +880,10 @@ Layout noalloc_layout(const msl_geometry& g) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
-  L.twz_hi = take(g.nz * 8);
-  L.twz_lo = take(g.nz * 8);
-  L.twy_hi = take(g.ny * 8);
-  L.twy_lo = take(g.ny * 8);
-  L.hz_hi = take(g.nz * 8);
-  L.hz_lo = take(g.nz * 8);
-  L.hy_hi = take(g.ny * 8);
-  L.hy_lo = take(g.ny * 8);
+  L.twz = take((size_t)msl::DITHER * g.nz * 8);
+  L.twy = take((size_t)msl::DITHER * g.ny * 8);
+  L.hz = take((size_t)msl::DITHER * g.nz * 8);
+  L.hy = take((size_t)msl::DITHER * g.ny * 8);
   const bool exact = g.propagator == MSL_PROP_EXACT;
   const size_t m = (size_t)g.ny * g.nz;
   L.H_hi = take(exact ? m * 8 : 0);
@@ -1341,14 +1355,10 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
     c.ny = g.ny;
     c.nz = g.nz;
     c.m = (int64_t)g.ny * g.nz;
-    c.twz_hi = P(b.twz_hi);
-    c.twz_lo = P(b.twz_lo);
-    c.twy_hi = P(b.twy_hi);
-    c.twy_lo = P(b.twy_lo);
-    c.hz_hi = P(b.hz_hi);
-    c.hz_lo = P(b.hz_lo);
-    c.hy_hi = P(b.hy_hi);
-    c.hy_lo = P(b.hy_lo);
+    c.twz = P(b.twz);
+    c.twy = P(b.twy);
+    c.hz = P(b.hz);
+    c.hy = P(b.hy);
     const double kdx = 2.0 * M_PI / g.wavelength_nm * g.dx_nm;
     c.kdx_hi = (float)kdx;
     c.kdx_lo = (float)(kdx - (double)c.kdx_hi);
@@ -1360,12 +1370,10 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
     c.intensity = x.intensity_out;
     const int tb = 256;
     const double kk = 2.0 * M_PI / g.wavelength_nm;
-    hipLaunchKernelGGL(k_twiddles, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, st, g.nz, P(b.twz_hi), P(b.twz_lo));
-    hipLaunchKernelGGL(k_twiddles, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, st, g.ny, P(b.twy_hi), P(b.twy_lo));
-    hipLaunchKernelGGL(k_hpar, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, st, g.nz, g.dz_nm, g.dx_nm, kk, P(b.hz_hi),
-                       P(b.hz_lo));
-    hipLaunchKernelGGL(k_hpar, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, st, g.ny, g.dy_nm, g.dx_nm, kk, P(b.hy_hi),
-                       P(b.hy_lo));
+    hipLaunchKernelGGL(k_twiddles, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, st, g.nz, P(b.twz));
+    hipLaunchKernelGGL(k_twiddles, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, st, g.ny, P(b.twy));
+    hipLaunchKernelGGL(k_hpar, dim3((g.nz + tb - 1) / tb), dim3(tb), 0, st, g.nz, g.dz_nm, g.dx_nm, kk, P(b.hz));
+    hipLaunchKernelGGL(k_hpar, dim3((g.ny + tb - 1) / tb), dim3(tb), 0, st, g.ny, g.dy_nm, g.dx_nm, kk, P(b.hy));
     MSL_TRY(hip_check(hipGetLastError(), "table kernels"));
     float2* f = reinterpret_cast<float2*>(x.field_out);
     const float2* in = reinterpret_cast<const float2*>(x.probe);

@@ -7,11 +7,19 @@
 // once to float32 therefore contributes the same relative error at every
 // slice and the errors add up linearly with the slice count, while the
 // rounding of data-dependent sums and products behaves like a random walk.
-// Every multiplication by a constant (FFT twiddles, the radix-8 internal
-// factor sqrt(1/2), the propagator) is thus done with a two-term (hi + lo)
-// float32 constant applied through FMAs, and the transmission is applied as
-// psi + psi * (T - 1) with T - 1 evaluated directly, so that its rounding is
-// relative to the small quantity T - 1.
+// The constants of the paraxial passes (FFT twiddles, the radix-8 internal
+// factor sqrt(1/2), the one-axis propagator) are therefore single float32
+// values that change from pass to pass: each one takes, over a cycle of
+// DITHER passes along its axis, its two neighbouring float32 values in the
+// order of a first-order sigma-delta modulator, so the running sum of its
+// rounding errors stays within about one ulp instead of growing with the
+// slice count (pass s uses cycle position tab = (s / 2) mod DITHER, the same
+// in the forward sweep, the recompute and the reverse sweep, which is then
+// the exact adjoint of the computed forward).  The exact 2-D propagator,
+// applied through its own table, stays a two-term (hi + lo) constant applied
+// through FMAs.  The transmission is applied as psi + psi * (T - 1) with
+// T - 1 evaluated directly, so that its rounding is relative to the small
+// quantity T - 1.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,6 +39,7 @@ struct PassDesc {
   int pre, mid, post;
   int conj;             // adjoint: use conj(h) / conj(H)
   int slice;            // slice index of the transmission step
+  int tab;              // position in the constants' cycle, 0 .. DITHER - 1
   const float2* src;    // field read
   float2* dst;          // field written (may equal src; nullptr = not written)
   float2* psi_store;    // store the line before the mid step (nullptr = no)
@@ -51,11 +60,13 @@ struct Ctx {
   const float* beta;
   float* gdelta;                    // [Ns][ny][nz] or nullptr
   float* gbeta;
-  const float2* twz_hi; const float2* twz_lo;   // W_nz^e, e < nz
-  const float2* twy_hi; const float2* twy_lo;   // W_ny^e, e < ny
-  const float2* hz_hi; const float2* hz_lo;     // paraxial h_z / nz (DFT order)
-  const float2* hy_hi; const float2* hy_lo;     // paraxial h_y / ny
-  const float2* H_hi; const float2* H_lo;       // exact H[ky][kz] / ny
+  // Line tables, [DITHER][n] float2: row tab holds the constants of cycle
+  // position tab (see above)
+  const float2* twz;                // W_nz^e, e < nz
+  const float2* twy;                // W_ny^e, e < ny
+  const float2* hz;                 // paraxial h_z / nz (DFT order)
+  const float2* hy;                 // paraxial h_y / ny
+  const float2* H_hi; const float2* H_lo;       // exact H[ky][kz] / ny, two-term
   float kdx_hi, kdx_lo;             // k * dx as a two-term float
   float inv_m;                      // 1 / (ny nz)
   float* intensity;                 // far-field output (fftshifted) or nullptr
@@ -76,6 +87,37 @@ struct Ctx {
   const int32_t* slice_index;
   int32_t n_pool;
 };
+
+// ---------------------------------------------------------------------------
+// constants cycle
+
+constexpr int DITHER = 64;  // passes per axis in one cycle of the constants
+
+// sqrt(1/2) and its float32 neighbours below and above
+constexpr double RS2 = 0.70710678118654752440;
+constexpr float RS2_DN = 0.70710677f;
+constexpr float RS2_UP = 0.70710683f;
+static_assert((double)RS2_DN < RS2 && RS2 < (double)RS2_UP, "neighbours of sqrt(1/2)");
+
+// Bit i set: cycle position i uses RS2_UP.  First-order sigma-delta: each
+// position takes the neighbour that keeps the running error sum smaller.
+constexpr uint64_t rs2_cycle_mask() {
+  uint64_t m = 0;
+  double e = 0.0;
+  for (int i = 0; i < DITHER; ++i) {
+    const double dn = e + ((double)RS2_DN - RS2), upv = e + ((double)RS2_UP - RS2);
+    if ((upv < 0 ? -upv : upv) < (dn < 0 ? -dn : dn)) {
+      m |= 1ull << i;
+      e = upv;
+    } else {
+      e = dn;
+    }
+  }
+  return m;
+}
+constexpr uint64_t RS2_MASK = rs2_cycle_mask();
+
+__host__ __device__ inline float rs2_at(int tab) { return ((RS2_MASK >> tab) & 1) ? RS2_UP : RS2_DN; }
 
 // ---------------------------------------------------------------------------
 // complex helpers
@@ -100,11 +142,16 @@ __device__ __forceinline__ float2 cmul_comp_dyn(float2 x, float2 wh, float2 wl, 
   return conj ? cmul_comp<true>(x, wh, wl) : cmul_comp<false>(x, wh, wl);
 }
 
-// sqrt(1/2) as hi + lo float32 (hi = nearest float, lo = nearest float of the rest)
-constexpr float RS2_HI = 0.70710677f;
-constexpr float RS2_LO = 1.21016175e-08f;
+// x * w, or x * conj(w) when CONJ (single-term constant w).
+template <bool CONJ>
+__device__ __forceinline__ float2 cmul(float2 x, float2 w) {
+  const float wi = CONJ ? -w.y : w.y;
+  return make_float2(__builtin_fmaf(x.x, w.x, -(x.y * wi)), __builtin_fmaf(x.x, wi, x.y * w.x));
+}
 
-__device__ __forceinline__ float scale_rs2(float s) { return __builtin_fmaf(s, RS2_HI, s * RS2_LO); }
+__device__ __forceinline__ float2 cmul_dyn(float2 x, float2 w, bool conj) {
+  return conj ? cmul<true>(x, w) : cmul<false>(x, w);
+}
 
 // 4-point DFT, forward (W4 = -i) or inverse (W4 = +i), unnormalised.
 template <bool INV>
@@ -118,19 +165,20 @@ __device__ __forceinline__ void dft4(float2 y0, float2 y1, float2 y2, float2 y3,
   Y3 = csub(c1, c3);
 }
 
-// 8-point DFT in place: v[k] <- sum_n v[n] W8^{+-nk}.
+// 8-point DFT in place: v[k] <- sum_n v[n] W8^{+-nk}; rs2 is this pass's
+// float32 value of sqrt(1/2).
 template <bool INV>
-__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+__device__ __forceinline__ void dft8(float2 (&v)[8], float rs2) {
   const float2 a0 = cadd(v[0], v[4]), a1 = cadd(v[1], v[5]), a2 = cadd(v[2], v[6]), a3 = cadd(v[3], v[7]);
   float2 b0 = csub(v[0], v[4]), b1 = csub(v[1], v[5]), b2 = csub(v[2], v[6]), b3 = csub(v[3], v[7]);
   if (!INV) {
-    b1 = make_float2(scale_rs2(b1.x + b1.y), scale_rs2(b1.y - b1.x));    // * (1 - i)/sqrt2
-    b2 = make_float2(b2.y, -b2.x);                                      // * -i
-    b3 = make_float2(scale_rs2(b3.y - b3.x), -scale_rs2(b3.x + b3.y));  // * (-1 - i)/sqrt2
+    b1 = make_float2((b1.x + b1.y) * rs2, (b1.y - b1.x) * rs2);    // * (1 - i)/sqrt2
+    b2 = make_float2(b2.y, -b2.x);                                  // * -i
+    b3 = make_float2((b3.y - b3.x) * rs2, -((b3.x + b3.y) * rs2));  // * (-1 - i)/sqrt2
   } else {
-    b1 = make_float2(scale_rs2(b1.x - b1.y), scale_rs2(b1.x + b1.y));   // * (1 + i)/sqrt2
-    b2 = make_float2(-b2.y, b2.x);                                      // * +i
-    b3 = make_float2(-scale_rs2(b3.x + b3.y), scale_rs2(b3.x - b3.y));  // * (-1 + i)/sqrt2
+    b1 = make_float2((b1.x - b1.y) * rs2, (b1.x + b1.y) * rs2);     // * (1 + i)/sqrt2
+    b2 = make_float2(-b2.y, b2.x);                                  // * +i
+    b3 = make_float2(-((b3.x + b3.y) * rs2), (b3.x - b3.y) * rs2);  // * (-1 + i)/sqrt2
   }
   dft4<INV>(a0, a1, a2, a3, v[0], v[2], v[4], v[6]);
   dft4<INV>(b0, b1, b2, b3, v[1], v[3], v[5], v[7]);
@@ -163,9 +211,9 @@ struct LinePts {
 };
 
 template <int P, bool INV>
-__device__ __forceinline__ void dft_p(float2 (&v)[P]) {
+__device__ __forceinline__ void dft_p(float2 (&v)[P], float rs2) {
   if constexpr (P == 8) {
-    dft8<INV>(v);
+    dft8<INV>(v, rs2);
   } else {
     float2 y0, y1, y2, y3;
     dft4<INV>(v[0], v[1], v[2], v[3], y0, y1, y2, y3);
@@ -179,30 +227,28 @@ __device__ __forceinline__ void dft_p(float2 (&v)[P]) {
 // Per-lane twiddles of one line FFT: lane j of an N-point line needs
 // W_N^{(j mod NS) r N / (P NS)}, r = 1..P-1, for every twiddled radix-P stage
 // (sub-length NS = R0, P R0, ...).  They are loaded once per pass into
-// registers, hi and lo parts, and serve the forward and inverse transforms.
+// registers from the pass's row of the twiddle table and serve the forward
+// and inverse transforms; rs2 is the pass's value of sqrt(1/2).
 template <int N, int P = LinePts<N>::P>
 struct LineTw {
   static constexpr int LG = ilog2c(N), LP = ilog2c(P);
   static constexpr int R0LOG = (LG % LP == 0) ? LP : (LG % LP);
   static constexpr int R0 = 1 << R0LOG;     // first stage radix (no twiddles)
   static constexpr int NST = (LG - R0LOG) / LP;
-  float2 hi[NST][P - 1];
-  float2 lo[NST][P - 1];
+  float2 w[NST][P - 1];
+  float rs2;
 };
 
 template <int N, int P = LinePts<N>::P>
-__device__ __forceinline__ void load_tw(LineTw<N, P>& tw, const float2* __restrict__ twh,
-                                        const float2* __restrict__ twl, int j) {
+__device__ __forceinline__ void load_tw(LineTw<N, P>& tw, const float2* __restrict__ tab_row, int j, int tab) {
 #pragma unroll
   for (int s = 0, NS = LineTw<N, P>::R0; s < LineTw<N, P>::NST; ++s, NS *= P) {
     const int jm = j % NS;
     const int step = N / (P * NS);
 #pragma unroll
-    for (int r = 1; r < P; ++r) {
-      tw.hi[s][r - 1] = twh[jm * r * step];
-      tw.lo[s][r - 1] = twl[jm * r * step];
-    }
+    for (int r = 1; r < P; ++r) tw.w[s][r - 1] = tab_row[jm * r * step];
   }
+  tw.rs2 = rs2_at(tab);
 }
 
 // The two LDS exchange buffers of one line.  Consecutive exchanges of a
@@ -237,7 +283,7 @@ __device__ __forceinline__ void fft_line(float2 (&v)[P], const LineLds& sh, int 
   // ---- stage 0: radix R0, sub-length 1, trivial twiddles; writes exchange 0 (buffer a)
   float2* const w0 = sh.a;
   if constexpr (R0 == P) {
-    dft_p<P, INV>(v);
+    dft_p<P, INV>(v, tw.rs2);
 #pragma unroll
     for (int r = 0; r < P; ++r) w0[lds_pad(P * j + r)] = v[r];
   } else {
@@ -268,8 +314,8 @@ __device__ __forceinline__ void fft_line(float2 (&v)[P], const LineLds& sh, int 
 #pragma unroll
     for (int t = 0; t < P; ++t) v[t] = rd[lds_pad(j + t * L)];
 #pragma unroll
-    for (int r = 1; r < P; ++r) v[r] = cmul_comp<INV>(v[r], tw.hi[s][r - 1], tw.lo[s][r - 1]);
-    dft_p<P, INV>(v);
+    for (int r = 1; r < P; ++r) v[r] = cmul<INV>(v[r], tw.w[s][r - 1]);
+    dft_p<P, INV>(v, tw.rs2);
     if (s + 1 < NX) {
       float2* const wr = (s & 1) ? sh.a : sh.b;
       const int base = (j / NS) * NS * P + (j % NS);
@@ -435,7 +481,8 @@ struct LineIn {
   float dl[P], bt[P];     // delta, beta of the slice
   float2 ps[P];           // psi_s (adjoint)
   float gi[P];            // far-field seed (shifted read)
-  float2 hh[P], hl[P];    // propagator factor (1-D paraxial or 2-D exact)
+  float2 hh[P];           // propagator factor (1-D paraxial; 2-D exact: hi part)
+  float2 hl[P];           // 2-D exact propagator: lo part
   LineTw<N, P> tw;
 };
 
@@ -452,15 +499,12 @@ __device__ __forceinline__ void load_static(const Ctx& c, const PassDesc& pd_, i
     pd.mid = KIND == KIND_FWD_MID ? MID_T_FWD : MID_T_ADJ;
   }
   constexpr int L = N / P;
-  load_tw<N, P>(in.tw, AXIS == ROW ? c.twz_hi : c.twy_hi, AXIS == ROW ? c.twz_lo : c.twy_lo, j);
+  const uint32_t row = (uint32_t)pd.tab * (uint32_t)N;
+  load_tw<N, P>(in.tw, (AXIS == ROW ? c.twz : c.twy) + row, j, pd.tab);
   if (uses_h1d(pd)) {
-    const float2* hh = AXIS == ROW ? c.hz_hi : c.hy_hi;
-    const float2* hl = AXIS == ROW ? c.hz_lo : c.hy_lo;
+    const float2* hh = (AXIS == ROW ? c.hz : c.hy) + row;
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
-      in.hh[t] = hh[j + t * L];
-      in.hl[t] = hl[j + t * L];
-    }
+    for (int t = 0; t < P; ++t) in.hh[t] = hh[j + t * L];
   } else if (pd.post == POST_PROP2D) {
 #pragma unroll
     for (int t = 0; t < P; ++t) {
@@ -541,11 +585,14 @@ __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int
   for (int t = 0; t < P; ++t) in.v[t] = field_ld<COH>(pd.src + a.base + (uint32_t)t * a.stride);
 }
 
-template <int N, int P = LinePts<N>::P>
+// FFT, propagator, inverse FFT along the line: the one-axis paraxial factor
+// (single-term), or with TWO_TERM the exact 2-D factor (hi + lo).
+template <int N, bool TWO_TERM, int P = LinePts<N>::P>
 __device__ __forceinline__ void prop_line(float2 (&v)[P], const LineLds& sh, int j, const LineIn<N, P>& in, bool conj) {
   fft_line<N, false, P>(v, sh, j, in.tw);
 #pragma unroll
-  for (int t = 0; t < P; ++t) v[t] = cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj);
+  for (int t = 0; t < P; ++t)
+    v[t] = TWO_TERM ? cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj) : cmul_dyn(v[t], in.hh[t], conj);
   fft_line<N, true, P>(v, sh, j, in.tw);
 }
 
@@ -566,7 +613,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   switch (pd.pre) {
-    case PRE_PROP: prop_line<N, P>(v, sh, j, in, pd.conj != 0); break;
+    case PRE_PROP: prop_line<N, false, P>(v, sh, j, in, pd.conj != 0); break;
     case PRE_FFT: fft_line<N, false, P>(v, sh, j, in.tw); break;
     case PRE_IFFT_N:
       fft_line<N, true, P>(v, sh, j, in.tw);
@@ -638,9 +685,9 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   switch (pd.post) {
-    case POST_PROP: prop_line<N, P>(v, sh, j, in, pd.conj != 0); break;
+    case POST_PROP: prop_line<N, false, P>(v, sh, j, in, pd.conj != 0); break;
     case POST_FFT: fft_line<N, false, P>(v, sh, j, in.tw); break;
-    case POST_PROP2D: prop_line<N, P>(v, sh, j, in, pd.conj != 0); break;  // H[ky][kz] / ny loaded in hh, hl
+    case POST_PROP2D: prop_line<N, true, P>(v, sh, j, in, pd.conj != 0); break;  // H[ky][kz] / ny in hh, hl
     default: break;
   }
 

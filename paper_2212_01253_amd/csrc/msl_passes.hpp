@@ -75,6 +75,17 @@ __host__ __device__ inline int phase_npasses(const PhaseSpec& ph) {
 
 __host__ __device__ inline int work_lay(const PhaseSpec& ph) { return ph.rowmajor ? LAY_R : LAY_T; }
 
+// Cycle position of the constants (twiddles, sqrt(1/2), one-axis propagator)
+// in the passes that belong to slice s (s = ns: the pass after the last
+// slice).  Paraxial passes alternate axes with the slice parity, so each axis
+// advances one position every two slices; the exact schedule runs a pass
+// along each axis per slice.  Every phase (forward, recompute, reverse)
+// derives it from the slice alone, so the recompute repeats the forward
+// bit for bit and the reverse sweep applies the adjoint of the same constants.
+__host__ __device__ inline int tab_of(const PhaseSpec& ph, int s) {
+  return (ph.exact ? s : (s >> 1)) & (DITHER - 1);
+}
+
 // Layout of a segment field of slice s (its entrance field, stored by the
 // recompute and read by the reverse sweep): in the paraxial schedule both
 // passes run along the slice's own axis, so odd slices' fields are kept in
@@ -93,6 +104,7 @@ __host__ __device__ inline PassDesc make_pass(const PhaseSpec& ph, int axis, boo
   p.post = POST_NONE;
   p.conj = 0;
   p.slice = 0;
+  p.tab = 0;
   const int wl = work_lay(ph);
   if (first && ph.in_rm) {
     p.src = ph.in_rm;
@@ -141,6 +153,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       if (!ph.exact) {
         const int axis = ((ph.s0 + p) & 1) ? COL : ROW;
         PassDesc d = make_pass(ph, axis, first, last);
+        d.tab = tab_of(ph, ph.s0 + p);
         if (p < n) {
           d.pre = p == 0 ? PRE_NONE : PRE_PROP;
           d.mid = MID_T_FWD;
@@ -155,11 +168,13 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       } else {
         if (p & 1) {
           PassDesc d = make_pass(ph, COL, first, last);
+          d.tab = tab_of(ph, ph.s0 + p / 2);
           d.post = POST_PROP2D;
           return d;
         }
         const int q = p / 2;
         PassDesc d = make_pass(ph, ROW, first, last);
+        d.tab = tab_of(ph, ph.s0 + q);
         d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
         if (q < n) {
           d.mid = MID_T_FWD;
@@ -174,6 +189,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       if (!ph.exact) {
         const int axis = ((ph.s0 + p) & 1) ? COL : ROW;
         PassDesc d = make_pass(ph, axis, first, false);
+        d.tab = tab_of(ph, ph.s0 + p);
         d.pre = p == 0 ? PRE_NONE : PRE_PROP;
         if (p > 0) {
           d.psi_store = ph.seg + (int64_t)(p - 1) * ph.m;
@@ -190,11 +206,13 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       } else {
         if (p & 1) {
           PassDesc d = make_pass(ph, COL, first, false);
+          d.tab = tab_of(ph, ph.s0 + p / 2);
           d.post = POST_PROP2D;
           return d;
         }
         const int q = p / 2;
         PassDesc d = make_pass(ph, ROW, first, false);
+        d.tab = tab_of(ph, ph.s0 + q);
         d.pre = q == 0 ? PRE_NONE : PRE_IFFT_N;
         if (q > 0) {
           d.psi_store = ph.seg + (int64_t)(q - 1) * ph.m;
@@ -213,6 +231,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
       if (ph.leading && p == 0) {
         // precedes the pass of slice ns - 1, so it takes the other axis
         PassDesc d = make_pass(ph, phase_first_axis(ph), first, last);
+        d.tab = tab_of(ph, ph.ns);
         if (ph.exact) d.post = POST_FFT;
         else { d.pre = PRE_PROP; d.conj = 1; }
         return d;
@@ -222,6 +241,7 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
         const int s = ph.s1 - 1 - q;
         const int axis = (s & 1) ? COL : ROW;
         PassDesc d = make_pass(ph, axis, first, last);
+        d.tab = tab_of(ph, s);
         d.pre = PRE_PROP;
         d.conj = 1;
         d.mid = MID_T_ADJ;
@@ -239,11 +259,13 @@ __host__ __device__ inline PassDesc phase_pass(const PhaseSpec& ph, int p) {
         const int s = ph.s1 - 1 - q / 2;
         if ((q & 1) == 0) {
           PassDesc d = make_pass(ph, COL, first, last);
+          d.tab = tab_of(ph, s);
           d.post = POST_PROP2D;
           d.conj = 1;
           return d;
         }
         PassDesc d = make_pass(ph, ROW, first, last);
+        d.tab = tab_of(ph, s);
         d.pre = PRE_IFFT_N;
         d.mid = MID_T_ADJ;
         d.slice = s;

@@ -4,8 +4,9 @@
 // FP64 line engine (naive DFTs, exact propagator factors and transmission),
 // and compares the results with direct 2-D evaluations of the same
 // quantities.  This tests the scheduling logic (pass order, axis alternation,
-// checkpoint and segment slots, reverse indexing) without a GPU; the GPU
-// kernels are checked separately against the oracle.
+// checkpoint and segment slots, reverse indexing, the constants' cycle
+// positions) without a GPU; the GPU kernels are checked separately against
+// the oracle.
 //
 // Build: hipcc --offload-host-only -std=c++17 -I include -o schedule_check schedule_check.cpp
 // Run:   ./schedule_check   (prints "OK" and exits 0 on success)
@@ -38,6 +39,17 @@ cd hpar(int m, int n, double d, const Geo& g) {
   const double k = 2 * M_PI / g.lam, q = kf(m, n, d);
   return std::polar(1.0, g.dx * q * q / (2 * k));
 }
+
+// Stand-in for the cycle of single-float32 constants of the paraxial passes:
+// the engine multiplies the one-axis propagator factor of a pass at cycle
+// position t by a small phase that depends on t, the axis and the frequency,
+// and the direct references apply the factor that the slice calls for (its
+// pass along each axis advances one position every two slices).  A pass with
+// another position than its slice's, or a recompute or reverse pass whose
+// position differs from the forward's, then changes the results.
+cd tabmod(int t, int axis, int i) { return std::polar(1.0, 1e-3 * (t + 1) * (axis + 2) * (1 + i % 3)); }
+
+int slice_tab(int q) { return q / 2 % msl::DITHER; }
 
 cd hexact(int my, int mz, const Geo& g) {
   const double k = 2 * M_PI / g.lam, ky = kf(my, g.ny, g.dy), kz = kf(mz, g.nz, g.dz);
@@ -137,7 +149,7 @@ void run_pass(Engine& E, const msl::PassDesc& pd) {
     auto prop = [&](bool conj) {
       v = dft(v, -1);
       for (int i = 0; i < n; ++i) {
-        cd h = row ? hpar(i, g.nz, g.dz, g) : hpar(i, g.ny, g.dy, g);
+        cd h = (row ? hpar(i, g.nz, g.dz, g) : hpar(i, g.ny, g.dy, g)) * tabmod(pd.tab, pd.axis, i);
         v[i] *= (conj ? std::conj(h) : h) / double(n);
       }
       v = dft(v, +1);
@@ -228,6 +240,38 @@ Field prop2(const Field& x, const Geo& g, bool conj) {
   return dft2(y, g, +1);
 }
 
+// Paraxial propagation between the transmissions of slices s and s + 1 (s =
+// ns - 1: after the last): the second half of the pass of slice s and the
+// first half of the pass of slice s + 1, one along each axis, each with the
+// cycle factor of its own pass.
+Field prop_slice(const Field& x, const Geo& g, int s, bool conj) {
+  if (g.exact) return prop2(x, g, conj);
+  const int qr = (s % 2 == 0) ? s : s + 1, qc = (s % 2 == 1) ? s : s + 1;  // row pass: even slice
+  Field y = dft2(x, g, -1);
+  const double m = double(g.ny) * g.nz;
+  for (int r = 0; r < g.ny; ++r)
+    for (int c = 0; c < g.nz; ++c) {
+      const cd h = H2(r, c, g) * tabmod(slice_tab(qr), msl::ROW, c) * tabmod(slice_tab(qc), msl::COL, r);
+      y[(int64_t)r * g.nz + c] *= (conj ? std::conj(h) : h) / m;
+    }
+  return dft2(y, g, +1);
+}
+
+// Per axis, the forward phase's passes must take consecutive cycle positions
+// (one step per pass of that axis, wrapping at DITHER) from 0.
+int check_tab_sequence(const msl::PhaseSpec& ph) {
+  int next[2] = {0, 0};
+  for (int p = 0; p < msl::phase_npasses(ph); ++p) {
+    const msl::PassDesc d = msl::phase_pass(ph, p);
+    if (d.tab != next[d.axis]) {
+      std::printf("pass %d (axis %d) at cycle position %d, expected %d\n", p, d.axis, d.tab, next[d.axis]);
+      return 1;
+    }
+    next[d.axis] = (next[d.axis] + 1) % msl::DITHER;
+  }
+  return 0;
+}
+
 double rel(const Field& a, const Field& b) {
   double n = 0, d = 0;
   for (size_t i = 0; i < a.size(); ++i) { n += std::norm(a[i] - b[i]); d += std::norm(b[i]); }
@@ -285,6 +329,7 @@ int check(const Geo& g, int kck) {
     ph.out_rm = fake(9);
   }
   ph.ckpt = fake(1); ph.ckpt_every = kck;
+  int bad = check_tab_sequence(ph);
   run_phase(E, ph);
 
   // direct reference
@@ -293,9 +338,8 @@ int check(const Geo& g, int kck) {
   for (int s = 0; s < g.ns; ++s) {
     kept.push_back(psi);
     for (int64_t e = 0; e < m; ++e) psi[e] *= tfun(E, s, e);
-    psi = prop2(psi, g, false);
+    psi = prop_slice(psi, g, s, false);
   }
-  int bad = 0;
   const double ef = rel(out.f[0], psi);
   if (ef > 1e-10) { std::printf("forward mismatch %g\n", ef); ++bad; }
   for (int c = 0; c < nck; ++c) {
@@ -366,7 +410,7 @@ int check(const Geo& g, int kck) {
   std::vector<double> gd(g.ns * m), gb(g.ns * m);
   const double k = 2 * M_PI / g.lam;
   for (int s = g.ns - 1; s >= 0; --s) {
-    Field gp = prop2(gg, g, true);
+    Field gp = prop_slice(gg, g, s, true);
     for (int64_t e = 0; e < m; ++e) {
       const cd T = tfun(E, s, e);
       const cd cc = std::conj(gp[e]) * (T * kept[s][e]);
@@ -391,7 +435,7 @@ int main() {
   int bad = 0;
   for (int exact = 0; exact < 2; ++exact) {
     const int cfg[][4] = {{8, 16, 1, 1}, {8, 16, 5, 2}, {16, 8, 7, 3}, {8, 8, 6, 6}, {16, 16, 9, 4}, {8, 32, 4, 10},
-                          {16, 8, 11, 5}, {8, 8, 8, 3}, {16, 16, 2, 1}};
+                          {16, 8, 11, 5}, {8, 8, 8, 3}, {16, 16, 2, 1}, {8, 8, 140, 16}};
     for (auto& c : cfg) {
       Geo g{c[0], c[1], c[2], 0.9, 1.3, 7.0, 0.15, exact == 1};
       bad += check(g, c[3]);

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert msl.abi_version() == 4
+    assert msl.abi_version() == 5
 
 
 def G(**kw):

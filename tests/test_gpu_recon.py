@@ -103,10 +103,19 @@ def test_reconstruction_iterations_match_the_oracle(M):
     from paper_2212_01253_amd import recon
     g, region, kd, kb, counts, s, truth, init = _small_problem()
     lr = 1e-5
-    R = recon.Reconstructor(g, kd, kb, region, counts, s, ckpt_every=8, adam=recon.Adam(lr=lr))
+    amp = RO.poisson_loss_scale(counts, s)
+    # ADAM steps by about lr * g / (|g| + eps): with a negligible eps every voxel moves a full lr
+    # in the direction of its gradient's sign, and for the few voxels whose gradient is near zero
+    # (below 1e-5 of the largest) float32 rounding decides that sign (one such flip moves a voxel
+    # by 2 lr, as large as its delta, and the loss by ~1e-4).  An eps of 1e-2 of the largest
+    # first gradient lets those voxels take near-zero steps, so the comparison measures the
+    # gradient and the update, not rounding-decided signs; the descent is as fast (the loss falls
+    # 832 -> 71 in four steps).
+    _, g1 = RO.region_loss_and_gradient(g, kd, kb, region, init.astype(np.float64), amp)
+    eps = 1e-2 * float(np.abs(s * g1).max())
+    R = recon.Reconstructor(g, kd, kb, region, counts, s, ckpt_every=8, adam=recon.Adam(lr=lr, eps=eps))
     res = R.run(init, 4)
     th_gpu = R.theta.cpu().numpy()
-    amp = RO.poisson_loss_scale(counts, s)
     th, m, v = init.astype(np.float64), np.zeros(init.shape), np.zeros(init.shape)
     ref = []
     for t in range(1, 6):
@@ -114,14 +123,12 @@ def test_reconstruction_iterations_match_the_oracle(M):
         ref.append(s * L)
         if t == 5:
             break
-        th, m, v = RO.adam_step(th, s * gth, m, v, t, lr, 0.9, 0.999, 1e-12, 0.0, 1e-3)
+        th, m, v = RO.adam_step(th, s * gth, m, v, t, lr, 0.9, 0.999, eps, 0.0, 1e-3)
     rl = np.abs(np.array(res.losses) - np.array(ref)) / np.array(ref)
     dth = np.abs(th_gpu - th)
     print("loss rel", rl, "theta |diff| / lr: max", dth.max() / lr, "mean", dth.mean() / lr)
+    assert ref[-1] < 0.2 * ref[0]
     assert np.all(rl <= 1e-4)
-    # ADAM's early steps are ~lr * sign(gradient): a voxel whose gradient is near zero could take
-    # a different sign in float32 and move by up to 2 lr per step; none does here (measured
-    # max 1.2e-3 lr, mean 9e-6 lr)
     assert dth.max() <= 0.05 * lr
     assert dth.mean() <= 1e-3 * lr
 
