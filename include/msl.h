@@ -67,7 +67,7 @@
 extern "C" {
 #endif
 
-#define MSL_ABI_VERSION 5
+#define MSL_ABI_VERSION 6
 
 typedef struct { float re, im; } msl_c64;
 

@@ -61,15 +61,18 @@ int64_t msl_nn_conv3x3_scratch_elems(int32_t Co, int32_t C);
 /* 3x3 convolution, zero padding 1, stride 1 or 2, as an implicit matrix-core product on halo tiles
  * (no patch matrix in memory):
  * y[o][b][i][j] = act(sum_c sum_t w16[o][9c + t] bf16(x[c][b][s i + dy][s j + dx]) + bias[o]),
- * t = 3 (dy + 1) + (dx + 1); x float32 [C][B][H][W], w16 bfloat16 [Co][9C], bias float32 [Co] or
- * NULL, relu 0/1, y float32 [Co][B][H/s][W/s].  The products and sums are those of
- * msl_nn_gemm_bf16 with the patch matrix, in another order (over taps, then channels in
- * chunks of 16), so the two agree to float32 rounding.  wscratch: device, 16-byte aligned,
- * msl_nn_conv3x3_scratch_elems(Co, C) bfloat16 elements, overwritten (the weights in
- * [Co][9][pad16(C)] order); the call reads w16 once per call, not once per tile. */
+ * t = 3 (dy + 1) + (dx + 1); x [C][B][H][W] float32 (x_bf16 0) or bfloat16 bits (x_bf16 1: used
+ * as is, the same product as float32 x holding those values), w16 bfloat16 [Co][9C], bias float32
+ * [Co] or NULL, relu 0/1, y [Co][B][H/s][W/s] float32 (y_bf16 0) or bfloat16 bits (y_bf16 1: the
+ * float32 result rounded to nearest even; an activation stored for the next layer, which rounds
+ * its input to bfloat16 anyway).  The products and sums are those of msl_nn_gemm_bf16 with the
+ * patch matrix, in another order (over taps, then channels in chunks of 16), so the two agree to
+ * float32 rounding.  wscratch: device, 16-byte aligned, msl_nn_conv3x3_scratch_elems(Co, C)
+ * bfloat16 elements, overwritten (the weights in [Co][9][pad16(C)] order); the call reads w16 once
+ * per call, not once per tile. */
 msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const uint16_t* w16,
-                          const float* x, const float* bias, int32_t relu, float* y, uint16_t* wscratch,
-                          void* hip_stream);
+                          const void* x, int32_t x_bf16, const float* bias, int32_t relu, void* y, int32_t y_bf16,
+                          uint16_t* wscratch, void* hip_stream);
 
 /* Its input gradient, also implicit: dx[c][b][y][x] = sum over o and taps t of w16[o][9c + t] dy16[o][b][i][j]
  * where s i + dy = y and s j + dx = x (dy16 bfloat16 [Co][B][H/s][W/s]; dx float32 [C][B][H][W],
@@ -84,19 +87,21 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
                                   uint16_t* wscratch, void* hip_stream);
 
 /* Its weight gradient, implicit as well: dw[o][9c + t] = sum over output pixels p of dy16[o][p] times the
- * patch value (c, t) at p (x rounded to bfloat16 as in the forward); the pixel sum is split into at
+ * patch value (c, t) at p (x float32 rounded to bfloat16 as in the forward, or with x_bf16 1 bfloat16
+ * bits used as is: the same result as float32 x holding those values); the pixel sum is split into at
  * most `splits` parts written to partials (float32 [splits][Co][9C], caller-owned scratch) and then
  * summed in a fixed order into dw (float32 [Co][9C]).  When the output width W/s is a multiple of 8 the parts
  * are ranges of 128/s-pixel halo tiles (as many parts as fill the GPU, at most `splits`), otherwise
  * ranges of pixels of the patch-column product (msl_nn_gemm_bf16_splitk of dy16 and the patch
  * matrix, bit for bit).  1 <= splits <= 4096. */
 msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
-                                     const uint16_t* dy16, const float* x, float* dw, int32_t splits, float* partials,
-                                     void* hip_stream);
+                                     const uint16_t* dy16, const void* x, int32_t x_bf16, float* dw, int32_t splits,
+                                     float* partials, void* hip_stream);
 
 /* Nearest 2x upsampling [C][B][H][W] -> [C][B][2H][2W] (y may be a channel slice of a larger
- * array: it is written at y with the [C][B][2H][2W] layout), and its adjoint (sum of the four). */
-msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const float* x, float* y,
+ * array: it is written at y with the [C][B][2H][2W] layout; x and y float32, or bfloat16 bits with
+ * bf16 1, copied unchanged), and its adjoint (float32, sum of the four). */
+msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const void* x, void* y, int32_t bf16,
                             void* hip_stream);
 msl_status msl_nn_upsample2_adjoint(int32_t C, int32_t B, int32_t H, int32_t W, const float* dy, float* dx,
                                     void* hip_stream);
@@ -127,12 +132,12 @@ msl_status msl_nn_add(int64_t n, const float* x, float* y, void* hip_stream);
 msl_status msl_nn_to_bf16(int64_t n, const float* x, uint16_t* y16, void* hip_stream);
 
 /* One layer's output gradient made ready for its backward products, in one pass over dy (float32
- * [M][N], read only): g = dy where y > 0, else 0 (the ReLU adjoint; y float32 [M][N], or NULL for no
- * activation); dy16[m][n] = bfloat16(g) and bias_grad[m] = sum_n g (fixed-order sums, as
+ * [M][N], read only): g = dy where y > 0, else 0 (the ReLU adjoint; y [M][N] float32, or bfloat16
+ * bits with y_bf16 1, or NULL for no activation); dy16[m][n] = bfloat16(g) and bias_grad[m] = sum_n g (fixed-order sums, as
  * msl_nn_rowsum; parts: float32 scratch of at least 64 M).  dy16 equals msl_nn_relu_adjoint then
  * msl_nn_to_bf16 bit for bit; bias_grad is msl_nn_rowsum of g summed in another fixed order. */
-msl_status msl_nn_grad_prep(int32_t M, int32_t N, const float* y, const float* dy, uint16_t* dy16, float* bias_grad,
-                            float* parts, void* hip_stream);
+msl_status msl_nn_grad_prep(int32_t M, int32_t N, const void* y, int32_t y_bf16, const float* dy, uint16_t* dy16,
+                            float* bias_grad, float* parts, void* hip_stream);
 
 /* out[m] = sum_n X[m * N + n] (float32 sums of float32 rows, bias gradients), in a fixed order:
  * 64 partial sums per row into parts (float32 [M][64], caller-owned scratch), then their sum. */

@@ -122,6 +122,7 @@ struct ConvArgs {
   int64_t N;  // GEMM columns: B * Ho * Wo (forward) or B * H * W (input gradient)
   const uint16_t* w16;  // [Co][C * 9]
   const float* x;       // forward input [C][B][H][W]
+  const uint16_t* x16;  // weight gradient: the input as bfloat16 bits instead of x (or nullptr)
   const uint16_t* dy16; // input gradient: output gradient [Co][B][Ho][Wo], bfloat16
   const float* bias;
   float* y;             // forward output [Co][B][Ho][Wo] or input gradient [C][B][H][W]
@@ -368,16 +369,18 @@ __global__ void __launch_bounds__(256) k_conv_bwd_weight(ConvArgs a, int kchunk,
         b = (int)(t / a.Ho);
       }
       const int y0 = a.s * i - 1, x0 = a.s * j - 1;
-      const float* xb = a.x + (int64_t)b * a.H * a.W;
+      const int64_t ib = (int64_t)b * a.H * a.W;
       const int nb = n0 + nq;
       int c = nb / 9, tap = nb - 9 * c;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        float val = 0.0f;
+        uint16_t val = 0;
         const int yy = y0 + tap / 3, xx = x0 + tap % 3;
-        if (p_ok && nb + q < NC && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-          val = xb[(int64_t)c * cstride + (int64_t)yy * a.W + xx];
-        Bs[nq + q][kk] = to_bf16(val);
+        if (p_ok && nb + q < NC && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+          const int64_t e = ib + (int64_t)c * cstride + (int64_t)yy * a.W + xx;
+          val = a.x16 ? a.x16[e] : to_bf16(a.x[e]);
+        }
+        Bs[nq + q][kk] = val;
         if (++tap == 9) {
           tap = 0;
           ++c;
@@ -472,11 +475,12 @@ struct HaloArgs {
   int TW, TH, tiles_x, tiles_y;
   int Cp;                // row length of wp per tap: pad16(C)
   int vec;               // W a multiple of 4 and x aligned: whole 4-position groups read at once
-  int accum;             // add the result to y instead of overwriting it
+  int accum;             // add the result to y instead of overwriting it (float32 y only)
+  int ybf16;             // y holds bfloat16 bits (rounded to nearest even) instead of float32
   const uint16_t* wp;    // packed weights [M][9][Cp] (k_pack_weights)
   const void* x;         // [C][B][H][W], float32 or (xbf16) bfloat16 bits
   const float* bias;     // [M] or nullptr
-  float* y;              // [M][B][Ho][Wo]
+  void* y;               // [M][B][Ho][Wo], float32 or (ybf16) bfloat16 bits
 };
 
 // Four consecutive values of one channel row as bfloat16 bits: positions x0 .. x0+3 of row `row`
@@ -620,7 +624,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
       for (int i = 0; i < 4; ++i) {
         const int c = (m0 + cb * 32 + 8 * i + 4 * (lane >> 5)) >> 2;
         if (4 * c < a.M) {
-          float* const d = a.y + (int64_t)c * npix2 + o;
+          float* const d = static_cast<float*>(a.y) + (int64_t)c * npix2 + o;
           float2 u0 = make_float2(acc[4 * i + 0], acc[4 * i + 1]), u1 = make_float2(acc[4 * i + 2], acc[4 * i + 3]);
           if (a.accum) {
             const float2 p0 = *reinterpret_cast<const float2*>(d), p1 = *reinterpret_cast<const float2*>(d + W2);
@@ -643,8 +647,14 @@ __global__ void __launch_bounds__(256) k_conv_halo(HaloArgs a) {
             float v = acc[4 * i + j];
             if (a.bias) v += a.bias[m];
             if (a.relu) v = fmaxf(v, 0.0f);
-            if (a.accum) v += a.y[(int64_t)m * npix + o];
-            a.y[(int64_t)m * npix + o] = v;
+            const int64_t e = (int64_t)m * npix + o;
+            if (a.ybf16) {
+              static_cast<uint16_t*>(a.y)[e] = to_bf16(v);
+            } else {
+              float* const yf = static_cast<float*>(a.y);
+              if (a.accum) v += yf[e];
+              yf[e] = v;
+            }
           }
         }
     }
@@ -670,7 +680,7 @@ struct WgradArgs {
   int TW, TH, KT, tiles_x, tiles_y, ntiles, per_part;
   int vec;
   const uint16_t* dy16;  // [Co][B][Ho][Wo]
-  const float* x;        // [C][B][H][W]
+  const void* x;         // [C][B][H][W], float32 or (XBF16) bfloat16 bits
   float* partials;       // [parts][Co][9C]
 };
 
@@ -685,7 +695,7 @@ int wgrad_lds_bytes(int TW, int TH, int s, int ot) {
   return (wgrad_xs_slots(TW, TH, s) + ot * WOC * (TW * TH + 8)) * (int)sizeof(uint16_t);
 }
 
-template <int OT>
+template <int OT, bool XBF16>
 __global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
   constexpr int NOC = 32 * OT;                      // output channels of this workgroup
   extern __shared__ __attribute__((aligned(16))) uint16_t wg_smem[];
@@ -713,7 +723,7 @@ __global__ void __launch_bounds__(192) k_conv_wgrad_halo(WgradArgs a) {
     const int oy0 = (t % a.tiles_y) * a.TH;
     const int b = t / a.tiles_y;
     const int iy0 = oy0 * a.s - 1, ix0 = ox0 * a.s - 1;
-    stage_block<WCK, WCKP, false>(xs, a.x, a.C, c0, cstride, (int64_t)b * plane, a.H, a.W, iy0, ix0, HH, HW, vec);
+    stage_block<WCK, WCKP, XBF16>(xs, a.x, a.C, c0, cstride, (int64_t)b * plane, a.H, a.W, iy0, ix0, HH, HW, vec);
     // dy tile: item = (output channel, 8-pixel group of a tile row)
     const int ng = a.KT / 8;
     for (int it = tid; it < NOC * ng; it += blockDim.x) {
@@ -866,19 +876,26 @@ __global__ void __launch_bounds__(256) k_col2im(int C, int B, int H, int W, int 
   }
 }
 
+// Two equal neighbouring elements as one store (8 bytes for float32, 4 for bfloat16 bits).
+__device__ __forceinline__ void store_pair(float* p, float v) { *reinterpret_cast<float2*>(p) = make_float2(v, v); }
+__device__ __forceinline__ void store_pair(uint16_t* p, uint16_t v) {
+  *reinterpret_cast<uint32_t*>(p) = (uint32_t)v | ((uint32_t)v << 16);
+}
+
 // Nearest 2x upsampling, one thread per input element x[r][w] (r over C B H rows): it writes the
 // 2 x 2 block y[2r + d][2w .. 2w+1] (output row 2r + d of [C][B][2H][2W] is row r's copy d), as
-// 8-byte stores when y is 8-byte aligned.  IDX: the index type (32-bit when the sizes allow).
-template <typename IDX>
-__global__ void __launch_bounds__(256) k_upsample2(IDX total, int W, int vec, const float* __restrict__ x,
-                                                   float* __restrict__ y) {
+// two pair stores when y is aligned for them.  IDX: the index type (32-bit when the sizes allow);
+// T: float (float32) or uint16_t (bfloat16 bits, copied unchanged).
+template <typename IDX, typename T>
+__global__ void __launch_bounds__(256) k_upsample2(IDX total, int W, int vec, const T* __restrict__ x,
+                                                   T* __restrict__ y) {
   for (IDX e = (IDX)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (IDX)gridDim.x * blockDim.x) {
     const IDX r = e / W, w = e - r * W;
-    const float v = x[e];
-    float* const o = y + 2 * r * (2 * (IDX)W) + 2 * w;
+    const T v = x[e];
+    T* const o = y + 2 * r * (2 * (IDX)W) + 2 * w;
     if (vec) {
-      *reinterpret_cast<float2*>(o) = make_float2(v, v);
-      *reinterpret_cast<float2*>(o + 2 * W) = make_float2(v, v);
+      store_pair(o, v);
+      store_pair(o + 2 * W, v);
     } else {
       o[0] = v;
       o[1] = v;
@@ -1029,10 +1046,13 @@ __global__ void __launch_bounds__(64) k_rowsum_final(const float* __restrict__ p
 // is given: the ReLU adjoint), written as bfloat16 to dy16, and the partial row sums of g (bias
 // gradient; rows of N columns, kRowParts column chunks each, finished by k_rowsum_final).  dy is
 // read only.  VEC: N a multiple of 4 and the arrays aligned, four columns per access.
-template <bool VEC>
-__global__ void __launch_bounds__(256) k_grad_prep(int N, int chunk, const float* __restrict__ y,
+template <bool VEC, bool YBF16>
+__global__ void __launch_bounds__(256) k_grad_prep(int N, int chunk, const void* __restrict__ yv,
                                                    const float* __restrict__ dy, uint16_t* __restrict__ dy16,
                                                    float* __restrict__ part) {
+  const float* const y = static_cast<const float*>(yv);
+  const uint16_t* const y16 = static_cast<const uint16_t*>(yv);
+  auto bf = [](uint32_t h) { return __uint_as_float(h << 16); };
   __shared__ float red[256];
   const int n0 = blockIdx.x * chunk, n1 = min(N, n0 + chunk);
   const int64_t row = (int64_t)blockIdx.y * N;
@@ -1040,8 +1060,14 @@ __global__ void __launch_bounds__(256) k_grad_prep(int N, int chunk, const float
   if constexpr (VEC) {
     for (int n = n0 + 4 * (int)threadIdx.x; n < n1; n += 4 * 256) {
       float4 g = *reinterpret_cast<const float4*>(dy + row + n);
-      if (y) {
-        const float4 v = *reinterpret_cast<const float4*>(y + row + n);
+      if (yv) {
+        float4 v;
+        if constexpr (YBF16) {
+          const uint2 h = *reinterpret_cast<const uint2*>(y16 + row + n);
+          v = make_float4(bf(h.x & 0xffffu), bf(h.x >> 16), bf(h.y & 0xffffu), bf(h.y >> 16));
+        } else {
+          v = *reinterpret_cast<const float4*>(y + row + n);
+        }
         if (!(v.x > 0.0f)) g.x = 0.0f;
         if (!(v.y > 0.0f)) g.y = 0.0f;
         if (!(v.z > 0.0f)) g.z = 0.0f;
@@ -1056,7 +1082,7 @@ __global__ void __launch_bounds__(256) k_grad_prep(int N, int chunk, const float
   } else {
     for (int n = n0 + (int)threadIdx.x; n < n1; n += 256) {
       float g = dy[row + n];
-      if (y && !(y[row + n] > 0.0f)) g = 0.0f;
+      if (yv && !((YBF16 ? bf(y16[row + n]) : y[row + n]) > 0.0f)) g = 0.0f;
       dy16[row + n] = to_bf16(g);
       acc += g;
     }
@@ -1273,21 +1299,22 @@ int64_t msl_nn_conv3x3_scratch_elems(int32_t Co, int32_t C) {
 }
 
 msl_status msl_nn_conv3x3(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride, const uint16_t* w16,
-                          const float* x, const float* bias, int32_t relu, float* y, uint16_t* wscratch,
-                          void* hip_stream) {
+                          const void* x, int32_t x_bf16, const float* bias, int32_t relu, void* y, int32_t y_bf16,
+                          uint16_t* wscratch, void* hip_stream) {
   MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
                    W % stride == 0, "conv: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
   MSL_TRY(check_ptr(w16, 2, "w16"));
-  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(x, x_bf16 ? 2 : 4, "x"));
   MSL_TRY(check_ptr(bias, 4, "bias", true));
-  MSL_TRY(check_ptr(y, 4, "y"));
+  MSL_TRY(check_ptr(y, y_bf16 ? 2 : 4, "y"));
   MSL_TRY(check_ptr(wscratch, 16, "wscratch"));
   MSL_TRY(need((int64_t)C * 9 < (1 << 30) && (int64_t)B * H * W < (1ll << 40), "conv: sizes too large"));
   HaloArgs a{};
   a.M = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
   a.relu = relu ? 1 : 0;
+  a.ybf16 = y_bf16 ? 1 : 0;
   a.x = x; a.bias = bias; a.y = y;
-  return launch_conv_halo(a, Co, C, 0, w16, wscratch, false, static_cast<hipStream_t>(hip_stream));
+  return launch_conv_halo(a, Co, C, 0, w16, wscratch, x_bf16 != 0, static_cast<hipStream_t>(hip_stream));
 }
 
 msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
@@ -1327,13 +1354,13 @@ msl_status msl_nn_conv3x3_adjoint(int32_t Co, int32_t C, int32_t B, int32_t H, i
 }
 
 msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t H, int32_t W, int32_t stride,
-                                     const uint16_t* dy16, const float* x, float* dw, int32_t splits, float* partials,
-                                     void* hip_stream) {
+                                     const uint16_t* dy16, const void* x, int32_t x_bf16, float* dw, int32_t splits,
+                                     float* partials, void* hip_stream) {
   MSL_TRY(need(Co >= 1 && C >= 1 && B >= 1 && H >= 1 && W >= 1 && (stride == 1 || stride == 2) && H % stride == 0 &&
                    W % stride == 0, "conv weight gradient: need Co, C, B, H, W >= 1, stride 1 or 2 dividing H and W"));
   MSL_TRY(need(splits >= 1 && splits <= 4096, "conv weight gradient: splits must be in [1, 4096]"));
   MSL_TRY(check_ptr(dy16, 2, "dy16"));
-  MSL_TRY(check_ptr(x, 4, "x"));
+  MSL_TRY(check_ptr(x, x_bf16 ? 2 : 4, "x"));
   MSL_TRY(check_ptr(dw, 4, "dw"));
   MSL_TRY(check_ptr(partials, 4, "partials"));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -1360,12 +1387,15 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
     parts = std::max(1, std::min(parts, (2048 + cb * ob - 1) / (cb * ob)));
     w.per_part = (int)((ntiles + parts - 1) / parts);
     parts = (int)((ntiles + w.per_part - 1) / w.per_part);
-    w.vec = (W % 4 == 0 && aligned(x, 16)) ? 1 : 0;
+    w.vec = (W % 4 == 0 && aligned(x, x_bf16 ? 8 : 16)) ? 1 : 0;
     w.dy16 = dy16; w.x = x; w.partials = partials;
     const int lds = wgrad_lds_bytes(w.TW, w.TH, stride, ot);
     MSL_TRY(need(lds <= 64 * 1024 && cb <= 65535 && ob <= 65535, "conv weight gradient: sizes too large"));
-    if (ot == 2) hipLaunchKernelGGL(k_conv_wgrad_halo<2>, dim3(cb, ob, parts), dim3(192), lds, st, w);
-    else hipLaunchKernelGGL(k_conv_wgrad_halo<1>, dim3(cb, ob, parts), dim3(192), lds, st, w);
+    const dim3 grid(cb, ob, parts);
+    if (ot == 2 && x_bf16) hipLaunchKernelGGL((k_conv_wgrad_halo<2, true>), grid, dim3(192), lds, st, w);
+    else if (ot == 2) hipLaunchKernelGGL((k_conv_wgrad_halo<2, false>), grid, dim3(192), lds, st, w);
+    else if (x_bf16) hipLaunchKernelGGL((k_conv_wgrad_halo<1, true>), grid, dim3(192), lds, st, w);
+    else hipLaunchKernelGGL((k_conv_wgrad_halo<1, false>), grid, dim3(192), lds, st, w);
     const int64_t mn = (int64_t)Co * 9 * C;
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((mn + 15) / 16)), dim3(256), 0, st, mn, parts, partials, Co,
                        9 * C, 9 * C, dw);
@@ -1373,7 +1403,9 @@ msl_status msl_nn_conv3x3_weight_grad(int32_t Co, int32_t C, int32_t B, int32_t 
   }
   ConvArgs a{};
   a.Co = Co; a.C = C; a.B = B; a.H = H; a.W = W; a.s = stride; a.Ho = H / stride; a.Wo = W / stride;
-  a.dy16 = dy16; a.x = x;
+  a.dy16 = dy16;
+  if (x_bf16) a.x16 = static_cast<const uint16_t*>(x);
+  else a.x = static_cast<const float*>(x);
   const int64_t npix = (int64_t)B * a.Ho * a.Wo;
   MSL_TRY(need(npix < (1ll << 40) && (int64_t)C * 9 < (1 << 30), "conv weight gradient: sizes too large"));
   // pixel range per part: a multiple of the K tile (the split of msl_nn_gemm_bf16_splitk)
@@ -1422,17 +1454,28 @@ msl_status msl_nn_col2im3x3(int32_t C, int32_t B, int32_t H, int32_t W, int32_t 
   return launched("col2im kernel");
 }
 
-msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const float* x, float* y, void* hip_stream) {
+msl_status msl_nn_upsample2(int32_t C, int32_t B, int32_t H, int32_t W, const void* x, void* y, int32_t bf16,
+                            void* hip_stream) {
   MSL_TRY(need(C >= 1 && B >= 1 && H >= 1 && W >= 1, "upsample: sizes must be >= 1"));
-  MSL_TRY(check_ptr(x, 4, "x"));
-  MSL_TRY(check_ptr(y, 4, "y"));
+  const int es = bf16 ? 2 : 4;
+  MSL_TRY(check_ptr(x, es, "x"));
+  MSL_TRY(check_ptr(y, es, "y"));
   const int64_t total = (int64_t)C * B * H * W;   // input elements
-  const int vec = aligned(y, 8) ? 1 : 0;
+  const int vec = aligned(y, 2 * es) ? 1 : 0;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (4 * total < (1ll << 31))
-    hipLaunchKernelGGL(k_upsample2<int32_t>, dim3(blocks_for(total)), dim3(256), 0, st, (int32_t)total, W, vec, x, y);
-  else
-    hipLaunchKernelGGL(k_upsample2<int64_t>, dim3(blocks_for(total)), dim3(256), 0, st, total, W, vec, x, y);
+  const dim3 grid(blocks_for(total));
+  const bool small = 4 * total < (1ll << 31);
+  if (bf16) {
+    const uint16_t* xb = static_cast<const uint16_t*>(x);
+    uint16_t* yb = static_cast<uint16_t*>(y);
+    if (small) hipLaunchKernelGGL((k_upsample2<int32_t, uint16_t>), grid, dim3(256), 0, st, (int32_t)total, W, vec, xb, yb);
+    else hipLaunchKernelGGL((k_upsample2<int64_t, uint16_t>), grid, dim3(256), 0, st, total, W, vec, xb, yb);
+  } else {
+    const float* xf = static_cast<const float*>(x);
+    float* yf = static_cast<float*>(y);
+    if (small) hipLaunchKernelGGL((k_upsample2<int32_t, float>), grid, dim3(256), 0, st, (int32_t)total, W, vec, xf, yf);
+    else hipLaunchKernelGGL((k_upsample2<int64_t, float>), grid, dim3(256), 0, st, total, W, vec, xf, yf);
+  }
   return launched("upsample kernel");
 }
 
@@ -1544,21 +1587,23 @@ msl_status msl_nn_rowsum(int32_t M, int32_t N, const float* X, float* out, float
   return launched("rowsum kernels");
 }
 
-msl_status msl_nn_grad_prep(int32_t M, int32_t N, const float* y, const float* dy, uint16_t* dy16, float* bias_grad,
-                            float* parts, void* hip_stream) {
+msl_status msl_nn_grad_prep(int32_t M, int32_t N, const void* y, int32_t y_bf16, const float* dy, uint16_t* dy16,
+                            float* bias_grad, float* parts, void* hip_stream) {
   MSL_TRY(need(M >= 1 && N >= 1 && M <= 65535, "grad prep: need 1 <= M <= 65535 and N >= 1"));
-  MSL_TRY(check_ptr(y, 4, "y", true));
+  MSL_TRY(check_ptr(y, y_bf16 ? 2 : 4, "y", true));
   MSL_TRY(check_ptr(dy, 4, "dy"));
   MSL_TRY(check_ptr(dy16, 2, "dy16"));
   MSL_TRY(check_ptr(bias_grad, 4, "bias_grad"));
   MSL_TRY(check_ptr(parts, 4, "parts"));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const bool vec = N % 4 == 0 && aligned(dy, 16) && aligned(dy16, 8) && (!y || aligned(y, 16));
+  const bool vec = N % 4 == 0 && aligned(dy, 16) && aligned(dy16, 8) && (!y || aligned(y, y_bf16 ? 8 : 16));
   int chunk = (N + kRowParts - 1) / kRowParts;
   if (vec) chunk = (chunk + 3) / 4 * 4;
   const dim3 grid(kRowParts, M);
-  if (vec) hipLaunchKernelGGL(k_grad_prep<true>, grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
-  else hipLaunchKernelGGL(k_grad_prep<false>, grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
+  if (vec && y_bf16) hipLaunchKernelGGL((k_grad_prep<true, true>), grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
+  else if (vec) hipLaunchKernelGGL((k_grad_prep<true, false>), grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
+  else if (y_bf16) hipLaunchKernelGGL((k_grad_prep<false, true>), grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
+  else hipLaunchKernelGGL((k_grad_prep<false, false>), grid, dim3(256), 0, st, N, chunk, y, dy, dy16, parts);
   hipLaunchKernelGGL(k_rowsum_final, dim3(M), dim3(64), 0, st, parts, bias_grad);
   return launched("gradient preparation kernels");
 }

@@ -142,22 +142,28 @@ class UNet:
         c1, c2, c3, c4 = self.c, 2 * self.c, 4 * self.c, 8 * self.c
         d = self.dev
         z = lambda *shape: torch.zeros(shape, dtype=torch.float32, device=d)
+        # ReLU activations are stored as bfloat16 bits: every layer that reads them (convolutions,
+        # their weight gradients) rounds its input to bfloat16 anyway, the ReLU adjoint only needs
+        # their sign, and upsampling and concatenation copy them, so the network computes the same
+        # values with half the activation traffic.  The input, the output layer and all gradients
+        # stay float32.
+        z16 = lambda *shape: torch.zeros(shape, dtype=BF16, device=d)
         hw = [(H, W), (H // 2, W // 2), (H // 4, W // 4), (H // 8, W // 8)]
         b = {"key": key}
         b["x"] = z(2, B, H, W)
         ramp = torch.linspace(-1.0, 1.0, H, device=d)   # channel 1: the row coordinate
         b["x"][1].copy_(ramp.view(1, H, 1).expand(B, H, W))
-        b["e1a"] = z(c1, B, *hw[0])
-        b["cat1"] = z(c2 + c1, B, *hw[0])          # [up(d2); e1]
-        b["e2a"] = z(c2, B, *hw[1])
-        b["cat2"] = z(c3 + c2, B, *hw[1])          # [up(d3); e2]
-        b["e3a"] = z(c3, B, *hw[2])
-        b["cat3"] = z(c4 + c3, B, *hw[2])          # [up(e4); e3]
-        b["e4a"] = z(c4, B, *hw[3])
-        b["e4"] = z(c4, B, *hw[3])
-        b["d3"] = z(c3, B, *hw[2])
-        b["d2"] = z(c2, B, *hw[1])
-        b["d1"] = z(c1, B, *hw[0])
+        b["e1a"] = z16(c1, B, *hw[0])
+        b["cat1"] = z16(c2 + c1, B, *hw[0])          # [up(d2); e1]
+        b["e2a"] = z16(c2, B, *hw[1])
+        b["cat2"] = z16(c3 + c2, B, *hw[1])          # [up(d3); e2]
+        b["e3a"] = z16(c3, B, *hw[2])
+        b["cat3"] = z16(c4 + c3, B, *hw[2])          # [up(e4); e3]
+        b["e4a"] = z16(c4, B, *hw[3])
+        b["e4"] = z16(c4, B, *hw[3])
+        b["d3"] = z16(c3, B, *hw[2])
+        b["d2"] = z16(c2, B, *hw[1])
+        b["d1"] = z16(c1, B, *hw[0])
         b["out"] = z(1, B, H, W)
         b["pred"] = z(B, H // self.f, W)
         nmax = B * H * W
@@ -173,7 +179,7 @@ class UNet:
         b["parts"] = torch.zeros(need, dtype=torch.float32, device=d)
         # gradient buffers with the activations' shapes
         for k in ("e1a", "cat1", "e2a", "cat2", "e3a", "cat3", "e4a", "e4", "d3", "d2", "d1", "out"):
-            b["d_" + k] = torch.zeros_like(b[k])
+            b["d_" + k] = torch.zeros(b[k].shape, dtype=torch.float32, device=d)
         b["d_pred"] = torch.zeros_like(b["pred"])
         b["loss"] = torch.zeros((), dtype=torch.float64, device=d)
         # global head

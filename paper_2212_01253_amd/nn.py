@@ -37,7 +37,7 @@ def lib():
             "msl_nn_gemm_bf16_splitk": [I, I, I, P, I, I, P, I, I, P, I, I, P, P],
             "msl_nn_im2col3x3": [I, I, I, I, I, P, P, P],
             "msl_nn_col2im3x3": [I, I, I, I, I, P, P, P],
-            "msl_nn_upsample2": [I, I, I, I, P, P, P],
+            "msl_nn_upsample2": [I, I, I, I, P, P, I, P],
             "msl_nn_upsample2_adjoint": [I, I, I, I, P, P, P],
             "msl_nn_rowpool": [I, I, I, I, P, P, P],
             "msl_nn_rowpool_adjoint": [I, I, I, I, P, P, P],
@@ -53,10 +53,10 @@ def lib():
             "msl_nn_row_features": [I, I, I, P, P, P, P, P],
             "msl_nn_add_row_bias": [I, I, I, P, P, P],
             "msl_nn_row_bias_adjoint": [I, I, I, P, P, P],
-            "msl_nn_conv3x3": [I, I, I, I, I, I, P, P, P, I, P, P, P],
+            "msl_nn_conv3x3": [I, I, I, I, I, I, P, P, I, P, I, P, I, P, P],
             "msl_nn_conv3x3_adjoint": [I, I, I, I, I, I, P, P, P, I, P, P],
-            "msl_nn_conv3x3_weight_grad": [I, I, I, I, I, I, P, P, P, I, P, P],
-            "msl_nn_grad_prep": [I, I, P, P, P, P, P, P],
+            "msl_nn_conv3x3_weight_grad": [I, I, I, I, I, I, P, P, I, P, I, P, P],
+            "msl_nn_grad_prep": [I, I, P, I, P, P, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -89,6 +89,15 @@ def _s():
 BF16 = torch.int16   # storage dtype of bfloat16 bit patterns
 
 
+def _act(t):
+    """(pointer, 1 if bfloat16 bits) of an activation held as float32 or as bfloat16 bits."""
+    if t is None:
+        return None, 0
+    if t.dtype == BF16:
+        return _p(t, BF16), 1
+    return _p(t, torch.float32), 0
+
+
 def gemm(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, beta=0.0, bias=None, relu=False, C16=None):
     _ck(lib().msl_nn_gemm_bf16(M, N, K, _p(A, BF16), lda, int(transA), _p(B, BF16), ldb, int(transB),
                                _p(C, torch.float32), ldc, float(beta), _p(bias, torch.float32), int(relu),
@@ -115,9 +124,12 @@ def conv_scratch(Co, C, device):
 
 
 def conv3x3(Co, C, B, H, W, stride, w16, x, y, bias=None, relu=False, scratch=None):
+    """msl_nn_conv3x3; x and y each float32 or bfloat16 bits (BF16 storage)."""
     ws = scratch if scratch is not None else conv_scratch(Co, C, x.device)
-    _ck(lib().msl_nn_conv3x3(Co, C, B, H, W, stride, _p(w16, BF16), _p(x, torch.float32), _p(bias, torch.float32),
-                             int(relu), _p(y, torch.float32), _p(ws, BF16), _s()))
+    xp, xb = _act(x)
+    yp, yb = _act(y)
+    _ck(lib().msl_nn_conv3x3(Co, C, B, H, W, stride, _p(w16, BF16), xp, xb, _p(bias, torch.float32),
+                             int(relu), yp, yb, _p(ws, BF16), _s()))
 
 
 def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx, scratch=None, accumulate=False):
@@ -127,13 +139,17 @@ def conv3x3_adjoint(Co, C, B, H, W, stride, w16, dy16, dx, scratch=None, accumul
 
 
 def grad_prep(M, N, y, dy, dy16, bias_grad, parts):
-    """msl_nn_grad_prep: dy16 = bf16(dy masked by y > 0, or unmasked when y is None), bias_grad = row sums."""
-    _ck(lib().msl_nn_grad_prep(M, N, _p(y, torch.float32), _p(dy, torch.float32), _p(dy16, BF16),
+    """msl_nn_grad_prep: dy16 = bf16(dy masked by y > 0, or unmasked when y is None), bias_grad = row sums;
+    y float32 or bfloat16 bits."""
+    yp, yb = _act(y)
+    _ck(lib().msl_nn_grad_prep(M, N, yp, yb, _p(dy, torch.float32), _p(dy16, BF16),
                                _p(bias_grad, torch.float32), _p(parts, torch.float32), _s()))
 
 
 def conv3x3_weight_grad(Co, C, B, H, W, stride, dy16, x, dw, splits, partials):
-    _ck(lib().msl_nn_conv3x3_weight_grad(Co, C, B, H, W, stride, _p(dy16, BF16), _p(x, torch.float32),
+    """msl_nn_conv3x3_weight_grad; x float32 or bfloat16 bits."""
+    xp, xb = _act(x)
+    _ck(lib().msl_nn_conv3x3_weight_grad(Co, C, B, H, W, stride, _p(dy16, BF16), xp, xb,
                                          _p(dw, torch.float32), int(splits), _p(partials, torch.float32), _s()))
 
 
@@ -146,7 +162,12 @@ def col2im(C, B, H, W, stride, col, dx):
 
 
 def upsample2(C, B, H, W, x, y):
-    _ck(lib().msl_nn_upsample2(C, B, H, W, _p(x, torch.float32), _p(y, torch.float32), _s()))
+    """msl_nn_upsample2; x and y both float32 or both bfloat16 bits."""
+    xp, xb = _act(x)
+    yp, yb = _act(y)
+    if xb != yb:
+        raise ValueError("upsample2: x and y must have the same dtype")
+    _ck(lib().msl_nn_upsample2(C, B, H, W, xp, yp, xb, _s()))
 
 
 def upsample2_adjoint(C, B, H, W, dy, dx):

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert msl.abi_version() == 5
+    assert msl.abi_version() == 6
 
 
 def G(**kw):
@@ -214,19 +214,32 @@ def test_nn_entry_points_validate(L):
     assert N.msl_nn_add_row_bias(0, 4, 8, FAKE, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_row_bias_adjoint(2, 0, 8, FAKE, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_row_bias_adjoint(2, 4, 8, None, FAKE, None) == msl.ERR_ARG
-    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 3, FAKE, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG      # stride 3
-    assert N.msl_nn_conv3x3(4, 3, 2, 9, 8, 2, FAKE, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG      # odd H
-    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE + 1, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG  # misaligned
-    assert N.msl_nn_conv3x3(0, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, FAKE, None) == msl.ERR_ARG
-    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, None, None) == msl.ERR_ARG      # no scratch
-    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, None, 0, FAKE, FAKE + 8, None) == msl.ERR_ARG  # misaligned
+    # conv3x3(Co, C, B, H, W, stride, w16, x, x_bf16, bias, relu, y, y_bf16, wscratch, stream)
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 3, FAKE, FAKE, 0, None, 0, FAKE, 0, FAKE, None) == msl.ERR_ARG      # stride 3
+    assert N.msl_nn_conv3x3(4, 3, 2, 9, 8, 2, FAKE, FAKE, 0, None, 0, FAKE, 0, FAKE, None) == msl.ERR_ARG      # odd H
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE + 1, FAKE, 0, None, 0, FAKE, 0, FAKE, None) == msl.ERR_ARG  # misaligned
+    assert N.msl_nn_conv3x3(0, 3, 2, 8, 8, 1, FAKE, FAKE, 0, None, 0, FAKE, 0, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, 0, None, 0, FAKE, 0, None, None) == msl.ERR_ARG      # no scratch
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, 0, None, 0, FAKE, 0, FAKE + 8, None) == msl.ERR_ARG  # misaligned
+    # float32 x or y must be 4-byte aligned (bfloat16 bits 2-byte)
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE + 2, 0, None, 0, FAKE, 0, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE, 0, None, 0, FAKE + 2, 0, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3(4, 3, 2, 8, 8, 1, FAKE, FAKE + 1, 1, None, 0, FAKE, 0, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, None, FAKE, 0, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_conv3x3_adjoint(4, 0, 2, 8, 8, 1, FAKE, FAKE, FAKE, 0, FAKE, None) == msl.ERR_ARG
     assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 0, None, None) == msl.ERR_ARG   # no scratch
     assert N.msl_nn_conv3x3_adjoint(4, 3, 2, 8, 8, 2, FAKE, FAKE, FAKE + 4, 1, FAKE, None) == msl.ERR_ARG  # accumulate, dx misaligned
     assert N.msl_nn_conv3x3_scratch_elems(20, 3) == 16 * 32 * 16 and N.msl_nn_conv3x3_scratch_elems(0, 3) == 0
-    assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 0, FAKE, None) == msl.ERR_ARG   # splits
-    assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, FAKE, 2, None, None) == msl.ERR_ARG
+    # weight_grad(Co, C, B, H, W, stride, dy16, x, x_bf16, dw, splits, partials, stream)
+    assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, 0, FAKE, 0, FAKE, None) == msl.ERR_ARG   # splits
+    assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE, 0, FAKE, 2, None, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE + 2, 0, FAKE, 2, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_conv3x3_weight_grad(4, 3, 2, 8, 8, 1, FAKE, FAKE + 1, 1, FAKE, 2, FAKE, None) == msl.ERR_ARG
+    # grad_prep(M, N, y, y_bf16, dy, dy16, bias_grad, parts, stream); upsample2(C, B, H, W, x, y, bf16, stream)
+    assert N.msl_nn_grad_prep(4, 8, FAKE + 2, 0, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_grad_prep(4, 8, FAKE + 1, 1, FAKE, FAKE, FAKE, FAKE, None) == msl.ERR_ARG
+    assert N.msl_nn_upsample2(2, 1, 4, 4, FAKE + 2, FAKE, 0, None) == msl.ERR_ARG
+    assert N.msl_nn_upsample2(2, 1, 4, 4, FAKE, FAKE + 1, 1, None) == msl.ERR_ARG
 
 
 def test_rotation_validates(L):

@@ -134,6 +134,23 @@ def test_implicit_convolution(T, C, B, H, W, O, s):
     assert rel(dx.cpu().numpy(), rdx) <= 1e-6
     assert np.array_equal(dx2.cpu().numpy(), 2 * dx.cpu().numpy())
     assert rel(dw.cpu().numpy(), rdw.reshape(O, C * 9)) <= 1e-6
+    # bfloat16 activations: the same values as bfloat16 bits stage the same operands, so the
+    # convolution and its weight gradient equal the float32-input results bit for bit, and a
+    # bfloat16 output is the float32 output rounded to nearest even
+    x16 = dev(bf16_bits(N.bf16(x)))
+    yb = torch.zeros((O, B, Ho, Wo), dtype=torch.float32, device="cuda")
+    T.conv3x3(O, C, B, H, W, s, w16, x16, yb, bias=dev(bias), relu=True)
+    y16 = torch.zeros((O, B, Ho, Wo), dtype=torch.int16, device="cuda")
+    T.conv3x3(O, C, B, H, W, s, w16, x16, y16, bias=dev(bias), relu=True)
+    ry16 = torch.zeros(O * n, dtype=torch.int16, device="cuda")
+    T.to_bf16(y, ry16)
+    torch.cuda.synchronize()
+    assert np.array_equal(yb.cpu().numpy(), y.cpu().numpy())
+    assert np.array_equal(y16.cpu().numpy().ravel(), ry16.cpu().numpy())
+    dwb = torch.full((O, C * 9), float("nan"), dtype=torch.float32, device="cuda")
+    T.conv3x3_weight_grad(O, C, B, H, W, s, dy16, x16, dwb, splits, parts)   # both paths (Wo % 8)
+    torch.cuda.synchronize()
+    assert np.array_equal(dwb.cpu().numpy(), dw.cpu().numpy())
 
 
 def test_resampling_and_elementwise_kernels(T):
@@ -164,6 +181,13 @@ def test_resampling_and_elementwise_kernels(T):
     T.mse(dev(pr), dev(tg), gr, loss)
     torch.cuda.synchronize()
     assert np.array_equal(y.cpu().numpy(), N.upsample2(x).astype(np.float32))
+    # bfloat16 bits are copied unchanged (aligned pair stores, and the scalar path for an odd offset)
+    xb = N.bf16(x).astype(np.float32)
+    for off in (0, 1):
+        y16 = torch.zeros(3 * 2 * 8 * 12 + off, dtype=torch.int16, device="cuda")
+        T.upsample2(3, 2, 4, 6, dev(bf16_bits(xb)), y16[off:])
+        torch.cuda.synchronize()
+        assert np.array_equal(y16[off:].cpu().numpy(), bf16_bits(N.upsample2(xb)).ravel())
     assert np.allclose(dx.cpu().numpy(), N.upsample2_adjoint(dy), rtol=1e-6, atol=1e-6)
     assert np.allclose(q.cpu().numpy(), N.rowpool(p, 4), rtol=1e-6, atol=1e-6)
     assert np.allclose(dp.cpu().numpy(), N.rowpool_adjoint(dq, 4), rtol=1e-6, atol=0)
@@ -198,6 +222,19 @@ def test_gradient_preparation_in_one_pass(T, M, N):
         assert np.array_equal(dyd.cpu().numpy(), dy)
         assert np.array_equal(d16.cpu().numpy(), ref16.cpu().numpy())
         assert np.allclose(gb.cpu().numpy(), g.astype(np.float64).sum(axis=1), rtol=1e-5, atol=1e-4)
+    # y as bfloat16 bits masks like the float32 values they hold: bit for bit the same outputs
+    from oracle import nn_oracle as nno          # (N is the column count here)
+    yb = nno.bf16(y).astype(np.float32)
+    yb[0, :5] = 0.0                               # exact zeros and a negative zero mask too
+    yb[0, 5] = -0.0
+    outs = []
+    for yt in (dev(yb), dev(bf16_bits(yb))):
+        d16 = torch.zeros(M * N, dtype=torch.int16, device="cuda")
+        gb = torch.zeros(M, dtype=torch.float32, device="cuda")
+        T.grad_prep(M, N, yt, dev(dy), d16, gb, parts)
+        torch.cuda.synchronize()
+        outs.append((d16.cpu().numpy(), gb.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
 def test_global_head_kernels(T):
