@@ -651,6 +651,10 @@ PhaseSpec blank_phase(const Call& k, int kind) {
 struct BatchRec {
   Ctx c;
   float2* field;
+  // byte offsets in the batch workspace of the instance's tables, slice pack and working field:
+  // the kernel forms those pointers from the workspace base it receives as an argument, so the
+  // compiler addresses them as global memory (pointers read from the records are generic)
+  uint64_t off_twz, off_twy, off_hz, off_hy, off_pack, off_field;
 };
 
 constexpr int kRecChunk = 16;  // records per descriptor-store launch (kernel arguments < 4 KB)
@@ -670,51 +674,60 @@ __global__ void k_store_recs(RecChunk chunk, BatchRec* dst) {
 // group b mod groups_per_inst of instance b / groups_per_inst (after the
 // XCD-aware renumbering of the whole grid).
 template <int N, int P, int AXIS>
-__global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__ recs, int groups_per_inst,
-                                                    PassDesc tmpl) {
+__global__ void __launch_bounds__(256) k_pass_batch(const BatchRec* __restrict__ recs, char* __restrict__ wsb,
+                                                    int groups_per_inst, PassDesc tmpl) {
   extern __shared__ float2 lds[];  // line_pass_lds_bytes(N, G)
   constexpr int L = N / P;
   const int G = blockDim.x / L;
   const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int gb = msl::xcd_group(blockIdx.x, gridDim.x);
   const int inst = gb / groups_per_inst;
-  const Ctx c = recs[inst].c;
+  const BatchRec& r = recs[inst];
+  Ctx c = r.c;
+  c.twz = reinterpret_cast<const float2*>(wsb + r.off_twz);
+  c.twy = reinterpret_cast<const float2*>(wsb + r.off_twy);
+  c.hz = reinterpret_cast<const float2*>(wsb + r.off_hz);
+  c.hy = reinterpret_cast<const float2*>(wsb + r.off_hy);
+  c.dbT = reinterpret_cast<const float2*>(wsb + r.off_pack);
+  float2* const field = reinterpret_cast<float2*>(wsb + r.off_field);
   PassDesc pd = tmpl;
-  pd.src = recs[inst].field;
-  pd.dst = recs[inst].field;
+  pd.src = field;
+  pd.dst = field;
   msl::run_line<N, AXIS, false, msl::KIND_FWD_MID, msl::TS_PACK, P>(c, pd, (gb % groups_per_inst) * G + g, j,
                                                                    line_buffers<N>(lds, g, G));
 }
 
 template <int N, int P, int AXIS>
-hipError_t launch_pass_batch_tp(const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl, hipStream_t st) {
+hipError_t launch_pass_batch_tp(const BatchRec* recs, char* wsb, int n_inst, int nlines, const PassDesc& tmpl,
+                                hipStream_t st) {
   constexpr int L = N / P;
   const int G = lines_per_group(N, nlines);
   const int gpi = nlines / G;
   hipLaunchKernelGGL((k_pass_batch<N, P, AXIS>), dim3(n_inst * gpi), dim3(L * G), (unsigned)line_pass_lds_bytes(N, G),
-                     st, recs, gpi, tmpl);
+                     st, recs, wsb, gpi, tmpl);
   return hipGetLastError();
 }
 
 template <int N, int AXIS>
-hipError_t launch_pass_batch_t(const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl, hipStream_t st) {
+hipError_t launch_pass_batch_t(const BatchRec* recs, char* wsb, int n_inst, int nlines, const PassDesc& tmpl,
+                               hipStream_t st) {
   if constexpr (N >= 64) {
-    if (points_per_lane(N) == 8) return launch_pass_batch_tp<N, 8, AXIS>(recs, n_inst, nlines, tmpl, st);
+    if (points_per_lane(N) == 8) return launch_pass_batch_tp<N, 8, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
   }
-  return launch_pass_batch_tp<N, 4, AXIS>(recs, n_inst, nlines, tmpl, st);
+  return launch_pass_batch_tp<N, 4, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
 }
 
 template <int AXIS>
-hipError_t launch_pass_batch_axis(int n, const BatchRec* recs, int n_inst, int nlines, const PassDesc& tmpl,
+hipError_t launch_pass_batch_axis(int n, const BatchRec* recs, char* wsb, int n_inst, int nlines, const PassDesc& tmpl,
                                   hipStream_t st) {
   switch (n) {
-    case 16: return launch_pass_batch_t<16, AXIS>(recs, n_inst, nlines, tmpl, st);
-    case 32: return launch_pass_batch_t<32, AXIS>(recs, n_inst, nlines, tmpl, st);
-    case 64: return launch_pass_batch_t<64, AXIS>(recs, n_inst, nlines, tmpl, st);
-    case 128: return launch_pass_batch_t<128, AXIS>(recs, n_inst, nlines, tmpl, st);
-    case 256: return launch_pass_batch_t<256, AXIS>(recs, n_inst, nlines, tmpl, st);
-    case 512: return launch_pass_batch_t<512, AXIS>(recs, n_inst, nlines, tmpl, st);
-    case 1024: return launch_pass_batch_t<1024, AXIS>(recs, n_inst, nlines, tmpl, st);
+    case 16: return launch_pass_batch_t<16, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
+    case 32: return launch_pass_batch_t<32, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
+    case 64: return launch_pass_batch_t<64, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
+    case 128: return launch_pass_batch_t<128, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
+    case 256: return launch_pass_batch_t<256, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
+    case 512: return launch_pass_batch_t<512, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
+    case 1024: return launch_pass_batch_t<1024, AXIS>(recs, wsb, n_inst, nlines, tmpl, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1389,6 +1402,12 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
     c.dbT = pack;
     recs[r].c = c;
     recs[r].field = P(b.tmp);  // tiled working field
+    recs[r].off_twz = b.twz;
+    recs[r].off_twy = b.twy;
+    recs[r].off_hz = b.hz;
+    recs[r].off_hy = b.hy;
+    recs[r].off_pack = b.pack;
+    recs[r].off_field = b.tmp;
     PhaseSpec& ph = phs[r];
     ph = PhaseSpec{};
     ph.kind = msl::PH_FWD_FULL;
@@ -1437,8 +1456,8 @@ msl_status msl_forward_batch(const msl_instance* inst, int32_t n, void* workspac
       if (active > 0) {
         const PassDesc tmpl = msl::phase_pass(phs[g0], p);
         const hipError_t e = tmpl.axis == msl::ROW
-                                 ? launch_pass_batch_axis<msl::ROW>(nz, drecs + g0, active, ny, tmpl, gs)
-                                 : launch_pass_batch_axis<msl::COL>(ny, drecs + g0, active, nz, tmpl, gs);
+                                 ? launch_pass_batch_axis<msl::ROW>(nz, drecs + g0, ws, active, ny, tmpl, gs)
+                                 : launch_pass_batch_axis<msl::COL>(ny, drecs + g0, ws, active, nz, tmpl, gs);
         MSL_TRY(hip_check(e, "batched pass kernel"));
       }
       // instances whose slice loop ended at p: their last propagation
