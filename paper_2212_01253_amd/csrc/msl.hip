@@ -398,13 +398,19 @@ int max_lines_per_group(int n, int p) {
   return G;
 }
 
-// Default: one 64-lane wavefront's worth of lanes, and at least two lines
-// (the two lines of a row or column of tiles).
-int lines_per_group(int n, int nlines) {
+// Default: lines shorter than a wavefront fill one 64-lane wavefront; longer
+// lines go two to a workgroup (the two lines of a row or column of tiles)
+// when the launch has at least two lines per compute unit, else one, so that
+// a launch of few lines still spreads over every compute unit (a 256-line
+// pass: 256 one-line workgroups, measured faster than 128 two-line ones; at
+// 512 lines two per workgroup are faster).  launch_lines: the lines of every
+// instance the launch covers.
+constexpr int kComputeUnits = 256;
+int lines_per_group(int n, int nlines, int64_t launch_lines) {
   const int p = points_per_lane(n);
   const int L = n / p;
   int G = g_lines_per_group[__builtin_ctz((unsigned)n)];
-  if (G <= 0) G = L >= 32 ? 2 : 64 / L;
+  if (G <= 0) G = L >= 64 ? (launch_lines >= 2 * kComputeUnits ? 2 : 1) : (L >= 32 ? 2 : 64 / L);
   G = std::min(G, max_lines_per_group(n, p));
   return std::min(G, nlines);
 }
@@ -413,7 +419,7 @@ template <int N, int P, int AXIS>
 hipError_t launch_pass_tp(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const int nlines = AXIS == msl::ROW ? c.ny : c.nz;
   constexpr int L = N / P;
-  const int G = lines_per_group(N, nlines);
+  const int G = lines_per_group(N, nlines, nlines);
   const dim3 grid(nlines / G), block(L * G);
   int kind = msl::pass_kind(pd);
   if (!c.dbT) kind = msl::KIND_GENERIC;  // the specialised kinds read the slice pack
@@ -701,7 +707,7 @@ template <int N, int P, int AXIS>
 hipError_t launch_pass_batch_tp(const BatchRec* recs, char* wsb, int n_inst, int nlines, const PassDesc& tmpl,
                                 hipStream_t st) {
   constexpr int L = N / P;
-  const int G = lines_per_group(N, nlines);
+  const int G = lines_per_group(N, nlines, (int64_t)nlines * n_inst);
   const int gpi = nlines / G;
   hipLaunchKernelGGL((k_pass_batch<N, P, AXIS>), dim3(n_inst * gpi), dim3(L * G), (unsigned)line_pass_lds_bytes(N, G),
                      st, recs, wsb, gpi, tmpl);
@@ -835,13 +841,10 @@ msl_status autotune_shapes(Run run, hipStream_t st, int reps, const int* slots, 
     for (int q = 0; q < nslots; ++q) {
       const int e = slots[q], n = 1 << e;
       const int keep_v = g_lines_per_group[e], keep_p = g_points_per_lane[e];
-      // the shape in effect, timed already
-      const int cur_v = lines_per_group(n, 1 << 30), cur_p = points_per_lane(n);
       int best_v = keep_v, best_p = keep_p;
       for (int p : {4, 8}) {
         if (p == 8 && n < 64) continue;
         for (int v = 1; v <= max_lines_per_group(n, p); v *= 2) {
-          if (v == cur_v && p == cur_p) continue;
           g_points_per_lane[e] = p;
           g_lines_per_group[e] = v;
           float t = 0.0f;
