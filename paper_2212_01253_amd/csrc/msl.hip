@@ -372,9 +372,17 @@ __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   constexpr int L = N / P;
   constexpr int TS = KIND == msl::KIND_GENERIC ? msl::TS_RUNTIME : msl::TS_PACK;
   const int G = blockDim.x / L;
-  const int g = threadIdx.x % G, j = threadIdx.x / G;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
-  msl::run_line<N, AXIS, false, KIND, TS, P>(c, pd, group * G + g, j, line_buffers<N>(lds, g, G));
+  if constexpr (L == 64 && N < 512 && KIND != msl::KIND_GENERIC) {
+    // lines of one wavefront (256 points at 4 per lane): each wavefront takes a
+    // whole line and orders its stage exchanges itself (measured faster on the
+    // 256-point passes; at 512 points the interleaved mapping below is faster)
+    const int g = threadIdx.x / L, j = threadIdx.x % L;
+    msl::run_line<N, AXIS, false, KIND, TS, P, true>(c, pd, group * G + g, j, line_buffers<N>(lds, g, G));
+  } else {
+    const int g = threadIdx.x % G, j = threadIdx.x / G;
+    msl::run_line<N, AXIS, false, KIND, TS, P>(c, pd, group * G + g, j, line_buffers<N>(lds, g, G));
+  }
 }
 
 // Points per lane of the per-pass and batch line kernels for n-point lines:

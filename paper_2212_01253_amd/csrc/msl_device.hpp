@@ -274,12 +274,25 @@ struct LineLds {
 // writer of exchange e has passed that barrier.  Successive calls keep the
 // alternation when the exchange count NST is even; for an odd count every
 // call starts on buffer a after a barrier of its own.
-template <int N, bool INV, int P = LinePts<N>::P>
+// Exchange ordering: a workgroup barrier, or (WAVE: every line held by one
+// wavefront) ordering within the wavefront, whose LDS accesses run in order.
+template <bool WAVE>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int N, bool INV, int P = LinePts<N>::P, bool WAVE = false>
 __device__ __forceinline__ void fft_line(float2 (&v)[P], const LineLds& sh, int j, const LineTw<N, P>& tw) {
   constexpr int L = N / P;
   constexpr int R0 = LineTw<N, P>::R0;
   constexpr int NX = LineTw<N, P>::NST;  // exchanges: after stage 0 and after every radix-P stage but the last
-  if constexpr (NX % 2 == 1) __syncthreads();
+  if constexpr (NX % 2 == 1) line_sync<WAVE>();
   // ---- stage 0: radix R0, sub-length 1, trivial twiddles; writes exchange 0 (buffer a)
   float2* const w0 = sh.a;
   if constexpr (R0 == P) {
@@ -306,7 +319,7 @@ __device__ __forceinline__ void fft_line(float2 (&v)[P], const LineLds& sh, int 
       }
     }
   }
-  __syncthreads();
+  line_sync<WAVE>();
   // ---- radix-P stages with sub-length NS = R0, P R0, ...; stage s reads exchange s
 #pragma unroll
   for (int s = 0, NS = R0; s < NX; ++s, NS *= P) {
@@ -321,7 +334,7 @@ __device__ __forceinline__ void fft_line(float2 (&v)[P], const LineLds& sh, int 
       const int base = (j / NS) * NS * P + (j % NS);
 #pragma unroll
       for (int r = 0; r < P; ++r) wr[lds_pad(base + r * NS)] = v[r];
-      __syncthreads();
+      line_sync<WAVE>();
     }
   }
 }
@@ -587,16 +600,17 @@ __device__ __forceinline__ void load_field(const Ctx& c, const PassDesc& pd, int
 
 // FFT, propagator, inverse FFT along the line: the one-axis paraxial factor
 // (single-term), or with TWO_TERM the exact 2-D factor (hi + lo).
-template <int N, bool TWO_TERM, int P = LinePts<N>::P>
+template <int N, bool TWO_TERM, int P = LinePts<N>::P, bool WAVE = false>
 __device__ __forceinline__ void prop_line(float2 (&v)[P], const LineLds& sh, int j, const LineIn<N, P>& in, bool conj) {
-  fft_line<N, false, P>(v, sh, j, in.tw);
+  fft_line<N, false, P, WAVE>(v, sh, j, in.tw);
 #pragma unroll
   for (int t = 0; t < P; ++t)
     v[t] = TWO_TERM ? cmul_comp_dyn(v[t], in.hh[t], in.hl[t], conj) : cmul_dyn(v[t], in.hh[t], conj);
-  fft_line<N, true, P>(v, sh, j, in.tw);
+  fft_line<N, true, P, WAVE>(v, sh, j, in.tw);
 }
 
-template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P>
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P,
+          bool WAVE = false>
 __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, int line, int j, const LineLds& sh,
                                              LineIn<N, P>& in) {
   constexpr int L = N / P;
@@ -613,7 +627,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   switch (pd.pre) {
-    case PRE_PROP: prop_line<N, false, P>(v, sh, j, in, pd.conj != 0); break;
+    case PRE_PROP: prop_line<N, false, P, WAVE>(v, sh, j, in, pd.conj != 0); break;
     case PRE_FFT: fft_line<N, false, P>(v, sh, j, in.tw); break;
     case PRE_IFFT_N:
       fft_line<N, true, P>(v, sh, j, in.tw);
@@ -685,7 +699,7 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 
   switch (pd.post) {
-    case POST_PROP: prop_line<N, false, P>(v, sh, j, in, pd.conj != 0); break;
+    case POST_PROP: prop_line<N, false, P, WAVE>(v, sh, j, in, pd.conj != 0); break;
     case POST_FFT: fft_line<N, false, P>(v, sh, j, in.tw); break;
     case POST_PROP2D: prop_line<N, true, P>(v, sh, j, in, pd.conj != 0); break;  // H[ky][kz] / ny in hh, hl
     default: break;
@@ -698,12 +712,15 @@ __device__ __forceinline__ void compute_line(const Ctx& c, const PassDesc& pd_, 
   }
 }
 
-template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P>
+// WAVE: each line is held by one wavefront (the caller maps lanes so), and the
+// stage exchanges are ordered inside it instead of by workgroup barriers.
+template <int N, int AXIS, bool COH = false, int KIND = KIND_GENERIC, int TS = TS_RUNTIME, int P = LinePts<N>::P,
+          bool WAVE = false>
 __device__ __forceinline__ void run_line(const Ctx& c, const PassDesc& pd, int line, int j, const LineLds& sh) {
   LineIn<N, P> in;
   load_field<N, AXIS, COH, KIND, P>(c, pd, line, j, in);
   load_static<N, AXIS, KIND, TS, P>(c, pd, line, j, in);
-  compute_line<N, AXIS, COH, KIND, TS, P>(c, pd, line, j, sh, in);
+  compute_line<N, AXIS, COH, KIND, TS, P, WAVE>(c, pd, line, j, sh, in);
 }
 
 // Either axis, chosen per pass at run time (square grids: both line lengths are N).
