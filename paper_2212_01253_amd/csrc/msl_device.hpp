@@ -233,20 +233,39 @@ template <int N, int P = LinePts<N>::P>
 struct LineTw {
   static constexpr int LG = ilog2c(N), LP = ilog2c(P);
   static constexpr int R0LOG = (LG % LP == 0) ? LP : (LG % LP);
-  static constexpr int R0 = 1 << R0LOG;     // first stage radix (no twiddles)
+  static constexpr int R0 = 1 << R0LOG;     // the one stage radix other than P (R0 = P: none)
   static constexpr int NST = (LG - R0LOG) / LP;
-  float2 w[NST][P - 1];
+  // R0 = P: a radix-P stage without twiddles, then NST twiddled radix-P stages.
+  // R0 < P: a radix-P stage without twiddles, NST - 1 twiddled radix-P stages,
+  // and the radix-R0 stage last, where each lane's P / R0 butterflies take
+  // R0 - 1 twiddles each (P - P / R0 per lane instead of the P - 1 of a
+  // twiddled radix-P stage).
+  static constexpr bool R0LAST = R0 < P;
+  static constexpr int Q = P / R0;
+  static constexpr int NPW = R0LAST ? NST - 1 : NST;  // twiddled radix-P stages
+  float2 w[NPW > 0 ? NPW : 1][P - 1];
+  float2 wl[R0LAST ? Q : 1][R0LAST ? R0 - 1 : 1];
   float rs2;
 };
 
 template <int N, int P = LinePts<N>::P>
 __device__ __forceinline__ void load_tw(LineTw<N, P>& tw, const float2* __restrict__ tab_row, int j, int tab) {
+  using T = LineTw<N, P>;
+  // twiddled radix-P stages: sub-length NS = R0 P^s (R0 = P), or P^(s+1) (radix R0 last)
 #pragma unroll
-  for (int s = 0, NS = LineTw<N, P>::R0; s < LineTw<N, P>::NST; ++s, NS *= P) {
+  for (int s = 0, NS = T::R0LAST ? P : T::R0; s < T::NPW; ++s, NS *= P) {
     const int jm = j % NS;
     const int step = N / (P * NS);
 #pragma unroll
     for (int r = 1; r < P; ++r) tw.w[s][r - 1] = tab_row[jm * r * step];
+  }
+  if constexpr (T::R0LAST) {
+    // last stage, sub-length N / R0: butterfly i = j + L q takes W_N^(i r)
+    constexpr int L = N / P;
+#pragma unroll
+    for (int q = 0; q < T::Q; ++q)
+#pragma unroll
+      for (int r = 1; r < T::R0; ++r) tw.wl[q][r - 1] = tab_row[(j + L * q) * r];
   }
   tw.rs2 = rs2_at(tab);
 }
@@ -291,9 +310,55 @@ template <int N, bool INV, int P = LinePts<N>::P, bool WAVE = false>
 __device__ __forceinline__ void fft_line(float2 (&v)[P], const LineLds& sh, int j, const LineTw<N, P>& tw) {
   constexpr int L = N / P;
   constexpr int R0 = LineTw<N, P>::R0;
-  constexpr int NX = LineTw<N, P>::NST;  // exchanges: after stage 0 and after every radix-P stage but the last
+  constexpr int NX = LineTw<N, P>::NST;  // exchanges: after every stage but the last
   if constexpr (NX % 2 == 1) line_sync<WAVE>();
-  // ---- stage 0: radix R0, sub-length 1, trivial twiddles; writes exchange 0 (buffer a)
+  if constexpr (LineTw<N, P>::R0LAST) {
+    // ---- radix R0 last: stage 0 radix P, sub-length 1, no twiddles; writes exchange 0 (buffer a)
+    constexpr int NPW = LineTw<N, P>::NPW, Q = LineTw<N, P>::Q;
+    dft_p<P, INV>(v, tw.rs2);
+#pragma unroll
+    for (int r = 0; r < P; ++r) sh.a[lds_pad(P * j + r)] = v[r];
+    line_sync<WAVE>();
+    // ---- twiddled radix-P stages, sub-length NS = P, P^2, ...; stage s reads exchange s, writes s + 1
+#pragma unroll
+    for (int s = 0, NS = P; s < NPW; ++s, NS *= P) {
+      const float2* const rd = (s & 1) ? sh.b : sh.a;
+#pragma unroll
+      for (int t = 0; t < P; ++t) v[t] = rd[lds_pad(j + t * L)];
+#pragma unroll
+      for (int r = 1; r < P; ++r) v[r] = cmul<INV>(v[r], tw.w[s][r - 1]);
+      dft_p<P, INV>(v, tw.rs2);
+      float2* const wr = (s & 1) ? sh.a : sh.b;
+      const int base = (j / NS) * NS * P + (j % NS);
+#pragma unroll
+      for (int r = 0; r < P; ++r) wr[lds_pad(base + r * NS)] = v[r];
+      line_sync<WAVE>();
+    }
+    // ---- radix-R0 stage, sub-length N / R0: butterfly q of the lane is element j + L q and
+    // its partners at + r N / R0, i.e. v[q + Q r]; outputs land in the same slots (natural order)
+    {
+      const float2* const rd = (NPW & 1) ? sh.b : sh.a;
+#pragma unroll
+      for (int t = 0; t < P; ++t) v[t] = rd[lds_pad(j + t * L)];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+#pragma unroll
+        for (int r = 1; r < R0; ++r) v[q + Q * r] = cmul<INV>(v[q + Q * r], tw.wl[q][r - 1]);
+        if constexpr (R0 == 4) {
+          float2 y0, y1, y2, y3;
+          dft4<INV>(v[q], v[q + Q], v[q + 2 * Q], v[q + 3 * Q], y0, y1, y2, y3);
+          v[q] = y0;
+          v[q + Q] = y1;
+          v[q + 2 * Q] = y2;
+          v[q + 3 * Q] = y3;
+        } else {
+          dft2<INV>(v[q], v[q + Q]);
+        }
+      }
+    }
+    return;
+  }
+  // ---- stage 0: radix R0 = P, sub-length 1, trivial twiddles; writes exchange 0 (buffer a)
   float2* const w0 = sh.a;
   if constexpr (R0 == P) {
     dft_p<P, INV>(v, tw.rs2);
