@@ -366,17 +366,21 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partials, in
 // wavefront covers whole 2x2 tiles of the tiled working fields.
 // The specialised middle passes take the transmission from the slice pack,
 // which launch_pass_tp makes sure exists.
-template <int N, int P, int AXIS, int KIND>
+// WAVE_MAP: one line per wavefront also for 512-point lines (the host picks it
+// per pass: wave_mapped).
+template <int N, int P, int AXIS, int KIND, bool WAVE_MAP = false>
 __global__ void __launch_bounds__(256) k_pass(Ctx c, PassDesc pd) {
   extern __shared__ float2 lds[];  // line_pass_lds_bytes(N, G)
   constexpr int L = N / P;
+  static_assert(!WAVE_MAP || (L == 64 && KIND != msl::KIND_GENERIC), "one 64-lane line per wavefront");
   constexpr int TS = KIND == msl::KIND_GENERIC ? msl::TS_RUNTIME : msl::TS_PACK;
   const int G = blockDim.x / L;
   const int group = msl::xcd_group(blockIdx.x, gridDim.x);
-  if constexpr (L == 64 && N < 512 && KIND != msl::KIND_GENERIC) {
+  if constexpr (WAVE_MAP || (L == 64 && N < 512 && KIND != msl::KIND_GENERIC)) {
     // lines of one wavefront (256 points at 4 per lane): each wavefront takes a
     // whole line and orders its stage exchanges itself (measured faster on the
-    // 256-point passes; at 512 points the interleaved mapping below is faster)
+    // 256-point passes; at 512 points the interleaved mapping below is faster
+    // except in the forward sweep's row passes)
     const int g = threadIdx.x / L, j = threadIdx.x % L;
     msl::run_line<N, AXIS, false, KIND, TS, P, true>(c, pd, group * G + g, j, line_buffers<N>(lds, g, G));
   } else {
@@ -423,6 +427,19 @@ int lines_per_group(int n, int nlines, int64_t launch_lines) {
   return std::min(G, nlines);
 }
 
+// Middle passes over 512-point lines at 8 points per lane that take one line
+// per wavefront (no workgroup barriers in their exchanges) instead of two lines
+// interleaved over a workgroup (whole 2x2 tiles per load): the forward sweep's
+// row passes that store no field for the reverse sweep.  Measured on the
+// 512x512x2048 gradient step against the interleaved mapping everywhere: these
+// alone 32.20-32.27 ms against 32.46-32.51; with the column passes too 32.34-32.41
+// (a column line reads half of every 2x2 tile it touches, so its loads take
+// twice the requests); with the recompute's and the reverse sweep's row passes
+// too, which run side by side, 32.43-32.58.
+template <int N, int P, int AXIS>
+constexpr bool wave_mappable() { return N / P == 64 && N >= 512 && AXIS == msl::ROW; }
+bool wave_mapped(int kind, const PassDesc& pd) { return kind == msl::KIND_FWD_MID && !pd.psi_store; }
+
 template <int N, int P, int AXIS>
 hipError_t launch_pass_tp(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   const int nlines = AXIS == msl::ROW ? c.ny : c.nz;
@@ -433,7 +450,15 @@ hipError_t launch_pass_tp(const Ctx& c, const PassDesc& pd, hipStream_t st) {
   if (!c.dbT) kind = msl::KIND_GENERIC;  // the specialised kinds read the slice pack
   const unsigned lds = (unsigned)line_pass_lds_bytes(N, G);
   switch (kind) {
-    case msl::KIND_FWD_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_FWD_MID>), grid, block, lds, st, c, pd); break;
+    case msl::KIND_FWD_MID:
+      if constexpr (wave_mappable<N, P, AXIS>()) {
+        if (wave_mapped(kind, pd)) {
+          hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_FWD_MID, true>), grid, block, lds, st, c, pd);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_FWD_MID>), grid, block, lds, st, c, pd);
+      break;
     case msl::KIND_REV_MID: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_REV_MID>), grid, block, lds, st, c, pd); break;
     default: hipLaunchKernelGGL((k_pass<N, P, AXIS, msl::KIND_GENERIC>), grid, block, lds, st, c, pd); break;
   }

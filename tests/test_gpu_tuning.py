@@ -81,6 +81,23 @@ def test_every_shape_gives_identical_fields(M, ny, nz, ns):
     M.set_tuning({})
 
 
+@pytest.mark.parametrize("ny,nz,ns", [(512, 512, 10), (1024, 512, 7)])
+def test_forward_sweep_mapping_equals_the_checkpointing_one(M, ny, nz, ns):
+    # forward row passes over 512-point lines that store no field take one line per wavefront,
+    # those that store one (a checkpoint at every slice here) two lines interleaved over a
+    # workgroup: same arithmetic per line, so the exit fields are bit-identical, and within the
+    # parity gates
+    g, dn, bn = stack(ny, nz, ns, 31)
+    d, b = dev(dn), dev(bn)
+    M.set_tuning({})
+    f0, _ = M.forward(g, d, b, ckpt_every=0)
+    f1, ck = M.forward(g, d, b, ckpt_every=1)
+    import torch
+    torch.cuda.synchronize()
+    assert np.array_equal(f0.cpu().numpy(), f1.cpu().numpy())
+    check_field(f0.cpu().numpy(), O.forward(g, dn, bn), what=f"{ny}x{nz}")
+
+
 def batch_items(M, specs, seed0):
     import torch
     items = []
