@@ -421,23 +421,32 @@ def mean_target(data, chunk=256):
     return (acc / len(data)).float()
 
 
+def steps_per_epoch(n_samples, batch):
+    """Minibatches per epoch: every sample at least once (the last batch may wrap around)."""
+    return max(1, -(-n_samples // batch))
+
+
 def train(net, data, steps, batch=32, lr=1e-3, seed=1, log_every=0, val=None):
     """ADAM on the mean squared error over minibatches that walk the training set in a fresh
-    seeded permutation each epoch (every sample once per epoch; a last partial batch is left
-    out); returns the loss history and the seconds taken."""
+    seeded permutation each epoch (every sample at least once per epoch: the last batch of an
+    epoch is filled up from the start of that epoch's permutation); returns the loss history
+    and the seconds taken."""
     rng = np.random.Generator(np.random.PCG64(seed))
     n = data.n
     xb = torch.empty((1, batch, n, n), dtype=torch.float32, device="cuda")
     yb = torch.empty((batch, data.rows, n), dtype=torch.float32, device="cuda")
     hist = []
-    per_epoch = len(data) // batch
+    per_epoch = steps_per_epoch(len(data), batch)
     order = None
     t0 = time.perf_counter()
     for it in range(steps):
         if it % per_epoch == 0:
             order = rng.permutation(len(data))
         k = it % per_epoch
-        idx = torch.from_numpy(order[k * batch:(k + 1) * batch]).cuda()
+        sel = order[k * batch:(k + 1) * batch]
+        if len(sel) < batch:
+            sel = np.concatenate([sel, np.resize(order, batch - len(sel))])
+        idx = torch.from_numpy(sel).cuda()
         torch.index_select(data.x, 0, idx, out=xb[0])
         torch.index_select(data.y, 0, idx, out=yb)
         net.forward(xb)
@@ -486,7 +495,7 @@ def train_initialiser(n_samples=50000, steps=None, batch=32, lr=1e-3, n=256, n_s
     next to that of the offset alone (the population-mean cross-section); info["companions"]
     keeps the validation inputs (images the network never trained on) for batched inference."""
     if steps is None:
-        steps = max(1, epochs * (n_samples // batch))
+        steps = epochs * steps_per_epoch(n_samples, batch)
     data = TrainingSet(n_samples, n=n, n_slices=n_slices)
     val = TrainingSet(n_val, seed0=900000, n=n, n_slices=n_slices)
     net = UNet(c=32, seed=seed, n=n)
@@ -509,7 +518,7 @@ def train_initialiser(n_samples=50000, steps=None, batch=32, lr=1e-3, n=256, n_s
             "train_seconds": secs, "ms_per_step": 1e3 * secs / max(1, steps), "params": net.n_params,
             "val_mse": evaluate(net, val), "val_mse_mean_map": base,
             "val_row_profile_mse": row_net, "val_row_profile_mse_mean_map": row_mean,
-            "epochs": steps * batch / n_samples}
+            "epochs": steps / steps_per_epoch(n_samples, batch)}
     info["companions"] = val.x[:63].clone()
     del data, val
     return net, info
